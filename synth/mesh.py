@@ -1,0 +1,171 @@
+"""Seeded synthetic tetrahedral meshes.
+
+* ``cube_mesh(N, seed)``: the unit cube cut into N^3 hexahedra, each split
+  into the six Kuhn simplices along its (0,0,0)-(1,1,1) diagonal.  Interior
+  nodes are jittered by a seeded uniform perturbation of +-1% of the hex
+  size; boundary nodes stay on their faces so the faces remain planar.
+  The bottom face (z = 0) fixes the z velocity component; the top face
+  (z = 1) carries a uniform dead traction (0, 0, t_top).
+* ``tube_mesh(nr, nt, nz)``: a thick-walled tube (inner radius 1.0, wall 0.2,
+  length 2.0) meshed structured in (r, theta, z), periodic in theta, with the
+  same Kuhn split; carries two helical fibre directions per element.
+
+Node numbering is lexicographic with the first index fastest, tets are
+emitted hex by hex, and every tet is positively oriented in the reference
+configuration.
+"""
+from __future__ import annotations
+
+import itertools
+from dataclasses import dataclass, field
+
+import numpy as np
+
+
+@dataclass
+class Mesh:
+    name: str
+    X: np.ndarray              # [n][3] float64 reference coordinates
+    tets: np.ndarray           # [m][4] int32, positively oriented
+    bfaces: np.ndarray         # [f][3] int32 loaded boundary triangles
+    traction: np.ndarray       # [f][3] float64 dead traction at full load
+    dir_mask: np.ndarray       # [n][4] uint8: 1 = Dirichlet on (vx, vy, vz, p)
+    dir_vel: np.ndarray        # [n][3] float64 prescribed velocity on Dirichlet comps
+    fibre: np.ndarray | None = None   # [m][2][3] float64 unit fibre directions
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def n_nodes(self) -> int:
+        return int(self.X.shape[0])
+
+    @property
+    def n_tets(self) -> int:
+        return int(self.tets.shape[0])
+
+
+# The six Kuhn simplices of a hex: one per ordering (a, b, c) of the axes,
+# path 000 -> e_a -> e_a + e_b -> 111.
+_PERMS = list(itertools.permutations(range(3)))
+
+
+def _perm_sign(perm) -> int:
+    s = 1
+    p = list(perm)
+    for i in range(3):
+        for j in range(i + 1, 3):
+            if p[i] > p[j]:
+                s = -s
+    return s
+
+
+def _kuhn_tets(n1: int, n2: int, n3: int, node_id, wrap2: bool = False) -> np.ndarray:
+    """Kuhn-split every hex of an n1 x n2 x n3 index grid.
+
+    ``node_id(i, j, k)`` maps (vectorised) grid indices to node numbers.  With
+    ``wrap2`` the second index is periodic.
+    """
+    i, j, k = np.meshgrid(np.arange(n1), np.arange(n2), np.arange(n3), indexing="ij")
+    # hex order: first index fastest
+    i = i.transpose(2, 1, 0).ravel()
+    j = j.transpose(2, 1, 0).ravel()
+    k = k.transpose(2, 1, 0).ravel()
+    base = np.stack([i, j, k], axis=1)
+    out = []
+    for perm in _PERMS:
+        corners = [np.zeros(3, dtype=np.int64)]
+        c = np.zeros(3, dtype=np.int64)
+        for ax in perm:
+            c = c.copy()
+            c[ax] = 1
+            corners.append(c)
+        verts = []
+        for c in corners:
+            idx = base + c[None, :]
+            jj = idx[:, 1] % n2 if wrap2 else idx[:, 1]
+            verts.append(node_id(idx[:, 0], jj, idx[:, 2]))
+        verts = np.stack(verts, axis=1)
+        if _perm_sign(perm) < 0:           # odd ordering: swap to orient positively
+            verts = verts[:, [0, 2, 1, 3]]
+        out.append(verts)
+    # interleave so tets of one hex are contiguous: [hex][6]
+    tets = np.stack(out, axis=1).reshape(-1, 4)
+    return tets.astype(np.int32)
+
+
+def _faces_on(tets: np.ndarray, on_node: np.ndarray) -> np.ndarray:
+    """Triangles of ``tets`` whose three vertices all satisfy ``on_node``."""
+    faces = []
+    for drop in range(4):
+        keep = [a for a in range(4) if a != drop]
+        f = tets[:, keep]
+        sel = on_node[f].all(axis=1)
+        faces.append(f[sel])
+    return np.concatenate(faces, axis=0).astype(np.int32)
+
+
+def cube_mesh(N: int, seed: int = 0, jitter: float = 0.01, t_top: float = -1.0e4) -> Mesh:
+    """Unit cube, N^3 hexes x 6 Kuhn tets, seeded interior jitter."""
+    n1 = N + 1
+    g = np.arange(n1, dtype=np.float64) / N
+    zz, yy, xx = np.meshgrid(g, g, g, indexing="ij")
+    X = np.stack([xx.ravel(), yy.ravel(), zz.ravel()], axis=1)
+    ii = np.rint(X * N).astype(np.int64)
+    interior = np.all((ii > 0) & (ii < N), axis=1)
+    rng = np.random.default_rng(seed)
+    h = 1.0 / N
+    pert = rng.uniform(-jitter * h, jitter * h, size=X.shape)
+    X = X + pert * interior[:, None]
+
+    def node_id(i, j, k):
+        return i + n1 * (j + n1 * k)
+
+    tets = _kuhn_tets(N, N, N, node_id)
+    top = ii[:, 2] == N
+    bfaces = _faces_on(tets, top)
+    traction = np.zeros((bfaces.shape[0], 3))
+    traction[:, 2] = t_top
+    dir_mask = np.zeros((X.shape[0], 4), dtype=np.uint8)
+    dir_mask[ii[:, 2] == 0, 2] = 1
+    dir_vel = np.zeros((X.shape[0], 3))
+    return Mesh(name=f"cube{N}", X=X, tets=tets, bfaces=bfaces, traction=traction,
+                dir_mask=dir_mask, dir_vel=dir_vel, fibre=None,
+                meta={"N": N, "seed": seed, "jitter": jitter, "t_top": t_top})
+
+
+def tube_mesh(nr: int, nt: int, nz: int, r_in: float = 1.0, wall: float = 0.2,
+              length: float = 2.0, fibre_deg: float = 45.0, stretch: float = 1.5,
+              t_end: float = 1.0) -> Mesh:
+    """Thick-walled tube, structured in (r, theta, z), theta periodic.
+
+    z = 0 is clamped; on z = length the axial velocity is prescribed so that
+    the axial stretch reaches ``stretch`` at ``t_end``; the other faces are
+    traction free.  Fibres: cos(phi) e_theta +- sin(phi) e_z at the centroid.
+    """
+    r = r_in + wall * np.arange(nr + 1) / nr
+    th = 2.0 * np.pi * np.arange(nt) / nt
+    z = length * np.arange(nz + 1) / nz
+    Z, T, R = np.meshgrid(z, th, r, indexing="ij")        # r fastest
+    X = np.stack([(R * np.cos(T)).ravel(), (R * np.sin(T)).ravel(), Z.ravel()], axis=1)
+    kz = np.repeat(np.arange(nz + 1), nt * (nr + 1))
+
+    def node_id(i, j, k):
+        return i + (nr + 1) * (j + nt * k)
+
+    tets = _kuhn_tets(nr, nt, nz, node_id, wrap2=True)
+    dir_mask = np.zeros((X.shape[0], 4), dtype=np.uint8)
+    dir_vel = np.zeros((X.shape[0], 3))
+    dir_mask[kz == 0, 0:3] = 1
+    dir_mask[kz == nz, 2] = 1
+    dir_vel[kz == nz, 2] = (stretch - 1.0) * length / t_end
+    cen = X[tets].mean(axis=1)
+    ang = np.arctan2(cen[:, 1], cen[:, 0])
+    e_t = np.stack([-np.sin(ang), np.cos(ang), np.zeros_like(ang)], axis=1)
+    e_z = np.tile(np.array([0.0, 0.0, 1.0]), (tets.shape[0], 1))
+    phi = np.deg2rad(fibre_deg)
+    fibre = np.stack([np.cos(phi) * e_t + np.sin(phi) * e_z,
+                      np.cos(phi) * e_t - np.sin(phi) * e_z], axis=1)
+    bfaces = np.zeros((0, 3), dtype=np.int32)
+    traction = np.zeros((0, 3))
+    return Mesh(name=f"tube{nr}x{nt}x{nz}", X=X, tets=tets, bfaces=bfaces,
+                traction=traction, dir_mask=dir_mask, dir_vel=dir_vel, fibre=fibre,
+                meta={"nr": nr, "nt": nt, "nz": nz, "stretch": stretch, "t_end": t_end})
