@@ -1,0 +1,190 @@
+"""Benchmark: generalized-alpha Newton steps of the 64^3 cube (nu = 0.499) on one MI355X.
+
+A bench step is one time step of the predictor multi-corrector algorithm
+(stage, assemble, scale, nested FGMRES solve, update, per Newton iteration,
+until ||R|| / ||R_0|| <= 1e-8) for the synthetic unit-cube compression
+workload: 64^3 hexes x 6 Kuhn tets (1,572,864 tets, 274,625 nodes,
+1,098,500 unknowns), mu = 1e5, nu = 0.499, rho0 = 1000, dt = 1e-3, top
+traction -1e4 ramped over 10 steps.  Timed steps start from rest after the
+warm-up steps, so every run does the same work.  Both solver forms run:
+FP64 and mixed (FP32 intermediate/inner levels, FP64 outer FGMRES/Newton).
+
+Prints one JSON line (value = Newton iterations per second of the FP64 form).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "Newton-step time & BSR SpMV GB/s (%HBM peak); FP32-inner vs FP64 at 1e-8 rel res"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def spmv_A_bytes(n, nnzb, elem):
+    """Algorithmic bytes of one 3x3 block SpMV: values + column indices + row
+    pointers + x (once) + y."""
+    return (9 * elem + 4) * nnzb + 4 * (n + 1) + 2 * 3 * elem * n
+
+
+def time_spmv(prob, K, op, x, fp32, reps=50):
+    import torch
+    for _ in range(5):
+        prob.spmv(K, op, x, fp32)
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    s.record()
+    for _ in range(reps):
+        prob.spmv(K, op, x, fp32)
+    e.record()
+    torch.cuda.synchronize()
+    return s.elapsed_time(e) / reps * 1e-3   # seconds per launch
+
+
+def run_form(prob, mesh, ti, nopts, sopts, steps, warmup):
+    import torch
+    from paper_1809_06350_amd import vms as V
+
+    def from_rest():
+        return prob.new_state()
+
+    K = None
+    st = from_rest()
+    for s in range(warmup):
+        stats, K = prob.step(st, V.time_int(ti.dt, ti.rho_inf, s * ti.dt, ti.n_steps * ti.dt), nopts, sopts, K)
+        prob.roll(st)
+        log(f"  warmup step {s}: newton={stats['n_newton']} ms={stats['ms_total']:.1f}")
+    st = from_rest()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    per = []
+    for s in range(steps):
+        stats, K = prob.step(st, V.time_int(ti.dt, ti.rho_inf, s * ti.dt, ti.n_steps * ti.dt), nopts, sopts, K)
+        prob.roll(st)
+        per.append(stats)
+        log(f"  step {s}: newton={stats['n_newton']} outer={stats['it_outer_total']} A={stats['it_A_total']} "
+            f"S={stats['it_S_total']} I={stats['it_I_total']} ms={stats['ms_total']:.1f} "
+            f"(asm {stats['ms_assemble']:.1f}, solve {stats['ms_solve']:.1f})")
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    n_newton = sum(p["n_newton"] for p in per)
+    return {"wall_s": wall, "n_newton": n_newton, "per_step": per, "u": st["u"].clone(), "K": K}
+
+
+def cpu_baseline(N=16, nu=0.499):
+    """The oracle (NumPy/SciPy, sparse LU) on a 16^3 sample of the workload."""
+    import numpy as np  # noqa: F401
+
+    import synth
+    from oracle import assemble as AS
+    from oracle import newton as NW
+    mesh, mat, ti = synth.cube_case(N, nu=nu, n_steps=10)
+    disc = AS.Discretization(mesh, mat)
+    t0 = time.perf_counter()
+    st, info = NW.time_step(disc, ti, NW.rest_state(mesh), 0.0, tol_R=1e-8)
+    wall = time.perf_counter() - t0
+    threads = os.environ.get("OMP_NUM_THREADS") or os.environ.get("OPENBLAS_NUM_THREADS") or "unset"
+    return {"wall_s": wall, "n_newton": info["n_newton"], "n_unknowns": 4 * mesh.n_nodes,
+            "threads_env": threads}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--size", type=int, default=64)
+    ap.add_argument("--nu", type=float, default=0.499)
+    ap.add_argument("--forms", default="fp64,mixed")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import synth
+    from paper_1809_06350_amd import vms as V
+
+    N = args.size
+    mesh, mat, ti = synth.cube_case(N, nu=args.nu, n_steps=10)
+    log(f"cube {N}^3: nodes={mesh.n_nodes} tets={mesh.n_tets}")
+    prob = V.Problem(mesh, mat, "cuda:0")
+    n, nnzb = mesh.n_nodes, prob.nnzb
+    nopts = V.newton_opts(tol_R=1e-8, l_max=20)
+    forms = {
+        "fp64": V.solver_opts(rtol=1e-8, rtol_A=1e-6, rtol_S=1e-6, rtol_I=1e-4),
+        "mixed": V.solver_opts(rtol=1e-8, rtol_A=1e-5, rtol_S=1e-5, rtol_I=1e-3, precision=V.MIXED),
+    }
+    results = {}
+    for name in args.forms.split(","):
+        log(f"form {name}")
+        results[name] = run_form(prob, mesh, ti, nopts, forms[name], args.steps, args.warmup)
+
+    primary = "fp64" if "fp64" in results else list(results)[0]
+    r = results[primary]
+    value = r["n_newton"] / r["wall_s"]
+
+    # dominant kernel: the 3x3 block SpMV of the A-level GMRES (inner + intermediate)
+    K = r["K"]
+    x64 = torch.randn(n, 3, dtype=torch.float64, device="cuda:0", generator=torch.Generator("cuda:0").manual_seed(1))
+    t64 = time_spmv(prob, K, V.OP_A, x64, False)
+    by64 = spmv_A_bytes(n, nnzb, 8)
+    roof = {"bound": "hbm", "kernel": "k_spmv_A<double,double>", "achieved": by64 / t64 / 1e9,
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": by64 / t64 / 1e9 / HBM_PEAK_GBS, "traffic": None,
+            "bytes_per_launch": by64, "us_per_launch": t64 * 1e6}
+    extra = {}
+    if "mixed" in results:
+        Km = results["mixed"]["K"]
+        t32 = time_spmv(prob, Km, V.OP_A, x64.float(), True)
+        by32 = spmv_A_bytes(n, nnzb, 4)
+        extra["spmv_A_fp32"] = {"GB/s": by32 / t32 / 1e9, "us_per_launch": t32 * 1e6, "bytes_per_launch": by32,
+                                "frac_hbm": by32 / t32 / 1e9 / HBM_PEAK_GBS}
+        rm = results["mixed"]
+        u64 = results.get("fp64", rm)["u"]
+        err = float((rm["u"] - u64).norm() / u64.norm()) if "fp64" in results else None
+        extra["mixed"] = {"newton_per_s": rm["n_newton"] / rm["wall_s"],
+                          "ms_per_newton": 1e3 * rm["wall_s"] / rm["n_newton"],
+                          "ms_per_step": 1e3 * rm["wall_s"] / args.steps,
+                          "speedup_vs_fp64": (r["wall_s"] / rm["wall_s"]) if "fp64" in results else None,
+                          "u_rel_err_vs_fp64": err}
+    for name, rr in results.items():
+        last = rr["per_step"][-1]
+        extra[f"{name}_last_step"] = {k: last[k] for k in ("n_newton", "it_outer_total", "it_A_total", "it_S_total",
+                                                           "it_I_total", "ms_assemble", "ms_solve", "ms_total")}
+    out = {"metric": METRIC, "value": value, "unit": "newton_steps/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": 1e3 * r["wall_s"] / args.steps,
+           "ms_per_newton_step": 1e3 * r["wall_s"] / r["n_newton"], "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64" if primary == "fp64" else "f32+f64",
+           "data": "synthetic",
+           "config": {"workload": f"cube{N}^3 Kuhn tets, nu={args.nu}, neo-Hookean, dt=1e-3, Newton/FGMRES 1e-8",
+                      "nodes": n, "tets": mesh.n_tets, "unknowns": 4 * n, "nnzb": nnzb,
+                      "parallelism": "single GPU"},
+           "roofline": roof}
+    out.update(extra)
+    if not args.no_cpu_baseline:
+        log("cpu baseline: oracle on a 16^3 sample")
+        cb = cpu_baseline(16, args.nu)
+        rate16 = cb["n_newton"] / cb["wall_s"]
+        out["cpu_baseline"] = {"value": rate16 * cb["n_unknowns"] / (4 * n), "unit": "newton_steps/s",
+                               "cores": 1, "kind": "oracle",
+                               "sample": f"one time step of the 16^3 cube ({cb['n_unknowns']} unknowns, "
+                                         f"{cb['n_newton']} Newton its, {cb['wall_s']:.1f} s), scaled linearly "
+                                         f"by unknowns to {N}^3; SuperLU single-threaded, "
+                                         f"OMP/OPENBLAS threads={cb['threads_env']}"}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

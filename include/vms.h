@@ -1,0 +1,279 @@
+/* vms.h -- C ABI of the MI355X (gfx950) Newton-step library for the
+ * variational-multiscale / generalized-alpha P1-tetrahedral discretisation of
+ * hyper-elastodynamics with the nested block (Schur complement reduction)
+ * preconditioned FGMRES solver (Liu & Marsden, arXiv:1809.06350).
+ *
+ * The calls follow the paper's statement of one Newton-Raphson iteration of
+ * the predictor multi-corrector algorithm (section 3.3):
+ *     assemble(mesh, state, material) -> K = [[A, B], [C, D]], R = (R_m, R_p)
+ *     solve(K, R) -> Delta = (Delta v-dot, Delta p-dot)
+ *     update(state, Delta)
+ *
+ * Conventions (all entry points)
+ *  - Memory: every array pointer is a DEVICE pointer owned by the caller
+ *    unless its comment says "host".  The library allocates no device memory
+ *    after vms_ctx_create: solver scratch comes from a caller-provided
+ *    workspace.  vms_ctx_create allocates a small pinned host buffer.
+ *  - Streams: all kernels are enqueued on the stream given to
+ *    vms_ctx_create (in order).  Calls marked [async] return without waiting;
+ *    calls marked [sync] wait for the stream work they need to take host-side
+ *    decisions (convergence tests) and return after their last kernel is
+ *    enqueued-and-finished.
+ *  - Errors: integer status, no exceptions cross the ABI.  >0 is a warning
+ *    (outputs hold the last iterate), <0 an error; vms_last_error() gives the
+ *    message of the last non-OK status on that context.
+ *  - Dof order per node is (v_x, v_y, v_z, p); nodal vectors [n][4] are
+ *    node-interleaved, velocity vectors [n][3], pressure vectors [n].
+ *  - Block values are stored entry-major over the shared node-graph pattern:
+ *    A[9][nnzb] (row-major 3x3 entry e = 3*r + c), B[3][nnzb], C[3][nnzb],
+ *    D[nnzb]; block b of row i couples node i to node col[b].
+ *  - Indices are int32 (nnzb < 2^31).
+ *  - A context is not thread-safe; use one per stream.
+ */
+#ifndef VMS_H
+#define VMS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum vms_status {
+  VMS_OK = 0,
+  VMS_NOT_CONVERGED = 1,        /* Krylov or Newton iteration limit reached */
+  VMS_ERR_ARG = -1,             /* bad argument (NULL, size, index out of range) */
+  VMS_ERR_HIP = -2,             /* a HIP runtime call failed */
+  VMS_ERR_WORKSPACE = -3,       /* workspace too small */
+  VMS_ERR_INVERTED_ELEMENT = -4,/* J <= 0 in some element */
+  VMS_ERR_BREAKDOWN = -5,       /* Arnoldi breakdown with a nonzero residual */
+  VMS_ERR_NAN = -6              /* NaN/Inf in a residual or Krylov norm */
+};
+
+enum vms_material_kind { VMS_NH_COMP = 0, VMS_NH_INCOMP = 1, VMS_HGO_INCOMP = 2 };
+
+/* assembly flags */
+enum { VMS_ASM_RESIDUAL = 1, VMS_ASM_TANGENT = 2, VMS_ASM_RKCORR = 4 };
+
+/* operator ids for vms_spmv */
+enum { VMS_OP_FULL = 0, VMS_OP_A = 1, VMS_OP_B = 2, VMS_OP_C = 3, VMS_OP_D = 4 };
+
+/* block preconditioner variants (section 4.2-4.4 and the partial-factorization remark) */
+enum { VMS_PC_LDU = 0, VMS_PC_UPPER = 1, VMS_PC_LOWER = 2, VMS_PC_DIAG = 3 };
+
+/* precision of the intermediate and inner levels */
+enum { VMS_FP64 = 0, VMS_MIXED = 1 };
+
+/* Arnoldi orthogonalisation */
+enum { VMS_ORTH_CGS2 = 0, VMS_ORTH_MGS = 1 };
+
+typedef struct vms_ctx vms_ctx;
+
+typedef struct {
+  int32_t kind;     /* vms_material_kind */
+  double rho0;      /* reference density */
+  double mu;        /* shear modulus (neo-Hookean matrix) */
+  double kappa;     /* bulk modulus (NH_COMP only) */
+  double k1, k2, kd;/* HGO fibre stiffness, exponent, dispersion (HGO_INCOMP only) */
+  double c_m;       /* tau_M coefficient, the paper fixes 1e-3 */
+} vms_material;
+
+typedef struct {
+  double dt;        /* time step Delta t_n */
+  double rho_inf;   /* spectral radius at infinity; alpha_m, alpha_f, gamma follow (section 3.2) */
+  double t_n;       /* time at the start of the step */
+  double t_load;    /* the dead load ramps linearly to full at t_load (<= 0: full load) */
+} vms_timeint;
+
+typedef struct {
+  int32_t n_nodes, n_tets, n_bfaces, n_colours;
+  int64_t nnzb;
+  const double *X;          /* [n][3] reference coordinates */
+  const int32_t *tets;      /* [m][4] positively oriented */
+  const int32_t *bfaces;    /* [f][3] loaded boundary triangles (may be NULL if f = 0) */
+  const double *traction;   /* [f][3] dead traction at full load */
+  const uint8_t *dir_mask;  /* [n][4] 1 = Dirichlet on (v_x, v_y, v_z, p) */
+  const double *dir_vel;    /* [n][3] prescribed velocity of Dirichlet components */
+  const double *fibre;      /* [m][2][3] unit fibre directions (HGO) or NULL */
+  const int32_t *row_ptr;   /* [n+1] pattern from vms_setup_build */
+  const int32_t *col;       /* [nnzb] */
+  const int32_t *tpos;      /* [nnzb] position of the transposed block */
+  const int32_t *diag_pos;  /* [n] */
+  const int32_t *elem_blk;  /* [m][16] block of (tets[e][a], tets[e][b]) at a*4+b */
+  const int32_t *elem_by_colour; /* [m] elements grouped by colour */
+  const int32_t *nf_ptr;    /* [n+1] node -> loaded faces */
+  const int32_t *nf_face;   /* [3f] */
+  const int32_t *colour_ptr;/* HOST [n_colours+1] */
+} vms_mesh;
+
+typedef struct {
+  /* y_n, y-dot_n (read only) */
+  const double *u_n, *p_n, *v_n, *du_n, *dp_n, *dv_n;
+  /* the current iterate y_{n+1,(l)}, y-dot_{n+1,(l)} (updated in place) */
+  double *u, *p, *v, *du, *dp, *dv;
+} vms_state;
+
+typedef struct {
+  double *A, *B, *C, *D;          /* FP64 blocks, entry-major */
+  float *A32, *B32, *C32, *D32;   /* FP32 mirrors of the scaled blocks (mixed form) or NULL */
+  double *W;                      /* [n][4] symmetric diagonal scaling */
+} vms_matrix;
+
+typedef struct {
+  double rtol, atol; int32_t maxit;        /* outer FGMRES (delta^r, delta^a, n^max) */
+  double rtol_A, atol_A; int32_t maxit_A;  /* intermediate A-solves */
+  double rtol_S, atol_S; int32_t maxit_S;  /* Schur-complement solve */
+  double rtol_I, atol_I; int32_t maxit_I;  /* inner A-solve inside the Schur product */
+  int32_t precond;    /* VMS_PC_* */
+  int32_t precision;  /* VMS_FP64 or VMS_MIXED */
+  int32_t orth;       /* VMS_ORTH_* */
+  int32_t reserved;
+} vms_solver_opts;
+
+typedef struct {
+  int32_t status;
+  int32_t n_outer;                  /* FGMRES iterations */
+  int32_t n_A_solves, it_A;         /* intermediate A-solves and their total iterations */
+  int32_t n_S_solves, it_S;         /* Schur solves and their total iterations */
+  int32_t n_I_solves, it_I;         /* inner A-solves and their total iterations */
+  double res0, res;                 /* outer ||r*|| at start and the final least-squares residual */
+  double ms_total;                  /* host wall time of the call */
+} vms_solve_stats;
+
+typedef struct {
+  double tol_R, tol_A;  /* relative / absolute Newton tolerances (section 3.3) */
+  int32_t l_max;        /* maximum corrector iterations */
+  int32_t rk_corr;      /* 1: keep the -K_{.,u-dot} R-bar_k / alpha_m term of the stage-1 rhs */
+  double eps_diag;      /* scaling threshold epsilon_diag (section 4.1) */
+} vms_newton_opts;
+
+typedef struct {
+  int32_t status;
+  int32_t n_newton;         /* corrector iterations taken */
+  double res_norm[32];      /* ||R_(l)||, l = 1..min(l_max+1, 32) */
+  vms_solve_stats last;     /* stats of the last linear solve */
+  int32_t it_outer_total, it_A_total, it_S_total, it_I_total;
+  double ms_assemble, ms_solve, ms_total;
+} vms_step_stats;
+
+/* ---- context ------------------------------------------------------------ */
+
+/* Bind a context to HIP device `device` and stream `stream` (NULL = the null
+ * stream).  *out receives the context.  Returns VMS_ERR_HIP if the device is
+ * not usable. */
+int vms_ctx_create(vms_ctx **out, int device, void *stream);
+void vms_ctx_destroy(vms_ctx *ctx);
+/* Message of the last non-OK status on ctx (never NULL). */
+const char *vms_last_error(const vms_ctx *ctx);
+
+/* ---- setup (host, integer work) ---------------------------------------- */
+
+/* Sizes of the node-graph block pattern of the P1 tangent (every pair of
+ * nodes sharing a tetrahedron couples, section 3.1) and an upper bound on the
+ * element colours.  tets: HOST [m][4].  VMS_ERR_ARG on an out-of-range node. */
+int vms_setup_sizes(int32_t n_nodes, int32_t n_tets, const int32_t *tets,
+                    int64_t *nnzb, int32_t *n_colours_bound);
+
+/* Build, into HOST arrays sized by vms_setup_sizes: row_ptr[n+1], col[nnzb],
+ * tpos[nnzb], diag_pos[n], elem_blk[m][16], colour_ptr[bound+1],
+ * elem_by_colour[m], the actual colour count, and node -> loaded-face lists
+ * nf_ptr[n+1], nf_face[3f] (bfaces: HOST [f][3]).  Greedy element colouring in
+ * element order: elements of one colour share no node. */
+int vms_setup_build(int32_t n_nodes, int32_t n_tets, const int32_t *tets,
+                    int32_t n_bfaces, const int32_t *bfaces,
+                    int32_t *row_ptr, int32_t *col, int32_t *tpos, int32_t *diag_pos,
+                    int32_t *elem_blk, int32_t *colour_ptr, int32_t *elem_by_colour,
+                    int32_t *n_colours, int32_t *nf_ptr, int32_t *nf_face);
+
+/* ---- assembly (section 3.3 steps 1-4; consistent-linearization appendix) - */
+
+/* f_ext[n][3] = -int_Gamma N_A H dGamma_X for the dead traction at full load
+ * (the traction term of R_m in the appendix), 1/3 of each reference face area
+ * per vertex.  [async] */
+int vms_nodal_load(vms_ctx *ctx, const vms_mesh *mesh, double *f_ext);
+
+/* Set the iterate to the predictor y_(0) = y_n, y-dot_(0) = (gamma-1)/gamma
+ * y-dot_n (section 3.3, predictor stage); Dirichlet velocity components take
+ * u = dir_vel * t_{n+1}, v = u-dot = dir_vel, v-dot = 0.  [async] */
+int vms_predictor(vms_ctx *ctx, const vms_mesh *mesh, const vms_timeint *ti, vms_state *st);
+
+/* Element-by-element assembly at the generalized-alpha stages
+ * y-dot_{n+alpha_m}, y_{n+alpha_f} computed from (y_n, y-dot_n) and the
+ * iterate (section 3.3 step 1).
+ *   VMS_ASM_RESIDUAL: R[n][4] = (R_m, R_p) of the appendix (P1, 4-point
+ *     rule, tau_M frozen per element) plus load_scale * f_ext;
+ *   VMS_ASM_TANGENT: K->A, B, C, D of the block reduction (eqs. defining A,
+ *     B, C, D), exact linearisation of R;
+ *   VMS_ASM_RKCORR: corr[n][4] = (alpha_f gamma dt / alpha_m) dR/du . R-bar_k,
+ *     the K_{.,u-dot} R-bar_k / alpha_m term of the stage-1 right-hand side.
+ * Outputs are overwritten.  f_ext may be NULL (no load).  Returns
+ * VMS_ERR_INVERTED_ELEMENT (checked at the end of the call, [sync] then) if
+ * some element has J <= 0; otherwise [async]. */
+int vms_assemble(vms_ctx *ctx, const vms_mesh *mesh, const vms_material *mat,
+                 const vms_timeint *ti, const vms_state *st, const double *f_ext,
+                 vms_matrix *K, double *R, double *corr, unsigned flags);
+
+/* *norm_host = || {R-bar_k, R_p, R_m} ||_2 over non-Dirichlet dofs (section
+ * 3.3 step 3), R-bar_k = u-dot_{n+alpha_m} - v_{n+alpha_f}.  [sync]
+ * VMS_ERR_NAN if the norm is not finite. */
+int vms_residual_norm(vms_ctx *ctx, const vms_mesh *mesh, const vms_timeint *ti,
+                      const vms_state *st, const double *R, double *norm_host);
+
+/* ---- linear system (section 4) ------------------------------------------ */
+
+/* Dirichlet rows/columns (zeroed, unit diagonal, zero rhs) and symmetric
+ * diagonal scaling (section 4.1): W_ii = |K_ii|^(-1/2) if |K_ii| >= eps_diag
+ * else 1; K <- W K W in place, rhs_scaled[n][4] = W * (-R + corr) (corr may
+ * be NULL), K->W written.  With mirror32 != 0 also writes K->A32..D32.
+ * [async] */
+int vms_prepare_system(vms_ctx *ctx, const vms_mesh *mesh, vms_matrix *K, const double *R,
+                       const double *corr, double *rhs_scaled, double eps_diag, int mirror32);
+
+/* y = op * x for one block of K (VMS_OP_A: y[n][3] = A x[n][3]; B: y[n][3] =
+ * B x[n]; C: y[n] = C x[n][3]; D: y[n] = D x[n]; FULL: y[n][4] = K x[n][4]).
+ * fp32 != 0 uses the FP32 mirrors with float x, y.  [async] */
+int vms_spmv(vms_ctx *ctx, const vms_mesh *mesh, const vms_matrix *K, int op,
+             const void *x, void *y, int fp32);
+
+/* Workspace bytes needed by vms_solve_scaled / vms_solve_transpose for these
+ * options (Krylov bases of the four levels, control blocks, temporaries). */
+size_t vms_solve_workspace(const vms_mesh *mesh, const vms_solver_opts *opts);
+
+/* Solve the scaled system K* x* = rhs* by FGMRES (outer level) right-
+ * preconditioned by the nested Schur-complement-reduction preconditioner
+ * (Algorithm 1 with Algorithm 2 for the Schur products): GMRES on A with
+ * 3x3 block-Jacobi, GMRES on S = D - C A^-1 B with diag(S^) where
+ * S^ = D - C diag(A)^-1 B.  x0 = 0; every level stops at
+ * ||r|| <= max(rtol ||b||, atol) or maxit.  [sync]
+ * Returns VMS_NOT_CONVERGED (x_scaled holds the last iterate) when the outer
+ * level hits maxit. */
+int vms_solve_scaled(vms_ctx *ctx, const vms_mesh *mesh, const vms_matrix *K,
+                     const double *rhs_scaled, double *x_scaled, const vms_solver_opts *opts,
+                     void *workspace, size_t workspace_bytes, vms_solve_stats *stats);
+
+/* Stage 2 and update (section 3.3 steps 6-7): Delta = W x*; Delta u-dot =
+ * (alpha_f gamma dt/alpha_m) Delta v-dot - R-bar_k/alpha_m; y-dot += Delta
+ * y-dot, y += gamma dt Delta y-dot on the iterate (Dirichlet components fixed).
+ * [async] */
+int vms_newton_update(vms_ctx *ctx, const vms_mesh *mesh, const vms_timeint *ti,
+                      vms_state *st, const double *W, const double *x_scaled);
+
+/* Workspace bytes of vms_step: vms_solve_workspace + its residual vectors. */
+size_t vms_step_workspace(const vms_mesh *mesh, const vms_solver_opts *opts);
+
+/* One generalized-alpha time step by the predictor multi-corrector algorithm
+ * (section 3.3): predictor, then for l = 1..l_max: stage, residual, norm test
+ * (||R_(l)|| / ||R_(0)|| <= tol_R or ||R_(l)|| <= tol_A), tangent, scaled
+ * nested solve, stage 2 and update.  On return the iterate arrays of `st` hold
+ * y_{n+1}, y-dot_{n+1}.  f_ext from vms_nodal_load (or NULL).  K is used as
+ * storage for the tangent.  [sync]  VMS_NOT_CONVERGED if l_max is reached. */
+int vms_step(vms_ctx *ctx, const vms_mesh *mesh, const vms_material *mat,
+             const vms_timeint *ti, vms_state *st, const double *f_ext, vms_matrix *K,
+             const vms_newton_opts *nopts, const vms_solver_opts *sopts,
+             void *workspace, size_t workspace_bytes, vms_step_stats *stats);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* VMS_H */

@@ -1,0 +1,119 @@
+"""ctypes declarations of the C ABI in include/vms.h (argument marshalling only)."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libvms.so")
+
+c_double_p = C.POINTER(C.c_double)
+
+
+class Material(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("rho0", C.c_double), ("mu", C.c_double), ("kappa", C.c_double),
+                ("k1", C.c_double), ("k2", C.c_double), ("kd", C.c_double), ("c_m", C.c_double)]
+
+
+class TimeInt(C.Structure):
+    _fields_ = [("dt", C.c_double), ("rho_inf", C.c_double), ("t_n", C.c_double), ("t_load", C.c_double)]
+
+
+class Mesh(C.Structure):
+    _fields_ = [("n_nodes", C.c_int32), ("n_tets", C.c_int32), ("n_bfaces", C.c_int32),
+                ("n_colours", C.c_int32), ("nnzb", C.c_int64),
+                ("X", C.c_void_p), ("tets", C.c_void_p), ("bfaces", C.c_void_p), ("traction", C.c_void_p),
+                ("dir_mask", C.c_void_p), ("dir_vel", C.c_void_p), ("fibre", C.c_void_p),
+                ("row_ptr", C.c_void_p), ("col", C.c_void_p), ("tpos", C.c_void_p), ("diag_pos", C.c_void_p),
+                ("elem_blk", C.c_void_p), ("elem_by_colour", C.c_void_p), ("nf_ptr", C.c_void_p),
+                ("nf_face", C.c_void_p), ("colour_ptr", C.c_void_p)]
+
+
+class State(C.Structure):
+    _fields_ = [(k, C.c_void_p) for k in ("u_n", "p_n", "v_n", "du_n", "dp_n", "dv_n",
+                                          "u", "p", "v", "du", "dp", "dv")]
+
+
+class Matrix(C.Structure):
+    _fields_ = [(k, C.c_void_p) for k in ("A", "B", "C", "D", "A32", "B32", "C32", "D32", "W")]
+
+
+class SolverOpts(C.Structure):
+    _fields_ = [("rtol", C.c_double), ("atol", C.c_double), ("maxit", C.c_int32),
+                ("rtol_A", C.c_double), ("atol_A", C.c_double), ("maxit_A", C.c_int32),
+                ("rtol_S", C.c_double), ("atol_S", C.c_double), ("maxit_S", C.c_int32),
+                ("rtol_I", C.c_double), ("atol_I", C.c_double), ("maxit_I", C.c_int32),
+                ("precond", C.c_int32), ("precision", C.c_int32), ("orth", C.c_int32),
+                ("reserved", C.c_int32)]
+
+
+class SolveStats(C.Structure):
+    _fields_ = [("status", C.c_int32), ("n_outer", C.c_int32), ("n_A_solves", C.c_int32), ("it_A", C.c_int32),
+                ("n_S_solves", C.c_int32), ("it_S", C.c_int32), ("n_I_solves", C.c_int32), ("it_I", C.c_int32),
+                ("res0", C.c_double), ("res", C.c_double), ("ms_total", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class NewtonOpts(C.Structure):
+    _fields_ = [("tol_R", C.c_double), ("tol_A", C.c_double), ("l_max", C.c_int32), ("rk_corr", C.c_int32),
+                ("eps_diag", C.c_double)]
+
+
+class StepStats(C.Structure):
+    _fields_ = [("status", C.c_int32), ("n_newton", C.c_int32), ("res_norm", C.c_double * 32),
+                ("last", SolveStats), ("it_outer_total", C.c_int32), ("it_A_total", C.c_int32),
+                ("it_S_total", C.c_int32), ("it_I_total", C.c_int32), ("ms_assemble", C.c_double),
+                ("ms_solve", C.c_double), ("ms_total", C.c_double)]
+
+    def as_dict(self):
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k not in ("res_norm", "last")}
+        d["res_norm"] = list(self.res_norm[: max(self.n_newton + 1, 1)])
+        d["last"] = self.last.as_dict()
+        return d
+
+
+P = C.POINTER
+# name: (restype, argtypes) for every entry point declared in include/vms.h
+SIGNATURES = {
+    "vms_ctx_create": (C.c_int, [P(C.c_void_p), C.c_int, C.c_void_p]),
+    "vms_ctx_destroy": (None, [C.c_void_p]),
+    "vms_last_error": (C.c_char_p, [C.c_void_p]),
+    "vms_setup_sizes": (C.c_int, [C.c_int32, C.c_int32, C.c_void_p, P(C.c_int64), P(C.c_int32)]),
+    "vms_setup_build": (C.c_int, [C.c_int32, C.c_int32, C.c_void_p, C.c_int32, C.c_void_p] + [C.c_void_p] * 7 +
+                        [P(C.c_int32), C.c_void_p, C.c_void_p]),
+    "vms_nodal_load": (C.c_int, [C.c_void_p, P(Mesh), C.c_void_p]),
+    "vms_predictor": (C.c_int, [C.c_void_p, P(Mesh), P(TimeInt), P(State)]),
+    "vms_assemble": (C.c_int, [C.c_void_p, P(Mesh), P(Material), P(TimeInt), P(State), C.c_void_p, P(Matrix),
+                               C.c_void_p, C.c_void_p, C.c_uint]),
+    "vms_residual_norm": (C.c_int, [C.c_void_p, P(Mesh), P(TimeInt), P(State), C.c_void_p, P(C.c_double)]),
+    "vms_prepare_system": (C.c_int, [C.c_void_p, P(Mesh), P(Matrix), C.c_void_p, C.c_void_p, C.c_void_p,
+                                     C.c_double, C.c_int]),
+    "vms_spmv": (C.c_int, [C.c_void_p, P(Mesh), P(Matrix), C.c_int, C.c_void_p, C.c_void_p, C.c_int]),
+    "vms_solve_workspace": (C.c_size_t, [P(Mesh), P(SolverOpts)]),
+    "vms_solve_scaled": (C.c_int, [C.c_void_p, P(Mesh), P(Matrix), C.c_void_p, C.c_void_p, P(SolverOpts),
+                                   C.c_void_p, C.c_size_t, P(SolveStats)]),
+    "vms_newton_update": (C.c_int, [C.c_void_p, P(Mesh), P(TimeInt), P(State), C.c_void_p, C.c_void_p]),
+    "vms_step_workspace": (C.c_size_t, [P(Mesh), P(SolverOpts)]),
+    "vms_step": (C.c_int, [C.c_void_p, P(Mesh), P(Material), P(TimeInt), P(State), C.c_void_p, P(Matrix),
+                           P(NewtonOpts), P(SolverOpts), C.c_void_p, C.c_size_t, P(StepStats)]),
+}
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libvms.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with `python -m paper_1809_06350_amd.build`")
+    lib = C.CDLL(path)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib

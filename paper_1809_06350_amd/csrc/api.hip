@@ -1,0 +1,137 @@
+// Context management and the thin C-ABI wrappers around the assembly kernels.
+#include <cstring>
+
+#include "vms_internal.h"
+
+int vms_set_error(vms_ctx *ctx, int code, const char *fmt, ...) {
+  if (ctx) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    ctx->err = buf;
+  }
+  return code;
+}
+
+extern "C" int vms_ctx_create(vms_ctx **out, int device, void *stream) {
+  if (!out) return VMS_ERR_ARG;
+  *out = nullptr;
+  vms_ctx *c = new vms_ctx();
+  c->device = device;
+  c->stream = (hipStream_t)stream;
+  if (hipSetDevice(device) != hipSuccess) {
+    delete c;
+    return VMS_ERR_HIP;
+  }
+  if (hipMalloc((void **)&c->dstat, sizeof(vms_dev_status)) != hipSuccess) {
+    delete c;
+    return VMS_ERR_HIP;
+  }
+  if (hipHostMalloc((void **)&c->h_i, 64 * sizeof(int32_t), hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void **)&c->h_d, 64 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+    if (c->h_i) (void)hipHostFree(c->h_i);
+    (void)hipFree(c->dstat);
+    delete c;
+    return VMS_ERR_HIP;
+  }
+  if (hipMemset(c->dstat, 0, sizeof(vms_dev_status)) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
+    (void)hipHostFree(c->h_i);
+    (void)hipHostFree(c->h_d);
+    (void)hipFree(c->dstat);
+    delete c;
+    return VMS_ERR_HIP;
+  }
+  *out = c;
+  return VMS_OK;
+}
+
+extern "C" void vms_ctx_destroy(vms_ctx *ctx) {
+  if (!ctx) return;
+  (void)hipStreamSynchronize(ctx->stream);
+  if (ctx->dstat) (void)hipFree(ctx->dstat);
+  if (ctx->h_i) (void)hipHostFree(ctx->h_i);
+  if (ctx->h_d) (void)hipHostFree(ctx->h_d);
+  delete ctx;
+}
+
+extern "C" const char *vms_last_error(const vms_ctx *ctx) {
+  if (!ctx) return "null context";
+  return ctx->err.c_str();
+}
+
+static int check_state(vms_ctx *ctx, const vms_state *st) {
+  if (!st || !st->u_n || !st->p_n || !st->v_n || !st->du_n || !st->dp_n || !st->dv_n || !st->u || !st->p ||
+      !st->v || !st->du || !st->dp || !st->dv)
+    return vms_set_error(ctx, VMS_ERR_ARG, "incomplete state");
+  return VMS_OK;
+}
+
+extern "C" int vms_predictor(vms_ctx *ctx, const vms_mesh *mesh, const vms_timeint *ti, vms_state *st) {
+  if (!ctx) return VMS_ERR_ARG;
+  int rc = vms_check_mesh(ctx, mesh);
+  if (rc) return rc;
+  if ((rc = check_state(ctx, st))) return rc;
+  if (!ti || !(ti->dt > 0.0)) return vms_set_error(ctx, VMS_ERR_ARG, "bad time-integration parameters");
+  const vms_ga ga = vms_genalpha(ti);
+  return vms_launch_predictor(ctx, mesh, ga, ti->t_n + ti->dt, st);
+}
+
+extern "C" int vms_assemble(vms_ctx *ctx, const vms_mesh *mesh, const vms_material *mat, const vms_timeint *ti,
+                            const vms_state *st, const double *f_ext, vms_matrix *K, double *R, double *corr,
+                            unsigned flags) {
+  if (!ctx) return VMS_ERR_ARG;
+  int rc = vms_check_mesh(ctx, mesh);
+  if (rc) return rc;
+  if ((rc = check_state(ctx, st))) return rc;
+  if (!mat || !ti || !(ti->dt > 0.0)) return vms_set_error(ctx, VMS_ERR_ARG, "material/timeint missing");
+  if ((flags & VMS_ASM_RESIDUAL) && !R) return vms_set_error(ctx, VMS_ERR_ARG, "R missing");
+  if ((flags & VMS_ASM_RKCORR) && !corr) return vms_set_error(ctx, VMS_ERR_ARG, "corr missing");
+  if ((flags & VMS_ASM_TANGENT) && (!K || !K->A || !K->B || !K->C || !K->D))
+    return vms_set_error(ctx, VMS_ERR_ARG, "K arrays missing");
+  const vms_ga ga = vms_genalpha(ti);
+  if ((rc = vms_launch_clear_inverted(ctx))) return rc;
+  rc = vms_launch_assemble(ctx, mesh, mat, ga, st, f_ext, K, R, corr, flags);
+  if (rc) return rc;
+  VMS_HIP(ctx, hipMemcpyAsync(ctx->h_i, &ctx->dstat->inverted, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+  VMS_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  if (ctx->h_i[0]) return vms_set_error(ctx, VMS_ERR_INVERTED_ELEMENT, "element with J <= 0");
+  return VMS_OK;
+}
+
+extern "C" int vms_residual_norm(vms_ctx *ctx, const vms_mesh *mesh, const vms_timeint *ti, const vms_state *st,
+                                 const double *R, double *norm_host) {
+  if (!ctx) return VMS_ERR_ARG;
+  int rc = vms_check_mesh(ctx, mesh);
+  if (rc) return rc;
+  if ((rc = check_state(ctx, st))) return rc;
+  if (!ti || !R || !norm_host) return vms_set_error(ctx, VMS_ERR_ARG, "vms_residual_norm: bad arguments");
+  const vms_ga ga = vms_genalpha(ti);
+  if ((rc = vms_launch_norm(ctx, mesh, ga, st, R))) return rc;
+  VMS_HIP(ctx, hipMemcpyAsync(ctx->h_d, &ctx->dstat->norm2, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+  VMS_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  *norm_host = sqrt(ctx->h_d[0]);
+  if (!std::isfinite(*norm_host)) return vms_set_error(ctx, VMS_ERR_NAN, "residual norm is not finite");
+  return VMS_OK;
+}
+
+extern "C" int vms_prepare_system(vms_ctx *ctx, const vms_mesh *mesh, vms_matrix *K, const double *R,
+                                  const double *corr, double *rhs_scaled, double eps_diag, int mirror32) {
+  if (!ctx) return VMS_ERR_ARG;
+  int rc = vms_check_mesh(ctx, mesh);
+  if (rc) return rc;
+  if (rhs_scaled && !R) return vms_set_error(ctx, VMS_ERR_ARG, "R missing");
+  return vms_launch_prepare(ctx, mesh, K, R, corr, rhs_scaled, eps_diag, mirror32);
+}
+
+extern "C" int vms_newton_update(vms_ctx *ctx, const vms_mesh *mesh, const vms_timeint *ti, vms_state *st,
+                                 const double *W, const double *x_scaled) {
+  if (!ctx) return VMS_ERR_ARG;
+  int rc = vms_check_mesh(ctx, mesh);
+  if (rc) return rc;
+  if ((rc = check_state(ctx, st))) return rc;
+  if (!ti || !W || !x_scaled) return vms_set_error(ctx, VMS_ERR_ARG, "vms_newton_update: bad arguments");
+  const vms_ga ga = vms_genalpha(ti);
+  return vms_launch_update(ctx, mesh, ga, st, W, x_scaled);
+}

@@ -1,0 +1,146 @@
+// Host-side setup of the node-graph block pattern (integer work only).
+//
+// The tangent [[A, B], [C, D]] of the P1 discretisation couples every pair of
+// nodes that share a tetrahedron, so one CSR pattern over nodes (row_ptr,
+// col, sorted columns, diagonal included) serves all four value arrays.
+// Besides the pattern this file builds
+//   tpos[b]        position of block (j, i) for the block b = (i, j),
+//   diag_pos[i]    position of block (i, i),
+//   elem_blk[e][A*4+B]  position of block (tets[e][A], tets[e][B]),
+//   a greedy element colouring (elements of one colour share no node, so an
+//   element-by-element scatter within a colour is free of write conflicts),
+//   node -> loaded boundary face lists (for the dead-load vector).
+#include <algorithm>
+#include <cstdint>
+#include <cstring>
+#include <vector>
+
+#include "vms_internal.h"
+
+namespace {
+
+struct Graph {
+  std::vector<int32_t> row_ptr, col;
+};
+
+Graph build_graph(int32_t n, int32_t m, const int32_t *tets) {
+  std::vector<int32_t> deg(n, 0);
+  for (int64_t e = 0; e < m; ++e)
+    for (int a = 0; a < 4; ++a) deg[tets[4 * e + a]] += 4;
+  std::vector<int64_t> off(n + 1, 0);
+  for (int32_t i = 0; i < n; ++i) off[i + 1] = off[i] + deg[i];
+  std::vector<int32_t> tmp(off[n]);
+  std::vector<int64_t> fill(off.begin(), off.end() - 1);
+  for (int64_t e = 0; e < m; ++e)
+    for (int a = 0; a < 4; ++a) {
+      int32_t i = tets[4 * e + a];
+      for (int b = 0; b < 4; ++b) tmp[fill[i]++] = tets[4 * e + b];
+    }
+  Graph g;
+  g.row_ptr.assign(n + 1, 0);
+  g.col.reserve(off[n] / 3);
+  for (int32_t i = 0; i < n; ++i) {
+    auto first = tmp.begin() + off[i], last = tmp.begin() + off[i + 1];
+    std::sort(first, last);
+    auto uend = std::unique(first, last);
+    if (first == uend) {          // isolated node: keep a diagonal block
+      g.col.push_back(i);
+    } else {
+      g.col.insert(g.col.end(), first, uend);
+    }
+    g.row_ptr[i + 1] = (int32_t)g.col.size();
+  }
+  return g;
+}
+
+inline int32_t find_block(const Graph &g, int32_t i, int32_t j) {
+  auto first = g.col.begin() + g.row_ptr[i], last = g.col.begin() + g.row_ptr[i + 1];
+  auto it = std::lower_bound(first, last, j);
+  if (it == last || *it != j) return -1;
+  return (int32_t)(it - g.col.begin());
+}
+
+}  // namespace
+
+extern "C" int vms_setup_sizes(int32_t n_nodes, int32_t n_tets, const int32_t *tets,
+                               int64_t *nnzb, int32_t *n_colours) {
+  if (n_nodes <= 0 || n_tets < 0 || (!tets && n_tets > 0) || !nnzb || !n_colours) return VMS_ERR_ARG;
+  for (int64_t k = 0; k < 4 * (int64_t)n_tets; ++k)
+    if (tets[k] < 0 || tets[k] >= n_nodes) return VMS_ERR_ARG;
+  Graph g = build_graph(n_nodes, n_tets, tets);
+  *nnzb = (int64_t)g.col.size();
+  // colouring bound: greedy needs at most (max elements around an element) + 1
+  std::vector<int32_t> cnt(n_nodes, 0);
+  for (int64_t k = 0; k < 4 * (int64_t)n_tets; ++k) cnt[tets[k]]++;
+  int32_t mx = 0;
+  for (int32_t i = 0; i < n_nodes; ++i) mx = std::max(mx, cnt[i]);
+  *n_colours = std::min<int32_t>(4 * mx + 1, std::max<int32_t>(n_tets, 1));
+  return VMS_OK;
+}
+
+extern "C" int vms_setup_build(int32_t n_nodes, int32_t n_tets, const int32_t *tets,
+                               int32_t n_bfaces, const int32_t *bfaces,
+                               int32_t *row_ptr, int32_t *col, int32_t *tpos, int32_t *diag_pos,
+                               int32_t *elem_blk, int32_t *colour_ptr, int32_t *elem_by_colour,
+                               int32_t *n_colours_out, int32_t *nf_ptr, int32_t *nf_face) {
+  if (n_nodes <= 0 || n_tets < 0 || !row_ptr || !col || !tpos || !diag_pos || !elem_blk ||
+      !colour_ptr || !elem_by_colour || !n_colours_out || !nf_ptr || (n_bfaces > 0 && (!bfaces || !nf_face)))
+    return VMS_ERR_ARG;
+  for (int64_t k = 0; k < 4 * (int64_t)n_tets; ++k)
+    if (tets[k] < 0 || tets[k] >= n_nodes) return VMS_ERR_ARG;
+  for (int64_t k = 0; k < 3 * (int64_t)n_bfaces; ++k)
+    if (bfaces[k] < 0 || bfaces[k] >= n_nodes) return VMS_ERR_ARG;
+  Graph g = build_graph(n_nodes, n_tets, tets);
+  const int64_t nnzb = (int64_t)g.col.size();
+  std::memcpy(row_ptr, g.row_ptr.data(), sizeof(int32_t) * (n_nodes + 1));
+  std::memcpy(col, g.col.data(), sizeof(int32_t) * nnzb);
+  for (int32_t i = 0; i < n_nodes; ++i) {
+    diag_pos[i] = find_block(g, i, i);
+    for (int32_t b = g.row_ptr[i]; b < g.row_ptr[i + 1]; ++b) tpos[b] = find_block(g, g.col[b], i);
+  }
+  for (int64_t e = 0; e < n_tets; ++e)
+    for (int a = 0; a < 4; ++a)
+      for (int b = 0; b < 4; ++b)
+        elem_blk[16 * e + 4 * a + b] = find_block(g, tets[4 * e + a], tets[4 * e + b]);
+
+  // greedy colouring in element order
+  std::vector<int32_t> n2e_ptr(n_nodes + 1, 0);
+  for (int64_t k = 0; k < 4 * (int64_t)n_tets; ++k) n2e_ptr[tets[k] + 1]++;
+  for (int32_t i = 0; i < n_nodes; ++i) n2e_ptr[i + 1] += n2e_ptr[i];
+  std::vector<int32_t> n2e(4 * (int64_t)n_tets), fillp(n2e_ptr.begin(), n2e_ptr.end() - 1);
+  for (int64_t e = 0; e < n_tets; ++e)
+    for (int a = 0; a < 4; ++a) n2e[fillp[tets[4 * e + a]]++] = (int32_t)e;
+  std::vector<int32_t> colour(n_tets, -1), mark;
+  int32_t ncol = 0;
+  for (int64_t e = 0; e < n_tets; ++e) {
+    for (int a = 0; a < 4; ++a) {
+      int32_t i = tets[4 * e + a];
+      for (int32_t k = n2e_ptr[i]; k < n2e_ptr[i + 1]; ++k) {
+        int32_t c = colour[n2e[k]];
+        if (c >= 0) {
+          if ((int32_t)mark.size() <= c) mark.resize(c + 1, -1);
+          mark[c] = (int32_t)e;
+        }
+      }
+    }
+    int32_t c = 0;
+    while (c < (int32_t)mark.size() && mark[c] == (int32_t)e) ++c;
+    colour[e] = c;
+    ncol = std::max(ncol, c + 1);
+  }
+  std::fill(colour_ptr, colour_ptr + ncol + 1, 0);
+  for (int64_t e = 0; e < n_tets; ++e) colour_ptr[colour[e] + 1]++;
+  for (int32_t c = 0; c < ncol; ++c) colour_ptr[c + 1] += colour_ptr[c];
+  std::vector<int32_t> cf(colour_ptr, colour_ptr + ncol);
+  for (int64_t e = 0; e < n_tets; ++e) elem_by_colour[cf[colour[e]]++] = (int32_t)e;
+  *n_colours_out = ncol;
+
+  // node -> loaded faces
+  std::fill(nf_ptr, nf_ptr + n_nodes + 1, 0);
+  for (int64_t k = 0; k < 3 * (int64_t)n_bfaces; ++k) nf_ptr[bfaces[k] + 1]++;
+  for (int32_t i = 0; i < n_nodes; ++i) nf_ptr[i + 1] += nf_ptr[i];
+  std::vector<int32_t> ff(nf_ptr, nf_ptr + n_nodes);
+  for (int64_t f = 0; f < n_bfaces; ++f)
+    for (int a = 0; a < 3; ++a) nf_face[ff[bfaces[3 * f + a]]++] = (int32_t)f;
+  return VMS_OK;
+}

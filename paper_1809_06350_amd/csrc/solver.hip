@@ -1,0 +1,926 @@
+// Nested block-preconditioned Krylov solver (section 4) and the time step
+// driver (section 3.3).
+//
+// Levels (section 4.4):
+//   outer         FGMRES on the scaled K* = [[A, B], [C, D]], FP64, right-
+//                 preconditioned by the Schur complement reduction (Alg. 1);
+//   intermediate  GMRES on A (3x3 block-Jacobi right preconditioner, the
+//                 stand-in for the paper's AMG) and GMRES on
+//                 S = D - C A^-1 B (right preconditioner diag(S^),
+//                 S^ = D - C diag(A)^-1 B);
+//   inner         GMRES on A inside the matrix-free Schur product (Alg. 2).
+// Every level is right-preconditioned with x0 = 0 and stops on the
+// least-squares residual |g_{j+1}| <= max(rtol ||b||, atol) or at maxit.
+//
+// Device-resident Arnoldi: the Hessenberg matrix, Givens rotations and the
+// convergence flag live in a per-level control block in device memory; the
+// kernels of an iteration read the `done` flag and return immediately once
+// the level has converged, so the host can enqueue several A-level
+// iterations before it reads the flag back (one host sync per batch).
+// Orthogonalisation is classical Gram-Schmidt with one reorthogonalisation
+// (CGS2: two multi-dot / multi-update passes, O(1) launches per iteration) or
+// modified Gram-Schmidt (one fused dot/axpy launch per basis vector).
+//
+// Mixed form: the intermediate and inner levels run on FP32 copies of the
+// scaled blocks with FP32 Krylov vectors (FP64 accumulation of every sum and
+// FP64 Hessenberg/Givens); the outer FGMRES, its vectors and the Newton
+// update stay FP64.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <type_traits>
+
+#include "linalg.h"
+#include "vms_internal.h"
+
+namespace {
+
+enum { PC_NONE = 0, PC_BJ33 = 1, PC_DIAG = 2 };
+enum { KS_OK = 0, KS_MAXIT = 1, KS_NAN = 2, KS_BREAKDOWN = 3 };
+enum { IF_DONE = 0, IF_ITS = 1, IF_STATUS = 2, IF_COUNTER = 3 };
+
+struct KOff {
+  int m;
+  int64_t H, cs, sn, g, y, h1, h2, scal, part;
+};
+
+inline KOff make_off(int m) {
+  KOff o;
+  o.m = m;
+  int64_t p = 0;
+  o.H = p; p += (int64_t)(m + 1) * m;
+  o.cs = p; p += m;
+  o.sn = p; p += m;
+  o.g = p; p += m + 1;
+  o.y = p; p += m;
+  o.h1 = p; p += m + 1;
+  o.h2 = p; p += m + 1;
+  o.scal = p; p += 8;
+  o.part = p; p += (int64_t)(m + 1) * VMS_MAX_RED_BLOCKS;
+  return o;
+}
+inline int64_t ctrl_doubles(int m) {
+  KOff o = make_off(m);
+  return o.part + (int64_t)(m + 1) * VMS_MAX_RED_BLOCKS;
+}
+
+template <typename T>
+__device__ __forceinline__ double dl(const T *p, int64_t i) { return (double)p[i]; }
+
+// ---- init: beta = ||b||, tolerance, g0 -----------------------------------
+template <typename T>
+__global__ void __launch_bounds__(VMS_BLOCK)
+k_kinit_norm(int64_t nvec, const T *__restrict__ b, double *ctrl, KOff off, int *iflag, double rtol, double atol) {
+  __shared__ double sm[4];
+  double acc = 0.0;
+  for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < nvec; r += (int64_t)gridDim.x * blockDim.x) {
+    const double v = dl(b, r);
+    acc += v * v;
+  }
+  acc = block_sum(acc, sm);
+  if (threadIdx.x == 0) ctrl[off.part + blockIdx.x] = acc;
+  if (last_block_arrived((unsigned *)&iflag[IF_COUNTER])) {
+    double s = 0.0;
+    for (int k = threadIdx.x; k < (int)gridDim.x; k += blockDim.x) s += load_agent(&ctrl[off.part + k]);
+    s = block_sum(s, sm);
+    if (threadIdx.x == 0) {
+      const double beta = sqrt(s);
+      ctrl[off.scal + 0] = beta;
+      ctrl[off.scal + 1] = fmax(rtol * beta, atol);
+      ctrl[off.scal + 2] = beta;
+      ctrl[off.g] = beta;
+      iflag[IF_ITS] = 0;
+      if (!isfinite(beta)) {
+        iflag[IF_STATUS] = KS_NAN;
+        iflag[IF_DONE] = 1;
+      } else {
+        iflag[IF_STATUS] = KS_OK;
+        iflag[IF_DONE] = (beta == 0.0 || beta <= atol) ? 1 : 0;
+      }
+    }
+    reset_counter((unsigned *)&iflag[IF_COUNTER]);
+  }
+}
+
+// V_j = w / scale; Z_j = M^-1 V_j (block-Jacobi 3x3 or point diagonal)
+template <typename T>
+__device__ __forceinline__ void scale_and_precond(int64_t nvec, const T *w, double inv, T *V, T *Z, int pc,
+                                                  const T *pcd) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t t0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (pc == PC_BJ33) {
+    const int64_t nn = nvec / 3;
+    for (int64_t i = t0; i < nn; i += stride) {
+      const double v0 = dl(w, 3 * i) * inv, v1 = dl(w, 3 * i + 1) * inv, v2 = dl(w, 3 * i + 2) * inv;
+      V[3 * i] = (T)v0; V[3 * i + 1] = (T)v1; V[3 * i + 2] = (T)v2;
+      const T *M = pcd + 9 * i;
+      const double a0 = (double)(T)v0, a1 = (double)(T)v1, a2 = (double)(T)v2;
+      Z[3 * i] = (T)(dl(M, 0) * a0 + dl(M, 1) * a1 + dl(M, 2) * a2);
+      Z[3 * i + 1] = (T)(dl(M, 3) * a0 + dl(M, 4) * a1 + dl(M, 5) * a2);
+      Z[3 * i + 2] = (T)(dl(M, 6) * a0 + dl(M, 7) * a1 + dl(M, 8) * a2);
+    }
+  } else {
+    for (int64_t r = t0; r < nvec; r += stride) {
+      const T vv = (T)(dl(w, r) * inv);
+      V[r] = vv;
+      if (pc == PC_DIAG) Z[r] = (T)(dl(pcd, r) * (double)vv);
+    }
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(VMS_BLOCK)
+k_kinit_scale(int64_t nvec, const T *__restrict__ b, T *V0, T *Z0, const double *ctrl, KOff off, const int *iflag,
+              int pc, const T *pcd) {
+  if (iflag[IF_DONE]) return;
+  scale_and_precond(nvec, b, 1.0 / ctrl[off.scal + 0], V0, Z0, pc, pcd);
+}
+
+// out[k] = <V_k, w>, k < nk  (CGS pass), partial sums then last-block finalize
+template <typename T>
+__global__ void __launch_bounds__(VMS_BLOCK)
+k_mdot(int64_t nvec, const T *__restrict__ V, int nk, const T *__restrict__ w, double *ctrl, KOff off,
+       int64_t out_off, int *iflag) {
+  if (iflag[IF_DONE]) return;
+  __shared__ double sm[4];
+  const int NB = gridDim.x;
+  const int64_t stride = (int64_t)NB * blockDim.x;
+  const int64_t t0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  for (int k0 = 0; k0 < nk; k0 += 4) {
+    double a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+    const int kk = min(4, nk - k0);
+    for (int64_t r = t0; r < nvec; r += stride) {
+      const double wr = dl(w, r);
+      a0 += dl(V, (int64_t)k0 * nvec + r) * wr;
+      if (kk > 1) a1 += dl(V, (int64_t)(k0 + 1) * nvec + r) * wr;
+      if (kk > 2) a2 += dl(V, (int64_t)(k0 + 2) * nvec + r) * wr;
+      if (kk > 3) a3 += dl(V, (int64_t)(k0 + 3) * nvec + r) * wr;
+    }
+    a0 = block_sum(a0, sm);
+    if (kk > 1) a1 = block_sum(a1, sm);
+    if (kk > 2) a2 = block_sum(a2, sm);
+    if (kk > 3) a3 = block_sum(a3, sm);
+    if (threadIdx.x == 0) {
+      double *pp = ctrl + off.part + (int64_t)k0 * NB + blockIdx.x;
+      pp[0] = a0;
+      if (kk > 1) pp[NB] = a1;
+      if (kk > 2) pp[2 * NB] = a2;
+      if (kk > 3) pp[3 * NB] = a3;
+    }
+  }
+  if (last_block_arrived((unsigned *)&iflag[IF_COUNTER])) {
+    for (int k = 0; k < nk; ++k) {
+      double s = 0.0;
+      for (int q = threadIdx.x; q < NB; q += blockDim.x) s += load_agent(&ctrl[off.part + (int64_t)k * NB + q]);
+      s = block_sum(s, sm);
+      if (threadIdx.x == 0) ctrl[out_off + k] = s;
+    }
+    reset_counter((unsigned *)&iflag[IF_COUNTER]);
+  }
+}
+
+// w -= sum_k coef[k] V_k ; optionally accumulate ||w||^2 and finish the
+// Arnoldi step j (Hessenberg column, Givens rotation, convergence test).
+template <typename T, bool NORM>
+__global__ void __launch_bounds__(VMS_BLOCK)
+k_mupdate(int64_t nvec, const T *__restrict__ V, int nk, T *w, double *ctrl, KOff off, int64_t coef_off,
+          int *iflag, int j, int cgs, int maxit) {
+  if (iflag[IF_DONE]) return;
+  __shared__ double sm[4];
+  __shared__ double coef[64];
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t t0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  double ss = 0.0;
+  // the basis is processed in chunks of 64 coefficients staged through LDS;
+  // rows owned by this thread are revisited per chunk (partial results in w)
+  const int nchunk = (nk + 63) / 64;
+  for (int c = 0; c < nchunk; ++c) {
+    const int k0 = c * 64, kn = min(64, nk - k0);
+    __syncthreads();
+    if (threadIdx.x < kn) coef[threadIdx.x] = ctrl[coef_off + k0 + threadIdx.x];
+    __syncthreads();
+    const bool last = (c == nchunk - 1);
+    for (int64_t r = t0; r < nvec; r += stride) {
+      double acc = dl(w, r);
+      for (int k = 0; k < kn; ++k) acc -= coef[k] * dl(V, (int64_t)(k0 + k) * nvec + r);
+      const T out = (T)acc;
+      w[r] = out;
+      if (NORM && last) ss += (double)out * (double)out;
+    }
+  }
+  if (!NORM) return;
+  ss = block_sum(ss, sm);
+  if (threadIdx.x == 0) ctrl[off.part + blockIdx.x] = ss;
+  if (last_block_arrived((unsigned *)&iflag[IF_COUNTER])) {
+    double s = 0.0;
+    for (int q = threadIdx.x; q < (int)gridDim.x; q += blockDim.x) s += load_agent(&ctrl[off.part + q]);
+    s = block_sum(s, sm);
+    if (threadIdx.x == 0) {
+      const int m1 = off.m + 1;
+      double *col = ctrl + off.H + (int64_t)j * m1;
+      double *cs = ctrl + off.cs, *sn = ctrl + off.sn, *g = ctrl + off.g;
+      const double hn = sqrt(s);
+      if (cgs)
+        for (int i = 0; i <= j; ++i) col[i] = ctrl[off.h1 + i] + ctrl[off.h2 + i];
+      col[j + 1] = hn;
+      for (int i = 0; i < j; ++i) {
+        const double t = cs[i] * col[i] + sn[i] * col[i + 1];
+        col[i + 1] = -sn[i] * col[i] + cs[i] * col[i + 1];
+        col[i] = t;
+      }
+      const double den = hypot(col[j], col[j + 1]);
+      double c = 1.0, sv = 0.0;
+      if (den > 0.0) { c = col[j] / den; sv = col[j + 1] / den; }
+      cs[j] = c;
+      sn[j] = sv;
+      col[j] = den;
+      col[j + 1] = 0.0;
+      g[j + 1] = -sv * g[j];
+      g[j] = c * g[j];
+      const double res = fabs(g[j + 1]);
+      ctrl[off.scal + 2] = res;
+      ctrl[off.scal + 3] = hn;
+      iflag[IF_ITS] = j + 1;
+      if (!isfinite(res) || !isfinite(hn)) {
+        iflag[IF_STATUS] = KS_NAN;
+        iflag[IF_DONE] = 1;
+      } else if (den == 0.0) {
+        iflag[IF_STATUS] = KS_BREAKDOWN;
+        iflag[IF_ITS] = j;   // singular column: keep the previous solution
+        iflag[IF_DONE] = 1;
+      } else if (res <= ctrl[off.scal + 1] || hn == 0.0) {
+        iflag[IF_STATUS] = KS_OK;
+        iflag[IF_DONE] = 1;
+      } else if (j + 1 >= maxit) {
+        iflag[IF_STATUS] = KS_MAXIT;
+        iflag[IF_DONE] = 1;
+      }
+    }
+    reset_counter((unsigned *)&iflag[IF_COUNTER]);
+  }
+}
+
+// MGS step k: w -= H[k-1,j] V_{k-1} (k > 0), then H[k,j] = <w, V_k>
+template <typename T>
+__global__ void __launch_bounds__(VMS_BLOCK)
+k_mgs_step(int64_t nvec, const T *__restrict__ V, int k, T *w, double *ctrl, KOff off, int *iflag, int j) {
+  if (iflag[IF_DONE]) return;
+  __shared__ double sm[4];
+  const int m1 = off.m + 1;
+  double *col = ctrl + off.H + (int64_t)j * m1;
+  const double hprev = (k > 0) ? col[k - 1] : 0.0;
+  const T *Vp = V + (int64_t)(k > 0 ? k - 1 : 0) * nvec;
+  const T *Vk = V + (int64_t)k * nvec;
+  double acc = 0.0;
+  for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < nvec; r += (int64_t)gridDim.x * blockDim.x) {
+    double wr = dl(w, r);
+    if (k > 0) {
+      wr -= hprev * dl(Vp, r);
+      w[r] = (T)wr;
+      wr = (double)(T)wr;
+    }
+    acc += wr * dl(Vk, r);
+  }
+  acc = block_sum(acc, sm);
+  if (threadIdx.x == 0) ctrl[off.part + blockIdx.x] = acc;
+  if (last_block_arrived((unsigned *)&iflag[IF_COUNTER])) {
+    double s = 0.0;
+    for (int q = threadIdx.x; q < (int)gridDim.x; q += blockDim.x) s += load_agent(&ctrl[off.part + q]);
+    s = block_sum(s, sm);
+    if (threadIdx.x == 0) col[k] = s;
+    reset_counter((unsigned *)&iflag[IF_COUNTER]);
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(VMS_BLOCK)
+k_normalize(int64_t nvec, const T *__restrict__ w, T *V1, T *Z1, const double *ctrl, KOff off, const int *iflag,
+            int pc, const T *pcd) {
+  if (iflag[IF_DONE]) return;
+  scale_and_precond(nvec, w, 1.0 / ctrl[off.scal + 3], V1, Z1, pc, pcd);
+}
+
+// y = R^-1 g (column-oriented back substitution on the rotated Hessenberg)
+__global__ void __launch_bounds__(VMS_BLOCK) k_trisolve(double *ctrl, KOff off, const int *iflag) {
+  __shared__ double gs[1024];
+  const int k = iflag[IF_ITS];
+  const int m1 = off.m + 1;
+  const double *H = ctrl + off.H;
+  double *y = ctrl + off.y;
+  for (int i = threadIdx.x; i < k; i += blockDim.x) gs[i] = ctrl[off.g + i];
+  __syncthreads();
+  for (int i = k - 1; i >= 0; --i) {
+    const double yi = gs[i] / H[(int64_t)i * m1 + i];
+    __syncthreads();
+    for (int l = threadIdx.x; l < i; l += blockDim.x) gs[l] -= H[(int64_t)i * m1 + l] * yi;
+    if (threadIdx.x == 0) y[i] = yi;
+    __syncthreads();
+  }
+}
+
+// x = sum_{l < its} y_l Z_l
+template <typename T>
+__global__ void __launch_bounds__(VMS_BLOCK)
+k_combine(int64_t nvec, const T *__restrict__ Z, const double *ctrl, KOff off, const int *iflag, T *x) {
+  __shared__ double ys[64];
+  const int k = iflag[IF_ITS];
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t t0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  for (int64_t r = t0; r < nvec; r += stride) x[r] = (T)0;
+  for (int c0 = 0; c0 < k; c0 += 64) {
+    const int kn = min(64, k - c0);
+    __syncthreads();
+    if (threadIdx.x < kn) ys[threadIdx.x] = ctrl[off.y + c0 + threadIdx.x];
+    __syncthreads();
+    for (int64_t r = t0; r < nvec; r += stride) {
+      double acc = (c0 == 0) ? 0.0 : dl(x, r);
+      for (int l = 0; l < kn; ++l) acc += ys[l] * dl(Z, (int64_t)(c0 + l) * nvec + r);
+      x[r] = (T)acc;
+    }
+  }
+}
+
+// ---- preconditioner setup --------------------------------------------------
+// inverse of the 3x3 diagonal blocks of the scaled A
+template <typename T>
+__global__ void k_bj33_setup(int n, const int32_t *diag_pos, int64_t nnzb, const double *A, T *Minv) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int64_t b = diag_pos[i];
+  double a[9];
+  for (int e = 0; e < 9; ++e) a[e] = A[e * nnzb + b];
+  const double c00 = a[4] * a[8] - a[5] * a[7], c01 = a[5] * a[6] - a[3] * a[8], c02 = a[3] * a[7] - a[4] * a[6];
+  const double det = a[0] * c00 + a[1] * c01 + a[2] * c02;
+  const double id = (det != 0.0) ? 1.0 / det : 0.0;
+  double inv[9];
+  inv[0] = c00 * id;
+  inv[1] = (a[2] * a[7] - a[1] * a[8]) * id;
+  inv[2] = (a[1] * a[5] - a[2] * a[4]) * id;
+  inv[3] = c01 * id;
+  inv[4] = (a[0] * a[8] - a[2] * a[6]) * id;
+  inv[5] = (a[2] * a[3] - a[0] * a[5]) * id;
+  inv[6] = c02 * id;
+  inv[7] = (a[1] * a[6] - a[0] * a[7]) * id;
+  inv[8] = (a[0] * a[4] - a[1] * a[3]) * id;
+  for (int e = 0; e < 9; ++e) Minv[9 * (int64_t)i + e] = (T)inv[e];
+}
+
+// 1 / diag(S^),  S^_ii = D_ii - sum_k sum_c C_ik,c B_ki,c / A_kk,cc
+template <typename T>
+__global__ void k_shat_diag(int n, const int32_t *rp, const int32_t *col, const int32_t *tpos,
+                            const int32_t *diag_pos, int64_t nnzb, const double *A, const double *B,
+                            const double *C, const double *D, T *sdinv) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double s = D[diag_pos[i]];
+  for (int b = rp[i]; b < rp[i + 1]; ++b) {
+    const int k = col[b];
+    const int64_t dk = diag_pos[k], bt = tpos[b];
+    for (int c = 0; c < 3; ++c) {
+      const double akk = A[(4 * c) * nnzb + dk];
+      if (akk != 0.0) s -= C[c * nnzb + b] * B[c * nnzb + bt] / akk;
+    }
+  }
+  sdinv[i] = (T)((s != 0.0 && isfinite(s)) ? 1.0 / s : 1.0);
+}
+
+// full [n][4] FP64 <-> split velocity [n][3] / pressure [n] of type T
+template <typename T>
+__global__ void k_split(int n, const double *full, T *v, T *p) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int64_t o = 4 * (int64_t)i;
+  v[3 * (int64_t)i] = (T)full[o];
+  v[3 * (int64_t)i + 1] = (T)full[o + 1];
+  v[3 * (int64_t)i + 2] = (T)full[o + 2];
+  p[i] = (T)full[o + 3];
+}
+template <typename T>
+__global__ void k_merge(int n, const T *v, const T *p, double *full) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int64_t o = 4 * (int64_t)i;
+  full[o] = (double)v[3 * (int64_t)i];
+  full[o + 1] = (double)v[3 * (int64_t)i + 1];
+  full[o + 2] = (double)v[3 * (int64_t)i + 2];
+  full[o + 3] = (double)p[i];
+}
+__global__ void k_clear_ints(int *p, int n) {
+  const int i = threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+
+inline int grid1(int64_t n) { return (int)((n + VMS_BLOCK - 1) / VMS_BLOCK); }
+
+// ---- workspace carving -------------------------------------------------------
+struct Carver {
+  char *base;
+  size_t off = 0;
+  template <typename X>
+  X *take(int64_t count) {
+    off = (off + 255) & ~(size_t)255;
+    X *p = base ? (X *)(base + off) : nullptr;
+    off += sizeof(X) * (size_t)count;
+    return p;
+  }
+};
+
+template <typename T>
+struct KLevel {
+  int64_t nvec = 0;
+  int m = 0, nb = 1;
+  T *V = nullptr, *Z = nullptr, *W = nullptr;
+  double *ctrl = nullptr;
+  int *iflag = nullptr;
+  KOff off{};
+  void carve(Carver &cv, int64_t nv, int mm) {
+    nvec = nv;
+    m = std::max(mm, 1);
+    nb = vms_red_blocks(nv);
+    V = cv.take<T>((int64_t)(m + 1) * nv);
+    Z = cv.take<T>((int64_t)(m + 1) * nv);
+    W = cv.take<T>(nv);
+    off = make_off(m);
+    ctrl = cv.take<double>(ctrl_doubles(m));
+    iflag = cv.take<int>(8);
+  }
+};
+
+template <typename T>
+struct Nested {
+  vms_ctx *ctx;
+  const vms_mesh *mesh;
+  const vms_matrix *K;
+  const vms_solver_opts *o;
+  int n;
+  int64_t nnzb;
+  const T *A, *B, *C, *D;  // scaled blocks in the level precision
+  KLevel<T> LA, LS;
+  T *rv, *rp, *xh, *xp, *xv, *xbar, *xt, *Minv, *sdinv;
+  vms_solve_stats *stats;
+  int err = VMS_OK;
+
+  void carve(Carver &cv, const vms_mesh *m_, const vms_solver_opts *o_) {
+    const int64_t nn = m_->n_nodes;
+    LA.carve(cv, 3 * nn, std::max(o_->maxit_A, o_->maxit_I));
+    LS.carve(cv, nn, o_->maxit_S);
+    rv = cv.take<T>(3 * nn);
+    rp = cv.take<T>(nn);
+    xh = cv.take<T>(3 * nn);
+    xp = cv.take<T>(nn);
+    xv = cv.take<T>(3 * nn);
+    xbar = cv.take<T>(3 * nn);
+    xt = cv.take<T>(3 * nn);
+    Minv = cv.take<T>(9 * nn);
+    sdinv = cv.take<T>(nn);
+  }
+
+  int sync_flags(KLevel<T> &L) {
+    VMS_HIP(ctx, hipMemcpyAsync(ctx->h_i, L.iflag, 4 * sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+    VMS_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    return VMS_OK;
+  }
+
+  // generic right-preconditioned GMRES with a device preconditioner
+  // (op: W = Op Z_j enqueued by the callback)
+  template <typename OpF>
+  int gmres(KLevel<T> &L, const T *b, T *x, double rtol, double atol, int maxit, int pc, const T *pcd,
+            bool sync_each, int &est, OpF op, int &its_out) {
+    hipStream_t s = ctx->stream;
+    maxit = std::min(maxit, L.m);
+    hipLaunchKernelGGL(k_clear_ints, dim3(1), dim3(64), 0, s, L.iflag, 4);
+    hipLaunchKernelGGL(k_kinit_norm<T>, dim3(L.nb), dim3(VMS_BLOCK), 0, s, L.nvec, b, L.ctrl, L.off, L.iflag, rtol,
+                       atol);
+    hipLaunchKernelGGL(k_kinit_scale<T>, dim3(L.nb), dim3(VMS_BLOCK), 0, s, L.nvec, b, L.V, L.Z, L.ctrl, L.off,
+                       L.iflag, pc, pcd);
+    VMS_LAUNCH_CHECK(ctx);
+    int j = 0, rc;
+    bool done = false;
+    if (sync_each) {
+      if ((rc = sync_flags(L))) return rc;
+      done = ctx->h_i[IF_DONE] != 0;
+    }
+    int batch = sync_each ? 1 : std::max(1, est);
+    while (!done && j < maxit) {
+      const int nbt = std::min(batch, maxit - j);
+      for (int i = 0; i < nbt; ++i, ++j) {
+        if ((rc = op(j))) return rc;
+        if ((rc = orth(L, j, maxit))) return rc;
+        hipLaunchKernelGGL(k_normalize<T>, dim3(L.nb), dim3(VMS_BLOCK), 0, s, L.nvec, L.W,
+                           L.V + (int64_t)(j + 1) * L.nvec, L.Z + (int64_t)(j + 1) * L.nvec, L.ctrl, L.off,
+                           L.iflag, pc, pcd);
+      }
+      VMS_LAUNCH_CHECK(ctx);
+      if ((rc = sync_flags(L))) return rc;
+      done = ctx->h_i[IF_DONE] != 0;
+      if (!sync_each) batch = std::min(2 * batch, 64);
+    }
+    if (!done) {  // cannot happen: the Givens step flags maxit; keep a guard
+      if ((rc = sync_flags(L))) return rc;
+    }
+    const int status = ctx->h_i[IF_STATUS];
+    its_out = ctx->h_i[IF_ITS];
+    hipLaunchKernelGGL(k_trisolve, dim3(1), dim3(VMS_BLOCK), 0, s, L.ctrl, L.off, L.iflag);
+    hipLaunchKernelGGL(k_combine<T>, dim3(L.nb), dim3(VMS_BLOCK), 0, s, L.nvec, L.Z, L.ctrl, L.off, L.iflag, x);
+    VMS_LAUNCH_CHECK(ctx);
+    est = std::max(1, its_out);
+    if (status == KS_NAN) return vms_set_error(ctx, VMS_ERR_NAN, "NaN/Inf in a Krylov level");
+    return VMS_OK;
+  }
+
+  int orth(KLevel<T> &L, int j, int maxit) { return orth_level(ctx, L, j, maxit, o->orth); }
+
+  static int orth_level(vms_ctx *ctx, KLevel<T> &L, int j, int maxit, int mode) {
+    hipStream_t s = ctx->stream;
+    if (mode == VMS_ORTH_MGS) {
+      for (int k = 0; k <= j; ++k)
+        hipLaunchKernelGGL(k_mgs_step<T>, dim3(L.nb), dim3(VMS_BLOCK), 0, s, L.nvec, L.V, k, L.W, L.ctrl, L.off,
+                           L.iflag, j);
+      const int64_t coef = L.off.H + (int64_t)j * (L.m + 1) + j;
+      hipLaunchKernelGGL((k_mupdate<T, true>), dim3(L.nb), dim3(VMS_BLOCK), 0, s, L.nvec,
+                         L.V + (int64_t)j * L.nvec, 1, L.W, L.ctrl, L.off, coef, L.iflag, j, 0, maxit);
+    } else {
+      hipLaunchKernelGGL(k_mdot<T>, dim3(L.nb), dim3(VMS_BLOCK), 0, s, L.nvec, L.V, j + 1, L.W, L.ctrl, L.off,
+                         L.off.h1, L.iflag);
+      hipLaunchKernelGGL((k_mupdate<T, false>), dim3(L.nb), dim3(VMS_BLOCK), 0, s, L.nvec, L.V, j + 1, L.W,
+                         L.ctrl, L.off, L.off.h1, L.iflag, j, 1, maxit);
+      hipLaunchKernelGGL(k_mdot<T>, dim3(L.nb), dim3(VMS_BLOCK), 0, s, L.nvec, L.V, j + 1, L.W, L.ctrl, L.off,
+                         L.off.h2, L.iflag);
+      hipLaunchKernelGGL((k_mupdate<T, true>), dim3(L.nb), dim3(VMS_BLOCK), 0, s, L.nvec, L.V, j + 1, L.W,
+                         L.ctrl, L.off, L.off.h2, L.iflag, j, 1, maxit);
+    }
+    VMS_LAUNCH_CHECK(ctx);
+    return VMS_OK;
+  }
+
+  // x = A^-1 b by GMRES with block-Jacobi (intermediate or inner level)
+  int solve_A(const T *b, T *x, bool inner) {
+    int its = 0;
+    const double rtol = inner ? o->rtol_I : o->rtol_A, atol = inner ? o->atol_I : o->atol_A;
+    const int maxit = inner ? o->maxit_I : o->maxit_A;
+    int &est = inner ? ctx->est_I : ctx->est_A;
+    auto op = [&](int j) -> int {
+      hipLaunchKernelGGL((k_spmv_A<T, T>), dim3(spmv_grid(n)), dim3(VMS_BLOCK), 0, ctx->stream, n, nnzb,
+                         mesh->row_ptr, mesh->col, A, LA.Z + (int64_t)j * LA.nvec, LA.W, (const T *)nullptr, 1.0,
+                         LA.iflag + IF_DONE);
+      return VMS_OK;
+    };
+    int rc = gmres(LA, b, x, rtol, atol, maxit, PC_BJ33, Minv, false, est, op, its);
+    if (inner) { stats->n_I_solves++; stats->it_I += its; }
+    else { stats->n_A_solves++; stats->it_A += its; }
+    return rc;
+  }
+
+  // x_p = S^-1 b by GMRES with the matrix-free Schur product (Algorithm 2)
+  int solve_S(const T *b, T *x) {
+    int its = 0;
+    auto op = [&](int j) -> int {
+      const T *z = LS.Z + (int64_t)j * LS.nvec;
+      // x-bar = B z
+      hipLaunchKernelGGL((k_spmv_B<T, T>), dim3(spmv_grid(n)), dim3(VMS_BLOCK), 0, ctx->stream, n, nnzb,
+                         mesh->row_ptr, mesh->col, B, z, xbar, (const T *)nullptr, 1.0, (const int *)nullptr);
+      // x-tilde = A^-1 x-bar (inner solver)
+      int rc = solve_A(xbar, xt, true);
+      if (rc) return rc;
+      // W = D z - C x-tilde
+      hipLaunchKernelGGL((k_spmv_CD<T, T>), dim3(spmv_grid(n)), dim3(VMS_BLOCK), 0, ctx->stream, n, nnzb,
+                         mesh->row_ptr, mesh->col, C, D, xt, z, LS.W, (const T *)nullptr, -1.0, 1.0,
+                         (const int *)nullptr);
+      return VMS_OK;
+    };
+    int rc = gmres(LS, b, x, o->rtol_S, o->atol_S, o->maxit_S, PC_DIAG, sdinv, true, ctx->est_S, op, its);
+    stats->n_S_solves++;
+    stats->it_S += its;
+    return rc;
+  }
+
+  // z = P_SCR^-1 v (Algorithm 1 and its partial-factorization variants)
+  int apply(const double *v_full, double *z_full) {
+    hipStream_t s = ctx->stream;
+    hipLaunchKernelGGL(k_split<T>, dim3(grid1(n)), dim3(VMS_BLOCK), 0, s, n, v_full, rv, rp);
+    VMS_LAUNCH_CHECK(ctx);
+    int rc;
+    const int var = o->precond;
+    if (var == VMS_PC_LDU || var == VMS_PC_LOWER) {
+      if ((rc = solve_A(rv, xh, false))) return rc;                 // step 1
+      hipLaunchKernelGGL((k_spmv_CD<T, T>), dim3(spmv_grid(n)), dim3(VMS_BLOCK), 0, s, n, nnzb, mesh->row_ptr,
+                         mesh->col, C, D, xh, (const T *)nullptr, rp, rp, -1.0, 0.0, (const int *)nullptr);  // step 2
+    }
+    if ((rc = solve_S(rp, xp))) return rc;                           // step 3
+    if (var == VMS_PC_LDU || var == VMS_PC_UPPER) {
+      hipLaunchKernelGGL((k_spmv_B<T, T>), dim3(spmv_grid(n)), dim3(VMS_BLOCK), 0, s, n, nnzb, mesh->row_ptr,
+                         mesh->col, B, xp, rv, rv, -1.0, (const int *)nullptr);  // step 4
+      if ((rc = solve_A(rv, xv, false))) return rc;                 // step 5
+    } else if (var == VMS_PC_LOWER) {
+      hipLaunchKernelGGL(k_merge<T>, dim3(grid1(n)), dim3(VMS_BLOCK), 0, s, n, xh, xp, z_full);
+      VMS_LAUNCH_CHECK(ctx);
+      return VMS_OK;
+    } else {  // block diagonal
+      if ((rc = solve_A(rv, xv, false))) return rc;
+    }
+    hipLaunchKernelGGL(k_merge<T>, dim3(grid1(n)), dim3(VMS_BLOCK), 0, s, n, xv, xp, z_full);
+    VMS_LAUNCH_CHECK(ctx);
+    return VMS_OK;
+  }
+
+  int setup_precond() {
+    hipLaunchKernelGGL(k_bj33_setup<T>, dim3(grid1(n)), dim3(VMS_BLOCK), 0, ctx->stream, n, mesh->diag_pos, nnzb,
+                       K->A, Minv);
+    hipLaunchKernelGGL(k_shat_diag<T>, dim3(grid1(n)), dim3(VMS_BLOCK), 0, ctx->stream, n, mesh->row_ptr, mesh->col,
+                       mesh->tpos, mesh->diag_pos, nnzb, K->A, K->B, K->C, K->D, sdinv);
+    VMS_LAUNCH_CHECK(ctx);
+    return VMS_OK;
+  }
+};
+
+struct Outer {
+  KLevel<double> L;
+  void carve(Carver &cv, const vms_mesh *m, const vms_solver_opts *o) { L.carve(cv, 4 * (int64_t)m->n_nodes, o->maxit); }
+};
+
+size_t workspace_bytes(const vms_mesh *m, const vms_solver_opts *o) {
+  Carver cv{nullptr};
+  Outer ou;
+  ou.carve(cv, m, o);
+  if (o->precision == VMS_MIXED) {
+    Nested<float> ne;
+    ne.carve(cv, m, o);
+  } else {
+    Nested<double> ne;
+    ne.carve(cv, m, o);
+  }
+  return cv.off + 256;
+}
+
+int check_opts(vms_ctx *ctx, const vms_solver_opts *o) {
+  if (!o || o->maxit <= 0 || o->maxit_A <= 0 || o->maxit_S <= 0 || o->maxit_I <= 0 || o->maxit > 1000 ||
+      o->maxit_A > 1000 || o->maxit_S > 1000 || o->maxit_I > 1000)
+    return vms_set_error(ctx, VMS_ERR_ARG, "solver options: maxit must be in [1, 1000]");
+  if (o->precond < VMS_PC_LDU || o->precond > VMS_PC_DIAG)
+    return vms_set_error(ctx, VMS_ERR_ARG, "unknown preconditioner variant");
+  if (o->precision != VMS_FP64 && o->precision != VMS_MIXED)
+    return vms_set_error(ctx, VMS_ERR_ARG, "unknown precision");
+  return VMS_OK;
+}
+
+template <typename T>
+int solve_impl(vms_ctx *ctx, const vms_mesh *mesh, const vms_matrix *K, const double *rhs, double *x,
+               const vms_solver_opts *o, void *ws, vms_solve_stats *stats) {
+  Carver cv{(char *)ws};
+  Outer ou;
+  ou.carve(cv, mesh, o);
+  Nested<T> ne;
+  ne.carve(cv, mesh, o);
+  ne.ctx = ctx;
+  ne.mesh = mesh;
+  ne.K = K;
+  ne.o = o;
+  ne.n = mesh->n_nodes;
+  ne.nnzb = mesh->nnzb;
+  ne.stats = stats;
+  if (std::is_same<T, float>::value) {
+    ne.A = (const T *)K->A32; ne.B = (const T *)K->B32; ne.C = (const T *)K->C32; ne.D = (const T *)K->D32;
+  } else {
+    ne.A = (const T *)K->A; ne.B = (const T *)K->B; ne.C = (const T *)K->C; ne.D = (const T *)K->D;
+  }
+  int rc = ne.setup_precond();
+  if (rc) return rc;
+  KLevel<double> &L = ou.L;
+  const int n = mesh->n_nodes;
+  int est_outer = 1;
+  auto op = [&](int j) -> int {
+    // host-driven preconditioner: Z_j = P_SCR^-1 V_j, then W = K Z_j
+    int r = ne.apply(L.V + (int64_t)j * L.nvec, L.Z + (int64_t)j * L.nvec);
+    if (r) return r;
+    hipLaunchKernelGGL(k_spmv_full, dim3(spmv_grid(n)), dim3(VMS_BLOCK), 0, ctx->stream, n, mesh->nnzb,
+                       mesh->row_ptr, mesh->col, K->A, K->B, K->C, K->D, L.Z + (int64_t)j * L.nvec, L.W,
+                       L.iflag + IF_DONE);
+    return VMS_OK;
+  };
+  // the outer level runs its own copy of the generic loop in FP64
+  hipStream_t s = ctx->stream;
+  const int maxit = std::min(o->maxit, L.m);
+  hipLaunchKernelGGL(k_clear_ints, dim3(1), dim3(64), 0, s, L.iflag, 4);
+  hipLaunchKernelGGL(k_kinit_norm<double>, dim3(L.nb), dim3(VMS_BLOCK), 0, s, L.nvec, rhs, L.ctrl, L.off, L.iflag,
+                     o->rtol, o->atol);
+  hipLaunchKernelGGL(k_kinit_scale<double>, dim3(L.nb), dim3(VMS_BLOCK), 0, s, L.nvec, rhs, L.V, L.Z, L.ctrl, L.off,
+                     L.iflag, (int)PC_NONE, (const double *)nullptr);
+  VMS_LAUNCH_CHECK(ctx);
+  VMS_HIP(ctx, hipMemcpyAsync(ctx->h_i, L.iflag, 4 * sizeof(int), hipMemcpyDeviceToHost, s));
+  VMS_HIP(ctx, hipMemcpyAsync(ctx->h_d, L.ctrl + L.off.scal, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
+  VMS_HIP(ctx, hipStreamSynchronize(s));
+  stats->res0 = ctx->h_d[0];
+  bool done = ctx->h_i[IF_DONE] != 0;
+  int j = 0;
+  while (!done && j < maxit) {
+    if ((rc = op(j))) return rc;
+    if ((rc = Nested<double>::orth_level(ctx, L, j, maxit, o->orth))) return rc;
+    hipLaunchKernelGGL(k_normalize<double>, dim3(L.nb), dim3(VMS_BLOCK), 0, s, L.nvec, L.W,
+                       L.V + (int64_t)(j + 1) * L.nvec, L.Z + (int64_t)(j + 1) * L.nvec, L.ctrl, L.off, L.iflag,
+                       (int)PC_NONE, (const double *)nullptr);
+    VMS_LAUNCH_CHECK(ctx);
+    ++j;
+    VMS_HIP(ctx, hipMemcpyAsync(ctx->h_i, L.iflag, 4 * sizeof(int), hipMemcpyDeviceToHost, s));
+    VMS_HIP(ctx, hipStreamSynchronize(s));
+    done = ctx->h_i[IF_DONE] != 0;
+  }
+  (void)est_outer;
+  const int status = ctx->h_i[IF_STATUS];
+  stats->n_outer = ctx->h_i[IF_ITS];
+  hipLaunchKernelGGL(k_trisolve, dim3(1), dim3(VMS_BLOCK), 0, s, L.ctrl, L.off, L.iflag);
+  hipLaunchKernelGGL(k_combine<double>, dim3(L.nb), dim3(VMS_BLOCK), 0, s, L.nvec, L.Z, L.ctrl, L.off, L.iflag, x);
+  VMS_LAUNCH_CHECK(ctx);
+  VMS_HIP(ctx, hipMemcpyAsync(ctx->h_d, L.ctrl + L.off.scal, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
+  VMS_HIP(ctx, hipStreamSynchronize(s));
+  stats->res = (stats->n_outer > 0) ? ctx->h_d[2] : ctx->h_d[0];
+  if (status == KS_NAN) return vms_set_error(ctx, VMS_ERR_NAN, "NaN/Inf in the outer FGMRES");
+  if (status == KS_BREAKDOWN) return vms_set_error(ctx, VMS_ERR_BREAKDOWN, "outer Arnoldi breakdown");
+  if (status == KS_MAXIT) {
+    vms_set_error(ctx, VMS_NOT_CONVERGED, "outer FGMRES reached maxit = %d", maxit);
+    return VMS_NOT_CONVERGED;
+  }
+  return VMS_OK;
+}
+
+}  // namespace
+
+extern "C" size_t vms_solve_workspace(const vms_mesh *mesh, const vms_solver_opts *opts) {
+  if (!mesh || !opts || mesh->n_nodes <= 0) return 0;
+  return workspace_bytes(mesh, opts);
+}
+
+extern "C" int vms_solve_scaled(vms_ctx *ctx, const vms_mesh *mesh, const vms_matrix *K, const double *rhs_scaled,
+                                double *x_scaled, const vms_solver_opts *opts, void *workspace,
+                                size_t workspace_bytes_in, vms_solve_stats *stats) {
+  if (!ctx) return VMS_ERR_ARG;
+  int rc = vms_check_mesh(ctx, mesh);
+  if (rc) return rc;
+  if ((rc = check_opts(ctx, opts))) return rc;
+  if (!K || !K->A || !K->B || !K->C || !K->D || !rhs_scaled || !x_scaled || !stats || !workspace)
+    return vms_set_error(ctx, VMS_ERR_ARG, "vms_solve_scaled: missing argument");
+  if (opts->precision == VMS_MIXED && (!K->A32 || !K->B32 || !K->C32 || !K->D32))
+    return vms_set_error(ctx, VMS_ERR_ARG, "mixed precision needs the FP32 mirrors");
+  const size_t need = workspace_bytes(mesh, opts);
+  if (workspace_bytes_in < need)
+    return vms_set_error(ctx, VMS_ERR_WORKSPACE, "workspace too small: %zu < %zu", workspace_bytes_in, need);
+  void *ws = (void *)(((uintptr_t)workspace + 255) & ~(uintptr_t)255);
+  std::memset(stats, 0, sizeof(*stats));
+  const auto t0 = std::chrono::steady_clock::now();
+  if (opts->precision == VMS_MIXED)
+    rc = solve_impl<float>(ctx, mesh, K, rhs_scaled, x_scaled, opts, ws, stats);
+  else
+    rc = solve_impl<double>(ctx, mesh, K, rhs_scaled, x_scaled, opts, ws, stats);
+  stats->status = rc;
+  stats->ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  return rc;
+}
+
+int vms_launch_spmv(vms_ctx *ctx, const vms_mesh *mesh, const vms_matrix *K, int op, const void *x, void *y,
+                    int fp32) {
+  const int n = mesh->n_nodes;
+  const int64_t nnzb = mesh->nnzb;
+  dim3 gr(spmv_grid(n)), bl(VMS_BLOCK);
+  hipStream_t s = ctx->stream;
+  if (fp32 && op == VMS_OP_FULL) return vms_set_error(ctx, VMS_ERR_ARG, "FULL product is FP64 only");
+  if (fp32 ? (!K->A32 || !K->B32 || !K->C32 || !K->D32) : (!K->A || !K->B || !K->C || !K->D))
+    return vms_set_error(ctx, VMS_ERR_ARG, "matrix arrays missing");
+  const int *nd = nullptr;
+  switch (op) {
+    case VMS_OP_FULL:
+      hipLaunchKernelGGL(k_spmv_full, gr, bl, 0, s, n, nnzb, mesh->row_ptr, mesh->col, K->A, K->B, K->C, K->D,
+                         (const double *)x, (double *)y, nd);
+      break;
+    case VMS_OP_A:
+      if (fp32)
+        hipLaunchKernelGGL((k_spmv_A<float, float>), gr, bl, 0, s, n, nnzb, mesh->row_ptr, mesh->col, K->A32,
+                           (const float *)x, (float *)y, (const float *)nullptr, 1.0, nd);
+      else
+        hipLaunchKernelGGL((k_spmv_A<double, double>), gr, bl, 0, s, n, nnzb, mesh->row_ptr, mesh->col, K->A,
+                           (const double *)x, (double *)y, (const double *)nullptr, 1.0, nd);
+      break;
+    case VMS_OP_B:
+      if (fp32)
+        hipLaunchKernelGGL((k_spmv_B<float, float>), gr, bl, 0, s, n, nnzb, mesh->row_ptr, mesh->col, K->B32,
+                           (const float *)x, (float *)y, (const float *)nullptr, 1.0, nd);
+      else
+        hipLaunchKernelGGL((k_spmv_B<double, double>), gr, bl, 0, s, n, nnzb, mesh->row_ptr, mesh->col, K->B,
+                           (const double *)x, (double *)y, (const double *)nullptr, 1.0, nd);
+      break;
+    case VMS_OP_C:
+      if (fp32)
+        hipLaunchKernelGGL((k_spmv_CD<float, float>), gr, bl, 0, s, n, nnzb, mesh->row_ptr, mesh->col, K->C32,
+                           K->D32, (const float *)x, (const float *)nullptr, (float *)y, (const float *)nullptr, 1.0,
+                           0.0, nd);
+      else
+        hipLaunchKernelGGL((k_spmv_CD<double, double>), gr, bl, 0, s, n, nnzb, mesh->row_ptr, mesh->col, K->C, K->D,
+                           (const double *)x, (const double *)nullptr, (double *)y, (const double *)nullptr, 1.0,
+                           0.0, nd);
+      break;
+    case VMS_OP_D:
+      if (fp32)
+        hipLaunchKernelGGL((k_spmv_CD<float, float>), gr, bl, 0, s, n, nnzb, mesh->row_ptr, mesh->col, K->C32,
+                           K->D32, (const float *)nullptr, (const float *)x, (float *)y, (const float *)nullptr, 0.0,
+                           1.0, nd);
+      else
+        hipLaunchKernelGGL((k_spmv_CD<double, double>), gr, bl, 0, s, n, nnzb, mesh->row_ptr, mesh->col, K->C, K->D,
+                           (const double *)nullptr, (const double *)x, (double *)y, (const double *)nullptr, 0.0,
+                           1.0, nd);
+      break;
+    default:
+      return vms_set_error(ctx, VMS_ERR_ARG, "unknown operator id %d", op);
+  }
+  VMS_LAUNCH_CHECK(ctx);
+  return VMS_OK;
+}
+
+extern "C" int vms_spmv(vms_ctx *ctx, const vms_mesh *mesh, const vms_matrix *K, int op, const void *x, void *y,
+                        int fp32) {
+  if (!ctx) return VMS_ERR_ARG;
+  int rc = vms_check_mesh(ctx, mesh);
+  if (rc) return rc;
+  if (!K || !x || !y) return vms_set_error(ctx, VMS_ERR_ARG, "vms_spmv: missing argument");
+  return vms_launch_spmv(ctx, mesh, K, op, x, y, fp32);
+}
+
+// ---- time step ---------------------------------------------------------------
+extern "C" size_t vms_step_workspace(const vms_mesh *mesh, const vms_solver_opts *opts) {
+  if (!mesh || !opts || mesh->n_nodes <= 0) return 0;
+  return workspace_bytes(mesh, opts) + 4 * (size_t)(4 * mesh->n_nodes) * sizeof(double) + 4 * 256;
+}
+
+extern "C" int vms_step(vms_ctx *ctx, const vms_mesh *mesh, const vms_material *mat, const vms_timeint *ti,
+                        vms_state *st, const double *f_ext, vms_matrix *K, const vms_newton_opts *no,
+                        const vms_solver_opts *so, void *workspace, size_t workspace_bytes_in,
+                        vms_step_stats *stats) {
+  if (!ctx) return VMS_ERR_ARG;
+  int rc = vms_check_mesh(ctx, mesh);
+  if (rc) return rc;
+  if ((rc = check_opts(ctx, so))) return rc;
+  if (!mat || !ti || !st || !K || !no || !stats || !workspace || no->l_max <= 0 || !(ti->dt > 0.0))
+    return vms_set_error(ctx, VMS_ERR_ARG, "vms_step: missing argument");
+  const size_t need = vms_step_workspace(mesh, so);
+  if (workspace_bytes_in < need)
+    return vms_set_error(ctx, VMS_ERR_WORKSPACE, "workspace too small: %zu < %zu", workspace_bytes_in, need);
+  std::memset(stats, 0, sizeof(*stats));
+  const auto t_start = std::chrono::steady_clock::now();
+  const int n = mesh->n_nodes;
+  Carver cv{(char *)(((uintptr_t)workspace + 255) & ~(uintptr_t)255)};
+  double *R = cv.take<double>(4 * (int64_t)n);
+  double *corr = cv.take<double>(4 * (int64_t)n);
+  double *rhs = cv.take<double>(4 * (int64_t)n);
+  double *x = cv.take<double>(4 * (int64_t)n);
+  char *sws = (char *)cv.take<char>(0);
+  const size_t sws_bytes = workspace_bytes_in - (size_t)(sws - (char *)workspace);
+  const vms_ga ga = vms_genalpha(ti);
+  hipStream_t s = ctx->stream;
+  if ((rc = vms_launch_predictor(ctx, mesh, ga, ti->t_n + ti->dt, st))) return rc;
+  hipLaunchKernelGGL(k_clear_ints, dim3(1), dim3(64), 0, s, &ctx->dstat->inverted, 1);
+  double R0 = -1.0;
+  const bool mixed = so->precision == VMS_MIXED;
+  stats->status = VMS_NOT_CONVERGED;
+  for (int l = 1; l <= no->l_max; ++l) {
+    auto ta = std::chrono::steady_clock::now();
+    if ((rc = vms_launch_assemble(ctx, mesh, mat, ga, st, f_ext, nullptr, R, nullptr, VMS_ASM_RESIDUAL))) return rc;
+    if ((rc = vms_launch_norm(ctx, mesh, ga, st, R))) return rc;
+    VMS_HIP(ctx, hipMemcpyAsync(ctx->h_d, ctx->dstat, 24, hipMemcpyDeviceToHost, s));
+    VMS_HIP(ctx, hipStreamSynchronize(s));
+    const int inverted = ((const int *)ctx->h_d)[0];
+    const double nrm = sqrt(ctx->h_d[2]);
+    if (inverted) return vms_set_error(ctx, VMS_ERR_INVERTED_ELEMENT, "element with J <= 0 at iteration %d", l);
+    if (!std::isfinite(nrm)) return vms_set_error(ctx, VMS_ERR_NAN, "residual norm is not finite");
+    if (l - 1 < 32) stats->res_norm[l - 1] = nrm;
+    if (R0 < 0.0) R0 = nrm;
+    if ((R0 > 0.0 && nrm / R0 <= no->tol_R) || nrm <= no->tol_A) {
+      stats->status = VMS_OK;
+      stats->ms_assemble += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - ta).count();
+      break;
+    }
+    const unsigned fl = VMS_ASM_TANGENT | (no->rk_corr ? VMS_ASM_RKCORR : 0u);
+    if ((rc = vms_launch_assemble(ctx, mesh, mat, ga, st, f_ext, K, nullptr, no->rk_corr ? corr : nullptr, fl)))
+      return rc;
+    if ((rc = vms_launch_prepare(ctx, mesh, K, R, no->rk_corr ? corr : nullptr, rhs, no->eps_diag, mixed ? 1 : 0)))
+      return rc;
+    VMS_HIP(ctx, hipStreamSynchronize(s));
+    auto tb = std::chrono::steady_clock::now();
+    stats->ms_assemble += std::chrono::duration<double, std::milli>(tb - ta).count();
+    vms_solve_stats ss;
+    rc = vms_solve_scaled(ctx, mesh, K, rhs, x, so, sws, sws_bytes, &ss);
+    stats->ms_solve += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tb).count();
+    stats->last = ss;
+    stats->it_outer_total += ss.n_outer;
+    stats->it_A_total += ss.it_A;
+    stats->it_S_total += ss.it_S;
+    stats->it_I_total += ss.it_I;
+    if (rc < 0) return rc;
+    if ((rc = vms_launch_update(ctx, mesh, ga, st, K->W, x))) return rc;
+    stats->n_newton = l;
+  }
+  VMS_HIP(ctx, hipStreamSynchronize(s));
+  stats->ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+  if (stats->status != VMS_OK) {
+    vms_set_error(ctx, VMS_NOT_CONVERGED, "Newton did not converge in %d iterations", no->l_max);
+    return VMS_NOT_CONVERGED;
+  }
+  return VMS_OK;
+}

@@ -1,0 +1,130 @@
+// Internal declarations shared by the HIP translation units of libvms.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdint>
+#include <cstdio>
+#include <string>
+
+#include "vms.h"
+
+#define VMS_BLOCK 256
+#define VMS_MAX_RED_BLOCKS 1024
+
+// Small device-side status area owned by a context (allocated at create).
+struct vms_dev_status {
+  int inverted;        // an element had J <= 0 (sticky until cleared)
+  int pad0;
+  unsigned counter;    // last-block counter of the norm reduction
+  int pad1;
+  double norm2;        // result of the residual-norm reduction
+  double part[VMS_MAX_RED_BLOCKS];
+};
+
+struct vms_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+  vms_dev_status *dstat = nullptr;   // device
+  int32_t *h_i = nullptr;            // pinned host scratch (ints)
+  double *h_d = nullptr;             // pinned host scratch (doubles)
+  int est_A = 8, est_I = 8, est_S = 8;  // Krylov iteration estimates (batching)
+};
+
+int vms_set_error(vms_ctx *ctx, int code, const char *fmt, ...);
+
+#define VMS_HIP(ctx, call)                                                          \
+  do {                                                                              \
+    hipError_t e_ = (call);                                                         \
+    if (e_ != hipSuccess)                                                           \
+      return vms_set_error((ctx), VMS_ERR_HIP, "%s failed: %s (%s:%d)", #call,      \
+                           hipGetErrorString(e_), __FILE__, __LINE__);              \
+  } while (0)
+
+#define VMS_LAUNCH_CHECK(ctx) VMS_HIP(ctx, hipGetLastError())
+
+// ---------------------------------------------------------------------------
+// device helpers
+
+// Workgroups of a launch are handed to the 8 XCDs round-robin; remap the
+// hardware block id so that each XCD processes one contiguous slab of rows
+// (better reuse of gathered vector entries in that XCD's L2).
+__device__ __forceinline__ int xcd_block(int bid, int nblocks) {
+  const int full = (nblocks / 8) * 8;
+  if (bid >= full) return bid;
+  return (bid & 7) * (nblocks >> 3) + (bid >> 3);
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Sum over a 256-thread block; every thread receives the same value.
+// Fixed order, hence deterministic.
+__device__ __forceinline__ double block_sum(double v, double *sm) {
+  v = wave_sum(v);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) sm[w] = v;
+  __syncthreads();
+  const double r = (sm[0] + sm[1]) + (sm[2] + sm[3]);
+  __syncthreads();
+  return r;
+}
+
+__device__ __forceinline__ double load_agent(const double *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Returns true in exactly one block (the last to arrive); that block may then
+// read every block's partial results (written before this call).
+__device__ __forceinline__ bool last_block_arrived(unsigned *counter) {
+  __shared__ int last;
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const unsigned prev = atomicAdd(counter, 1u);
+    last = (prev == gridDim.x - 1) ? 1 : 0;
+  }
+  __syncthreads();
+  if (last) __threadfence();
+  return last != 0;
+}
+
+__device__ __forceinline__ void reset_counter(unsigned *counter) {
+  if (threadIdx.x == 0) atomicExch(counter, 0u);
+}
+
+inline int vms_red_blocks(int64_t n) {
+  int64_t nb = (n + 2 * VMS_BLOCK - 1) / (2 * VMS_BLOCK);
+  if (nb < 1) nb = 1;
+  if (nb > VMS_MAX_RED_BLOCKS) nb = VMS_MAX_RED_BLOCKS;
+  return (int)nb;
+}
+
+// ---------------------------------------------------------------------------
+// launchers implemented in assembly.hip / linalg.hip, used by solver.hip
+
+struct vms_ga {   // generalized-alpha constants
+  double am, af, gm, dt, c2, c3, load;
+};
+vms_ga vms_genalpha(const vms_timeint *ti);
+
+int vms_check_mesh(vms_ctx *ctx, const vms_mesh *m);
+int vms_launch_assemble(vms_ctx *ctx, const vms_mesh *mesh, const vms_material *mat,
+                        const vms_ga &ga, const vms_state *st, const double *f_ext,
+                        vms_matrix *K, double *R, double *corr, unsigned flags);
+int vms_launch_clear_inverted(vms_ctx *ctx);
+int vms_launch_norm(vms_ctx *ctx, const vms_mesh *mesh, const vms_ga &ga, const vms_state *st,
+                    const double *R);
+int vms_launch_prepare(vms_ctx *ctx, const vms_mesh *mesh, vms_matrix *K, const double *R,
+                       const double *corr, double *rhs, double eps_diag, int mirror32);
+int vms_launch_update(vms_ctx *ctx, const vms_mesh *mesh, const vms_ga &ga, vms_state *st,
+                      const double *W, const double *x);
+int vms_launch_predictor(vms_ctx *ctx, const vms_mesh *mesh, const vms_ga &ga, double t_np1,
+                         vms_state *st);
+int vms_launch_spmv(vms_ctx *ctx, const vms_mesh *mesh, const vms_matrix *K, int op,
+                    const void *x, void *y, int fp32);

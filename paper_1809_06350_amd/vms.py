@@ -1,0 +1,256 @@
+"""Python binding of libvms: device buffers from PyTorch, every step in HIP.
+
+The functions here only marshal arguments: they allocate tensors for the
+C ABI (include/vms.h), pass their device pointers and the current torch
+stream, and turn status codes into exceptions.  No part of the Newton step
+runs in Python; if libvms.so is missing, or no HIP device is present, the
+calls raise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+VMS_OK, VMS_NOT_CONVERGED = 0, 1
+ASM_RESIDUAL, ASM_TANGENT, ASM_RKCORR = 1, 2, 4
+OP_FULL, OP_A, OP_B, OP_C, OP_D = 0, 1, 2, 3, 4
+PC_LDU, PC_UPPER, PC_LOWER, PC_DIAG = 0, 1, 2, 3
+FP64, MIXED = 0, 1
+ORTH_CGS2, ORTH_MGS = 0, 1
+
+STATE_KEYS = ("u_n", "p_n", "v_n", "du_n", "dp_n", "dv_n", "u", "p", "v", "du", "dp", "dv")
+
+
+class VmsError(RuntimeError):
+    def __init__(self, what, code, msg):
+        super().__init__(f"{what}: status {code}: {msg}")
+        self.code = code
+
+
+def solver_opts(rtol=1e-8, atol=1e-50, maxit=200, rtol_A=1e-6, atol_A=1e-50, maxit_A=500,
+                rtol_S=1e-6, atol_S=1e-50, maxit_S=200, rtol_I=1e-4, atol_I=1e-50, maxit_I=500,
+                precond=PC_LDU, precision=FP64, orth=ORTH_CGS2) -> L.SolverOpts:
+    return L.SolverOpts(rtol, atol, maxit, rtol_A, atol_A, maxit_A, rtol_S, atol_S, maxit_S,
+                        rtol_I, atol_I, maxit_I, precond, precision, orth, 0)
+
+
+def newton_opts(tol_R=1e-8, tol_A=1e-50, l_max=20, rk_corr=1, eps_diag=1e-15) -> L.NewtonOpts:
+    return L.NewtonOpts(tol_R, tol_A, l_max, rk_corr, eps_diag)
+
+
+def time_int(dt, rho_inf=0.5, t_n=0.0, t_load=0.0) -> L.TimeInt:
+    return L.TimeInt(dt, rho_inf, t_n, t_load)
+
+
+def _p(t):
+    return None if t is None else t.data_ptr()
+
+
+@dataclass
+class Matrix:
+    A: torch.Tensor
+    B: torch.Tensor
+    C: torch.Tensor
+    D: torch.Tensor
+    W: torch.Tensor
+    A32: torch.Tensor | None = None
+    B32: torch.Tensor | None = None
+    C32: torch.Tensor | None = None
+    D32: torch.Tensor | None = None
+
+    def c(self) -> L.Matrix:
+        return L.Matrix(_p(self.A), _p(self.B), _p(self.C), _p(self.D), _p(self.A32), _p(self.B32),
+                        _p(self.C32), _p(self.D32), _p(self.W))
+
+
+class Problem:
+    """One mesh + material on one device: pattern, colouring, dead load, context."""
+
+    def __init__(self, mesh, mat, device="cuda:0"):
+        self.lib = L.load()
+        self.dev = torch.device(device)
+        if self.dev.type != "cuda" or not torch.cuda.is_available():
+            raise RuntimeError("libvms needs a HIP device (torch.cuda is not available)")
+        lib = self.lib
+        self.mesh = mesh
+        n, m, f = mesh.n_nodes, mesh.n_tets, int(mesh.bfaces.shape[0])
+        tets = np.ascontiguousarray(mesh.tets, dtype=np.int32)
+        bfaces = np.ascontiguousarray(mesh.bfaces, dtype=np.int32).reshape(-1, 3)
+        nnzb = C.c_int64()
+        ncb = C.c_int32()
+        self._check(lib.vms_setup_sizes(n, m, tets.ctypes.data, C.byref(nnzb), C.byref(ncb)), "vms_setup_sizes",
+                    ctx=False)
+        nz = nnzb.value
+        h = {"row_ptr": np.zeros(n + 1, np.int32), "col": np.zeros(nz, np.int32), "tpos": np.zeros(nz, np.int32),
+             "diag_pos": np.zeros(n, np.int32), "elem_blk": np.zeros(16 * m, np.int32),
+             "colour_ptr": np.zeros(ncb.value + 1, np.int32), "elem_by_colour": np.zeros(m, np.int32),
+             "nf_ptr": np.zeros(n + 1, np.int32), "nf_face": np.zeros(max(3 * f, 1), np.int32)}
+        ncol = C.c_int32()
+        self._check(lib.vms_setup_build(n, m, tets.ctypes.data, f, bfaces.ctypes.data if f else None,
+                                        *(h[k].ctypes.data for k in ("row_ptr", "col", "tpos", "diag_pos",
+                                                                     "elem_blk", "colour_ptr", "elem_by_colour")),
+                                        C.byref(ncol), h["nf_ptr"].ctypes.data, h["nf_face"].ctypes.data),
+                    "vms_setup_build", ctx=False)
+        self.host = h
+        self.n_colours = ncol.value
+        self.colour_ptr = np.ascontiguousarray(h["colour_ptr"][: self.n_colours + 1])
+        self.nnzb = nz
+        dev = self.dev
+
+        def up(a, dt):
+            return torch.from_numpy(np.ascontiguousarray(a, dtype=dt)).to(dev)
+
+        self.d = {"X": up(mesh.X, np.float64), "tets": up(tets, np.int32),
+                  "bfaces": up(bfaces if f else np.zeros((1, 3)), np.int32),
+                  "traction": up(mesh.traction if f else np.zeros((1, 3)), np.float64),
+                  "dir_mask": up(mesh.dir_mask, np.uint8), "dir_vel": up(mesh.dir_vel, np.float64),
+                  "fibre": up(mesh.fibre, np.float64) if mesh.fibre is not None else None}
+        for k in ("row_ptr", "col", "tpos", "diag_pos", "elem_blk", "elem_by_colour", "nf_ptr", "nf_face"):
+            self.d[k] = up(h[k], np.int32)
+        d = self.d
+        self.cmesh = L.Mesh(n, m, f, self.n_colours, nz, _p(d["X"]), _p(d["tets"]), _p(d["bfaces"]),
+                            _p(d["traction"]), _p(d["dir_mask"]), _p(d["dir_vel"]), _p(d["fibre"]),
+                            _p(d["row_ptr"]), _p(d["col"]), _p(d["tpos"]), _p(d["diag_pos"]), _p(d["elem_blk"]),
+                            _p(d["elem_by_colour"]), _p(d["nf_ptr"]), _p(d["nf_face"]),
+                            self.colour_ptr.ctypes.data)
+        self.set_material(mat)
+        self.stream = torch.cuda.current_stream(dev)
+        ctx = C.c_void_p()
+        rc = lib.vms_ctx_create(C.byref(ctx), dev.index or 0, C.c_void_p(self.stream.cuda_stream))
+        if rc != 0:
+            raise VmsError("vms_ctx_create", rc, "no usable HIP device")
+        self.ctx = ctx
+        self.f_ext = torch.zeros(3 * n, dtype=torch.float64, device=dev)
+        self._check(lib.vms_nodal_load(self.ctx, C.byref(self.cmesh), _p(self.f_ext)), "vms_nodal_load")
+        self._ws = None
+
+    # ---- helpers -----------------------------------------------------------
+    def set_material(self, mat):
+        kappa = float(mat.kappa) if np.isfinite(mat.kappa) else 0.0
+        self.mat = mat
+        self.cmat = L.Material(int(mat.kind), mat.rho0, mat.mu, kappa, mat.k1, mat.k2, mat.kd, mat.c_m)
+
+    def _check(self, rc, what, ctx=True, allow_nc=False):
+        if rc == 0 or (allow_nc and rc == VMS_NOT_CONVERGED):
+            return rc
+        msg = self.lib.vms_last_error(self.ctx).decode() if ctx else ""
+        raise VmsError(what, rc, msg)
+
+    def __del__(self):
+        try:
+            if getattr(self, "ctx", None):
+                self.lib.vms_ctx_destroy(self.ctx)
+                self.ctx = None
+        except Exception:
+            pass
+
+    def workspace(self, nbytes):
+        if self._ws is None or self._ws.numel() < nbytes:
+            self._ws = torch.empty(int(nbytes), dtype=torch.uint8, device=self.dev)
+        return self._ws
+
+    def new_state(self, init=None):
+        """Device state; ``init`` maps any of u, p, v, du, dp, dv (numpy) to y_n."""
+        n = self.mesh.n_nodes
+        st = {}
+        for k in STATE_KEYS:
+            base = k[:-2] if k.endswith("_n") else k
+            shape = (n,) if base in ("p", "dp") else (n, 3)
+            st[k] = torch.zeros(shape, dtype=torch.float64, device=self.dev)
+        if init:
+            for k, v in init.items():
+                st[k + "_n"].copy_(torch.from_numpy(np.asarray(v, dtype=np.float64)))
+                st[k].copy_(torch.from_numpy(np.asarray(v, dtype=np.float64)))
+        return st
+
+    @staticmethod
+    def cstate(st):
+        return L.State(*(_p(st[k]) for k in STATE_KEYS))
+
+    @staticmethod
+    def roll(st):
+        """y_n <- y_{n+1} after a converged step."""
+        for k in ("u", "p", "v", "du", "dp", "dv"):
+            st[k + "_n"].copy_(st[k])
+
+    def new_matrix(self, mirror32=False) -> Matrix:
+        nz, n, dev = self.nnzb, self.mesh.n_nodes, self.dev
+        f64 = dict(dtype=torch.float64, device=dev)
+        f32 = dict(dtype=torch.float32, device=dev)
+        K = Matrix(torch.zeros(9, nz, **f64), torch.zeros(3, nz, **f64), torch.zeros(3, nz, **f64),
+                   torch.zeros(nz, **f64), torch.ones(n, 4, **f64))
+        if mirror32:
+            K.A32, K.B32 = torch.zeros(9, nz, **f32), torch.zeros(3, nz, **f32)
+            K.C32, K.D32 = torch.zeros(3, nz, **f32), torch.zeros(nz, **f32)
+        return K
+
+    # ---- entry points ----------------------------------------------------------
+    def predictor(self, st, ti):
+        self._check(self.lib.vms_predictor(self.ctx, C.byref(self.cmesh), C.byref(ti), C.byref(self.cstate(st))),
+                    "vms_predictor")
+
+    def assemble(self, st, ti, flags, K=None, R=None, corr=None, load=True):
+        n = self.mesh.n_nodes
+        if flags & ASM_RESIDUAL and R is None:
+            R = torch.empty(n, 4, dtype=torch.float64, device=self.dev)
+        if flags & ASM_RKCORR and corr is None:
+            corr = torch.empty(n, 4, dtype=torch.float64, device=self.dev)
+        if flags & ASM_TANGENT and K is None:
+            K = self.new_matrix()
+        cK = K.c() if K is not None else L.Matrix()
+        self._check(self.lib.vms_assemble(self.ctx, C.byref(self.cmesh), C.byref(self.cmat), C.byref(ti),
+                                          C.byref(self.cstate(st)), _p(self.f_ext) if load else None,
+                                          C.byref(cK), _p(R), _p(corr), flags), "vms_assemble")
+        return K, R, corr
+
+    def residual_norm(self, st, ti, R):
+        out = C.c_double()
+        self._check(self.lib.vms_residual_norm(self.ctx, C.byref(self.cmesh), C.byref(ti), C.byref(self.cstate(st)),
+                                               _p(R), C.byref(out)), "vms_residual_norm")
+        return out.value
+
+    def prepare(self, K, R, corr=None, eps_diag=1e-15, mirror32=False):
+        rhs = torch.empty(self.mesh.n_nodes, 4, dtype=torch.float64, device=self.dev)
+        self._check(self.lib.vms_prepare_system(self.ctx, C.byref(self.cmesh), C.byref(K.c()), _p(R), _p(corr),
+                                                _p(rhs), eps_diag, 1 if mirror32 else 0), "vms_prepare_system")
+        return rhs
+
+    def spmv(self, K, op, x, fp32=False):
+        n = self.mesh.n_nodes
+        shape = {OP_FULL: (n, 4), OP_A: (n, 3), OP_B: (n, 3), OP_C: (n,), OP_D: (n,)}[op]
+        y = torch.empty(shape, dtype=torch.float32 if fp32 else torch.float64, device=self.dev)
+        self._check(self.lib.vms_spmv(self.ctx, C.byref(self.cmesh), C.byref(K.c()), op, _p(x), _p(y),
+                                      1 if fp32 else 0), "vms_spmv")
+        return y
+
+    def solve_scaled(self, K, rhs, opts, x=None, allow_nc=False):
+        nb = self.lib.vms_solve_workspace(C.byref(self.cmesh), C.byref(opts))
+        ws = self.workspace(nb + 512)
+        if x is None:
+            x = torch.empty_like(rhs)
+        stats = L.SolveStats()
+        self._check(self.lib.vms_solve_scaled(self.ctx, C.byref(self.cmesh), C.byref(K.c()), _p(rhs), _p(x),
+                                              C.byref(opts), _p(ws), ws.numel(), C.byref(stats)),
+                    "vms_solve_scaled", allow_nc=allow_nc)
+        return x, stats.as_dict()
+
+    def newton_update(self, st, ti, K, x):
+        self._check(self.lib.vms_newton_update(self.ctx, C.byref(self.cmesh), C.byref(ti), C.byref(self.cstate(st)),
+                                               _p(K.W), _p(x)), "vms_newton_update")
+
+    def step(self, st, ti, nopts, sopts, K=None, allow_nc=False):
+        if K is None:
+            K = self.new_matrix(mirror32=(sopts.precision == MIXED))
+        nb = self.lib.vms_step_workspace(C.byref(self.cmesh), C.byref(sopts))
+        ws = self.workspace(nb + 512)
+        stats = L.StepStats()
+        self._check(self.lib.vms_step(self.ctx, C.byref(self.cmesh), C.byref(self.cmat), C.byref(ti),
+                                      C.byref(self.cstate(st)), _p(self.f_ext), C.byref(K.c()), C.byref(nopts),
+                                      C.byref(sopts), _p(ws), ws.numel(), C.byref(stats)),
+                    "vms_step", allow_nc=allow_nc)
+        return stats.as_dict(), K
