@@ -106,6 +106,8 @@ def main():
     ap.add_argument("--size", type=int, default=64)
     ap.add_argument("--nu", type=float, default=0.499)
     ap.add_argument("--forms", default="fp64,mixed")
+    ap.add_argument("--shat-degree", type=int, default=8)
+    ap.add_argument("--shat-ratio", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -124,8 +126,10 @@ def main():
     n, nnzb = mesh.n_nodes, prob.nnzb
     nopts = V.newton_opts(tol_R=1e-8, l_max=20)
     forms = {
-        "fp64": V.solver_opts(rtol=1e-8, rtol_A=1e-6, rtol_S=1e-6, rtol_I=1e-4),
-        "mixed": V.solver_opts(rtol=1e-8, rtol_A=1e-5, rtol_S=1e-5, rtol_I=1e-3, precision=V.MIXED),
+        "fp64": V.solver_opts(rtol=1e-8, rtol_A=1e-6, rtol_S=1e-6, rtol_I=1e-4, shat_degree=args.shat_degree,
+                              shat_ratio=args.shat_ratio),
+        "mixed": V.solver_opts(rtol=1e-8, rtol_A=1e-5, rtol_S=1e-5, rtol_I=1e-3, precision=V.MIXED,
+                               shat_degree=args.shat_degree, shat_ratio=args.shat_ratio),
     }
     results = {}
     for name in args.forms.split(","):
@@ -170,6 +174,7 @@ def main():
            "data": "synthetic",
            "config": {"workload": f"cube{N}^3 Kuhn tets, nu={args.nu}, neo-Hookean, dt=1e-3, Newton/FGMRES 1e-8",
                       "nodes": n, "tets": mesh.n_tets, "unknowns": 4 * n, "nnzb": nnzb,
+                      "shat_degree": args.shat_degree, "shat_ratio": args.shat_ratio,
                       "parallelism": "single GPU"},
            "roofline": roof}
     out.update(extra)

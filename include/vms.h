@@ -128,7 +128,9 @@ typedef struct {
   int32_t precond;    /* VMS_PC_* */
   int32_t precision;  /* VMS_FP64 or VMS_MIXED */
   int32_t orth;       /* VMS_ORTH_* */
-  int32_t reserved;
+  int32_t shat_degree;/* right preconditioner of the Schur solve: 0 = diag(S^)^-1; k > 0 = degree-k
+                         Chebyshev polynomial in diag(S^)^-1 S^ on [lmax/shat_ratio, lmax] */
+  double shat_ratio;  /* lmax / lmin of the Chebyshev interval (used when shat_degree > 0) */
 } vms_solver_opts;
 
 typedef struct {

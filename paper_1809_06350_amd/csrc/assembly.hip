@@ -503,13 +503,15 @@ k_resnorm(int n, vms_ga ga, const uint8_t *dir, StateP sp, const double *R, vms_
   }
   acc = block_sum(acc, sm);
   if (threadIdx.x == 0) ds->part[blockIdx.x] = acc;
-  if (last_block_arrived(&ds->counter)) {
-    double s = 0.0;
-    for (int k = threadIdx.x; k < (int)gridDim.x; k += blockDim.x) s += load_agent(&ds->part[k]);
-    s = block_sum(s, sm);
-    if (threadIdx.x == 0) ds->norm2 = s;
-    reset_counter(&ds->counter);
-  }
+}
+
+// second pass of the norm: fixed-order sum of the per-workgroup partials
+__global__ void __launch_bounds__(VMS_BLOCK) k_resnorm_finalize(int nb, vms_dev_status *ds) {
+  __shared__ double sm[4];
+  double s = 0.0;
+  for (int k = threadIdx.x; k < nb; k += blockDim.x) s += ds->part[k];
+  s = block_sum(s, sm);
+  if (threadIdx.x == 0) ds->norm2 = s;
 }
 
 // W_ii = |K_ii|^(-1/2) (>= eps) else 1; Dirichlet dofs get a unit diagonal and W = 1
@@ -689,6 +691,7 @@ int vms_launch_norm(vms_ctx *ctx, const vms_mesh *mesh, const vms_ga &ga, const 
   const int nb = vms_red_blocks(n);
   hipLaunchKernelGGL(k_resnorm, dim3(nb), dim3(VMS_BLOCK), 0, ctx->stream, n, ga, mesh->dir_mask, mk_state(st),
                      R, ctx->dstat);
+  hipLaunchKernelGGL(k_resnorm_finalize, dim3(1), dim3(VMS_BLOCK), 0, ctx->stream, nb, ctx->dstat);
   VMS_LAUNCH_CHECK(ctx);
   return VMS_OK;
 }

@@ -68,10 +68,17 @@ inline int64_t ctrl_doubles(int m) {
 template <typename T>
 __device__ __forceinline__ double dl(const T *p, int64_t i) { return (double)p[i]; }
 
-// ---- init: beta = ||b||, tolerance, g0 -----------------------------------
+// ---- reductions ------------------------------------------------------------
+// Every reduction writes one partial per workgroup (part[blk * ld + k]) and a
+// separate single-workgroup kernel sums them in a fixed order: no atomics and
+// no device-scope fences (on a multi-XCD device those write back the L2),
+// deterministic results; the kernel boundary makes the partials visible.
+
+// partial sums of ||b||^2
 template <typename T>
 __global__ void __launch_bounds__(VMS_BLOCK)
-k_kinit_norm(int64_t nvec, const T *__restrict__ b, double *ctrl, KOff off, int *iflag, double rtol, double atol) {
+k_norm_part(int64_t nvec, const T *__restrict__ b, double *part, const int *iflag) {
+  if (iflag && iflag[IF_DONE]) return;
   __shared__ double sm[4];
   double acc = 0.0;
   for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < nvec; r += (int64_t)gridDim.x * blockDim.x) {
@@ -79,27 +86,34 @@ k_kinit_norm(int64_t nvec, const T *__restrict__ b, double *ctrl, KOff off, int 
     acc += v * v;
   }
   acc = block_sum(acc, sm);
-  if (threadIdx.x == 0) ctrl[off.part + blockIdx.x] = acc;
-  if (last_block_arrived((unsigned *)&iflag[IF_COUNTER])) {
-    double s = 0.0;
-    for (int k = threadIdx.x; k < (int)gridDim.x; k += blockDim.x) s += load_agent(&ctrl[off.part + k]);
-    s = block_sum(s, sm);
-    if (threadIdx.x == 0) {
-      const double beta = sqrt(s);
-      ctrl[off.scal + 0] = beta;
-      ctrl[off.scal + 1] = fmax(rtol * beta, atol);
-      ctrl[off.scal + 2] = beta;
-      ctrl[off.g] = beta;
-      iflag[IF_ITS] = 0;
-      if (!isfinite(beta)) {
-        iflag[IF_STATUS] = KS_NAN;
-        iflag[IF_DONE] = 1;
-      } else {
-        iflag[IF_STATUS] = KS_OK;
-        iflag[IF_DONE] = (beta == 0.0 || beta <= atol) ? 1 : 0;
-      }
+  if (threadIdx.x == 0) part[blockIdx.x] = acc;
+}
+
+__device__ __forceinline__ double sum_partials1(const double *part, int nb, double *sm) {
+  double s = 0.0;
+  for (int q = threadIdx.x; q < nb; q += blockDim.x) s += part[q];
+  return block_sum(s, sm);
+}
+
+// beta = ||b||, tolerance, g0 and the level flags
+__global__ void __launch_bounds__(VMS_BLOCK)
+k_kinit_finalize(int nb, double *ctrl, KOff off, int *iflag, double rtol, double atol) {
+  __shared__ double sm[4];
+  const double s = sum_partials1(ctrl + off.part, nb, sm);
+  if (threadIdx.x == 0) {
+    const double beta = sqrt(s);
+    ctrl[off.scal + 0] = beta;
+    ctrl[off.scal + 1] = fmax(rtol * beta, atol);
+    ctrl[off.scal + 2] = beta;
+    ctrl[off.g] = beta;
+    iflag[IF_ITS] = 0;
+    if (!isfinite(beta)) {
+      iflag[IF_STATUS] = KS_NAN;
+      iflag[IF_DONE] = 1;
+    } else {
+      iflag[IF_STATUS] = KS_OK;
+      iflag[IF_DONE] = (beta == 0.0 || beta <= atol) ? 1 : 0;
     }
-    reset_counter((unsigned *)&iflag[IF_COUNTER]);
   }
 }
 
@@ -112,10 +126,10 @@ __device__ __forceinline__ void scale_and_precond(int64_t nvec, const T *w, doub
   if (pc == PC_BJ33) {
     const int64_t nn = nvec / 3;
     for (int64_t i = t0; i < nn; i += stride) {
-      const double v0 = dl(w, 3 * i) * inv, v1 = dl(w, 3 * i + 1) * inv, v2 = dl(w, 3 * i + 2) * inv;
-      V[3 * i] = (T)v0; V[3 * i + 1] = (T)v1; V[3 * i + 2] = (T)v2;
+      const T v0 = (T)(dl(w, 3 * i) * inv), v1 = (T)(dl(w, 3 * i + 1) * inv), v2 = (T)(dl(w, 3 * i + 2) * inv);
+      V[3 * i] = v0; V[3 * i + 1] = v1; V[3 * i + 2] = v2;
       const T *M = pcd + 9 * i;
-      const double a0 = (double)(T)v0, a1 = (double)(T)v1, a2 = (double)(T)v2;
+      const double a0 = (double)v0, a1 = (double)v1, a2 = (double)v2;
       Z[3 * i] = (T)(dl(M, 0) * a0 + dl(M, 1) * a1 + dl(M, 2) * a2);
       Z[3 * i + 1] = (T)(dl(M, 3) * a0 + dl(M, 4) * a1 + dl(M, 5) * a2);
       Z[3 * i + 2] = (T)(dl(M, 6) * a0 + dl(M, 7) * a1 + dl(M, 8) * a2);
@@ -137,160 +151,179 @@ k_kinit_scale(int64_t nvec, const T *__restrict__ b, T *V0, T *Z0, const double 
   scale_and_precond(nvec, b, 1.0 / ctrl[off.scal + 0], V0, Z0, pc, pcd);
 }
 
-// out[k] = <V_k, w>, k < nk  (CGS pass), partial sums then last-block finalize
+// partial dots <V_k, w>, k < nk, eight basis vectors per pass over the rows
 template <typename T>
 __global__ void __launch_bounds__(VMS_BLOCK)
-k_mdot(int64_t nvec, const T *__restrict__ V, int nk, const T *__restrict__ w, double *ctrl, KOff off,
-       int64_t out_off, int *iflag) {
+k_mdot_part(int64_t nvec, const T *__restrict__ V, int nk, const T *__restrict__ w, double *part, int ld,
+            const int *iflag) {
   if (iflag[IF_DONE]) return;
-  __shared__ double sm[4];
-  const int NB = gridDim.x;
-  const int64_t stride = (int64_t)NB * blockDim.x;
+  __shared__ double sm[4][8];
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   const int64_t t0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  for (int k0 = 0; k0 < nk; k0 += 4) {
-    double a0 = 0, a1 = 0, a2 = 0, a3 = 0;
-    const int kk = min(4, nk - k0);
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int k0 = 0; k0 < nk; k0 += 8) {
+    const int kk = min(8, nk - k0);
+    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    const T *Vk = V + (int64_t)k0 * nvec;
     for (int64_t r = t0; r < nvec; r += stride) {
       const double wr = dl(w, r);
-      a0 += dl(V, (int64_t)k0 * nvec + r) * wr;
-      if (kk > 1) a1 += dl(V, (int64_t)(k0 + 1) * nvec + r) * wr;
-      if (kk > 2) a2 += dl(V, (int64_t)(k0 + 2) * nvec + r) * wr;
-      if (kk > 3) a3 += dl(V, (int64_t)(k0 + 3) * nvec + r) * wr;
+#pragma unroll
+      for (int q = 0; q < 8; ++q)
+        if (q < kk) acc[q] += dl(Vk, (int64_t)q * nvec + r) * wr;
     }
-    a0 = block_sum(a0, sm);
-    if (kk > 1) a1 = block_sum(a1, sm);
-    if (kk > 2) a2 = block_sum(a2, sm);
-    if (kk > 3) a3 = block_sum(a3, sm);
-    if (threadIdx.x == 0) {
-      double *pp = ctrl + off.part + (int64_t)k0 * NB + blockIdx.x;
-      pp[0] = a0;
-      if (kk > 1) pp[NB] = a1;
-      if (kk > 2) pp[2 * NB] = a2;
-      if (kk > 3) pp[3 * NB] = a3;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const double v = wave_sum(acc[q]);
+      if (lane == 0) sm[wv][q] = v;
     }
-  }
-  if (last_block_arrived((unsigned *)&iflag[IF_COUNTER])) {
-    for (int k = 0; k < nk; ++k) {
-      double s = 0.0;
-      for (int q = threadIdx.x; q < NB; q += blockDim.x) s += load_agent(&ctrl[off.part + (int64_t)k * NB + q]);
-      s = block_sum(s, sm);
-      if (threadIdx.x == 0) ctrl[out_off + k] = s;
-    }
-    reset_counter((unsigned *)&iflag[IF_COUNTER]);
+    __syncthreads();
+    if (threadIdx.x < kk)
+      part[(int64_t)blockIdx.x * ld + k0 + threadIdx.x] =
+          (sm[0][threadIdx.x] + sm[1][threadIdx.x]) + (sm[2][threadIdx.x] + sm[3][threadIdx.x]);
+    __syncthreads();
   }
 }
 
-// w -= sum_k coef[k] V_k ; optionally accumulate ||w||^2 and finish the
-// Arnoldi step j (Hessenberg column, Givens rotation, convergence test).
+// out[k] = sum_b part[b * ld + k]: a workgroup owns 16 consecutive k (16-wide
+// coalesced segments) and splits the partials over 16 groups of threads with
+// four independent accumulators each; fixed combination order.
+#define FIN_K 16
+__global__ void __launch_bounds__(VMS_BLOCK)
+k_dot_finalize(const double *part, int nb, int ld, int nk, double *out, const int *iflag) {
+  if (iflag[IF_DONE]) return;
+  __shared__ double sm[16][FIN_K + 1];
+  const int kl = threadIdx.x & (FIN_K - 1), bg = threadIdx.x / FIN_K;
+  const int k = blockIdx.x * FIN_K + kl;
+  double a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+  if (k < nk) {
+    int b = bg;
+    for (; b + 48 < nb; b += 64) {
+      a0 += part[(int64_t)b * ld + k];
+      a1 += part[(int64_t)(b + 16) * ld + k];
+      a2 += part[(int64_t)(b + 32) * ld + k];
+      a3 += part[(int64_t)(b + 48) * ld + k];
+    }
+    for (; b < nb; b += 16) a0 += part[(int64_t)b * ld + k];
+  }
+  sm[bg][kl] = (a0 + a1) + (a2 + a3);
+  __syncthreads();
+  if (bg == 0 && k < nk) {
+    double t = 0.0;
+    for (int q = 0; q < 16; ++q) t += sm[q][kl];
+    out[k] = t;
+  }
+}
+inline int fin_grid(int nk) { return (nk + FIN_K - 1) / FIN_K; }
+
+// w -= sum_k coef[k] V_k (four independent partial sums per row); with NORM
+// also the partial sums of the updated ||w||^2
 template <typename T, bool NORM>
 __global__ void __launch_bounds__(VMS_BLOCK)
-k_mupdate(int64_t nvec, const T *__restrict__ V, int nk, T *w, double *ctrl, KOff off, int64_t coef_off,
-          int *iflag, int j, int cgs, int maxit) {
+k_mupdate(int64_t nvec, const T *__restrict__ V, int nk, T *w, const double *coef, double *part, const int *iflag) {
   if (iflag[IF_DONE]) return;
+  __shared__ double cs[256];
   __shared__ double sm[4];
-  __shared__ double coef[64];
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   const int64_t t0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   double ss = 0.0;
-  // the basis is processed in chunks of 64 coefficients staged through LDS;
-  // rows owned by this thread are revisited per chunk (partial results in w)
-  const int nchunk = (nk + 63) / 64;
-  for (int c = 0; c < nchunk; ++c) {
-    const int k0 = c * 64, kn = min(64, nk - k0);
+  for (int c0 = 0; c0 < nk; c0 += 256) {
+    const int kn = min(256, nk - c0);
     __syncthreads();
-    if (threadIdx.x < kn) coef[threadIdx.x] = ctrl[coef_off + k0 + threadIdx.x];
+    if (threadIdx.x < kn) cs[threadIdx.x] = coef[c0 + threadIdx.x];
     __syncthreads();
-    const bool last = (c == nchunk - 1);
+    const bool last = (c0 + 256 >= nk);
+    const T *Vc = V + (int64_t)c0 * nvec;
     for (int64_t r = t0; r < nvec; r += stride) {
-      double acc = dl(w, r);
-      for (int k = 0; k < kn; ++k) acc -= coef[k] * dl(V, (int64_t)(k0 + k) * nvec + r);
-      const T out = (T)acc;
+      double a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+      int k = 0;
+      for (; k + 4 <= kn; k += 4) {
+        a0 += cs[k] * dl(Vc, (int64_t)k * nvec + r);
+        a1 += cs[k + 1] * dl(Vc, (int64_t)(k + 1) * nvec + r);
+        a2 += cs[k + 2] * dl(Vc, (int64_t)(k + 2) * nvec + r);
+        a3 += cs[k + 3] * dl(Vc, (int64_t)(k + 3) * nvec + r);
+      }
+      for (; k < kn; ++k) a0 += cs[k] * dl(Vc, (int64_t)k * nvec + r);
+      const T out = (T)(dl(w, r) - ((a0 + a1) + (a2 + a3)));
       w[r] = out;
       if (NORM && last) ss += (double)out * (double)out;
     }
   }
   if (!NORM) return;
   ss = block_sum(ss, sm);
-  if (threadIdx.x == 0) ctrl[off.part + blockIdx.x] = ss;
-  if (last_block_arrived((unsigned *)&iflag[IF_COUNTER])) {
-    double s = 0.0;
-    for (int q = threadIdx.x; q < (int)gridDim.x; q += blockDim.x) s += load_agent(&ctrl[off.part + q]);
-    s = block_sum(s, sm);
-    if (threadIdx.x == 0) {
-      const int m1 = off.m + 1;
-      double *col = ctrl + off.H + (int64_t)j * m1;
-      double *cs = ctrl + off.cs, *sn = ctrl + off.sn, *g = ctrl + off.g;
-      const double hn = sqrt(s);
-      if (cgs)
-        for (int i = 0; i <= j; ++i) col[i] = ctrl[off.h1 + i] + ctrl[off.h2 + i];
-      col[j + 1] = hn;
-      for (int i = 0; i < j; ++i) {
-        const double t = cs[i] * col[i] + sn[i] * col[i + 1];
-        col[i + 1] = -sn[i] * col[i] + cs[i] * col[i + 1];
-        col[i] = t;
-      }
-      const double den = hypot(col[j], col[j + 1]);
-      double c = 1.0, sv = 0.0;
-      if (den > 0.0) { c = col[j] / den; sv = col[j + 1] / den; }
-      cs[j] = c;
-      sn[j] = sv;
-      col[j] = den;
-      col[j + 1] = 0.0;
-      g[j + 1] = -sv * g[j];
-      g[j] = c * g[j];
-      const double res = fabs(g[j + 1]);
-      ctrl[off.scal + 2] = res;
-      ctrl[off.scal + 3] = hn;
-      iflag[IF_ITS] = j + 1;
-      if (!isfinite(res) || !isfinite(hn)) {
-        iflag[IF_STATUS] = KS_NAN;
-        iflag[IF_DONE] = 1;
-      } else if (den == 0.0) {
-        iflag[IF_STATUS] = KS_BREAKDOWN;
-        iflag[IF_ITS] = j;   // singular column: keep the previous solution
-        iflag[IF_DONE] = 1;
-      } else if (res <= ctrl[off.scal + 1] || hn == 0.0) {
-        iflag[IF_STATUS] = KS_OK;
-        iflag[IF_DONE] = 1;
-      } else if (j + 1 >= maxit) {
-        iflag[IF_STATUS] = KS_MAXIT;
-        iflag[IF_DONE] = 1;
-      }
-    }
-    reset_counter((unsigned *)&iflag[IF_COUNTER]);
+  if (threadIdx.x == 0) part[blockIdx.x] = ss;
+}
+
+// finish Arnoldi step j: Hessenberg column (h1 + h2 for CGS2), h_{j+1,j} =
+// ||w||, previous rotations, new Givens rotation, residual, flags
+__global__ void __launch_bounds__(VMS_BLOCK)
+k_givens(int nb, double *ctrl, KOff off, int *iflag, int j, int cgs, int maxit) {
+  if (iflag[IF_DONE]) return;
+  __shared__ double sm[4];
+  const double s = sum_partials1(ctrl + off.part, nb, sm);
+  if (threadIdx.x != 0) return;
+  const int m1 = off.m + 1;
+  double *col = ctrl + off.H + (int64_t)j * m1;
+  double *cs = ctrl + off.cs, *sn = ctrl + off.sn, *g = ctrl + off.g;
+  const double hn = sqrt(s);
+  if (cgs)
+    for (int i = 0; i <= j; ++i) col[i] = ctrl[off.h1 + i] + ctrl[off.h2 + i];
+  col[j + 1] = hn;
+  for (int i = 0; i < j; ++i) {
+    const double t = cs[i] * col[i] + sn[i] * col[i + 1];
+    col[i + 1] = -sn[i] * col[i] + cs[i] * col[i + 1];
+    col[i] = t;
+  }
+  const double den = hypot(col[j], col[j + 1]);
+  double c = 1.0, sv = 0.0;
+  if (den > 0.0) { c = col[j] / den; sv = col[j + 1] / den; }
+  cs[j] = c;
+  sn[j] = sv;
+  col[j] = den;
+  col[j + 1] = 0.0;
+  g[j + 1] = -sv * g[j];
+  g[j] = c * g[j];
+  const double res = fabs(g[j + 1]);
+  ctrl[off.scal + 2] = res;
+  ctrl[off.scal + 3] = hn;
+  iflag[IF_ITS] = j + 1;
+  if (!isfinite(res) || !isfinite(hn)) {
+    iflag[IF_STATUS] = KS_NAN;
+    iflag[IF_DONE] = 1;
+  } else if (den == 0.0) {
+    iflag[IF_STATUS] = KS_BREAKDOWN;
+    iflag[IF_ITS] = j;   // singular column: keep the previous iterate
+    iflag[IF_DONE] = 1;
+  } else if (res <= ctrl[off.scal + 1] || hn == 0.0) {
+    iflag[IF_STATUS] = KS_OK;
+    iflag[IF_DONE] = 1;
+  } else if (j + 1 >= maxit) {
+    iflag[IF_STATUS] = KS_MAXIT;
+    iflag[IF_DONE] = 1;
   }
 }
 
-// MGS step k: w -= H[k-1,j] V_{k-1} (k > 0), then H[k,j] = <w, V_k>
+// MGS step k: w -= H[k-1,j] V_{k-1} (k > 0), then partial dots <w, V_k>
 template <typename T>
 __global__ void __launch_bounds__(VMS_BLOCK)
-k_mgs_step(int64_t nvec, const T *__restrict__ V, int k, T *w, double *ctrl, KOff off, int *iflag, int j) {
+k_mgs_part(int64_t nvec, const T *__restrict__ V, int k, T *w, const double *hprev_p, double *part,
+           const int *iflag) {
   if (iflag[IF_DONE]) return;
   __shared__ double sm[4];
-  const int m1 = off.m + 1;
-  double *col = ctrl + off.H + (int64_t)j * m1;
-  const double hprev = (k > 0) ? col[k - 1] : 0.0;
+  const double hprev = (k > 0) ? *hprev_p : 0.0;
   const T *Vp = V + (int64_t)(k > 0 ? k - 1 : 0) * nvec;
   const T *Vk = V + (int64_t)k * nvec;
   double acc = 0.0;
   for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < nvec; r += (int64_t)gridDim.x * blockDim.x) {
     double wr = dl(w, r);
     if (k > 0) {
-      wr -= hprev * dl(Vp, r);
-      w[r] = (T)wr;
-      wr = (double)(T)wr;
+      const T u = (T)(wr - hprev * dl(Vp, r));
+      w[r] = u;
+      wr = (double)u;
     }
     acc += wr * dl(Vk, r);
   }
   acc = block_sum(acc, sm);
-  if (threadIdx.x == 0) ctrl[off.part + blockIdx.x] = acc;
-  if (last_block_arrived((unsigned *)&iflag[IF_COUNTER])) {
-    double s = 0.0;
-    for (int q = threadIdx.x; q < (int)gridDim.x; q += blockDim.x) s += load_agent(&ctrl[off.part + q]);
-    s = block_sum(s, sm);
-    if (threadIdx.x == 0) col[k] = s;
-    reset_counter((unsigned *)&iflag[IF_COUNTER]);
-  }
+  if (threadIdx.x == 0) part[blockIdx.x] = acc;
 }
 
 template <typename T>
@@ -385,6 +418,133 @@ __global__ void k_shat_diag(int n, const int32_t *rp, const int32_t *col, const 
   sdinv[i] = (T)((s != 0.0 && isfinite(s)) ? 1.0 / s : 1.0);
 }
 
+// ---- Chebyshev preconditioner on S^ = D - C diag(A)^-1 B (matrix free) ----
+// point diagonal of the scaled A, inverted
+template <typename T>
+__global__ void k_dAinv(int n, const int32_t *diag_pos, int64_t nnzb, const double *A, T *dAinv) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int64_t b = diag_pos[i];
+  for (int c = 0; c < 3; ++c) {
+    const double a = A[(4 * c) * nnzb + b];
+    dAinv[3 * (int64_t)i + c] = (T)((a != 0.0) ? 1.0 / a : 0.0);
+  }
+}
+
+// t = diag(A)^-1 (B x)
+template <typename T>
+__global__ void __launch_bounds__(VMS_BLOCK)
+k_shat_bt(int n, int64_t nnzb, const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
+          const T *__restrict__ B, const T *__restrict__ dAinv, const T *__restrict__ x, T *t) {
+  const int *done = nullptr;
+  SPMV_PROLOGUE
+  double a0 = 0, a1 = 0, a2 = 0;
+  for (int b = b0 + lane; b < b1; b += 16) {
+    const double xp = ld(x, col[b]);
+    a0 += ld(B, 0 * nnzb + b) * xp;
+    a1 += ld(B, 1 * nnzb + b) * xp;
+    a2 += ld(B, 2 * nnzb + b) * xp;
+  }
+  a0 = reduce16(a0);
+  a1 = reduce16(a1);
+  a2 = reduce16(a2);
+  if (act && lane == 0) {
+    const int64_t o = 3 * (int64_t)row;
+    t[o] = (T)(a0 * ld(dAinv, o));
+    t[o + 1] = (T)(a1 * ld(dAinv, o + 1));
+    t[o + 2] = (T)(a2 * ld(dAinv, o + 2));
+  }
+}
+
+// Chebyshev scalars for step k on [lmax/ratio, lmax] (lmax read on the device)
+__device__ __forceinline__ void cheb_coef(const double *lam, double ratio, int k, double &rho0, double &rho1,
+                                          double &delta, double &theta) {
+  const double lmax = 1.1 * (*lam);
+  const double lmin = lmax / ratio;
+  theta = 0.5 * (lmax + lmin);
+  delta = 0.5 * (lmax - lmin);
+  const double s1 = theta / delta;
+  double r = 1.0 / s1;
+  for (int q = 0; q < k; ++q) r = 1.0 / (2.0 * s1 - r);
+  rho0 = r;
+  rho1 = 1.0 / (2.0 * s1 - r);
+}
+
+// MODE 0 (power iteration): y = diag(S^)^-1 (D x - C t)
+// MODE 1 (Chebyshev step k): s = D d - C t; x += d; r -= s;
+//                            dn = rho1 rho0 d + 2 rho1/delta diag(S^)^-1 r
+template <typename T, int MODE>
+__global__ void __launch_bounds__(VMS_BLOCK)
+k_shat_dc(int n, int64_t nnzb, const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
+          const T *__restrict__ C, const T *__restrict__ D, const T *__restrict__ d, const T *__restrict__ t,
+          const T *__restrict__ sdinv, T *y, T *x, T *r, const double *lam, double ratio, int k) {
+  const int *done = nullptr;
+  SPMV_PROLOGUE
+  double a = 0.0, dd = 0.0;
+  for (int b = b0 + lane; b < b1; b += 16) {
+    const int64_t c = col[b];
+    a += ld(C, 0 * nnzb + b) * ld(t, 3 * c) + ld(C, 1 * nnzb + b) * ld(t, 3 * c + 1) +
+         ld(C, 2 * nnzb + b) * ld(t, 3 * c + 2);
+    dd += ld(D, b) * ld(d, c);
+  }
+  a = reduce16(a);
+  dd = reduce16(dd);
+  if (act && lane == 0) {
+    const double sv = dd - a;
+    if (MODE == 0) {
+      y[row] = (T)(ld(sdinv, row) * sv);
+    } else {
+      double rho0, rho1, delta, theta;
+      cheb_coef(lam, ratio, k, rho0, rho1, delta, theta);
+      const double di = ld(d, row);
+      x[row] = (T)(ld(x, row) + di);
+      const double rn = ld(r, row) - sv;
+      r[row] = (T)rn;
+      y[row] = (T)(rho1 * rho0 * di + 2.0 * rho1 / delta * ld(sdinv, row) * rn);
+    }
+  }
+}
+
+// r = v, x = 0, d0 = diag(S^)^-1 r / theta
+template <typename T>
+__global__ void k_cheb_init(int n, const T *v, const T *sdinv, T *x, T *r, T *d, const double *lam, double ratio) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double rho0, rho1, delta, theta;
+  cheb_coef(lam, ratio, 0, rho0, rho1, delta, theta);
+  const double vi = ld(v, i);
+  r[i] = (T)vi;
+  x[i] = (T)0;
+  d[i] = (T)(ld(sdinv, i) * vi / theta);
+}
+
+// deterministic oscillatory start vector of the power iteration
+template <typename T>
+__global__ void k_power_init(int n, T *x) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  uint32_t h = (uint32_t)i * 2654435761u;
+  h ^= h >> 15;
+  h *= 2246822519u;
+  h ^= h >> 13;
+  x[i] = (T)((double)(h & 0xffff) / 32768.0 - 1.0);
+}
+
+// lam = ||y|| from the norm partials
+__global__ void __launch_bounds__(VMS_BLOCK) k_store_norm(int nb, const double *part, double *lam) {
+  __shared__ double sm[4];
+  const double s = sum_partials1(part, nb, sm);
+  if (threadIdx.x == 0) *lam = sqrt(s);
+}
+
+template <typename T>
+__global__ void k_power_scale(int n, const T *y, const double *lam, T *x) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double l = *lam;
+  x[i] = (T)((l > 0.0) ? ld(y, i) / l : 0.0);
+}
+
 // full [n][4] FP64 <-> split velocity [n][3] / pressure [n] of type T
 template <typename T>
 __global__ void k_split(int n, const double *full, T *v, T *p) {
@@ -447,6 +607,94 @@ struct KLevel {
   }
 };
 
+inline int sync_level_flags(vms_ctx *ctx, const int *iflag) {
+  VMS_HIP(ctx, hipMemcpyAsync(ctx->h_i, iflag, 4 * sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+  VMS_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  return VMS_OK;
+}
+
+// Arnoldi step j of level L: orthogonalise W against V_0..V_j (CGS2 or MGS),
+// then the Hessenberg/Givens update and the convergence flags.
+template <typename T>
+int orth_level(vms_ctx *ctx, KLevel<T> &L, int j, int maxit, int mode) {
+  hipStream_t s = ctx->stream;
+  const dim3 gr(L.nb), bl(VMS_BLOCK);
+  double *part = L.ctrl + L.off.part;
+  const int ld = L.m + 1;
+  if (mode == VMS_ORTH_MGS) {
+    double *col = L.ctrl + L.off.H + (int64_t)j * ld;
+    for (int k = 0; k <= j; ++k) {
+      hipLaunchKernelGGL(k_mgs_part<T>, gr, bl, 0, s, L.nvec, L.V, k, L.W, (const double *)(col + (k > 0 ? k - 1 : 0)),
+                         part, L.iflag);
+      hipLaunchKernelGGL(k_dot_finalize, dim3(1), bl, 0, s, (const double *)part, L.nb, 1, 1, col + k, L.iflag);
+    }
+    hipLaunchKernelGGL((k_mupdate<T, true>), gr, bl, 0, s, L.nvec, L.V + (int64_t)j * L.nvec, 1, L.W,
+                       (const double *)(col + j), part, L.iflag);
+    hipLaunchKernelGGL(k_givens, dim3(1), bl, 0, s, L.nb, L.ctrl, L.off, L.iflag, j, 0, maxit);
+  } else {
+    double *h1 = L.ctrl + L.off.h1, *h2 = L.ctrl + L.off.h2;
+    hipLaunchKernelGGL(k_mdot_part<T>, gr, bl, 0, s, L.nvec, L.V, j + 1, L.W, part, ld, L.iflag);
+    hipLaunchKernelGGL(k_dot_finalize, dim3(fin_grid(j + 1)), bl, 0, s, (const double *)part, L.nb, ld, j + 1, h1,
+                       L.iflag);
+    hipLaunchKernelGGL((k_mupdate<T, false>), gr, bl, 0, s, L.nvec, L.V, j + 1, L.W, (const double *)h1, part,
+                       L.iflag);
+    hipLaunchKernelGGL(k_mdot_part<T>, gr, bl, 0, s, L.nvec, L.V, j + 1, L.W, part, ld, L.iflag);
+    hipLaunchKernelGGL(k_dot_finalize, dim3(fin_grid(j + 1)), bl, 0, s, (const double *)part, L.nb, ld, j + 1, h2,
+                       L.iflag);
+    hipLaunchKernelGGL((k_mupdate<T, true>), gr, bl, 0, s, L.nvec, L.V, j + 1, L.W, (const double *)h2, part,
+                       L.iflag);
+    hipLaunchKernelGGL(k_givens, dim3(1), bl, 0, s, L.nb, L.ctrl, L.off, L.iflag, j, 1, maxit);
+  }
+  VMS_LAUNCH_CHECK(ctx);
+  return VMS_OK;
+}
+
+// Right-preconditioned (F)GMRES with x0 = 0 on level L.  op(j) enqueues
+// W = Op Z_j; for pc != PC_NONE the device preconditioner fills Z_{j+1} from
+// V_{j+1}, otherwise op(j) itself must first fill Z_j (flexible variant).
+// Without sync_each the host enqueues `batch` iterations before it reads the
+// level flags (kernels past convergence return at once).
+template <typename T, typename OpF>
+int gmres_run(vms_ctx *ctx, KLevel<T> &L, const T *b, T *x, double rtol, double atol, int maxit, int orth, int pc,
+              const T *pcd, bool sync_each, int &est, OpF op, int &its_out, int &status_out) {
+  hipStream_t s = ctx->stream;
+  maxit = std::min(maxit, L.m);
+  const dim3 gr(L.nb), bl(VMS_BLOCK);
+  hipLaunchKernelGGL(k_clear_ints, dim3(1), dim3(64), 0, s, L.iflag, 4);
+  hipLaunchKernelGGL(k_norm_part<T>, gr, bl, 0, s, L.nvec, b, L.ctrl + L.off.part, (const int *)nullptr);
+  hipLaunchKernelGGL(k_kinit_finalize, dim3(1), bl, 0, s, L.nb, L.ctrl, L.off, L.iflag, rtol, atol);
+  hipLaunchKernelGGL(k_kinit_scale<T>, gr, bl, 0, s, L.nvec, b, L.V, L.Z, L.ctrl, L.off, L.iflag, pc, pcd);
+  VMS_LAUNCH_CHECK(ctx);
+  int j = 0, rc;
+  bool done = false;
+  if (sync_each) {
+    if ((rc = sync_level_flags(ctx, L.iflag))) return rc;
+    done = ctx->h_i[IF_DONE] != 0;
+  }
+  int batch = sync_each ? 1 : std::max(1, est);
+  while (!done && j < maxit) {
+    const int nbt = std::min(batch, maxit - j);
+    for (int i = 0; i < nbt; ++i, ++j) {
+      if ((rc = op(j))) return rc;
+      if ((rc = orth_level<T>(ctx, L, j, maxit, orth))) return rc;
+      hipLaunchKernelGGL(k_normalize<T>, gr, bl, 0, s, L.nvec, L.W, L.V + (int64_t)(j + 1) * L.nvec,
+                         L.Z + (int64_t)(j + 1) * L.nvec, L.ctrl, L.off, L.iflag, pc, pcd);
+    }
+    VMS_LAUNCH_CHECK(ctx);
+    if ((rc = sync_level_flags(ctx, L.iflag))) return rc;
+    done = ctx->h_i[IF_DONE] != 0;
+    if (!sync_each) batch = std::min(2 * batch, 64);
+  }
+  status_out = ctx->h_i[IF_STATUS];
+  its_out = ctx->h_i[IF_ITS];
+  hipLaunchKernelGGL(k_trisolve, dim3(1), bl, 0, s, L.ctrl, L.off, L.iflag);
+  hipLaunchKernelGGL(k_combine<T>, gr, bl, 0, s, L.nvec, L.Z, L.ctrl, L.off, L.iflag, x);
+  VMS_LAUNCH_CHECK(ctx);
+  est = std::max(1, its_out);
+  if (status_out == KS_NAN) return vms_set_error(ctx, VMS_ERR_NAN, "NaN/Inf in a Krylov level");
+  return VMS_OK;
+}
+
 template <typename T>
 struct Nested {
   vms_ctx *ctx;
@@ -458,6 +706,8 @@ struct Nested {
   const T *A, *B, *C, *D;  // scaled blocks in the level precision
   KLevel<T> LA, LS;
   T *rv, *rp, *xh, *xp, *xv, *xbar, *xt, *Minv, *sdinv;
+  T *dAinv, *ct, *cr, *cd0, *cd1, *px, *py;  // Chebyshev / power-iteration vectors
+  double *lam = nullptr;                      // device: lmax estimate of diag(S^)^-1 S^
   vms_solve_stats *stats;
   int err = VMS_OK;
 
@@ -474,84 +724,49 @@ struct Nested {
     xt = cv.take<T>(3 * nn);
     Minv = cv.take<T>(9 * nn);
     sdinv = cv.take<T>(nn);
+    dAinv = cv.take<T>(3 * nn);
+    ct = cv.take<T>(3 * nn);
+    cr = cv.take<T>(nn);
+    cd0 = cv.take<T>(nn);
+    cd1 = cv.take<T>(nn);
+    px = cv.take<T>(nn);
+    py = cv.take<T>(nn);
   }
 
-  int sync_flags(KLevel<T> &L) {
-    VMS_HIP(ctx, hipMemcpyAsync(ctx->h_i, L.iflag, 4 * sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
-    VMS_HIP(ctx, hipStreamSynchronize(ctx->stream));
-    return VMS_OK;
-  }
-
-  // generic right-preconditioned GMRES with a device preconditioner
-  // (op: W = Op Z_j enqueued by the callback)
-  template <typename OpF>
-  int gmres(KLevel<T> &L, const T *b, T *x, double rtol, double atol, int maxit, int pc, const T *pcd,
-            bool sync_each, int &est, OpF op, int &its_out) {
+  // z = p(diag(S^)^-1 S^) diag(S^)^-1 v: degree-k Chebyshev iteration for S^ z = v
+  void cheb_apply(const T *v, T *z) {
     hipStream_t s = ctx->stream;
-    maxit = std::min(maxit, L.m);
-    hipLaunchKernelGGL(k_clear_ints, dim3(1), dim3(64), 0, s, L.iflag, 4);
-    hipLaunchKernelGGL(k_kinit_norm<T>, dim3(L.nb), dim3(VMS_BLOCK), 0, s, L.nvec, b, L.ctrl, L.off, L.iflag, rtol,
-                       atol);
-    hipLaunchKernelGGL(k_kinit_scale<T>, dim3(L.nb), dim3(VMS_BLOCK), 0, s, L.nvec, b, L.V, L.Z, L.ctrl, L.off,
-                       L.iflag, pc, pcd);
-    VMS_LAUNCH_CHECK(ctx);
-    int j = 0, rc;
-    bool done = false;
-    if (sync_each) {
-      if ((rc = sync_flags(L))) return rc;
-      done = ctx->h_i[IF_DONE] != 0;
+    const int deg = o->shat_degree;
+    const double ratio = o->shat_ratio > 1.0 ? o->shat_ratio : 20.0;
+    const dim3 g1((n + VMS_BLOCK - 1) / VMS_BLOCK), gs(spmv_grid(n)), bl(VMS_BLOCK);
+    hipLaunchKernelGGL(k_cheb_init<T>, g1, bl, 0, s, n, v, (const T *)sdinv, z, cr, cd0, (const double *)lam, ratio);
+    T *d = cd0, *dn = cd1;
+    for (int k = 0; k < deg; ++k) {
+      hipLaunchKernelGGL(k_shat_bt<T>, gs, bl, 0, s, n, nnzb, mesh->row_ptr, mesh->col, B, (const T *)dAinv,
+                         (const T *)d, ct);
+      hipLaunchKernelGGL((k_shat_dc<T, 1>), gs, bl, 0, s, n, nnzb, mesh->row_ptr, mesh->col, C, D, (const T *)d,
+                         (const T *)ct, (const T *)sdinv, dn, z, cr, (const double *)lam, ratio, k);
+      std::swap(d, dn);
     }
-    int batch = sync_each ? 1 : std::max(1, est);
-    while (!done && j < maxit) {
-      const int nbt = std::min(batch, maxit - j);
-      for (int i = 0; i < nbt; ++i, ++j) {
-        if ((rc = op(j))) return rc;
-        if ((rc = orth(L, j, maxit))) return rc;
-        hipLaunchKernelGGL(k_normalize<T>, dim3(L.nb), dim3(VMS_BLOCK), 0, s, L.nvec, L.W,
-                           L.V + (int64_t)(j + 1) * L.nvec, L.Z + (int64_t)(j + 1) * L.nvec, L.ctrl, L.off,
-                           L.iflag, pc, pcd);
-      }
-      VMS_LAUNCH_CHECK(ctx);
-      if ((rc = sync_flags(L))) return rc;
-      done = ctx->h_i[IF_DONE] != 0;
-      if (!sync_each) batch = std::min(2 * batch, 64);
-    }
-    if (!done) {  // cannot happen: the Givens step flags maxit; keep a guard
-      if ((rc = sync_flags(L))) return rc;
-    }
-    const int status = ctx->h_i[IF_STATUS];
-    its_out = ctx->h_i[IF_ITS];
-    hipLaunchKernelGGL(k_trisolve, dim3(1), dim3(VMS_BLOCK), 0, s, L.ctrl, L.off, L.iflag);
-    hipLaunchKernelGGL(k_combine<T>, dim3(L.nb), dim3(VMS_BLOCK), 0, s, L.nvec, L.Z, L.ctrl, L.off, L.iflag, x);
-    VMS_LAUNCH_CHECK(ctx);
-    est = std::max(1, its_out);
-    if (status == KS_NAN) return vms_set_error(ctx, VMS_ERR_NAN, "NaN/Inf in a Krylov level");
-    return VMS_OK;
   }
 
-  int orth(KLevel<T> &L, int j, int maxit) { return orth_level(ctx, L, j, maxit, o->orth); }
-
-  static int orth_level(vms_ctx *ctx, KLevel<T> &L, int j, int maxit, int mode) {
+  // lmax of diag(S^)^-1 S^ by power iteration, kept on the device
+  void power_lmax(int iters) {
     hipStream_t s = ctx->stream;
-    if (mode == VMS_ORTH_MGS) {
-      for (int k = 0; k <= j; ++k)
-        hipLaunchKernelGGL(k_mgs_step<T>, dim3(L.nb), dim3(VMS_BLOCK), 0, s, L.nvec, L.V, k, L.W, L.ctrl, L.off,
-                           L.iflag, j);
-      const int64_t coef = L.off.H + (int64_t)j * (L.m + 1) + j;
-      hipLaunchKernelGGL((k_mupdate<T, true>), dim3(L.nb), dim3(VMS_BLOCK), 0, s, L.nvec,
-                         L.V + (int64_t)j * L.nvec, 1, L.W, L.ctrl, L.off, coef, L.iflag, j, 0, maxit);
-    } else {
-      hipLaunchKernelGGL(k_mdot<T>, dim3(L.nb), dim3(VMS_BLOCK), 0, s, L.nvec, L.V, j + 1, L.W, L.ctrl, L.off,
-                         L.off.h1, L.iflag);
-      hipLaunchKernelGGL((k_mupdate<T, false>), dim3(L.nb), dim3(VMS_BLOCK), 0, s, L.nvec, L.V, j + 1, L.W,
-                         L.ctrl, L.off, L.off.h1, L.iflag, j, 1, maxit);
-      hipLaunchKernelGGL(k_mdot<T>, dim3(L.nb), dim3(VMS_BLOCK), 0, s, L.nvec, L.V, j + 1, L.W, L.ctrl, L.off,
-                         L.off.h2, L.iflag);
-      hipLaunchKernelGGL((k_mupdate<T, true>), dim3(L.nb), dim3(VMS_BLOCK), 0, s, L.nvec, L.V, j + 1, L.W,
-                         L.ctrl, L.off, L.off.h2, L.iflag, j, 1, maxit);
+    const dim3 g1((n + VMS_BLOCK - 1) / VMS_BLOCK), gs(spmv_grid(n)), bl(VMS_BLOCK);
+    const int nb = vms_red_blocks(n);
+    double *part = LS.ctrl + LS.off.part;
+    hipLaunchKernelGGL(k_power_init<T>, g1, bl, 0, s, n, px);
+    for (int it = 0; it < iters; ++it) {
+      hipLaunchKernelGGL(k_shat_bt<T>, gs, bl, 0, s, n, nnzb, mesh->row_ptr, mesh->col, B, (const T *)dAinv,
+                         (const T *)px, ct);
+      hipLaunchKernelGGL((k_shat_dc<T, 0>), gs, bl, 0, s, n, nnzb, mesh->row_ptr, mesh->col, C, D, (const T *)px,
+                         (const T *)ct, (const T *)sdinv, py, (T *)nullptr, (T *)nullptr, (const double *)nullptr,
+                         0.0, 0);
+      hipLaunchKernelGGL(k_norm_part<T>, dim3(nb), bl, 0, s, (int64_t)n, (const T *)py, part, (const int *)nullptr);
+      hipLaunchKernelGGL(k_store_norm, dim3(1), bl, 0, s, nb, (const double *)part, lam);
+      hipLaunchKernelGGL(k_power_scale<T>, g1, bl, 0, s, n, (const T *)py, (const double *)lam, px);
     }
-    VMS_LAUNCH_CHECK(ctx);
-    return VMS_OK;
   }
 
   // x = A^-1 b by GMRES with block-Jacobi (intermediate or inner level)
@@ -566,7 +781,8 @@ struct Nested {
                          LA.iflag + IF_DONE);
       return VMS_OK;
     };
-    int rc = gmres(LA, b, x, rtol, atol, maxit, PC_BJ33, Minv, false, est, op, its);
+    int st = 0;
+    int rc = gmres_run<T>(ctx, LA, b, x, rtol, atol, maxit, o->orth, PC_BJ33, Minv, false, est, op, its, st);
     if (inner) { stats->n_I_solves++; stats->it_I += its; }
     else { stats->n_A_solves++; stats->it_A += its; }
     return rc;
@@ -575,8 +791,10 @@ struct Nested {
   // x_p = S^-1 b by GMRES with the matrix-free Schur product (Algorithm 2)
   int solve_S(const T *b, T *x) {
     int its = 0;
+    const bool cheb = o->shat_degree > 0;
     auto op = [&](int j) -> int {
-      const T *z = LS.Z + (int64_t)j * LS.nvec;
+      T *z = LS.Z + (int64_t)j * LS.nvec;
+      if (cheb) cheb_apply(LS.V + (int64_t)j * LS.nvec, z);
       // x-bar = B z
       hipLaunchKernelGGL((k_spmv_B<T, T>), dim3(spmv_grid(n)), dim3(VMS_BLOCK), 0, ctx->stream, n, nnzb,
                          mesh->row_ptr, mesh->col, B, z, xbar, (const T *)nullptr, 1.0, (const int *)nullptr);
@@ -589,7 +807,9 @@ struct Nested {
                          (const int *)nullptr);
       return VMS_OK;
     };
-    int rc = gmres(LS, b, x, o->rtol_S, o->atol_S, o->maxit_S, PC_DIAG, sdinv, true, ctx->est_S, op, its);
+    int st = 0;
+    int rc = gmres_run<T>(ctx, LS, b, x, o->rtol_S, o->atol_S, o->maxit_S, o->orth, cheb ? PC_NONE : PC_DIAG, sdinv,
+                          true, ctx->est_S, op, its, st);
     stats->n_S_solves++;
     stats->it_S += its;
     return rc;
@@ -629,6 +849,12 @@ struct Nested {
                        K->A, Minv);
     hipLaunchKernelGGL(k_shat_diag<T>, dim3(grid1(n)), dim3(VMS_BLOCK), 0, ctx->stream, n, mesh->row_ptr, mesh->col,
                        mesh->tpos, mesh->diag_pos, nnzb, K->A, K->B, K->C, K->D, sdinv);
+    if (o->shat_degree > 0) {
+      lam = LS.ctrl + LS.off.scal + 5;
+      hipLaunchKernelGGL(k_dAinv<T>, dim3(grid1(n)), dim3(VMS_BLOCK), 0, ctx->stream, n, mesh->diag_pos, nnzb, K->A,
+                         dAinv);
+      power_lmax(12);
+    }
     VMS_LAUNCH_CHECK(ctx);
     return VMS_OK;
   }
@@ -661,6 +887,8 @@ int check_opts(vms_ctx *ctx, const vms_solver_opts *o) {
     return vms_set_error(ctx, VMS_ERR_ARG, "unknown preconditioner variant");
   if (o->precision != VMS_FP64 && o->precision != VMS_MIXED)
     return vms_set_error(ctx, VMS_ERR_ARG, "unknown precision");
+  if (o->shat_degree < 0 || o->shat_degree > 64)
+    return vms_set_error(ctx, VMS_ERR_ARG, "shat_degree must be in [0, 64]");
   return VMS_OK;
 }
 
@@ -698,42 +926,18 @@ int solve_impl(vms_ctx *ctx, const vms_mesh *mesh, const vms_matrix *K, const do
                        L.iflag + IF_DONE);
     return VMS_OK;
   };
-  // the outer level runs its own copy of the generic loop in FP64
+  // outer FGMRES: FP64, host-driven preconditioner, flags read every iteration
   hipStream_t s = ctx->stream;
   const int maxit = std::min(o->maxit, L.m);
-  hipLaunchKernelGGL(k_clear_ints, dim3(1), dim3(64), 0, s, L.iflag, 4);
-  hipLaunchKernelGGL(k_kinit_norm<double>, dim3(L.nb), dim3(VMS_BLOCK), 0, s, L.nvec, rhs, L.ctrl, L.off, L.iflag,
-                     o->rtol, o->atol);
-  hipLaunchKernelGGL(k_kinit_scale<double>, dim3(L.nb), dim3(VMS_BLOCK), 0, s, L.nvec, rhs, L.V, L.Z, L.ctrl, L.off,
-                     L.iflag, (int)PC_NONE, (const double *)nullptr);
-  VMS_LAUNCH_CHECK(ctx);
-  VMS_HIP(ctx, hipMemcpyAsync(ctx->h_i, L.iflag, 4 * sizeof(int), hipMemcpyDeviceToHost, s));
+  int status = 0, its = 0;
+  rc = gmres_run<double>(ctx, L, rhs, x, o->rtol, o->atol, maxit, o->orth, PC_NONE, (const double *)nullptr, true,
+                         est_outer, op, its, status);
+  if (rc) return rc;
+  stats->n_outer = its;
   VMS_HIP(ctx, hipMemcpyAsync(ctx->h_d, L.ctrl + L.off.scal, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
   VMS_HIP(ctx, hipStreamSynchronize(s));
   stats->res0 = ctx->h_d[0];
-  bool done = ctx->h_i[IF_DONE] != 0;
-  int j = 0;
-  while (!done && j < maxit) {
-    if ((rc = op(j))) return rc;
-    if ((rc = Nested<double>::orth_level(ctx, L, j, maxit, o->orth))) return rc;
-    hipLaunchKernelGGL(k_normalize<double>, dim3(L.nb), dim3(VMS_BLOCK), 0, s, L.nvec, L.W,
-                       L.V + (int64_t)(j + 1) * L.nvec, L.Z + (int64_t)(j + 1) * L.nvec, L.ctrl, L.off, L.iflag,
-                       (int)PC_NONE, (const double *)nullptr);
-    VMS_LAUNCH_CHECK(ctx);
-    ++j;
-    VMS_HIP(ctx, hipMemcpyAsync(ctx->h_i, L.iflag, 4 * sizeof(int), hipMemcpyDeviceToHost, s));
-    VMS_HIP(ctx, hipStreamSynchronize(s));
-    done = ctx->h_i[IF_DONE] != 0;
-  }
-  (void)est_outer;
-  const int status = ctx->h_i[IF_STATUS];
-  stats->n_outer = ctx->h_i[IF_ITS];
-  hipLaunchKernelGGL(k_trisolve, dim3(1), dim3(VMS_BLOCK), 0, s, L.ctrl, L.off, L.iflag);
-  hipLaunchKernelGGL(k_combine<double>, dim3(L.nb), dim3(VMS_BLOCK), 0, s, L.nvec, L.Z, L.ctrl, L.off, L.iflag, x);
-  VMS_LAUNCH_CHECK(ctx);
-  VMS_HIP(ctx, hipMemcpyAsync(ctx->h_d, L.ctrl + L.off.scal, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
-  VMS_HIP(ctx, hipStreamSynchronize(s));
-  stats->res = (stats->n_outer > 0) ? ctx->h_d[2] : ctx->h_d[0];
+  stats->res = (its > 0) ? ctx->h_d[2] : ctx->h_d[0];
   if (status == KS_NAN) return vms_set_error(ctx, VMS_ERR_NAN, "NaN/Inf in the outer FGMRES");
   if (status == KS_BREAKDOWN) return vms_set_error(ctx, VMS_ERR_BREAKDOWN, "outer Arnoldi breakdown");
   if (status == KS_MAXIT) {

@@ -17,8 +17,8 @@
 struct vms_dev_status {
   int inverted;        // an element had J <= 0 (sticky until cleared)
   int pad0;
-  unsigned counter;    // last-block counter of the norm reduction
   int pad1;
+  int pad2;
   double norm2;        // result of the residual-norm reduction
   double part[VMS_MAX_RED_BLOCKS];
 };
@@ -73,29 +73,6 @@ __device__ __forceinline__ double block_sum(double v, double *sm) {
   const double r = (sm[0] + sm[1]) + (sm[2] + sm[3]);
   __syncthreads();
   return r;
-}
-
-__device__ __forceinline__ double load_agent(const double *p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Returns true in exactly one block (the last to arrive); that block may then
-// read every block's partial results (written before this call).
-__device__ __forceinline__ bool last_block_arrived(unsigned *counter) {
-  __shared__ int last;
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const unsigned prev = atomicAdd(counter, 1u);
-    last = (prev == gridDim.x - 1) ? 1 : 0;
-  }
-  __syncthreads();
-  if (last) __threadfence();
-  return last != 0;
-}
-
-__device__ __forceinline__ void reset_counter(unsigned *counter) {
-  if (threadIdx.x == 0) atomicExch(counter, 0u);
 }
 
 inline int vms_red_blocks(int64_t n) {

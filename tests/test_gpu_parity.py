@@ -180,13 +180,13 @@ def test_dirichlet_and_scaling_match_oracle(problems, name):
 
 
 @pytest.mark.parametrize("precond,max_outer", [(V.PC_LDU, 1), (V.PC_UPPER, 2), (V.PC_LOWER, 2)])
-@pytest.mark.parametrize("orth", [V.ORTH_CGS2, V.ORTH_MGS])
-def test_nested_solve_matches_lu(problems, precond, max_outer, orth):
+@pytest.mark.parametrize("orth,shat", [(V.ORTH_CGS2, 0), (V.ORTH_MGS, 0), (V.ORTH_CGS2, 6)])
+def test_nested_solve_matches_lu(problems, precond, max_outer, orth, shat):
     import scipy.sparse.linalg as spla
     prob, mesh, mat, ti, disc = problems("cube-comp")
     st, K, rhs, Ks, rs, W, _ = _prepared(prob, mesh, ti, disc, 71)
     opts = V.solver_opts(rtol=1e-9, rtol_A=1e-13, rtol_S=1e-13, rtol_I=1e-14, maxit=50, maxit_A=400,
-                         maxit_S=400, maxit_I=400, precond=precond, orth=orth)
+                         maxit_S=400, maxit_I=400, precond=precond, orth=orth, shat_degree=shat)
     x, stats = prob.solve_scaled(K, rhs, opts)
     xg = x.cpu().numpy().ravel()
     xo = spla.splu(Ks.tocsc()).solve(rs)
@@ -198,14 +198,16 @@ def test_nested_solve_matches_lu(problems, precond, max_outer, orth):
 
 @pytest.mark.parametrize("name", ["cube-nu0499", "cube-incomp", "tube-hgo"])
 @pytest.mark.parametrize("precision", [V.FP64, V.MIXED])
-def test_solve_reaches_requested_residual(problems, name, precision):
+@pytest.mark.parametrize("shat", [0, 6])
+def test_solve_reaches_requested_residual(problems, name, precision, shat):
     import scipy.sparse.linalg as spla
     prob, mesh, mat, ti, disc = problems(name)
     st, K, rhs, Ks, rs, W, _ = _prepared(prob, mesh, ti, disc, 81, mirror32=(precision == V.MIXED))
     if precision == V.MIXED:
-        opts = V.solver_opts(rtol=1e-8, rtol_A=1e-5, rtol_S=1e-5, rtol_I=1e-3, precision=V.MIXED)
+        opts = V.solver_opts(rtol=1e-8, rtol_A=1e-5, rtol_S=1e-5, rtol_I=1e-3, precision=V.MIXED,
+                             shat_degree=shat)
     else:
-        opts = V.solver_opts(rtol=1e-8)
+        opts = V.solver_opts(rtol=1e-8, shat_degree=shat)
     x, stats = prob.solve_scaled(K, rhs, opts)
     xg = x.cpu().numpy().ravel()
     print(f"[solve] {name} precision={precision} stats={stats}", flush=True)
