@@ -37,6 +37,22 @@ def spmv_A_bytes(n, nnzb, elem):
     return (9 * elem + 4) * nnzb + 4 * (n + 1) + 2 * 3 * elem * n
 
 
+def pmc_traffic(key):
+    """HBM bytes per launch of the A-block SpMV from the committed rocprofv3
+    counter summary, if the kernel source is unchanged since it was taken."""
+    import hashlib
+    src = os.path.join(ROOT, "paper_1809_06350_amd", "csrc", "linalg.h")
+    prof = os.path.join(ROOT, "profiles", "spmv_A_cube64_pmc.md")
+    try:
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+        kv = dict(line.split(": ", 1) for line in open(prof).read().splitlines() if ": " in line)
+        if kv.get("source_sha256_16", "").strip() == sha:
+            return float(kv[key])
+    except (OSError, ValueError, KeyError):
+        pass
+    return None
+
+
 def time_spmv(prob, K, op, x, fp32, reps=50):
     import torch
     for _ in range(5):
@@ -98,6 +114,39 @@ def cpu_baseline(N=16, nu=0.499):
             "threads_env": threads}
 
 
+def spmv_only(prob, mesh, ti, reps):
+    """Kernel-level run for hardware counters: A-block SpMV on the assembled,
+    scaled first Newton system, and a plain copy of known size."""
+    import torch
+    from paper_1809_06350_amd import vms as V
+    st = prob.new_state()
+    tiv = V.time_int(ti.dt, ti.rho_inf, 0.0, ti.n_steps * ti.dt)
+    prob.predictor(st, tiv)
+    K, R, _ = prob.assemble(st, tiv, V.ASM_RESIDUAL | V.ASM_TANGENT)
+    K32 = prob.new_matrix(mirror32=True)
+    for a, b in ((K32.A, K.A), (K32.B, K.B), (K32.C, K.C), (K32.D, K.D)):
+        a.copy_(b)
+    prob.prepare(K32, R, None, 1e-15, True)
+    n = mesh.n_nodes
+    x = torch.randn(n, 3, dtype=torch.float64, device="cuda:0", generator=torch.Generator("cuda:0").manual_seed(1))
+    xf = x.float()
+    src = torch.ones(256 << 20, dtype=torch.uint8, device="cuda:0")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(reps):
+        prob.spmv(K32, V.OP_A, x, False)
+    for _ in range(reps):
+        prob.spmv(K32, V.OP_A, xf, True)
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    t64 = time_spmv(prob, K32, V.OP_A, x, False)
+    t32 = time_spmv(prob, K32, V.OP_A, xf, True)
+    print(json.dumps({"spmv_only": True, "n": n, "nnzb": prob.nnzb, "copy_bytes": src.numel(),
+                      "bytes_fp64": spmv_A_bytes(n, prob.nnzb, 8), "us_fp64": t64 * 1e6,
+                      "bytes_fp32": spmv_A_bytes(n, prob.nnzb, 4), "us_fp32": t32 * 1e6}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -109,6 +158,9 @@ def main():
     ap.add_argument("--shat-degree", type=int, default=8)
     ap.add_argument("--shat-ratio", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--spmv-only", type=int, default=0,
+                    help="only launch the A-block SpMV (FP64 and FP32) this many times each on the first "
+                         "Newton system, plus a 256 MiB device copy as the counter calibration kernel")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
@@ -125,6 +177,9 @@ def main():
     prob = V.Problem(mesh, mat, "cuda:0")
     n, nnzb = mesh.n_nodes, prob.nnzb
     nopts = V.newton_opts(tol_R=1e-8, l_max=20)
+    if args.spmv_only:
+        spmv_only(prob, mesh, ti, args.spmv_only)
+        return
     forms = {
         "fp64": V.solver_opts(rtol=1e-8, rtol_A=1e-6, rtol_S=1e-6, rtol_I=1e-4, shat_degree=args.shat_degree,
                               shat_ratio=args.shat_ratio),
@@ -146,7 +201,8 @@ def main():
     t64 = time_spmv(prob, K, V.OP_A, x64, False)
     by64 = spmv_A_bytes(n, nnzb, 8)
     roof = {"bound": "hbm", "kernel": "k_spmv_A<double,double>", "achieved": by64 / t64 / 1e9,
-            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": by64 / t64 / 1e9 / HBM_PEAK_GBS, "traffic": None,
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": by64 / t64 / 1e9 / HBM_PEAK_GBS,
+            "traffic": pmc_traffic("traffic_bytes_fp64") if N == 64 else None,
             "bytes_per_launch": by64, "us_per_launch": t64 * 1e6}
     extra = {}
     if "mixed" in results:
