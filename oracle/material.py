@@ -41,8 +41,8 @@ def wave_speed(mat) -> float:
     compressible materials (lambda + 2 mu = kappa + 4 mu / 3), shear wave speed
     sqrt(mu/rho0) for incompressible ones."""
     if mat.kind == NH_COMP:
-        return float(np.sqrt((mat.kappa + 4.0 * mat.mu / 3.0) / mat.rho0))
-    return float(np.sqrt(mat.mu / mat.rho0))
+        return np.sqrt((mat.kappa + 4.0 * mat.mu / 3.0) / mat.rho0)
+    return np.sqrt(mat.mu / mat.rho0)
 
 
 def structure_tensors(fibre, kd):

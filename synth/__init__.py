@@ -5,7 +5,7 @@ random vectors.  It holds none of the method's arithmetic (no residual, no
 tangent, no solver step): every number it produces is problem data that both
 sides consume independently.
 """
-from .mesh import cube_mesh, tube_mesh, Mesh
+from .mesh import cube_mesh, tube_mesh, helical_fibres, Mesh
 from .cases import (Material, TimeInt, cube_case, tube_case, material_from_nu,
                     random_vector, random_state, NH_COMP, NH_INCOMP, HGO_INCOMP)
 

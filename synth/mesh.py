@@ -132,6 +132,19 @@ def cube_mesh(N: int, seed: int = 0, jitter: float = 0.01, t_top: float = -1.0e4
                 meta={"N": N, "seed": seed, "jitter": jitter, "t_top": t_top})
 
 
+def helical_fibres(X, tets, phi):
+    """Fibre directions a_{1,2} = cos(phi) e_theta +- sin(phi) e_z at the element
+    centroids and their derivatives with respect to phi (phi may be complex)."""
+    cen = X[tets].mean(axis=1)
+    ang = np.arctan2(cen[:, 1], cen[:, 0])
+    e_t = np.stack([-np.sin(ang), np.cos(ang), np.zeros_like(ang)], axis=1)
+    e_z = np.tile(np.array([0.0, 0.0, 1.0]), (tets.shape[0], 1))
+    c, s = np.cos(phi), np.sin(phi)
+    fibre = np.stack([c * e_t + s * e_z, c * e_t - s * e_z], axis=1)
+    dfibre = np.stack([-s * e_t + c * e_z, -s * e_t - c * e_z], axis=1)
+    return fibre, dfibre
+
+
 def tube_mesh(nr: int, nt: int, nz: int, r_in: float = 1.0, wall: float = 0.2,
               length: float = 2.0, fibre_deg: float = 45.0, stretch: float = 1.5,
               t_end: float = 1.0) -> Mesh:
@@ -157,15 +170,10 @@ def tube_mesh(nr: int, nt: int, nz: int, r_in: float = 1.0, wall: float = 0.2,
     dir_mask[kz == 0, 0:3] = 1
     dir_mask[kz == nz, 2] = 1
     dir_vel[kz == nz, 2] = (stretch - 1.0) * length / t_end
-    cen = X[tets].mean(axis=1)
-    ang = np.arctan2(cen[:, 1], cen[:, 0])
-    e_t = np.stack([-np.sin(ang), np.cos(ang), np.zeros_like(ang)], axis=1)
-    e_z = np.tile(np.array([0.0, 0.0, 1.0]), (tets.shape[0], 1))
-    phi = np.deg2rad(fibre_deg)
-    fibre = np.stack([np.cos(phi) * e_t + np.sin(phi) * e_z,
-                      np.cos(phi) * e_t - np.sin(phi) * e_z], axis=1)
+    fibre, _ = helical_fibres(X, tets, np.deg2rad(fibre_deg))
     bfaces = np.zeros((0, 3), dtype=np.int32)
     traction = np.zeros((0, 3))
     return Mesh(name=f"tube{nr}x{nt}x{nz}", X=X, tets=tets, bfaces=bfaces,
                 traction=traction, dir_mask=dir_mask, dir_vel=dir_vel, fibre=fibre,
-                meta={"nr": nr, "nt": nt, "nz": nz, "stretch": stretch, "t_end": t_end})
+                meta={"nr": nr, "nt": nt, "nz": nz, "stretch": stretch, "t_end": t_end,
+                      "fibre_rad": float(np.deg2rad(fibre_deg))})
