@@ -275,6 +275,48 @@ int vms_step(vms_ctx *ctx, const vms_mesh *mesh, const vms_material *mat,
              const vms_newton_opts *nopts, const vms_solver_opts *sopts,
              void *workspace, size_t workspace_bytes, vms_step_stats *stats);
 
+/* ---- adjoint (implicit differentiation of a converged time step) --------- */
+
+/* Transposed solve (W K^T W) lam* = rhs_scaled through the same nested
+ * preconditioner built for K^T = [[A^T, C^T], [B^T, D^T]] (Algorithm 1 applied
+ * to the transposed system; its Schur complement is S^T = D^T - B^T A^-T C^T).
+ * K holds the scaled system from vms_prepare_system (K->W its scaling); Kt is
+ * caller storage with the same layout (FP32 parts needed only for VMS_MIXED)
+ * and is overwritten with the transposed blocks.  [sync]  Same status codes
+ * as vms_solve_scaled. */
+int vms_solve_transpose(vms_ctx *ctx, const vms_mesh *mesh, const vms_matrix *K, vms_matrix *Kt,
+                        const double *rhs_scaled, double *lam_scaled, const vms_solver_opts *opts,
+                        void *workspace, size_t workspace_bytes, vms_solve_stats *stats);
+
+/* out[k] (HOST, 5 doubles) = lam^T dR/dtheta_k at the generalized-alpha stages
+ * of `st`, theta = (mu, kappa, k1, k2, fibre angle) for the bits set in pmask
+ * (1 << k); lam[n][4] = (lam_m, lam_p).  The derivatives differentiate the
+ * residual of the consistent-linearization appendix in closed form (tau_M
+ * depends on mu and kappa through the wave speed).  dfibre[m][2][3] = d a_i /
+ * d angle (needed for bit 4).  Workspace >= vms_adjoint_workspace.  [sync] */
+int vms_param_sensitivity(vms_ctx *ctx, const vms_mesh *mesh, const vms_material *mat,
+                          const vms_timeint *ti, const vms_state *st, const double *dfibre,
+                          const double *lam, int pmask, double *out, void *workspace,
+                          size_t workspace_bytes);
+
+/* Workspace bytes of vms_adjoint_step / vms_param_sensitivity. */
+size_t vms_adjoint_workspace(const vms_mesh *mesh, const vms_solver_opts *opts);
+
+/* One backward step of the adjoint through the time history.  st holds y_n,
+ * y-dot_n and, as the iterate, the converged y_{n+1}, y-dot_{n+1}.  In:
+ * ybar1, ydbar1[n][7] = dJ/d(y_{n+1}), dJ/d(y-dot_{n+1}) as (u 3, p, v 3) and
+ * (u-dot 3, p-dot, v-dot 3).  Out: ybar0, ydbar0 = dJ/d(y_n), dJ/d(y-dot_n).
+ * Re-assembles the tangent at the converged state into K, solves the
+ * transposed reduced system (Kt is its storage), recovers the kinematic
+ * multiplier from the block factorisation, back-propagates through the
+ * generalized-alpha stage relations and subtracts lam^T dG/dtheta from
+ * dJdtheta (HOST, 5 doubles, bits of pmask).  [sync] */
+int vms_adjoint_step(vms_ctx *ctx, const vms_mesh *mesh, const vms_material *mat, const vms_timeint *ti,
+                     const vms_state *st, const double *dfibre, vms_matrix *K, vms_matrix *Kt,
+                     const double *ybar1, const double *ydbar1, double *ybar0, double *ydbar0, int pmask,
+                     double *dJdtheta, const vms_solver_opts *opts, double eps_diag, void *workspace,
+                     size_t workspace_bytes, vms_solve_stats *stats);
+
 #ifdef __cplusplus
 }
 #endif

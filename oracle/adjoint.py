@@ -140,35 +140,41 @@ def theta_cotangent(mesh, mat, ti, theta, sn, s1, lam, k):
     return float(np.sum(lam_m * R[:, :, 0:3]) + np.sum(lam_p * R[:, :, 3]))
 
 
-def adjoint_gradient(mesh, mat, ti, theta, states, dJdu, params=(0, 1)):
-    """dJ/dtheta for J = J(u_N) with dJ/du_N = dJdu [n][3]."""
+def backward_step(mesh, mat, ti, theta, sn, s1, ybar, ydbar, params=(0, 1)):
+    """One step of the recursion: returns (y-bar_n, y-dot-bar_n, -lam^T dG/dtheta, lam)."""
     mesh_t, mat_t = with_params(mesh, mat, theta)
     disc = AS.Discretization(mesh_t, mat_t)
     am, af, gm = E.genalpha(ti.rho_inf)
     n = mesh.n_nodes
-    ybar = np.zeros((n, 7))
-    ybar[:, 0:3] = dJdu
-    ydbar = np.zeros((n, 7))
-    grad = np.zeros(5)
     mask = np.zeros((n, 7), dtype=bool)
     mask[:, 0:3] = disc.vmask
     mask[:, 3] = disc.pmask
     mask[:, 4:7] = disc.vmask
     d = mask.ravel()
     keep = sp.diags((~d).astype(float))
+    st = NW.stage(sn, s1, am, af)
+    Kf, _ = F3.full_system(disc, ti, st, 0.0)
+    Kd = (keep @ Kf @ keep + sp.diags(d.astype(float))).tocsc()
+    g = ydbar + gm * ti.dt * ybar
+    g[mask] = 0.0
+    lam = spla.splu(Kd.T.tocsc()).solve(g.ravel()).reshape(n, 7)
+    cot_y, cot_yd = step_cotangents(mesh_t, mat_t, ti, sn, s1, lam)
+    dth = np.zeros(5)
+    for k in params:
+        dth[k] = -theta_cotangent(mesh, mat, ti, theta, sn, s1, lam, k)
+    return ybar - cot_y, (1.0 - gm) * ti.dt * ybar - cot_yd, dth, lam
+
+
+def adjoint_gradient(mesh, mat, ti, theta, states, dJdu, params=(0, 1)):
+    """dJ/dtheta for J = J(u_N) with dJ/du_N = dJdu [n][3]."""
+    n = mesh.n_nodes
+    ybar = np.zeros((n, 7))
+    ybar[:, 0:3] = dJdu
+    ydbar = np.zeros((n, 7))
+    grad = np.zeros(5)
     for s in range(len(states) - 2, -1, -1):
-        sn, s1 = states[s], states[s + 1]
-        st = NW.stage(sn, s1, am, af)
-        load = NW.load_scale(ti, s * ti.dt + af * ti.dt)
-        Kf, _ = F3.full_system(disc, ti, st, load)
-        Kd = (keep @ Kf @ keep + sp.diags(d.astype(float))).tocsc()
-        g = ydbar + gm * ti.dt * ybar
-        g[mask] = 0.0
-        lam = spla.splu(Kd.T.tocsc()).solve(g.ravel()).reshape(n, 7)
-        cot_y, cot_yd = step_cotangents(mesh_t, mat_t, ti, sn, s1, lam)
-        for k in params:
-            grad[k] -= theta_cotangent(mesh, mat, ti, theta, sn, s1, lam, k)
-        ybar, ydbar = ybar - cot_y, (1.0 - gm) * ti.dt * ybar - cot_yd
+        ybar, ydbar, dth, _ = backward_step(mesh, mat, ti, theta, states[s], states[s + 1], ybar, ydbar, params)
+        grad += dth
     return grad
 
 

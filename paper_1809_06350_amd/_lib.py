@@ -98,6 +98,15 @@ SIGNATURES = {
     "vms_step_workspace": (C.c_size_t, [P(Mesh), P(SolverOpts)]),
     "vms_step": (C.c_int, [C.c_void_p, P(Mesh), P(Material), P(TimeInt), P(State), C.c_void_p, P(Matrix),
                            P(NewtonOpts), P(SolverOpts), C.c_void_p, C.c_size_t, P(StepStats)]),
+    "vms_solve_transpose": (C.c_int, [C.c_void_p, P(Mesh), P(Matrix), P(Matrix), C.c_void_p, C.c_void_p,
+                                      P(SolverOpts), C.c_void_p, C.c_size_t, P(SolveStats)]),
+    "vms_param_sensitivity": (C.c_int, [C.c_void_p, P(Mesh), P(Material), P(TimeInt), P(State), C.c_void_p,
+                                        C.c_void_p, C.c_int, P(C.c_double), C.c_void_p, C.c_size_t]),
+    "vms_adjoint_workspace": (C.c_size_t, [P(Mesh), P(SolverOpts)]),
+    "vms_adjoint_step": (C.c_int, [C.c_void_p, P(Mesh), P(Material), P(TimeInt), P(State), C.c_void_p, P(Matrix),
+                                   P(Matrix), C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int,
+                                   P(C.c_double), P(SolverOpts), C.c_double, C.c_void_p, C.c_size_t,
+                                   P(SolveStats)]),
 }
 
 _lib = None

@@ -14,7 +14,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libvms.so")
 
-SOURCES = ["api.hip", "assembly.hip", "solver.hip", "setup.cpp"]
+SOURCES = ["api.hip", "assembly.hip", "solver.hip", "adjoint.hip", "setup.cpp"]
 HEADERS = ["vms_internal.h", "linalg.h"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -71,10 +71,13 @@ __global__ void __launch_bounds__(128)
 k_assemble(int ne, const int32_t *__restrict__ elems, const double *__restrict__ X,
            const int32_t *__restrict__ tets, const double *__restrict__ fibre, MatP mp, vms_ga ga,
            StateP sp, int64_t nnzb, const int32_t *__restrict__ elem_blk, double *KA, double *KB,
-           double *KC, double *KD, double *R, double *corr, int *inverted) {
+           double *KC, double *KD, double *R, double *corr, const double *__restrict__ lam, double *vjp,
+           const double *__restrict__ dfibre, int pmask, double *sens, int *inverted) {
   constexpr bool RES = FL & VMS_ASM_RESIDUAL;
   constexpr bool TAN = FL & VMS_ASM_TANGENT;
   constexpr bool COR = FL & VMS_ASM_RKCORR;
+  constexpr bool VJP = FL & VMS_ASM_VJP;
+  constexpr bool SENS = FL & VMS_ASM_SENS;
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= ne) return;
   const int e = elems[t];
@@ -273,6 +276,94 @@ k_assemble(int ne, const int32_t *__restrict__ elems, const double *__restrict__
     PaA[a] = w * J * (QB * Sbp + QD * beta[a] * dpq[a] + divv);
   }
 
+  if (SENS) {
+    // lam_e^T dR_e/dtheta for theta = (mu, kappa, k1, k2, fibre angle phi)
+    double Xb[3], Sdr[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) Xb[i] = w * Srv[i] + V * gradp[i];
+    const bool comp = (mp.kind == VMS_NH_COMP);
+    const double c2w = comp ? (mp.kappa + 4.0 * mp.mu / 3.0) : mp.mu;
+    for (int k = 0; k < 5; ++k) {
+      double val = 0.0;
+      if (pmask & (1 << k)) {
+        double dP[3][3] = {}, dtau = 0.0, drho[4] = {0, 0, 0, 0}, dbeta[4] = {0, 0, 0, 0};
+        if (k == 0) {           // mu: neo-Hookean stress and tau_M through the wave speed
+#pragma unroll
+          for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int I = 0; I < 3; ++I) dP[i][I] = Jm23 * (F[i][I] - trC / 3.0 * FiT[i][I]);
+          dtau = comp ? -tau * (2.0 / 3.0) / c2w : -0.5 * tau / mp.mu;
+        } else if (k == 1) {    // kappa: rho(p), beta(p) and tau_M
+          if (comp) {
+            dtau = -0.5 * tau / c2w;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              const double sq = sqrt(pq[q] * pq[q] + mp.kappa * mp.kappa);
+              drho[q] = mp.rho0 * (mp.kappa * mp.kappa / sq - sq - pq[q]) / (mp.kappa * mp.kappa);
+              dbeta[q] = -mp.kappa / (sq * sq * sq);
+            }
+          }
+        } else if (hgo) {       // fibre families
+#pragma unroll
+          for (int f = 0; f < 2; ++f) {
+            const double E = Jm23 * HC[f] - 1.0;
+            if (k == 2 || k == 3) {
+              const double sc = (k == 2) ? W1[f] / mp.k1 : W1[f] * E * E;
+#pragma unroll
+              for (int i = 0; i < 3; ++i)
+#pragma unroll
+                for (int I = 0; I < 3; ++I) {
+                  const double FH = mp.kd * F[i][I] + (1.0 - 3.0 * mp.kd) * Fa[f][i] * fa[f][I];
+                  dP[i][I] += sc * Jm23 * (2.0 * FH - 2.0 / 3.0 * HC[f] * FiT[i][I]);
+                }
+            } else {            // phi: a_f -> a_f + da_f dphi
+              double da[3], Fda[3];
+#pragma unroll
+              for (int I = 0; I < 3; ++I) da[I] = dfibre[6 * (int64_t)e + 3 * f + I];
+#pragma unroll
+              for (int i = 0; i < 3; ++i) Fda[i] = F[i][0] * da[0] + F[i][1] * da[1] + F[i][2] * da[2];
+              const double dHC = (1.0 - 3.0 * mp.kd) * 2.0 * dot3(Fa[f], Fda);
+              const double dW1 = W2[f] * Jm23 * dHC;
+#pragma unroll
+              for (int i = 0; i < 3; ++i)
+#pragma unroll
+                for (int I = 0; I < 3; ++I) {
+                  const double FH = mp.kd * F[i][I] + (1.0 - 3.0 * mp.kd) * Fa[f][i] * fa[f][I];
+                  const double FdH = (1.0 - 3.0 * mp.kd) * (Fda[i] * fa[f][I] + Fa[f][i] * da[I]);
+                  const double Q = Jm23 * (2.0 * FH - 2.0 / 3.0 * HC[f] * FiT[i][I]);
+                  const double dQ = Jm23 * (2.0 * FdH - 2.0 / 3.0 * dHC * FiT[i][I]);
+                  dP[i][I] += dW1 * Q + W1[f] * dQ;
+                }
+            }
+          }
+        }
+        // assemble lam^T dR/dtheta over the element's nodes
+        double Sdrv[3] = {0, 0, 0};
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+          for (int i = 0; i < 3; ++i) Sdrv[i] += drho[q] * dvq[q][i];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+          const double *la = lam + 4 * (int64_t)nd[a];
+          double dRp = dtau * J * dot3(g[a], Xb) + tau * J * w * dot3(g[a], Sdrv);
+#pragma unroll
+          for (int q = 0; q < 4; ++q) dRp += w * J * (QB + (q == a ? QD : 0.0)) * dbeta[q] * dpq[q];
+          val += la[3] * dRp;
+#pragma unroll
+          for (int i = 0; i < 3; ++i) {
+            double dRm = V * (dP[i][0] * G[a][0] + dP[i][1] * G[a][1] + dP[i][2] * G[a][2]);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) dRm += w * J * (QB + (q == a ? QD : 0.0)) * drho[q] * dvq[q][i];
+            val += la[i] * dRm;
+          }
+        }
+      }
+      sens[5 * (int64_t)e + k] = val;
+    }
+    (void)Sdr;
+  }
+
   if (RES) {
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
@@ -291,7 +382,7 @@ k_assemble(int ne, const int32_t *__restrict__ elems, const double *__restrict__
     }
   }
 
-  if (TAN || COR) {
+  if (TAN || COR || VJP) {
     // per-quadrature-point weights for the sum_q c_q N_qA N_qB forms
     double cR[4], cB[4], cBp[4];
     double SR = 0, SB = 0, SBp = 0;
@@ -364,36 +455,53 @@ k_assemble(int ne, const int32_t *__restrict__ elems, const double *__restrict__
           Kpu[j] = g[b][j] * PaA[a] - J * w * Lg[j] +
                    tau * J * (g[b][j] * gX[a] - g[a][j] * gX[b] - V * gg * gradp[j]);
 
+        // remaining partial derivatives of (R_m, R_p)_A with respect to node B's staged fields
+        double rpv[3] = {0, 0, 0};  // sum_q w J rho_p,q v-dot_q N_qA N_qB
+        double rN = 0.0;             // sum_q w rho_q N_qB
+        double st = 0.0;             // sum_q w rho_p,q N_qB (g_A . v-dot_q)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const double na = QB + (q == a ? QD : 0.0), nb = QB + (q == b ? QD : 0.0);
+#pragma unroll
+          for (int i = 0; i < 3; ++i) rpv[i] += w * J * rhop[q] * dvq[q][i] * na * nb;
+          rN += w * rho[q] * nb;
+          st += w * rhop[q] * nb * dot3(g[a], dvq[q]);
+        }
+        const double mR = qsum2(cR, SR, a, b);           // dR_m/dv-dot = mR I
+        double dRm_dp[3], dRp_dvd[3], dRp_dv[3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+          dRm_dp[i] = rpv[i] - J * g[a][i] * w;
+          dRp_dvd[i] = tau * J * g[a][i] * rN;
+          dRp_dv[i] = J * g[b][i] * w;
+        }
+        const double dRp_dp = qsum2(cBp, SBp, a, b) + tau * J * (V * gg + st);
+        const double dRp_dpd = qsum2(cB, SB, a, b);
         if (TAN) {
           const int64_t blk = elem_blk[16 * (int64_t)e + 4 * a + b];
-          const double mR = qsum2(cR, SR, a, b);
 #pragma unroll
           for (int i = 0; i < 3; ++i)
 #pragma unroll
             for (int j = 0; j < 3; ++j)
               KA[(3 * i + j) * nnzb + blk] += (i == j ? ga.am * mR : 0.0) + ga.c3 * Ku[i][j];
-          // B = c2 dR_m/dp
-          double rpv[3] = {0, 0, 0};
 #pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            const double nn = (QB + (q == a ? QD : 0.0)) * (QB + (q == b ? QD : 0.0));
+          for (int i = 0; i < 3; ++i) KB[i * nnzb + blk] += ga.c2 * dRm_dp[i];
 #pragma unroll
-            for (int i = 0; i < 3; ++i) rpv[i] += w * J * rhop[q] * dvq[q][i] * nn;
+          for (int j = 0; j < 3; ++j) KC[j * nnzb + blk] += ga.am * dRp_dvd[j] + ga.c2 * dRp_dv[j] + ga.c3 * Kpu[j];
+          KD[blk] += ga.am * dRp_dpd + ga.c2 * dRp_dp;
+        }
+        if (VJP) {
+          // cotangents of node B's staged fields: lam_A^T dR_A / d(field_B)
+          const double *la = lam + 4 * (int64_t)nd[a];
+          double *ob = vjp + 11 * (int64_t)nd[b];
+#pragma unroll
+          for (int j = 0; j < 3; ++j) {
+            ob[j] += la[0] * Ku[0][j] + la[1] * Ku[1][j] + la[2] * Ku[2][j] + la[3] * Kpu[j];
+            ob[4 + j] += la[3] * dRp_dv[j];
+            ob[7 + j] += la[j] * mR + la[3] * dRp_dvd[j];
           }
-#pragma unroll
-          for (int i = 0; i < 3; ++i) KB[i * nnzb + blk] += ga.c2 * (rpv[i] - J * g[a][i] * w);
-          // C = am dR_p/dv-dot + c2 dR_p/dv + c3 dR_p/du
-          double rN = 0.0;  // sum_q w rho_q N_qB
-#pragma unroll
-          for (int q = 0; q < 4; ++q) rN += w * rho[q] * (QB + (q == b ? QD : 0.0));
-#pragma unroll
-          for (int j = 0; j < 3; ++j)
-            KC[j * nnzb + blk] += ga.am * tau * J * g[a][j] * rN + ga.c2 * J * g[b][j] * w + ga.c3 * Kpu[j];
-          // D = am dR_p/dp-dot + c2 dR_p/dp
-          double st = 0.0;
-#pragma unroll
-          for (int q = 0; q < 4; ++q) st += w * rhop[q] * (QB + (q == b ? QD : 0.0)) * dot3(g[a], dvq[q]);
-          KD[blk] += ga.am * qsum2(cB, SB, a, b) + ga.c2 * (qsum2(cBp, SBp, a, b) + tau * J * (V * gg + st));
+          ob[3] += la[0] * dRm_dp[0] + la[1] * dRm_dp[1] + la[2] * dRm_dp[2] + la[3] * dRp_dp;
+          ob[10] += la[3] * dRp_dpd;
         }
         if (COR) {
 #pragma unroll
@@ -633,7 +741,8 @@ int vms_check_mesh(vms_ctx *ctx, const vms_mesh *m) {
 
 int vms_launch_assemble(vms_ctx *ctx, const vms_mesh *mesh, const vms_material *mat, const vms_ga &ga,
                         const vms_state *st, const double *f_ext, vms_matrix *K, double *R, double *corr,
-                        unsigned flags) {
+                        unsigned flags, const double *lam, double *vjp, const double *dfibre, int pmask,
+                        double *sens) {
   const int n = mesh->n_nodes;
   const int64_t nnzb = mesh->nnzb;
   MatP mp{mat->kind, mat->rho0, mat->mu, mat->kappa, mat->k1, mat->k2, mat->kd, mat->c_m, 0.0};
@@ -649,6 +758,13 @@ int vms_launch_assemble(vms_ctx *ctx, const vms_mesh *mesh, const vms_material *
     hipLaunchKernelGGL(k_fill, dim3(grid1(3 * nnzb)), dim3(VMS_BLOCK), 0, ctx->stream, 3 * nnzb, K->C, 0.0);
     hipLaunchKernelGGL(k_fill, dim3(grid1(nnzb)), dim3(VMS_BLOCK), 0, ctx->stream, nnzb, K->D, 0.0);
   }
+  const bool vj = flags & VMS_ASM_VJP;
+  if ((flags & VMS_ASM_SENS) && (!lam || !sens || ((pmask & 16) && !dfibre)))
+    return vms_set_error(ctx, VMS_ERR_ARG, "sensitivity needs lam, an output array (and dfibre for phi)");
+  if (vj) {
+    if (!lam || !vjp) return vms_set_error(ctx, VMS_ERR_ARG, "VJP needs lam and an output array");
+    hipLaunchKernelGGL(k_fill, dim3(grid1(11 * (int64_t)n)), dim3(VMS_BLOCK), 0, ctx->stream, 11 * (int64_t)n, vjp, 0.0);
+  }
   if (res || cor)
     hipLaunchKernelGGL(k_init_residual, dim3(grid1(n)), dim3(VMS_BLOCK), 0, ctx->stream, n, f_ext, ga.load,
                        res ? R : nullptr, cor ? corr : nullptr);
@@ -662,9 +778,10 @@ int vms_launch_assemble(vms_ctx *ctx, const vms_mesh *mesh, const vms_material *
   case FLV:                                                                                               \
     hipLaunchKernelGGL(k_assemble<FLV>, gr, bl, 0, ctx->stream, ne, el, mesh->X, mesh->tets, mesh->fibre, \
                        mp, ga, sp, nnzb, mesh->elem_blk, K ? K->A : nullptr, K ? K->B : nullptr,           \
-                       K ? K->C : nullptr, K ? K->D : nullptr, R, corr, &ctx->dstat->inverted);           \
+                       K ? K->C : nullptr, K ? K->D : nullptr, R, corr, lam, vjp, dfibre, pmask, sens,    \
+                       &ctx->dstat->inverted);                                                             \
     break;
-    switch (flags & 7u) {
+    switch (flags & 31u) {
       VMS_ASM_CASE(1)
       VMS_ASM_CASE(2)
       VMS_ASM_CASE(3)
@@ -672,6 +789,8 @@ int vms_launch_assemble(vms_ctx *ctx, const vms_mesh *mesh, const vms_material *
       VMS_ASM_CASE(5)
       VMS_ASM_CASE(6)
       VMS_ASM_CASE(7)
+      VMS_ASM_CASE(8)
+      VMS_ASM_CASE(16)
       default: return vms_set_error(ctx, VMS_ERR_ARG, "no assembly flag set");
     }
 #undef VMS_ASM_CASE

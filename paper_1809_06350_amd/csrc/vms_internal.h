@@ -12,6 +12,10 @@
 
 #define VMS_BLOCK 256
 #define VMS_MAX_RED_BLOCKS 1024
+// internal assembly mode: cotangents lam^T dR/d(staged fields), [n][11] = (u 3, p, v 3, v-dot 3, p-dot)
+#define VMS_ASM_VJP 8u
+// internal assembly mode: per-element lam_e^T dR_e/dtheta, [m][5] for (mu, kappa, k1, k2, phi)
+#define VMS_ASM_SENS 16u
 
 // Small device-side status area owned by a context (allocated at create).
 struct vms_dev_status {
@@ -93,7 +97,9 @@ vms_ga vms_genalpha(const vms_timeint *ti);
 int vms_check_mesh(vms_ctx *ctx, const vms_mesh *m);
 int vms_launch_assemble(vms_ctx *ctx, const vms_mesh *mesh, const vms_material *mat,
                         const vms_ga &ga, const vms_state *st, const double *f_ext,
-                        vms_matrix *K, double *R, double *corr, unsigned flags);
+                        vms_matrix *K, double *R, double *corr, unsigned flags,
+                        const double *lam = nullptr, double *vjp = nullptr, const double *dfibre = nullptr,
+                        int pmask = 0, double *sens = nullptr);
 int vms_launch_clear_inverted(vms_ctx *ctx);
 int vms_launch_norm(vms_ctx *ctx, const vms_mesh *mesh, const vms_ga &ga, const vms_state *st,
                     const double *R);

@@ -126,6 +126,7 @@ class Problem:
         if rc != 0:
             raise VmsError("vms_ctx_create", rc, "no usable HIP device")
         self.ctx = ctx
+        self.dfibre = None
         self.f_ext = torch.zeros(3 * n, dtype=torch.float64, device=dev)
         self._check(lib.vms_nodal_load(self.ctx, C.byref(self.cmesh), _p(self.f_ext)), "vms_nodal_load")
         self._ws = None
@@ -243,6 +244,50 @@ class Problem:
     def newton_update(self, st, ti, K, x):
         self._check(self.lib.vms_newton_update(self.ctx, C.byref(self.cmesh), C.byref(ti), C.byref(self.cstate(st)),
                                                _p(K.W), _p(x)), "vms_newton_update")
+
+    def solve_transpose(self, K, Kt, rhs, opts, x=None, allow_nc=False):
+        nb = self.lib.vms_solve_workspace(C.byref(self.cmesh), C.byref(opts))
+        ws = self.workspace(nb + 512)
+        if x is None:
+            x = torch.empty_like(rhs)
+        stats = L.SolveStats()
+        self._check(self.lib.vms_solve_transpose(self.ctx, C.byref(self.cmesh), C.byref(K.c()), C.byref(Kt.c()),
+                                                 _p(rhs), _p(x), C.byref(opts), _p(ws), ws.numel(),
+                                                 C.byref(stats)), "vms_solve_transpose", allow_nc=allow_nc)
+        return x, stats.as_dict()
+
+    def adjoint_workspace(self, opts):
+        nb = self.lib.vms_adjoint_workspace(C.byref(self.cmesh), C.byref(opts))
+        return self.workspace(nb + 512)
+
+    def param_sensitivity(self, st, ti, lam, pmask, opts=None):
+        ws = self.adjoint_workspace(opts or solver_opts())
+        out = (C.c_double * 5)()
+        self._check(self.lib.vms_param_sensitivity(self.ctx, C.byref(self.cmesh), C.byref(self.cmat), C.byref(ti),
+                                                   C.byref(self.cstate(st)), _p(self.dfibre), _p(lam), pmask,
+                                                   out, _p(ws), ws.numel()), "vms_param_sensitivity")
+        return np.array(out[:])
+
+    def adjoint_step(self, st, ti, K, Kt, ybar1, ydbar1, pmask, dJ, opts, eps_diag=1e-15):
+        """One backward step; returns (ybar0, ydbar0, stats) and updates dJ (numpy, 5) in place."""
+        ws = self.adjoint_workspace(opts)
+        ybar0 = torch.empty_like(ybar1)
+        ydbar0 = torch.empty_like(ydbar1)
+        acc = (C.c_double * 5)(*dJ)
+        stats = L.SolveStats()
+        self._check(self.lib.vms_adjoint_step(self.ctx, C.byref(self.cmesh), C.byref(self.cmat), C.byref(ti),
+                                              C.byref(self.cstate(st)), _p(self.dfibre), C.byref(K.c()),
+                                              C.byref(Kt.c()), _p(ybar1), _p(ydbar1), _p(ybar0), _p(ydbar0),
+                                              pmask, acc, C.byref(opts), eps_diag, _p(ws), ws.numel(),
+                                              C.byref(stats)), "vms_adjoint_step")
+        dJ[:] = np.array(acc[:])
+        return ybar0, ydbar0, stats.as_dict()
+
+    def set_fibres(self, fibre, dfibre):
+        """Upload fibre directions and their derivative with respect to the fibre angle."""
+        self.d["fibre"] = torch.from_numpy(np.ascontiguousarray(fibre, dtype=np.float64)).to(self.dev)
+        self.dfibre = torch.from_numpy(np.ascontiguousarray(dfibre, dtype=np.float64)).to(self.dev)
+        self.cmesh.fibre = _p(self.d["fibre"])
 
     def step(self, st, ti, nopts, sopts, K=None, allow_nc=False):
         if K is None:
