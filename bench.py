@@ -157,6 +157,8 @@ def main():
     ap.add_argument("--forms", default="fp64,mixed")
     ap.add_argument("--shat-degree", type=int, default=8)
     ap.add_argument("--shat-ratio", type=float, default=20.0)
+    ap.add_argument("--mixed-tol", default="1e-6,1e-6,1e-4",
+                    help="intermediate A, Schur and inner tolerances of the mixed form")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--spmv-only", type=int, default=0,
                     help="only launch the A-block SpMV (FP64 and FP32) this many times each on the first "
@@ -177,13 +179,14 @@ def main():
     prob = V.Problem(mesh, mat, "cuda:0")
     n, nnzb = mesh.n_nodes, prob.nnzb
     nopts = V.newton_opts(tol_R=1e-8, l_max=20)
+    mt = [float(x) for x in args.mixed_tol.split(",")]
     if args.spmv_only:
         spmv_only(prob, mesh, ti, args.spmv_only)
         return
     forms = {
         "fp64": V.solver_opts(rtol=1e-8, rtol_A=1e-6, rtol_S=1e-6, rtol_I=1e-4, shat_degree=args.shat_degree,
                               shat_ratio=args.shat_ratio),
-        "mixed": V.solver_opts(rtol=1e-8, rtol_A=1e-5, rtol_S=1e-5, rtol_I=1e-3, precision=V.MIXED,
+        "mixed": V.solver_opts(rtol=1e-8, rtol_A=mt[0], rtol_S=mt[1], rtol_I=mt[2], precision=V.MIXED,
                                shat_degree=args.shat_degree, shat_ratio=args.shat_ratio),
     }
     results = {}

@@ -59,15 +59,29 @@ __device__ __forceinline__ double dot3(const double *a, const double *b) {
   return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
 }
 
-// sum_q c_q N_qA N_qB for the symmetric rule (N_qA = QB + QD delta_qA)
-__device__ __forceinline__ double qsum2(const double *c, double S, int A, int B) {
-  double r = QB * QB * S + QB * QD * (c[A] + c[B]);
-  if (A == B) r += QD * QD * c[A];
+// Sum over the four lanes of an element (every lane receives the same bits:
+// the pairwise sums are commutative and combined in the same order).
+__device__ __forceinline__ double qsum4(double v) {
+  v += __shfl_xor(v, 1, 64);
+  v += __shfl_xor(v, 2, 64);
+  return v;
+}
+__device__ __forceinline__ double qget(double v, int src_lane) { return __shfl(v, src_lane, 64); }
+
+// sum_q c_q N_qA N_qB for the symmetric rule (N_qA = QB + QD delta_qA), S = sum_q c_q
+__device__ __forceinline__ double qsum2(double ca, double cb, double S, bool same) {
+  double r = QB * QB * S + QB * QD * (ca + cb);
+  if (same) r += QD * QD * ca;
   return r;
 }
 
-template <int FL>
-__global__ void __launch_bounds__(128)
+// Four lanes per element: lane a owns local node a (and quadrature point a of
+// the symmetric rule, whose point q has N_q = QB + QD delta_qA).  Element sums
+// (F, grad v, grad p, quadrature sums) are quad reductions; in the pair loop
+// lane a computes row a of the element matrix, fetching node b's data from
+// lane b by shuffle, so no lane holds the whole element.
+template <int FL, bool HGO>
+__global__ void __launch_bounds__(256)
 k_assemble(int ne, const int32_t *__restrict__ elems, const double *__restrict__ X,
            const int32_t *__restrict__ tets, const double *__restrict__ fibre, MatP mp, vms_ga ga,
            StateP sp, int64_t nnzb, const int32_t *__restrict__ elem_blk, double *KA, double *KB,
@@ -78,79 +92,76 @@ k_assemble(int ne, const int32_t *__restrict__ elems, const double *__restrict__
   constexpr bool COR = FL & VMS_ASM_RKCORR;
   constexpr bool VJP = FL & VMS_ASM_VJP;
   constexpr bool SENS = FL & VMS_ASM_SENS;
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= ne) return;
-  const int e = elems[t];
-  int nd[4];
-#pragma unroll
-  for (int a = 0; a < 4; ++a) nd[a] = tets[4 * (int64_t)e + a];
+  const int gt = blockIdx.x * blockDim.x + threadIdx.x;
+  const int k = gt >> 2;
+  const int a = gt & 3;
+  const int base = (threadIdx.x & 63) & ~3;
+  const bool act = k < ne;
+  const int e = elems[act ? k : ne - 1];
+  const int nda = tets[4 * (int64_t)e + a];
 
-  // staged nodal values: rates at n+alpha_m, values at n+alpha_f
-  double u[4][3], v[4][3], dv[4][3], rk[4][3], p[4], dp[4], Xe[4][3];
+  // staged values of node a: rates at n+alpha_m, values at n+alpha_f
+  double Xa[3], ua[3], va[3], dva[3], rka[3];
+  const int64_t o3 = 3 * (int64_t)nda;
 #pragma unroll
-  for (int a = 0; a < 4; ++a) {
-    const int64_t o = 3 * (int64_t)nd[a];
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-      Xe[a][i] = X[o + i];
-      u[a][i] = sp.u_n[o + i] + ga.af * (sp.u[o + i] - sp.u_n[o + i]);
-      v[a][i] = sp.v_n[o + i] + ga.af * (sp.v[o + i] - sp.v_n[o + i]);
-      dv[a][i] = sp.dv_n[o + i] + ga.am * (sp.dv[o + i] - sp.dv_n[o + i]);
-      if (COR) rk[a][i] = sp.du_n[o + i] + ga.am * (sp.du[o + i] - sp.du_n[o + i]) - v[a][i];
-    }
-    p[a] = sp.p_n[nd[a]] + ga.af * (sp.p[nd[a]] - sp.p_n[nd[a]]);
-    dp[a] = sp.dp_n[nd[a]] + ga.am * (sp.dp[nd[a]] - sp.dp_n[nd[a]]);
+  for (int i = 0; i < 3; ++i) {
+    Xa[i] = X[o3 + i];
+    ua[i] = sp.u_n[o3 + i] + ga.af * (sp.u[o3 + i] - sp.u_n[o3 + i]);
+    va[i] = sp.v_n[o3 + i] + ga.af * (sp.v[o3 + i] - sp.v_n[o3 + i]);
+    dva[i] = sp.dv_n[o3 + i] + ga.am * (sp.dv[o3 + i] - sp.dv_n[o3 + i]);
+    rka[i] = COR ? sp.du_n[o3 + i] + ga.am * (sp.du[o3 + i] - sp.du_n[o3 + i]) - va[i] : 0.0;
   }
+  const double pa = sp.p_n[nda] + ga.af * (sp.p[nda] - sp.p_n[nda]);
+  const double dpa = sp.dp_n[nda] + ga.am * (sp.dp[nda] - sp.dp_n[nda]);
 
-  // reference geometry: gradients G_A are the rows of the inverse edge matrix
+  // reference geometry: G_A are the rows of the inverse edge matrix
+  double Xn[4][3];
+#pragma unroll
+  for (int b = 0; b < 4; ++b)
+#pragma unroll
+    for (int i = 0; i < 3; ++i) Xn[b][i] = qget(Xa[i], base + b);
   double e1[3], e2[3], e3[3];
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
-    e1[i] = Xe[1][i] - Xe[0][i];
-    e2[i] = Xe[2][i] - Xe[0][i];
-    e3[i] = Xe[3][i] - Xe[0][i];
+    e1[i] = Xn[1][i] - Xn[0][i];
+    e2[i] = Xn[2][i] - Xn[0][i];
+    e3[i] = Xn[3][i] - Xn[0][i];
   }
-  double G[4][3];
-  G[1][0] = e2[1] * e3[2] - e2[2] * e3[1];
-  G[1][1] = e2[2] * e3[0] - e2[0] * e3[2];
-  G[1][2] = e2[0] * e3[1] - e2[1] * e3[0];
-  G[2][0] = e3[1] * e1[2] - e3[2] * e1[1];
-  G[2][1] = e3[2] * e1[0] - e3[0] * e1[2];
-  G[2][2] = e3[0] * e1[1] - e3[1] * e1[0];
-  G[3][0] = e1[1] * e2[2] - e1[2] * e2[1];
-  G[3][1] = e1[2] * e2[0] - e1[0] * e2[2];
-  G[3][2] = e1[0] * e2[1] - e1[1] * e2[0];
-  const double det6 = dot3(e1, G[1]);
+  double G1[3], G2[3], G3[3];
+  G1[0] = e2[1] * e3[2] - e2[2] * e3[1];
+  G1[1] = e2[2] * e3[0] - e2[0] * e3[2];
+  G1[2] = e2[0] * e3[1] - e2[1] * e3[0];
+  G2[0] = e3[1] * e1[2] - e3[2] * e1[1];
+  G2[1] = e3[2] * e1[0] - e3[0] * e1[2];
+  G2[2] = e3[0] * e1[1] - e3[1] * e1[0];
+  G3[0] = e1[1] * e2[2] - e1[2] * e2[1];
+  G3[1] = e1[2] * e2[0] - e1[0] * e2[2];
+  G3[2] = e1[0] * e2[1] - e1[1] * e2[0];
+  const double det6 = dot3(e1, G1);
   const double V = det6 / 6.0;
+  double Ga[3];
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
-    G[1][i] /= det6;
-    G[2][i] /= det6;
-    G[3][i] /= det6;
-    G[0][i] = -(G[1][i] + G[2][i] + G[3][i]);
+    const double g1 = G1[i] / det6, g2 = G2[i] / det6, g3 = G3[i] / det6;
+    Ga[i] = (a == 0) ? -(g1 + g2 + g3) : (a == 1) ? g1 : (a == 2) ? g2 : g3;
   }
   double h2 = 0.0;
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int p0 = 0; p0 < 4; ++p0)
 #pragma unroll
-    for (int b = a + 1; b < 4; ++b) {
-      const double d0 = Xe[a][0] - Xe[b][0], d1 = Xe[a][1] - Xe[b][1], d2 = Xe[a][2] - Xe[b][2];
+    for (int p1 = p0 + 1; p1 < 4; ++p1) {
+      const double d0 = Xn[p0][0] - Xn[p1][0], d1 = Xn[p0][1] - Xn[p1][1], d2 = Xn[p0][2] - Xn[p1][2];
       h2 = fmax(h2, d0 * d0 + d1 * d1 + d2 * d2);
     }
   const double tau = mp.cm * sqrt(h2) / (mp.cwave * mp.rho0);
 
-  // deformation
+  // deformation gradient F = I + sum_A u_A (x) G_A
   double F[3][3];
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
-    for (int I = 0; I < 3; ++I) {
-      double s = (i == I) ? 1.0 : 0.0;
-#pragma unroll
-      for (int a = 0; a < 4; ++a) s += u[a][i] * G[a][I];
-      F[i][I] = s;
-    }
-  double cof[3][3];  // cofactor matrix: F^-1 = cof^T / J
+    for (int I = 0; I < 3; ++I) F[i][I] = (i == I ? 1.0 : 0.0) + qsum4(ua[i] * Ga[I]);
+  double cof[3][3];  // cofactors: F^-T = cof / J
   cof[0][0] = F[1][1] * F[2][2] - F[1][2] * F[2][1];
   cof[0][1] = F[1][2] * F[2][0] - F[1][0] * F[2][2];
   cof[0][2] = F[1][0] * F[2][1] - F[1][1] * F[2][0];
@@ -161,40 +172,29 @@ k_assemble(int ne, const int32_t *__restrict__ elems, const double *__restrict__
   cof[2][1] = F[0][2] * F[1][0] - F[0][0] * F[1][2];
   cof[2][2] = F[0][0] * F[1][1] - F[0][1] * F[1][0];
   const double J = F[0][0] * cof[0][0] + F[0][1] * cof[0][1] + F[0][2] * cof[0][2];
-  if (!(J > 0.0)) {
-    atomicOr(inverted, 1);
-    return;
-  }
-  double FiT[3][3];  // F^-T (i, I) = cof(i, I) / J
+  const bool ok = act && (J > 0.0);
+  if (act && !(J > 0.0) && a == 0) atomicOr(inverted, 1);
+  double FiT[3][3];
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
     for (int I = 0; I < 3; ++I) FiT[i][I] = cof[i][I] / J;
 
-  // spatial gradients g_A = F^-T G_A and nodal-field gradients
-  double g[4][3], FG[4][3];
-#pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-      g[a][i] = FiT[i][0] * G[a][0] + FiT[i][1] * G[a][1] + FiT[i][2] * G[a][2];
-      FG[a][i] = F[i][0] * G[a][0] + F[i][1] * G[a][1] + F[i][2] * G[a][2];
-    }
-  double L[3][3], gradp[3], divv = 0.0;
+  // spatial gradient g_a = F^-T G_a, F G_a, grad v, grad p
+  double ga_[3], FGa[3];
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
-    gradp[i] = 0.0;
-#pragma unroll
-    for (int j = 0; j < 3; ++j) {
-      double s = 0.0;
-#pragma unroll
-      for (int a = 0; a < 4; ++a) s += v[a][i] * g[a][j];
-      L[i][j] = s;
-    }
-#pragma unroll
-    for (int a = 0; a < 4; ++a) gradp[i] += p[a] * g[a][i];
-    divv += L[i][i];
+    ga_[i] = FiT[i][0] * Ga[0] + FiT[i][1] * Ga[1] + FiT[i][2] * Ga[2];
+    FGa[i] = F[i][0] * Ga[0] + F[i][1] * Ga[1] + F[i][2] * Ga[2];
   }
+  double L[3][3], gradp[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+#pragma unroll
+    for (int j = 0; j < 3; ++j) L[i][j] = qsum4(va[i] * ga_[j]);
+    gradp[i] = qsum4(pa * ga_[i]);
+  }
+  const double divv = L[0][0] + L[1][1] + L[2][2];
   double trC = 0.0;
 #pragma unroll
   for (int i = 0; i < 3; ++i)
@@ -203,17 +203,9 @@ k_assemble(int ne, const int32_t *__restrict__ elems, const double *__restrict__
   const double cJ = cbrt(J);
   const double Jm23 = 1.0 / (cJ * cJ);
 
-  // iso first Piola stress P~ = d(rho0 G_iso)/dF
-  double P[3][3];
-#pragma unroll
-  for (int i = 0; i < 3; ++i)
-#pragma unroll
-    for (int I = 0; I < 3; ++I) P[i][I] = mp.mu * Jm23 * (F[i][I] - trC / 3.0 * FiT[i][I]);
-
   // fibre families (HGO): H = kd I + (1 - 3 kd) a (x) a
-  double fa[2][3], Fa[2][3], HC[2], W1[2], W2[2];
-  const bool hgo = (mp.kind == VMS_HGO_INCOMP);
-  if (hgo) {
+  double fa[2][3] = {}, Fa[2][3] = {}, HC[2] = {}, W1[2] = {}, W2[2] = {};
+  if (HGO) {
 #pragma unroll
     for (int f = 0; f < 2; ++f) {
 #pragma unroll
@@ -225,98 +217,93 @@ k_assemble(int ne, const int32_t *__restrict__ elems, const double *__restrict__
       const double ee = exp(mp.k2 * E * E);
       W1[f] = mp.k1 * E * ee;
       W2[f] = mp.k1 * ee * (1.0 + 2.0 * mp.k2 * E * E);
-      // P += W1 Q, Q = Jm23 (2 F H - 2/3 HC F^-T)
-#pragma unroll
-      for (int i = 0; i < 3; ++i)
-#pragma unroll
-        for (int I = 0; I < 3; ++I) {
-          const double FH = mp.kd * F[i][I] + (1.0 - 3.0 * mp.kd) * Fa[f][i] * fa[f][I];
-          P[i][I] += W1[f] * Jm23 * (2.0 * FH - 2.0 / 3.0 * HC[f] * FiT[i][I]);
-        }
     }
   }
 
-  // quadrature-point fields
-  double pq[4], dpq[4], dvq[4][3], rho[4], beta[4], rhop[4], betap[4];
-  const double Sp = p[0] + p[1] + p[2] + p[3];
-  const double Sdp = dp[0] + dp[1] + dp[2] + dp[3];
-  double Sdv[3];
+  // quadrature point a: p, p-dot, v-dot and the constitutive scalars
+  const double Sp = qsum4(pa), Sdp = qsum4(dpa);
+  double dvq[3];
 #pragma unroll
-  for (int i = 0; i < 3; ++i) Sdv[i] = dv[0][i] + dv[1][i] + dv[2][i] + dv[3][i];
+  for (int i = 0; i < 3; ++i) dvq[i] = QB * qsum4(dva[i]) + QD * dva[i];
+  const double pq = QB * Sp + QD * pa, dpq = QB * Sdp + QD * dpa;
+  double rho, beta, rhop, betap;
+  rho_beta(mp, pq, rho, beta, rhop, betap);
+  double rv[3], Srv[3];
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    pq[q] = QB * Sp + QD * p[q];
-    dpq[q] = QB * Sdp + QD * dp[q];
-#pragma unroll
-    for (int i = 0; i < 3; ++i) dvq[q][i] = QB * Sdv[i] + QD * dv[q][i];
-    rho_beta(mp, pq[q], rho[q], beta[q], rhop[q], betap[q]);
+  for (int i = 0; i < 3; ++i) {
+    rv[i] = rho * dvq[i];
+    Srv[i] = qsum4(rv[i]);
   }
+  const double Sbp = qsum4(beta * dpq);
   const double w = V / 4.0;
   const double pbar = Sp / 4.0;
-
-  // per-node quadrature sums
-  double sA[4][3];   // sum_q w N_qA J rho_q v-dot_q
-  double PaA[4];     // sum_q w J N_qA (beta_q p-dot_q + div v)
-  double rvq[4][3];  // rho_q v-dot_q
-  double Srv[3] = {0, 0, 0};
+  double sA[3];  // sum_q w N_qa J rho_q v-dot_q
 #pragma unroll
-  for (int q = 0; q < 4; ++q)
+  for (int i = 0; i < 3; ++i) sA[i] = w * J * (QB * Srv[i] + QD * rv[i]);
+  const double PaA = w * J * (QB * Sbp + QD * beta * dpq + divv);
+  double Xbar[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) Xbar[i] = w * Srv[i] + V * gradp[i];
+
+  if (RES) {
+    double Pg[3];
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
-      rvq[q][i] = rho[q] * dvq[q][i];
-      Srv[i] += rvq[q][i];
+      double pgi = mp.mu * Jm23 * ((F[i][0] - trC / 3.0 * FiT[i][0]) * Ga[0] + (F[i][1] - trC / 3.0 * FiT[i][1]) * Ga[1] +
+                                   (F[i][2] - trC / 3.0 * FiT[i][2]) * Ga[2]);
+      if (HGO) {
+#pragma unroll
+        for (int f = 0; f < 2; ++f) {
+          const double aG = dot3(fa[f], Ga);
+          const double FHG = mp.kd * FGa[i] + (1.0 - 3.0 * mp.kd) * Fa[f][i] * aG;
+          pgi += W1[f] * Jm23 * (2.0 * FHG - 2.0 / 3.0 * HC[f] * ga_[i]);
+        }
+      }
+      Pg[i] = pgi;
     }
-  double Sbp = 0.0;
+    if (ok) {
+      const int64_t o = 4 * (int64_t)nda;
 #pragma unroll
-  for (int q = 0; q < 4; ++q) Sbp += beta[q] * dpq[q];
-#pragma unroll
-  for (int a = 0; a < 4; ++a) {
-#pragma unroll
-    for (int i = 0; i < 3; ++i) sA[a][i] = w * J * (QB * Srv[i] + QD * rvq[a][i]);
-    PaA[a] = w * J * (QB * Sbp + QD * beta[a] * dpq[a] + divv);
+      for (int i = 0; i < 3; ++i) R[o + i] += sA[i] + V * Pg[i] - V * J * pbar * ga_[i];
+      R[o + 3] += PaA + tau * J * dot3(ga_, Xbar);
+    }
   }
 
   if (SENS) {
-    // lam_e^T dR_e/dtheta for theta = (mu, kappa, k1, k2, fibre angle phi)
-    double Xb[3], Sdr[3];
-#pragma unroll
-    for (int i = 0; i < 3; ++i) Xb[i] = w * Srv[i] + V * gradp[i];
+    // lam_e^T dR_e/dtheta, theta = (mu, kappa, k1, k2, fibre angle); lane a adds node a's rows
+    const double *la = lam + 4 * (int64_t)nda;
     const bool comp = (mp.kind == VMS_NH_COMP);
     const double c2w = comp ? (mp.kappa + 4.0 * mp.mu / 3.0) : mp.mu;
-    for (int k = 0; k < 5; ++k) {
+    for (int kk = 0; kk < 5; ++kk) {
       double val = 0.0;
-      if (pmask & (1 << k)) {
-        double dP[3][3] = {}, dtau = 0.0, drho[4] = {0, 0, 0, 0}, dbeta[4] = {0, 0, 0, 0};
-        if (k == 0) {           // mu: neo-Hookean stress and tau_M through the wave speed
+      if (pmask & (1 << kk)) {
+        double dPg[3] = {0, 0, 0}, dtau = 0.0, drho = 0.0, dbeta = 0.0;   // at quadrature point a
+        if (kk == 0) {
 #pragma unroll
           for (int i = 0; i < 3; ++i)
-#pragma unroll
-            for (int I = 0; I < 3; ++I) dP[i][I] = Jm23 * (F[i][I] - trC / 3.0 * FiT[i][I]);
+            dPg[i] = Jm23 * ((F[i][0] - trC / 3.0 * FiT[i][0]) * Ga[0] + (F[i][1] - trC / 3.0 * FiT[i][1]) * Ga[1] +
+                             (F[i][2] - trC / 3.0 * FiT[i][2]) * Ga[2]);
           dtau = comp ? -tau * (2.0 / 3.0) / c2w : -0.5 * tau / mp.mu;
-        } else if (k == 1) {    // kappa: rho(p), beta(p) and tau_M
+        } else if (kk == 1) {
           if (comp) {
             dtau = -0.5 * tau / c2w;
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-              const double sq = sqrt(pq[q] * pq[q] + mp.kappa * mp.kappa);
-              drho[q] = mp.rho0 * (mp.kappa * mp.kappa / sq - sq - pq[q]) / (mp.kappa * mp.kappa);
-              dbeta[q] = -mp.kappa / (sq * sq * sq);
-            }
+            const double sq = sqrt(pq * pq + mp.kappa * mp.kappa);
+            drho = mp.rho0 * (mp.kappa * mp.kappa / sq - sq - pq) / (mp.kappa * mp.kappa);
+            dbeta = -mp.kappa / (sq * sq * sq);
           }
-        } else if (hgo) {       // fibre families
+        } else if (HGO) {
 #pragma unroll
           for (int f = 0; f < 2; ++f) {
             const double E = Jm23 * HC[f] - 1.0;
-            if (k == 2 || k == 3) {
-              const double sc = (k == 2) ? W1[f] / mp.k1 : W1[f] * E * E;
+            const double aG = dot3(fa[f], Ga);
+            if (kk == 2 || kk == 3) {
+              const double sc = (kk == 2) ? W1[f] / mp.k1 : W1[f] * E * E;
 #pragma unroll
-              for (int i = 0; i < 3; ++i)
-#pragma unroll
-                for (int I = 0; I < 3; ++I) {
-                  const double FH = mp.kd * F[i][I] + (1.0 - 3.0 * mp.kd) * Fa[f][i] * fa[f][I];
-                  dP[i][I] += sc * Jm23 * (2.0 * FH - 2.0 / 3.0 * HC[f] * FiT[i][I]);
-                }
-            } else {            // phi: a_f -> a_f + da_f dphi
+              for (int i = 0; i < 3; ++i) {
+                const double FHG = mp.kd * FGa[i] + (1.0 - 3.0 * mp.kd) * Fa[f][i] * aG;
+                dPg[i] += sc * Jm23 * (2.0 * FHG - 2.0 / 3.0 * HC[f] * ga_[i]);
+              }
+            } else {
               double da[3], Fda[3];
 #pragma unroll
               for (int I = 0; I < 3; ++I) da[I] = dfibre[6 * (int64_t)e + 3 * f + I];
@@ -324,200 +311,166 @@ k_assemble(int ne, const int32_t *__restrict__ elems, const double *__restrict__
               for (int i = 0; i < 3; ++i) Fda[i] = F[i][0] * da[0] + F[i][1] * da[1] + F[i][2] * da[2];
               const double dHC = (1.0 - 3.0 * mp.kd) * 2.0 * dot3(Fa[f], Fda);
               const double dW1 = W2[f] * Jm23 * dHC;
+              const double daG = dot3(da, Ga);
 #pragma unroll
-              for (int i = 0; i < 3; ++i)
-#pragma unroll
-                for (int I = 0; I < 3; ++I) {
-                  const double FH = mp.kd * F[i][I] + (1.0 - 3.0 * mp.kd) * Fa[f][i] * fa[f][I];
-                  const double FdH = (1.0 - 3.0 * mp.kd) * (Fda[i] * fa[f][I] + Fa[f][i] * da[I]);
-                  const double Q = Jm23 * (2.0 * FH - 2.0 / 3.0 * HC[f] * FiT[i][I]);
-                  const double dQ = Jm23 * (2.0 * FdH - 2.0 / 3.0 * dHC * FiT[i][I]);
-                  dP[i][I] += dW1 * Q + W1[f] * dQ;
-                }
+              for (int i = 0; i < 3; ++i) {
+                const double FHG = mp.kd * FGa[i] + (1.0 - 3.0 * mp.kd) * Fa[f][i] * aG;
+                const double FdHG = (1.0 - 3.0 * mp.kd) * (Fda[i] * aG + Fa[f][i] * daG);
+                const double QG = Jm23 * (2.0 * FHG - 2.0 / 3.0 * HC[f] * ga_[i]);
+                const double dQG = Jm23 * (2.0 * FdHG - 2.0 / 3.0 * dHC * ga_[i]);
+                dPg[i] += dW1 * QG + W1[f] * dQG;
+              }
             }
           }
         }
-        // assemble lam^T dR/dtheta over the element's nodes
-        double Sdrv[3] = {0, 0, 0};
+        // quadrature sums of the rho / beta derivatives
+        double dr[3];
 #pragma unroll
-        for (int q = 0; q < 4; ++q)
+        for (int i = 0; i < 3; ++i) dr[i] = drho * dvq[i];
+        double Sdr[3];
 #pragma unroll
-          for (int i = 0; i < 3; ++i) Sdrv[i] += drho[q] * dvq[q][i];
+        for (int i = 0; i < 3; ++i) Sdr[i] = qsum4(dr[i]);
+        const double Sdb = qsum4(dbeta * dpq);
+        double dRp = dtau * J * dot3(ga_, Xbar) + tau * J * w * dot3(ga_, Sdr) + w * J * (QB * Sdb + QD * dbeta * dpq);
+        val = la[3] * dRp;
 #pragma unroll
-        for (int a = 0; a < 4; ++a) {
-          const double *la = lam + 4 * (int64_t)nd[a];
-          double dRp = dtau * J * dot3(g[a], Xb) + tau * J * w * dot3(g[a], Sdrv);
-#pragma unroll
-          for (int q = 0; q < 4; ++q) dRp += w * J * (QB + (q == a ? QD : 0.0)) * dbeta[q] * dpq[q];
-          val += la[3] * dRp;
-#pragma unroll
-          for (int i = 0; i < 3; ++i) {
-            double dRm = V * (dP[i][0] * G[a][0] + dP[i][1] * G[a][1] + dP[i][2] * G[a][2]);
-#pragma unroll
-            for (int q = 0; q < 4; ++q) dRm += w * J * (QB + (q == a ? QD : 0.0)) * drho[q] * dvq[q][i];
-            val += la[i] * dRm;
-          }
-        }
+        for (int i = 0; i < 3; ++i) val += la[i] * (V * dPg[i] + w * J * (QB * Sdr[i] + QD * dr[i]));
       }
-      sens[5 * (int64_t)e + k] = val;
-    }
-    (void)Sdr;
-  }
-
-  if (RES) {
-#pragma unroll
-    for (int a = 0; a < 4; ++a) {
-      const int64_t o = 4 * (int64_t)nd[a];
-      double rp = PaA[a];
-      double st = 0.0;
-#pragma unroll
-      for (int i = 0; i < 3; ++i) st += g[a][i] * (w * Srv[i] + V * gradp[i]);
-      rp += tau * J * st;
-#pragma unroll
-      for (int i = 0; i < 3; ++i) {
-        const double pg = P[i][0] * G[a][0] + P[i][1] * G[a][1] + P[i][2] * G[a][2];
-        R[o + i] += sA[a][i] + V * pg - V * J * pbar * g[a][i];
-      }
-      R[o + 3] += rp;
+      val = qsum4(val);
+      if (ok && a == 0) sens[5 * (int64_t)e + kk] = val;
     }
   }
 
   if (TAN || COR || VJP) {
-    // per-quadrature-point weights for the sum_q c_q N_qA N_qB forms
-    double cR[4], cB[4], cBp[4];
-    double SR = 0, SB = 0, SBp = 0;
+    const double cRa = w * J * rho, cBa = w * J * beta, cBpa = w * J * betap * dpq;
+    const double SR = qsum4(cRa), SB = qsum4(cBa), SBp = qsum4(cBpa), Srho = qsum4(rho);
+    double rpd[3], Srpd[3];   // rho_p v-dot at quadrature point a, and its quadrature sum
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      cR[q] = w * J * rho[q];
-      cB[q] = w * J * beta[q];
-      cBp[q] = w * J * betap[q] * dpq[q];
-      SR += cR[q];
-      SB += cB[q];
-      SBp += cBp[q];
+    for (int i = 0; i < 3; ++i) {
+      rpd[i] = rhop * dvq[i];
+      Srpd[i] = qsum4(rpd[i]);
     }
-    double Xbar[3];
+    const double gXa = dot3(ga_, Xbar);
+    double Lga[3];  // (grad v)^T g_a
 #pragma unroll
-    for (int i = 0; i < 3; ++i) Xbar[i] = w * Srv[i] + V * gradp[i];
-    double gX[4], cpu[4][3] = {}, cpp[4] = {};
+    for (int j = 0; j < 3; ++j) Lga[j] = L[0][j] * ga_[0] + L[1][j] * ga_[1] + L[2][j] * ga_[2];
+    const double *la = VJP ? lam + 4 * (int64_t)nda : nullptr;
+    double cu[3] = {0, 0, 0}, cp = 0.0;
+#pragma unroll 1
+    for (int b = 0; b < 4; ++b) {
+      const int src = base + b;
+      double Gb[3], gb[3], FGb[3], Lgb[3], rpdb[3], rkb[3];
 #pragma unroll
-    for (int a = 0; a < 4; ++a) gX[a] = dot3(g[a], Xbar);
-
+      for (int i = 0; i < 3; ++i) {
+        Gb[i] = qget(Ga[i], src);
+        gb[i] = qget(ga_[i], src);
+        FGb[i] = qget(FGa[i], src);
+        Lgb[i] = qget(Lga[i], src);
+        rpdb[i] = qget(rpd[i], src);
+        rkb[i] = COR ? qget(rka[i], src) : 0.0;
+      }
+      const double gXb = qget(gXa, src), cRb = qget(cRa, src), cBb = qget(cBa, src), cBpb = qget(cBpa, src);
+      const double rhob = qget(rho, src);
+      const bool same = (a == b);
+      const double ab = dot3(Ga, Gb);
+      const double gg = dot3(ga_, gb);
+      // d(R_m)_a / du_b
+      double Ku[3][3];
 #pragma unroll
-    for (int a = 0; a < 4; ++a) {
-      double cu[3] = {0, 0, 0}, cp = 0.0;
+      for (int i = 0; i < 3; ++i)
 #pragma unroll
-      for (int b = 0; b < 4; ++b) {
-        // d(R_m)_A / du_B  (3x3, i row, j column)
-        const double ab = dot3(G[a], G[b]);
-        const double gg = dot3(g[a], g[b]);
-        double Ku[3][3];
+        for (int j = 0; j < 3; ++j) {
+          const double m = (i == j ? ab : 0.0) - 2.0 / 3.0 * FGa[i] * gb[j] - 2.0 / 3.0 * ga_[i] * FGb[j] +
+                           2.0 / 9.0 * trC * ga_[i] * gb[j] + trC / 3.0 * ga_[j] * gb[i];
+          Ku[i][j] = V * mp.mu * Jm23 * m + V * J * pbar * (ga_[j] * gb[i] - ga_[i] * gb[j]) + sA[i] * gb[j];
+        }
+      if (HGO) {
 #pragma unroll
-        for (int i = 0; i < 3; ++i)
+        for (int f = 0; f < 2; ++f) {
+          const double aGa = dot3(fa[f], Ga), aGb = dot3(fa[f], Gb);
+          const double GHG = mp.kd * ab + (1.0 - 3.0 * mp.kd) * aGa * aGb;
+          double FHa[3], FHb[3], Qa[3], Qb[3];
 #pragma unroll
-          for (int j = 0; j < 3; ++j) {
-            double m = (i == j ? ab : 0.0) - 2.0 / 3.0 * FG[a][i] * g[b][j] -
-                       2.0 / 3.0 * g[a][i] * FG[b][j] + 2.0 / 9.0 * trC * g[a][i] * g[b][j] +
-                       trC / 3.0 * g[a][j] * g[b][i];
-            Ku[i][j] = V * mp.mu * Jm23 * m + V * J * pbar * (g[a][j] * g[b][i] - g[a][i] * g[b][j]) +
-                       sA[a][i] * g[b][j];
+          for (int i = 0; i < 3; ++i) {
+            FHa[i] = mp.kd * FGa[i] + (1.0 - 3.0 * mp.kd) * Fa[f][i] * aGa;
+            FHb[i] = mp.kd * FGb[i] + (1.0 - 3.0 * mp.kd) * Fa[f][i] * aGb;
+            Qa[i] = Jm23 * (2.0 * FHa[i] - 2.0 / 3.0 * HC[f] * ga_[i]);
+            Qb[i] = Jm23 * (2.0 * FHb[i] - 2.0 / 3.0 * HC[f] * gb[i]);
           }
-        if (hgo) {
-#pragma unroll
-          for (int f = 0; f < 2; ++f) {
-            const double aGa = dot3(fa[f], G[a]), aGb = dot3(fa[f], G[b]);
-            const double GHG = mp.kd * ab + (1.0 - 3.0 * mp.kd) * aGa * aGb;
-            double FHa[3], FHb[3], Qa[3], Qb[3];
-#pragma unroll
-            for (int i = 0; i < 3; ++i) {
-              FHa[i] = mp.kd * FG[a][i] + (1.0 - 3.0 * mp.kd) * Fa[f][i] * aGa;
-              FHb[i] = mp.kd * FG[b][i] + (1.0 - 3.0 * mp.kd) * Fa[f][i] * aGb;
-              Qa[i] = Jm23 * (2.0 * FHa[i] - 2.0 / 3.0 * HC[f] * g[a][i]);
-              Qb[i] = Jm23 * (2.0 * FHb[i] - 2.0 / 3.0 * HC[f] * g[b][i]);
-            }
-#pragma unroll
-            for (int i = 0; i < 3; ++i)
-#pragma unroll
-              for (int j = 0; j < 3; ++j) {
-                const double d2E = -2.0 / 3.0 * Jm23 * g[b][j] * (2.0 * FHa[i] - 2.0 / 3.0 * HC[f] * g[a][i]) +
-                                   Jm23 * ((i == j ? 2.0 * GHG : 0.0) - 4.0 / 3.0 * g[a][i] * FHb[j] +
-                                           2.0 / 3.0 * HC[f] * g[a][j] * g[b][i]);
-                Ku[i][j] += V * (W2[f] * Qa[i] * Qb[j] + W1[f] * d2E);
-              }
-          }
-        }
-        // d(R_p)_A / du_B (1x3)
-        double Lg[3];
-#pragma unroll
-        for (int j = 0; j < 3; ++j) Lg[j] = L[0][j] * g[b][0] + L[1][j] * g[b][1] + L[2][j] * g[b][2];
-        double Kpu[3];
-#pragma unroll
-        for (int j = 0; j < 3; ++j)
-          Kpu[j] = g[b][j] * PaA[a] - J * w * Lg[j] +
-                   tau * J * (g[b][j] * gX[a] - g[a][j] * gX[b] - V * gg * gradp[j]);
-
-        // remaining partial derivatives of (R_m, R_p)_A with respect to node B's staged fields
-        double rpv[3] = {0, 0, 0};  // sum_q w J rho_p,q v-dot_q N_qA N_qB
-        double rN = 0.0;             // sum_q w rho_q N_qB
-        double st = 0.0;             // sum_q w rho_p,q N_qB (g_A . v-dot_q)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const double na = QB + (q == a ? QD : 0.0), nb = QB + (q == b ? QD : 0.0);
-#pragma unroll
-          for (int i = 0; i < 3; ++i) rpv[i] += w * J * rhop[q] * dvq[q][i] * na * nb;
-          rN += w * rho[q] * nb;
-          st += w * rhop[q] * nb * dot3(g[a], dvq[q]);
-        }
-        const double mR = qsum2(cR, SR, a, b);           // dR_m/dv-dot = mR I
-        double dRm_dp[3], dRp_dvd[3], dRp_dv[3];
-#pragma unroll
-        for (int i = 0; i < 3; ++i) {
-          dRm_dp[i] = rpv[i] - J * g[a][i] * w;
-          dRp_dvd[i] = tau * J * g[a][i] * rN;
-          dRp_dv[i] = J * g[b][i] * w;
-        }
-        const double dRp_dp = qsum2(cBp, SBp, a, b) + tau * J * (V * gg + st);
-        const double dRp_dpd = qsum2(cB, SB, a, b);
-        if (TAN) {
-          const int64_t blk = elem_blk[16 * (int64_t)e + 4 * a + b];
 #pragma unroll
           for (int i = 0; i < 3; ++i)
 #pragma unroll
-            for (int j = 0; j < 3; ++j)
-              KA[(3 * i + j) * nnzb + blk] += (i == j ? ga.am * mR : 0.0) + ga.c3 * Ku[i][j];
-#pragma unroll
-          for (int i = 0; i < 3; ++i) KB[i * nnzb + blk] += ga.c2 * dRm_dp[i];
-#pragma unroll
-          for (int j = 0; j < 3; ++j) KC[j * nnzb + blk] += ga.am * dRp_dvd[j] + ga.c2 * dRp_dv[j] + ga.c3 * Kpu[j];
-          KD[blk] += ga.am * dRp_dpd + ga.c2 * dRp_dp;
+            for (int j = 0; j < 3; ++j) {
+              const double d2E = -2.0 / 3.0 * Jm23 * gb[j] * (2.0 * FHa[i] - 2.0 / 3.0 * HC[f] * ga_[i]) +
+                                 Jm23 * ((i == j ? 2.0 * GHG : 0.0) - 4.0 / 3.0 * ga_[i] * FHb[j] +
+                                         2.0 / 3.0 * HC[f] * ga_[j] * gb[i]);
+              Ku[i][j] += V * (W2[f] * Qa[i] * Qb[j] + W1[f] * d2E);
+            }
         }
-        if (VJP) {
-          // cotangents of node B's staged fields: lam_A^T dR_A / d(field_B)
-          const double *la = lam + 4 * (int64_t)nd[a];
-          double *ob = vjp + 11 * (int64_t)nd[b];
+      }
+      // d(R_p)_a / du_b
+      double Kpu[3];
 #pragma unroll
-          for (int j = 0; j < 3; ++j) {
-            ob[j] += la[0] * Ku[0][j] + la[1] * Ku[1][j] + la[2] * Ku[2][j] + la[3] * Kpu[j];
-            ob[4 + j] += la[3] * dRp_dv[j];
-            ob[7 + j] += la[j] * mR + la[3] * dRp_dvd[j];
-          }
-          ob[3] += la[0] * dRm_dp[0] + la[1] * dRm_dp[1] + la[2] * dRm_dp[2] + la[3] * dRp_dp;
-          ob[10] += la[3] * dRp_dpd;
-        }
-        if (COR) {
+      for (int j = 0; j < 3; ++j)
+        Kpu[j] = gb[j] * PaA - J * w * Lgb[j] + tau * J * (gb[j] * gXa - ga_[j] * gXb - V * gg * gradp[j]);
+      // remaining partial derivatives with respect to node b's staged fields
+      const double mR = qsum2(cRa, cRb, SR, same);
+      const double rN = w * (QB * Srho + QD * rhob);
+      const double st = w * (QB * dot3(ga_, Srpd) + QD * dot3(ga_, rpdb));
+      double dRm_dp[3], dRp_dvd[3], dRp_dv[3];
 #pragma unroll
-          for (int i = 0; i < 3; ++i) cu[i] += Ku[i][0] * rk[b][0] + Ku[i][1] * rk[b][1] + Ku[i][2] * rk[b][2];
-          cp += Kpu[0] * rk[b][0] + Kpu[1] * rk[b][1] + Kpu[2] * rk[b][2];
-        }
+      for (int i = 0; i < 3; ++i) {
+        const double rpv = w * J * (QB * QB * Srpd[i] + QB * QD * (rpd[i] + rpdb[i]) + (same ? QD * QD * rpd[i] : 0.0));
+        dRm_dp[i] = rpv - J * ga_[i] * w;
+        dRp_dvd[i] = tau * J * ga_[i] * rN;
+        dRp_dv[i] = J * gb[i] * w;
+      }
+      const double dRp_dp = qsum2(cBpa, cBpb, SBp, same) + tau * J * (V * gg + st);
+      const double dRp_dpd = qsum2(cBa, cBb, SB, same);
+      if (TAN && ok) {
+        const int64_t blk = elem_blk[16 * (int64_t)e + 4 * a + b];
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+          for (int j = 0; j < 3; ++j)
+            KA[(3 * i + j) * nnzb + blk] += (i == j ? ga.am * mR : 0.0) + ga.c3 * Ku[i][j];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) KB[i * nnzb + blk] += ga.c2 * dRm_dp[i];
+#pragma unroll
+        for (int j = 0; j < 3; ++j) KC[j * nnzb + blk] += ga.am * dRp_dvd[j] + ga.c2 * dRp_dv[j] + ga.c3 * Kpu[j];
+        KD[blk] += ga.am * dRp_dpd + ga.c2 * dRp_dp;
       }
       if (COR) {
-        const double s = ga.c2 / ga.am;
-        const int64_t o = 4 * (int64_t)nd[a];
 #pragma unroll
-        for (int i = 0; i < 3; ++i) cpu[a][i] = s * cu[i];
-        cpp[a] = s * cp;
-        for (int i = 0; i < 3; ++i) corr[o + i] += cpu[a][i];
-        corr[o + 3] += cpp[a];
+        for (int i = 0; i < 3; ++i) cu[i] += Ku[i][0] * rkb[0] + Ku[i][1] * rkb[1] + Ku[i][2] * rkb[2];
+        cp += Kpu[0] * rkb[0] + Kpu[1] * rkb[1] + Kpu[2] * rkb[2];
       }
+      if (VJP) {
+        // lam_a^T dR_a/d(field_b), summed over the element's rows a, written by lane b
+        double c[11];
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+          c[j] = la[0] * Ku[0][j] + la[1] * Ku[1][j] + la[2] * Ku[2][j] + la[3] * Kpu[j];
+          c[4 + j] = la[3] * dRp_dv[j];
+          c[7 + j] = la[j] * mR + la[3] * dRp_dvd[j];
+        }
+        c[3] = la[0] * dRm_dp[0] + la[1] * dRm_dp[1] + la[2] * dRm_dp[2] + la[3] * dRp_dp;
+        c[10] = la[3] * dRp_dpd;
+        const int ndb = tets[4 * (int64_t)e + b];
+        const bool okb = act && (J > 0.0);
+#pragma unroll
+        for (int q = 0; q < 11; ++q) {
+          const double t = qsum4(c[q]);
+          if (okb && same) vjp[11 * (int64_t)ndb + q] += t;
+        }
+      }
+    }
+    if (COR && ok) {
+      const double s = ga.c2 / ga.am;
+      const int64_t o = 4 * (int64_t)nda;
+#pragma unroll
+      for (int i = 0; i < 3; ++i) corr[o + i] += s * cu[i];
+      corr[o + 3] += s * cp;
     }
   }
 }
@@ -758,6 +711,7 @@ int vms_launch_assemble(vms_ctx *ctx, const vms_mesh *mesh, const vms_material *
     hipLaunchKernelGGL(k_fill, dim3(grid1(3 * nnzb)), dim3(VMS_BLOCK), 0, ctx->stream, 3 * nnzb, K->C, 0.0);
     hipLaunchKernelGGL(k_fill, dim3(grid1(nnzb)), dim3(VMS_BLOCK), 0, ctx->stream, nnzb, K->D, 0.0);
   }
+  const bool hgo = (mat->kind == VMS_HGO_INCOMP);
   const bool vj = flags & VMS_ASM_VJP;
   if ((flags & VMS_ASM_SENS) && (!lam || !sens || ((pmask & 16) && !dfibre)))
     return vms_set_error(ctx, VMS_ERR_ARG, "sensitivity needs lam, an output array (and dfibre for phi)");
@@ -773,14 +727,15 @@ int vms_launch_assemble(vms_ctx *ctx, const vms_mesh *mesh, const vms_material *
     const int c0 = mesh->colour_ptr[c], ne = mesh->colour_ptr[c + 1] - c0;
     if (ne <= 0) continue;
     const int32_t *el = mesh->elem_by_colour + c0;
-    dim3 gr((ne + 127) / 128), bl(128);
+    dim3 gr((4 * ne + 255) / 256), bl(256);
 #define VMS_ASM_CASE(FLV)                                                                                 \
-  case FLV:                                                                                               \
-    hipLaunchKernelGGL(k_assemble<FLV>, gr, bl, 0, ctx->stream, ne, el, mesh->X, mesh->tets, mesh->fibre, \
+  case FLV: {                                                                                             \
+    auto kern = hgo ? (k_assemble<FLV, true>) : (k_assemble<FLV, false>);                                 \
+    hipLaunchKernelGGL(kern, gr, bl, 0, ctx->stream, ne, el, mesh->X, mesh->tets, mesh->fibre,            \
                        mp, ga, sp, nnzb, mesh->elem_blk, K ? K->A : nullptr, K ? K->B : nullptr,           \
                        K ? K->C : nullptr, K ? K->D : nullptr, R, corr, lam, vjp, dfibre, pmask, sens,    \
                        &ctx->dstat->inverted);                                                             \
-    break;
+  } break;
     switch (flags & 31u) {
       VMS_ASM_CASE(1)
       VMS_ASM_CASE(2)
