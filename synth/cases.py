@@ -55,9 +55,10 @@ def cube_case(N: int, nu: float | None = None, kappa: float = 1.0e6, seed: int =
     return mesh, mat, TimeInt(dt=dt, rho_inf=0.5, n_steps=n_steps)
 
 
-def tube_case(nr: int = 2, nt: int = 16, nz: int = 8, dt: float = 0.05, n_steps: int = 20):
+def tube_case(nr: int = 2, nt: int = 16, nz: int = 8, dt: float = 0.05, n_steps: int = 20,
+              stretch: float = 1.5):
     """Fully incompressible HGO tube under axial stretch."""
-    mesh = tube_mesh(nr, nt, nz, t_end=dt * n_steps)
+    mesh = tube_mesh(nr, nt, nz, t_end=dt * n_steps, stretch=stretch)
     mat = Material(kind=HGO_INCOMP, rho0=1000.0, mu=3.0e4, kappa=np.inf,
                    k1=2.36e5, k2=0.84, kd=0.0)
     return mesh, mat, TimeInt(dt=dt, rho_inf=0.5, n_steps=n_steps)
