@@ -27,7 +27,8 @@
  *  - Block values are stored entry-major over the shared node-graph pattern:
  *    A[9][nnzb] (row-major 3x3 entry e = 3*r + c), B[3][nnzb], C[3][nnzb],
  *    D[nnzb]; block b of row i couples node i to node col[b].
- *  - Indices are int32 (nnzb < 2^31).
+ *  - Indices are int32 (nnzb < 2^31, n_tets <= VMS_MAX_TETS so that the
+ *    16 element-local pairs of every element are numbered in int32).
  *  - A context is not thread-safe; use one per stream.
  */
 #ifndef VMS_H
@@ -35,6 +36,8 @@
 
 #include <stddef.h>
 #include <stdint.h>
+
+#define VMS_MAX_TETS 134217727   /* 2^27 - 1: 16 * n_tets fits in int32 */
 
 #ifdef __cplusplus
 extern "C" {
@@ -87,7 +90,7 @@ typedef struct {
 } vms_timeint;
 
 typedef struct {
-  int32_t n_nodes, n_tets, n_bfaces, n_colours;
+  int32_t n_nodes, n_tets, n_bfaces;
   int64_t nnzb;
   const double *X;          /* [n][3] reference coordinates */
   const int32_t *tets;      /* [m][4] positively oriented */
@@ -100,11 +103,10 @@ typedef struct {
   const int32_t *col;       /* [nnzb] */
   const int32_t *tpos;      /* [nnzb] position of the transposed block */
   const int32_t *diag_pos;  /* [n] */
-  const int32_t *elem_blk;  /* [m][16] block of (tets[e][a], tets[e][b]) at a*4+b */
-  const int32_t *elem_by_colour; /* [m] elements grouped by colour */
+  const int32_t *blk_src_ptr; /* [nnzb+1] contributions of each block ... */
+  const int32_t *blk_src;   /* [16m] ... as e*16 + a*4 + b, increasing e within a block */
   const int32_t *nf_ptr;    /* [n+1] node -> loaded faces */
   const int32_t *nf_face;   /* [3f] */
-  const int32_t *colour_ptr;/* HOST [n_colours+1] */
 } vms_mesh;
 
 typedef struct {
@@ -171,22 +173,21 @@ const char *vms_last_error(const vms_ctx *ctx);
 
 /* ---- setup (host, integer work) ---------------------------------------- */
 
-/* Sizes of the node-graph block pattern of the P1 tangent (every pair of
- * nodes sharing a tetrahedron couples, section 3.1) and an upper bound on the
- * element colours.  tets: HOST [m][4].  VMS_ERR_ARG on an out-of-range node. */
-int vms_setup_sizes(int32_t n_nodes, int32_t n_tets, const int32_t *tets,
-                    int64_t *nnzb, int32_t *n_colours_bound);
+/* Size of the node-graph block pattern of the P1 tangent (every pair of
+ * nodes sharing a tetrahedron couples, section 3.1).  tets: HOST [m][4].
+ * VMS_ERR_ARG on an out-of-range node or n_tets > VMS_MAX_TETS. */
+int vms_setup_sizes(int32_t n_nodes, int32_t n_tets, const int32_t *tets, int64_t *nnzb);
 
-/* Build, into HOST arrays sized by vms_setup_sizes: row_ptr[n+1], col[nnzb],
- * tpos[nnzb], diag_pos[n], elem_blk[m][16], colour_ptr[bound+1],
- * elem_by_colour[m], the actual colour count, and node -> loaded-face lists
- * nf_ptr[n+1], nf_face[3f] (bfaces: HOST [f][3]).  Greedy element colouring in
- * element order: elements of one colour share no node. */
+/* Build, into HOST arrays sized by vms_setup_sizes: row_ptr[n+1], col[nnzb]
+ * (sorted within a row, diagonal included), tpos[nnzb] (position of the
+ * transposed block), diag_pos[n], the block contribution lists
+ * blk_src_ptr[nnzb+1], blk_src[16m] (every element-local pair e*16 + a*4 + b
+ * under the block (tets[e][a], tets[e][b]), in increasing e), and node ->
+ * loaded-face lists nf_ptr[n+1], nf_face[3f] (bfaces: HOST [f][3]). */
 int vms_setup_build(int32_t n_nodes, int32_t n_tets, const int32_t *tets,
                     int32_t n_bfaces, const int32_t *bfaces,
                     int32_t *row_ptr, int32_t *col, int32_t *tpos, int32_t *diag_pos,
-                    int32_t *elem_blk, int32_t *colour_ptr, int32_t *elem_by_colour,
-                    int32_t *n_colours, int32_t *nf_ptr, int32_t *nf_face);
+                    int32_t *blk_src_ptr, int32_t *blk_src, int32_t *nf_ptr, int32_t *nf_face);
 
 /* ---- assembly (section 3.3 steps 1-4; consistent-linearization appendix) - */
 
@@ -200,21 +201,30 @@ int vms_nodal_load(vms_ctx *ctx, const vms_mesh *mesh, double *f_ext);
  * u = dir_vel * t_{n+1}, v = u-dot = dir_vel, v-dot = 0.  [async] */
 int vms_predictor(vms_ctx *ctx, const vms_mesh *mesh, const vms_timeint *ti, vms_state *st);
 
+/* Workspace bytes of vms_assemble for these flags: the element matrices and
+ * vectors (2 KB per element for the tangent, 128 B each for the residual and
+ * the R-bar_k term). */
+size_t vms_assemble_workspace(const vms_mesh *mesh, unsigned flags);
+
 /* Element-by-element assembly at the generalized-alpha stages
  * y-dot_{n+alpha_m}, y_{n+alpha_f} computed from (y_n, y-dot_n) and the
- * iterate (section 3.3 step 1).
+ * iterate (section 3.3 step 1).  Every element writes its matrices to the
+ * workspace; each block (and each nodal entry) then sums its contributions
+ * in element order, so the result is bitwise reproducible.
  *   VMS_ASM_RESIDUAL: R[n][4] = (R_m, R_p) of the appendix (P1, 4-point
  *     rule, tau_M frozen per element) plus load_scale * f_ext;
  *   VMS_ASM_TANGENT: K->A, B, C, D of the block reduction (eqs. defining A,
  *     B, C, D), exact linearisation of R;
  *   VMS_ASM_RKCORR: corr[n][4] = (alpha_f gamma dt / alpha_m) dR/du . R-bar_k,
  *     the K_{.,u-dot} R-bar_k / alpha_m term of the stage-1 right-hand side.
- * Outputs are overwritten.  f_ext may be NULL (no load).  Returns
- * VMS_ERR_INVERTED_ELEMENT (checked at the end of the call, [sync] then) if
- * some element has J <= 0; otherwise [async]. */
+ * Outputs are overwritten.  f_ext may be NULL (no load).  workspace: at
+ * least vms_assemble_workspace(mesh, flags) bytes (VMS_ERR_WORKSPACE
+ * otherwise).  [sync]: returns VMS_ERR_INVERTED_ELEMENT if some element has
+ * J <= 0 (the outputs are then undefined). */
 int vms_assemble(vms_ctx *ctx, const vms_mesh *mesh, const vms_material *mat,
                  const vms_timeint *ti, const vms_state *st, const double *f_ext,
-                 vms_matrix *K, double *R, double *corr, unsigned flags);
+                 vms_matrix *K, double *R, double *corr, unsigned flags,
+                 void *workspace, size_t workspace_bytes);
 
 /* *norm_host = || {R-bar_k, R_p, R_m} ||_2 over non-Dirichlet dofs (section
  * 3.3 step 3), R-bar_k = u-dot_{n+alpha_m} - v_{n+alpha_f}.  [sync]
@@ -261,7 +271,8 @@ int vms_solve_scaled(vms_ctx *ctx, const vms_mesh *mesh, const vms_matrix *K,
 int vms_newton_update(vms_ctx *ctx, const vms_mesh *mesh, const vms_timeint *ti,
                       vms_state *st, const double *W, const double *x_scaled);
 
-/* Workspace bytes of vms_step: vms_solve_workspace + its residual vectors. */
+/* Workspace bytes of vms_step: the larger of vms_solve_workspace and the
+ * assembly's element buffers (they are used in turn), plus its vectors. */
 size_t vms_step_workspace(const vms_mesh *mesh, const vms_solver_opts *opts);
 
 /* One generalized-alpha time step by the predictor multi-corrector algorithm

@@ -20,13 +20,12 @@ class TimeInt(C.Structure):
 
 
 class Mesh(C.Structure):
-    _fields_ = [("n_nodes", C.c_int32), ("n_tets", C.c_int32), ("n_bfaces", C.c_int32),
-                ("n_colours", C.c_int32), ("nnzb", C.c_int64),
+    _fields_ = [("n_nodes", C.c_int32), ("n_tets", C.c_int32), ("n_bfaces", C.c_int32), ("nnzb", C.c_int64),
                 ("X", C.c_void_p), ("tets", C.c_void_p), ("bfaces", C.c_void_p), ("traction", C.c_void_p),
                 ("dir_mask", C.c_void_p), ("dir_vel", C.c_void_p), ("fibre", C.c_void_p),
                 ("row_ptr", C.c_void_p), ("col", C.c_void_p), ("tpos", C.c_void_p), ("diag_pos", C.c_void_p),
-                ("elem_blk", C.c_void_p), ("elem_by_colour", C.c_void_p), ("nf_ptr", C.c_void_p),
-                ("nf_face", C.c_void_p), ("colour_ptr", C.c_void_p)]
+                ("blk_src_ptr", C.c_void_p), ("blk_src", C.c_void_p), ("nf_ptr", C.c_void_p),
+                ("nf_face", C.c_void_p)]
 
 
 class State(C.Structure):
@@ -80,13 +79,13 @@ SIGNATURES = {
     "vms_ctx_create": (C.c_int, [P(C.c_void_p), C.c_int, C.c_void_p]),
     "vms_ctx_destroy": (None, [C.c_void_p]),
     "vms_last_error": (C.c_char_p, [C.c_void_p]),
-    "vms_setup_sizes": (C.c_int, [C.c_int32, C.c_int32, C.c_void_p, P(C.c_int64), P(C.c_int32)]),
-    "vms_setup_build": (C.c_int, [C.c_int32, C.c_int32, C.c_void_p, C.c_int32, C.c_void_p] + [C.c_void_p] * 7 +
-                        [P(C.c_int32), C.c_void_p, C.c_void_p]),
+    "vms_setup_sizes": (C.c_int, [C.c_int32, C.c_int32, C.c_void_p, P(C.c_int64)]),
+    "vms_setup_build": (C.c_int, [C.c_int32, C.c_int32, C.c_void_p, C.c_int32, C.c_void_p] + [C.c_void_p] * 8),
     "vms_nodal_load": (C.c_int, [C.c_void_p, P(Mesh), C.c_void_p]),
     "vms_predictor": (C.c_int, [C.c_void_p, P(Mesh), P(TimeInt), P(State)]),
+    "vms_assemble_workspace": (C.c_size_t, [P(Mesh), C.c_uint]),
     "vms_assemble": (C.c_int, [C.c_void_p, P(Mesh), P(Material), P(TimeInt), P(State), C.c_void_p, P(Matrix),
-                               C.c_void_p, C.c_void_p, C.c_uint]),
+                               C.c_void_p, C.c_void_p, C.c_uint, C.c_void_p, C.c_size_t]),
     "vms_residual_norm": (C.c_int, [C.c_void_p, P(Mesh), P(TimeInt), P(State), C.c_void_p, P(C.c_double)]),
     "vms_prepare_system": (C.c_int, [C.c_void_p, P(Mesh), P(Matrix), C.c_void_p, C.c_void_p, C.c_void_p,
                                      C.c_double, C.c_int]),

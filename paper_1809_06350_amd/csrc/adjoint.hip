@@ -182,8 +182,8 @@ extern "C" int vms_param_sensitivity(vms_ctx *ctx, const vms_mesh *mesh, const v
   double *dout = b.take<double>(8);
   const vms_ga ga = vms_genalpha(ti);
   if ((rc = vms_launch_clear_inverted(ctx))) return rc;
-  if ((rc = vms_launch_assemble(ctx, mesh, mat, ga, st, nullptr, nullptr, nullptr, nullptr, VMS_ASM_SENS, lam,
-                                nullptr, dfibre, pmask, sens)))
+  if ((rc = vms_launch_assemble(ctx, mesh, mat, ga, st, nullptr, nullptr, nullptr, nullptr, VMS_ASM_SENS, nullptr, 0,
+                                lam, nullptr, dfibre, pmask, sens)))
     return rc;
   return sens_sum(ctx, mesh->n_tets, sens, part, dout, out);
 }
@@ -197,7 +197,12 @@ extern "C" size_t vms_adjoint_workspace(const vms_mesh *mesh, const vms_solver_o
   b.take<double>(4 * n);   // lam
   b.take<double>(3 * n);   // mu_u
   b.take<double>(11 * n);  // vjp
-  return b.off + sens_bytes(mesh) + vms_solve_workspace(mesh, opts) + 1024;
+  // the solver's bases and the assembly's element buffers share one region (used in turn)
+  const size_t asm_b = vms_asm_scratch_bytes(mesh, VMS_ASM_TANGENT) > vms_asm_scratch_bytes(mesh, VMS_ASM_VJP)
+                           ? vms_asm_scratch_bytes(mesh, VMS_ASM_TANGENT)
+                           : vms_asm_scratch_bytes(mesh, VMS_ASM_VJP);
+  const size_t sol_b = vms_solve_workspace(mesh, opts);
+  return b.off + sens_bytes(mesh) + (sol_b > asm_b ? sol_b : asm_b) + 1024;
 }
 
 extern "C" int vms_adjoint_step(vms_ctx *ctx, const vms_mesh *mesh, const vms_material *mat, const vms_timeint *ti,
@@ -230,7 +235,9 @@ extern "C" int vms_adjoint_step(vms_ctx *ctx, const vms_mesh *mesh, const vms_ma
   const bool m32 = opts->precision == VMS_MIXED;
   // tangent at the converged state, Dirichlet rows, scaling
   if ((rc = vms_launch_clear_inverted(ctx))) return rc;
-  if ((rc = vms_launch_assemble(ctx, mesh, mat, ga, st, nullptr, K, nullptr, nullptr, VMS_ASM_TANGENT))) return rc;
+  if ((rc = vms_launch_assemble(ctx, mesh, mat, ga, st, nullptr, K, nullptr, nullptr, VMS_ASM_TANGENT, sws,
+                                sws_bytes)))
+    return rc;
   if ((rc = vms_launch_prepare(ctx, mesh, K, nullptr, nullptr, nullptr, eps_diag, 0))) return rc;
   hipLaunchKernelGGL(k_adj_seed, dim3(grid1(n)), dim3(VMS_BLOCK), 0, s, n, ga, mesh->dir_mask, (const double *)K->W,
                      ybar1, ydbar1, rhs, mu_u);
@@ -244,14 +251,15 @@ extern "C" int vms_adjoint_step(vms_ctx *ctx, const vms_mesh *mesh, const vms_ma
   hipLaunchKernelGGL(k_unscale, dim3(grid1(4 * (int64_t)n)), dim3(VMS_BLOCK), 0, s, 4 * (int64_t)n,
                      (const double *)K->W, (const double *)lams, lam);
   // staged-field cotangents, then y-bar_n, y-dot-bar_n
-  if ((rc = vms_launch_assemble(ctx, mesh, mat, ga, st, nullptr, nullptr, nullptr, nullptr, VMS_ASM_VJP, lam, vjp)))
+  if ((rc = vms_launch_assemble(ctx, mesh, mat, ga, st, nullptr, nullptr, nullptr, nullptr, VMS_ASM_VJP, sws,
+                                sws_bytes, lam, vjp)))
     return rc;
   hipLaunchKernelGGL(k_adj_back, dim3(grid1(n)), dim3(VMS_BLOCK), 0, s, n, ga, mesh->dir_mask, (const double *)mu_u,
                      (const double *)vjp, ybar1, ybar0, ydbar0);
   VMS_LAUNCH_CHECK(ctx);
   if (pmask) {
-    if ((rc = vms_launch_assemble(ctx, mesh, mat, ga, st, nullptr, nullptr, nullptr, nullptr, VMS_ASM_SENS, lam,
-                                  nullptr, dfibre, pmask, sens)))
+    if ((rc = vms_launch_assemble(ctx, mesh, mat, ga, st, nullptr, nullptr, nullptr, nullptr, VMS_ASM_SENS, nullptr,
+                                  0, lam, nullptr, dfibre, pmask, sens)))
       return rc;
     double g[5];
     if ((rc = sens_sum(ctx, mesh->n_tets, sens, part, dout, g))) return rc;

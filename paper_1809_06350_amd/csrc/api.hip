@@ -78,9 +78,14 @@ extern "C" int vms_predictor(vms_ctx *ctx, const vms_mesh *mesh, const vms_timei
   return vms_launch_predictor(ctx, mesh, ga, ti->t_n + ti->dt, st);
 }
 
+extern "C" size_t vms_assemble_workspace(const vms_mesh *mesh, unsigned flags) {
+  if (!mesh || mesh->n_tets < 0) return 0;
+  return vms_asm_scratch_bytes(mesh, flags & 7u);
+}
+
 extern "C" int vms_assemble(vms_ctx *ctx, const vms_mesh *mesh, const vms_material *mat, const vms_timeint *ti,
                             const vms_state *st, const double *f_ext, vms_matrix *K, double *R, double *corr,
-                            unsigned flags) {
+                            unsigned flags, void *workspace, size_t workspace_bytes) {
   if (!ctx) return VMS_ERR_ARG;
   int rc = vms_check_mesh(ctx, mesh);
   if (rc) return rc;
@@ -90,9 +95,10 @@ extern "C" int vms_assemble(vms_ctx *ctx, const vms_mesh *mesh, const vms_materi
   if ((flags & VMS_ASM_RKCORR) && !corr) return vms_set_error(ctx, VMS_ERR_ARG, "corr missing");
   if ((flags & VMS_ASM_TANGENT) && (!K || !K->A || !K->B || !K->C || !K->D))
     return vms_set_error(ctx, VMS_ERR_ARG, "K arrays missing");
+  if ((flags & 7u) == 0 || (flags & ~7u)) return vms_set_error(ctx, VMS_ERR_ARG, "bad assembly flags");
   const vms_ga ga = vms_genalpha(ti);
   if ((rc = vms_launch_clear_inverted(ctx))) return rc;
-  rc = vms_launch_assemble(ctx, mesh, mat, ga, st, f_ext, K, R, corr, flags);
+  rc = vms_launch_assemble(ctx, mesh, mat, ga, st, f_ext, K, R, corr, flags, workspace, workspace_bytes);
   if (rc) return rc;
   VMS_HIP(ctx, hipMemcpyAsync(ctx->h_i, &ctx->dstat->inverted, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
   VMS_HIP(ctx, hipStreamSynchronize(ctx->stream));

@@ -16,9 +16,17 @@
 // tau_M = c_m h_e / (c rho0) is frozen per element: h_e = longest reference
 // edge, c the bulk (compressible) or shear (incompressible) wave speed.
 //
-// One thread per element; elements of one colour share no node, so the
-// read-modify-write scatter into the block arrays is free of conflicts and the
-// summation order is fixed by the colour order (bitwise reproducible).
+// Four lanes per element, all elements in one launch.  Each element writes its
+// 16 node-pair blocks (16 values each) and its nodal rows to element buffers
+// in HBM with plain stores; a gather then sums, for every block (node), the
+// contributions listed by setup in element order.  No atomics, no colouring,
+// and the sums are bitwise reproducible.
+//
+// Element buffer layouts (doubles, e = element, a/b = local node):
+//   KE[e][4a+b][16] = (A 3x3 row-major, B 3, C 3, D) of block (a, b)
+//   RE[e][a][4]     = (R_m, R_p) rows of node a
+//   CE[e][a][4]     = R-bar_k correction rows of node a
+//   VE[e][a][12]    = cotangents of node a's staged fields (11 used)
 #include <cmath>
 
 #include "vms_internal.h"
@@ -82,11 +90,10 @@ __device__ __forceinline__ double qsum2(double ca, double cb, double S, bool sam
 // lane b by shuffle, so no lane holds the whole element.
 template <int FL, bool HGO>
 __global__ void __launch_bounds__(256)
-k_assemble(int ne, const int32_t *__restrict__ elems, const double *__restrict__ X,
-           const int32_t *__restrict__ tets, const double *__restrict__ fibre, MatP mp, vms_ga ga,
-           StateP sp, int64_t nnzb, const int32_t *__restrict__ elem_blk, double *KA, double *KB,
-           double *KC, double *KD, double *R, double *corr, const double *__restrict__ lam, double *vjp,
-           const double *__restrict__ dfibre, int pmask, double *sens, int *inverted) {
+k_assemble(int ne, const double *__restrict__ X, const int32_t *__restrict__ tets,
+           const double *__restrict__ fibre, MatP mp, vms_ga ga, StateP sp, double *__restrict__ KE,
+           double *__restrict__ RE, double *__restrict__ CE, const double *__restrict__ lam,
+           double *__restrict__ VE, const double *__restrict__ dfibre, int pmask, double *sens, int *inverted) {
   constexpr bool RES = FL & VMS_ASM_RESIDUAL;
   constexpr bool TAN = FL & VMS_ASM_TANGENT;
   constexpr bool COR = FL & VMS_ASM_RKCORR;
@@ -97,7 +104,7 @@ k_assemble(int ne, const int32_t *__restrict__ elems, const double *__restrict__
   const int a = gt & 3;
   const int base = (threadIdx.x & 63) & ~3;
   const bool act = k < ne;
-  const int e = elems[act ? k : ne - 1];
+  const int e = act ? k : ne - 1;
   const int nda = tets[4 * (int64_t)e + a];
 
   // staged values of node a: rates at n+alpha_m, values at n+alpha_f
@@ -261,11 +268,14 @@ k_assemble(int ne, const int32_t *__restrict__ elems, const double *__restrict__
       }
       Pg[i] = pgi;
     }
-    if (ok) {
-      const int64_t o = 4 * (int64_t)nda;
-#pragma unroll
-      for (int i = 0; i < 3; ++i) R[o + i] += sA[i] + V * Pg[i] - V * J * pbar * ga_[i];
-      R[o + 3] += PaA + tau * J * dot3(ga_, Xbar);
+    if (act) {
+      double2 *o = reinterpret_cast<double2 *>(RE + 4 * (4 * (int64_t)e + a));
+      const double r0 = sA[0] + V * Pg[0] - V * J * pbar * ga_[0];
+      const double r1 = sA[1] + V * Pg[1] - V * J * pbar * ga_[1];
+      const double r2 = sA[2] + V * Pg[2] - V * J * pbar * ga_[2];
+      const double r3 = PaA + tau * J * dot3(ga_, Xbar);
+      o[0] = ok ? make_double2(r0, r1) : make_double2(0.0, 0.0);
+      o[1] = ok ? make_double2(r2, r3) : make_double2(0.0, 0.0);
     }
   }
 
@@ -427,18 +437,20 @@ k_assemble(int ne, const int32_t *__restrict__ elems, const double *__restrict__
       }
       const double dRp_dp = qsum2(cBpa, cBpb, SBp, same) + tau * J * (V * gg + st);
       const double dRp_dpd = qsum2(cBa, cBb, SB, same);
-      if (TAN && ok) {
-        const int64_t blk = elem_blk[16 * (int64_t)e + 4 * a + b];
+      if (TAN && act) {
+        double kv[16];
 #pragma unroll
         for (int i = 0; i < 3; ++i)
 #pragma unroll
-          for (int j = 0; j < 3; ++j)
-            KA[(3 * i + j) * nnzb + blk] += (i == j ? ga.am * mR : 0.0) + ga.c3 * Ku[i][j];
+          for (int j = 0; j < 3; ++j) kv[3 * i + j] = (i == j ? ga.am * mR : 0.0) + ga.c3 * Ku[i][j];
 #pragma unroll
-        for (int i = 0; i < 3; ++i) KB[i * nnzb + blk] += ga.c2 * dRm_dp[i];
+        for (int i = 0; i < 3; ++i) kv[9 + i] = ga.c2 * dRm_dp[i];
 #pragma unroll
-        for (int j = 0; j < 3; ++j) KC[j * nnzb + blk] += ga.am * dRp_dvd[j] + ga.c2 * dRp_dv[j] + ga.c3 * Kpu[j];
-        KD[blk] += ga.am * dRp_dpd + ga.c2 * dRp_dp;
+        for (int j = 0; j < 3; ++j) kv[12 + j] = ga.am * dRp_dvd[j] + ga.c2 * dRp_dv[j] + ga.c3 * Kpu[j];
+        kv[15] = ga.am * dRp_dpd + ga.c2 * dRp_dp;
+        double2 *o = reinterpret_cast<double2 *>(KE + 16 * (16 * (int64_t)e + 4 * a + b));
+#pragma unroll
+        for (int q = 0; q < 8; ++q) o[q] = ok ? make_double2(kv[2 * q], kv[2 * q + 1]) : make_double2(0.0, 0.0);
       }
       if (COR) {
 #pragma unroll
@@ -456,45 +468,74 @@ k_assemble(int ne, const int32_t *__restrict__ elems, const double *__restrict__
         }
         c[3] = la[0] * dRm_dp[0] + la[1] * dRm_dp[1] + la[2] * dRm_dp[2] + la[3] * dRp_dp;
         c[10] = la[3] * dRp_dpd;
-        const int ndb = tets[4 * (int64_t)e + b];
-        const bool okb = act && (J > 0.0);
+        double *o = VE + 12 * (4 * (int64_t)e + b);
 #pragma unroll
         for (int q = 0; q < 11; ++q) {
           const double t = qsum4(c[q]);
-          if (okb && same) vjp[11 * (int64_t)ndb + q] += t;
+          if (act && same) o[q] = ok ? t : 0.0;
         }
       }
     }
-    if (COR && ok) {
-      const double s = ga.c2 / ga.am;
-      const int64_t o = 4 * (int64_t)nda;
-#pragma unroll
-      for (int i = 0; i < 3; ++i) corr[o + i] += s * cu[i];
-      corr[o + 3] += s * cp;
+    if (COR && act) {
+      const double s = ok ? ga.c2 / ga.am : 0.0;
+      double2 *o = reinterpret_cast<double2 *>(CE + 4 * (4 * (int64_t)e + a));
+      o[0] = make_double2(s * cu[0], s * cu[1]);
+      o[1] = make_double2(s * cu[2], s * cp);
     }
   }
 }
 
-// R = load * f_ext (momentum rows), 0 (mass rows); corr = 0
-__global__ void k_init_residual(int n, const double *f_ext, double load, double *R, double *corr) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const int64_t o = 4 * (int64_t)i;
-  if (R) {
-    for (int c = 0; c < 3; ++c) R[o + c] = f_ext ? load * f_ext[3 * (int64_t)i + c] : 0.0;
-    R[o + 3] = 0.0;
+// K blocks from the element buffer: 16 lanes per block (one per value), the
+// contributions summed in the order setup listed them (increasing element).
+__global__ void __launch_bounds__(VMS_BLOCK)
+k_gather_blocks(int64_t nnzb, const int32_t *__restrict__ ptr, const int32_t *__restrict__ src,
+                const double *__restrict__ KE, double *__restrict__ KA, double *__restrict__ KB,
+                double *__restrict__ KC, double *__restrict__ KD) {
+  const int64_t gt = (int64_t)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+  const int64_t b = gt >> 4;
+  const int v = (int)(gt & 15);
+  if (b >= nnzb) return;
+  const int k0 = ptr[b], k1 = ptr[b + 1];
+  double s = 0.0;
+  int k = k0;
+  for (; k + 4 <= k1; k += 4) {   // four loads in flight, sums in list order
+    const int64_t s0 = src[k], s1 = src[k + 1], s2 = src[k + 2], s3 = src[k + 3];
+    const double x0 = KE[16 * s0 + v], x1 = KE[16 * s1 + v], x2 = KE[16 * s2 + v], x3 = KE[16 * s3 + v];
+    s = (((s + x0) + x1) + x2) + x3;
   }
-  if (corr)
-    for (int c = 0; c < 4; ++c) corr[o + c] = 0.0;
+  for (; k < k1; ++k) s += KE[16 * (int64_t)src[k] + v];
+  if (v < 9)
+    KA[v * nnzb + b] = s;
+  else if (v < 12)
+    KB[(v - 9) * nnzb + b] = s;
+  else if (v < 15)
+    KC[(v - 12) * nnzb + b] = s;
+  else
+    KD[b] = s;
+}
+
+// Nodal rows from an element buffer E[e][a][ws]: out[i][c] (c < w) = init +
+// sum over the (element, local node) incidences of node i, which are the
+// contributions of its diagonal block (pairs a*4 + a).  init = load * f_ext
+// on the momentum rows when f_ext is given, else 0.
+__global__ void __launch_bounds__(VMS_BLOCK)
+k_gather_nodes(int n, int w, const int32_t *__restrict__ diag_pos, const int32_t *__restrict__ ptr,
+               const int32_t *__restrict__ src, const double *__restrict__ E, int ws, double *__restrict__ out,
+               const double *__restrict__ f_ext, double load) {
+  const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gt >= (int64_t)n * w) return;
+  const int i = (int)(gt / w), c = (int)(gt % w);
+  const int blk = diag_pos[i];
+  double s = (f_ext && c < 3) ? load * f_ext[3 * (int64_t)i + c] : 0.0;
+  for (int k = ptr[blk]; k < ptr[blk + 1]; ++k) {
+    const int q = src[k];
+    s += E[(4 * (int64_t)(q >> 4) + ((q & 15) >> 2)) * ws + c];
+  }
+  out[gt] = s;
 }
 
 __global__ void k_clear_flag(int *p) {
   if (threadIdx.x == 0) *p = 0;
-}
-
-__global__ void k_fill(int64_t n, double *x, double v) {
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i < n) x[i] = v;
 }
 
 __global__ void k_nodal_load(int n, const int32_t *nf_ptr, const int32_t *nf_face, const int32_t *bfaces,
@@ -683,20 +724,27 @@ vms_ga vms_genalpha(const vms_timeint *ti) {
 }
 
 int vms_check_mesh(vms_ctx *ctx, const vms_mesh *m) {
-  if (!m || m->n_nodes <= 0 || m->n_tets < 0 || m->nnzb <= 0 || !m->X || !m->tets || !m->dir_mask ||
-      !m->row_ptr || !m->col || !m->tpos || !m->diag_pos || !m->elem_blk || !m->elem_by_colour ||
-      !m->colour_ptr || m->n_colours <= 0)
+  if (!m || m->n_nodes <= 0 || m->n_tets < 0 || m->n_tets > VMS_MAX_TETS || m->nnzb <= 0 || !m->X || !m->tets ||
+      !m->dir_mask || !m->row_ptr || !m->col || !m->tpos || !m->diag_pos || !m->blk_src_ptr ||
+      (m->n_tets > 0 && !m->blk_src))
     return vms_set_error(ctx, VMS_ERR_ARG, "incomplete mesh description");
-  if (m->colour_ptr[m->n_colours] != m->n_tets)
-    return vms_set_error(ctx, VMS_ERR_ARG, "colour_ptr does not cover every element");
   return VMS_OK;
+}
+
+size_t vms_asm_scratch_bytes(const vms_mesh *mesh, unsigned flags) {
+  size_t per = 0;   // doubles per element
+  if (flags & VMS_ASM_TANGENT) per += 256;
+  if (flags & VMS_ASM_RESIDUAL) per += 16;
+  if (flags & VMS_ASM_RKCORR) per += 16;
+  if (flags & VMS_ASM_VJP) per += 48;
+  return per * sizeof(double) * (size_t)(mesh->n_tets > 0 ? mesh->n_tets : 0) + 4 * 256;
 }
 
 int vms_launch_assemble(vms_ctx *ctx, const vms_mesh *mesh, const vms_material *mat, const vms_ga &ga,
                         const vms_state *st, const double *f_ext, vms_matrix *K, double *R, double *corr,
-                        unsigned flags, const double *lam, double *vjp, const double *dfibre, int pmask,
-                        double *sens) {
-  const int n = mesh->n_nodes;
+                        unsigned flags, void *scratch, size_t scratch_bytes, const double *lam, double *vjp,
+                        const double *dfibre, int pmask, double *sens) {
+  const int n = mesh->n_nodes, m = mesh->n_tets;
   const int64_t nnzb = mesh->nnzb;
   MatP mp{mat->kind, mat->rho0, mat->mu, mat->kappa, mat->k1, mat->k2, mat->kd, mat->c_m, 0.0};
   mp.cwave = (mat->kind == VMS_NH_COMP) ? sqrt((mat->kappa + 4.0 * mat->mu / 3.0) / mat->rho0)
@@ -705,36 +753,32 @@ int vms_launch_assemble(vms_ctx *ctx, const vms_mesh *mesh, const vms_material *
     return vms_set_error(ctx, VMS_ERR_ARG, "HGO material needs fibre directions");
   const StateP sp = mk_state(st);
   const bool res = flags & VMS_ASM_RESIDUAL, tan = flags & VMS_ASM_TANGENT, cor = flags & VMS_ASM_RKCORR;
-  if (tan) {
-    hipLaunchKernelGGL(k_fill, dim3(grid1(9 * nnzb)), dim3(VMS_BLOCK), 0, ctx->stream, 9 * nnzb, K->A, 0.0);
-    hipLaunchKernelGGL(k_fill, dim3(grid1(3 * nnzb)), dim3(VMS_BLOCK), 0, ctx->stream, 3 * nnzb, K->B, 0.0);
-    hipLaunchKernelGGL(k_fill, dim3(grid1(3 * nnzb)), dim3(VMS_BLOCK), 0, ctx->stream, 3 * nnzb, K->C, 0.0);
-    hipLaunchKernelGGL(k_fill, dim3(grid1(nnzb)), dim3(VMS_BLOCK), 0, ctx->stream, nnzb, K->D, 0.0);
-  }
-  const bool hgo = (mat->kind == VMS_HGO_INCOMP);
-  const bool vj = flags & VMS_ASM_VJP;
-  if ((flags & VMS_ASM_SENS) && (!lam || !sens || ((pmask & 16) && !dfibre)))
+  const bool vj = flags & VMS_ASM_VJP, sn = flags & VMS_ASM_SENS;
+  if (sn && (!lam || !sens || ((pmask & 16) && !dfibre)))
     return vms_set_error(ctx, VMS_ERR_ARG, "sensitivity needs lam, an output array (and dfibre for phi)");
-  if (vj) {
-    if (!lam || !vjp) return vms_set_error(ctx, VMS_ERR_ARG, "VJP needs lam and an output array");
-    hipLaunchKernelGGL(k_fill, dim3(grid1(11 * (int64_t)n)), dim3(VMS_BLOCK), 0, ctx->stream, 11 * (int64_t)n, vjp, 0.0);
-  }
-  if (res || cor)
-    hipLaunchKernelGGL(k_init_residual, dim3(grid1(n)), dim3(VMS_BLOCK), 0, ctx->stream, n, f_ext, ga.load,
-                       res ? R : nullptr, cor ? corr : nullptr);
-  VMS_LAUNCH_CHECK(ctx);
-  for (int c = 0; c < mesh->n_colours; ++c) {
-    const int c0 = mesh->colour_ptr[c], ne = mesh->colour_ptr[c + 1] - c0;
-    if (ne <= 0) continue;
-    const int32_t *el = mesh->elem_by_colour + c0;
-    dim3 gr((4 * ne + 255) / 256), bl(256);
+  if (vj && (!lam || !vjp)) return vms_set_error(ctx, VMS_ERR_ARG, "VJP needs lam and an output array");
+  if ((res || tan || cor || vj) && (!scratch || scratch_bytes < vms_asm_scratch_bytes(mesh, flags)))
+    return vms_set_error(ctx, VMS_ERR_WORKSPACE, "assembly workspace too small: %zu < %zu", scratch_bytes,
+                         vms_asm_scratch_bytes(mesh, flags));
+  // element buffers, 256-byte aligned
+  char *p = (char *)(((uintptr_t)scratch + 255) & ~(uintptr_t)255);
+  auto take = [&](size_t per) {
+    double *r = (double *)p;
+    p += ((per * sizeof(double) * (size_t)m + 255) / 256) * 256;
+    return r;
+  };
+  double *KE = tan ? take(256) : nullptr;
+  double *RE = res ? take(16) : nullptr;
+  double *CE = cor ? take(16) : nullptr;
+  double *VE = vj ? take(48) : nullptr;
+  const bool hgo = (mat->kind == VMS_HGO_INCOMP);
+  if (m > 0) {
+    dim3 gr((unsigned)((4 * (int64_t)m + 255) / 256)), bl(256);
 #define VMS_ASM_CASE(FLV)                                                                                 \
   case FLV: {                                                                                             \
     auto kern = hgo ? (k_assemble<FLV, true>) : (k_assemble<FLV, false>);                                 \
-    hipLaunchKernelGGL(kern, gr, bl, 0, ctx->stream, ne, el, mesh->X, mesh->tets, mesh->fibre,            \
-                       mp, ga, sp, nnzb, mesh->elem_blk, K ? K->A : nullptr, K ? K->B : nullptr,           \
-                       K ? K->C : nullptr, K ? K->D : nullptr, R, corr, lam, vjp, dfibre, pmask, sens,    \
-                       &ctx->dstat->inverted);                                                             \
+    hipLaunchKernelGGL(kern, gr, bl, 0, ctx->stream, m, mesh->X, mesh->tets, mesh->fibre, mp, ga, sp, KE, \
+                       RE, CE, lam, VE, dfibre, pmask, sens, &ctx->dstat->inverted);                      \
   } break;
     switch (flags & 31u) {
       VMS_ASM_CASE(1)
@@ -746,10 +790,25 @@ int vms_launch_assemble(vms_ctx *ctx, const vms_mesh *mesh, const vms_material *
       VMS_ASM_CASE(7)
       VMS_ASM_CASE(8)
       VMS_ASM_CASE(16)
-      default: return vms_set_error(ctx, VMS_ERR_ARG, "no assembly flag set");
+      default: return vms_set_error(ctx, VMS_ERR_ARG, "unsupported assembly flags");
     }
 #undef VMS_ASM_CASE
+    VMS_LAUNCH_CHECK(ctx);
   }
+  if (tan)
+    hipLaunchKernelGGL(k_gather_blocks, dim3(grid1(16 * nnzb)), dim3(VMS_BLOCK), 0, ctx->stream, nnzb,
+                       mesh->blk_src_ptr, mesh->blk_src, (const double *)KE, K->A, K->B, K->C, K->D);
+  if (res)
+    hipLaunchKernelGGL(k_gather_nodes, dim3(grid1(4 * (int64_t)n)), dim3(VMS_BLOCK), 0, ctx->stream, n, 4,
+                       mesh->diag_pos, mesh->blk_src_ptr, mesh->blk_src, (const double *)RE, 4, R, f_ext, ga.load);
+  if (cor)
+    hipLaunchKernelGGL(k_gather_nodes, dim3(grid1(4 * (int64_t)n)), dim3(VMS_BLOCK), 0, ctx->stream, n, 4,
+                       mesh->diag_pos, mesh->blk_src_ptr, mesh->blk_src, (const double *)CE, 4, corr,
+                       (const double *)nullptr, 0.0);
+  if (vj)
+    hipLaunchKernelGGL(k_gather_nodes, dim3(grid1(11 * (int64_t)n)), dim3(VMS_BLOCK), 0, ctx->stream, n, 11,
+                       mesh->diag_pos, mesh->blk_src_ptr, mesh->blk_src, (const double *)VE, 12, vjp,
+                       (const double *)nullptr, 0.0);
   VMS_LAUNCH_CHECK(ctx);
   return VMS_OK;
 }

@@ -6,9 +6,14 @@
 // Besides the pattern this file builds
 //   tpos[b]        position of block (j, i) for the block b = (i, j),
 //   diag_pos[i]    position of block (i, i),
-//   elem_blk[e][A*4+B]  position of block (tets[e][A], tets[e][B]),
-//   a greedy element colouring (elements of one colour share no node, so an
-//   element-by-element scatter within a colour is free of write conflicts),
+//   blk_src_ptr / blk_src: for every block, the element-local pairs that add
+//                  into it, as e*16 + A*4 + B (element e, rows of node
+//                  tets[e][A], columns of node tets[e][B]), in increasing
+//                  element order; the gather that sums element matrices into
+//                  the blocks follows this order, so the assembled values do not
+//                  depend on scheduling.  The contributions of a diagonal
+//                  block are exactly the (element, local node) incidences of
+//                  its node, which also serves the nodal gathers,
 //   node -> loaded boundary face lists (for the dead-load vector).
 #include <algorithm>
 #include <cstdint>
@@ -62,29 +67,22 @@ inline int32_t find_block(const Graph &g, int32_t i, int32_t j) {
 
 }  // namespace
 
-extern "C" int vms_setup_sizes(int32_t n_nodes, int32_t n_tets, const int32_t *tets,
-                               int64_t *nnzb, int32_t *n_colours) {
-  if (n_nodes <= 0 || n_tets < 0 || (!tets && n_tets > 0) || !nnzb || !n_colours) return VMS_ERR_ARG;
+extern "C" int vms_setup_sizes(int32_t n_nodes, int32_t n_tets, const int32_t *tets, int64_t *nnzb) {
+  if (n_nodes <= 0 || n_tets < 0 || (!tets && n_tets > 0) || !nnzb) return VMS_ERR_ARG;
+  if ((int64_t)n_tets > VMS_MAX_TETS) return VMS_ERR_ARG;
   for (int64_t k = 0; k < 4 * (int64_t)n_tets; ++k)
     if (tets[k] < 0 || tets[k] >= n_nodes) return VMS_ERR_ARG;
   Graph g = build_graph(n_nodes, n_tets, tets);
   *nnzb = (int64_t)g.col.size();
-  // colouring bound: greedy needs at most (max elements around an element) + 1
-  std::vector<int32_t> cnt(n_nodes, 0);
-  for (int64_t k = 0; k < 4 * (int64_t)n_tets; ++k) cnt[tets[k]]++;
-  int32_t mx = 0;
-  for (int32_t i = 0; i < n_nodes; ++i) mx = std::max(mx, cnt[i]);
-  *n_colours = std::min<int32_t>(4 * mx + 1, std::max<int32_t>(n_tets, 1));
   return VMS_OK;
 }
 
 extern "C" int vms_setup_build(int32_t n_nodes, int32_t n_tets, const int32_t *tets,
                                int32_t n_bfaces, const int32_t *bfaces,
                                int32_t *row_ptr, int32_t *col, int32_t *tpos, int32_t *diag_pos,
-                               int32_t *elem_blk, int32_t *colour_ptr, int32_t *elem_by_colour,
-                               int32_t *n_colours_out, int32_t *nf_ptr, int32_t *nf_face) {
-  if (n_nodes <= 0 || n_tets < 0 || !row_ptr || !col || !tpos || !diag_pos || !elem_blk ||
-      !colour_ptr || !elem_by_colour || !n_colours_out || !nf_ptr || (n_bfaces > 0 && (!bfaces || !nf_face)))
+                               int32_t *blk_src_ptr, int32_t *blk_src, int32_t *nf_ptr, int32_t *nf_face) {
+  if (n_nodes <= 0 || n_tets < 0 || (int64_t)n_tets > VMS_MAX_TETS || !row_ptr || !col || !tpos || !diag_pos ||
+      !blk_src_ptr || (n_tets > 0 && (!tets || !blk_src)) || !nf_ptr || (n_bfaces > 0 && (!bfaces || !nf_face)))
     return VMS_ERR_ARG;
   for (int64_t k = 0; k < 4 * (int64_t)n_tets; ++k)
     if (tets[k] < 0 || tets[k] >= n_nodes) return VMS_ERR_ARG;
@@ -98,42 +96,16 @@ extern "C" int vms_setup_build(int32_t n_nodes, int32_t n_tets, const int32_t *t
     diag_pos[i] = find_block(g, i, i);
     for (int32_t b = g.row_ptr[i]; b < g.row_ptr[i + 1]; ++b) tpos[b] = find_block(g, g.col[b], i);
   }
+  // block <- (element, local pair): counting sort of the 16 m pairs by block, element order kept
+  std::vector<int32_t> eb(16 * (size_t)n_tets);
   for (int64_t e = 0; e < n_tets; ++e)
     for (int a = 0; a < 4; ++a)
-      for (int b = 0; b < 4; ++b)
-        elem_blk[16 * e + 4 * a + b] = find_block(g, tets[4 * e + a], tets[4 * e + b]);
-
-  // greedy colouring in element order
-  std::vector<int32_t> n2e_ptr(n_nodes + 1, 0);
-  for (int64_t k = 0; k < 4 * (int64_t)n_tets; ++k) n2e_ptr[tets[k] + 1]++;
-  for (int32_t i = 0; i < n_nodes; ++i) n2e_ptr[i + 1] += n2e_ptr[i];
-  std::vector<int32_t> n2e(4 * (int64_t)n_tets), fillp(n2e_ptr.begin(), n2e_ptr.end() - 1);
-  for (int64_t e = 0; e < n_tets; ++e)
-    for (int a = 0; a < 4; ++a) n2e[fillp[tets[4 * e + a]]++] = (int32_t)e;
-  std::vector<int32_t> colour(n_tets, -1), mark;
-  int32_t ncol = 0;
-  for (int64_t e = 0; e < n_tets; ++e) {
-    for (int a = 0; a < 4; ++a) {
-      int32_t i = tets[4 * e + a];
-      for (int32_t k = n2e_ptr[i]; k < n2e_ptr[i + 1]; ++k) {
-        int32_t c = colour[n2e[k]];
-        if (c >= 0) {
-          if ((int32_t)mark.size() <= c) mark.resize(c + 1, -1);
-          mark[c] = (int32_t)e;
-        }
-      }
-    }
-    int32_t c = 0;
-    while (c < (int32_t)mark.size() && mark[c] == (int32_t)e) ++c;
-    colour[e] = c;
-    ncol = std::max(ncol, c + 1);
-  }
-  std::fill(colour_ptr, colour_ptr + ncol + 1, 0);
-  for (int64_t e = 0; e < n_tets; ++e) colour_ptr[colour[e] + 1]++;
-  for (int32_t c = 0; c < ncol; ++c) colour_ptr[c + 1] += colour_ptr[c];
-  std::vector<int32_t> cf(colour_ptr, colour_ptr + ncol);
-  for (int64_t e = 0; e < n_tets; ++e) elem_by_colour[cf[colour[e]]++] = (int32_t)e;
-  *n_colours_out = ncol;
+      for (int b = 0; b < 4; ++b) eb[16 * e + 4 * a + b] = find_block(g, tets[4 * e + a], tets[4 * e + b]);
+  std::fill(blk_src_ptr, blk_src_ptr + nnzb + 1, 0);
+  for (size_t k = 0; k < eb.size(); ++k) blk_src_ptr[eb[k] + 1]++;
+  for (int64_t b = 0; b < nnzb; ++b) blk_src_ptr[b + 1] += blk_src_ptr[b];
+  std::vector<int32_t> fill(blk_src_ptr, blk_src_ptr + nnzb);
+  for (size_t k = 0; k < eb.size(); ++k) blk_src[fill[eb[k]]++] = (int32_t)k;
 
   // node -> loaded faces
   std::fill(nf_ptr, nf_ptr + n_nodes + 1, 0);

@@ -1050,7 +1050,10 @@ extern "C" int vms_spmv(vms_ctx *ctx, const vms_mesh *mesh, const vms_matrix *K,
 // ---- time step ---------------------------------------------------------------
 extern "C" size_t vms_step_workspace(const vms_mesh *mesh, const vms_solver_opts *opts) {
   if (!mesh || !opts || mesh->n_nodes <= 0) return 0;
-  return workspace_bytes(mesh, opts) + 4 * (size_t)(4 * mesh->n_nodes) * sizeof(double) + 4 * 256;
+  // the solver's bases and the assembly's element buffers share one region (used in turn)
+  const size_t asm_b = vms_asm_scratch_bytes(mesh, VMS_ASM_TANGENT | VMS_ASM_RKCORR);
+  const size_t sol_b = workspace_bytes(mesh, opts);
+  return (sol_b > asm_b ? sol_b : asm_b) + 4 * (size_t)(4 * mesh->n_nodes) * sizeof(double) + 4 * 256;
 }
 
 extern "C" int vms_step(vms_ctx *ctx, const vms_mesh *mesh, const vms_material *mat, const vms_timeint *ti,
@@ -1085,7 +1088,9 @@ extern "C" int vms_step(vms_ctx *ctx, const vms_mesh *mesh, const vms_material *
   stats->status = VMS_NOT_CONVERGED;
   for (int l = 1; l <= no->l_max; ++l) {
     auto ta = std::chrono::steady_clock::now();
-    if ((rc = vms_launch_assemble(ctx, mesh, mat, ga, st, f_ext, nullptr, R, nullptr, VMS_ASM_RESIDUAL))) return rc;
+    if ((rc = vms_launch_assemble(ctx, mesh, mat, ga, st, f_ext, nullptr, R, nullptr, VMS_ASM_RESIDUAL, sws,
+                                  sws_bytes)))
+      return rc;
     if ((rc = vms_launch_norm(ctx, mesh, ga, st, R))) return rc;
     VMS_HIP(ctx, hipMemcpyAsync(ctx->h_d, ctx->dstat, 24, hipMemcpyDeviceToHost, s));
     VMS_HIP(ctx, hipStreamSynchronize(s));
@@ -1101,7 +1106,8 @@ extern "C" int vms_step(vms_ctx *ctx, const vms_mesh *mesh, const vms_material *
       break;
     }
     const unsigned fl = VMS_ASM_TANGENT | (no->rk_corr ? VMS_ASM_RKCORR : 0u);
-    if ((rc = vms_launch_assemble(ctx, mesh, mat, ga, st, f_ext, K, nullptr, no->rk_corr ? corr : nullptr, fl)))
+    if ((rc = vms_launch_assemble(ctx, mesh, mat, ga, st, f_ext, K, nullptr, no->rk_corr ? corr : nullptr, fl, sws,
+                                  sws_bytes)))
       return rc;
     if ((rc = vms_launch_prepare(ctx, mesh, K, R, no->rk_corr ? corr : nullptr, rhs, no->eps_diag, mixed ? 1 : 0)))
       return rc;

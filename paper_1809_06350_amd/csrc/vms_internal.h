@@ -95,9 +95,12 @@ struct vms_ga {   // generalized-alpha constants
 vms_ga vms_genalpha(const vms_timeint *ti);
 
 int vms_check_mesh(vms_ctx *ctx, const vms_mesh *m);
+// Bytes of element buffers the assembly needs for these flags.
+size_t vms_asm_scratch_bytes(const vms_mesh *mesh, unsigned flags);
 int vms_launch_assemble(vms_ctx *ctx, const vms_mesh *mesh, const vms_material *mat,
                         const vms_ga &ga, const vms_state *st, const double *f_ext,
                         vms_matrix *K, double *R, double *corr, unsigned flags,
+                        void *scratch, size_t scratch_bytes,
                         const double *lam = nullptr, double *vjp = nullptr, const double *dfibre = nullptr,
                         int pmask = 0, double *sens = nullptr);
 int vms_launch_clear_inverted(vms_ctx *ctx);

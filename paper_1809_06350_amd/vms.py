@@ -70,7 +70,7 @@ class Matrix:
 
 
 class Problem:
-    """One mesh + material on one device: pattern, colouring, dead load, context."""
+    """One mesh + material on one device: pattern, contribution lists, dead load, context."""
 
     def __init__(self, mesh, mat, device="cuda:0"):
         self.lib = L.load()
@@ -83,23 +83,17 @@ class Problem:
         tets = np.ascontiguousarray(mesh.tets, dtype=np.int32)
         bfaces = np.ascontiguousarray(mesh.bfaces, dtype=np.int32).reshape(-1, 3)
         nnzb = C.c_int64()
-        ncb = C.c_int32()
-        self._check(lib.vms_setup_sizes(n, m, tets.ctypes.data, C.byref(nnzb), C.byref(ncb)), "vms_setup_sizes",
-                    ctx=False)
+        self._check(lib.vms_setup_sizes(n, m, tets.ctypes.data, C.byref(nnzb)), "vms_setup_sizes", ctx=False)
         nz = nnzb.value
         h = {"row_ptr": np.zeros(n + 1, np.int32), "col": np.zeros(nz, np.int32), "tpos": np.zeros(nz, np.int32),
-             "diag_pos": np.zeros(n, np.int32), "elem_blk": np.zeros(16 * m, np.int32),
-             "colour_ptr": np.zeros(ncb.value + 1, np.int32), "elem_by_colour": np.zeros(m, np.int32),
+             "diag_pos": np.zeros(n, np.int32), "blk_src_ptr": np.zeros(nz + 1, np.int32),
+             "blk_src": np.zeros(max(16 * m, 1), np.int32),
              "nf_ptr": np.zeros(n + 1, np.int32), "nf_face": np.zeros(max(3 * f, 1), np.int32)}
-        ncol = C.c_int32()
         self._check(lib.vms_setup_build(n, m, tets.ctypes.data, f, bfaces.ctypes.data if f else None,
                                         *(h[k].ctypes.data for k in ("row_ptr", "col", "tpos", "diag_pos",
-                                                                     "elem_blk", "colour_ptr", "elem_by_colour")),
-                                        C.byref(ncol), h["nf_ptr"].ctypes.data, h["nf_face"].ctypes.data),
+                                                                     "blk_src_ptr", "blk_src", "nf_ptr", "nf_face"))),
                     "vms_setup_build", ctx=False)
         self.host = h
-        self.n_colours = ncol.value
-        self.colour_ptr = np.ascontiguousarray(h["colour_ptr"][: self.n_colours + 1])
         self.nnzb = nz
         dev = self.dev
 
@@ -111,14 +105,13 @@ class Problem:
                   "traction": up(mesh.traction if f else np.zeros((1, 3)), np.float64),
                   "dir_mask": up(mesh.dir_mask, np.uint8), "dir_vel": up(mesh.dir_vel, np.float64),
                   "fibre": up(mesh.fibre, np.float64) if mesh.fibre is not None else None}
-        for k in ("row_ptr", "col", "tpos", "diag_pos", "elem_blk", "elem_by_colour", "nf_ptr", "nf_face"):
+        for k in ("row_ptr", "col", "tpos", "diag_pos", "blk_src_ptr", "blk_src", "nf_ptr", "nf_face"):
             self.d[k] = up(h[k], np.int32)
         d = self.d
-        self.cmesh = L.Mesh(n, m, f, self.n_colours, nz, _p(d["X"]), _p(d["tets"]), _p(d["bfaces"]),
+        self.cmesh = L.Mesh(n, m, f, nz, _p(d["X"]), _p(d["tets"]), _p(d["bfaces"]),
                             _p(d["traction"]), _p(d["dir_mask"]), _p(d["dir_vel"]), _p(d["fibre"]),
-                            _p(d["row_ptr"]), _p(d["col"]), _p(d["tpos"]), _p(d["diag_pos"]), _p(d["elem_blk"]),
-                            _p(d["elem_by_colour"]), _p(d["nf_ptr"]), _p(d["nf_face"]),
-                            self.colour_ptr.ctypes.data)
+                            _p(d["row_ptr"]), _p(d["col"]), _p(d["tpos"]), _p(d["diag_pos"]), _p(d["blk_src_ptr"]),
+                            _p(d["blk_src"]), _p(d["nf_ptr"]), _p(d["nf_face"]))
         self.set_material(mat)
         self.stream = torch.cuda.current_stream(dev)
         ctx = C.c_void_p()
@@ -205,9 +198,10 @@ class Problem:
         if flags & ASM_TANGENT and K is None:
             K = self.new_matrix()
         cK = K.c() if K is not None else L.Matrix()
+        ws = self.workspace(self.lib.vms_assemble_workspace(C.byref(self.cmesh), flags) + 512)
         self._check(self.lib.vms_assemble(self.ctx, C.byref(self.cmesh), C.byref(self.cmat), C.byref(ti),
                                           C.byref(self.cstate(st)), _p(self.f_ext) if load else None,
-                                          C.byref(cK), _p(R), _p(corr), flags), "vms_assemble")
+                                          C.byref(cK), _p(R), _p(corr), flags, _p(ws), ws.numel()), "vms_assemble")
         return K, R, corr
 
     def residual_norm(self, st, ti, R):

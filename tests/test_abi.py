@@ -1,7 +1,7 @@
 """Host-side checks of the C ABI (no GPU needed): the library loads, exports
 every entry point that include/vms.h declares, and its integer setup (block
-pattern, transpose map, element->block map, colouring, node->face lists) is
-exact against independent constructions."""
+pattern, transpose map, block contribution lists, node->face lists) is exact
+against independent constructions."""
 import ctypes as C
 import os
 import re
@@ -37,21 +37,17 @@ def build_host(mesh):
     n, m, f = mesh.n_nodes, mesh.n_tets, mesh.bfaces.shape[0]
     tets = np.ascontiguousarray(mesh.tets, np.int32)
     bf = np.ascontiguousarray(mesh.bfaces, np.int32)
-    nnzb, ncb = C.c_int64(), C.c_int32()
-    assert lib.vms_setup_sizes(n, m, tets.ctypes.data, C.byref(nnzb), C.byref(ncb)) == 0
+    nnzb = C.c_int64()
+    assert lib.vms_setup_sizes(n, m, tets.ctypes.data, C.byref(nnzb)) == 0
     nz = nnzb.value
     h = {"row_ptr": np.zeros(n + 1, np.int32), "col": np.zeros(nz, np.int32), "tpos": np.zeros(nz, np.int32),
-         "diag_pos": np.zeros(n, np.int32), "elem_blk": np.zeros(16 * m, np.int32),
-         "colour_ptr": np.zeros(ncb.value + 1, np.int32), "elem_by_colour": np.zeros(m, np.int32),
+         "diag_pos": np.zeros(n, np.int32), "blk_src_ptr": np.zeros(nz + 1, np.int32),
+         "blk_src": np.zeros(16 * m, np.int32),
          "nf_ptr": np.zeros(n + 1, np.int32), "nf_face": np.zeros(max(3 * f, 1), np.int32)}
-    ncol = C.c_int32()
     rc = lib.vms_setup_build(n, m, tets.ctypes.data, f, bf.ctypes.data,
-                             *(h[k].ctypes.data for k in ("row_ptr", "col", "tpos", "diag_pos", "elem_blk",
-                                                          "colour_ptr", "elem_by_colour")),
-                             C.byref(ncol), h["nf_ptr"].ctypes.data, h["nf_face"].ctypes.data)
+                             *(h[k].ctypes.data for k in ("row_ptr", "col", "tpos", "diag_pos", "blk_src_ptr",
+                                                          "blk_src", "nf_ptr", "nf_face")))
     assert rc == 0
-    h["n_colours"] = ncol.value
-    h["colour_ptr"] = h["colour_ptr"][: ncol.value + 1]
     return h
 
 
@@ -76,25 +72,22 @@ def test_pattern_matches_element_connectivity(N):
     np.testing.assert_array_equal(col[h["tpos"]], rows)
     np.testing.assert_array_equal(col[h["diag_pos"]], np.arange(n))
     np.testing.assert_array_equal(rows[h["diag_pos"]], np.arange(n))
-    # element -> block map
-    eb = h["elem_blk"].reshape(-1, 4, 4)
-    np.testing.assert_array_equal(rows[eb], np.repeat(t[:, :, None], 4, axis=2))
-    np.testing.assert_array_equal(col[eb], np.repeat(t[:, None, :], 4, axis=1))
-
-
-@pytest.mark.parametrize("N", [2, 4, 6])
-def test_colouring_is_conflict_free_and_complete(N):
-    mesh = synth.cube_mesh(N)
-    h = build_host(mesh)
-    cp, ebc = h["colour_ptr"], h["elem_by_colour"]
-    assert cp[-1] == mesh.n_tets
-    assert np.array_equal(np.sort(ebc), np.arange(mesh.n_tets))
-    for c in range(h["n_colours"]):
-        el = ebc[cp[c]:cp[c + 1]]
-        nodes = mesh.tets[el].ravel()
-        assert np.unique(nodes).size == nodes.size, f"colour {c} shares a node"
-    # greedy colouring of a Kuhn mesh: a few dozen colours at most
-    assert h["n_colours"] <= 64
+    # block contribution lists: every element-local pair exactly once, under its block, in element order
+    ptr, src = h["blk_src_ptr"], h["blk_src"]
+    assert ptr[0] == 0 and ptr[-1] == 16 * mesh.n_tets
+    np.testing.assert_array_equal(np.sort(src), np.arange(16 * mesh.n_tets))
+    blk = np.repeat(np.arange(col.size), np.diff(ptr))
+    e, a, b = src >> 4, (src >> 2) & 3, src & 3
+    np.testing.assert_array_equal(rows[blk], t[e, a])
+    np.testing.assert_array_equal(col[blk], t[e, b])
+    for k in range(col.size):
+        assert np.all(np.diff(e[ptr[k]:ptr[k + 1]]) >= 0)
+    # a diagonal block lists each element around its node once, with pair a*4 + a
+    d = h["diag_pos"]
+    for i in range(n):
+        s_ = src[ptr[d[i]]:ptr[d[i] + 1]]
+        assert np.all((s_ & 15) % 5 == 0)
+        np.testing.assert_array_equal(s_ >> 4, np.nonzero((t == i).any(axis=1))[0])
 
 
 def test_node_face_lists():
@@ -109,5 +102,5 @@ def test_node_face_lists():
 def test_setup_rejects_out_of_range_nodes():
     lib = L.load()
     tets = np.array([[0, 1, 2, 7]], np.int32)
-    nnzb, ncb = C.c_int64(), C.c_int32()
-    assert lib.vms_setup_sizes(4, 1, tets.ctypes.data, C.byref(nnzb), C.byref(ncb)) == -1
+    nnzb = C.c_int64()
+    assert lib.vms_setup_sizes(4, 1, tets.ctypes.data, C.byref(nnzb)) == -1
