@@ -159,6 +159,8 @@ def main():
     ap.add_argument("--shat-ratio", type=float, default=20.0)
     ap.add_argument("--mixed-tol", default="1e-6,1e-6,1e-4",
                     help="intermediate A, Schur and inner tolerances of the mixed form")
+    ap.add_argument("--orth", default="cgs1", choices=["cgs2", "cgs1", "cgs_ifneeded", "mgs"],
+                    help="Arnoldi orthogonalisation of every Krylov level")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--spmv-only", type=int, default=0,
                     help="only launch the A-block SpMV (FP64 and FP32) this many times each on the first "
@@ -183,11 +185,13 @@ def main():
     if args.spmv_only:
         spmv_only(prob, mesh, ti, args.spmv_only)
         return
+    orth = {"cgs2": V.ORTH_CGS2, "cgs1": V.ORTH_CGS1, "cgs_ifneeded": V.ORTH_CGS_IFNEEDED,
+            "mgs": V.ORTH_MGS}[args.orth]
     forms = {
         "fp64": V.solver_opts(rtol=1e-8, rtol_A=1e-6, rtol_S=1e-6, rtol_I=1e-4, shat_degree=args.shat_degree,
-                              shat_ratio=args.shat_ratio),
+                              shat_ratio=args.shat_ratio, orth=orth),
         "mixed": V.solver_opts(rtol=1e-8, rtol_A=mt[0], rtol_S=mt[1], rtol_I=mt[2], precision=V.MIXED,
-                               shat_degree=args.shat_degree, shat_ratio=args.shat_ratio),
+                               shat_degree=args.shat_degree, shat_ratio=args.shat_ratio, orth=orth),
     }
     results = {}
     for name in args.forms.split(","):
@@ -233,7 +237,7 @@ def main():
            "data": "synthetic",
            "config": {"workload": f"cube{N}^3 Kuhn tets, nu={args.nu}, neo-Hookean, dt=1e-3, Newton/FGMRES 1e-8",
                       "nodes": n, "tets": mesh.n_tets, "unknowns": 4 * n, "nnzb": nnzb,
-                      "shat_degree": args.shat_degree, "shat_ratio": args.shat_ratio,
+                      "shat_degree": args.shat_degree, "shat_ratio": args.shat_ratio, "orth": args.orth,
                       "parallelism": "single GPU"},
            "roofline": roof}
     out.update(extra)

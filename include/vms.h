@@ -68,8 +68,11 @@ enum { VMS_PC_LDU = 0, VMS_PC_UPPER = 1, VMS_PC_LOWER = 2, VMS_PC_DIAG = 3 };
 /* precision of the intermediate and inner levels */
 enum { VMS_FP64 = 0, VMS_MIXED = 1 };
 
-/* Arnoldi orthogonalisation */
-enum { VMS_ORTH_CGS2 = 0, VMS_ORTH_MGS = 1 };
+/* Arnoldi orthogonalisation: classical Gram-Schmidt with one
+ * reorthogonalisation pass; modified Gram-Schmidt; classical Gram-Schmidt
+ * without reorthogonalisation; classical Gram-Schmidt with a second pass only
+ * when the first one removed more than half of ||w||^2 */
+enum { VMS_ORTH_CGS2 = 0, VMS_ORTH_MGS = 1, VMS_ORTH_CGS1 = 2, VMS_ORTH_CGS_IFNEEDED = 3 };
 
 typedef struct vms_ctx vms_ctx;
 
@@ -129,7 +132,8 @@ typedef struct {
   double rtol_I, atol_I; int32_t maxit_I;  /* inner A-solve inside the Schur product */
   int32_t precond;    /* VMS_PC_* */
   int32_t precision;  /* VMS_FP64 or VMS_MIXED */
-  int32_t orth;       /* VMS_ORTH_* */
+  int32_t orth;       /* VMS_ORTH_* of the A-, S- and inner levels; the outer FGMRES uses
+                         VMS_ORTH_MGS if that is chosen, else VMS_ORTH_CGS2 */
   int32_t shat_degree;/* right preconditioner of the Schur solve: 0 = diag(S^)^-1; k > 0 = degree-k
                          Chebyshev polynomial in diag(S^)^-1 S^ on [lmax/shat_ratio, lmax] */
   double shat_ratio;  /* lmax / lmin of the Chebyshev interval (used when shat_degree > 0) */

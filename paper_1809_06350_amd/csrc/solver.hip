@@ -17,9 +17,11 @@
 // kernels of an iteration read the `done` flag and return immediately once
 // the level has converged, so the host can enqueue several A-level
 // iterations before it reads the flag back (one host sync per batch).
-// Orthogonalisation is classical Gram-Schmidt with one reorthogonalisation
-// (CGS2: two multi-dot / multi-update passes, O(1) launches per iteration) or
-// modified Gram-Schmidt (one fused dot/axpy launch per basis vector).
+// Orthogonalisation is classical Gram-Schmidt -- one multi-dot and one
+// multi-update pass per iteration (CGS1), a second pass always (CGS2) or when
+// the first removed more than half of the vector ("if needed") -- or modified
+// Gram-Schmidt (one dot/axpy launch pair per basis vector).  The outer FGMRES
+// always uses CGS2 (or MGS).
 //
 // Mixed form: the intermediate and inner levels run on FP32 copies of the
 // scaled blocks with FP32 Krylov vectors (FP64 accumulation of every sum and
@@ -37,12 +39,21 @@
 namespace {
 
 enum { PC_NONE = 0, PC_BJ33 = 1, PC_DIAG = 2 };
+
+// Arnoldi vector kernels: 1024-thread workgroups, at most 256 of them (their
+// partials are reduced inside the consuming kernel)
+#define KRY_BLOCK 1024
+#define KRY_MAX_BLOCKS 256
+inline int kry_blocks(int64_t nvec) {
+  int64_t nb = (nvec + 2 * KRY_BLOCK - 1) / (2 * KRY_BLOCK);
+  return (int)std::min<int64_t>(std::max<int64_t>(nb, 1), KRY_MAX_BLOCKS);
+}
 enum { KS_OK = 0, KS_MAXIT = 1, KS_NAN = 2, KS_BREAKDOWN = 3 };
 enum { IF_DONE = 0, IF_ITS = 1, IF_STATUS = 2, IF_COUNTER = 3 };
 
 struct KOff {
   int m;
-  int64_t H, cs, sn, g, y, h1, h2, scal, part;
+  int64_t H, cs, sn, g, y, h1, h2, scal, pn, pn2, part;
 };
 
 inline KOff make_off(int m) {
@@ -57,6 +68,8 @@ inline KOff make_off(int m) {
   o.h1 = p; p += m + 1;
   o.h2 = p; p += m + 1;
   o.scal = p; p += 8;
+  o.pn = p; p += VMS_MAX_RED_BLOCKS;
+  o.pn2 = p; p += VMS_MAX_RED_BLOCKS;
   o.part = p; p += (int64_t)(m + 1) * VMS_MAX_RED_BLOCKS;
   return o;
 }
@@ -151,16 +164,51 @@ k_kinit_scale(int64_t nvec, const T *__restrict__ b, T *V0, T *Z0, const double 
   scale_and_precond(nvec, b, 1.0 / ctrl[off.scal + 0], V0, Z0, pc, pcd);
 }
 
-// partial dots <V_k, w>, k < nk, eight basis vectors per pass over the rows
+// sum of the nbp (<= KRY_MAX_BLOCKS) partials p[0], p[ld], ... in a fixed order
+__device__ __forceinline__ double kry_sum_partials(const double *p, int nbp, int ld, double *sm) {
+  double v = (threadIdx.x < (unsigned)nbp) ? p[(int64_t)threadIdx.x * ld] : 0.0;
+  v = wave_sum(v);
+  const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  if ((threadIdx.x & 63) == 0) sm[w] = v;
+  __syncthreads();
+  double r = 0.0;
+  for (int q = 0; q < nw; ++q) r += sm[q];
+  __syncthreads();
+  return r;
+}
+
+// Reorthogonalisation test of the "if needed" mode (Daniel-Gragg-Kaufman-
+// Stewart with eta^2 = 1/2): after the first pass w' = w - V h, a second pass
+// is needed when ||w'||^2 < (||w'||^2 + ||h||^2) / 2, i.e. when more than half
+// of ||w||^2 was removed.  Every kernel of the step evaluates it from the same
+// data in the same order, so they all take the same decision.
+__device__ __forceinline__ bool kry_need_reorth(const double *ctrl, const KOff &off, int nbp, int nk, double *sm) {
+  const double w2 = kry_sum_partials(ctrl + off.pn, nbp, 1, sm);
+  double hh = 0.0;
+  for (int k = threadIdx.x; k < nk; k += blockDim.x) hh += ctrl[off.h1 + k] * ctrl[off.h1 + k];
+  hh = wave_sum(hh);
+  const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  if ((threadIdx.x & 63) == 0) sm[w] = hh;
+  __syncthreads();
+  double h2 = 0.0;
+  for (int q = 0; q < nw; ++q) h2 += sm[q];
+  __syncthreads();
+  return w2 < 0.5 * (w2 + h2);
+}
+
+// partial dots <V_k, w>, k < nk, eight basis vectors per pass over the rows;
+// one partial per workgroup (up to 16 wavefronts), summed over the waves in
+// wave order
 template <typename T>
-__global__ void __launch_bounds__(VMS_BLOCK)
+__global__ void __launch_bounds__(KRY_BLOCK)
 k_mdot_part(int64_t nvec, const T *__restrict__ V, int nk, const T *__restrict__ w, double *part, int ld,
-            const int *iflag) {
+            const int *iflag, const double *sel_ctrl = nullptr, KOff sel_off = KOff{}, int sel_nbp = 0) {
   if (iflag[IF_DONE]) return;
-  __shared__ double sm[4][8];
+  __shared__ double sm[16][8];
+  if (sel_ctrl && !kry_need_reorth(sel_ctrl, sel_off, sel_nbp, nk, &sm[0][0])) return;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   const int64_t t0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = blockDim.x >> 6;
   for (int k0 = 0; k0 < nk; k0 += 8) {
     const int kk = min(8, nk - k0);
     double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
@@ -177,10 +225,83 @@ k_mdot_part(int64_t nvec, const T *__restrict__ V, int nk, const T *__restrict__
       if (lane == 0) sm[wv][q] = v;
     }
     __syncthreads();
-    if (threadIdx.x < kk)
-      part[(int64_t)blockIdx.x * ld + k0 + threadIdx.x] =
-          (sm[0][threadIdx.x] + sm[1][threadIdx.x]) + (sm[2][threadIdx.x] + sm[3][threadIdx.x]);
+    if (threadIdx.x < kk) {
+      double t = 0.0;
+      for (int q = 0; q < nw; ++q) t += sm[q][threadIdx.x];
+      part[(int64_t)blockIdx.x * ld + k0 + threadIdx.x] = t;
+    }
     __syncthreads();
+  }
+}
+
+// ---- fused Arnoldi kernels (classical Gram-Schmidt) ------------------------
+// Workgroups of KRY_BLOCK threads, at most KRY_MAX_BLOCKS of them, so that a
+// consumer can reduce the producer's partials itself: every workgroup sums
+// the same partials in the same fixed order and obtains identical values,
+// which removes a separate finalize launch per reduction.
+
+// cs[k] = sum_b part[b * ld + k] for k < nk: 16 coefficients per round, the
+// partials split over 64 thread groups and combined by a fixed binary tree
+// (needs exactly KRY_BLOCK = 1024 threads)
+__device__ __forceinline__ void kry_reduce_coefs(const double *part, int nbp, int ld, int nk, double *cs,
+                                                 double (*red)[17]) {
+  const int kl = threadIdx.x & 15, bg = threadIdx.x >> 4;   // bg < 64 for 1024 threads
+  for (int k0 = 0; k0 < nk; k0 += 16) {
+    const int k = k0 + kl;
+    double a = 0.0;
+    if (k < nk)
+      for (int b = bg; b < nbp; b += 64) a += part[(int64_t)b * ld + k];
+    red[bg][kl] = a;
+    __syncthreads();
+    for (int h = 32; h > 0; h >>= 1) {
+      if (bg < h) red[bg][kl] += red[bg + h][kl];
+      __syncthreads();
+    }
+    if (bg == 0 && k < nk) cs[k] = red[0][kl];
+    __syncthreads();
+  }
+}
+
+// w -= sum_k h_k V_k with h reduced in-kernel from the k_mdot_part partials;
+// workgroup 0 stores h (Hessenberg column part); with NORM also the partial
+// sums of the updated ||w||^2 (pn[blockIdx.x])
+template <typename T, bool NORM>
+__global__ void __launch_bounds__(KRY_BLOCK)
+k_mupdate_fin(int64_t nvec, const T *__restrict__ V, int nk, T *w, const double *part, int nbp, int ld,
+              double *hout, double *pn, const int *iflag, const double *sel_ctrl = nullptr, KOff sel_off = KOff{}) {
+  if (iflag[IF_DONE]) return;
+  __shared__ double cs[1024];
+  __shared__ double red[64][17];
+  __shared__ double sm[16];
+  if (sel_ctrl && !kry_need_reorth(sel_ctrl, sel_off, nbp, nk, sm)) return;
+  kry_reduce_coefs(part, nbp, ld, nk, cs, red);
+  if (blockIdx.x == 0)
+    for (int k = threadIdx.x; k < nk; k += blockDim.x) hout[k] = cs[k];
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  double ss = 0.0;
+  for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < nvec; r += stride) {
+    double a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+    int k = 0;
+    for (; k + 4 <= nk; k += 4) {
+      a0 += cs[k] * dl(V, (int64_t)k * nvec + r);
+      a1 += cs[k + 1] * dl(V, (int64_t)(k + 1) * nvec + r);
+      a2 += cs[k + 2] * dl(V, (int64_t)(k + 2) * nvec + r);
+      a3 += cs[k + 3] * dl(V, (int64_t)(k + 3) * nvec + r);
+    }
+    for (; k < nk; ++k) a0 += cs[k] * dl(V, (int64_t)k * nvec + r);
+    const T out = (T)(dl(w, r) - ((a0 + a1) + (a2 + a3)));
+    w[r] = out;
+    if (NORM) ss += (double)out * (double)out;
+  }
+  if (!NORM) return;
+  ss = wave_sum(ss);
+  const int wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  if ((threadIdx.x & 63) == 0) sm[wv] = ss;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int q = 0; q < nw; ++q) t += sm[q];
+    pn[blockIdx.x] = t;
   }
 }
 
@@ -213,7 +334,6 @@ k_dot_finalize(const double *part, int nb, int ld, int nk, double *out, const in
     out[k] = t;
   }
 }
-inline int fin_grid(int nk) { return (nk + FIN_K - 1) / FIN_K; }
 
 // w -= sum_k coef[k] V_k (four independent partial sums per row); with NORM
 // also the partial sums of the updated ||w||^2
@@ -253,19 +373,16 @@ k_mupdate(int64_t nvec, const T *__restrict__ V, int nk, T *w, const double *coe
   if (threadIdx.x == 0) part[blockIdx.x] = ss;
 }
 
-// finish Arnoldi step j: Hessenberg column (h1 + h2 for CGS2), h_{j+1,j} =
-// ||w||, previous rotations, new Givens rotation, residual, flags
-__global__ void __launch_bounds__(VMS_BLOCK)
-k_givens(int nb, double *ctrl, KOff off, int *iflag, int j, int cgs, int maxit) {
-  if (iflag[IF_DONE]) return;
-  __shared__ double sm[4];
-  const double s = sum_partials1(ctrl + off.part, nb, sm);
-  if (threadIdx.x != 0) return;
+// finish Arnoldi step j (one thread): Hessenberg column (h1, plus h2 after a
+// reorthogonalisation pass), h_{j+1,j} = ||w|| = hn, previous rotations, new
+// Givens rotation, least-squares residual |g_{j+1}|, flags
+__device__ void givens_update(double *ctrl, const KOff &off, int *iflag, int j, int nsum, int maxit, double hn) {
   const int m1 = off.m + 1;
   double *col = ctrl + off.H + (int64_t)j * m1;
   double *cs = ctrl + off.cs, *sn = ctrl + off.sn, *g = ctrl + off.g;
-  const double hn = sqrt(s);
-  if (cgs)
+  if (nsum == 1)
+    for (int i = 0; i <= j; ++i) col[i] = ctrl[off.h1 + i];
+  else if (nsum == 2)
     for (int i = 0; i <= j; ++i) col[i] = ctrl[off.h1 + i] + ctrl[off.h2 + i];
   col[j + 1] = hn;
   for (int i = 0; i < j; ++i) {
@@ -300,6 +417,34 @@ k_givens(int nb, double *ctrl, KOff off, int *iflag, int j, int cgs, int maxit) 
     iflag[IF_STATUS] = KS_MAXIT;
     iflag[IF_DONE] = 1;
   }
+}
+
+// MGS path: Hessenberg column already in place, ||w||^2 partials in part
+__global__ void __launch_bounds__(VMS_BLOCK)
+k_givens(int nb, double *ctrl, KOff off, int *iflag, int j, int maxit) {
+  if (iflag[IF_DONE]) return;
+  __shared__ double sm[4];
+  const double s = sum_partials1(ctrl + off.part, nb, sm);
+  if (threadIdx.x == 0) givens_update(ctrl, off, iflag, j, 0, maxit, sqrt(s));
+}
+
+// CGS path: h_{j+1,j} = ||w|| from the k_mupdate_fin norm partials (reduced by
+// every workgroup), V_{j+1} = w / h_{j+1,j}, Z_{j+1} = M^-1 V_{j+1}; thread 0
+// of workgroup 0 also finishes the Givens step.  nsum: 1 = one pass (h1,
+// norm partials pn), 2 = two passes (h1 + h2, pn2), 3 = decide as the
+// "if needed" test does.  (Workgroups that start after
+// it has set the done flag skip the normalisation, whose result is then not
+// used.)
+template <typename T>
+__global__ void __launch_bounds__(KRY_BLOCK)
+k_normalize_givens(int64_t nvec, const T *__restrict__ w, T *V1, T *Z1, double *ctrl, KOff off, int *iflag, int nbp,
+                   int j, int nsum, int maxit, int pc, const T *pcd) {
+  if (iflag[IF_DONE]) return;
+  __shared__ double sm[16];
+  if (nsum == 3) nsum = kry_need_reorth(ctrl, off, nbp, j + 1, sm) ? 2 : 1;   // "if needed" mode
+  const double hn = sqrt(kry_sum_partials(ctrl + (nsum == 2 ? off.pn2 : off.pn), nbp, 1, sm));
+  if (blockIdx.x == 0 && threadIdx.x == 0) givens_update(ctrl, off, iflag, j, nsum, maxit, hn);
+  scale_and_precond(nvec, w, hn > 0.0 ? 1.0 / hn : 0.0, V1, Z1, pc, pcd);
 }
 
 // MGS step k: w -= H[k-1,j] V_{k-1} (k > 0), then partial dots <w, V_k>
@@ -589,7 +734,7 @@ struct Carver {
 template <typename T>
 struct KLevel {
   int64_t nvec = 0;
-  int m = 0, nb = 1;
+  int m = 0, nb = 1, nbk = 1;
   T *V = nullptr, *Z = nullptr, *W = nullptr;
   double *ctrl = nullptr;
   int *iflag = nullptr;
@@ -598,6 +743,7 @@ struct KLevel {
     nvec = nv;
     m = std::max(mm, 1);
     nb = vms_red_blocks(nv);
+    nbk = kry_blocks(nv);
     V = cv.take<T>((int64_t)(m + 1) * nv);
     Z = cv.take<T>((int64_t)(m + 1) * nv);
     W = cv.take<T>(nv);
@@ -613,15 +759,22 @@ inline int sync_level_flags(vms_ctx *ctx, const int *iflag) {
   return VMS_OK;
 }
 
-// Arnoldi step j of level L: orthogonalise W against V_0..V_j (CGS2 or MGS),
-// then the Hessenberg/Givens update and the convergence flags.
+// Arnoldi step j of level L: orthogonalise W against V_0..V_j, finish the
+// Hessenberg/Givens update and the convergence flags, and form V_{j+1} and
+// Z_{j+1} = M^-1 V_{j+1}.
+//   CGS1: multi-dot, multi-update (+ norm partials), normalize/Givens
+//   CGS2: the same with a second multi-dot/multi-update pass
+//   CGS "if needed": the second pass only where the test of
+//         kry_need_reorth asks for it (its kernels return at once otherwise)
+//   MGS:  one dot/axpy launch pair per basis vector
 template <typename T>
-int orth_level(vms_ctx *ctx, KLevel<T> &L, int j, int maxit, int mode) {
+int orth_level(vms_ctx *ctx, KLevel<T> &L, int j, int maxit, int mode, int pc, const T *pcd) {
   hipStream_t s = ctx->stream;
-  const dim3 gr(L.nb), bl(VMS_BLOCK);
   double *part = L.ctrl + L.off.part;
   const int ld = L.m + 1;
+  T *V1 = L.V + (int64_t)(j + 1) * L.nvec, *Z1 = L.Z + (int64_t)(j + 1) * L.nvec;
   if (mode == VMS_ORTH_MGS) {
+    const dim3 gr(L.nb), bl(VMS_BLOCK);
     double *col = L.ctrl + L.off.H + (int64_t)j * ld;
     for (int k = 0; k <= j; ++k) {
       hipLaunchKernelGGL(k_mgs_part<T>, gr, bl, 0, s, L.nvec, L.V, k, L.W, (const double *)(col + (k > 0 ? k - 1 : 0)),
@@ -630,20 +783,34 @@ int orth_level(vms_ctx *ctx, KLevel<T> &L, int j, int maxit, int mode) {
     }
     hipLaunchKernelGGL((k_mupdate<T, true>), gr, bl, 0, s, L.nvec, L.V + (int64_t)j * L.nvec, 1, L.W,
                        (const double *)(col + j), part, L.iflag);
-    hipLaunchKernelGGL(k_givens, dim3(1), bl, 0, s, L.nb, L.ctrl, L.off, L.iflag, j, 0, maxit);
+    hipLaunchKernelGGL(k_givens, dim3(1), bl, 0, s, L.nb, L.ctrl, L.off, L.iflag, j, maxit);
+    hipLaunchKernelGGL(k_normalize<T>, gr, bl, 0, s, L.nvec, L.W, V1, Z1, L.ctrl, L.off, L.iflag, pc, pcd);
   } else {
+    const dim3 gk(L.nbk), bk(KRY_BLOCK);
     double *h1 = L.ctrl + L.off.h1, *h2 = L.ctrl + L.off.h2;
-    hipLaunchKernelGGL(k_mdot_part<T>, gr, bl, 0, s, L.nvec, L.V, j + 1, L.W, part, ld, L.iflag);
-    hipLaunchKernelGGL(k_dot_finalize, dim3(fin_grid(j + 1)), bl, 0, s, (const double *)part, L.nb, ld, j + 1, h1,
-                       L.iflag);
-    hipLaunchKernelGGL((k_mupdate<T, false>), gr, bl, 0, s, L.nvec, L.V, j + 1, L.W, (const double *)h1, part,
-                       L.iflag);
-    hipLaunchKernelGGL(k_mdot_part<T>, gr, bl, 0, s, L.nvec, L.V, j + 1, L.W, part, ld, L.iflag);
-    hipLaunchKernelGGL(k_dot_finalize, dim3(fin_grid(j + 1)), bl, 0, s, (const double *)part, L.nb, ld, j + 1, h2,
-                       L.iflag);
-    hipLaunchKernelGGL((k_mupdate<T, true>), gr, bl, 0, s, L.nvec, L.V, j + 1, L.W, (const double *)h2, part,
-                       L.iflag);
-    hipLaunchKernelGGL(k_givens, dim3(1), bl, 0, s, L.nb, L.ctrl, L.off, L.iflag, j, 1, maxit);
+    double *pn = L.ctrl + L.off.pn, *pn2 = L.ctrl + L.off.pn2;
+    hipLaunchKernelGGL(k_mdot_part<T>, gk, bk, 0, s, L.nvec, L.V, j + 1, L.W, part, ld, L.iflag,
+                       (const double *)nullptr, KOff{}, 0);
+    if (mode == VMS_ORTH_CGS2) {
+      hipLaunchKernelGGL((k_mupdate_fin<T, false>), gk, bk, 0, s, L.nvec, L.V, j + 1, L.W, (const double *)part,
+                         L.nbk, ld, h1, pn, L.iflag, (const double *)nullptr, KOff{});
+      hipLaunchKernelGGL(k_mdot_part<T>, gk, bk, 0, s, L.nvec, L.V, j + 1, L.W, part, ld, L.iflag,
+                         (const double *)nullptr, KOff{}, 0);
+      hipLaunchKernelGGL((k_mupdate_fin<T, true>), gk, bk, 0, s, L.nvec, L.V, j + 1, L.W, (const double *)part,
+                         L.nbk, ld, h2, pn2, L.iflag, (const double *)nullptr, KOff{});
+    } else {
+      hipLaunchKernelGGL((k_mupdate_fin<T, true>), gk, bk, 0, s, L.nvec, L.V, j + 1, L.W, (const double *)part,
+                         L.nbk, ld, h1, pn, L.iflag, (const double *)nullptr, KOff{});
+      if (mode == VMS_ORTH_CGS_IFNEEDED) {   // second pass only where the test asks for it
+        hipLaunchKernelGGL(k_mdot_part<T>, gk, bk, 0, s, L.nvec, L.V, j + 1, L.W, part, ld, L.iflag,
+                           (const double *)L.ctrl, L.off, L.nbk);
+        hipLaunchKernelGGL((k_mupdate_fin<T, true>), gk, bk, 0, s, L.nvec, L.V, j + 1, L.W, (const double *)part,
+                           L.nbk, ld, h2, pn2, L.iflag, (const double *)L.ctrl, L.off);
+      }
+    }
+    const int nsum = (mode == VMS_ORTH_CGS2) ? 2 : (mode == VMS_ORTH_CGS_IFNEEDED) ? 3 : 1;
+    hipLaunchKernelGGL(k_normalize_givens<T>, gk, bk, 0, s, L.nvec, (const T *)L.W, V1, Z1, L.ctrl, L.off, L.iflag,
+                       L.nbk, j, nsum, maxit, pc, pcd);
   }
   VMS_LAUNCH_CHECK(ctx);
   return VMS_OK;
@@ -676,9 +843,7 @@ int gmres_run(vms_ctx *ctx, KLevel<T> &L, const T *b, T *x, double rtol, double 
     const int nbt = std::min(batch, maxit - j);
     for (int i = 0; i < nbt; ++i, ++j) {
       if ((rc = op(j))) return rc;
-      if ((rc = orth_level<T>(ctx, L, j, maxit, orth))) return rc;
-      hipLaunchKernelGGL(k_normalize<T>, gr, bl, 0, s, L.nvec, L.W, L.V + (int64_t)(j + 1) * L.nvec,
-                         L.Z + (int64_t)(j + 1) * L.nvec, L.ctrl, L.off, L.iflag, pc, pcd);
+      if ((rc = orth_level<T>(ctx, L, j, maxit, orth, pc, pcd))) return rc;
     }
     VMS_LAUNCH_CHECK(ctx);
     if ((rc = sync_level_flags(ctx, L.iflag))) return rc;
@@ -889,6 +1054,9 @@ int check_opts(vms_ctx *ctx, const vms_solver_opts *o) {
     return vms_set_error(ctx, VMS_ERR_ARG, "unknown precision");
   if (o->shat_degree < 0 || o->shat_degree > 64)
     return vms_set_error(ctx, VMS_ERR_ARG, "shat_degree must be in [0, 64]");
+  if (o->orth != VMS_ORTH_CGS2 && o->orth != VMS_ORTH_MGS && o->orth != VMS_ORTH_CGS1 &&
+      o->orth != VMS_ORTH_CGS_IFNEEDED)
+    return vms_set_error(ctx, VMS_ERR_ARG, "unknown orthogonalisation");
   return VMS_OK;
 }
 
@@ -930,7 +1098,10 @@ int solve_impl(vms_ctx *ctx, const vms_mesh *mesh, const vms_matrix *K, const do
   hipStream_t s = ctx->stream;
   const int maxit = std::min(o->maxit, L.m);
   int status = 0, its = 0;
-  rc = gmres_run<double>(ctx, L, rhs, x, o->rtol, o->atol, maxit, o->orth, PC_NONE, (const double *)nullptr, true,
+  // the outer FGMRES (a few iterations) always reorthogonalises, so its least-squares residual is that of a
+  // numerically orthonormal basis whatever the inner levels use
+  const int orth_outer = (o->orth == VMS_ORTH_MGS) ? VMS_ORTH_MGS : VMS_ORTH_CGS2;
+  rc = gmres_run<double>(ctx, L, rhs, x, o->rtol, o->atol, maxit, orth_outer, PC_NONE, (const double *)nullptr, true,
                          est_outer, op, its, status);
   if (rc) return rc;
   stats->n_outer = its;

@@ -180,7 +180,8 @@ def test_dirichlet_and_scaling_match_oracle(problems, name):
 
 
 @pytest.mark.parametrize("precond,max_outer", [(V.PC_LDU, 1), (V.PC_UPPER, 2), (V.PC_LOWER, 2)])
-@pytest.mark.parametrize("orth,shat", [(V.ORTH_CGS2, 0), (V.ORTH_MGS, 0), (V.ORTH_CGS2, 6)])
+@pytest.mark.parametrize("orth,shat", [(V.ORTH_CGS2, 0), (V.ORTH_MGS, 0), (V.ORTH_CGS2, 6), (V.ORTH_CGS1, 0),
+                                       (V.ORTH_CGS_IFNEEDED, 0), (V.ORTH_CGS_IFNEEDED, 6)])
 def test_nested_solve_matches_lu(problems, precond, max_outer, orth, shat):
     import scipy.sparse.linalg as spla
     prob, mesh, mat, ti, disc = problems("cube-comp")
