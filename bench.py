@@ -32,9 +32,10 @@ def log(msg):
 
 
 def spmv_A_bytes(n, nnzb, elem):
-    """Algorithmic bytes of one 3x3 block SpMV: values + column indices + row
-    pointers + x (once) + y."""
-    return (9 * elem + 4) * nnzb + 4 * (n + 1) + 2 * 3 * elem * n
+    """Algorithmic bytes of one 3x3 block SpMV over the nnzb real blocks (the
+    padding slots of the fixed-width rows are not counted): values + column
+    indices + x (once) + y."""
+    return (9 * elem + 4) * nnzb + 2 * 3 * elem * n
 
 
 def pmc_traffic(key):
@@ -67,7 +68,10 @@ def time_spmv(prob, K, op, x, fp32, reps=50):
     return s.elapsed_time(e) / reps * 1e-3   # seconds per launch
 
 
-def run_form(prob, mesh, ti, nopts, sopts, steps, warmup):
+def run_form(prob, mesh, ti, nopts, sopts, steps, warmup, timing=False):
+    """Warm-up steps, then `steps` timed steps from rest.  With timing on, every
+    launch of the A-block product inside the timed steps is bracketed by HIP
+    events on the library's stream (the torch current stream)."""
     import torch
     from paper_1809_06350_amd import vms as V
 
@@ -81,6 +85,7 @@ def run_form(prob, mesh, ti, nopts, sopts, steps, warmup):
         prob.roll(st)
         log(f"  warmup step {s}: newton={stats['n_newton']} ms={stats['ms_total']:.1f}")
     st = from_rest()
+    prob.set_timing(timing)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     per = []
@@ -93,12 +98,17 @@ def run_form(prob, mesh, ti, nopts, sopts, steps, warmup):
             f"(asm {stats['ms_assemble']:.1f}, solve {stats['ms_solve']:.1f})")
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    fp32 = sopts.precision == V.MIXED
+    ktime = prob.kernel_time(fp32=fp32) if timing else (0.0, 0)
+    prob.set_timing(False)
     n_newton = sum(p["n_newton"] for p in per)
-    return {"wall_s": wall, "n_newton": n_newton, "per_step": per, "u": st["u"].clone(), "K": K}
+    return {"wall_s": wall, "n_newton": n_newton, "per_step": per, "u": st["u"].clone(), "K": K,
+            "spmv_A_ms": ktime[0], "spmv_A_launches": ktime[1]}
 
 
-def cpu_baseline(N=16, nu=0.499):
-    """The oracle (NumPy/SciPy, sparse LU) on a 16^3 sample of the workload."""
+def cpu_baseline(N=16, nu=0.499, steps=2):
+    """The oracle (NumPy/SciPy, sparse LU) on a 16^3 sample of the workload:
+    its first `steps` time steps from rest."""
     import numpy as np  # noqa: F401
 
     import synth
@@ -107,16 +117,22 @@ def cpu_baseline(N=16, nu=0.499):
     mesh, mat, ti = synth.cube_case(N, nu=nu, n_steps=10)
     disc = AS.Discretization(mesh, mat)
     t0 = time.perf_counter()
-    st, info = NW.time_step(disc, ti, NW.rest_state(mesh), 0.0, tol_R=1e-8)
+    st, n_newton = NW.rest_state(mesh), 0
+    for s in range(steps):
+        st, info = NW.time_step(disc, ti, st, s * ti.dt, tol_R=1e-8)
+        n_newton += info["n_newton"]
     wall = time.perf_counter() - t0
     threads = os.environ.get("OMP_NUM_THREADS") or os.environ.get("OPENBLAS_NUM_THREADS") or "unset"
-    return {"wall_s": wall, "n_newton": info["n_newton"], "n_unknowns": 4 * mesh.n_nodes,
+    return {"wall_s": wall, "n_newton": n_newton, "steps": steps, "n_unknowns": 4 * mesh.n_nodes,
             "threads_env": threads}
 
 
 def spmv_only(prob, mesh, ti, reps):
-    """Kernel-level run for hardware counters: A-block SpMV on the assembled,
-    scaled first Newton system, and a plain copy of known size."""
+    """Kernel-level run for hardware counters: the A-block SpMV (FP64 and FP32)
+    on the assembled, scaled first Newton system, and a calibration kernel of
+    known traffic: a 1 GiB -> 1 GiB float64 elementwise product (torch), larger
+    than the 256 MB Infinity Cache, so that each dispatch reads and writes
+    2^30 bytes of HBM."""
     import torch
     from paper_1809_06350_amd import vms as V
     st = prob.new_state()
@@ -130,7 +146,7 @@ def spmv_only(prob, mesh, ti, reps):
     n = mesh.n_nodes
     x = torch.randn(n, 3, dtype=torch.float64, device="cuda:0", generator=torch.Generator("cuda:0").manual_seed(1))
     xf = x.float()
-    src = torch.ones(256 << 20, dtype=torch.uint8, device="cuda:0")
+    src = torch.ones(1 << 27, dtype=torch.float64, device="cuda:0")
     dst = torch.empty_like(src)
     torch.cuda.synchronize()
     for _ in range(reps):
@@ -138,19 +154,21 @@ def spmv_only(prob, mesh, ti, reps):
     for _ in range(reps):
         prob.spmv(K32, V.OP_A, xf, True)
     for _ in range(reps):
-        dst.copy_(src)
+        torch.mul(src, 1.0, out=dst)
     torch.cuda.synchronize()
     t64 = time_spmv(prob, K32, V.OP_A, x, False)
     t32 = time_spmv(prob, K32, V.OP_A, xf, True)
-    print(json.dumps({"spmv_only": True, "n": n, "nnzb": prob.nnzb, "copy_bytes": src.numel(),
-                      "bytes_fp64": spmv_A_bytes(n, prob.nnzb, 8), "us_fp64": t64 * 1e6,
-                      "bytes_fp32": spmv_A_bytes(n, prob.nnzb, 4), "us_fp32": t32 * 1e6}), flush=True)
+    nz = int(prob.host["row_len"].sum())
+    print(json.dumps({"spmv_only": True, "n": n, "nnzb": nz, "nnzb_slots": prob.nnzb,
+                      "calibration_bytes_each_way": src.numel() * 8,
+                      "bytes_fp64": spmv_A_bytes(n, nz, 8), "us_fp64": t64 * 1e6,
+                      "bytes_fp32": spmv_A_bytes(n, nz, 4), "us_fp32": t32 * 1e6}), flush=True)
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--size", type=int, default=64)
     ap.add_argument("--nu", type=float, default=0.499)
@@ -162,6 +180,9 @@ def main():
     ap.add_argument("--orth", default="cgs1", choices=["cgs2", "cgs1", "cgs_ifneeded", "mgs"],
                     help="Arnoldi orthogonalisation of every Krylov level")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--kernel-timing", action="store_true",
+                    help="also event-time every A-block product launch inside the timed steps (each launch then "
+                         "carries start/stop events, which lengthens it and the steps by the event overhead)")
     ap.add_argument("--spmv-only", type=int, default=0,
                     help="only launch the A-block SpMV (FP64 and FP32) this many times each on the first "
                          "Newton system, plus a 256 MiB device copy as the counter calibration kernel")
@@ -179,7 +200,7 @@ def main():
     mesh, mat, ti = synth.cube_case(N, nu=args.nu, n_steps=10)
     log(f"cube {N}^3: nodes={mesh.n_nodes} tets={mesh.n_tets}")
     prob = V.Problem(mesh, mat, "cuda:0")
-    n, nnzb = mesh.n_nodes, prob.nnzb
+    n, nnzb = mesh.n_nodes, int(prob.host["row_len"].sum())   # real blocks (slots: prob.nnzb)
     nopts = V.newton_opts(tol_R=1e-8, l_max=20)
     mt = [float(x) for x in args.mixed_tol.split(",")]
     if args.spmv_only:
@@ -196,13 +217,18 @@ def main():
     results = {}
     for name in args.forms.split(","):
         log(f"form {name}")
-        results[name] = run_form(prob, mesh, ti, nopts, forms[name], args.steps, args.warmup)
+        results[name] = run_form(prob, mesh, ti, nopts, forms[name], args.steps, args.warmup,
+                                 timing=args.kernel_timing)
 
     primary = "fp64" if "fp64" in results else list(results)[0]
     r = results[primary]
     value = r["n_newton"] / r["wall_s"]
 
-    # dominant kernel: the 3x3 block SpMV of the A-level GMRES (inner + intermediate)
+    # dominant kernel: the 3x3 block SpMV of the A-level GMRES (inner + intermediate), on the matrix of the
+    # workload's last Newton system: its average duration over 50 back-to-back launches between two HIP
+    # events on the library's stream (the torch current stream).  With --kernel-timing every launch inside
+    # the timed steps is event-timed as well and reported beside it (that figure includes the per-launch
+    # event overhead).
     K = r["K"]
     x64 = torch.randn(n, 3, dtype=torch.float64, device="cuda:0", generator=torch.Generator("cuda:0").manual_seed(1))
     t64 = time_spmv(prob, K, V.OP_A, x64, False)
@@ -210,20 +236,30 @@ def main():
     roof = {"bound": "hbm", "kernel": "k_spmv_A<double,double>", "achieved": by64 / t64 / 1e9,
             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": by64 / t64 / 1e9 / HBM_PEAK_GBS,
             "traffic": pmc_traffic("traffic_bytes_fp64") if N == 64 else None,
-            "bytes_per_launch": by64, "us_per_launch": t64 * 1e6}
+            "bytes_per_launch": by64, "us_per_launch": t64 * 1e6,
+            "timing": "HIP events around 50 back-to-back launches on the last Newton system of the timed steps"}
     extra = {}
+    if r["spmv_A_launches"] > 0:
+        t_in = r["spmv_A_ms"] * 1e-3 / r["spmv_A_launches"]
+        extra["spmv_A_in_steps"] = {"us_per_launch": t_in * 1e6, "GB/s": by64 / t_in / 1e9,
+                                    "launches": r["spmv_A_launches"],
+                                    "note": "start/stop events of every working launch in the timed steps"}
+    first = r["per_step"][0]
+    extra["first_step"] = {"ms": first["ms_total"], "n_newton": first["n_newton"],
+                           "ms_per_newton": first["ms_total"] / max(first["n_newton"], 1)}
     if "mixed" in results:
-        Km = results["mixed"]["K"]
-        t32 = time_spmv(prob, Km, V.OP_A, x64.float(), True)
-        by32 = spmv_A_bytes(n, nnzb, 4)
-        extra["spmv_A_fp32"] = {"GB/s": by32 / t32 / 1e9, "us_per_launch": t32 * 1e6, "bytes_per_launch": by32,
-                                "frac_hbm": by32 / t32 / 1e9 / HBM_PEAK_GBS}
         rm = results["mixed"]
+        by32 = spmv_A_bytes(n, nnzb, 4)
+        t32 = time_spmv(prob, rm["K"], V.OP_A, x64.float(), True)
+        extra["spmv_A_fp32"] = {"GB/s": by32 / t32 / 1e9, "us_per_launch": t32 * 1e6, "bytes_per_launch": by32,
+                                "frac_hbm": by32 / t32 / 1e9 / HBM_PEAK_GBS,
+                                "traffic": pmc_traffic("traffic_bytes_fp32") if N == 64 else None}
         u64 = results.get("fp64", rm)["u"]
         err = float((rm["u"] - u64).norm() / u64.norm()) if "fp64" in results else None
         extra["mixed"] = {"newton_per_s": rm["n_newton"] / rm["wall_s"],
                           "ms_per_newton": 1e3 * rm["wall_s"] / rm["n_newton"],
                           "ms_per_step": 1e3 * rm["wall_s"] / args.steps,
+                          "first_step_ms": rm["per_step"][0]["ms_total"],
                           "speedup_vs_fp64": (r["wall_s"] / rm["wall_s"]) if "fp64" in results else None,
                           "u_rel_err_vs_fp64": err}
     for name, rr in results.items():
@@ -237,6 +273,7 @@ def main():
            "data": "synthetic",
            "config": {"workload": f"cube{N}^3 Kuhn tets, nu={args.nu}, neo-Hookean, dt=1e-3, Newton/FGMRES 1e-8",
                       "nodes": n, "tets": mesh.n_tets, "unknowns": 4 * n, "nnzb": nnzb,
+                      "block_slots": prob.nnzb,
                       "shat_degree": args.shat_degree, "shat_ratio": args.shat_ratio, "orth": args.orth,
                       "parallelism": "single GPU"},
            "roofline": roof}
@@ -247,9 +284,9 @@ def main():
         rate16 = cb["n_newton"] / cb["wall_s"]
         out["cpu_baseline"] = {"value": rate16 * cb["n_unknowns"] / (4 * n), "unit": "newton_steps/s",
                                "cores": 1, "kind": "oracle",
-                               "sample": f"one time step of the 16^3 cube ({cb['n_unknowns']} unknowns, "
-                                         f"{cb['n_newton']} Newton its, {cb['wall_s']:.1f} s), scaled linearly "
-                                         f"by unknowns to {N}^3; SuperLU single-threaded, "
+                               "sample": f"the first {cb['steps']} time steps of the 16^3 cube ({cb['n_unknowns']} "
+                                         f"unknowns, {cb['n_newton']} Newton its, {cb['wall_s']:.1f} s), scaled "
+                                         f"linearly by unknowns to {N}^3; SuperLU single-threaded, "
                                          f"OMP/OPENBLAS threads={cb['threads_env']}"}
     print(json.dumps(out), flush=True)
 

@@ -26,8 +26,11 @@
  *    node-interleaved, velocity vectors [n][3], pressure vectors [n].
  *  - Block values are stored entry-major over the shared node-graph pattern:
  *    A[9][nnzb] (row-major 3x3 entry e = 3*r + c), B[3][nnzb], C[3][nnzb],
- *    D[nnzb]; block b of row i couples node i to node col[b].
- *  - Indices are int32 (nnzb < 2^31, n_tets <= VMS_MAX_TETS so that the
+ *    D[nnzb]; block b of row i couples node i to node col[b].  Rows have W
+ *    fixed slots (slot_width, a multiple of 16): row i owns b = W*i + s,
+ *    s < W, nnzb = W*n; its row_len[i] real blocks come first (sorted
+ *    columns), the other slots are padding (column i, values zero).
+ *  - Indices are int32 (nnzb = W n < 2^31, n_tets <= VMS_MAX_TETS so that the
  *    16 element-local pairs of every element are numbered in int32).
  *  - A context is not thread-safe; use one per stream.
  */
@@ -94,7 +97,8 @@ typedef struct {
 
 typedef struct {
   int32_t n_nodes, n_tets, n_bfaces;
-  int64_t nnzb;
+  int32_t slot_width;       /* W: block slots per row (multiple of 16) */
+  int64_t nnzb;             /* W * n_nodes */
   const double *X;          /* [n][3] reference coordinates */
   const int32_t *tets;      /* [m][4] positively oriented */
   const int32_t *bfaces;    /* [f][3] loaded boundary triangles (may be NULL if f = 0) */
@@ -102,8 +106,7 @@ typedef struct {
   const uint8_t *dir_mask;  /* [n][4] 1 = Dirichlet on (v_x, v_y, v_z, p) */
   const double *dir_vel;    /* [n][3] prescribed velocity of Dirichlet components */
   const double *fibre;      /* [m][2][3] unit fibre directions (HGO) or NULL */
-  const int32_t *row_ptr;   /* [n+1] pattern from vms_setup_build */
-  const int32_t *col;       /* [nnzb] */
+  const int32_t *col;       /* [nnzb] pattern from vms_setup_build */
   const int32_t *tpos;      /* [nnzb] position of the transposed block */
   const int32_t *diag_pos;  /* [n] */
   const int32_t *blk_src_ptr; /* [nnzb+1] contributions of each block ... */
@@ -175,22 +178,43 @@ void vms_ctx_destroy(vms_ctx *ctx);
 /* Message of the last non-OK status on ctx (never NULL). */
 const char *vms_last_error(const vms_ctx *ctx);
 
+/* Launch timing of the A-block product, the solver's dominant kernel (a
+ * measurement aid for the HBM roofline of its products).  With enable != 0
+ * every launch of it -- inside vms_solve_scaled / vms_step (intermediate and
+ * inner A-levels) and from vms_spmv(VMS_OP_A) -- carries a start and a stop
+ * HIP event that the dispatch itself records (hipExtLaunchKernelGGL: the
+ * kernel's own begin and end on the context stream), and the kernel sets a
+ * per-launch device flag when it does work (launches enqueued past a level's
+ * convergence return at once and are not counted).
+ * Enabling or disabling resets the counts; the first enable allocates a
+ * 512 KB device flag array.  [sync] */
+int vms_ctx_set_timing(vms_ctx *ctx, int enable);
+/* Sum of the event-timed durations (ms) and number of the counted launches
+ * since the last call or reset, kind 0 = FP64 product, 1 = FP32 product;
+ * resets that kind's counts.  At most 65536 launches per kind are recorded
+ * between two calls.  [sync] */
+int vms_ctx_kernel_time(vms_ctx *ctx, int kind, double *ms_total, int64_t *launches);
+
 /* ---- setup (host, integer work) ---------------------------------------- */
 
 /* Size of the node-graph block pattern of the P1 tangent (every pair of
- * nodes sharing a tetrahedron couples, section 3.1).  tets: HOST [m][4].
- * VMS_ERR_ARG on an out-of-range node or n_tets > VMS_MAX_TETS. */
-int vms_setup_sizes(int32_t n_nodes, int32_t n_tets, const int32_t *tets, int64_t *nnzb);
+ * nodes sharing a tetrahedron couples, section 3.1): *slot_width = W (the
+ * longest row rounded up to a multiple of 16), *nnzb = W * n_nodes.  tets:
+ * HOST [m][4].  VMS_ERR_ARG on an out-of-range node, n_tets > VMS_MAX_TETS
+ * or W * n_nodes >= 2^31. */
+int vms_setup_sizes(int32_t n_nodes, int32_t n_tets, const int32_t *tets, int64_t *nnzb,
+                    int32_t *slot_width);
 
-/* Build, into HOST arrays sized by vms_setup_sizes: row_ptr[n+1], col[nnzb]
- * (sorted within a row, diagonal included), tpos[nnzb] (position of the
- * transposed block), diag_pos[n], the block contribution lists
+/* Build, into HOST arrays sized by vms_setup_sizes: row_len[n], col[nnzb]
+ * (slot layout above), tpos[nnzb] (position of the transposed block; a
+ * padding slot maps to itself), diag_pos[n], the block contribution lists
  * blk_src_ptr[nnzb+1], blk_src[16m] (every element-local pair e*16 + a*4 + b
- * under the block (tets[e][a], tets[e][b]), in increasing e), and node ->
- * loaded-face lists nf_ptr[n+1], nf_face[3f] (bfaces: HOST [f][3]). */
+ * under the block (tets[e][a], tets[e][b]), in increasing e; padding slots
+ * have none), and node -> loaded-face lists nf_ptr[n+1], nf_face[3f]
+ * (bfaces: HOST [f][3]). */
 int vms_setup_build(int32_t n_nodes, int32_t n_tets, const int32_t *tets,
                     int32_t n_bfaces, const int32_t *bfaces,
-                    int32_t *row_ptr, int32_t *col, int32_t *tpos, int32_t *diag_pos,
+                    int32_t *row_len, int32_t *col, int32_t *tpos, int32_t *diag_pos,
                     int32_t *blk_src_ptr, int32_t *blk_src, int32_t *nf_ptr, int32_t *nf_face);
 
 /* ---- assembly (section 3.3 steps 1-4; consistent-linearization appendix) - */

@@ -20,10 +20,11 @@ class TimeInt(C.Structure):
 
 
 class Mesh(C.Structure):
-    _fields_ = [("n_nodes", C.c_int32), ("n_tets", C.c_int32), ("n_bfaces", C.c_int32), ("nnzb", C.c_int64),
+    _fields_ = [("n_nodes", C.c_int32), ("n_tets", C.c_int32), ("n_bfaces", C.c_int32), ("slot_width", C.c_int32),
+                ("nnzb", C.c_int64),
                 ("X", C.c_void_p), ("tets", C.c_void_p), ("bfaces", C.c_void_p), ("traction", C.c_void_p),
                 ("dir_mask", C.c_void_p), ("dir_vel", C.c_void_p), ("fibre", C.c_void_p),
-                ("row_ptr", C.c_void_p), ("col", C.c_void_p), ("tpos", C.c_void_p), ("diag_pos", C.c_void_p),
+                ("col", C.c_void_p), ("tpos", C.c_void_p), ("diag_pos", C.c_void_p),
                 ("blk_src_ptr", C.c_void_p), ("blk_src", C.c_void_p), ("nf_ptr", C.c_void_p),
                 ("nf_face", C.c_void_p)]
 
@@ -79,7 +80,9 @@ SIGNATURES = {
     "vms_ctx_create": (C.c_int, [P(C.c_void_p), C.c_int, C.c_void_p]),
     "vms_ctx_destroy": (None, [C.c_void_p]),
     "vms_last_error": (C.c_char_p, [C.c_void_p]),
-    "vms_setup_sizes": (C.c_int, [C.c_int32, C.c_int32, C.c_void_p, P(C.c_int64)]),
+    "vms_ctx_set_timing": (C.c_int, [C.c_void_p, C.c_int]),
+    "vms_ctx_kernel_time": (C.c_int, [C.c_void_p, C.c_int, P(C.c_double), P(C.c_int64)]),
+    "vms_setup_sizes": (C.c_int, [C.c_int32, C.c_int32, C.c_void_p, P(C.c_int64), P(C.c_int32)]),
     "vms_setup_build": (C.c_int, [C.c_int32, C.c_int32, C.c_void_p, C.c_int32, C.c_void_p] + [C.c_void_p] * 8),
     "vms_nodal_load": (C.c_int, [C.c_void_p, P(Mesh), C.c_void_p]),
     "vms_predictor": (C.c_int, [C.c_void_p, P(Mesh), P(TimeInt), P(State)]),

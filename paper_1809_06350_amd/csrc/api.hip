@@ -50,10 +50,64 @@ extern "C" int vms_ctx_create(vms_ctx **out, int device, void *stream) {
 extern "C" void vms_ctx_destroy(vms_ctx *ctx) {
   if (!ctx) return;
   (void)hipStreamSynchronize(ctx->stream);
+  for (int k = 0; k < 2; ++k)
+    for (hipEvent_t e : ctx->tev[k]) (void)hipEventDestroy(e);
+  if (ctx->tflag) (void)hipFree(ctx->tflag);
   if (ctx->dstat) (void)hipFree(ctx->dstat);
   if (ctx->h_i) (void)hipHostFree(ctx->h_i);
   if (ctx->h_d) (void)hipHostFree(ctx->h_d);
   delete ctx;
+}
+
+// ---- launch timing of the A-block product --------------------------------------
+vms_timed vms_timer_next(vms_ctx *ctx, int kind) {
+  vms_timed t;
+  if (!ctx->timing || ctx->tused[kind] >= VMS_MAX_TIMED) return t;
+  const int i = ctx->tused[kind];
+  auto &ev = ctx->tev[kind];
+  while ((int)ev.size() < 2 * (i + 1)) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return t;
+    ev.push_back(e);
+  }
+  ctx->tused[kind] = i + 1;
+  t.slot = i;
+  t.worked = ctx->tflag + (int64_t)kind * VMS_MAX_TIMED + i;
+  t.e0 = ev[2 * i];
+  t.e1 = ev[2 * i + 1];
+  return t;
+}
+
+extern "C" int vms_ctx_set_timing(vms_ctx *ctx, int enable) {
+  if (!ctx) return VMS_ERR_ARG;
+  VMS_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  if (enable && !ctx->tflag) VMS_HIP(ctx, hipMalloc((void **)&ctx->tflag, 2 * VMS_MAX_TIMED * sizeof(int)));
+  if (ctx->tflag) VMS_HIP(ctx, hipMemset(ctx->tflag, 0, 2 * VMS_MAX_TIMED * sizeof(int)));
+  ctx->tused[0] = ctx->tused[1] = 0;
+  ctx->timing = enable != 0;
+  return VMS_OK;
+}
+
+extern "C" int vms_ctx_kernel_time(vms_ctx *ctx, int kind, double *ms_total, int64_t *launches) {
+  if (!ctx || kind < 0 || kind > 1 || !ms_total || !launches) return VMS_ERR_ARG;
+  *ms_total = 0.0;
+  *launches = 0;
+  VMS_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  const int used = ctx->tused[kind];
+  if (used == 0) return VMS_OK;
+  std::vector<int> flag(used);
+  VMS_HIP(ctx, hipMemcpy(flag.data(), ctx->tflag + (int64_t)kind * VMS_MAX_TIMED, used * sizeof(int),
+                         hipMemcpyDeviceToHost));
+  for (int i = 0; i < used; ++i) {
+    if (!flag[i]) continue;   // the level had converged: the kernel returned at once
+    float ms = 0.0f;
+    VMS_HIP(ctx, hipEventElapsedTime(&ms, ctx->tev[kind][2 * i], ctx->tev[kind][2 * i + 1]));
+    *ms_total += ms;
+    ++*launches;
+  }
+  VMS_HIP(ctx, hipMemset(ctx->tflag + (int64_t)kind * VMS_MAX_TIMED, 0, used * sizeof(int)));
+  ctx->tused[kind] = 0;
+  return VMS_OK;
 }
 
 extern "C" const char *vms_last_error(const vms_ctx *ctx) {

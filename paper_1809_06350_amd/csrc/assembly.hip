@@ -633,7 +633,7 @@ __global__ void k_diagW(int n, const int32_t *diag_pos, int64_t nnzb, const doub
 
 // K <- W K W with Dirichlet rows/columns replaced by the identity
 __global__ void __launch_bounds__(VMS_BLOCK)
-k_scale_blocks(int n, int64_t nnzb, const int32_t *rp, const int32_t *col, const uint8_t *dir,
+k_scale_blocks(int n, int64_t nnzb, int SW, const int32_t *col, const int32_t *diag_pos, const uint8_t *dir,
                const double *W, double *A, double *B, double *C, double *D, float *A32, float *B32,
                float *C32, float *D32) {
   const int lane = threadIdx.x & 15;
@@ -641,11 +641,12 @@ k_scale_blocks(int n, int64_t nnzb, const int32_t *rp, const int32_t *col, const
   if (row >= n) return;
   const uint8_t *di = dir + 4 * (int64_t)row;
   const double *Wi = W + 4 * (int64_t)row;
-  for (int b = rp[row] + lane; b < rp[row + 1]; b += 16) {
+  const int bd = diag_pos[row];
+  for (int b = SW * row + lane; b < SW * row + SW; b += 16) {   // padding slots stay zero
     const int j = col[b];
     const uint8_t *dj = dir + 4 * (int64_t)j;
     const double *Wj = W + 4 * (int64_t)j;
-    const bool same = (j == row);
+    const bool same = (b == bd);
     for (int r = 0; r < 3; ++r)
       for (int c = 0; c < 3; ++c) {
         const int64_t k = (3 * r + c) * nnzb + b;
@@ -725,7 +726,8 @@ vms_ga vms_genalpha(const vms_timeint *ti) {
 
 int vms_check_mesh(vms_ctx *ctx, const vms_mesh *m) {
   if (!m || m->n_nodes <= 0 || m->n_tets < 0 || m->n_tets > VMS_MAX_TETS || m->nnzb <= 0 || !m->X || !m->tets ||
-      !m->dir_mask || !m->row_ptr || !m->col || !m->tpos || !m->diag_pos || !m->blk_src_ptr ||
+      !m->dir_mask || m->slot_width < 16 || (m->slot_width & 15) || m->nnzb != (int64_t)m->slot_width * m->n_nodes ||
+      !m->col || !m->tpos || !m->diag_pos || !m->blk_src_ptr ||
       (m->n_tets > 0 && !m->blk_src))
     return vms_set_error(ctx, VMS_ERR_ARG, "incomplete mesh description");
   return VMS_OK;
@@ -840,7 +842,7 @@ int vms_launch_prepare(vms_ctx *ctx, const vms_mesh *mesh, vms_matrix *K, const 
   hipLaunchKernelGGL(k_diagW, dim3(grid1(n)), dim3(VMS_BLOCK), 0, ctx->stream, n, mesh->diag_pos, nnzb, K->A,
                      K->D, mesh->dir_mask, eps_diag, K->W);
   hipLaunchKernelGGL(k_scale_blocks, dim3((n + 15) / 16), dim3(VMS_BLOCK), 0, ctx->stream, n, nnzb,
-                     mesh->row_ptr, mesh->col, mesh->dir_mask, K->W, K->A, K->B, K->C, K->D,
+                     mesh->slot_width, mesh->col, mesh->diag_pos, mesh->dir_mask, K->W, K->A, K->B, K->C, K->D,
                      mirror32 ? K->A32 : nullptr, mirror32 ? K->B32 : nullptr, mirror32 ? K->C32 : nullptr,
                      mirror32 ? K->D32 : nullptr);
   if (rhs)

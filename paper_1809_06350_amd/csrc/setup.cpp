@@ -1,8 +1,13 @@
 // Host-side setup of the node-graph block pattern (integer work only).
 //
 // The tangent [[A, B], [C, D]] of the P1 discretisation couples every pair of
-// nodes that share a tetrahedron, so one CSR pattern over nodes (row_ptr,
-// col, sorted columns, diagonal included) serves all four value arrays.
+// nodes that share a tetrahedron, so one block pattern over nodes serves all
+// four value arrays.  Rows are stored in fixed-width slots: row i owns blocks
+// b = W*i + s, s < W, with W the largest row length rounded up to a multiple
+// of 16; its row_len[i] real blocks come first with sorted columns (diagonal
+// included), the padding slots hold column i, zero values and no
+// contributions.  Products then find a row without reading row pointers, and
+// every row starts on a 16-block boundary.
 // Besides the pattern this file builds
 //   tpos[b]        position of block (j, i) for the block b = (i, j),
 //   diag_pos[i]    position of block (i, i),
@@ -67,21 +72,31 @@ inline int32_t find_block(const Graph &g, int32_t i, int32_t j) {
 
 }  // namespace
 
-extern "C" int vms_setup_sizes(int32_t n_nodes, int32_t n_tets, const int32_t *tets, int64_t *nnzb) {
-  if (n_nodes <= 0 || n_tets < 0 || (!tets && n_tets > 0) || !nnzb) return VMS_ERR_ARG;
+static int32_t slot_width(const Graph &g, int32_t n) {
+  int32_t mx = 1;
+  for (int32_t i = 0; i < n; ++i) mx = std::max(mx, g.row_ptr[i + 1] - g.row_ptr[i]);
+  return 16 * ((mx + 15) / 16);
+}
+
+extern "C" int vms_setup_sizes(int32_t n_nodes, int32_t n_tets, const int32_t *tets, int64_t *nnzb,
+                               int32_t *slot_width_out) {
+  if (n_nodes <= 0 || n_tets < 0 || (!tets && n_tets > 0) || !nnzb || !slot_width_out) return VMS_ERR_ARG;
   if ((int64_t)n_tets > VMS_MAX_TETS) return VMS_ERR_ARG;
   for (int64_t k = 0; k < 4 * (int64_t)n_tets; ++k)
     if (tets[k] < 0 || tets[k] >= n_nodes) return VMS_ERR_ARG;
   Graph g = build_graph(n_nodes, n_tets, tets);
-  *nnzb = (int64_t)g.col.size();
+  const int32_t W = slot_width(g, n_nodes);
+  if ((int64_t)W * n_nodes >= ((int64_t)1 << 31)) return VMS_ERR_ARG;
+  *slot_width_out = W;
+  *nnzb = (int64_t)W * n_nodes;
   return VMS_OK;
 }
 
 extern "C" int vms_setup_build(int32_t n_nodes, int32_t n_tets, const int32_t *tets,
                                int32_t n_bfaces, const int32_t *bfaces,
-                               int32_t *row_ptr, int32_t *col, int32_t *tpos, int32_t *diag_pos,
+                               int32_t *row_len, int32_t *col, int32_t *tpos, int32_t *diag_pos,
                                int32_t *blk_src_ptr, int32_t *blk_src, int32_t *nf_ptr, int32_t *nf_face) {
-  if (n_nodes <= 0 || n_tets < 0 || (int64_t)n_tets > VMS_MAX_TETS || !row_ptr || !col || !tpos || !diag_pos ||
+  if (n_nodes <= 0 || n_tets < 0 || (int64_t)n_tets > VMS_MAX_TETS || !row_len || !col || !tpos || !diag_pos ||
       !blk_src_ptr || (n_tets > 0 && (!tets || !blk_src)) || !nf_ptr || (n_bfaces > 0 && (!bfaces || !nf_face)))
     return VMS_ERR_ARG;
   for (int64_t k = 0; k < 4 * (int64_t)n_tets; ++k)
@@ -89,18 +104,35 @@ extern "C" int vms_setup_build(int32_t n_nodes, int32_t n_tets, const int32_t *t
   for (int64_t k = 0; k < 3 * (int64_t)n_bfaces; ++k)
     if (bfaces[k] < 0 || bfaces[k] >= n_nodes) return VMS_ERR_ARG;
   Graph g = build_graph(n_nodes, n_tets, tets);
-  const int64_t nnzb = (int64_t)g.col.size();
-  std::memcpy(row_ptr, g.row_ptr.data(), sizeof(int32_t) * (n_nodes + 1));
-  std::memcpy(col, g.col.data(), sizeof(int32_t) * nnzb);
+  const int32_t W = slot_width(g, n_nodes);
+  if ((int64_t)W * n_nodes >= ((int64_t)1 << 31)) return VMS_ERR_ARG;
+  const int64_t nnzb = (int64_t)W * n_nodes;
+  // slot position of the CSR block k of row i
+  auto slot = [&](int32_t i, int32_t k) { return (int32_t)((int64_t)W * i + (k - g.row_ptr[i])); };
   for (int32_t i = 0; i < n_nodes; ++i) {
-    diag_pos[i] = find_block(g, i, i);
-    for (int32_t b = g.row_ptr[i]; b < g.row_ptr[i + 1]; ++b) tpos[b] = find_block(g, g.col[b], i);
+    const int32_t len = g.row_ptr[i + 1] - g.row_ptr[i];
+    row_len[i] = len;
+    for (int32_t s = 0; s < W; ++s) {
+      const int64_t b = (int64_t)W * i + s;
+      if (s < len) {
+        col[b] = g.col[g.row_ptr[i] + s];
+        const int32_t j = col[b];
+        tpos[b] = slot(j, find_block(g, j, i));
+      } else {
+        col[b] = i;
+        tpos[b] = (int32_t)b;
+      }
+    }
+    diag_pos[i] = slot(i, find_block(g, i, i));
   }
   // block <- (element, local pair): counting sort of the 16 m pairs by block, element order kept
   std::vector<int32_t> eb(16 * (size_t)n_tets);
   for (int64_t e = 0; e < n_tets; ++e)
     for (int a = 0; a < 4; ++a)
-      for (int b = 0; b < 4; ++b) eb[16 * e + 4 * a + b] = find_block(g, tets[4 * e + a], tets[4 * e + b]);
+      for (int b = 0; b < 4; ++b) {
+        const int32_t i = tets[4 * e + a];
+        eb[16 * e + 4 * a + b] = slot(i, find_block(g, i, tets[4 * e + b]));
+      }
   std::fill(blk_src_ptr, blk_src_ptr + nnzb + 1, 0);
   for (size_t k = 0; k < eb.size(); ++k) blk_src_ptr[eb[k] + 1]++;
   for (int64_t b = 0; b < nnzb; ++b) blk_src_ptr[b + 1] += blk_src_ptr[b];

@@ -546,13 +546,13 @@ __global__ void k_bj33_setup(int n, const int32_t *diag_pos, int64_t nnzb, const
 
 // 1 / diag(S^),  S^_ii = D_ii - sum_k sum_c C_ik,c B_ki,c / A_kk,cc
 template <typename T>
-__global__ void k_shat_diag(int n, const int32_t *rp, const int32_t *col, const int32_t *tpos,
+__global__ void k_shat_diag(int n, int W, const int32_t *col, const int32_t *tpos,
                             const int32_t *diag_pos, int64_t nnzb, const double *A, const double *B,
                             const double *C, const double *D, T *sdinv) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   double s = D[diag_pos[i]];
-  for (int b = rp[i]; b < rp[i + 1]; ++b) {
+  for (int b = W * i; b < W * i + W; ++b) {   // padding slots hold zeros
     const int k = col[b];
     const int64_t dk = diag_pos[k], bt = tpos[b];
     for (int c = 0; c < 3; ++c) {
@@ -579,10 +579,13 @@ __global__ void k_dAinv(int n, const int32_t *diag_pos, int64_t nnzb, const doub
 // t = diag(A)^-1 (B x)
 template <typename T>
 __global__ void __launch_bounds__(VMS_BLOCK)
-k_shat_bt(int n, int64_t nnzb, const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
+k_shat_bt(int n, int64_t nnzb, int W, const int32_t *__restrict__ col,
           const T *__restrict__ B, const T *__restrict__ dAinv, const T *__restrict__ x, T *t) {
   const int *done = nullptr;
   SPMV_PROLOGUE
+  // the row's own values are loaded before the product so that their latency overlaps it
+  const int64_t o = 3 * (int64_t)(act ? row : 0);
+  const double di0 = ld(dAinv, o), di1 = ld(dAinv, o + 1), di2 = ld(dAinv, o + 2);
   double a0 = 0, a1 = 0, a2 = 0;
   for (int b = b0 + lane; b < b1; b += 16) {
     const double xp = ld(x, col[b]);
@@ -594,10 +597,9 @@ k_shat_bt(int n, int64_t nnzb, const int32_t *__restrict__ rp, const int32_t *__
   a1 = reduce16(a1);
   a2 = reduce16(a2);
   if (act && lane == 0) {
-    const int64_t o = 3 * (int64_t)row;
-    t[o] = (T)(a0 * ld(dAinv, o));
-    t[o + 1] = (T)(a1 * ld(dAinv, o + 1));
-    t[o + 2] = (T)(a2 * ld(dAinv, o + 2));
+    t[o] = (T)(a0 * di0);
+    t[o + 1] = (T)(a1 * di1);
+    t[o + 2] = (T)(a2 * di2);
   }
 }
 
@@ -620,11 +622,21 @@ __device__ __forceinline__ void cheb_coef(const double *lam, double ratio, int k
 //                            dn = rho1 rho0 d + 2 rho1/delta diag(S^)^-1 r
 template <typename T, int MODE>
 __global__ void __launch_bounds__(VMS_BLOCK)
-k_shat_dc(int n, int64_t nnzb, const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
+k_shat_dc(int n, int64_t nnzb, int W, const int32_t *__restrict__ col,
           const T *__restrict__ C, const T *__restrict__ D, const T *__restrict__ d, const T *__restrict__ t,
           const T *__restrict__ sdinv, T *y, T *x, T *r, const double *lam, double ratio, int k) {
   const int *done = nullptr;
   SPMV_PROLOGUE
+  // the row's own values and the Chebyshev scalars ahead of the product (latency overlap)
+  const int ro = act ? row : 0;
+  const double sdi = ld(sdinv, ro);
+  double di = 0.0, xi = 0.0, ri = 0.0, rho0 = 0.0, rho1 = 0.0, delta = 1.0, theta = 1.0;
+  if (MODE == 1) {
+    di = ld(d, ro);
+    xi = ld(x, ro);
+    ri = ld(r, ro);
+    cheb_coef(lam, ratio, k, rho0, rho1, delta, theta);
+  }
   double a = 0.0, dd = 0.0;
   for (int b = b0 + lane; b < b1; b += 16) {
     const int64_t c = col[b];
@@ -637,15 +649,12 @@ k_shat_dc(int n, int64_t nnzb, const int32_t *__restrict__ rp, const int32_t *__
   if (act && lane == 0) {
     const double sv = dd - a;
     if (MODE == 0) {
-      y[row] = (T)(ld(sdinv, row) * sv);
+      y[row] = (T)(sdi * sv);
     } else {
-      double rho0, rho1, delta, theta;
-      cheb_coef(lam, ratio, k, rho0, rho1, delta, theta);
-      const double di = ld(d, row);
-      x[row] = (T)(ld(x, row) + di);
-      const double rn = ld(r, row) - sv;
+      x[row] = (T)(xi + di);
+      const double rn = ri - sv;
       r[row] = (T)rn;
-      y[row] = (T)(rho1 * rho0 * di + 2.0 * rho1 / delta * ld(sdinv, row) * rn);
+      y[row] = (T)(rho1 * rho0 * di + 2.0 * rho1 / delta * sdi * rn);
     }
   }
 }
@@ -717,6 +726,21 @@ __global__ void k_clear_ints(int *p, int n) {
 }
 
 inline int grid1(int64_t n) { return (int)((n + VMS_BLOCK - 1) / VMS_BLOCK); }
+
+// y = A x (A-block product, the solver's dominant kernel).  With launch timing
+// on, the launch carries start/stop events taken by the dispatch itself.
+template <typename T>
+void launch_spmv_A(vms_ctx *ctx, const vms_mesh *mesh, const T *A, const T *x, T *y, const int *done) {
+  const dim3 gr(spmv_grid(mesh->n_nodes)), bl(VMS_BLOCK);
+  const vms_timed tm = vms_timer_next(ctx, std::is_same<T, float>::value ? 1 : 0);
+  if (tm.slot >= 0)
+    hipExtLaunchKernelGGL((k_spmv_A<T, T>), gr, bl, 0, ctx->stream, tm.e0, tm.e1, 0, (int)mesh->n_nodes,
+                          (int64_t)mesh->nnzb, (int)mesh->slot_width, mesh->col, A, x, y, (const T *)nullptr, 1.0,
+                          done, tm.worked);
+  else
+    hipLaunchKernelGGL((k_spmv_A<T, T>), gr, bl, 0, ctx->stream, (int)mesh->n_nodes, (int64_t)mesh->nnzb,
+                       (int)mesh->slot_width, mesh->col, A, x, y, (const T *)nullptr, 1.0, done, (int *)nullptr);
+}
 
 // ---- workspace carving -------------------------------------------------------
 struct Carver {
@@ -907,9 +931,9 @@ struct Nested {
     hipLaunchKernelGGL(k_cheb_init<T>, g1, bl, 0, s, n, v, (const T *)sdinv, z, cr, cd0, (const double *)lam, ratio);
     T *d = cd0, *dn = cd1;
     for (int k = 0; k < deg; ++k) {
-      hipLaunchKernelGGL(k_shat_bt<T>, gs, bl, 0, s, n, nnzb, mesh->row_ptr, mesh->col, B, (const T *)dAinv,
+      hipLaunchKernelGGL(k_shat_bt<T>, gs, bl, 0, s, n, nnzb, mesh->slot_width, mesh->col, B, (const T *)dAinv,
                          (const T *)d, ct);
-      hipLaunchKernelGGL((k_shat_dc<T, 1>), gs, bl, 0, s, n, nnzb, mesh->row_ptr, mesh->col, C, D, (const T *)d,
+      hipLaunchKernelGGL((k_shat_dc<T, 1>), gs, bl, 0, s, n, nnzb, mesh->slot_width, mesh->col, C, D, (const T *)d,
                          (const T *)ct, (const T *)sdinv, dn, z, cr, (const double *)lam, ratio, k);
       std::swap(d, dn);
     }
@@ -923,9 +947,9 @@ struct Nested {
     double *part = LS.ctrl + LS.off.part;
     hipLaunchKernelGGL(k_power_init<T>, g1, bl, 0, s, n, px);
     for (int it = 0; it < iters; ++it) {
-      hipLaunchKernelGGL(k_shat_bt<T>, gs, bl, 0, s, n, nnzb, mesh->row_ptr, mesh->col, B, (const T *)dAinv,
+      hipLaunchKernelGGL(k_shat_bt<T>, gs, bl, 0, s, n, nnzb, mesh->slot_width, mesh->col, B, (const T *)dAinv,
                          (const T *)px, ct);
-      hipLaunchKernelGGL((k_shat_dc<T, 0>), gs, bl, 0, s, n, nnzb, mesh->row_ptr, mesh->col, C, D, (const T *)px,
+      hipLaunchKernelGGL((k_shat_dc<T, 0>), gs, bl, 0, s, n, nnzb, mesh->slot_width, mesh->col, C, D, (const T *)px,
                          (const T *)ct, (const T *)sdinv, py, (T *)nullptr, (T *)nullptr, (const double *)nullptr,
                          0.0, 0);
       hipLaunchKernelGGL(k_norm_part<T>, dim3(nb), bl, 0, s, (int64_t)n, (const T *)py, part, (const int *)nullptr);
@@ -941,9 +965,7 @@ struct Nested {
     const int maxit = inner ? o->maxit_I : o->maxit_A;
     int &est = inner ? ctx->est_I : ctx->est_A;
     auto op = [&](int j) -> int {
-      hipLaunchKernelGGL((k_spmv_A<T, T>), dim3(spmv_grid(n)), dim3(VMS_BLOCK), 0, ctx->stream, n, nnzb,
-                         mesh->row_ptr, mesh->col, A, LA.Z + (int64_t)j * LA.nvec, LA.W, (const T *)nullptr, 1.0,
-                         LA.iflag + IF_DONE);
+      launch_spmv_A<T>(ctx, mesh, A, LA.Z + (int64_t)j * LA.nvec, LA.W, LA.iflag + IF_DONE);
       return VMS_OK;
     };
     int st = 0;
@@ -962,13 +984,13 @@ struct Nested {
       if (cheb) cheb_apply(LS.V + (int64_t)j * LS.nvec, z);
       // x-bar = B z
       hipLaunchKernelGGL((k_spmv_B<T, T>), dim3(spmv_grid(n)), dim3(VMS_BLOCK), 0, ctx->stream, n, nnzb,
-                         mesh->row_ptr, mesh->col, B, z, xbar, (const T *)nullptr, 1.0, (const int *)nullptr);
+                         mesh->slot_width, mesh->col, B, z, xbar, (const T *)nullptr, 1.0, (const int *)nullptr);
       // x-tilde = A^-1 x-bar (inner solver)
       int rc = solve_A(xbar, xt, true);
       if (rc) return rc;
       // W = D z - C x-tilde
       hipLaunchKernelGGL((k_spmv_CD<T, T>), dim3(spmv_grid(n)), dim3(VMS_BLOCK), 0, ctx->stream, n, nnzb,
-                         mesh->row_ptr, mesh->col, C, D, xt, z, LS.W, (const T *)nullptr, -1.0, 1.0,
+                         mesh->slot_width, mesh->col, C, D, xt, z, LS.W, (const T *)nullptr, -1.0, 1.0,
                          (const int *)nullptr);
       return VMS_OK;
     };
@@ -989,12 +1011,12 @@ struct Nested {
     const int var = o->precond;
     if (var == VMS_PC_LDU || var == VMS_PC_LOWER) {
       if ((rc = solve_A(rv, xh, false))) return rc;                 // step 1
-      hipLaunchKernelGGL((k_spmv_CD<T, T>), dim3(spmv_grid(n)), dim3(VMS_BLOCK), 0, s, n, nnzb, mesh->row_ptr,
+      hipLaunchKernelGGL((k_spmv_CD<T, T>), dim3(spmv_grid(n)), dim3(VMS_BLOCK), 0, s, n, nnzb, mesh->slot_width,
                          mesh->col, C, D, xh, (const T *)nullptr, rp, rp, -1.0, 0.0, (const int *)nullptr);  // step 2
     }
     if ((rc = solve_S(rp, xp))) return rc;                           // step 3
     if (var == VMS_PC_LDU || var == VMS_PC_UPPER) {
-      hipLaunchKernelGGL((k_spmv_B<T, T>), dim3(spmv_grid(n)), dim3(VMS_BLOCK), 0, s, n, nnzb, mesh->row_ptr,
+      hipLaunchKernelGGL((k_spmv_B<T, T>), dim3(spmv_grid(n)), dim3(VMS_BLOCK), 0, s, n, nnzb, mesh->slot_width,
                          mesh->col, B, xp, rv, rv, -1.0, (const int *)nullptr);  // step 4
       if ((rc = solve_A(rv, xv, false))) return rc;                 // step 5
     } else if (var == VMS_PC_LOWER) {
@@ -1012,7 +1034,7 @@ struct Nested {
   int setup_precond() {
     hipLaunchKernelGGL(k_bj33_setup<T>, dim3(grid1(n)), dim3(VMS_BLOCK), 0, ctx->stream, n, mesh->diag_pos, nnzb,
                        K->A, Minv);
-    hipLaunchKernelGGL(k_shat_diag<T>, dim3(grid1(n)), dim3(VMS_BLOCK), 0, ctx->stream, n, mesh->row_ptr, mesh->col,
+    hipLaunchKernelGGL(k_shat_diag<T>, dim3(grid1(n)), dim3(VMS_BLOCK), 0, ctx->stream, n, mesh->slot_width, mesh->col,
                        mesh->tpos, mesh->diag_pos, nnzb, K->A, K->B, K->C, K->D, sdinv);
     if (o->shat_degree > 0) {
       lam = LS.ctrl + LS.off.scal + 5;
@@ -1090,7 +1112,7 @@ int solve_impl(vms_ctx *ctx, const vms_mesh *mesh, const vms_matrix *K, const do
     int r = ne.apply(L.V + (int64_t)j * L.nvec, L.Z + (int64_t)j * L.nvec);
     if (r) return r;
     hipLaunchKernelGGL(k_spmv_full, dim3(spmv_grid(n)), dim3(VMS_BLOCK), 0, ctx->stream, n, mesh->nnzb,
-                       mesh->row_ptr, mesh->col, K->A, K->B, K->C, K->D, L.Z + (int64_t)j * L.nvec, L.W,
+                       mesh->slot_width, mesh->col, K->A, K->B, K->C, K->D, L.Z + (int64_t)j * L.nvec, L.W,
                        L.iflag + IF_DONE);
     return VMS_OK;
   };
@@ -1163,42 +1185,40 @@ int vms_launch_spmv(vms_ctx *ctx, const vms_mesh *mesh, const vms_matrix *K, int
   const int *nd = nullptr;
   switch (op) {
     case VMS_OP_FULL:
-      hipLaunchKernelGGL(k_spmv_full, gr, bl, 0, s, n, nnzb, mesh->row_ptr, mesh->col, K->A, K->B, K->C, K->D,
+      hipLaunchKernelGGL(k_spmv_full, gr, bl, 0, s, n, nnzb, mesh->slot_width, mesh->col, K->A, K->B, K->C, K->D,
                          (const double *)x, (double *)y, nd);
       break;
     case VMS_OP_A:
       if (fp32)
-        hipLaunchKernelGGL((k_spmv_A<float, float>), gr, bl, 0, s, n, nnzb, mesh->row_ptr, mesh->col, K->A32,
-                           (const float *)x, (float *)y, (const float *)nullptr, 1.0, nd);
+        launch_spmv_A<float>(ctx, mesh, K->A32, (const float *)x, (float *)y, nd);
       else
-        hipLaunchKernelGGL((k_spmv_A<double, double>), gr, bl, 0, s, n, nnzb, mesh->row_ptr, mesh->col, K->A,
-                           (const double *)x, (double *)y, (const double *)nullptr, 1.0, nd);
+        launch_spmv_A<double>(ctx, mesh, K->A, (const double *)x, (double *)y, nd);
       break;
     case VMS_OP_B:
       if (fp32)
-        hipLaunchKernelGGL((k_spmv_B<float, float>), gr, bl, 0, s, n, nnzb, mesh->row_ptr, mesh->col, K->B32,
+        hipLaunchKernelGGL((k_spmv_B<float, float>), gr, bl, 0, s, n, nnzb, mesh->slot_width, mesh->col, K->B32,
                            (const float *)x, (float *)y, (const float *)nullptr, 1.0, nd);
       else
-        hipLaunchKernelGGL((k_spmv_B<double, double>), gr, bl, 0, s, n, nnzb, mesh->row_ptr, mesh->col, K->B,
+        hipLaunchKernelGGL((k_spmv_B<double, double>), gr, bl, 0, s, n, nnzb, mesh->slot_width, mesh->col, K->B,
                            (const double *)x, (double *)y, (const double *)nullptr, 1.0, nd);
       break;
     case VMS_OP_C:
       if (fp32)
-        hipLaunchKernelGGL((k_spmv_CD<float, float>), gr, bl, 0, s, n, nnzb, mesh->row_ptr, mesh->col, K->C32,
+        hipLaunchKernelGGL((k_spmv_CD<float, float>), gr, bl, 0, s, n, nnzb, mesh->slot_width, mesh->col, K->C32,
                            K->D32, (const float *)x, (const float *)nullptr, (float *)y, (const float *)nullptr, 1.0,
                            0.0, nd);
       else
-        hipLaunchKernelGGL((k_spmv_CD<double, double>), gr, bl, 0, s, n, nnzb, mesh->row_ptr, mesh->col, K->C, K->D,
+        hipLaunchKernelGGL((k_spmv_CD<double, double>), gr, bl, 0, s, n, nnzb, mesh->slot_width, mesh->col, K->C, K->D,
                            (const double *)x, (const double *)nullptr, (double *)y, (const double *)nullptr, 1.0,
                            0.0, nd);
       break;
     case VMS_OP_D:
       if (fp32)
-        hipLaunchKernelGGL((k_spmv_CD<float, float>), gr, bl, 0, s, n, nnzb, mesh->row_ptr, mesh->col, K->C32,
+        hipLaunchKernelGGL((k_spmv_CD<float, float>), gr, bl, 0, s, n, nnzb, mesh->slot_width, mesh->col, K->C32,
                            K->D32, (const float *)nullptr, (const float *)x, (float *)y, (const float *)nullptr, 0.0,
                            1.0, nd);
       else
-        hipLaunchKernelGGL((k_spmv_CD<double, double>), gr, bl, 0, s, n, nnzb, mesh->row_ptr, mesh->col, K->C, K->D,
+        hipLaunchKernelGGL((k_spmv_CD<double, double>), gr, bl, 0, s, n, nnzb, mesh->slot_width, mesh->col, K->C, K->D,
                            (const double *)nullptr, (const double *)x, (double *)y, (const double *)nullptr, 0.0,
                            1.0, nd);
       break;

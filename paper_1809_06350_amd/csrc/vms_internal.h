@@ -1,12 +1,14 @@
 // Internal declarations shared by the HIP translation units of libvms.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cstdarg>
 #include <cstdint>
 #include <cstdio>
 #include <string>
+#include <vector>
 
 #include "vms.h"
 
@@ -27,6 +29,8 @@ struct vms_dev_status {
   double part[VMS_MAX_RED_BLOCKS];
 };
 
+#define VMS_MAX_TIMED 65536   // timed launches per kind between two reads
+
 struct vms_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
@@ -35,7 +39,24 @@ struct vms_ctx {
   int32_t *h_i = nullptr;            // pinned host scratch (ints)
   double *h_d = nullptr;             // pinned host scratch (doubles)
   int est_A = 8, est_I = 8, est_S = 8;  // Krylov iteration estimates (batching)
+  // launch timing of the A-block product (vms_ctx_set_timing): per kind (0 FP64, 1 FP32) a pool of
+  // event pairs and a device flag per launch that the kernel sets when it did work
+  bool timing = false;
+  std::vector<hipEvent_t> tev[2];
+  int tused[2] = {0, 0};
+  int *tflag = nullptr;              // device [2][VMS_MAX_TIMED]
 };
+
+// Next timed launch of the A-block product (kind 0 FP64, 1 FP32) when timing
+// is on: the start/stop events that the launch passes to hipExtLaunchKernelGGL
+// (they take the kernel's own start and end times) and its work flag;
+// slot < 0 when timing is off or the pool is full.
+struct vms_timed {
+  int slot = -1;
+  int *worked = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+};
+vms_timed vms_timer_next(vms_ctx *ctx, int kind);
 
 int vms_set_error(vms_ctx *ctx, int code, const char *fmt, ...);
 

@@ -82,17 +82,20 @@ class Problem:
         n, m, f = mesh.n_nodes, mesh.n_tets, int(mesh.bfaces.shape[0])
         tets = np.ascontiguousarray(mesh.tets, dtype=np.int32)
         bfaces = np.ascontiguousarray(mesh.bfaces, dtype=np.int32).reshape(-1, 3)
-        nnzb = C.c_int64()
-        self._check(lib.vms_setup_sizes(n, m, tets.ctypes.data, C.byref(nnzb)), "vms_setup_sizes", ctx=False)
+        nnzb, sw = C.c_int64(), C.c_int32()
+        self._check(lib.vms_setup_sizes(n, m, tets.ctypes.data, C.byref(nnzb), C.byref(sw)), "vms_setup_sizes",
+                    ctx=False)
         nz = nnzb.value
-        h = {"row_ptr": np.zeros(n + 1, np.int32), "col": np.zeros(nz, np.int32), "tpos": np.zeros(nz, np.int32),
+        h = {"row_len": np.zeros(n, np.int32), "col": np.zeros(nz, np.int32), "tpos": np.zeros(nz, np.int32),
              "diag_pos": np.zeros(n, np.int32), "blk_src_ptr": np.zeros(nz + 1, np.int32),
              "blk_src": np.zeros(max(16 * m, 1), np.int32),
              "nf_ptr": np.zeros(n + 1, np.int32), "nf_face": np.zeros(max(3 * f, 1), np.int32)}
         self._check(lib.vms_setup_build(n, m, tets.ctypes.data, f, bfaces.ctypes.data if f else None,
-                                        *(h[k].ctypes.data for k in ("row_ptr", "col", "tpos", "diag_pos",
+                                        *(h[k].ctypes.data for k in ("row_len", "col", "tpos", "diag_pos",
                                                                      "blk_src_ptr", "blk_src", "nf_ptr", "nf_face"))),
                     "vms_setup_build", ctx=False)
+        self.slot_width = sw.value
+        h["row_ptr"] = (self.slot_width * np.arange(n + 1)).astype(np.int64)   # slot start of each row
         self.host = h
         self.nnzb = nz
         dev = self.dev
@@ -105,12 +108,12 @@ class Problem:
                   "traction": up(mesh.traction if f else np.zeros((1, 3)), np.float64),
                   "dir_mask": up(mesh.dir_mask, np.uint8), "dir_vel": up(mesh.dir_vel, np.float64),
                   "fibre": up(mesh.fibre, np.float64) if mesh.fibre is not None else None}
-        for k in ("row_ptr", "col", "tpos", "diag_pos", "blk_src_ptr", "blk_src", "nf_ptr", "nf_face"):
+        for k in ("col", "tpos", "diag_pos", "blk_src_ptr", "blk_src", "nf_ptr", "nf_face"):
             self.d[k] = up(h[k], np.int32)
         d = self.d
-        self.cmesh = L.Mesh(n, m, f, nz, _p(d["X"]), _p(d["tets"]), _p(d["bfaces"]),
+        self.cmesh = L.Mesh(n, m, f, self.slot_width, nz, _p(d["X"]), _p(d["tets"]), _p(d["bfaces"]),
                             _p(d["traction"]), _p(d["dir_mask"]), _p(d["dir_vel"]), _p(d["fibre"]),
-                            _p(d["row_ptr"]), _p(d["col"]), _p(d["tpos"]), _p(d["diag_pos"]), _p(d["blk_src_ptr"]),
+                            _p(d["col"]), _p(d["tpos"]), _p(d["diag_pos"]), _p(d["blk_src_ptr"]),
                             _p(d["blk_src"]), _p(d["nf_ptr"]), _p(d["nf_face"]))
         self.set_material(mat)
         self.stream = torch.cuda.current_stream(dev)
@@ -143,6 +146,17 @@ class Problem:
                 self.ctx = None
         except Exception:
             pass
+
+    def set_timing(self, enable):
+        """Event-time every launch of the A-block product (vms_ctx_set_timing)."""
+        self._check(self.lib.vms_ctx_set_timing(self.ctx, 1 if enable else 0), "vms_ctx_set_timing")
+
+    def kernel_time(self, fp32=False):
+        """(total ms, launches) of the A-block product since the last call (vms_ctx_kernel_time)."""
+        ms, cnt = C.c_double(), C.c_int64()
+        self._check(self.lib.vms_ctx_kernel_time(self.ctx, 1 if fp32 else 0, C.byref(ms), C.byref(cnt)),
+                    "vms_ctx_kernel_time")
+        return ms.value, cnt.value
 
     def workspace(self, nbytes):
         if self._ws is None or self._ws.numel() < nbytes:

@@ -4,12 +4,20 @@ import scipy.sparse as sp
 import torch
 
 
-def blocks_from_scipy(prob, K):
-    """Entry-major block arrays of an interleaved 4n x 4n matrix on prob's pattern."""
+def pattern(prob):
+    """(row of every block slot, its column, mask of the real (non-padding) slots)."""
     h = prob.host
-    n = prob.mesh.n_nodes
-    rows = np.repeat(np.arange(n), np.diff(h["row_ptr"]))
-    col = h["col"]
+    n, W = prob.mesh.n_nodes, prob.slot_width
+    rows = np.repeat(np.arange(n), W)
+    real = (np.arange(n * W) % W) < np.repeat(h["row_len"], W)
+    return rows, h["col"], real
+
+
+def blocks_from_scipy(prob, K):
+    """Entry-major block arrays of an interleaved 4n x 4n matrix on prob's pattern (padding slots zero)."""
+    rows, col, real = pattern(prob)
+    rows = np.where(real, rows, 0)
+    col = np.where(real, col, 0)
     K = K.tocsr()
     A = np.zeros((9, col.size))
     B = np.zeros((3, col.size))
@@ -20,14 +28,17 @@ def blocks_from_scipy(prob, K):
         B[r] = np.asarray(K[4 * rows + r, 4 * col + 3]).ravel()
         Cm[r] = np.asarray(K[4 * rows + 3, 4 * col + r]).ravel()
     D = np.asarray(K[4 * rows + 3, 4 * col + 3]).ravel()
+    for arr in (A, B, Cm):
+        arr[:, ~real] = 0.0
+    D[~real] = 0.0
     return A, B, Cm, D
 
 
 def scipy_from_blocks(prob, A, B, Cm, D):
-    h = prob.host
     n = prob.mesh.n_nodes
-    rows = np.repeat(np.arange(n), np.diff(h["row_ptr"]))
-    col = h["col"]
+    rows, col, real = pattern(prob)
+    rows, col = rows[real], col[real]
+    A, B, Cm, D = A[:, real], B[:, real], Cm[:, real], D[real]
     R, Cc, V = [], [], []
     for r in range(3):
         for c in range(3):

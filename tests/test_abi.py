@@ -37,15 +37,16 @@ def build_host(mesh):
     n, m, f = mesh.n_nodes, mesh.n_tets, mesh.bfaces.shape[0]
     tets = np.ascontiguousarray(mesh.tets, np.int32)
     bf = np.ascontiguousarray(mesh.bfaces, np.int32)
-    nnzb = C.c_int64()
-    assert lib.vms_setup_sizes(n, m, tets.ctypes.data, C.byref(nnzb)) == 0
+    nnzb, sw = C.c_int64(), C.c_int32()
+    assert lib.vms_setup_sizes(n, m, tets.ctypes.data, C.byref(nnzb), C.byref(sw)) == 0
     nz = nnzb.value
-    h = {"row_ptr": np.zeros(n + 1, np.int32), "col": np.zeros(nz, np.int32), "tpos": np.zeros(nz, np.int32),
+    assert nz == sw.value * n and sw.value % 16 == 0
+    h = {"W": sw.value, "row_len": np.zeros(n, np.int32), "col": np.zeros(nz, np.int32), "tpos": np.zeros(nz, np.int32),
          "diag_pos": np.zeros(n, np.int32), "blk_src_ptr": np.zeros(nz + 1, np.int32),
          "blk_src": np.zeros(16 * m, np.int32),
          "nf_ptr": np.zeros(n + 1, np.int32), "nf_face": np.zeros(max(3 * f, 1), np.int32)}
     rc = lib.vms_setup_build(n, m, tets.ctypes.data, f, bf.ctypes.data,
-                             *(h[k].ctypes.data for k in ("row_ptr", "col", "tpos", "diag_pos", "blk_src_ptr",
+                             *(h[k].ctypes.data for k in ("row_len", "col", "tpos", "diag_pos", "blk_src_ptr",
                                                           "blk_src", "nf_ptr", "nf_face")))
     assert rc == 0
     return h
@@ -63,15 +64,25 @@ def test_pattern_matches_element_connectivity(N):
     G = sp.coo_matrix((np.ones(r.size), (r, c)), shape=(n, n)).tocsr()
     G.sum_duplicates()
     G.sort_indices()
-    np.testing.assert_array_equal(h["row_ptr"], G.indptr)
-    np.testing.assert_array_equal(h["col"], G.indices)
-    rows = np.repeat(np.arange(n), np.diff(G.indptr))
+    W = h["W"]
+    np.testing.assert_array_equal(h["row_len"], np.diff(G.indptr))
+    assert W == 16 * ((np.diff(G.indptr).max() + 15) // 16)
     col = h["col"]
+    rows = np.repeat(np.arange(n), W)
+    slot = np.arange(n * W) % W
+    real = slot < np.repeat(h["row_len"], W)
+    # real slots: the sorted CSR columns of the row; padding slots: the row's own node, mapped to themselves
+    np.testing.assert_array_equal(col[real], G.indices)
+    np.testing.assert_array_equal(col[~real], rows[~real])
+    np.testing.assert_array_equal(h["tpos"][~real], np.nonzero(~real)[0])
     # transpose map and diagonal positions
-    np.testing.assert_array_equal(rows[h["tpos"]], col)
-    np.testing.assert_array_equal(col[h["tpos"]], rows)
+    tp = h["tpos"][real]
+    assert np.all(real[tp])
+    np.testing.assert_array_equal(rows[tp], col[real])
+    np.testing.assert_array_equal(col[tp], rows[real])
     np.testing.assert_array_equal(col[h["diag_pos"]], np.arange(n))
     np.testing.assert_array_equal(rows[h["diag_pos"]], np.arange(n))
+    assert np.all(real[h["diag_pos"]])
     # block contribution lists: every element-local pair exactly once, under its block, in element order
     ptr, src = h["blk_src_ptr"], h["blk_src"]
     assert ptr[0] == 0 and ptr[-1] == 16 * mesh.n_tets
@@ -82,6 +93,7 @@ def test_pattern_matches_element_connectivity(N):
     np.testing.assert_array_equal(col[blk], t[e, b])
     for k in range(col.size):
         assert np.all(np.diff(e[ptr[k]:ptr[k + 1]]) >= 0)
+    assert np.all(np.diff(ptr)[~real] == 0)      # padding slots receive nothing
     # a diagonal block lists each element around its node once, with pair a*4 + a
     d = h["diag_pos"]
     for i in range(n):
@@ -102,5 +114,5 @@ def test_node_face_lists():
 def test_setup_rejects_out_of_range_nodes():
     lib = L.load()
     tets = np.array([[0, 1, 2, 7]], np.int32)
-    nnzb = C.c_int64()
-    assert lib.vms_setup_sizes(4, 1, tets.ctypes.data, C.byref(nnzb)) == -1
+    nnzb, sw = C.c_int64(), C.c_int32()
+    assert lib.vms_setup_sizes(4, 1, tets.ctypes.data, C.byref(nnzb), C.byref(sw)) == -1

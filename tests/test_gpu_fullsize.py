@@ -82,7 +82,8 @@ def _sampled_rows(mesh, mat, ti, prob, seed, n_sample=12):
                     blocks[t[ei, B_]] += Ke[ei, A_, :, B_, :]
         row_o[0:3] += fext[node]
         for j, blk_o in blocks.items():
-            lo, hi = h["row_ptr"][node], h["row_ptr"][node + 1]
+            lo = h["row_ptr"][node]
+            hi = lo + h["row_len"][node]
             b = lo + int(np.searchsorted(h["col"][lo:hi], j))
             assert h["col"][b] == j
             yield "A", A[:, b].reshape(3, 3), blk_o[0:3, 0:3]
