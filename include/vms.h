@@ -41,6 +41,7 @@
 #include <stdint.h>
 
 #define VMS_MAX_TETS 134217727   /* 2^27 - 1: 16 * n_tets fits in int32 */
+#define VMS_MAX_SHAT_ROW 128     /* longest off-diagonal row of the distance-2 pattern, in slots */
 
 #ifdef __cplusplus
 extern "C" {
@@ -111,6 +112,9 @@ typedef struct {
   const int32_t *diag_pos;  /* [n] */
   const int32_t *blk_src_ptr; /* [nnzb+1] contributions of each block ... */
   const int32_t *blk_src;   /* [16m] ... as e*16 + a*4 + b, increasing e within a block */
+  int32_t shat_width;       /* W2: slots per row of the off-diagonal distance-2 pattern (multiple of 64) */
+  const int32_t *shat_col;  /* [n * W2] off-diagonal pattern of S^ = D - C diag(A)^-1 B: sorted
+                               columns first, padding slots hold the row's own node */
   const int32_t *nf_ptr;    /* [n+1] node -> loaded faces */
   const int32_t *nf_face;   /* [3f] */
 } vms_mesh;
@@ -199,23 +203,27 @@ int vms_ctx_kernel_time(vms_ctx *ctx, int kind, double *ms_total, int64_t *launc
 
 /* Size of the node-graph block pattern of the P1 tangent (every pair of
  * nodes sharing a tetrahedron couples, section 3.1): *slot_width = W (the
- * longest row rounded up to a multiple of 16), *nnzb = W * n_nodes.  tets:
- * HOST [m][4].  VMS_ERR_ARG on an out-of-range node, n_tets > VMS_MAX_TETS
- * or W * n_nodes >= 2^31. */
+ * longest row rounded up to a multiple of 16), *nnzb = W * n_nodes, and
+ * *shat_width = W2, the longest off-diagonal row of the distance-2 pattern
+ * (nodes two graph steps apart) rounded up to a multiple of 64.  tets: HOST
+ * [m][4].  VMS_ERR_ARG on an out-of-range node, n_tets > VMS_MAX_TETS,
+ * W * n_nodes or W2 * n_nodes >= 2^31, or W2 > VMS_MAX_SHAT_ROW. */
 int vms_setup_sizes(int32_t n_nodes, int32_t n_tets, const int32_t *tets, int64_t *nnzb,
-                    int32_t *slot_width);
+                    int32_t *slot_width, int32_t *shat_width);
 
 /* Build, into HOST arrays sized by vms_setup_sizes: row_len[n], col[nnzb]
  * (slot layout above), tpos[nnzb] (position of the transposed block; a
  * padding slot maps to itself), diag_pos[n], the block contribution lists
  * blk_src_ptr[nnzb+1], blk_src[16m] (every element-local pair e*16 + a*4 + b
  * under the block (tets[e][a], tets[e][b]), in increasing e; padding slots
- * have none), and node -> loaded-face lists nf_ptr[n+1], nf_face[3f]
- * (bfaces: HOST [f][3]). */
+ * have none), the off-diagonal distance-2 pattern shat_col[n * W2] (sorted
+ * columns first, padding slots hold the row's own node), and node ->
+ * loaded-face lists nf_ptr[n+1], nf_face[3f] (bfaces: HOST [f][3]). */
 int vms_setup_build(int32_t n_nodes, int32_t n_tets, const int32_t *tets,
                     int32_t n_bfaces, const int32_t *bfaces,
                     int32_t *row_len, int32_t *col, int32_t *tpos, int32_t *diag_pos,
-                    int32_t *blk_src_ptr, int32_t *blk_src, int32_t *nf_ptr, int32_t *nf_face);
+                    int32_t *blk_src_ptr, int32_t *blk_src, int32_t *shat_col,
+                    int32_t *nf_ptr, int32_t *nf_face);
 
 /* ---- assembly (section 3.3 steps 1-4; consistent-linearization appendix) - */
 
@@ -276,6 +284,15 @@ int vms_prepare_system(vms_ctx *ctx, const vms_mesh *mesh, vms_matrix *K, const 
 int vms_spmv(vms_ctx *ctx, const vms_mesh *mesh, const vms_matrix *K, int op,
              const void *x, void *y, int fp32);
 
+/* S^ = D - C diag(A)^-1 B from the blocks of K -- the approximate Schur
+ * complement that preconditions the Schur solve, with diag(A) the point
+ * diagonal (section 4.2): off-diagonal part S[n * W2] on shat_col (zero in
+ * padding slots), diagonal Sdiag[n], and sdinv[n] = diag(S^)^-1 (1 where
+ * S^_ii is 0 or not finite).  The solver forms the same matrix internally.
+ * [async] */
+int vms_schur_hat(vms_ctx *ctx, const vms_mesh *mesh, const vms_matrix *K, double *S, double *Sdiag,
+                  double *sdinv);
+
 /* Workspace bytes needed by vms_solve_scaled / vms_solve_transpose for these
  * options (Krylov bases of the four levels, control blocks, temporaries). */
 size_t vms_solve_workspace(const vms_mesh *mesh, const vms_solver_opts *opts);
@@ -283,8 +300,9 @@ size_t vms_solve_workspace(const vms_mesh *mesh, const vms_solver_opts *opts);
 /* Solve the scaled system K* x* = rhs* by FGMRES (outer level) right-
  * preconditioned by the nested Schur-complement-reduction preconditioner
  * (Algorithm 1 with Algorithm 2 for the Schur products): GMRES on A with
- * 3x3 block-Jacobi, GMRES on S = D - C A^-1 B with diag(S^) where
- * S^ = D - C diag(A)^-1 B.  x0 = 0; every level stops at
+ * 3x3 block-Jacobi, GMRES on S = D - C A^-1 B preconditioned from
+ * S^ = D - C diag(A)^-1 B (assembled as by vms_schur_hat): diag(S^)^-1 or a
+ * Chebyshev polynomial in diag(S^)^-1 S^ (shat_degree).  x0 = 0; every level stops at
  * ||r|| <= max(rtol ||b||, atol) or maxit.  [sync]
  * Returns VMS_NOT_CONVERGED (x_scaled holds the last iterate) when the outer
  * level hits maxit. */

@@ -19,6 +19,12 @@
 //                  depend on scheduling.  The contributions of a diagonal
 //                  block are exactly the (element, local node) incidences of
 //                  its node, which also serves the nodal gathers,
+//   shat_col: the off-diagonal distance-2 node pattern (every other node
+//                  reachable in two graph steps), the pattern of
+//                  S^ = D - C diag(A)^-1 B without its diagonal, in rows of
+//                  shat_width fixed slots (a multiple of 64: one wavefront
+//                  per row, one entry per lane): sorted columns first,
+//                  padding slots hold the row's own node,
 //   node -> loaded boundary face lists (for the dead-load vector).
 #include <algorithm>
 #include <cstdint>
@@ -72,6 +78,34 @@ inline int32_t find_block(const Graph &g, int32_t i, int32_t j) {
 
 }  // namespace
 
+// off-diagonal distance-2 pattern: row i lists every j != i with a k in N(i) and j in N(k)
+static void build_ring2(const Graph &g, int32_t n, std::vector<int64_t> &ptr, std::vector<int32_t> *col) {
+  ptr.assign(n + 1, 0);
+  std::vector<int32_t> mark(n, -1), row;
+  for (int32_t i = 0; i < n; ++i) {
+    row.clear();
+    mark[i] = i;
+    for (int32_t a = g.row_ptr[i]; a < g.row_ptr[i + 1]; ++a) {
+      const int32_t k = g.col[a];
+      for (int32_t b = g.row_ptr[k]; b < g.row_ptr[k + 1]; ++b) {
+        const int32_t j = g.col[b];
+        if (mark[j] != i) { mark[j] = i; row.push_back(j); }
+      }
+    }
+    if (col) {
+      std::sort(row.begin(), row.end());
+      col->insert(col->end(), row.begin(), row.end());
+    }
+    ptr[i + 1] = ptr[i] + (int64_t)row.size();
+  }
+}
+
+static int32_t ring2_width(const std::vector<int64_t> &p2, int32_t n) {
+  int64_t mx = 1;
+  for (int32_t i = 0; i < n; ++i) mx = std::max(mx, p2[i + 1] - p2[i]);
+  return (int32_t)(64 * ((mx + 63) / 64));
+}
+
 static int32_t slot_width(const Graph &g, int32_t n) {
   int32_t mx = 1;
   for (int32_t i = 0; i < n; ++i) mx = std::max(mx, g.row_ptr[i + 1] - g.row_ptr[i]);
@@ -79,24 +113,32 @@ static int32_t slot_width(const Graph &g, int32_t n) {
 }
 
 extern "C" int vms_setup_sizes(int32_t n_nodes, int32_t n_tets, const int32_t *tets, int64_t *nnzb,
-                               int32_t *slot_width_out) {
-  if (n_nodes <= 0 || n_tets < 0 || (!tets && n_tets > 0) || !nnzb || !slot_width_out) return VMS_ERR_ARG;
+                               int32_t *slot_width_out, int32_t *shat_width_out) {
+  if (n_nodes <= 0 || n_tets < 0 || (!tets && n_tets > 0) || !nnzb || !slot_width_out || !shat_width_out)
+    return VMS_ERR_ARG;
   if ((int64_t)n_tets > VMS_MAX_TETS) return VMS_ERR_ARG;
   for (int64_t k = 0; k < 4 * (int64_t)n_tets; ++k)
     if (tets[k] < 0 || tets[k] >= n_nodes) return VMS_ERR_ARG;
   Graph g = build_graph(n_nodes, n_tets, tets);
   const int32_t W = slot_width(g, n_nodes);
   if ((int64_t)W * n_nodes >= ((int64_t)1 << 31)) return VMS_ERR_ARG;
+  std::vector<int64_t> p2;
+  build_ring2(g, n_nodes, p2, nullptr);
+  const int32_t W2 = ring2_width(p2, n_nodes);
+  if (W2 > VMS_MAX_SHAT_ROW || (int64_t)W2 * n_nodes >= ((int64_t)1 << 31)) return VMS_ERR_ARG;
   *slot_width_out = W;
   *nnzb = (int64_t)W * n_nodes;
+  *shat_width_out = W2;
   return VMS_OK;
 }
 
 extern "C" int vms_setup_build(int32_t n_nodes, int32_t n_tets, const int32_t *tets,
                                int32_t n_bfaces, const int32_t *bfaces,
                                int32_t *row_len, int32_t *col, int32_t *tpos, int32_t *diag_pos,
-                               int32_t *blk_src_ptr, int32_t *blk_src, int32_t *nf_ptr, int32_t *nf_face) {
+                               int32_t *blk_src_ptr, int32_t *blk_src, int32_t *shat_col,
+                               int32_t *nf_ptr, int32_t *nf_face) {
   if (n_nodes <= 0 || n_tets < 0 || (int64_t)n_tets > VMS_MAX_TETS || !row_len || !col || !tpos || !diag_pos ||
+      !shat_col ||
       !blk_src_ptr || (n_tets > 0 && (!tets || !blk_src)) || !nf_ptr || (n_bfaces > 0 && (!bfaces || !nf_face)))
     return VMS_ERR_ARG;
   for (int64_t k = 0; k < 4 * (int64_t)n_tets; ++k)
@@ -138,6 +180,20 @@ extern "C" int vms_setup_build(int32_t n_nodes, int32_t n_tets, const int32_t *t
   for (int64_t b = 0; b < nnzb; ++b) blk_src_ptr[b + 1] += blk_src_ptr[b];
   std::vector<int32_t> fill(blk_src_ptr, blk_src_ptr + nnzb);
   for (size_t k = 0; k < eb.size(); ++k) blk_src[fill[eb[k]]++] = (int32_t)k;
+
+  // off-diagonal distance-2 pattern of S^ in fixed-width rows
+  {
+    std::vector<int64_t> p2;
+    std::vector<int32_t> c2;
+    build_ring2(g, n_nodes, p2, &c2);
+    const int32_t W2 = ring2_width(p2, n_nodes);
+    if (W2 > VMS_MAX_SHAT_ROW || (int64_t)W2 * n_nodes >= ((int64_t)1 << 31)) return VMS_ERR_ARG;
+    for (int32_t i = 0; i < n_nodes; ++i) {
+      const int64_t len = p2[i + 1] - p2[i];
+      for (int32_t s2 = 0; s2 < W2; ++s2)
+        shat_col[(int64_t)W2 * i + s2] = (s2 < len) ? c2[p2[i] + s2] : i;
+    }
+  }
 
   // node -> loaded faces
   std::fill(nf_ptr, nf_ptr + n_nodes + 1, 0);

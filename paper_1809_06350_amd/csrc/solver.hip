@@ -544,62 +544,80 @@ __global__ void k_bj33_setup(int n, const int32_t *diag_pos, int64_t nnzb, const
   for (int e = 0; e < 9; ++e) Minv[9 * (int64_t)i + e] = (T)inv[e];
 }
 
-// 1 / diag(S^),  S^_ii = D_ii - sum_k sum_c C_ik,c B_ki,c / A_kk,cc
-template <typename T>
-__global__ void k_shat_diag(int n, int W, const int32_t *col, const int32_t *tpos,
-                            const int32_t *diag_pos, int64_t nnzb, const double *A, const double *B,
-                            const double *C, const double *D, T *sdinv) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  double s = D[diag_pos[i]];
-  for (int b = W * i; b < W * i + W; ++b) {   // padding slots hold zeros
-    const int k = col[b];
-    const int64_t dk = diag_pos[k], bt = tpos[b];
-    for (int c = 0; c < 3; ++c) {
-      const double akk = A[(4 * c) * nnzb + dk];
-      if (akk != 0.0) s -= C[c * nnzb + b] * B[c * nnzb + bt] / akk;
-    }
-  }
-  sdinv[i] = (T)((s != 0.0 && isfinite(s)) ? 1.0 / s : 1.0);
-}
-
-// ---- Chebyshev preconditioner on S^ = D - C diag(A)^-1 B (matrix free) ----
-// point diagonal of the scaled A, inverted
-template <typename T>
-__global__ void k_dAinv(int n, const int32_t *diag_pos, int64_t nnzb, const double *A, T *dAinv) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const int64_t b = diag_pos[i];
-  for (int c = 0; c < 3; ++c) {
-    const double a = A[(4 * c) * nnzb + b];
-    dAinv[3 * (int64_t)i + c] = (T)((a != 0.0) ? 1.0 / a : 0.0);
-  }
-}
-
-// t = diag(A)^-1 (B x)
+// ---- S^ = D - C diag(A)^-1 B, assembled on the distance-2 pattern ----------
+// Off-diagonal part in rows of W2 fixed slots (sorted columns, then padding
+// slots that hold the row's own node), diagonal apart.  16 lanes per row i
+// (one per block slot of a 1-ring row), 16 rows per workgroup.  The row's
+// columns and accumulators live in LDS; the neighbours k of i are visited in
+// slot order, and for each k the 16 lanes take the blocks (k, j) of row k:
+// lane l adds -sum_c C_ik,c B_kj,c / A_kk,cc to the accumulator of column j
+// (one lane per j within a k, so no two lanes of a step touch one
+// accumulator), then D_ij is added.  Fixed order: deterministic.  Also
+// writes diag(S^)^-1 (1 where S^_ii is 0 or not finite).
+#define SHAT_ROWS 16
 template <typename T>
 __global__ void __launch_bounds__(VMS_BLOCK)
-k_shat_bt(int n, int64_t nnzb, int W, const int32_t *__restrict__ col,
-          const T *__restrict__ B, const T *__restrict__ dAinv, const T *__restrict__ x, T *t) {
-  const int *done = nullptr;
-  SPMV_PROLOGUE
-  // the row's own values are loaded before the product so that their latency overlaps it
-  const int64_t o = 3 * (int64_t)(act ? row : 0);
-  const double di0 = ld(dAinv, o), di1 = ld(dAinv, o + 1), di2 = ld(dAinv, o + 2);
-  double a0 = 0, a1 = 0, a2 = 0;
-  for (int b = b0 + lane; b < b1; b += 16) {
-    const double xp = ld(x, col[b]);
-    a0 += ld(B, 0 * nnzb + b) * xp;
-    a1 += ld(B, 1 * nnzb + b) * xp;
-    a2 += ld(B, 2 * nnzb + b) * xp;
+k_shat_form(int n, int W, const int32_t *__restrict__ col, const int32_t *__restrict__ diag_pos, int64_t nnzb,
+            const double *__restrict__ A, const double *__restrict__ B, const double *__restrict__ C,
+            const double *__restrict__ D, int W2, const int32_t *__restrict__ sc, T *S, T *Sd, T *sdinv) {
+  __shared__ int32_t scol[SHAT_ROWS][VMS_MAX_SHAT_ROW];
+  __shared__ double acc[SHAT_ROWS][VMS_MAX_SHAT_ROW];
+  __shared__ double dacc[SHAT_ROWS];
+  const int lane = threadIdx.x & 15, g = threadIdx.x >> 4;
+  const int row = blockIdx.x * SHAT_ROWS + g;
+  if (row >= n) return;   // a row's 16 lanes share one wavefront and use only their own LDS rows
+  const int64_t r0 = (int64_t)W2 * row;
+  int cnt = 0;
+  for (int q = lane; q < W2; q += 16) {
+    const int j = sc[r0 + q];
+    scol[g][q] = j;
+    acc[g][q] = 0.0;
+    cnt += (j != row);
   }
-  a0 = reduce16(a0);
-  a1 = reduce16(a1);
-  a2 = reduce16(a2);
-  if (act && lane == 0) {
-    t[o] = (T)(a0 * di0);
-    t[o + 1] = (T)(a1 * di1);
-    t[o + 2] = (T)(a2 * di2);
+  if (lane == 0) dacc[g] = 0.0;
+#pragma unroll
+  for (int o = 8; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o, 16);
+  const int len = cnt;   // real (sorted) entries come first
+  auto slot = [&](int j) {   // position of column j != row in the row's sorted list
+    int lo = 0, hi = len - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (scol[g][mid] < j) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+  };
+  for (int kk = 0; kk < W; ++kk) {
+    const int64_t bik = (int64_t)W * row + kk;
+    const double c0 = C[bik], c1 = C[nnzb + bik], c2 = C[2 * nnzb + bik];
+    if (c0 == 0.0 && c1 == 0.0 && c2 == 0.0) continue;   // padding slot, or no coupling
+    const int k = col[bik];
+    const int64_t dk = diag_pos[k];
+    const double a0 = A[dk], a1 = A[4 * nnzb + dk], a2 = A[8 * nnzb + dk];
+    const double w0 = (a0 != 0.0) ? c0 / a0 : 0.0, w1 = (a1 != 0.0) ? c1 / a1 : 0.0, w2 = (a2 != 0.0) ? c2 / a2 : 0.0;
+    for (int l = lane; l < W; l += 16) {
+      const int64_t bkj = (int64_t)W * k + l;
+      const double v = w0 * B[bkj] + w1 * B[nnzb + bkj] + w2 * B[2 * nnzb + bkj];
+      if (v != 0.0) {
+        const int j = col[bkj];
+        if (j == row) dacc[g] -= v;
+        else acc[g][slot(j)] -= v;
+      }
+    }
+  }
+  for (int l = lane; l < W; l += 16) {
+    const int64_t b = (int64_t)W * row + l;
+    const double dv = D[b];
+    if (dv != 0.0) {
+      const int j = col[b];
+      if (j == row) dacc[g] += dv;
+      else acc[g][slot(j)] += dv;
+    }
+  }
+  for (int q = lane; q < W2; q += 16) S[r0 + q] = (T)acc[g][q];
+  if (lane == 0) {
+    const double v = dacc[g];
+    Sd[row] = (T)v;
+    sdinv[row] = (T)((v != 0.0 && isfinite(v)) ? 1.0 / v : 1.0);
   }
 }
 
@@ -617,42 +635,49 @@ __device__ __forceinline__ void cheb_coef(const double *lam, double ratio, int k
   rho1 = 1.0 / (2.0 * s1 - r);
 }
 
-// MODE 0 (power iteration): y = diag(S^)^-1 (D x - C t)
-// MODE 1 (Chebyshev step k): s = D d - C t; x += d; r -= s;
-//                            dn = rho1 rho0 d + 2 rho1/delta diag(S^)^-1 r
+// y = S^ d: 16 lanes per row, 16 rows per workgroup; lane l takes the
+// off-diagonal slots l, l + 16, l + 32, l + 48 of each 64-slot segment (four
+// column loads and four gathers in flight per lane), the diagonal is added by
+// lane 0; then
+// MODE 0 (power iteration): y = diag(S^)^-1 S^ d
+// MODE 1 (Chebyshev step k): x += d; r -= S^ d; y = rho1 rho0 d + 2 rho1/delta diag(S^)^-1 r
 template <typename T, int MODE>
 __global__ void __launch_bounds__(VMS_BLOCK)
-k_shat_dc(int n, int64_t nnzb, int W, const int32_t *__restrict__ col,
-          const T *__restrict__ C, const T *__restrict__ D, const T *__restrict__ d, const T *__restrict__ t,
-          const T *__restrict__ sdinv, T *y, T *x, T *r, const double *lam, double ratio, int k) {
-  const int *done = nullptr;
-  SPMV_PROLOGUE
-  // the row's own values and the Chebyshev scalars ahead of the product (latency overlap)
+k_shat_cheb(int n, int W2, const int32_t *__restrict__ sc, const T *__restrict__ S, const T *__restrict__ Sd,
+            const T *__restrict__ d, const T *__restrict__ sdinv, T *y, T *x, T *r, const double *lam, double ratio,
+            int k) {
+  const int lane = threadIdx.x & 15;
+  const int row = xcd_block(blockIdx.x, gridDim.x) * SPMV_ROWS_PER_BLOCK + (threadIdx.x >> 4);
+  const bool act = row < n;
   const int ro = act ? row : 0;
-  const double sdi = ld(sdinv, ro);
-  double di = 0.0, xi = 0.0, ri = 0.0, rho0 = 0.0, rho1 = 0.0, delta = 1.0, theta = 1.0;
+  const int64_t r0 = (int64_t)W2 * ro;
+  // the row's own values and the Chebyshev scalars ahead of the product (latency overlap)
+  const double sdi = ld(sdinv, ro), sii = ld(Sd, ro), di = ld(d, ro);
+  double xi = 0.0, ri = 0.0, rho0 = 0.0, rho1 = 0.0, delta = 1.0, theta = 1.0;
   if (MODE == 1) {
-    di = ld(d, ro);
     xi = ld(x, ro);
     ri = ld(r, ro);
     cheb_coef(lam, ratio, k, rho0, rho1, delta, theta);
   }
-  double a = 0.0, dd = 0.0;
-  for (int b = b0 + lane; b < b1; b += 16) {
-    const int64_t c = col[b];
-    a += ld(C, 0 * nnzb + b) * ld(t, 3 * c) + ld(C, 1 * nnzb + b) * ld(t, 3 * c + 1) +
-         ld(C, 2 * nnzb + b) * ld(t, 3 * c + 2);
-    dd += ld(D, b) * ld(d, c);
+  double a = 0.0;
+  for (int q0 = 0; q0 < W2; q0 += 64) {
+    int c[4];
+    double v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      c[u] = sc[r0 + q0 + lane + 16 * u];
+      v[u] = ld(S, r0 + q0 + lane + 16 * u);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) a += v[u] * ld(d, c[u]);
   }
-  a = reduce16(a);
-  dd = reduce16(dd);
+  a = reduce16(a) + sii * di;
   if (act && lane == 0) {
-    const double sv = dd - a;
     if (MODE == 0) {
-      y[row] = (T)(sdi * sv);
+      y[row] = (T)(sdi * a);
     } else {
       x[row] = (T)(xi + di);
-      const double rn = ri - sv;
+      const double rn = ri - a;
       r[row] = (T)rn;
       y[row] = (T)(rho1 * rho0 * di + 2.0 * rho1 / delta * sdi * rn);
     }
@@ -895,7 +920,7 @@ struct Nested {
   const T *A, *B, *C, *D;  // scaled blocks in the level precision
   KLevel<T> LA, LS;
   T *rv, *rp, *xh, *xp, *xv, *xbar, *xt, *Minv, *sdinv;
-  T *dAinv, *ct, *cr, *cd0, *cd1, *px, *py;  // Chebyshev / power-iteration vectors
+  T *Shat, *Shd, *cr, *cd0, *cd1, *px, *py;  // S^ (off-diagonal, diagonal); Chebyshev / power-iteration vectors
   double *lam = nullptr;                      // device: lmax estimate of diag(S^)^-1 S^
   vms_solve_stats *stats;
   int err = VMS_OK;
@@ -913,8 +938,8 @@ struct Nested {
     xt = cv.take<T>(3 * nn);
     Minv = cv.take<T>(9 * nn);
     sdinv = cv.take<T>(nn);
-    dAinv = cv.take<T>(3 * nn);
-    ct = cv.take<T>(3 * nn);
+    Shat = cv.take<T>((int64_t)m_->shat_width * nn);
+    Shd = cv.take<T>(nn);
     cr = cv.take<T>(nn);
     cd0 = cv.take<T>(nn);
     cd1 = cv.take<T>(nn);
@@ -927,14 +952,12 @@ struct Nested {
     hipStream_t s = ctx->stream;
     const int deg = o->shat_degree;
     const double ratio = o->shat_ratio > 1.0 ? o->shat_ratio : 20.0;
-    const dim3 g1((n + VMS_BLOCK - 1) / VMS_BLOCK), gs(spmv_grid(n)), bl(VMS_BLOCK);
+    const dim3 g1((n + VMS_BLOCK - 1) / VMS_BLOCK), gw(spmv_grid(n)), bl(VMS_BLOCK);
     hipLaunchKernelGGL(k_cheb_init<T>, g1, bl, 0, s, n, v, (const T *)sdinv, z, cr, cd0, (const double *)lam, ratio);
     T *d = cd0, *dn = cd1;
     for (int k = 0; k < deg; ++k) {
-      hipLaunchKernelGGL(k_shat_bt<T>, gs, bl, 0, s, n, nnzb, mesh->slot_width, mesh->col, B, (const T *)dAinv,
-                         (const T *)d, ct);
-      hipLaunchKernelGGL((k_shat_dc<T, 1>), gs, bl, 0, s, n, nnzb, mesh->slot_width, mesh->col, C, D, (const T *)d,
-                         (const T *)ct, (const T *)sdinv, dn, z, cr, (const double *)lam, ratio, k);
+      hipLaunchKernelGGL((k_shat_cheb<T, 1>), gw, bl, 0, s, n, mesh->shat_width, mesh->shat_col, (const T *)Shat,
+                         (const T *)Shd, (const T *)d, (const T *)sdinv, dn, z, cr, (const double *)lam, ratio, k);
       std::swap(d, dn);
     }
   }
@@ -942,16 +965,14 @@ struct Nested {
   // lmax of diag(S^)^-1 S^ by power iteration, kept on the device
   void power_lmax(int iters) {
     hipStream_t s = ctx->stream;
-    const dim3 g1((n + VMS_BLOCK - 1) / VMS_BLOCK), gs(spmv_grid(n)), bl(VMS_BLOCK);
+    const dim3 g1((n + VMS_BLOCK - 1) / VMS_BLOCK), gw(spmv_grid(n)), bl(VMS_BLOCK);
     const int nb = vms_red_blocks(n);
     double *part = LS.ctrl + LS.off.part;
     hipLaunchKernelGGL(k_power_init<T>, g1, bl, 0, s, n, px);
     for (int it = 0; it < iters; ++it) {
-      hipLaunchKernelGGL(k_shat_bt<T>, gs, bl, 0, s, n, nnzb, mesh->slot_width, mesh->col, B, (const T *)dAinv,
-                         (const T *)px, ct);
-      hipLaunchKernelGGL((k_shat_dc<T, 0>), gs, bl, 0, s, n, nnzb, mesh->slot_width, mesh->col, C, D, (const T *)px,
-                         (const T *)ct, (const T *)sdinv, py, (T *)nullptr, (T *)nullptr, (const double *)nullptr,
-                         0.0, 0);
+      hipLaunchKernelGGL((k_shat_cheb<T, 0>), gw, bl, 0, s, n, mesh->shat_width, mesh->shat_col, (const T *)Shat,
+                         (const T *)Shd, (const T *)px, (const T *)sdinv, py, (T *)nullptr, (T *)nullptr,
+                         (const double *)nullptr, 0.0, 0);
       hipLaunchKernelGGL(k_norm_part<T>, dim3(nb), bl, 0, s, (int64_t)n, (const T *)py, part, (const int *)nullptr);
       hipLaunchKernelGGL(k_store_norm, dim3(1), bl, 0, s, nb, (const double *)part, lam);
       hipLaunchKernelGGL(k_power_scale<T>, g1, bl, 0, s, n, (const T *)py, (const double *)lam, px);
@@ -1034,12 +1055,12 @@ struct Nested {
   int setup_precond() {
     hipLaunchKernelGGL(k_bj33_setup<T>, dim3(grid1(n)), dim3(VMS_BLOCK), 0, ctx->stream, n, mesh->diag_pos, nnzb,
                        K->A, Minv);
-    hipLaunchKernelGGL(k_shat_diag<T>, dim3(grid1(n)), dim3(VMS_BLOCK), 0, ctx->stream, n, mesh->slot_width, mesh->col,
-                       mesh->tpos, mesh->diag_pos, nnzb, K->A, K->B, K->C, K->D, sdinv);
+    // S^ from the FP64 scaled blocks (stored in the level precision), and diag(S^)^-1
+    hipLaunchKernelGGL(k_shat_form<T>, dim3((n + SHAT_ROWS - 1) / SHAT_ROWS), dim3(VMS_BLOCK), 0, ctx->stream, n,
+                       mesh->slot_width, mesh->col, mesh->diag_pos, nnzb, K->A, K->B, K->C, K->D, mesh->shat_width,
+                       mesh->shat_col, Shat, Shd, sdinv);
     if (o->shat_degree > 0) {
       lam = LS.ctrl + LS.off.scal + 5;
-      hipLaunchKernelGGL(k_dAinv<T>, dim3(grid1(n)), dim3(VMS_BLOCK), 0, ctx->stream, n, mesh->diag_pos, nnzb, K->A,
-                         dAinv);
       power_lmax(12);
     }
     VMS_LAUNCH_CHECK(ctx);
@@ -1236,6 +1257,21 @@ extern "C" int vms_spmv(vms_ctx *ctx, const vms_mesh *mesh, const vms_matrix *K,
   if (rc) return rc;
   if (!K || !x || !y) return vms_set_error(ctx, VMS_ERR_ARG, "vms_spmv: missing argument");
   return vms_launch_spmv(ctx, mesh, K, op, x, y, fp32);
+}
+
+extern "C" int vms_schur_hat(vms_ctx *ctx, const vms_mesh *mesh, const vms_matrix *K, double *S, double *Sdiag,
+                             double *sdinv) {
+  if (!ctx) return VMS_ERR_ARG;
+  int rc = vms_check_mesh(ctx, mesh);
+  if (rc) return rc;
+  if (!K || !K->A || !K->B || !K->C || !K->D || !S || !Sdiag || !sdinv)
+    return vms_set_error(ctx, VMS_ERR_ARG, "vms_schur_hat: missing argument");
+  const int n = mesh->n_nodes;
+  hipLaunchKernelGGL(k_shat_form<double>, dim3((n + SHAT_ROWS - 1) / SHAT_ROWS), dim3(VMS_BLOCK), 0, ctx->stream, n,
+                     mesh->slot_width, mesh->col, mesh->diag_pos, mesh->nnzb, K->A, K->B, K->C, K->D,
+                     mesh->shat_width, mesh->shat_col, S, Sdiag, sdinv);
+  VMS_LAUNCH_CHECK(ctx);
+  return VMS_OK;
 }
 
 // ---- time step ---------------------------------------------------------------

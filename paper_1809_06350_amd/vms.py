@@ -82,19 +82,22 @@ class Problem:
         n, m, f = mesh.n_nodes, mesh.n_tets, int(mesh.bfaces.shape[0])
         tets = np.ascontiguousarray(mesh.tets, dtype=np.int32)
         bfaces = np.ascontiguousarray(mesh.bfaces, dtype=np.int32).reshape(-1, 3)
-        nnzb, sw = C.c_int64(), C.c_int32()
-        self._check(lib.vms_setup_sizes(n, m, tets.ctypes.data, C.byref(nnzb), C.byref(sw)), "vms_setup_sizes",
-                    ctx=False)
+        nnzb, sw, w2 = C.c_int64(), C.c_int32(), C.c_int32()
+        self._check(lib.vms_setup_sizes(n, m, tets.ctypes.data, C.byref(nnzb), C.byref(sw), C.byref(w2)),
+                    "vms_setup_sizes", ctx=False)
         nz = nnzb.value
         h = {"row_len": np.zeros(n, np.int32), "col": np.zeros(nz, np.int32), "tpos": np.zeros(nz, np.int32),
              "diag_pos": np.zeros(n, np.int32), "blk_src_ptr": np.zeros(nz + 1, np.int32),
              "blk_src": np.zeros(max(16 * m, 1), np.int32),
+             "shat_col": np.zeros(n * w2.value, np.int32),
              "nf_ptr": np.zeros(n + 1, np.int32), "nf_face": np.zeros(max(3 * f, 1), np.int32)}
         self._check(lib.vms_setup_build(n, m, tets.ctypes.data, f, bfaces.ctypes.data if f else None,
                                         *(h[k].ctypes.data for k in ("row_len", "col", "tpos", "diag_pos",
-                                                                     "blk_src_ptr", "blk_src", "nf_ptr", "nf_face"))),
+                                                                     "blk_src_ptr", "blk_src", "shat_col", "nf_ptr",
+                                                                     "nf_face"))),
                     "vms_setup_build", ctx=False)
         self.slot_width = sw.value
+        self.shat_width = w2.value
         h["row_ptr"] = (self.slot_width * np.arange(n + 1)).astype(np.int64)   # slot start of each row
         self.host = h
         self.nnzb = nz
@@ -108,13 +111,14 @@ class Problem:
                   "traction": up(mesh.traction if f else np.zeros((1, 3)), np.float64),
                   "dir_mask": up(mesh.dir_mask, np.uint8), "dir_vel": up(mesh.dir_vel, np.float64),
                   "fibre": up(mesh.fibre, np.float64) if mesh.fibre is not None else None}
-        for k in ("col", "tpos", "diag_pos", "blk_src_ptr", "blk_src", "nf_ptr", "nf_face"):
+        for k in ("col", "tpos", "diag_pos", "blk_src_ptr", "blk_src", "shat_col", "nf_ptr", "nf_face"):
             self.d[k] = up(h[k], np.int32)
         d = self.d
         self.cmesh = L.Mesh(n, m, f, self.slot_width, nz, _p(d["X"]), _p(d["tets"]), _p(d["bfaces"]),
                             _p(d["traction"]), _p(d["dir_mask"]), _p(d["dir_vel"]), _p(d["fibre"]),
                             _p(d["col"]), _p(d["tpos"]), _p(d["diag_pos"]), _p(d["blk_src_ptr"]),
-                            _p(d["blk_src"]), _p(d["nf_ptr"]), _p(d["nf_face"]))
+                            _p(d["blk_src"]), self.shat_width, _p(d["shat_col"]), _p(d["nf_ptr"]),
+                            _p(d["nf_face"]))
         self.set_material(mat)
         self.stream = torch.cuda.current_stream(dev)
         ctx = C.c_void_p()
@@ -237,6 +241,16 @@ class Problem:
         self._check(self.lib.vms_spmv(self.ctx, C.byref(self.cmesh), C.byref(K.c()), op, _p(x), _p(y),
                                       1 if fp32 else 0), "vms_spmv")
         return y
+
+    def schur_hat(self, K):
+        """S^ of the scaled blocks of K: (off-diagonal [n][W2] on shat_col, diagonal, diag(S^)^-1)."""
+        n = self.mesh.n_nodes
+        S = torch.empty(n, self.shat_width, dtype=torch.float64, device=self.dev)
+        Sd = torch.empty(n, dtype=torch.float64, device=self.dev)
+        sdinv = torch.empty(n, dtype=torch.float64, device=self.dev)
+        self._check(self.lib.vms_schur_hat(self.ctx, C.byref(self.cmesh), C.byref(K.c()), _p(S), _p(Sd), _p(sdinv)),
+                    "vms_schur_hat")
+        return S, Sd, sdinv
 
     def solve_scaled(self, K, rhs, opts, x=None, allow_nc=False):
         nb = self.lib.vms_solve_workspace(C.byref(self.cmesh), C.byref(opts))

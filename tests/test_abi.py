@@ -37,19 +37,22 @@ def build_host(mesh):
     n, m, f = mesh.n_nodes, mesh.n_tets, mesh.bfaces.shape[0]
     tets = np.ascontiguousarray(mesh.tets, np.int32)
     bf = np.ascontiguousarray(mesh.bfaces, np.int32)
-    nnzb, sw = C.c_int64(), C.c_int32()
-    assert lib.vms_setup_sizes(n, m, tets.ctypes.data, C.byref(nnzb), C.byref(sw)) == 0
+    nnzb, sw, w2 = C.c_int64(), C.c_int32(), C.c_int32()
+    assert lib.vms_setup_sizes(n, m, tets.ctypes.data, C.byref(nnzb), C.byref(sw), C.byref(w2)) == 0
     nz = nnzb.value
     assert nz == sw.value * n and sw.value % 16 == 0
-    h = {"W": sw.value, "row_len": np.zeros(n, np.int32), "col": np.zeros(nz, np.int32), "tpos": np.zeros(nz, np.int32),
+    assert w2.value % 64 == 0
+    h = {"W": sw.value, "W2": w2.value, "row_len": np.zeros(n, np.int32), "col": np.zeros(nz, np.int32), "tpos": np.zeros(nz, np.int32),
          "diag_pos": np.zeros(n, np.int32), "blk_src_ptr": np.zeros(nz + 1, np.int32),
          "blk_src": np.zeros(16 * m, np.int32),
+         "shat_col": np.zeros(n * w2.value, np.int32),
          "nf_ptr": np.zeros(n + 1, np.int32), "nf_face": np.zeros(max(3 * f, 1), np.int32)}
     rc = lib.vms_setup_build(n, m, tets.ctypes.data, f, bf.ctypes.data,
                              *(h[k].ctypes.data for k in ("row_len", "col", "tpos", "diag_pos", "blk_src_ptr",
-                                                          "blk_src", "nf_ptr", "nf_face")))
+                                                          "blk_src", "shat_col", "nf_ptr", "nf_face")))
     assert rc == 0
     return h
+
 
 
 @pytest.mark.parametrize("N", [1, 3, 4])
@@ -94,6 +97,18 @@ def test_pattern_matches_element_connectivity(N):
     for k in range(col.size):
         assert np.all(np.diff(e[ptr[k]:ptr[k + 1]]) >= 0)
     assert np.all(np.diff(ptr)[~real] == 0)      # padding slots receive nothing
+    # distance-2 pattern: the off-diagonal pattern of G @ G (nodes two graph steps away), sorted, in W2 slots
+    G2 = (G @ G).tocsr()
+    G2.setdiag(0)
+    G2.eliminate_zeros()
+    G2.sort_indices()
+    W2 = h["W2"]
+    assert W2 == 64 * ((np.diff(G2.indptr).max() + 63) // 64)
+    sc = h["shat_col"].reshape(n, W2)
+    for i in range(n):
+        real = G2.indices[G2.indptr[i]:G2.indptr[i + 1]]
+        np.testing.assert_array_equal(sc[i, :real.size], real)
+        assert np.all(sc[i, real.size:] == i)
     # a diagonal block lists each element around its node once, with pair a*4 + a
     d = h["diag_pos"]
     for i in range(n):
@@ -114,5 +129,5 @@ def test_node_face_lists():
 def test_setup_rejects_out_of_range_nodes():
     lib = L.load()
     tets = np.array([[0, 1, 2, 7]], np.int32)
-    nnzb, sw = C.c_int64(), C.c_int32()
-    assert lib.vms_setup_sizes(4, 1, tets.ctypes.data, C.byref(nnzb), C.byref(sw)) == -1
+    nnzb, sw, w2 = C.c_int64(), C.c_int32(), C.c_int32()
+    assert lib.vms_setup_sizes(4, 1, tets.ctypes.data, C.byref(nnzb), C.byref(sw), C.byref(w2)) == -1

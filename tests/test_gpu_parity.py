@@ -159,6 +159,29 @@ def _prepared(prob, mesh, ti, disc, seed, mirror32=False, nonzero_rk=True):
     return st, K, rhs, Ks, W * rd, W, (sn, it, sto)
 
 
+@pytest.mark.parametrize("name", ["cube-nu0499", "cube-incomp", "tube-hgo"])
+def test_schur_hat_matches_oracle(problems, name):
+    """S^ = D - C diag(A)^-1 B (section 4.2) of the oracle's scaled system, formed with scipy."""
+    import scipy.sparse as sp
+    prob, mesh, mat, ti, disc = problems(name)
+    st, K, rhs, Ks, rs, W, _ = _prepared(prob, mesh, ti, disc, 61)
+    S, Sd, sdinv = prob.schur_hat(K)
+    A, B, Cm, D, iv, ip = AS.split_blocks(Ks)
+    dA = A.diagonal()
+    Sh = (D - Cm @ sp.diags(np.where(dA != 0.0, 1.0 / np.where(dA != 0.0, dA, 1.0), 0.0)) @ B).tocsr()
+    h = prob.host
+    n = mesh.n_nodes
+    W2 = prob.shat_width
+    rows = np.repeat(np.arange(n), W2)
+    Sg = (sp.coo_matrix((S.cpu().numpy().ravel(), (rows, h["shat_col"])), shape=(n, n))
+          + sp.diags(Sd.cpu().numpy())).tocsr()
+    scale = np.abs(Sh).max()
+    assert np.abs(Sg - Sh).max() <= 1e-12 * scale
+    dS = Sh.diagonal()
+    expect = np.where((dS != 0.0) & np.isfinite(dS), 1.0 / np.where(dS != 0.0, dS, 1.0), 1.0)
+    assert rel_err(sdinv.cpu().numpy(), expect) < 1e-12
+
+
 def _with_mirrors(prob, K):
     K2 = prob.new_matrix(mirror32=True)
     for a, b in ((K2.A, K.A), (K2.B, K.B), (K2.C, K.C), (K2.D, K.D)):
