@@ -1,6 +1,8 @@
 // Context management and the thin C-ABI wrappers around the assembly kernels.
 #include <cstring>
 
+#include <atomic>
+
 #include "vms_internal.h"
 
 int vms_set_error(vms_ctx *ctx, int code, const char *fmt, ...) {
@@ -30,15 +32,20 @@ extern "C" int vms_ctx_create(vms_ctx **out, int device, void *stream) {
     return VMS_ERR_HIP;
   }
   if (hipHostMalloc((void **)&c->h_i, 64 * sizeof(int32_t), hipHostMallocDefault) != hipSuccess ||
-      hipHostMalloc((void **)&c->h_d, 64 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+      hipHostMalloc((void **)&c->h_d, 64 * sizeof(double), hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void **)&c->h_post, 64 * sizeof(int32_t), hipHostMallocCoherent | hipHostMallocMapped) !=
+          hipSuccess) {
     if (c->h_i) (void)hipHostFree(c->h_i);
+    if (c->h_d) (void)hipHostFree(c->h_d);
     (void)hipFree(c->dstat);
     delete c;
     return VMS_ERR_HIP;
   }
+  for (int q = 0; q < 64; ++q) c->h_post[q] = 0;
   if (hipMemset(c->dstat, 0, sizeof(vms_dev_status)) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
     (void)hipHostFree(c->h_i);
     (void)hipHostFree(c->h_d);
+    (void)hipHostFree((void *)c->h_post);
     (void)hipFree(c->dstat);
     delete c;
     return VMS_ERR_HIP;
@@ -56,7 +63,43 @@ extern "C" void vms_ctx_destroy(vms_ctx *ctx) {
   if (ctx->dstat) (void)hipFree(ctx->dstat);
   if (ctx->h_i) (void)hipHostFree(ctx->h_i);
   if (ctx->h_d) (void)hipHostFree(ctx->h_d);
+  if (ctx->h_post) (void)hipHostFree((void *)ctx->h_post);
   delete ctx;
+}
+
+// ---- low-latency flag readback ---------------------------------------------------
+// One thread copies the flags, then (after a system-scope fence) the sequence
+// number, into the coherent host buffer.
+__global__ void k_post_flags(const int *dev, volatile int32_t *host, int32_t seq) {
+  if (threadIdx.x != 0) return;
+  for (int q = 0; q < 4; ++q) host[1 + q] = dev[q];
+  __threadfence_system();
+  host[0] = seq;
+}
+
+int vms_read_flags(vms_ctx *ctx, const int *dev) {
+  const int32_t seq = ++ctx->post_seq;
+  hipLaunchKernelGGL(k_post_flags, dim3(1), dim3(64), 0, ctx->stream, dev, ctx->h_post, seq);
+  VMS_LAUNCH_CHECK(ctx);
+  for (long spin = 0;; ++spin) {
+    if (ctx->h_post[0] == seq) {
+      std::atomic_thread_fence(std::memory_order_acquire);
+      for (int q = 0; q < 4; ++q) ctx->h_i[q] = ctx->h_post[1 + q];
+      return VMS_OK;
+    }
+    if ((spin & 1023) == 1023) {   // now and then: has the stream failed, or drained without the post?
+      const hipError_t e = hipStreamQuery(ctx->stream);
+      if (e != hipErrorNotReady) {
+        if (e != hipSuccess)
+          return vms_set_error(ctx, VMS_ERR_HIP, "stream failed: %s", hipGetErrorString(e));
+        if (ctx->h_post[0] == seq) continue;
+        // drained but the post is not visible: read the flags the ordinary way
+        VMS_HIP(ctx, hipMemcpyAsync(ctx->h_i, dev, 4 * sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+        VMS_HIP(ctx, hipStreamSynchronize(ctx->stream));
+        return VMS_OK;
+      }
+    }
+  }
 }
 
 // ---- launch timing of the A-block product --------------------------------------

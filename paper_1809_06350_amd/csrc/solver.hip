@@ -802,11 +802,7 @@ struct KLevel {
   }
 };
 
-inline int sync_level_flags(vms_ctx *ctx, const int *iflag) {
-  VMS_HIP(ctx, hipMemcpyAsync(ctx->h_i, iflag, 4 * sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
-  VMS_HIP(ctx, hipStreamSynchronize(ctx->stream));
-  return VMS_OK;
-}
+inline int sync_level_flags(vms_ctx *ctx, const int *iflag) { return vms_read_flags(ctx, iflag); }
 
 // Arnoldi step j of level L: orthogonalise W against V_0..V_j, finish the
 // Hessenberg/Givens update and the convergence flags, and form V_{j+1} and

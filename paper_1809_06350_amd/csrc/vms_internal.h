@@ -45,7 +45,16 @@ struct vms_ctx {
   std::vector<hipEvent_t> tev[2];
   int tused[2] = {0, 0};
   int *tflag = nullptr;              // device [2][VMS_MAX_TIMED]
+  // low-latency flag readback: a one-thread kernel copies a level's flags and a
+  // sequence number into pinned coherent host memory, the host spins on it
+  volatile int32_t *h_post = nullptr;   // [8]: seq, flags[4]
+  int32_t post_seq = 0;
 };
+
+// Read the 4 ints at dev (device) into ctx->h_i once every earlier kernel of
+// the stream has finished, by the low-latency path (falls back to a stream
+// synchronisation if the posted sequence number does not arrive).
+int vms_read_flags(vms_ctx *ctx, const int *dev);
 
 // Next timed launch of the A-block product (kind 0 FP64, 1 FP32) when timing
 // is on: the start/stop events that the launch passes to hipExtLaunchKernelGGL
