@@ -156,4 +156,4 @@ def test_autograd_gradient_matches_oracle(name, precision):
     print(f"[autograd] {name} precision={precision} gpu={gg} oracle={go}", flush=True)
     assert rel_err(u.detach().cpu().numpy(), uo) < 1e-9
     for k in params:
-        assert gg[k] == pytest.approx(go[k], rel=1e-5), AD.PARAMS[k]
+        assert gg[k] == pytest.approx(go[k], rel=1e-5, abs=0.0), AD.PARAMS[k]

@@ -157,11 +157,14 @@ def test_cube64_time_step_satisfies_oracle_equations(precision):
 
 @pytest.mark.parametrize("nu", [0.3, 0.45, 0.499, 0.5])
 def test_cube32_poisson_sweep_satisfies_oracle_equations(nu):
+    """The 32^3 Poisson-ratio sweep over the full 10-step load ramp (every step must converge);
+    the oracle's equations are checked at the first, a middle and the last step."""
     mesh, mat, ti = synth.cube_case(32, nu=nu, n_steps=10)
     prob = _problem(mesh, mat)
-    states = _gpu_steps(prob, mesh, ti, 2, V.solver_opts(rtol=1e-8))
-    for s in range(2):
+    states = _gpu_steps(prob, mesh, ti, 10, V.solver_opts(rtol=1e-8))
+    for s in (0, 5, 9):
         ratio = _oracle_residual_ratio(mesh, mat, ti, s, states[s], states[s + 1])
+        print(f"[sweep32] nu={nu} step {s} oracle |R|/|R0| = {ratio:.3e}", flush=True)
         assert ratio <= 1.5e-8, (nu, s, ratio)
 
 
@@ -174,31 +177,59 @@ def test_full_tube_time_step_satisfies_oracle_equations():
     assert ratio <= 1.5e-8
 
 
-def test_cube32_adjoint_matches_central_differences():
-    mesh, mat, ti = synth.cube_case(32, nu=0.499, n_steps=10)
+def _adjoint_vs_fd(mesh, mat, ti, n_steps, sel, params, theta0, seed, sopts, nopts, rel, h_rel=None):
+    """J = 1/2 ||u_sel - u_target||^2 with u_target from a forward run at seeded, perturbed
+    parameters; the autograd gradient against central differences (step h_rel[k] relative,
+    1e-6 by default, tolerance rel[k] relative with no absolute floor)."""
+    h_rel = h_rel or {}
     prob = _problem(mesh, mat)
-    sopts = V.solver_opts(rtol=1e-12, rtol_A=1e-12, rtol_S=1e-12, rtol_I=1e-13)
-    nopts = V.newton_opts(tol_R=1e-12)
-    hist = GA.TimeHistory(prob, ti, 2, nopts, sopts, sopts, 0b00011)
-    theta0 = np.array([mat.mu, mat.kappa, 0.0, 0.0, 0.0])
-    top = torch.from_numpy(np.isclose(mesh.X[:, 2], 1.0)).cuda()
-    u0 = hist.run(theta0).clone()
-    target = 0.9 * u0[top]
+    pmask = sum(1 << k for k in params)
+    hist = GA.TimeHistory(prob, ti, n_steps, nopts, sopts, sopts, pmask)
+    rng = np.random.default_rng(seed)
+    th_t = theta0.copy()
+    for k in params:
+        th_t[k] *= 1.0 + 0.05 * rng.uniform(-1.0, 1.0)
+    selt = torch.from_numpy(sel).cuda()
+    target = hist.run(th_t)[selt].clone()
 
     def J_of(theta):
         u = hist.run(theta)
-        return 0.5 * float(((u[top] - target) ** 2).sum())
+        print("[adjoint] forward Newton histories:", [st["res_norm"] for st in hist.stats], flush=True)
+        return 0.5 * float(((u[selt] - target) ** 2).sum())
 
     theta = torch.tensor(theta0, requires_grad=True)
     u = GA.VmsAdjoint.apply(theta, hist)
-    J = 0.5 * ((u[top] - target) ** 2).sum()
+    J = 0.5 * ((u[selt] - target) ** 2).sum()
     J.backward()
     g = theta.grad.numpy()
-    for k in (0, 1):
-        h = 1e-6 * theta0[k]
+    for k in params:
+        h = h_rel.get(k, 1e-6) * abs(theta0[k])
         tp, tm = theta0.copy(), theta0.copy()
         tp[k] += h
         tm[k] -= h
         fd = (J_of(tp) - J_of(tm)) / (2 * h)
-        print(f"[adjoint32] k={k} adjoint={g[k]:.8e} fd={fd:.8e}", flush=True)
-        assert g[k] == pytest.approx(fd, rel=1e-4)
+        print(f"[adjoint] param {k}: adjoint={g[k]:.10e} fd={fd:.10e} rel.diff={abs(g[k] - fd) / abs(fd):.2e}",
+              flush=True)
+        assert g[k] == pytest.approx(fd, rel=rel[k], abs=0.0)
+
+
+def test_cube32_adjoint_matches_central_differences():
+    mesh, mat, ti = synth.cube_case(32, nu=0.499, n_steps=10)
+    sopts = V.solver_opts(rtol=1e-12, rtol_A=1e-12, rtol_S=1e-12, rtol_I=1e-13)
+    theta0 = np.array([mat.mu, mat.kappa, 0.0, 0.0, 0.0])
+    _adjoint_vs_fd(mesh, mat, ti, 2, np.isclose(mesh.X[:, 2], 1.0), (0, 1), theta0, 5, sopts,
+                   V.newton_opts(tol_R=1e-12), rel={0: 1e-5, 1: 1e-5})
+
+
+def test_full_tube_adjoint_matches_central_differences():
+    """The artery mesh at full size (8 x 256 x 160, 1 966 080 tets): dJ/d(mu, k1, k2, fibre angle).
+    The forward solves bottom out at a relative residual of 2e-11 on this mesh.  dJ/dk2 scales with
+    the fourth power of the 0.1 % fibre strain, so a 1e-6 step in k2 changes J by less than that
+    floor does; k2 takes a 1e-3 step (truncation error ~1e-6)."""
+    mesh, mat, ti = synth.tube_case(8, 256, 160, dt=1e-3, n_steps=20, stretch=1.001)
+    sopts = V.solver_opts(rtol=1e-12, rtol_A=1e-12, rtol_S=1e-12, rtol_I=1e-13)
+    theta0 = np.array([mat.mu, 0.0, mat.k1, mat.k2, mesh.meta["fibre_rad"]])
+    r = np.hypot(mesh.X[:, 0], mesh.X[:, 1])
+    _adjoint_vs_fd(mesh, mat, ti, 1, np.isclose(r, 1.2), (0, 2, 3, 4), theta0, 6, sopts,
+                   V.newton_opts(tol_R=1e-11, l_max=30), rel={0: 1e-5, 2: 1e-5, 3: 1e-5, 4: 1e-5},
+                   h_rel={3: 1e-3})

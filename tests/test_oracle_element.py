@@ -175,7 +175,7 @@ def test_rest_state_blocks_reduce_to_textbook_operators():
                 np.testing.assert_allclose(K[0:3, 0:3], A_tb, rtol=1e-12, atol=1e-12 * np.abs(A_tb).max())
                 np.testing.assert_allclose(K[0:3, 3], B_tb, rtol=1e-12, atol=1e-13 * np.abs(B_tb).max())
                 np.testing.assert_allclose(K[3, 0:3], C_tb, rtol=1e-12, atol=1e-13 * np.abs(C_tb).max())
-                assert K[3, 3] == pytest.approx(D_tb, rel=1e-12)
+                assert K[3, 3] == pytest.approx(D_tb, rel=1e-12, abs=0.0)
 
 
 def test_tau_m_values():
@@ -183,4 +183,4 @@ def test_tau_m_values():
     for N, nu, expect in ((32, 0.45, 1.63e-9), (64, 0.499, 1.21e-10)):
         mat = synth.material_from_nu(1e5, nu)
         Xe = np.array([[[0, 0, 0], [1, 0, 0], [1, 1, 0], [1, 1, 1]]], dtype=float) / N
-        assert E.tau_m(Xe, mat)[0] == pytest.approx(expect, rel=5e-3)
+        assert E.tau_m(Xe, mat)[0] == pytest.approx(expect, rel=5e-3, abs=0.0)
