@@ -175,7 +175,9 @@ def main():
     ap.add_argument("--forms", default="fp64,mixed")
     ap.add_argument("--shat-degree", type=int, default=8)
     ap.add_argument("--shat-ratio", type=float, default=20.0)
-    ap.add_argument("--mixed-tol", default="1e-6,1e-6,1e-4",
+    ap.add_argument("--fp64-tol", default="1e-5,3e-6,1e-4",
+                    help="intermediate A, Schur and inner tolerances of the FP64 form")
+    ap.add_argument("--mixed-tol", default="1e-5,3e-6,1e-4",
                     help="intermediate A, Schur and inner tolerances of the mixed form")
     ap.add_argument("--orth", default="cgs1", choices=["cgs2", "cgs1", "cgs_ifneeded", "mgs"],
                     help="Arnoldi orthogonalisation of every Krylov level")
@@ -203,13 +205,14 @@ def main():
     n, nnzb = mesh.n_nodes, int(prob.host["row_len"].sum())   # real blocks (slots: prob.nnzb)
     nopts = V.newton_opts(tol_R=1e-8, l_max=20)
     mt = [float(x) for x in args.mixed_tol.split(",")]
+    ft = [float(x) for x in args.fp64_tol.split(",")]
     if args.spmv_only:
         spmv_only(prob, mesh, ti, args.spmv_only)
         return
     orth = {"cgs2": V.ORTH_CGS2, "cgs1": V.ORTH_CGS1, "cgs_ifneeded": V.ORTH_CGS_IFNEEDED,
             "mgs": V.ORTH_MGS}[args.orth]
     forms = {
-        "fp64": V.solver_opts(rtol=1e-8, rtol_A=1e-6, rtol_S=1e-6, rtol_I=1e-4, shat_degree=args.shat_degree,
+        "fp64": V.solver_opts(rtol=1e-8, rtol_A=ft[0], rtol_S=ft[1], rtol_I=ft[2], shat_degree=args.shat_degree,
                               shat_ratio=args.shat_ratio, orth=orth),
         "mixed": V.solver_opts(rtol=1e-8, rtol_A=mt[0], rtol_S=mt[1], rtol_I=mt[2], precision=V.MIXED,
                                shat_degree=args.shat_degree, shat_ratio=args.shat_ratio, orth=orth),

@@ -32,8 +32,8 @@ class VmsError(RuntimeError):
         self.code = code
 
 
-def solver_opts(rtol=1e-8, atol=1e-50, maxit=200, rtol_A=1e-6, atol_A=1e-50, maxit_A=500,
-                rtol_S=1e-6, atol_S=1e-50, maxit_S=200, rtol_I=1e-4, atol_I=1e-50, maxit_I=500,
+def solver_opts(rtol=1e-8, atol=1e-50, maxit=200, rtol_A=1e-5, atol_A=1e-50, maxit_A=500,
+                rtol_S=3e-6, atol_S=1e-50, maxit_S=200, rtol_I=1e-4, atol_I=1e-50, maxit_I=500,
                 precond=PC_LDU, precision=FP64, orth=ORTH_CGS1, shat_degree=8,
                 shat_ratio=20.0) -> L.SolverOpts:
     return L.SolverOpts(rtol, atol, maxit, rtol_A, atol_A, maxit_A, rtol_S, atol_S, maxit_S,
