@@ -725,7 +725,8 @@ vms_ga vms_genalpha(const vms_timeint *ti) {
 }
 
 int vms_check_mesh(vms_ctx *ctx, const vms_mesh *m) {
-  if (!m || m->n_nodes <= 0 || m->n_tets < 0 || m->n_tets > VMS_MAX_TETS || m->nnzb <= 0 || !m->X || !m->tets ||
+  if (!m || m->n_nodes <= 0 || m->n_tets < 0 || m->n_tets > VMS_MAX_TETS || m->nnzb <= 0 || !m->X ||
+      (m->n_tets > 0 && !m->tets) ||
       !m->dir_mask || m->slot_width < 16 || (m->slot_width & 15) || m->nnzb != (int64_t)m->slot_width * m->n_nodes ||
       !m->col || !m->tpos || !m->diag_pos || !m->blk_src_ptr || !m->shat_col || m->shat_width < 64 || (m->shat_width & 63) ||
       m->shat_width > VMS_MAX_SHAT_ROW ||

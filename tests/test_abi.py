@@ -131,3 +131,49 @@ def test_setup_rejects_out_of_range_nodes():
     tets = np.array([[0, 1, 2, 7]], np.int32)
     nnzb, sw, w2 = C.c_int64(), C.c_int32(), C.c_int32()
     assert lib.vms_setup_sizes(4, 1, tets.ctypes.data, C.byref(nnzb), C.byref(sw), C.byref(w2)) == -1
+
+
+def _sizes(n, tets):
+    lib = L.load()
+    tets = np.ascontiguousarray(tets, np.int32).reshape(-1, 4)
+    nnzb, sw, w2 = C.c_int64(), C.c_int32(), C.c_int32()
+    rc = lib.vms_setup_sizes(n, tets.shape[0], tets.ctypes.data, C.byref(nnzb), C.byref(sw), C.byref(w2))
+    return rc, nnzb.value, sw.value, w2.value
+
+
+def test_setup_isolated_nodes_and_empty_mesh():
+    """Nodes outside every element keep a diagonal block (no contributions, empty distance-2 row);
+    a mesh with no elements has only such rows."""
+    mesh = synth.cube_mesh(1)
+    n0 = mesh.n_nodes
+    X = np.vstack([mesh.X, [[5.0, 5.0, 5.0], [6.0, 6.0, 6.0]]])
+    m2 = type(mesh)(**{**mesh.__dict__, "X": X, "dir_mask": np.zeros((n0 + 2, 4), np.uint8),
+                       "dir_vel": np.zeros((n0 + 2, 3))})
+    h = build_host(m2)
+    W = h["W"]
+    for i in (n0, n0 + 1):
+        assert h["row_len"][i] == 1
+        np.testing.assert_array_equal(h["col"][W * i:W * i + W], i)
+        assert h["diag_pos"][i] == W * i
+        b = h["diag_pos"][i]
+        assert h["blk_src_ptr"][b + 1] == h["blk_src_ptr"][b]
+        np.testing.assert_array_equal(h["shat_col"].reshape(-1, h["W2"])[i], i)
+    rc, nnzb, sw, w2 = _sizes(3, np.zeros((0, 4), np.int32))
+    assert rc == 0 and sw == 16 and nnzb == 48 and w2 == 64
+
+
+def test_setup_limits():
+    """n_tets beyond VMS_MAX_TETS is refused before the array is read; a distance-2 row longer
+    than VMS_MAX_SHAT_ROW (here: every node couples to a hub node) is refused."""
+    lib = L.load()
+    small = np.zeros(4, np.int32)
+    nnzb, sw, w2 = C.c_int64(), C.c_int32(), C.c_int32()
+    assert lib.vms_setup_sizes(4, 134217728, small.ctypes.data, C.byref(nnzb), C.byref(sw), C.byref(w2)) == -1
+    assert lib.vms_setup_sizes(4, -1, small.ctypes.data, C.byref(nnzb), C.byref(sw), C.byref(w2)) == -1
+    assert lib.vms_setup_sizes(4, 1, small.ctypes.data, None, C.byref(sw), C.byref(w2)) == -1
+    hub = np.array([[0, 3 * k + 1, 3 * k + 2, 3 * k + 3] for k in range(66)], np.int32)
+    rc, nnzb_, sw_, w2_ = _sizes(199, hub)
+    assert rc == -1
+    few = hub[:20]                     # 61 nodes: the longest distance-2 row has 60 entries
+    rc, nnzb_, sw_, w2_ = _sizes(61, few)
+    assert rc == 0 and sw_ == 64 and w2_ == 64 and nnzb_ == 64 * 61
