@@ -77,10 +77,7 @@ __global__ void k_post_flags(const int *dev, volatile int32_t *host, int32_t seq
   host[0] = seq;
 }
 
-int vms_read_flags(vms_ctx *ctx, const int *dev) {
-  const int32_t seq = ++ctx->post_seq;
-  hipLaunchKernelGGL(k_post_flags, dim3(1), dim3(64), 0, ctx->stream, dev, ctx->h_post, seq);
-  VMS_LAUNCH_CHECK(ctx);
+int vms_wait_post(vms_ctx *ctx, int32_t seq, const int *dev) {
   for (long spin = 0;; ++spin) {
     if (ctx->h_post[0] == seq) {
       std::atomic_thread_fence(std::memory_order_acquire);
@@ -100,6 +97,13 @@ int vms_read_flags(vms_ctx *ctx, const int *dev) {
       }
     }
   }
+}
+
+int vms_read_flags(vms_ctx *ctx, const int *dev) {
+  const int32_t seq = ++ctx->post_seq;
+  hipLaunchKernelGGL(k_post_flags, dim3(1), dim3(64), 0, ctx->stream, dev, ctx->h_post, seq);
+  VMS_LAUNCH_CHECK(ctx);
+  return vms_wait_post(ctx, seq, dev);
 }
 
 // ---- launch timing of the A-block product --------------------------------------

@@ -108,28 +108,6 @@ __device__ __forceinline__ double sum_partials1(const double *part, int nb, doub
   return block_sum(s, sm);
 }
 
-// beta = ||b||, tolerance, g0 and the level flags
-__global__ void __launch_bounds__(VMS_BLOCK)
-k_kinit_finalize(int nb, double *ctrl, KOff off, int *iflag, double rtol, double atol) {
-  __shared__ double sm[4];
-  const double s = sum_partials1(ctrl + off.part, nb, sm);
-  if (threadIdx.x == 0) {
-    const double beta = sqrt(s);
-    ctrl[off.scal + 0] = beta;
-    ctrl[off.scal + 1] = fmax(rtol * beta, atol);
-    ctrl[off.scal + 2] = beta;
-    ctrl[off.g] = beta;
-    iflag[IF_ITS] = 0;
-    if (!isfinite(beta)) {
-      iflag[IF_STATUS] = KS_NAN;
-      iflag[IF_DONE] = 1;
-    } else {
-      iflag[IF_STATUS] = KS_OK;
-      iflag[IF_DONE] = (beta == 0.0 || beta <= atol) ? 1 : 0;
-    }
-  }
-}
-
 // V_j = w / scale; Z_j = M^-1 V_j (block-Jacobi 3x3 or point diagonal)
 template <typename T>
 __device__ __forceinline__ void scale_and_precond(int64_t nvec, const T *w, double inv, T *V, T *Z, int pc,
@@ -156,12 +134,27 @@ __device__ __forceinline__ void scale_and_precond(int64_t nvec, const T *w, doub
   }
 }
 
+// Start of a level: beta = ||b|| from the k_norm_part partials (every
+// workgroup reduces them in the same order), V_0 = b / beta, Z_0 = M^-1 V_0;
+// workgroup 0 also sets the tolerance, g_0 and the level flags.
 template <typename T>
 __global__ void __launch_bounds__(VMS_BLOCK)
-k_kinit_scale(int64_t nvec, const T *__restrict__ b, T *V0, T *Z0, const double *ctrl, KOff off, const int *iflag,
-              int pc, const T *pcd) {
-  if (iflag[IF_DONE]) return;
-  scale_and_precond(nvec, b, 1.0 / ctrl[off.scal + 0], V0, Z0, pc, pcd);
+k_kinit(int64_t nvec, const T *__restrict__ b, T *V0, T *Z0, double *ctrl, KOff off, int *iflag, int nb,
+        double rtol, double atol, int pc, const T *pcd) {
+  __shared__ double sm[4];
+  const double beta = sqrt(sum_partials1(ctrl + off.part, nb, sm));
+  const bool done = !isfinite(beta) || beta == 0.0 || beta <= atol;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    ctrl[off.scal + 0] = beta;
+    ctrl[off.scal + 1] = fmax(rtol * beta, atol);
+    ctrl[off.scal + 2] = beta;
+    ctrl[off.g] = beta;
+    iflag[IF_ITS] = 0;
+    iflag[IF_STATUS] = isfinite(beta) ? KS_OK : KS_NAN;
+    iflag[IF_DONE] = done ? 1 : 0;
+  }
+  if (done) return;
+  scale_and_precond(nvec, b, 1.0 / beta, V0, Z0, pc, pcd);
 }
 
 // sum of the nbp (<= KRY_MAX_BLOCKS) partials p[0], p[ld], ... in a fixed order
@@ -419,6 +412,14 @@ __device__ void givens_update(double *ctrl, const KOff &off, int *iflag, int j, 
   }
 }
 
+// Copy the level flags, then (after a system-scope fence) the sequence number,
+// into the coherent host buffer the host spins on.
+__device__ __forceinline__ void post_flags(const int *iflag, volatile int32_t *post, int32_t seq) {
+  for (int q = 0; q < 4; ++q) post[1 + q] = iflag[q];
+  __threadfence_system();
+  post[0] = seq;
+}
+
 // MGS path: Hessenberg column already in place, ||w||^2 partials in part
 __global__ void __launch_bounds__(VMS_BLOCK)
 k_givens(int nb, double *ctrl, KOff off, int *iflag, int j, int maxit) {
@@ -438,12 +439,21 @@ k_givens(int nb, double *ctrl, KOff off, int *iflag, int j, int maxit) {
 template <typename T>
 __global__ void __launch_bounds__(KRY_BLOCK)
 k_normalize_givens(int64_t nvec, const T *__restrict__ w, T *V1, T *Z1, double *ctrl, KOff off, int *iflag, int nbp,
-                   int j, int nsum, int maxit, int pc, const T *pcd) {
-  if (iflag[IF_DONE]) return;
+                   int j, int nsum, int maxit, int pc, const T *pcd, volatile int32_t *post, int32_t seq) {
   __shared__ double sm[16];
+  __shared__ int done0;   // one read per workgroup: workgroup 0 may set the flag during this kernel
+  if (threadIdx.x == 0) done0 = iflag[IF_DONE];
+  __syncthreads();
+  if (done0) {
+    if (post && blockIdx.x == 0 && threadIdx.x == 0) post_flags(iflag, post, seq);
+    return;
+  }
   if (nsum == 3) nsum = kry_need_reorth(ctrl, off, nbp, j + 1, sm) ? 2 : 1;   // "if needed" mode
   const double hn = sqrt(kry_sum_partials(ctrl + (nsum == 2 ? off.pn2 : off.pn), nbp, 1, sm));
-  if (blockIdx.x == 0 && threadIdx.x == 0) givens_update(ctrl, off, iflag, j, nsum, maxit, hn);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    givens_update(ctrl, off, iflag, j, nsum, maxit, hn);
+    if (post) post_flags(iflag, post, seq);   // the host may decide while the normalisation runs
+  }
   scale_and_precond(nvec, w, hn > 0.0 ? 1.0 / hn : 0.0, V1, Z1, pc, pcd);
 }
 
@@ -516,6 +526,34 @@ k_combine(int64_t nvec, const T *__restrict__ Z, const double *ctrl, KOff off, c
       for (int l = 0; l < kn; ++l) acc += ys[l] * dl(Z, (int64_t)(c0 + l) * nvec + r);
       x[r] = (T)acc;
     }
+  }
+}
+
+// Back substitution and x = sum_l y_l Z_l in one kernel for short bases: every
+// workgroup solves the (its x its) triangular system in LDS (same order, same
+// result) before its rows of the combination.
+#define COMBINE_SOLVE_MAX 64
+template <typename T>
+__global__ void __launch_bounds__(VMS_BLOCK)
+k_solve_combine(int64_t nvec, const T *__restrict__ Z, const double *ctrl, KOff off, const int *iflag, T *x) {
+  __shared__ double gs[COMBINE_SOLVE_MAX];
+  __shared__ double ys[COMBINE_SOLVE_MAX];
+  const int k = iflag[IF_ITS];
+  const int m1 = off.m + 1;
+  const double *H = ctrl + off.H;
+  if (threadIdx.x < k) gs[threadIdx.x] = ctrl[off.g + threadIdx.x];
+  __syncthreads();
+  for (int i = k - 1; i >= 0; --i) {
+    if (threadIdx.x == 0) ys[i] = gs[i] / H[(int64_t)i * m1 + i];
+    __syncthreads();
+    if (threadIdx.x < i) gs[threadIdx.x] -= H[(int64_t)i * m1 + threadIdx.x] * ys[i];
+    __syncthreads();
+  }
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < nvec; r += stride) {
+    double acc = 0.0;
+    for (int l = 0; l < k; ++l) acc += ys[l] * dl(Z, (int64_t)l * nvec + r);
+    x[r] = (T)acc;
   }
 }
 
@@ -813,7 +851,8 @@ inline int sync_level_flags(vms_ctx *ctx, const int *iflag) { return vms_read_fl
 //         kry_need_reorth asks for it (its kernels return at once otherwise)
 //   MGS:  one dot/axpy launch pair per basis vector
 template <typename T>
-int orth_level(vms_ctx *ctx, KLevel<T> &L, int j, int maxit, int mode, int pc, const T *pcd) {
+int orth_level(vms_ctx *ctx, KLevel<T> &L, int j, int maxit, int mode, int pc, const T *pcd,
+               volatile int32_t *post = nullptr, int32_t seq = 0) {
   hipStream_t s = ctx->stream;
   double *part = L.ctrl + L.off.part;
   const int ld = L.m + 1;
@@ -855,7 +894,7 @@ int orth_level(vms_ctx *ctx, KLevel<T> &L, int j, int maxit, int mode, int pc, c
     }
     const int nsum = (mode == VMS_ORTH_CGS2) ? 2 : (mode == VMS_ORTH_CGS_IFNEEDED) ? 3 : 1;
     hipLaunchKernelGGL(k_normalize_givens<T>, gk, bk, 0, s, L.nvec, (const T *)L.W, V1, Z1, L.ctrl, L.off, L.iflag,
-                       L.nbk, j, nsum, maxit, pc, pcd);
+                       L.nbk, j, nsum, maxit, pc, pcd, post, seq);
   }
   VMS_LAUNCH_CHECK(ctx);
   return VMS_OK;
@@ -872,33 +911,43 @@ int gmres_run(vms_ctx *ctx, KLevel<T> &L, const T *b, T *x, double rtol, double 
   hipStream_t s = ctx->stream;
   maxit = std::min(maxit, L.m);
   const dim3 gr(L.nb), bl(VMS_BLOCK);
-  hipLaunchKernelGGL(k_clear_ints, dim3(1), dim3(64), 0, s, L.iflag, 4);
   hipLaunchKernelGGL(k_norm_part<T>, gr, bl, 0, s, L.nvec, b, L.ctrl + L.off.part, (const int *)nullptr);
-  hipLaunchKernelGGL(k_kinit_finalize, dim3(1), bl, 0, s, L.nb, L.ctrl, L.off, L.iflag, rtol, atol);
-  hipLaunchKernelGGL(k_kinit_scale<T>, gr, bl, 0, s, L.nvec, b, L.V, L.Z, L.ctrl, L.off, L.iflag, pc, pcd);
+  hipLaunchKernelGGL(k_kinit<T>, gr, bl, 0, s, L.nvec, b, L.V, L.Z, L.ctrl, L.off, L.iflag, L.nb, rtol, atol, pc, pcd);
   VMS_LAUNCH_CHECK(ctx);
   int j = 0, rc;
-  bool done = false;
+  bool done = false, read = false;
   if (sync_each) {
     if ((rc = sync_level_flags(ctx, L.iflag))) return rc;
     done = ctx->h_i[IF_DONE] != 0;
+    read = true;
   }
+  const bool posting = (orth != VMS_ORTH_MGS);   // the last normalisation kernel of a batch posts the flags
   int batch = sync_each ? 1 : std::max(1, est);
   while (!done && j < maxit) {
     const int nbt = std::min(batch, maxit - j);
+    int32_t seq = 0;
     for (int i = 0; i < nbt; ++i, ++j) {
       if ((rc = op(j))) return rc;
-      if ((rc = orth_level<T>(ctx, L, j, maxit, orth, pc, pcd))) return rc;
+      const bool last = posting && (i == nbt - 1);
+      if (last) seq = ++ctx->post_seq;
+      if ((rc = orth_level<T>(ctx, L, j, maxit, orth, pc, pcd, last ? ctx->h_post : nullptr, seq))) return rc;
     }
     VMS_LAUNCH_CHECK(ctx);
-    if ((rc = sync_level_flags(ctx, L.iflag))) return rc;
+    if ((rc = posting ? vms_wait_post(ctx, seq, L.iflag) : sync_level_flags(ctx, L.iflag))) return rc;
     done = ctx->h_i[IF_DONE] != 0;
+    read = true;
     if (!sync_each) batch = std::min(2 * batch, 64);
   }
+  if (!read && (rc = sync_level_flags(ctx, L.iflag))) return rc;
   status_out = ctx->h_i[IF_STATUS];
   its_out = ctx->h_i[IF_ITS];
-  hipLaunchKernelGGL(k_trisolve, dim3(1), bl, 0, s, L.ctrl, L.off, L.iflag);
-  hipLaunchKernelGGL(k_combine<T>, gr, bl, 0, s, L.nvec, L.Z, L.ctrl, L.off, L.iflag, x);
+  if (its_out <= COMBINE_SOLVE_MAX) {
+    hipLaunchKernelGGL(k_solve_combine<T>, gr, bl, 0, s, L.nvec, (const T *)L.Z, (const double *)L.ctrl, L.off,
+                       (const int *)L.iflag, x);
+  } else {
+    hipLaunchKernelGGL(k_trisolve, dim3(1), bl, 0, s, L.ctrl, L.off, L.iflag);
+    hipLaunchKernelGGL(k_combine<T>, gr, bl, 0, s, L.nvec, L.Z, L.ctrl, L.off, L.iflag, x);
+  }
   VMS_LAUNCH_CHECK(ctx);
   est = std::max(1, its_out);
   if (status_out == KS_NAN) return vms_set_error(ctx, VMS_ERR_NAN, "NaN/Inf in a Krylov level");

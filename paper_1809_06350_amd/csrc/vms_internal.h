@@ -55,6 +55,10 @@ struct vms_ctx {
 // the stream has finished, by the low-latency path (falls back to a stream
 // synchronisation if the posted sequence number does not arrive).
 int vms_read_flags(vms_ctx *ctx, const int *dev);
+// Wait until sequence number seq has been posted to ctx->h_post by a kernel
+// already enqueued, then copy the posted flags to ctx->h_i (on a failed or
+// drained stream: as vms_read_flags, reading the flags at dev).
+int vms_wait_post(vms_ctx *ctx, int32_t seq, const int *dev);
 
 // Next timed launch of the A-block product (kind 0 FP64, 1 FP32) when timing
 // is on: the start/stop events that the launch passes to hipExtLaunchKernelGGL
