@@ -7,7 +7,9 @@ workload: 64^3 hexes x 6 Kuhn tets (1,572,864 tets, 274,625 nodes,
 1,098,500 unknowns), mu = 1e5, nu = 0.499, rho0 = 1000, dt = 1e-3, top
 traction -1e4 ramped over 10 steps.  Timed steps start from rest after the
 warm-up steps, so every run does the same work.  Both solver forms run:
-FP64 and mixed (FP32 intermediate/inner levels, FP64 outer FGMRES/Newton).
+FP64 (GMRES at every level) and mixed (FP32 intermediate/inner levels with
+CG on the A-solves, FP64 outer FGMRES/Newton); --fp64-a-krylov and
+--mixed-a-krylov choose the A-level method of each form.
 
 Prints one JSON line (value = Newton iterations per second of the FP64 form).
 """
@@ -181,6 +183,12 @@ def main():
                     help="intermediate A, Schur and inner tolerances of the mixed form")
     ap.add_argument("--orth", default="cgs1", choices=["cgs2", "cgs1", "cgs_ifneeded", "mgs"],
                     help="Arnoldi orthogonalisation of every Krylov level")
+    akc = ["gmres", "cg-inner", "cg", "cg-inner-sym", "cg-sym"]
+    ap.add_argument("--fp64-a-krylov", default="gmres", choices=akc,
+                    help="Krylov method of the A-solves in the FP64 form: GMRES, or CG at the inner level or at "
+                         "both A-levels, on A itself or on (A + A^T)/2 (-sym)")
+    ap.add_argument("--mixed-a-krylov", default="cg", choices=akc,
+                    help="the same for the mixed form")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-timing", action="store_true",
                     help="also event-time every A-block product launch inside the timed steps (each launch then "
@@ -211,11 +219,16 @@ def main():
         return
     orth = {"cgs2": V.ORTH_CGS2, "cgs1": V.ORTH_CGS1, "cgs_ifneeded": V.ORTH_CGS_IFNEEDED,
             "mgs": V.ORTH_MGS}[args.orth]
+    akm = {"gmres": (V.AK_GMRES, 0), "cg-inner": (V.AK_CG_INNER, 0), "cg": (V.AK_CG, 0),
+           "cg-inner-sym": (V.AK_CG_INNER, 1), "cg-sym": (V.AK_CG, 1)}
+    fk, fs = akm[args.fp64_a_krylov]
+    mk, ms = akm[args.mixed_a_krylov]
     forms = {
         "fp64": V.solver_opts(rtol=1e-8, rtol_A=ft[0], rtol_S=ft[1], rtol_I=ft[2], shat_degree=args.shat_degree,
-                              shat_ratio=args.shat_ratio, orth=orth),
+                              shat_ratio=args.shat_ratio, orth=orth, a_krylov=fk, cg_symmetrise=fs),
         "mixed": V.solver_opts(rtol=1e-8, rtol_A=mt[0], rtol_S=mt[1], rtol_I=mt[2], precision=V.MIXED,
-                               shat_degree=args.shat_degree, shat_ratio=args.shat_ratio, orth=orth),
+                               shat_degree=args.shat_degree, shat_ratio=args.shat_ratio, orth=orth, a_krylov=mk,
+                               cg_symmetrise=ms),
     }
     results = {}
     for name in args.forms.split(","):
@@ -278,6 +291,7 @@ def main():
                       "nodes": n, "tets": mesh.n_tets, "unknowns": 4 * n, "nnzb": nnzb,
                       "block_slots": prob.nnzb,
                       "shat_degree": args.shat_degree, "shat_ratio": args.shat_ratio, "orth": args.orth,
+                      "a_krylov": {"fp64": args.fp64_a_krylov, "mixed": args.mixed_a_krylov},
                       "parallelism": "single GPU"},
            "roofline": roof}
     out.update(extra)

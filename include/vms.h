@@ -78,6 +78,18 @@ enum { VMS_FP64 = 0, VMS_MIXED = 1 };
  * when the first one removed more than half of ||w||^2 */
 enum { VMS_ORTH_CGS2 = 0, VMS_ORTH_MGS = 1, VMS_ORTH_CGS1 = 2, VMS_ORTH_CGS_IFNEEDED = 3 };
 
+/* Krylov method of the A-solves.  The paper's conclusions suggest symmetrising
+ * the inner A system of the Schur product (Algorithm 2) and solving it by
+ * conjugate gradients: VMS_AK_GMRES keeps GMRES on A at both A-levels;
+ * VMS_AK_CG_INNER runs preconditioned CG (3x3 block-Jacobi) at the inner
+ * level only; VMS_AK_CG at the inner and intermediate levels.  CG runs on
+ * A_s = (A + A^T)/2 when cg_symmetrise is set (then the block-Jacobi
+ * preconditioner of both A-levels is built from the symmetrised diagonal
+ * blocks), otherwise on A as assembled (A is symmetric when the accelerations
+ * vanish, and nearly so otherwise).  Only preconditioner applications change:
+ * the outer FGMRES still solves the unsymmetrised system. */
+enum { VMS_AK_GMRES = 0, VMS_AK_CG_INNER = 1, VMS_AK_CG = 2 };
+
 typedef struct vms_ctx vms_ctx;
 
 typedef struct {
@@ -144,6 +156,8 @@ typedef struct {
   int32_t shat_degree;/* right preconditioner of the Schur solve: 0 = diag(S^)^-1; k > 0 = degree-k
                          Chebyshev polynomial in diag(S^)^-1 S^ on [lmax/shat_ratio, lmax] */
   double shat_ratio;  /* lmax / lmin of the Chebyshev interval (used when shat_degree > 0) */
+  int32_t a_krylov;   /* VMS_AK_*: GMRES or CG at the inner (or both) A-levels */
+  int32_t cg_symmetrise; /* CG levels: 1 = on (A + A^T)/2, 0 = on A */
 } vms_solver_opts;
 
 typedef struct {

@@ -560,12 +560,16 @@ k_solve_combine(int64_t nvec, const T *__restrict__ Z, const double *ctrl, KOff 
 // ---- preconditioner setup --------------------------------------------------
 // inverse of the 3x3 diagonal blocks of the scaled A
 template <typename T>
-__global__ void k_bj33_setup(int n, const int32_t *diag_pos, int64_t nnzb, const double *A, T *Minv) {
+__global__ void k_bj33_setup(int n, const int32_t *diag_pos, int64_t nnzb, const double *A, T *Minv, int sym) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const int64_t b = diag_pos[i];
   double a[9];
   for (int e = 0; e < 9; ++e) a[e] = A[e * nnzb + b];
+  if (sym) {   // inverse of the symmetric part of the diagonal block
+    for (int r = 0; r < 3; ++r)
+      for (int c = r + 1; c < 3; ++c) a[3 * r + c] = a[3 * c + r] = 0.5 * (a[3 * r + c] + a[3 * c + r]);
+  }
   const double c00 = a[4] * a[8] - a[5] * a[7], c01 = a[5] * a[6] - a[3] * a[8], c02 = a[3] * a[7] - a[4] * a[6];
   const double det = a[0] * c00 + a[1] * c01 + a[2] * c02;
   const double id = (det != 0.0) ? 1.0 / det : 0.0;
@@ -580,6 +584,239 @@ __global__ void k_bj33_setup(int n, const int32_t *diag_pos, int64_t nnzb, const
   inv[7] = (a[1] * a[6] - a[0] * a[7]) * id;
   inv[8] = (a[0] * a[4] - a[1] * a[3]) * id;
   for (int e = 0; e < 9; ++e) Minv[9 * (int64_t)i + e] = (T)inv[e];
+}
+
+// ---- conjugate gradients on the symmetrised A --------------------------------
+// The paper's conclusions suggest symmetrising the inner A system and solving
+// it by CG.  A_s = (A + A^T)/2 is formed on the block pattern: block (i,j)
+// and the transpose of block (j,i) (slot tpos) are averaged entry by entry in
+// FP64 and stored in the level precision.  Padding slots (tpos = self, zero
+// values) stay zero.
+template <typename T>
+__global__ void __launch_bounds__(VMS_BLOCK)
+k_sym_A(int64_t nnzb, const int32_t *__restrict__ tpos, const double *__restrict__ A, T *As) {
+  const int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (b >= nnzb) return;
+  const int64_t t = tpos[b];
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+      As[(3 * r + c) * nnzb + b] = (T)(0.5 * (A[(3 * r + c) * nnzb + b] + A[(3 * c + r) * nnzb + t]));
+}
+
+// Sum of nbp partials (any count) by one workgroup in a fixed order; every
+// thread receives the same value.
+__device__ __forceinline__ double cg_sum_partials(const double *p, int nbp, double *sm) {
+  double v = 0.0;
+  for (int q = threadIdx.x; q < nbp; q += blockDim.x) v += p[q];
+  v = wave_sum(v);
+  const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  if ((threadIdx.x & 63) == 0) sm[w] = v;
+  __syncthreads();
+  double r = 0.0;
+  for (int q = 0; q < nw; ++q) r += sm[q];
+  __syncthreads();
+  return r;
+}
+
+// Two sums over a 1024-thread workgroup (fixed order), written by thread 0.
+__device__ __forceinline__ void cg_block_sums2(double a, double b, double *pa, double *pb, double (*sm)[16]) {
+  a = wave_sum(a);
+  b = wave_sum(b);
+  const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  if ((threadIdx.x & 63) == 0) { sm[0][w] = a; sm[1][w] = b; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double ta = 0.0, tb = 0.0;
+    for (int q = 0; q < nw; ++q) { ta += sm[0][q]; tb += sm[1][q]; }
+    *pa = ta;
+    *pb = tb;
+  }
+}
+
+// z = M^-1 r for one node (3x3 block-Jacobi), rounded to T
+template <typename T>
+__device__ __forceinline__ void bj33_apply(const T *M, const double r[3], T z[3]) {
+#pragma unroll
+  for (int c = 0; c < 3; ++c) z[c] = (T)(dl(M, 3 * c) * r[0] + dl(M, 3 * c + 1) * r[1] + dl(M, 3 * c + 2) * r[2]);
+}
+
+// CG start with x0 = 0: r = b, z = M^-1 r, x = 0, and the partials of <r,z>
+// and <r,r> (one per workgroup); resets the level flags.
+template <typename T>
+__global__ void __launch_bounds__(KRY_BLOCK)
+k_cg_init(int64_t nn, const T *__restrict__ b, T *x, T *r, T *z, const T *__restrict__ Minv, double *prz,
+          double *prr, int *iflag) {
+  __shared__ double sm[2][16];
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    iflag[IF_DONE] = 0;
+    iflag[IF_ITS] = 0;
+    iflag[IF_STATUS] = KS_OK;
+  }
+  double rz = 0.0, rr = 0.0;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nn; i += stride) {
+    double rv[3];
+    T zv[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      rv[c] = dl(b, 3 * i + c);
+      r[3 * i + c] = (T)rv[c];
+      x[3 * i + c] = (T)0;
+    }
+    bj33_apply(Minv + 9 * i, rv, zv);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      z[3 * i + c] = zv[c];
+      rz += rv[c] * (double)zv[c];
+      rr += rv[c] * rv[c];
+    }
+  }
+  cg_block_sums2(rz, rr, prz + blockIdx.x, prr + blockIdx.x, sm);
+}
+
+// CG iteration j, first half.  Every workgroup sums the partials of
+// rz_j = <r_j, z_j> and rr_j = <r_j, r_j> and takes the same decision: stop
+// when ||r_j|| <= max(rtol ||b||, atol) (or at maxit, or on NaN); workgroup 0
+// records the flags (and posts them to host memory when asked).  Otherwise,
+// with beta_j = rz_j / rz_{j-1} (beta_0 = 0), w = A z_j is formed and the
+// rows' own entries of p_j = z_j + beta_j p_{j-1} and
+// q_j = A p_j = w + beta_j q_{j-1} are updated in place (only z is gathered),
+// with one partial of <p_j, q_j> per workgroup.  Layout of the A-block product
+// (16 lanes per row, 16 rows per workgroup); a workgroup takes a contiguous
+// range of row groups (XCD-aware order) when the grid is capped.
+#ifndef CG_SPMV_BLOCKS
+#define CG_SPMV_BLOCKS 2048
+#endif
+inline int cg_spmv_blocks(int n) {
+  const int ng = (n + SPMV_ROWS_PER_BLOCK - 1) / SPMV_ROWS_PER_BLOCK;
+  return std::max(1, std::min(ng, CG_SPMV_BLOCKS));
+}
+template <typename T>
+__global__ void __launch_bounds__(VMS_BLOCK)
+k_cg_spmv(int n, int64_t nnzb, int W, const int32_t *__restrict__ col, const T *__restrict__ A,
+          const T *__restrict__ z, T *p, T *q, double *ctrl, KOff off, double *ppart, int *iflag, int j, int nbk,
+          double rtol, double atol, int maxit, volatile int32_t *post, int32_t seq) {
+  __shared__ double sm[16];
+  __shared__ int done0;
+  if (threadIdx.x == 0) done0 = iflag[IF_DONE];
+  __syncthreads();
+  if (done0) {
+    if (post && blockIdx.x == 0 && threadIdx.x == 0) post_flags(iflag, post, seq);
+    return;
+  }
+  const double rz = cg_sum_partials(ctrl + off.pn, nbk, sm);
+  const double rr = cg_sum_partials(ctrl + off.pn2, nbk, sm);
+  const double rn = sqrt(rr);
+  const double tol = (j == 0) ? fmax(rtol * rn, atol) : ctrl[off.scal + 1];
+  const bool bad = !isfinite(rr) || !isfinite(rz);
+  const bool conv = !bad && rn <= tol;
+  const bool stop = bad || conv || j >= maxit;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (j == 0) {
+      ctrl[off.scal + 0] = rn;
+      ctrl[off.scal + 1] = tol;
+    }
+    ctrl[off.scal + 2] = rn;
+    ctrl[off.scal + 3 + (j & 1)] = rz;   // rz_j; rz_{j-1} sits in the other slot
+    if (stop) {
+      iflag[IF_ITS] = j;
+      iflag[IF_STATUS] = bad ? KS_NAN : (conv ? KS_OK : KS_MAXIT);
+      iflag[IF_DONE] = 1;
+    }
+    if (post) post_flags(iflag, post, seq);
+  }
+  if (stop) return;
+  const bool first = (j == 0);
+  const double beta = first ? 0.0 : rz / ctrl[off.scal + 3 + ((j - 1) & 1)];
+  constexpr bool NT = sizeof(T) == 8;
+  const int lane = threadIdx.x & 15, sub = threadIdx.x >> 4;
+  const int ng = (n + SPMV_ROWS_PER_BLOCK - 1) / SPMV_ROWS_PER_BLOCK;
+  const int vb = xcd_block(blockIdx.x, gridDim.x);   // even split: every workgroup gets floor or ceil(ng / grid)
+  const int g0 = (int)((int64_t)vb * ng / gridDim.x), g1 = (int)((int64_t)(vb + 1) * ng / gridDim.x);
+  double pq = 0.0;
+  for (int g = g0; g < g1; ++g) {
+    const int row = g * SPMV_ROWS_PER_BLOCK + sub;
+    const bool act = row < n;
+    const int b0 = act ? W * row : 0, b1 = act ? b0 + W : 0;
+    // lanes 0-2 own component `lane` of the row: its z, p, q are loaded ahead of the product
+    const bool own = act && lane < 3;
+    const int64_t oc = 3 * (int64_t)(act ? row : 0) + (lane < 3 ? lane : 0);
+    double zc = 0.0, pc = 0.0, qc = 0.0;
+    if (own) {
+      zc = ld(z, oc);
+      if (!first) { pc = ld(p, oc); qc = ld(q, oc); }
+    }
+    double a0 = 0, a1 = 0, a2 = 0;
+    for (int b = b0 + lane; b < b1; b += 16) {
+      const int64_t o = 3 * (int64_t)ldc<NT>(col, b);
+      const double x0 = ld(z, o), x1 = ld(z, o + 1), x2 = ld(z, o + 2);
+      a0 += ldm<NT>(A, 0 * nnzb + b) * x0 + ldm<NT>(A, 1 * nnzb + b) * x1 + ldm<NT>(A, 2 * nnzb + b) * x2;
+      a1 += ldm<NT>(A, 3 * nnzb + b) * x0 + ldm<NT>(A, 4 * nnzb + b) * x1 + ldm<NT>(A, 5 * nnzb + b) * x2;
+      a2 += ldm<NT>(A, 6 * nnzb + b) * x0 + ldm<NT>(A, 7 * nnzb + b) * x1 + ldm<NT>(A, 8 * nnzb + b) * x2;
+    }
+    a0 = reduce16(a0);
+    a1 = reduce16(a1);
+    a2 = reduce16(a2);
+    if (own) {
+      const double w = lane == 0 ? a0 : (lane == 1 ? a1 : a2);
+      const T pn = first ? (T)zc : (T)(zc + beta * pc);
+      const T qn = first ? (T)w : (T)(w + beta * qc);
+      p[oc] = pn;
+      q[oc] = qn;
+      pq += (double)pn * (double)qn;
+    }
+  }
+  pq = block_sum(pq, sm);
+  if (threadIdx.x == 0) ppart[blockIdx.x] = pq;
+}
+
+// CG iteration j, second half: alpha = rz_j / <p_j, q> (partials summed by
+// every workgroup), x += alpha p_j, r -= alpha q, z = M^-1 r, and the
+// partials of <r,z> and <r,r> for the next iteration's test.  A non-positive
+// <p, A_s p> ends the level (status breakdown; x keeps the last iterate).
+template <typename T>
+__global__ void __launch_bounds__(KRY_BLOCK)
+k_cg_update(int64_t nn, T *x, T *r, T *z, const T *__restrict__ p, const T *__restrict__ q,
+            const T *__restrict__ Minv, double *ctrl, KOff off, const double *ppart, int nps, int *iflag, int j) {
+  __shared__ double sm[2][16];
+  __shared__ int done0;
+  if (threadIdx.x == 0) done0 = iflag[IF_DONE];
+  __syncthreads();
+  if (done0) return;
+  const double pq = cg_sum_partials(ppart, nps, sm[0]);
+  const double alpha = ctrl[off.scal + 3 + (j & 1)] / pq;
+  if (!(pq > 0.0) || !isfinite(alpha)) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      iflag[IF_ITS] = j;
+      iflag[IF_STATUS] = isfinite(pq) ? KS_BREAKDOWN : KS_NAN;
+      iflag[IF_DONE] = 1;
+    }
+    return;
+  }
+  double rz = 0.0, rr = 0.0;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nn; i += stride) {
+    double rv[3];
+    T zv[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const int64_t o = 3 * i + c;
+      x[o] = (T)(dl(x, o) + alpha * dl(p, o));
+      const T rt = (T)(dl(r, o) - alpha * dl(q, o));
+      r[o] = rt;
+      rv[c] = (double)rt;
+    }
+    bj33_apply(Minv + 9 * i, rv, zv);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      z[3 * i + c] = zv[c];
+      rz += rv[c] * (double)zv[c];
+      rr += rv[c] * rv[c];
+    }
+  }
+  cg_block_sums2(rz, rr, ctrl + off.pn + blockIdx.x, ctrl + off.pn2 + blockIdx.x, sm);
 }
 
 // ---- S^ = D - C diag(A)^-1 B, assembled on the distance-2 pattern ----------
@@ -954,6 +1191,61 @@ int gmres_run(vms_ctx *ctx, KLevel<T> &L, const T *b, T *x, double rtol, double 
   return VMS_OK;
 }
 
+// Preconditioned CG (3x3 block-Jacobi) on the symmetrised A of level L with
+// x0 = 0: two kernels per iteration (product with the direction update, then
+// the vector update); the level's vectors hold r, z, the two alternating
+// directions and q = A_s p.  The stopping test runs at the start of the
+// product kernel, so the host enqueues batches of iterations and reads the
+// flags that the last product kernel of a batch posts.
+template <typename T>
+int cg_run(vms_ctx *ctx, KLevel<T> &L, const vms_mesh *mesh, const T *Acg, double *ppart, const T *b, T *x,
+           double rtol, double atol, int maxit, const T *Minv, int &est, int &its_out, int &status_out) {
+  hipStream_t s = ctx->stream;
+  const int n = mesh->n_nodes;
+  const int64_t nn = n;
+  T *r = L.V, *z = L.Z, *p = L.V + L.nvec, *q = L.W;
+  const int gs = cg_spmv_blocks(n);
+  // vector kernels: two nodes per thread (measured faster than one per thread with twice the workgroups)
+  const dim3 gk(kry_blocks(nn)), bk(KRY_BLOCK), gsp(gs), bl(VMS_BLOCK);
+  const int nbk = (int)gk.x;
+  hipLaunchKernelGGL(k_cg_init<T>, gk, bk, 0, s, nn, b, x, r, z, Minv, L.ctrl + L.off.pn, L.ctrl + L.off.pn2,
+                     L.iflag);
+  auto spmv = [&](int j, volatile int32_t *post, int32_t seq) {
+    hipLaunchKernelGGL(k_cg_spmv<T>, gsp, bl, 0, s, n, (int64_t)mesh->nnzb, (int)mesh->slot_width, mesh->col, Acg,
+                       (const T *)z, p, q, L.ctrl, L.off, ppart, L.iflag, j, nbk, rtol, atol, maxit, post, seq);
+  };
+  int j = 0;
+  spmv(0, nullptr, 0);
+  VMS_LAUNCH_CHECK(ctx);
+  int batch = std::max(1, est);
+  bool done = false;
+  while (!done) {
+    const int nbt = std::min(batch, maxit - j);
+    if (nbt <= 0) {   // not reached: the product kernel of iteration maxit always ends the level
+      int rc = sync_level_flags(ctx, L.iflag);
+      if (rc) return rc;
+      break;
+    }
+    const int32_t seq = ++ctx->post_seq;
+    for (int i = 0; i < nbt; ++i) {
+      hipLaunchKernelGGL(k_cg_update<T>, gk, bk, 0, s, nn, x, r, z, (const T *)p, (const T *)q, Minv, L.ctrl, L.off,
+                         (const double *)ppart, gs, L.iflag, j);
+      ++j;
+      spmv(j, i == nbt - 1 ? ctx->h_post : nullptr, seq);
+    }
+    VMS_LAUNCH_CHECK(ctx);
+    int rc = vms_wait_post(ctx, seq, L.iflag);
+    if (rc) return rc;
+    done = ctx->h_i[IF_DONE] != 0;
+    batch = std::min(2 * batch, 64);
+  }
+  status_out = ctx->h_i[IF_STATUS];
+  its_out = ctx->h_i[IF_ITS];
+  est = std::max(1, its_out);
+  if (status_out == KS_NAN) return vms_set_error(ctx, VMS_ERR_NAN, "NaN/Inf in a CG level");
+  return VMS_OK;
+}
+
 template <typename T>
 struct Nested {
   vms_ctx *ctx;
@@ -966,6 +1258,8 @@ struct Nested {
   KLevel<T> LA, LS;
   T *rv, *rp, *xh, *xp, *xv, *xbar, *xt, *Minv, *sdinv;
   T *Shat, *Shd, *cr, *cd0, *cd1, *px, *py;  // S^ (off-diagonal, diagonal); Chebyshev / power-iteration vectors
+  T *As = nullptr;                            // (A + A^T)/2 for the CG levels (when symmetrised)
+  double *cgpart = nullptr;                   // partials of <p, A p> of the CG product kernel
   double *lam = nullptr;                      // device: lmax estimate of diag(S^)^-1 S^
   vms_solve_stats *stats;
   int err = VMS_OK;
@@ -990,6 +1284,10 @@ struct Nested {
     cd1 = cv.take<T>(nn);
     px = cv.take<T>(nn);
     py = cv.take<T>(nn);
+    if (o_->a_krylov != VMS_AK_GMRES) {
+      cgpart = cv.take<double>(cg_spmv_blocks(m_->n_nodes));
+      if (o_->cg_symmetrise) As = cv.take<T>(9 * m_->nnzb);
+    }
   }
 
   // z = p(diag(S^)^-1 S^) diag(S^)^-1 v: degree-k Chebyshev iteration for S^ z = v
@@ -1035,7 +1333,10 @@ struct Nested {
       return VMS_OK;
     };
     int st = 0;
-    int rc = gmres_run<T>(ctx, LA, b, x, rtol, atol, maxit, o->orth, PC_BJ33, Minv, false, est, op, its, st);
+    const bool cg = inner ? (o->a_krylov != VMS_AK_GMRES) : (o->a_krylov == VMS_AK_CG);
+    int rc = cg ? cg_run<T>(ctx, LA, mesh, o->cg_symmetrise ? (const T *)As : A, cgpart, b, x, rtol, atol, maxit,
+                            Minv, est, its, st)
+                : gmres_run<T>(ctx, LA, b, x, rtol, atol, maxit, o->orth, PC_BJ33, Minv, false, est, op, its, st);
     if (inner) { stats->n_I_solves++; stats->it_I += its; }
     else { stats->n_A_solves++; stats->it_A += its; }
     return rc;
@@ -1098,8 +1399,11 @@ struct Nested {
   }
 
   int setup_precond() {
+    const int sym = (o->a_krylov != VMS_AK_GMRES && o->cg_symmetrise);
     hipLaunchKernelGGL(k_bj33_setup<T>, dim3(grid1(n)), dim3(VMS_BLOCK), 0, ctx->stream, n, mesh->diag_pos, nnzb,
-                       K->A, Minv);
+                       K->A, Minv, sym);
+    if (sym)
+      hipLaunchKernelGGL(k_sym_A<T>, dim3(grid1(nnzb)), dim3(VMS_BLOCK), 0, ctx->stream, nnzb, mesh->tpos, K->A, As);
     // S^ from the FP64 scaled blocks (stored in the level precision), and diag(S^)^-1
     hipLaunchKernelGGL(k_shat_form<T>, dim3((n + SHAT_ROWS - 1) / SHAT_ROWS), dim3(VMS_BLOCK), 0, ctx->stream, n,
                        mesh->slot_width, mesh->col, mesh->diag_pos, nnzb, K->A, K->B, K->C, K->D, mesh->shat_width,
@@ -1145,6 +1449,10 @@ int check_opts(vms_ctx *ctx, const vms_solver_opts *o) {
   if (o->orth != VMS_ORTH_CGS2 && o->orth != VMS_ORTH_MGS && o->orth != VMS_ORTH_CGS1 &&
       o->orth != VMS_ORTH_CGS_IFNEEDED)
     return vms_set_error(ctx, VMS_ERR_ARG, "unknown orthogonalisation");
+  if (o->a_krylov != VMS_AK_GMRES && o->a_krylov != VMS_AK_CG_INNER && o->a_krylov != VMS_AK_CG)
+    return vms_set_error(ctx, VMS_ERR_ARG, "unknown A-level Krylov method");
+  if (o->cg_symmetrise != 0 && o->cg_symmetrise != 1)
+    return vms_set_error(ctx, VMS_ERR_ARG, "cg_symmetrise must be 0 or 1");
   return VMS_OK;
 }
 

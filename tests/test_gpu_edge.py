@@ -69,12 +69,33 @@ def test_iteration_limit_and_zero_rhs():
 
 
 @pytest.mark.parametrize("kw", [dict(maxit=0), dict(maxit_A=1001), dict(maxit_I=0), dict(orth=7),
-                                dict(shat_degree=65), dict(precision=2), dict(precond=9)])
+                                dict(shat_degree=65), dict(precision=2), dict(precond=9), dict(a_krylov=3),
+                                dict(a_krylov=V.AK_CG, cg_symmetrise=2)])
 def test_bad_solver_options_are_refused(kw):
     prob, mesh, ti, st, K, rhs = _system()
     with pytest.raises(V.VmsError) as ei:
         prob.solve_scaled(K, rhs, V.solver_opts(**kw))
     assert ei.value.code == -1
+
+
+@pytest.mark.parametrize("sym", [0, 1])
+def test_cg_levels_zero_velocity_rhs_and_maxit(sym):
+    """CG A-levels: a zero right-hand side (the first A-solve of Algorithm 1
+    when the velocity residual vanishes) returns x = 0 at once, and A-levels
+    capped at two iterations still give a usable preconditioner (the outer
+    FGMRES converges, with more iterations)."""
+    prob, mesh, ti, st, K, rhs = _system()
+    b = rhs.clone()
+    b.view(-1, 4)[:, :3] = 0.0
+    for kw in (dict(), dict(maxit_A=2, maxit_I=2)):
+        opts = V.solver_opts(a_krylov=V.AK_CG, cg_symmetrise=sym, **kw)
+        x, stats = prob.solve_scaled(K, b, opts)
+        r = prob.spmv(K, V.OP_FULL, x).reshape(-1) - b.reshape(-1)
+        print(f"[cg edge] sym={sym} {kw} stats={stats}", flush=True)
+        assert stats["status"] == 0
+        assert float(r.norm()) <= 1e-8 * float(b.norm())
+        if kw:
+            assert stats["it_A"] <= 2 * stats["n_A_solves"] and stats["it_I"] <= 2 * stats["n_I_solves"]
 
 
 def test_small_workspaces_are_refused():

@@ -137,8 +137,11 @@ def test_block_products_match_oracle_matrix(problems, name):
     assert rel_err(prob.spmv(K, V.OP_D, xpt).cpu().numpy().ravel(), Do @ xp) < 1e-13
 
 
-def _prepared(prob, mesh, ti, disc, seed, mirror32=False, nonzero_rk=True):
+def _prepared(prob, mesh, ti, disc, seed, mirror32=False, nonzero_rk=True, zero_accel=False):
     sn, it = states(mesh, seed)
+    if zero_accel:   # v-dot = 0 at both levels: the inertial term rho v-dot dJ/du drops out of A
+        sn["dv"][:] = 0.0
+        it["dv"][:] = 0.0
     vm = mesh.dir_mask[:, 0:3].astype(bool)
     for k in ("u", "v", "du", "dv"):
         sn[k][vm] = 0.0
@@ -239,6 +242,46 @@ def test_solve_reaches_requested_residual(problems, name, precision, shat):
     assert res <= 2e-8
     xo = spla.splu(Ks.tocsc()).solve(rs)
     assert np.linalg.norm(xg - xo) <= 1e-5 * np.linalg.norm(xo)
+
+
+@pytest.mark.parametrize("name", ["cube-nu0499", "tube-hgo"])
+@pytest.mark.parametrize("precision", [V.FP64, V.MIXED])
+@pytest.mark.parametrize("a_krylov,sym", [(V.AK_CG_INNER, 1), (V.AK_CG, 1), (V.AK_CG, 0)])
+def test_cg_levels_solve_matches_lu(problems, name, precision, a_krylov, sym):
+    """CG on (A + A^T)/2 at the A-levels (the inner-solver choice suggested in
+    the paper's conclusions) only changes the preconditioner: the outer FGMRES
+    still reaches the requested residual of the unsymmetrised system."""
+    import scipy.sparse.linalg as spla
+    prob, mesh, mat, ti, disc = problems(name)
+    st, K, rhs, Ks, rs, W, _ = _prepared(prob, mesh, ti, disc, 83, mirror32=(precision == V.MIXED))
+    opts = V.solver_opts(rtol=1e-8, precision=precision, shat_degree=6, a_krylov=a_krylov, cg_symmetrise=sym)
+    x, stats = prob.solve_scaled(K, rhs, opts)
+    xg = x.cpu().numpy().ravel()
+    print(f"[solve] {name} precision={precision} a_krylov={a_krylov} sym={sym} stats={stats}", flush=True)
+    assert np.linalg.norm(Ks @ xg - rs) <= 2e-8 * np.linalg.norm(rs)
+    xo = spla.splu(Ks.tocsc()).solve(rs)
+    assert np.linalg.norm(xg - xo) <= 1e-5 * np.linalg.norm(xo)
+    assert stats["n_I_solves"] > 0 and stats["it_I"] > 0
+
+
+@pytest.mark.parametrize("a_krylov,sym", [(V.AK_CG_INNER, 1), (V.AK_CG, 1), (V.AK_CG, 0)])
+def test_cg_exact_on_symmetric_A(problems, a_krylov, sym):
+    """With zero accelerations A is symmetric, so (A + A^T)/2 = A: CG solved
+    to 1e-14 makes the full block factorization exact (Algorithm 1), and the
+    outer FGMRES stops after one iteration, as it does with GMRES."""
+    import scipy.sparse.linalg as spla
+    prob, mesh, mat, ti, disc = problems("cube-comp")
+    st, K, rhs, Ks, rs, W, _ = _prepared(prob, mesh, ti, disc, 71, zero_accel=True)
+    A = AS.split_blocks(Ks)[0]
+    assert abs(A - A.T).max() <= 1e-14 * abs(A).max()
+    opts = V.solver_opts(rtol=1e-9, rtol_A=1e-13, rtol_S=1e-13, rtol_I=1e-14, maxit=50, maxit_A=400,
+                         maxit_S=400, maxit_I=400, shat_degree=6, a_krylov=a_krylov, cg_symmetrise=sym)
+    x, stats = prob.solve_scaled(K, rhs, opts)
+    xg = x.cpu().numpy().ravel()
+    print(f"[solve] symmetric A, a_krylov={a_krylov} sym={sym} stats={stats}", flush=True)
+    assert stats["n_outer"] == 1
+    xo = spla.splu(Ks.tocsc()).solve(rs)
+    assert np.linalg.norm(xg - xo) <= 1e-7 * np.linalg.norm(xo)
 
 
 def test_newton_update_matches_oracle(problems):
