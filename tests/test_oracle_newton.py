@@ -178,3 +178,28 @@ def test_matrix_free_schur_equals_dense():
     xp = np.random.default_rng(3).standard_normal(D.shape[0])
     np.testing.assert_allclose(KR.schur_apply_matrix_free(A, B, C, D, xp), S @ xp,
                                rtol=1e-10, atol=1e-12 * np.abs(S @ xp).max())
+
+
+@pytest.mark.parametrize("nu", [0.3, 0.499])
+def test_velocity_block_is_symmetric_without_acceleration(nu):
+    """A = dR_m/d(v-dot) is the mass term plus c3 times the second derivative
+    of the stored energy and of the pressure work, both symmetric, plus the
+    inertial term N_A rho v-dot_i dJ/du (no body force here).  So A is
+    symmetric when v-dot = 0, and its skew part is linear in v-dot (section
+    3.3 definition of A; App. A).  A transposed or dropped stiffness term
+    breaks the first property, a misplaced inertial term the second."""
+    mesh, mat, ti = synth.cube_case(3, nu=nu)
+    disc = AS.Discretization(mesh, mat)
+    am, af, gm = E.genalpha(ti.rho_inf)
+    skew = []
+    for scale in (0.0, 1.0, 2.0):
+        sn = synth.random_state(mesh.n_nodes, 31)
+        it = synth.random_state(mesh.n_nodes, 32)
+        sn["dv"] *= scale
+        it["dv"] *= scale
+        K, _, _, _ = NW.linear_system(disc, ti, NW.stage(sn, it, am, af), 0.5)
+        A = AS.split_blocks(K.tocsr())[0]
+        skew.append(spla.norm(A - A.T) / spla.norm(A))
+    assert skew[0] <= 1e-14
+    assert skew[1] > 1e-8
+    assert skew[2] == pytest.approx(2.0 * skew[1], rel=1e-3, abs=0.0)
