@@ -175,11 +175,13 @@ def main():
     ap.add_argument("--size", type=int, default=64)
     ap.add_argument("--nu", type=float, default=0.499)
     ap.add_argument("--forms", default="fp64,mixed")
-    ap.add_argument("--shat-degree", type=int, default=8)
+    ap.add_argument("--shat-degree", type=int, default=16)
     ap.add_argument("--shat-ratio", type=float, default=20.0)
-    ap.add_argument("--fp64-tol", default="1e-5,3e-6,1e-4",
+    ap.add_argument("--shat-method", default="cg", choices=["chebyshev", "cg"],
+                    help="S^ preconditioner of the Schur solve: Chebyshev polynomial or CG steps (--shat-degree)")
+    ap.add_argument("--fp64-tol", default="3e-5,1e-5,1e-4",
                     help="intermediate A, Schur and inner tolerances of the FP64 form")
-    ap.add_argument("--mixed-tol", default="1e-5,3e-6,1e-4",
+    ap.add_argument("--mixed-tol", default="3e-5,1e-5,1e-4",
                     help="intermediate A, Schur and inner tolerances of the mixed form")
     ap.add_argument("--orth", default="cgs1", choices=["cgs2", "cgs1", "cgs_ifneeded", "mgs"],
                     help="Arnoldi orthogonalisation of every Krylov level")
@@ -223,12 +225,14 @@ def main():
            "cg-inner-sym": (V.AK_CG_INNER, 1), "cg-sym": (V.AK_CG, 1)}
     fk, fs = akm[args.fp64_a_krylov]
     mk, ms = akm[args.mixed_a_krylov]
+    sm = {"chebyshev": V.SHAT_CHEBYSHEV, "cg": V.SHAT_CG}[args.shat_method]
     forms = {
         "fp64": V.solver_opts(rtol=1e-8, rtol_A=ft[0], rtol_S=ft[1], rtol_I=ft[2], shat_degree=args.shat_degree,
-                              shat_ratio=args.shat_ratio, orth=orth, a_krylov=fk, cg_symmetrise=fs),
+                              shat_ratio=args.shat_ratio, orth=orth, a_krylov=fk, cg_symmetrise=fs,
+                              shat_method=sm),
         "mixed": V.solver_opts(rtol=1e-8, rtol_A=mt[0], rtol_S=mt[1], rtol_I=mt[2], precision=V.MIXED,
                                shat_degree=args.shat_degree, shat_ratio=args.shat_ratio, orth=orth, a_krylov=mk,
-                               cg_symmetrise=ms),
+                               cg_symmetrise=ms, shat_method=sm),
     }
     results = {}
     for name in args.forms.split(","):
@@ -290,7 +294,8 @@ def main():
            "config": {"workload": f"cube{N}^3 Kuhn tets, nu={args.nu}, neo-Hookean, dt=1e-3, Newton/FGMRES 1e-8",
                       "nodes": n, "tets": mesh.n_tets, "unknowns": 4 * n, "nnzb": nnzb,
                       "block_slots": prob.nnzb,
-                      "shat_degree": args.shat_degree, "shat_ratio": args.shat_ratio, "orth": args.orth,
+                      "shat_degree": args.shat_degree, "shat_ratio": args.shat_ratio,
+                      "shat_method": args.shat_method, "orth": args.orth,
                       "a_krylov": {"fp64": args.fp64_a_krylov, "mixed": args.mixed_a_krylov},
                       "parallelism": "single GPU"},
            "roofline": roof}

@@ -90,6 +90,13 @@ enum { VMS_ORTH_CGS2 = 0, VMS_ORTH_MGS = 1, VMS_ORTH_CGS1 = 2, VMS_ORTH_CGS_IFNE
  * the outer FGMRES still solves the unsymmetrised system. */
 enum { VMS_AK_GMRES = 0, VMS_AK_CG_INNER = 1, VMS_AK_CG = 2 };
 
+/* How the Schur solve's right preconditioner approximates S^-1 when
+ * shat_degree = k > 0: the degree-k Chebyshev polynomial in diag(S^)^-1 S^
+ * (a fixed linear operator), or k steps of diag(S^)-preconditioned CG on S^
+ * (the Krylov-optimal degree-k polynomial for each vector; nonlinear, which
+ * the flexible Schur-level GMRES allows). */
+enum { VMS_SHAT_CHEBYSHEV = 0, VMS_SHAT_CG = 1 };
+
 typedef struct vms_ctx vms_ctx;
 
 typedef struct {
@@ -154,10 +161,12 @@ typedef struct {
   int32_t orth;       /* VMS_ORTH_* of the A-, S- and inner levels; the outer FGMRES uses
                          VMS_ORTH_MGS if that is chosen, else VMS_ORTH_CGS2 */
   int32_t shat_degree;/* right preconditioner of the Schur solve: 0 = diag(S^)^-1; k > 0 = degree-k
-                         Chebyshev polynomial in diag(S^)^-1 S^ on [lmax/shat_ratio, lmax] */
+                         Chebyshev polynomial in diag(S^)^-1 S^ on [lmax/shat_ratio, lmax], or k CG
+                         steps on S^ (shat_method) */
   double shat_ratio;  /* lmax / lmin of the Chebyshev interval (used when shat_degree > 0) */
   int32_t a_krylov;   /* VMS_AK_*: GMRES or CG at the inner (or both) A-levels */
   int32_t cg_symmetrise; /* CG levels: 1 = on (A + A^T)/2, 0 = on A */
+  int32_t shat_method;   /* VMS_SHAT_*: Chebyshev polynomial or CG steps on S^ (shat_degree > 0) */
 } vms_solver_opts;
 
 typedef struct {

@@ -819,6 +819,135 @@ k_cg_update(int64_t nn, T *x, T *r, T *z, const T *__restrict__ p, const T *__re
   cg_block_sums2(rz, rr, ctrl + off.pn + blockIdx.x, ctrl + off.pn2 + blockIdx.x, sm);
 }
 
+// ---- CG steps on S^ as the Schur-level preconditioner ---------------------------
+// A fixed number k of Jacobi-preconditioned CG steps on S^ z = v from z = 0:
+// for each right-hand side the Krylov-optimal polynomial of degree k, where
+// the Chebyshev option applies one fixed polynomial.  The result depends
+// nonlinearly on v, which the flexible Schur-level GMRES (it keeps the Z
+// vectors) tolerates.  Same kernel pattern as the CG A-levels: the product
+// kernel forms w = S^ z and the rows' own p = z + beta p, q = w + beta q;
+// the update kernel advances x, r, z.  A zero or non-finite <r,z> or
+// <p,S^p> ends the steps early (x keeps the last iterate); the host never
+// waits on them.
+
+// sum over a workgroup of any size (fixed order), valid in thread 0
+__device__ __forceinline__ double blk_sum_any(double v, double *sm) {
+  v = wave_sum(v);
+  const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  if ((threadIdx.x & 63) == 0) sm[w] = v;
+  __syncthreads();
+  double r = 0.0;
+  if (threadIdx.x == 0)
+    for (int q = 0; q < nw; ++q) r += sm[q];
+  return r;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(KRY_BLOCK)
+k_scg_init(int n, const T *__restrict__ v, const T *__restrict__ dinv, T *x, T *r, T *z, double *prz, int *flag) {
+  __shared__ double sm[16];
+  if (blockIdx.x == 0 && threadIdx.x == 0) *flag = 0;
+  double rz = 0.0;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const double vi = ld(v, i);
+    const T zi = (T)(ld(dinv, i) * vi);
+    r[i] = (T)vi;
+    z[i] = zi;
+    x[i] = (T)0;
+    rz += vi * (double)zi;
+  }
+  rz = blk_sum_any(rz, sm);
+  if (threadIdx.x == 0) prz[blockIdx.x] = rz;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(VMS_BLOCK)
+k_scg_spmv(int n, int W2, const int32_t *__restrict__ sc, const T *__restrict__ S, const T *__restrict__ Sd,
+           const T *__restrict__ z, T *p, T *q, double *ctl, const double *prz, int nrz, double *ppq, int *flag,
+           int i) {
+  __shared__ double sm[16];
+  __shared__ int done0;
+  if (threadIdx.x == 0) done0 = *flag;
+  __syncthreads();
+  if (done0) return;
+  const double rz = cg_sum_partials(prz, nrz, sm);
+  if (!(rz > 0.0) || !isfinite(rz)) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) *flag = 1;
+    return;
+  }
+  const bool first = (i == 0);
+  const double beta = first ? 0.0 : rz / ctl[(i - 1) & 1];
+  if (blockIdx.x == 0 && threadIdx.x == 0) ctl[i & 1] = rz;
+  const int lane = threadIdx.x & 15, sub = threadIdx.x >> 4;
+  const int ng = (n + SPMV_ROWS_PER_BLOCK - 1) / SPMV_ROWS_PER_BLOCK;
+  const int vb = xcd_block(blockIdx.x, gridDim.x);
+  const int g0 = (int)((int64_t)vb * ng / gridDim.x), g1 = (int)((int64_t)(vb + 1) * ng / gridDim.x);
+  double pq = 0.0;
+  for (int g = g0; g < g1; ++g) {
+    const int row = g * SPMV_ROWS_PER_BLOCK + sub;
+    const bool act = row < n;
+    const int ro = act ? row : 0;
+    const int64_t r0 = (int64_t)W2 * ro;
+    // the row's own values ahead of the product
+    const double zi = ld(z, ro), sii = ld(Sd, ro);
+    const double pi = first ? 0.0 : ld(p, ro), qi = first ? 0.0 : ld(q, ro);
+    double a = 0.0;
+    for (int q0 = 0; q0 < W2; q0 += 64) {
+      int c[4];
+      double v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        c[u] = sc[r0 + q0 + lane + 16 * u];
+        v[u] = ld(S, r0 + q0 + lane + 16 * u);
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) a += v[u] * ld(z, c[u]);
+    }
+    a = reduce16(a) + sii * zi;
+    if (act && lane == 0) {
+      const T pn = first ? (T)zi : (T)(zi + beta * pi);
+      const T qn = first ? (T)a : (T)(a + beta * qi);
+      p[row] = pn;
+      q[row] = qn;
+      pq += (double)pn * (double)qn;
+    }
+  }
+  pq = block_sum(pq, sm);
+  if (threadIdx.x == 0) ppq[blockIdx.x] = pq;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(KRY_BLOCK)
+k_scg_update(int n, T *x, T *r, T *z, const T *__restrict__ p, const T *__restrict__ q, const T *__restrict__ dinv,
+             const double *ctl, const double *ppq, int npq, double *prz, int *flag, int i, int last) {
+  __shared__ double sm[16];
+  __shared__ int done0;
+  if (threadIdx.x == 0) done0 = *flag;
+  __syncthreads();
+  if (done0) return;
+  const double pq = cg_sum_partials(ppq, npq, sm);
+  const double alpha = ctl[i & 1] / pq;
+  if (!(pq > 0.0) || !isfinite(alpha)) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) *flag = 1;
+    return;
+  }
+  double rz = 0.0;
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) {
+    x[k] = (T)(ld(x, k) + alpha * ld(p, k));
+    if (!last) {
+      const T rk = (T)(ld(r, k) - alpha * ld(q, k));
+      const T zk = (T)(ld(dinv, k) * (double)rk);
+      r[k] = rk;
+      z[k] = zk;
+      rz += (double)rk * (double)zk;
+    }
+  }
+  if (!last) {
+    rz = blk_sum_any(rz, sm);
+    if (threadIdx.x == 0) prz[blockIdx.x] = rz;
+  }
+}
+
 // ---- S^ = D - C diag(A)^-1 B, assembled on the distance-2 pattern ----------
 // Off-diagonal part in rows of W2 fixed slots (sorted columns, then padding
 // slots that hold the row's own node), diagonal apart.  16 lanes per row i
@@ -1260,6 +1389,8 @@ struct Nested {
   T *Shat, *Shd, *cr, *cd0, *cd1, *px, *py;  // S^ (off-diagonal, diagonal); Chebyshev / power-iteration vectors
   T *As = nullptr;                            // (A + A^T)/2 for the CG levels (when symmetrised)
   double *cgpart = nullptr;                   // partials of <p, A p> of the CG product kernel
+  double *sctl = nullptr;                     // CG steps on S^: rz history [2], <p,q> partials, <r,z> partials
+  int *sflag = nullptr;
   double *lam = nullptr;                      // device: lmax estimate of diag(S^)^-1 S^
   vms_solve_stats *stats;
   int err = VMS_OK;
@@ -1284,6 +1415,10 @@ struct Nested {
     cd1 = cv.take<T>(nn);
     px = cv.take<T>(nn);
     py = cv.take<T>(nn);
+    if (o_->shat_method == VMS_SHAT_CG && o_->shat_degree > 0) {
+      sctl = cv.take<double>(2 + CG_SPMV_BLOCKS + VMS_MAX_RED_BLOCKS);
+      sflag = cv.take<int>(1);
+    }
     if (o_->a_krylov != VMS_AK_GMRES) {
       cgpart = cv.take<double>(cg_spmv_blocks(m_->n_nodes));
       if (o_->cg_symmetrise) As = cv.take<T>(9 * m_->nnzb);
@@ -1302,6 +1437,25 @@ struct Nested {
       hipLaunchKernelGGL((k_shat_cheb<T, 1>), gw, bl, 0, s, n, mesh->shat_width, mesh->shat_col, (const T *)Shat,
                          (const T *)Shd, (const T *)d, (const T *)sdinv, dn, z, cr, (const double *)lam, ratio, k);
       std::swap(d, dn);
+    }
+  }
+
+  // z = k Jacobi-preconditioned CG steps on S^ z = v (k = shat_degree)
+  void scg_apply(const T *v, T *z) {
+    hipStream_t s = ctx->stream;
+    const int k = o->shat_degree;
+    const int gs = cg_spmv_blocks(n);
+    const int nbv = kry_blocks(n);
+    double *ppq = sctl + 2, *prz = sctl + 2 + CG_SPMV_BLOCKS;
+    T *r = cr, *zz = cd0, *p = cd1, *q = px;
+    hipLaunchKernelGGL(k_scg_init<T>, dim3(nbv), dim3(KRY_BLOCK), 0, s, n, v, (const T *)sdinv, z, r, zz, prz, sflag);
+    for (int i = 0; i < k; ++i) {
+      hipLaunchKernelGGL(k_scg_spmv<T>, dim3(gs), dim3(VMS_BLOCK), 0, s, n, mesh->shat_width, mesh->shat_col,
+                         (const T *)Shat, (const T *)Shd, (const T *)zz, p, q, sctl, (const double *)prz, nbv, ppq,
+                         sflag, i);
+      hipLaunchKernelGGL(k_scg_update<T>, dim3(nbv), dim3(KRY_BLOCK), 0, s, n, z, r, zz, (const T *)p, (const T *)q,
+                         (const T *)sdinv, (const double *)sctl, (const double *)ppq, gs, prz, sflag, i,
+                         (int)(i == k - 1));
     }
   }
 
@@ -1348,7 +1502,10 @@ struct Nested {
     const bool cheb = o->shat_degree > 0;
     auto op = [&](int j) -> int {
       T *z = LS.Z + (int64_t)j * LS.nvec;
-      if (cheb) cheb_apply(LS.V + (int64_t)j * LS.nvec, z);
+      if (cheb) {
+        if (o->shat_method == VMS_SHAT_CG) scg_apply(LS.V + (int64_t)j * LS.nvec, z);
+        else cheb_apply(LS.V + (int64_t)j * LS.nvec, z);
+      }
       // x-bar = B z
       hipLaunchKernelGGL((k_spmv_B<T, T>), dim3(spmv_grid(n)), dim3(VMS_BLOCK), 0, ctx->stream, n, nnzb,
                          mesh->slot_width, mesh->col, B, z, xbar, (const T *)nullptr, 1.0, (const int *)nullptr);
@@ -1408,7 +1565,7 @@ struct Nested {
     hipLaunchKernelGGL(k_shat_form<T>, dim3((n + SHAT_ROWS - 1) / SHAT_ROWS), dim3(VMS_BLOCK), 0, ctx->stream, n,
                        mesh->slot_width, mesh->col, mesh->diag_pos, nnzb, K->A, K->B, K->C, K->D, mesh->shat_width,
                        mesh->shat_col, Shat, Shd, sdinv);
-    if (o->shat_degree > 0) {
+    if (o->shat_degree > 0 && o->shat_method == VMS_SHAT_CHEBYSHEV) {
       lam = LS.ctrl + LS.off.scal + 5;
       power_lmax(12);
     }
@@ -1453,6 +1610,8 @@ int check_opts(vms_ctx *ctx, const vms_solver_opts *o) {
     return vms_set_error(ctx, VMS_ERR_ARG, "unknown A-level Krylov method");
   if (o->cg_symmetrise != 0 && o->cg_symmetrise != 1)
     return vms_set_error(ctx, VMS_ERR_ARG, "cg_symmetrise must be 0 or 1");
+  if (o->shat_method != VMS_SHAT_CHEBYSHEV && o->shat_method != VMS_SHAT_CG)
+    return vms_set_error(ctx, VMS_ERR_ARG, "unknown S^ preconditioner method");
   return VMS_OK;
 }
 

@@ -206,14 +206,18 @@ def test_dirichlet_and_scaling_match_oracle(problems, name):
 
 
 @pytest.mark.parametrize("precond,max_outer", [(V.PC_LDU, 1), (V.PC_UPPER, 2), (V.PC_LOWER, 2)])
-@pytest.mark.parametrize("orth,shat", [(V.ORTH_CGS2, 0), (V.ORTH_MGS, 0), (V.ORTH_CGS2, 6), (V.ORTH_CGS1, 0),
-                                       (V.ORTH_CGS_IFNEEDED, 0), (V.ORTH_CGS_IFNEEDED, 6)])
-def test_nested_solve_matches_lu(problems, precond, max_outer, orth, shat):
+@pytest.mark.parametrize("orth,shat,method", [(V.ORTH_CGS2, 0, V.SHAT_CHEBYSHEV), (V.ORTH_MGS, 0, V.SHAT_CHEBYSHEV),
+                                              (V.ORTH_CGS2, 6, V.SHAT_CHEBYSHEV), (V.ORTH_CGS1, 0, V.SHAT_CHEBYSHEV),
+                                              (V.ORTH_CGS_IFNEEDED, 0, V.SHAT_CHEBYSHEV),
+                                              (V.ORTH_CGS_IFNEEDED, 6, V.SHAT_CHEBYSHEV),
+                                              (V.ORTH_CGS1, 16, V.SHAT_CG)])
+def test_nested_solve_matches_lu(problems, precond, max_outer, orth, shat, method):
     import scipy.sparse.linalg as spla
     prob, mesh, mat, ti, disc = problems("cube-comp")
     st, K, rhs, Ks, rs, W, _ = _prepared(prob, mesh, ti, disc, 71)
     opts = V.solver_opts(rtol=1e-9, rtol_A=1e-13, rtol_S=1e-13, rtol_I=1e-14, maxit=50, maxit_A=400,
-                         maxit_S=400, maxit_I=400, precond=precond, orth=orth, shat_degree=shat)
+                         maxit_S=400, maxit_I=400, precond=precond, orth=orth, shat_degree=shat,
+                         shat_method=method)
     x, stats = prob.solve_scaled(K, rhs, opts)
     xg = x.cpu().numpy().ravel()
     xo = spla.splu(Ks.tocsc()).solve(rs)
@@ -225,16 +229,16 @@ def test_nested_solve_matches_lu(problems, precond, max_outer, orth, shat):
 
 @pytest.mark.parametrize("name", ["cube-nu0499", "cube-incomp", "tube-hgo"])
 @pytest.mark.parametrize("precision", [V.FP64, V.MIXED])
-@pytest.mark.parametrize("shat", [0, 6])
-def test_solve_reaches_requested_residual(problems, name, precision, shat):
+@pytest.mark.parametrize("shat,shat_method", [(0, V.SHAT_CHEBYSHEV), (6, V.SHAT_CHEBYSHEV), (6, V.SHAT_CG)])
+def test_solve_reaches_requested_residual(problems, name, precision, shat, shat_method):
     import scipy.sparse.linalg as spla
     prob, mesh, mat, ti, disc = problems(name)
     st, K, rhs, Ks, rs, W, _ = _prepared(prob, mesh, ti, disc, 81, mirror32=(precision == V.MIXED))
     if precision == V.MIXED:
         opts = V.solver_opts(rtol=1e-8, rtol_A=1e-5, rtol_S=1e-5, rtol_I=1e-3, precision=V.MIXED,
-                             shat_degree=shat)
+                             shat_degree=shat, shat_method=shat_method)
     else:
-        opts = V.solver_opts(rtol=1e-8, shat_degree=shat)
+        opts = V.solver_opts(rtol=1e-8, shat_degree=shat, shat_method=shat_method)
     x, stats = prob.solve_scaled(K, rhs, opts)
     xg = x.cpu().numpy().ravel()
     print(f"[solve] {name} precision={precision} stats={stats}", flush=True)
@@ -282,6 +286,35 @@ def test_cg_exact_on_symmetric_A(problems, a_krylov, sym):
     assert stats["n_outer"] == 1
     xo = spla.splu(Ks.tocsc()).solve(rs)
     assert np.linalg.norm(xg - xo) <= 1e-7 * np.linalg.norm(xo)
+
+
+def test_shat_cg_steps_approach_exact_shat(problems):
+    """k CG steps on S^ converge to S^-1 as k grows: with k = 60 and exact
+    inner and A-solves, the one Schur solve of the nested solve takes as many
+    iterations (within one) as the oracle's S-GMRES on the same right-hand
+    side (Algorithm 1, steps 1-2 applied to the first outer Krylov vector)
+    preconditioned by an exact S^ solve.  Steepest descent or a wrong CG
+    coefficient would need several more."""
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as spla
+    from oracle import krylov as KR
+    prob, mesh, mat, ti, disc = problems("cube-nu0499")
+    st, K, rhs, Ks, rs, W, _ = _prepared(prob, mesh, ti, disc, 85)
+    opts = V.solver_opts(rtol=1e-9, rtol_A=1e-13, rtol_S=1e-10, rtol_I=1e-13, maxit_S=400, maxit_A=400,
+                         maxit_I=400, shat_degree=60, shat_method=V.SHAT_CG)
+    x, stats = prob.solve_scaled(K, rhs, opts)
+    print(f"[solve] S^ CG(60) stats={stats}", flush=True)
+    assert stats["n_outer"] == 1 and stats["n_S_solves"] == 1
+    A, B, Cm, D, iv, ip = AS.split_blocks(Ks)
+    Sh = (D - Cm @ sp.diags(1.0 / A.diagonal()) @ B).tocsc()
+    luA, luS = spla.splu(A.tocsc()), spla.splu(Sh)
+    v0 = rs / np.linalg.norm(rs)
+    bS = v0[ip] - Cm @ luA.solve(v0[iv])
+    its = KR.fgmres(lambda v: D @ v - Cm @ luA.solve(B @ v), bS, precond=luS.solve, rtol=1e-10, maxit=400)[1]
+    print(f"[solve] oracle S-GMRES with exact S^: {its} iterations", flush=True)
+    assert abs(stats["it_S"] - its) <= 1
+    xo = spla.splu(Ks.tocsc()).solve(rs)
+    assert np.linalg.norm(x.cpu().numpy().ravel() - xo) <= 1e-7 * np.linalg.norm(xo)
 
 
 def test_newton_update_matches_oracle(problems):
