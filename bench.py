@@ -40,14 +40,39 @@ def spmv_A_bytes(n, nnzb, elem):
     return (9 * elem + 4) * nnzb + 2 * 3 * elem * n
 
 
-def pmc_traffic(key):
-    """HBM bytes per launch of the A-block SpMV from the committed rocprofv3
-    counter summary, if the kernel source is unchanged since it was taken."""
+def shat_bytes(n, nnz, elem):
+    """Algorithmic bytes of one S^ product of the Schur preconditioner's CG
+    steps (its first step, as timed): the real off-diagonal entries (value +
+    column index), the diagonal, x once (gathers cached) and y."""
+    return (elem + 4) * nnz + 3 * elem * n
+
+
+# kernel -> (source file, first and end markers of the kernel's source text (None: whole file), summary)
+PMC_FILES = {
+    "spmv_A": ("linalg.h", None, None, "spmv_A_cube64_pmc.md"),
+    "shat": ("solver.hip", "// Off-diagonal part of row ro of S^ times z",
+             "template <typename T>\n__global__ void __launch_bounds__(KRY_BLOCK)\nk_scg_update(",
+             "shat_spmv_cube64_pmc.md"),
+}
+
+
+def kernel_source_sha(kernel):
+    """First 16 hex digits of the SHA-256 of the kernel's source text."""
     import hashlib
-    src = os.path.join(ROOT, "paper_1809_06350_amd", "csrc", "linalg.h")
-    prof = os.path.join(ROOT, "profiles", "spmv_A_cube64_pmc.md")
+    srcname, first, end, _ = PMC_FILES[kernel]
+    text = open(os.path.join(ROOT, "paper_1809_06350_amd", "csrc", srcname), "rb").read()
+    if first is not None:
+        a = text.index(first.encode())
+        text = text[a:text.index(end.encode(), a)]
+    return hashlib.sha256(text).hexdigest()[:16]
+
+
+def pmc_traffic(kernel, key):
+    """HBM bytes per launch from the committed rocprofv3 counter summary of
+    that kernel, if its source is unchanged since the counters were taken."""
+    prof = os.path.join(ROOT, "profiles", PMC_FILES[kernel][3])
     try:
-        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+        sha = kernel_source_sha(kernel)
         kv = dict(line.split(": ", 1) for line in open(prof).read().splitlines() if ": " in line)
         if kv.get("source_sha256_16", "").strip() == sha:
             return float(kv[key])
@@ -56,18 +81,43 @@ def pmc_traffic(key):
     return None
 
 
-def time_spmv(prob, K, op, x, fp32, reps=50):
+def time_launches(fn, reps=50):
+    """Average duration of fn() over reps back-to-back launches between two
+    HIP events on the torch current stream (the library's stream)."""
     import torch
     for _ in range(5):
-        prob.spmv(K, op, x, fp32)
+        fn()
     s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     s.record()
     for _ in range(reps):
-        prob.spmv(K, op, x, fp32)
+        fn()
     e.record()
     torch.cuda.synchronize()
     return s.elapsed_time(e) / reps * 1e-3   # seconds per launch
+
+
+def time_spmv(prob, K, op, x, fp32, reps=50):
+    return time_launches(lambda: prob.spmv(K, op, x, fp32), reps)
+
+
+def shat_real_entries(prob):
+    import numpy as np
+    n = prob.mesh.n_nodes
+    sc = prob.host["shat_col"].reshape(n, -1)
+    return int((sc != np.arange(n)[:, None]).sum())
+
+
+def time_shat(prob, K, fp32, reps=50):
+    """The S^ product kernel on the S^ of K: seconds per launch."""
+    import torch
+    S, Sd, _ = prob.schur_hat(K)
+    if fp32:
+        S, Sd = S.float(), Sd.float()
+    x = torch.randn(prob.mesh.n_nodes, dtype=S.dtype, device=S.device,
+                    generator=torch.Generator(S.device).manual_seed(2))
+    y = torch.empty_like(x)
+    return time_launches(lambda: prob.shat_spmv(S, Sd, x, out=y), reps)
 
 
 def run_form(prob, mesh, ti, nopts, sopts, steps, warmup, timing=False):
@@ -155,16 +205,30 @@ def spmv_only(prob, mesh, ti, reps):
         prob.spmv(K32, V.OP_A, x, False)
     for _ in range(reps):
         prob.spmv(K32, V.OP_A, xf, True)
+    S, Sd, _ = prob.schur_hat(K32)
+    S32, Sd32 = S.float(), Sd.float()
+    xs = torch.randn(n, dtype=torch.float64, device="cuda:0", generator=torch.Generator("cuda:0").manual_seed(2))
+    ys, xs32 = torch.empty_like(xs), xs.float()
+    ys32 = torch.empty_like(xs32)
+    for _ in range(reps):
+        prob.shat_spmv(S, Sd, xs, out=ys)
+    for _ in range(reps):
+        prob.shat_spmv(S32, Sd32, xs32, out=ys32)
     for _ in range(reps):
         torch.mul(src, 1.0, out=dst)
     torch.cuda.synchronize()
     t64 = time_spmv(prob, K32, V.OP_A, x, False)
     t32 = time_spmv(prob, K32, V.OP_A, xf, True)
+    nzs = shat_real_entries(prob)
     nz = int(prob.host["row_len"].sum())
     print(json.dumps({"spmv_only": True, "n": n, "nnzb": nz, "nnzb_slots": prob.nnzb,
                       "calibration_bytes_each_way": src.numel() * 8,
                       "bytes_fp64": spmv_A_bytes(n, nz, 8), "us_fp64": t64 * 1e6,
-                      "bytes_fp32": spmv_A_bytes(n, nz, 4), "us_fp32": t32 * 1e6}), flush=True)
+                      "bytes_fp32": spmv_A_bytes(n, nz, 4), "us_fp32": t32 * 1e6,
+                      "shat_nnz": nzs, "shat_bytes_fp64": shat_bytes(n, nzs, 8),
+                      "shat_us_fp64": time_shat(prob, K32, False) * 1e6,
+                      "shat_bytes_fp32": shat_bytes(n, nzs, 4),
+                      "shat_us_fp32": time_shat(prob, K32, True) * 1e6}), flush=True)
 
 
 def main():
@@ -244,21 +308,42 @@ def main():
     r = results[primary]
     value = r["n_newton"] / r["wall_s"]
 
-    # dominant kernel: the 3x3 block SpMV of the A-level GMRES (inner + intermediate), on the matrix of the
-    # workload's last Newton system: its average duration over 50 back-to-back launches between two HIP
-    # events on the library's stream (the torch current stream).  With --kernel-timing every launch inside
-    # the timed steps is event-timed as well and reported beside it (that figure includes the per-launch
-    # event overhead).
+    # dominant kernel of the FP64 form: the 3x3 block product of the A-levels or the S^ product of the
+    # Schur preconditioner's CG steps, whichever takes more time per step (launches counted from the
+    # solver statistics times the kernel's duration).  Each duration is the average over 50 back-to-back
+    # launches on the matrices of the workload's last Newton system, between two HIP events on the
+    # library's stream (the torch current stream).  With --kernel-timing every launch of the A-product
+    # inside the timed steps is event-timed as well and reported beside it (that figure includes the
+    # per-launch event overhead).
     K = r["K"]
+    so = forms[primary]
     x64 = torch.randn(n, 3, dtype=torch.float64, device="cuda:0", generator=torch.Generator("cuda:0").manual_seed(1))
     t64 = time_spmv(prob, K, V.OP_A, x64, False)
     by64 = spmv_A_bytes(n, nnzb, 8)
-    roof = {"bound": "hbm", "kernel": "k_spmv_A<double,double>", "achieved": by64 / t64 / 1e9,
-            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": by64 / t64 / 1e9 / HBM_PEAK_GBS,
-            "traffic": pmc_traffic("traffic_bytes_fp64") if N == 64 else None,
-            "bytes_per_launch": by64, "us_per_launch": t64 * 1e6,
+    nzs = shat_real_entries(prob)
+    ts64 = time_shat(prob, K, False)
+    bys64 = shat_bytes(n, nzs, 8)
+    steps_stats = r["per_step"]
+    launches_A = sum(p["it_A_total"] + p["it_I_total"] for p in steps_stats) / args.steps
+    launches_S = (sum(p["it_S_total"] for p in steps_stats) / args.steps * so.shat_degree
+                  if so.shat_method == V.SHAT_CG else 0.0)
+    kern = {
+        "k_spmv_A<double,double>": {"achieved": by64 / t64 / 1e9, "us_per_launch": t64 * 1e6,
+                                    "bytes_per_launch": by64, "launches_per_step": launches_A,
+                                    "est_ms_per_step": launches_A * t64 * 1e3,
+                                    "traffic": pmc_traffic("spmv_A", "traffic_bytes_fp64") if N == 64 else None},
+        "k_scg_spmv<double>": {"achieved": bys64 / ts64 / 1e9, "us_per_launch": ts64 * 1e6,
+                               "bytes_per_launch": bys64, "launches_per_step": launches_S,
+                               "est_ms_per_step": launches_S * ts64 * 1e3,
+                               "traffic": pmc_traffic("shat", "traffic_bytes_fp64") if N == 64 else None},
+    }
+    dom = max(kern, key=lambda k: kern[k]["est_ms_per_step"])
+    kd = kern[dom]
+    roof = {"bound": "hbm", "kernel": dom, "achieved": kd["achieved"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": kd["achieved"] / HBM_PEAK_GBS, "traffic": kd["traffic"],
+            "bytes_per_launch": kd["bytes_per_launch"], "us_per_launch": kd["us_per_launch"],
             "timing": "HIP events around 50 back-to-back launches on the last Newton system of the timed steps"}
-    extra = {}
+    extra = {"fp64_kernels": kern}
     if r["spmv_A_launches"] > 0:
         t_in = r["spmv_A_ms"] * 1e-3 / r["spmv_A_launches"]
         extra["spmv_A_in_steps"] = {"us_per_launch": t_in * 1e6, "GB/s": by64 / t_in / 1e9,
@@ -273,7 +358,12 @@ def main():
         t32 = time_spmv(prob, rm["K"], V.OP_A, x64.float(), True)
         extra["spmv_A_fp32"] = {"GB/s": by32 / t32 / 1e9, "us_per_launch": t32 * 1e6, "bytes_per_launch": by32,
                                 "frac_hbm": by32 / t32 / 1e9 / HBM_PEAK_GBS,
-                                "traffic": pmc_traffic("traffic_bytes_fp32") if N == 64 else None}
+                                "traffic": pmc_traffic("spmv_A", "traffic_bytes_fp32") if N == 64 else None}
+        ts32 = time_shat(prob, rm["K"], True)
+        bys32 = shat_bytes(n, nzs, 4)
+        extra["shat_fp32"] = {"GB/s": bys32 / ts32 / 1e9, "us_per_launch": ts32 * 1e6, "bytes_per_launch": bys32,
+                              "frac_hbm": bys32 / ts32 / 1e9 / HBM_PEAK_GBS,
+                              "traffic": pmc_traffic("shat", "traffic_bytes_fp32") if N == 64 else None}
         u64 = results.get("fp64", rm)["u"]
         err = float((rm["u"] - u64).norm() / u64.norm()) if "fp64" in results else None
         extra["mixed"] = {"newton_per_s": rm["n_newton"] / rm["wall_s"],

@@ -316,6 +316,15 @@ int vms_spmv(vms_ctx *ctx, const vms_mesh *mesh, const vms_matrix *K, int op,
 int vms_schur_hat(vms_ctx *ctx, const vms_mesh *mesh, const vms_matrix *K, double *S, double *Sdiag,
                   double *sdinv);
 
+/* y = S^ x for the S^ of vms_schur_hat (off-diagonal S[n * shat_width] on
+ * mesh->shat_col, diagonal Sd[n]; section 4.2), by the product kernel of the
+ * Schur preconditioner's CG steps (its first step).  S, Sd, x, y are FP64, or
+ * all FP32 when fp32 != 0; x[n] and y[n] must not alias.  Uses the
+ * context's small device scratch, so calls on one context must not overlap.
+ * [async] */
+int vms_shat_spmv(vms_ctx *ctx, const vms_mesh *mesh, const void *S, const void *Sd, const void *x, void *y,
+                  int fp32);
+
 /* Workspace bytes needed by vms_solve_scaled / vms_solve_transpose for these
  * options (Krylov bases of the four levels, control blocks, temporaries). */
 size_t vms_solve_workspace(const vms_mesh *mesh, const vms_solver_opts *opts);
@@ -324,8 +333,9 @@ size_t vms_solve_workspace(const vms_mesh *mesh, const vms_solver_opts *opts);
  * preconditioned by the nested Schur-complement-reduction preconditioner
  * (Algorithm 1 with Algorithm 2 for the Schur products): GMRES on A with
  * 3x3 block-Jacobi, GMRES on S = D - C A^-1 B preconditioned from
- * S^ = D - C diag(A)^-1 B (assembled as by vms_schur_hat): diag(S^)^-1 or a
- * Chebyshev polynomial in diag(S^)^-1 S^ (shat_degree).  x0 = 0; every level stops at
+ * S^ = D - C diag(A)^-1 B (assembled as by vms_schur_hat): diag(S^)^-1, a
+ * Chebyshev polynomial in diag(S^)^-1 S^, or CG steps on S^ (shat_degree,
+ * shat_method); CG or GMRES on the A-levels (a_krylov).  x0 = 0; every level stops at
  * ||r|| <= max(rtol ||b||, atol) or maxit.  [sync]
  * Returns VMS_NOT_CONVERGED (x_scaled holds the last iterate) when the outer
  * level hits maxit. */

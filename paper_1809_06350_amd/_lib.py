@@ -96,6 +96,7 @@ SIGNATURES = {
                                      C.c_double, C.c_int]),
     "vms_spmv": (C.c_int, [C.c_void_p, P(Mesh), P(Matrix), C.c_int, C.c_void_p, C.c_void_p, C.c_int]),
     "vms_schur_hat": (C.c_int, [C.c_void_p, P(Mesh), P(Matrix), C.c_void_p, C.c_void_p, C.c_void_p]),
+    "vms_shat_spmv": (C.c_int, [C.c_void_p, P(Mesh), C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]),
     "vms_solve_workspace": (C.c_size_t, [P(Mesh), P(SolverOpts)]),
     "vms_solve_scaled": (C.c_int, [C.c_void_p, P(Mesh), P(Matrix), C.c_void_p, C.c_void_p, P(SolverOpts),
                                    C.c_void_p, C.c_size_t, P(SolveStats)]),

@@ -687,8 +687,9 @@ k_cg_init(int64_t nn, const T *__restrict__ b, T *x, T *r, T *z, const T *__rest
 // (16 lanes per row, 16 rows per workgroup); a workgroup takes a contiguous
 // range of row groups (XCD-aware order) when the grid is capped.
 #ifndef CG_SPMV_BLOCKS
-#define CG_SPMV_BLOCKS 2048
+#define CG_SPMV_BLOCKS VMS_SCG_MAX_BLOCKS
 #endif
+static_assert(CG_SPMV_BLOCKS <= VMS_SCG_MAX_BLOCKS, "CG product grid larger than the partial buffers");
 inline int cg_spmv_blocks(int n) {
   const int ng = (n + SPMV_ROWS_PER_BLOCK - 1) / SPMV_ROWS_PER_BLOCK;
   return std::max(1, std::min(ng, CG_SPMV_BLOCKS));
@@ -860,6 +861,34 @@ k_scg_init(int n, const T *__restrict__ v, const T *__restrict__ dinv, T *x, T *
   if (threadIdx.x == 0) prz[blockIdx.x] = rz;
 }
 
+// Off-diagonal part of row ro of S^ times z: lane l of the row's 16 takes
+// slots l, l + 16, l + 32, l + 48 of each 64-slot segment (four column loads
+// and four gathers in flight per lane).  With sorted columns the 16 lanes of
+// one gather touch neighbouring columns; giving each lane four consecutive
+// slots instead (one vector load each for columns and values) measured
+// slower, since each gather instruction then spans the whole row.
+template <typename T>
+__device__ __forceinline__ double shat_row_dot(int W2, const int32_t *__restrict__ sc, const T *__restrict__ S,
+                                               const T *__restrict__ z, int64_t r0, int lane) {
+  double a = 0.0;
+  for (int q0 = 0; q0 < W2; q0 += 64) {
+    int c[4];
+    double v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      c[u] = sc[r0 + q0 + lane + 16 * u];
+      v[u] = ld(S, r0 + q0 + lane + 16 * u);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) a += v[u] * ld(z, c[u]);
+  }
+  return a;
+}
+
+// CG step i on S^, first half: every workgroup sums the <r,z> partials
+// (zero or non-finite: the steps end), beta = rz_i / rz_{i-1}; then w = S^ z
+// and the rows' own q = w + beta q, p = z + beta p (step 0: q = w, and p_0 = z
+// is copied by the update kernel), with one partial of <p,q> per workgroup.
 template <typename T>
 __global__ void __launch_bounds__(VMS_BLOCK)
 k_scg_spmv(int n, int W2, const int32_t *__restrict__ sc, const T *__restrict__ S, const T *__restrict__ Sd,
@@ -887,27 +916,14 @@ k_scg_spmv(int n, int W2, const int32_t *__restrict__ sc, const T *__restrict__ 
     const int row = g * SPMV_ROWS_PER_BLOCK + sub;
     const bool act = row < n;
     const int ro = act ? row : 0;
-    const int64_t r0 = (int64_t)W2 * ro;
     // the row's own values ahead of the product
     const double zi = ld(z, ro), sii = ld(Sd, ro);
     const double pi = first ? 0.0 : ld(p, ro), qi = first ? 0.0 : ld(q, ro);
-    double a = 0.0;
-    for (int q0 = 0; q0 < W2; q0 += 64) {
-      int c[4];
-      double v[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        c[u] = sc[r0 + q0 + lane + 16 * u];
-        v[u] = ld(S, r0 + q0 + lane + 16 * u);
-      }
-#pragma unroll
-      for (int u = 0; u < 4; ++u) a += v[u] * ld(z, c[u]);
-    }
-    a = reduce16(a) + sii * zi;
+    const double a = reduce16(shat_row_dot(W2, sc, S, z, (int64_t)W2 * ro, lane)) + sii * zi;
     if (act && lane == 0) {
       const T pn = first ? (T)zi : (T)(zi + beta * pi);
       const T qn = first ? (T)a : (T)(a + beta * qi);
-      p[row] = pn;
+      if (!first) p[row] = pn;
       q[row] = qn;
       pq += (double)pn * (double)qn;
     }
@@ -918,7 +934,7 @@ k_scg_spmv(int n, int W2, const int32_t *__restrict__ sc, const T *__restrict__ 
 
 template <typename T>
 __global__ void __launch_bounds__(KRY_BLOCK)
-k_scg_update(int n, T *x, T *r, T *z, const T *__restrict__ p, const T *__restrict__ q, const T *__restrict__ dinv,
+k_scg_update(int n, T *x, T *r, T *z, T *p, const T *__restrict__ q, const T *__restrict__ dinv,
              const double *ctl, const double *ppq, int npq, double *prz, int *flag, int i, int last) {
   __shared__ double sm[16];
   __shared__ int done0;
@@ -933,7 +949,9 @@ k_scg_update(int n, T *x, T *r, T *z, const T *__restrict__ p, const T *__restri
   }
   double rz = 0.0;
   for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) {
-    x[k] = (T)(ld(x, k) + alpha * ld(p, k));
+    const T pk = (i == 0) ? z[k] : p[k];   // p_0 = z_0, kept for the next step
+    if (i == 0 && !last) p[k] = pk;
+    x[k] = (T)(ld(x, k) + alpha * (double)pk);
     if (!last) {
       const T rk = (T)(ld(r, k) - alpha * ld(q, k));
       const T zk = (T)(ld(dinv, k) * (double)rk);
@@ -1453,7 +1471,7 @@ struct Nested {
       hipLaunchKernelGGL(k_scg_spmv<T>, dim3(gs), dim3(VMS_BLOCK), 0, s, n, mesh->shat_width, mesh->shat_col,
                          (const T *)Shat, (const T *)Shd, (const T *)zz, p, q, sctl, (const double *)prz, nbv, ppq,
                          sflag, i);
-      hipLaunchKernelGGL(k_scg_update<T>, dim3(nbv), dim3(KRY_BLOCK), 0, s, n, z, r, zz, (const T *)p, (const T *)q,
+      hipLaunchKernelGGL(k_scg_update<T>, dim3(nbv), dim3(KRY_BLOCK), 0, s, n, z, r, zz, p, (const T *)q,
                          (const T *)sdinv, (const double *)sctl, (const double *)ppq, gs, prz, sflag, i,
                          (int)(i == k - 1));
     }
@@ -1782,6 +1800,30 @@ extern "C" int vms_schur_hat(vms_ctx *ctx, const vms_mesh *mesh, const vms_matri
   hipLaunchKernelGGL(k_shat_form<double>, dim3((n + SHAT_ROWS - 1) / SHAT_ROWS), dim3(VMS_BLOCK), 0, ctx->stream, n,
                      mesh->slot_width, mesh->col, mesh->diag_pos, mesh->nnzb, K->A, K->B, K->C, K->D,
                      mesh->shat_width, mesh->shat_col, S, Sdiag, sdinv);
+  VMS_LAUNCH_CHECK(ctx);
+  return VMS_OK;
+}
+
+extern "C" int vms_shat_spmv(vms_ctx *ctx, const vms_mesh *mesh, const void *S, const void *Sd, const void *x,
+                             void *y, int fp32) {
+  if (!ctx) return VMS_ERR_ARG;
+  int rc = vms_check_mesh(ctx, mesh);
+  if (rc) return rc;
+  if (!S || !Sd || !x || !y) return vms_set_error(ctx, VMS_ERR_ARG, "vms_shat_spmv: missing argument");
+  if (x == y) return vms_set_error(ctx, VMS_ERR_ARG, "vms_shat_spmv: x and y must not alias");
+  const int n = mesh->n_nodes;
+  vms_dev_status *d = ctx->dstat;
+  // step 0 of the CG product kernel with a unit <r,z>: y = S^ x (its <x, y> partials go to scratch)
+  if (fp32)
+    hipLaunchKernelGGL(k_scg_spmv<float>, dim3(cg_spmv_blocks(n)), dim3(VMS_BLOCK), 0, ctx->stream, n,
+                       mesh->shat_width, mesh->shat_col, (const float *)S, (const float *)Sd, (const float *)x,
+                       (float *)nullptr, (float *)y, d->scg_ctl, (const double *)&d->scg_one, 1, d->scg_part,
+                       &d->scg_flag, 0);
+  else
+    hipLaunchKernelGGL(k_scg_spmv<double>, dim3(cg_spmv_blocks(n)), dim3(VMS_BLOCK), 0, ctx->stream, n,
+                       mesh->shat_width, mesh->shat_col, (const double *)S, (const double *)Sd, (const double *)x,
+                       (double *)nullptr, (double *)y, d->scg_ctl, (const double *)&d->scg_one, 1, d->scg_part,
+                       &d->scg_flag, 0);
   VMS_LAUNCH_CHECK(ctx);
   return VMS_OK;
 }

@@ -255,6 +255,17 @@ class Problem:
                     "vms_schur_hat")
         return S, Sd, sdinv
 
+    def shat_spmv(self, S, Sd, x, out=None):
+        """y = S^ x for (S, Sd) from schur_hat (FP64, or all FP32)."""
+        fp32 = S.dtype == torch.float32
+        for t in (S, Sd, x):
+            if t.dtype != S.dtype or not t.is_contiguous() or t.device != self.dev:
+                raise ValueError("shat_spmv: S, Sd, x must be contiguous, on the problem's device, one dtype")
+        y = torch.empty_like(x) if out is None else out
+        self._check(self.lib.vms_shat_spmv(self.ctx, C.byref(self.cmesh), _p(S), _p(Sd), _p(x), _p(y),
+                                           1 if fp32 else 0), "vms_shat_spmv")
+        return y
+
     def solve_scaled(self, K, rhs, opts, x=None, allow_nc=False):
         nb = self.lib.vms_solve_workspace(C.byref(self.cmesh), C.byref(opts))
         ws = self.workspace(nb + 512)

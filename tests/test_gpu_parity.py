@@ -185,6 +185,30 @@ def test_schur_hat_matches_oracle(problems, name):
     assert rel_err(sdinv.cpu().numpy(), expect) < 1e-12
 
 
+@pytest.mark.parametrize("name", ["cube-nu0499", "tube-hgo"])
+@pytest.mark.parametrize("fp32", [False, True])
+def test_shat_product_matches_oracle(problems, name, fp32):
+    """y = S^ x by the product kernel of the Schur preconditioner's CG steps
+    against the oracle's S^ (scipy) times the same x; FP32 storage with FP64
+    accumulation to 1e-5 of the largest |S^| |x| row sum."""
+    import scipy.sparse as sp
+    prob, mesh, mat, ti, disc = problems(name)
+    st, K, rhs, Ks, rs, W, _ = _prepared(prob, mesh, ti, disc, 62)
+    S, Sd, _ = prob.schur_hat(K)
+    A, B, Cm, D, iv, ip = AS.split_blocks(Ks)
+    Sh = (D - Cm @ sp.diags(1.0 / A.diagonal()) @ B).tocsr()
+    x = np.random.default_rng(3).standard_normal(mesh.n_nodes)
+    xt = torch.from_numpy(x).to("cuda:0")
+    if fp32:
+        y = prob.shat_spmv(S.float(), Sd.float(), xt.float()).double().cpu().numpy()
+        x = xt.float().double().cpu().numpy()
+    else:
+        y = prob.shat_spmv(S, Sd, xt).cpu().numpy()
+    ref = Sh @ x
+    scale = (abs(Sh) @ np.abs(x)).max()
+    assert np.abs(y - ref).max() <= (1e-5 if fp32 else 1e-11) * scale
+
+
 def _with_mirrors(prob, K):
     K2 = prob.new_matrix(mirror32=True)
     for a, b in ((K2.A, K.A), (K2.B, K.B), (K2.C, K.C), (K2.D, K.D)):
