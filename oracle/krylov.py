@@ -14,6 +14,7 @@ from __future__ import annotations
 
 import numpy as np
 import scipy.linalg as sla
+import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
 
@@ -98,6 +99,31 @@ def block_preconditioner(A, B, C, D, variant="ldu"):
             xp = sla.lu_solve(luS, rp)
         else:
             raise ValueError(variant)
+        return np.concatenate([xv, xp])
+
+    return apply
+
+
+def shat(A, B, C, D):
+    """S^ = D - C diag(A)^-1 B (section 4.2), sparse."""
+    return (D - C @ sp.diags(1.0 / A.diagonal()) @ B).tocsr()
+
+
+def simple_preconditioner(A, B, C, D):
+    """P_SIMPLE^-1 r with exact solves of A and S^ (section 4.3, H1 = H2 =
+    diag(A)^-1): P_SIMPLE = L Dg U with L = [[I, 0], [C A^-1, I]],
+    Dg = diag(A, S^), U = [[I, diag(A)^-1 B], [0, I]], inverted factor by
+    factor: y_v = A^-1 r_v, y_p = S^-1 (r_p - C y_v), x_v = y_v - diag(A)^-1 B y_p."""
+    luA = spla.splu(A.tocsc())
+    luS = spla.splu(shat(A, B, C, D).tocsc())
+    dAinv = 1.0 / A.diagonal()
+    nv = A.shape[0]
+
+    def apply(r):
+        rv, rp = r[:nv], r[nv:]
+        yv = luA.solve(rv)
+        xp = luS.solve(rp - C @ yv)
+        xv = yv - dAinv * (B @ xp)
         return np.concatenate([xv, xp])
 
     return apply

@@ -203,3 +203,33 @@ def test_velocity_block_is_symmetric_without_acceleration(nu):
     assert skew[0] <= 1e-14
     assert skew[1] > 1e-8
     assert skew[2] == pytest.approx(2.0 * skew[1], rel=1e-3, abs=0.0)
+
+
+def test_simple_preconditioner_inverts_its_closed_form():
+    """Section 4.3: P_SIMPLE = L diag(A, S^) U equals [[A, A diag(A)^-1 B], [C, D]];
+    the factor-by-factor inverse applied to P_SIMPLE x returns x."""
+    import scipy.sparse as sp
+    Ks, _ = _scaled_blocks()
+    A, B, C, D, _, _ = AS.split_blocks(Ks)
+    P = sp.bmat([[A, A @ sp.diags(1.0 / A.diagonal()) @ B], [C, D]]).tocsr()
+    x = np.random.default_rng(11).standard_normal(P.shape[0])
+    y = KR.simple_preconditioner(A, B, C, D)(P @ x)
+    np.testing.assert_allclose(y, x, rtol=1e-9, atol=1e-10 * np.abs(x).max())
+
+
+def test_simple_is_exact_when_A_is_diagonal():
+    """With A replaced by its diagonal, P_SIMPLE is the matrix itself, so
+    FGMRES preconditioned by it stops after one iteration; with the real A it
+    needs more (the case the nested preconditioner is built for)."""
+    import scipy.sparse as sp
+    Ks, r = _scaled_blocks()
+    A, B, C, D, iv, ip = AS.split_blocks(Ks)
+    rp = r[np.concatenate([iv, ip])]
+    Ad = sp.diags(A.diagonal()).tocsr()
+    Kd = sp.bmat([[Ad, B], [C, D]]).tocsr()
+    _, its_d, _ = KR.fgmres(lambda z: Kd @ z, rp, KR.simple_preconditioner(Ad, B, C, D), rtol=1e-10, maxit=50)
+    assert its_d == 1
+    Kp = sp.bmat([[A, B], [C, D]]).tocsr()
+    x, its, _ = KR.fgmres(lambda z: Kp @ z, rp, KR.simple_preconditioner(A, B, C, D), rtol=1e-10, maxit=200)
+    assert its > 2
+    np.testing.assert_allclose(Kp @ x, rp, rtol=0, atol=1e-9 * np.linalg.norm(rp))
