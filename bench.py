@@ -255,6 +255,11 @@ def main():
                          "both A-levels, on A itself or on (A + A^T)/2 (-sym)")
     ap.add_argument("--mixed-a-krylov", default="cg", choices=akc,
                     help="the same for the mixed form")
+    ap.add_argument("--precond", default="ldu", choices=["ldu", "upper", "lower", "diag", "simple"],
+                    help="block preconditioner: the nested Schur complement reduction (ldu) and its partial "
+                         "factorizations, or SIMPLE")
+    ap.add_argument("--schur-step", default="krylov", choices=["krylov", "shat"],
+                    help="Schur step: Krylov solve to the Schur tolerance, or one S^ preconditioner application")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-timing", action="store_true",
                     help="also event-time every A-block product launch inside the timed steps (each launch then "
@@ -290,13 +295,16 @@ def main():
     fk, fs = akm[args.fp64_a_krylov]
     mk, ms = akm[args.mixed_a_krylov]
     sm = {"chebyshev": V.SHAT_CHEBYSHEV, "cg": V.SHAT_CG}[args.shat_method]
+    pc = {"ldu": V.PC_LDU, "upper": V.PC_UPPER, "lower": V.PC_LOWER, "diag": V.PC_DIAG,
+          "simple": V.PC_SIMPLE}[args.precond]
+    ss = {"krylov": V.SCHUR_KRYLOV, "shat": V.SCHUR_SHAT}[args.schur_step]
     forms = {
         "fp64": V.solver_opts(rtol=1e-8, rtol_A=ft[0], rtol_S=ft[1], rtol_I=ft[2], shat_degree=args.shat_degree,
                               shat_ratio=args.shat_ratio, orth=orth, a_krylov=fk, cg_symmetrise=fs,
-                              shat_method=sm),
+                              shat_method=sm, precond=pc, schur_solve=ss),
         "mixed": V.solver_opts(rtol=1e-8, rtol_A=mt[0], rtol_S=mt[1], rtol_I=mt[2], precision=V.MIXED,
                                shat_degree=args.shat_degree, shat_ratio=args.shat_ratio, orth=orth, a_krylov=mk,
-                               cg_symmetrise=ms, shat_method=sm),
+                               cg_symmetrise=ms, shat_method=sm, precond=pc, schur_solve=ss),
     }
     results = {}
     for name in args.forms.split(","):
@@ -385,7 +393,8 @@ def main():
                       "nodes": n, "tets": mesh.n_tets, "unknowns": 4 * n, "nnzb": nnzb,
                       "block_slots": prob.nnzb,
                       "shat_degree": args.shat_degree, "shat_ratio": args.shat_ratio,
-                      "shat_method": args.shat_method, "orth": args.orth,
+                      "shat_method": args.shat_method, "orth": args.orth, "precond": args.precond,
+                      "schur_step": args.schur_step,
                       "a_krylov": {"fp64": args.fp64_a_krylov, "mixed": args.mixed_a_krylov},
                       "parallelism": "single GPU"},
            "roofline": roof}

@@ -66,8 +66,17 @@ enum { VMS_ASM_RESIDUAL = 1, VMS_ASM_TANGENT = 2, VMS_ASM_RKCORR = 4 };
 /* operator ids for vms_spmv */
 enum { VMS_OP_FULL = 0, VMS_OP_A = 1, VMS_OP_B = 2, VMS_OP_C = 3, VMS_OP_D = 4 };
 
-/* block preconditioner variants (section 4.2-4.4 and the partial-factorization remark) */
-enum { VMS_PC_LDU = 0, VMS_PC_UPPER = 1, VMS_PC_LOWER = 2, VMS_PC_DIAG = 3 };
+/* block preconditioner variants: the Schur complement reduction of Algorithm 1 (LDU) and its
+ * partial factorizations (section 4.4 remark), and SIMPLE (section 4.3: exact A in the lower and
+ * diagonal factors, diag(A)^-1 in the upper one, S^ for the Schur complement) */
+enum { VMS_PC_LDU = 0, VMS_PC_UPPER = 1, VMS_PC_LOWER = 2, VMS_PC_DIAG = 3, VMS_PC_SIMPLE = 4 };
+
+/* The Schur step of the block preconditioner: a Krylov solve to rtol_S (GMRES on S by the
+ * matrix-free product of Algorithm 2; for SIMPLE, GMRES on the assembled S^), right-preconditioned
+ * by the S^ preconditioner (shat_degree, shat_method); or one application of that S^
+ * preconditioner alone, with no inner A-solve (section 4.4: the loosest choice of the Schur and
+ * inner tolerances, where the method meets the coupled SIMPLE-type approach). */
+enum { VMS_SCHUR_KRYLOV = 0, VMS_SCHUR_SHAT = 1 };
 
 /* precision of the intermediate and inner levels */
 enum { VMS_FP64 = 0, VMS_MIXED = 1 };
@@ -167,6 +176,7 @@ typedef struct {
   int32_t a_krylov;   /* VMS_AK_*: GMRES or CG at the inner (or both) A-levels */
   int32_t cg_symmetrise; /* CG levels: 1 = on (A + A^T)/2, 0 = on A */
   int32_t shat_method;   /* VMS_SHAT_*: Chebyshev polynomial or CG steps on S^ (shat_degree > 0) */
+  int32_t schur_solve;   /* VMS_SCHUR_*: Krylov solve of the Schur step, or one S^ preconditioner application */
 } vms_solver_opts;
 
 typedef struct {

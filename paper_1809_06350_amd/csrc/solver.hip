@@ -1167,6 +1167,47 @@ __global__ void k_merge(int n, const T *v, const T *p, double *full) {
   full[o + 2] = (double)v[3 * (int64_t)i + 2];
   full[o + 3] = (double)p[i];
 }
+// y = S^ x (off-diagonal distance-2 slots plus the diagonal), skipped when the level is done
+template <typename T>
+__global__ void __launch_bounds__(VMS_BLOCK)
+k_shat_spmv(int n, int W2, const int32_t *__restrict__ sc, const T *__restrict__ S, const T *__restrict__ Sd,
+            const T *__restrict__ x, T *y, const int *done) {
+  if (done && *done) return;
+  const int lane = threadIdx.x & 15;
+  const int row = xcd_block(blockIdx.x, gridDim.x) * SPMV_ROWS_PER_BLOCK + (threadIdx.x >> 4);
+  const bool act = row < n;
+  const int ro = act ? row : 0;
+  const double xi = ld(x, ro), sii = ld(Sd, ro);
+  const double a = reduce16(shat_row_dot(W2, sc, S, x, (int64_t)W2 * ro, lane)) + sii * xi;
+  if (act && lane == 0) y[row] = (T)a;
+}
+
+// z = d .* v
+template <typename T>
+__global__ void k_diag_scale(int n, const T *d, const T *v, T *z) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) z[i] = (T)(ld(d, i) * ld(v, i));
+}
+
+// diag(A)^-1: the diagonal entries of the 3x3 diagonal blocks (1 where zero)
+template <typename T>
+__global__ void k_diagA_inv(int n, const int32_t *diag_pos, int64_t nnzb, const double *A, T *dAinv) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int64_t b = diag_pos[i];
+  for (int c = 0; c < 3; ++c) {
+    const double a = A[(4 * c) * nnzb + b];
+    dAinv[3 * (int64_t)i + c] = (T)((a != 0.0 && isfinite(a)) ? 1.0 / a : 1.0);
+  }
+}
+
+// last factor of the SIMPLE preconditioner: x_v = y_v - diag(A)^-1 w, w = B x_p
+template <typename T>
+__global__ void k_simple_vel(int64_t nv, const T *y, const T *w, const T *dAinv, T *x) {
+  const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (k < nv) x[k] = (T)(ld(y, k) - ld(dAinv, k) * ld(w, k));
+}
+
 __global__ void k_clear_ints(int *p, int n) {
   const int i = threadIdx.x;
   if (i < n) p[i] = 0;
@@ -1409,6 +1450,7 @@ struct Nested {
   double *cgpart = nullptr;                   // partials of <p, A p> of the CG product kernel
   double *sctl = nullptr;                     // CG steps on S^: rz history [2], <p,q> partials, <r,z> partials
   int *sflag = nullptr;
+  T *dAinv = nullptr;                         // SIMPLE: diag(A)^-1
   double *lam = nullptr;                      // device: lmax estimate of diag(S^)^-1 S^
   vms_solve_stats *stats;
   int err = VMS_OK;
@@ -1433,6 +1475,7 @@ struct Nested {
     cd1 = cv.take<T>(nn);
     px = cv.take<T>(nn);
     py = cv.take<T>(nn);
+    if (o_->precond == VMS_PC_SIMPLE) dAinv = cv.take<T>(3 * nn);
     if (o_->shat_method == VMS_SHAT_CG && o_->shat_degree > 0) {
       sctl = cv.take<double>(2 + CG_SPMV_BLOCKS + VMS_MAX_RED_BLOCKS);
       sflag = cv.take<int>(1);
@@ -1544,19 +1587,73 @@ struct Nested {
     return rc;
   }
 
-  // z = P_SCR^-1 v (Algorithm 1 and its partial-factorization variants)
+  // z ~ S^-1 v by the Schur solve's preconditioner: diag(S^)^-1, Chebyshev or CG steps on S^
+  void shat_prec(const T *v, T *z) {
+    if (o->shat_degree <= 0)
+      hipLaunchKernelGGL(k_diag_scale<T>, dim3(grid1(n)), dim3(VMS_BLOCK), 0, ctx->stream, n, (const T *)sdinv, v, z);
+    else if (o->shat_method == VMS_SHAT_CG)
+      scg_apply(v, z);
+    else
+      cheb_apply(v, z);
+  }
+
+  // x = S^-1 b by flexible GMRES on the assembled S^ (SIMPLE, section 4.3), right-preconditioned
+  // like the Schur solve
+  int solve_shat(const T *b, T *x) {
+    int its = 0, st = 0;
+    auto op = [&](int j) -> int {
+      T *z = LS.Z + (int64_t)j * LS.nvec;
+      shat_prec(LS.V + (int64_t)j * LS.nvec, z);
+      hipLaunchKernelGGL(k_shat_spmv<T>, dim3(spmv_grid(n)), dim3(VMS_BLOCK), 0, ctx->stream, n, mesh->shat_width,
+                         mesh->shat_col, (const T *)Shat, (const T *)Shd, (const T *)z, LS.W,
+                         (const int *)(LS.iflag + IF_DONE));
+      return VMS_OK;
+    };
+    int rc = gmres_run<T>(ctx, LS, b, x, o->rtol_S, o->atol_S, o->maxit_S, o->orth, PC_NONE, (const T *)nullptr,
+                          true, ctx->est_S, op, its, st);
+    stats->n_S_solves++;
+    stats->it_S += its;
+    return rc;
+  }
+
+  // x_p for the Schur step: a Krylov solve (S by Algorithm 2, or S^ for SIMPLE) or one application
+  // of the S^ preconditioner
+  int schur_step(const T *b, T *x) {
+    if (o->schur_solve == VMS_SCHUR_SHAT) {
+      shat_prec(b, x);
+      VMS_LAUNCH_CHECK(ctx);
+      stats->n_S_solves++;
+      return VMS_OK;
+    }
+    return (o->precond == VMS_PC_SIMPLE) ? solve_shat(b, x) : solve_S(b, x);
+  }
+
+  // z = P_SCR^-1 v (Algorithm 1 and its partial-factorization variants) or P_SIMPLE^-1 v (section 4.3)
   int apply(const double *v_full, double *z_full) {
     hipStream_t s = ctx->stream;
     hipLaunchKernelGGL(k_split<T>, dim3(grid1(n)), dim3(VMS_BLOCK), 0, s, n, v_full, rv, rp);
     VMS_LAUNCH_CHECK(ctx);
     int rc;
     const int var = o->precond;
+    if (var == VMS_PC_SIMPLE) {
+      if ((rc = solve_A(rv, xh, false))) return rc;                 // y_v = A^-1 r_v
+      hipLaunchKernelGGL((k_spmv_CD<T, T>), dim3(spmv_grid(n)), dim3(VMS_BLOCK), 0, s, n, nnzb, mesh->slot_width,
+                         mesh->col, C, D, xh, (const T *)nullptr, rp, rp, -1.0, 0.0, (const int *)nullptr);
+      if ((rc = schur_step(rp, xp))) return rc;                      // x_p = S^-1 (r_p - C y_v)
+      hipLaunchKernelGGL((k_spmv_B<T, T>), dim3(spmv_grid(n)), dim3(VMS_BLOCK), 0, s, n, nnzb, mesh->slot_width,
+                         mesh->col, B, xp, xbar, (const T *)nullptr, 1.0, (const int *)nullptr);
+      hipLaunchKernelGGL(k_simple_vel<T>, dim3(grid1(3 * (int64_t)n)), dim3(VMS_BLOCK), 0, s, 3 * (int64_t)n,
+                         (const T *)xh, (const T *)xbar, (const T *)dAinv, xv);  // x_v = y_v - diag(A)^-1 B x_p
+      hipLaunchKernelGGL(k_merge<T>, dim3(grid1(n)), dim3(VMS_BLOCK), 0, s, n, xv, xp, z_full);
+      VMS_LAUNCH_CHECK(ctx);
+      return VMS_OK;
+    }
     if (var == VMS_PC_LDU || var == VMS_PC_LOWER) {
       if ((rc = solve_A(rv, xh, false))) return rc;                 // step 1
       hipLaunchKernelGGL((k_spmv_CD<T, T>), dim3(spmv_grid(n)), dim3(VMS_BLOCK), 0, s, n, nnzb, mesh->slot_width,
                          mesh->col, C, D, xh, (const T *)nullptr, rp, rp, -1.0, 0.0, (const int *)nullptr);  // step 2
     }
-    if ((rc = solve_S(rp, xp))) return rc;                           // step 3
+    if ((rc = schur_step(rp, xp))) return rc;                        // step 3
     if (var == VMS_PC_LDU || var == VMS_PC_UPPER) {
       hipLaunchKernelGGL((k_spmv_B<T, T>), dim3(spmv_grid(n)), dim3(VMS_BLOCK), 0, s, n, nnzb, mesh->slot_width,
                          mesh->col, B, xp, rv, rv, -1.0, (const int *)nullptr);  // step 4
@@ -1579,6 +1676,9 @@ struct Nested {
                        K->A, Minv, sym);
     if (sym)
       hipLaunchKernelGGL(k_sym_A<T>, dim3(grid1(nnzb)), dim3(VMS_BLOCK), 0, ctx->stream, nnzb, mesh->tpos, K->A, As);
+    if (o->precond == VMS_PC_SIMPLE)
+      hipLaunchKernelGGL(k_diagA_inv<T>, dim3(grid1(n)), dim3(VMS_BLOCK), 0, ctx->stream, n, mesh->diag_pos, nnzb,
+                         K->A, dAinv);
     // S^ from the FP64 scaled blocks (stored in the level precision), and diag(S^)^-1
     hipLaunchKernelGGL(k_shat_form<T>, dim3((n + SHAT_ROWS - 1) / SHAT_ROWS), dim3(VMS_BLOCK), 0, ctx->stream, n,
                        mesh->slot_width, mesh->col, mesh->diag_pos, nnzb, K->A, K->B, K->C, K->D, mesh->shat_width,
@@ -1615,7 +1715,7 @@ int check_opts(vms_ctx *ctx, const vms_solver_opts *o) {
   if (!o || o->maxit <= 0 || o->maxit_A <= 0 || o->maxit_S <= 0 || o->maxit_I <= 0 || o->maxit > 1000 ||
       o->maxit_A > 1000 || o->maxit_S > 1000 || o->maxit_I > 1000)
     return vms_set_error(ctx, VMS_ERR_ARG, "solver options: maxit must be in [1, 1000]");
-  if (o->precond < VMS_PC_LDU || o->precond > VMS_PC_DIAG)
+  if (o->precond < VMS_PC_LDU || o->precond > VMS_PC_SIMPLE)
     return vms_set_error(ctx, VMS_ERR_ARG, "unknown preconditioner variant");
   if (o->precision != VMS_FP64 && o->precision != VMS_MIXED)
     return vms_set_error(ctx, VMS_ERR_ARG, "unknown precision");
@@ -1630,6 +1730,8 @@ int check_opts(vms_ctx *ctx, const vms_solver_opts *o) {
     return vms_set_error(ctx, VMS_ERR_ARG, "cg_symmetrise must be 0 or 1");
   if (o->shat_method != VMS_SHAT_CHEBYSHEV && o->shat_method != VMS_SHAT_CG)
     return vms_set_error(ctx, VMS_ERR_ARG, "unknown S^ preconditioner method");
+  if (o->schur_solve != VMS_SCHUR_KRYLOV && o->schur_solve != VMS_SCHUR_SHAT)
+    return vms_set_error(ctx, VMS_ERR_ARG, "unknown Schur step");
   return VMS_OK;
 }
 

@@ -341,6 +341,49 @@ def test_shat_cg_steps_approach_exact_shat(problems):
     assert np.linalg.norm(x.cpu().numpy().ravel() - xo) <= 1e-7 * np.linalg.norm(xo)
 
 
+@pytest.mark.parametrize("name", ["cube-comp", "cube-nu0499"])
+def test_simple_matches_oracle_iterations(problems, name):
+    """SIMPLE (section 4.3) with its A- and S^-solves run to 1e-13 takes as
+    many outer FGMRES iterations (within one) as the oracle's FGMRES with the
+    exact SIMPLE factors, and reaches the LU solution."""
+    import scipy.sparse.linalg as spla
+    from oracle import krylov as KR
+    prob, mesh, mat, ti, disc = problems(name)
+    st, K, rhs, Ks, rs, W, _ = _prepared(prob, mesh, ti, disc, 87)
+    opts = V.solver_opts(rtol=1e-9, rtol_A=1e-13, rtol_S=1e-13, maxit=100, maxit_A=400, maxit_S=400,
+                         precond=V.PC_SIMPLE)
+    x, stats = prob.solve_scaled(K, rhs, opts)
+    print(f"[solve] SIMPLE {name} stats={stats}", flush=True)
+    A, B, Cm, D, iv, ip = AS.split_blocks(Ks)
+    perm = np.concatenate([iv, ip])
+    Kp = Ks[perm][:, perm].tocsr()
+    _, its, _ = KR.fgmres(lambda z: Kp @ z, rs[perm], KR.simple_preconditioner(A, B, Cm, D), rtol=1e-9, maxit=100)
+    print(f"[solve] oracle SIMPLE: {its} outer iterations", flush=True)
+    assert abs(stats["n_outer"] - its) <= 1
+    assert stats["n_I_solves"] == 0 and stats["n_S_solves"] == stats["n_outer"]
+    xo = spla.splu(Ks.tocsc()).solve(rs)
+    assert np.linalg.norm(x.cpu().numpy().ravel() - xo) <= 1e-7 * np.linalg.norm(xo)
+
+
+@pytest.mark.parametrize("precond", [V.PC_LDU, V.PC_SIMPLE])
+@pytest.mark.parametrize("precision", [V.FP64, V.MIXED])
+def test_single_shat_schur_step_reaches_lu(problems, precond, precision):
+    """The Schur step as one application of the S^ preconditioner (no inner
+    solve, the loosest end of section 4.4) is still a valid preconditioner:
+    the outer FGMRES reaches the requested residual and the LU solution."""
+    import scipy.sparse.linalg as spla
+    prob, mesh, mat, ti, disc = problems("cube-nu0499")
+    st, K, rhs, Ks, rs, W, _ = _prepared(prob, mesh, ti, disc, 89, mirror32=(precision == V.MIXED))
+    opts = V.solver_opts(rtol=1e-8, precond=precond, precision=precision, schur_solve=V.SCHUR_SHAT)
+    x, stats = prob.solve_scaled(K, rhs, opts)
+    print(f"[solve] S^-only precond={precond} precision={precision} stats={stats}", flush=True)
+    assert stats["n_I_solves"] == 0 and stats["it_S"] == 0 and stats["n_S_solves"] == stats["n_outer"]
+    xg = x.cpu().numpy().ravel()
+    assert np.linalg.norm(Ks @ xg - rs) <= 2e-8 * np.linalg.norm(rs)
+    xo = spla.splu(Ks.tocsc()).solve(rs)
+    assert np.linalg.norm(xg - xo) <= 1e-5 * np.linalg.norm(xo)
+
+
 def test_newton_update_matches_oracle(problems):
     prob, mesh, mat, ti, disc = problems("cube-comp")
     sn, it = states(mesh, 91)
