@@ -40,11 +40,15 @@ def spmv_A_bytes(n, nnzb, elem):
     return (9 * elem + 4) * nnzb + 2 * 3 * elem * n
 
 
-def shat_bytes(n, nnz, elem):
+def shat_bytes(n, nnz, elem, idx=4):
     """Algorithmic bytes of one S^ product of the Schur preconditioner's CG
     steps (its first step, as timed): the real off-diagonal entries (value +
-    column index), the diagonal, x once (gathers cached) and y."""
-    return (elem + 4) * nnz + 3 * elem * n
+    column index or 2-byte offset), the diagonal, x once (gathers cached) and y."""
+    return (elem + idx) * nnz + 3 * elem * n
+
+
+def shat_idx_bytes(prob):
+    return 2 if prob.d.get("shat_off") is not None else 4
 
 
 # kernel -> (source file, first and end markers of the kernel's source text (None: whole file), summary)
@@ -225,9 +229,9 @@ def spmv_only(prob, mesh, ti, reps):
                       "calibration_bytes_each_way": src.numel() * 8,
                       "bytes_fp64": spmv_A_bytes(n, nz, 8), "us_fp64": t64 * 1e6,
                       "bytes_fp32": spmv_A_bytes(n, nz, 4), "us_fp32": t32 * 1e6,
-                      "shat_nnz": nzs, "shat_bytes_fp64": shat_bytes(n, nzs, 8),
+                      "shat_nnz": nzs, "shat_bytes_fp64": shat_bytes(n, nzs, 8, shat_idx_bytes(prob)),
                       "shat_us_fp64": time_shat(prob, K32, False) * 1e6,
-                      "shat_bytes_fp32": shat_bytes(n, nzs, 4),
+                      "shat_bytes_fp32": shat_bytes(n, nzs, 4, shat_idx_bytes(prob)),
                       "shat_us_fp32": time_shat(prob, K32, True) * 1e6}), flush=True)
 
 
@@ -330,7 +334,7 @@ def main():
     by64 = spmv_A_bytes(n, nnzb, 8)
     nzs = shat_real_entries(prob)
     ts64 = time_shat(prob, K, False)
-    bys64 = shat_bytes(n, nzs, 8)
+    bys64 = shat_bytes(n, nzs, 8, shat_idx_bytes(prob))
     steps_stats = r["per_step"]
     launches_A = sum(p["it_A_total"] + p["it_I_total"] for p in steps_stats) / args.steps
     launches_S = (sum(p["it_S_total"] for p in steps_stats) / args.steps * so.shat_degree
@@ -368,7 +372,7 @@ def main():
                                 "frac_hbm": by32 / t32 / 1e9 / HBM_PEAK_GBS,
                                 "traffic": pmc_traffic("spmv_A", "traffic_bytes_fp32") if N == 64 else None}
         ts32 = time_shat(prob, rm["K"], True)
-        bys32 = shat_bytes(n, nzs, 4)
+        bys32 = shat_bytes(n, nzs, 4, shat_idx_bytes(prob))
         extra["shat_fp32"] = {"GB/s": bys32 / ts32 / 1e9, "us_per_launch": ts32 * 1e6, "bytes_per_launch": bys32,
                               "frac_hbm": bys32 / ts32 / 1e9 / HBM_PEAK_GBS,
                               "traffic": pmc_traffic("shat", "traffic_bytes_fp32") if N == 64 else None}

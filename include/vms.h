@@ -143,6 +143,9 @@ typedef struct {
   int32_t shat_width;       /* W2: slots per row of the off-diagonal distance-2 pattern (multiple of 64) */
   const int32_t *shat_col;  /* [n * W2] off-diagonal pattern of S^ = D - C diag(A)^-1 B: sorted
                                columns first, padding slots hold the row's own node */
+  const int16_t *shat_off;  /* [n * W2] or NULL: shat_col - row, when every offset fits in int16
+                               (vms_setup_sizes' shat_span <= 32767); the S^ products then read
+                               these 2-byte offsets instead of the 4-byte columns */
   const int32_t *nf_ptr;    /* [n+1] node -> loaded faces */
   const int32_t *nf_face;   /* [3f] */
 } vms_mesh;
@@ -238,11 +241,13 @@ int vms_ctx_kernel_time(vms_ctx *ctx, int kind, double *ms_total, int64_t *launc
  * nodes sharing a tetrahedron couples, section 3.1): *slot_width = W (the
  * longest row rounded up to a multiple of 16), *nnzb = W * n_nodes, and
  * *shat_width = W2, the longest off-diagonal row of the distance-2 pattern
- * (nodes two graph steps apart) rounded up to a multiple of 64.  tets: HOST
+ * (nodes two graph steps apart) rounded up to a multiple of 64; if shat_span
+ * is not NULL, *shat_span = the largest |column - row| of that pattern (at
+ * most 32767: the compact 2-byte offsets shat_off can be built).  tets: HOST
  * [m][4].  VMS_ERR_ARG on an out-of-range node, n_tets > VMS_MAX_TETS,
  * W * n_nodes or W2 * n_nodes >= 2^31, or W2 > VMS_MAX_SHAT_ROW. */
 int vms_setup_sizes(int32_t n_nodes, int32_t n_tets, const int32_t *tets, int64_t *nnzb,
-                    int32_t *slot_width, int32_t *shat_width);
+                    int32_t *slot_width, int32_t *shat_width, int32_t *shat_span);
 
 /* Build, into HOST arrays sized by vms_setup_sizes: row_len[n], col[nnzb]
  * (slot layout above), tpos[nnzb] (position of the transposed block; a
@@ -250,12 +255,14 @@ int vms_setup_sizes(int32_t n_nodes, int32_t n_tets, const int32_t *tets, int64_
  * blk_src_ptr[nnzb+1], blk_src[16m] (every element-local pair e*16 + a*4 + b
  * under the block (tets[e][a], tets[e][b]), in increasing e; padding slots
  * have none), the off-diagonal distance-2 pattern shat_col[n * W2] (sorted
- * columns first, padding slots hold the row's own node), and node ->
- * loaded-face lists nf_ptr[n+1], nf_face[3f] (bfaces: HOST [f][3]). */
+ * columns first, padding slots hold the row's own node), optionally its
+ * offsets shat_off[n * W2] = shat_col - row (NULL: not built; VMS_ERR_ARG if
+ * one does not fit in int16), and node -> loaded-face lists nf_ptr[n+1],
+ * nf_face[3f] (bfaces: HOST [f][3]). */
 int vms_setup_build(int32_t n_nodes, int32_t n_tets, const int32_t *tets,
                     int32_t n_bfaces, const int32_t *bfaces,
                     int32_t *row_len, int32_t *col, int32_t *tpos, int32_t *diag_pos,
-                    int32_t *blk_src_ptr, int32_t *blk_src, int32_t *shat_col,
+                    int32_t *blk_src_ptr, int32_t *blk_src, int32_t *shat_col, int16_t *shat_off,
                     int32_t *nf_ptr, int32_t *nf_face);
 
 /* ---- assembly (section 3.3 steps 1-4; consistent-linearization appendix) - */

@@ -26,7 +26,7 @@ class Mesh(C.Structure):
                 ("dir_mask", C.c_void_p), ("dir_vel", C.c_void_p), ("fibre", C.c_void_p),
                 ("col", C.c_void_p), ("tpos", C.c_void_p), ("diag_pos", C.c_void_p),
                 ("blk_src_ptr", C.c_void_p), ("blk_src", C.c_void_p), ("shat_width", C.c_int32),
-                ("shat_col", C.c_void_p), ("nf_ptr", C.c_void_p),
+                ("shat_col", C.c_void_p), ("shat_off", C.c_void_p), ("nf_ptr", C.c_void_p),
                 ("nf_face", C.c_void_p)]
 
 
@@ -85,8 +85,9 @@ SIGNATURES = {
     "vms_last_error": (C.c_char_p, [C.c_void_p]),
     "vms_ctx_set_timing": (C.c_int, [C.c_void_p, C.c_int]),
     "vms_ctx_kernel_time": (C.c_int, [C.c_void_p, C.c_int, P(C.c_double), P(C.c_int64)]),
-    "vms_setup_sizes": (C.c_int, [C.c_int32, C.c_int32, C.c_void_p, P(C.c_int64), P(C.c_int32), P(C.c_int32)]),
-    "vms_setup_build": (C.c_int, [C.c_int32, C.c_int32, C.c_void_p, C.c_int32, C.c_void_p] + [C.c_void_p] * 9),
+    "vms_setup_sizes": (C.c_int, [C.c_int32, C.c_int32, C.c_void_p, P(C.c_int64), P(C.c_int32), P(C.c_int32),
+                                  P(C.c_int32)]),
+    "vms_setup_build": (C.c_int, [C.c_int32, C.c_int32, C.c_void_p, C.c_int32, C.c_void_p] + [C.c_void_p] * 10),
     "vms_nodal_load": (C.c_int, [C.c_void_p, P(Mesh), C.c_void_p]),
     "vms_predictor": (C.c_int, [C.c_void_p, P(Mesh), P(TimeInt), P(State)]),
     "vms_assemble_workspace": (C.c_size_t, [P(Mesh), C.c_uint]),

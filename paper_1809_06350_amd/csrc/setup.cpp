@@ -27,6 +27,7 @@
 //                  padding slots hold the row's own node,
 //   node -> loaded boundary face lists (for the dead-load vector).
 #include <algorithm>
+#include <cstdlib>
 #include <cstdint>
 #include <cstring>
 #include <vector>
@@ -113,7 +114,7 @@ static int32_t slot_width(const Graph &g, int32_t n) {
 }
 
 extern "C" int vms_setup_sizes(int32_t n_nodes, int32_t n_tets, const int32_t *tets, int64_t *nnzb,
-                               int32_t *slot_width_out, int32_t *shat_width_out) {
+                               int32_t *slot_width_out, int32_t *shat_width_out, int32_t *shat_span_out) {
   if (n_nodes <= 0 || n_tets < 0 || (!tets && n_tets > 0) || !nnzb || !slot_width_out || !shat_width_out)
     return VMS_ERR_ARG;
   if ((int64_t)n_tets > VMS_MAX_TETS) return VMS_ERR_ARG;
@@ -123,19 +124,26 @@ extern "C" int vms_setup_sizes(int32_t n_nodes, int32_t n_tets, const int32_t *t
   const int32_t W = slot_width(g, n_nodes);
   if ((int64_t)W * n_nodes >= ((int64_t)1 << 31)) return VMS_ERR_ARG;
   std::vector<int64_t> p2;
-  build_ring2(g, n_nodes, p2, nullptr);
+  std::vector<int32_t> c2;
+  build_ring2(g, n_nodes, p2, shat_span_out ? &c2 : nullptr);
   const int32_t W2 = ring2_width(p2, n_nodes);
   if (W2 > VMS_MAX_SHAT_ROW || (int64_t)W2 * n_nodes >= ((int64_t)1 << 31)) return VMS_ERR_ARG;
   *slot_width_out = W;
   *nnzb = (int64_t)W * n_nodes;
   *shat_width_out = W2;
+  if (shat_span_out) {
+    int64_t span = 0;
+    for (int32_t i = 0; i < n_nodes; ++i)
+      for (int64_t k = p2[i]; k < p2[i + 1]; ++k) span = std::max<int64_t>(span, std::abs((int64_t)c2[k] - i));
+    *shat_span_out = (int32_t)span;
+  }
   return VMS_OK;
 }
 
 extern "C" int vms_setup_build(int32_t n_nodes, int32_t n_tets, const int32_t *tets,
                                int32_t n_bfaces, const int32_t *bfaces,
                                int32_t *row_len, int32_t *col, int32_t *tpos, int32_t *diag_pos,
-                               int32_t *blk_src_ptr, int32_t *blk_src, int32_t *shat_col,
+                               int32_t *blk_src_ptr, int32_t *blk_src, int32_t *shat_col, int16_t *shat_off,
                                int32_t *nf_ptr, int32_t *nf_face) {
   if (n_nodes <= 0 || n_tets < 0 || (int64_t)n_tets > VMS_MAX_TETS || !row_len || !col || !tpos || !diag_pos ||
       !shat_col ||
@@ -190,8 +198,15 @@ extern "C" int vms_setup_build(int32_t n_nodes, int32_t n_tets, const int32_t *t
     if (W2 > VMS_MAX_SHAT_ROW || (int64_t)W2 * n_nodes >= ((int64_t)1 << 31)) return VMS_ERR_ARG;
     for (int32_t i = 0; i < n_nodes; ++i) {
       const int64_t len = p2[i + 1] - p2[i];
-      for (int32_t s2 = 0; s2 < W2; ++s2)
-        shat_col[(int64_t)W2 * i + s2] = (s2 < len) ? c2[p2[i] + s2] : i;
+      for (int32_t s2 = 0; s2 < W2; ++s2) {
+        const int32_t c = (s2 < len) ? c2[p2[i] + s2] : i;
+        shat_col[(int64_t)W2 * i + s2] = c;
+        if (shat_off) {
+          const int32_t d = c - i;
+          if (d < -32768 || d > 32767) return VMS_ERR_ARG;
+          shat_off[(int64_t)W2 * i + s2] = (int16_t)d;
+        }
+      }
     }
   }
 

@@ -866,23 +866,34 @@ k_scg_init(int n, const T *__restrict__ v, const T *__restrict__ dinv, T *x, T *
 // and four gathers in flight per lane).  With sorted columns the 16 lanes of
 // one gather touch neighbouring columns; giving each lane four consecutive
 // slots instead (one vector load each for columns and values) measured
-// slower, since each gather instruction then spans the whole row.
-template <typename T>
-__device__ __forceinline__ double shat_row_dot(int W2, const int32_t *__restrict__ sc, const T *__restrict__ S,
-                                               const T *__restrict__ z, int64_t r0, int lane) {
+// slower, since each gather instruction then spans the whole row.  The
+// columns come as 2-byte offsets from the row when so != NULL (a quarter of
+// the FP32 product's bytes saved), else as 4-byte indices.
+template <typename T, bool OFF>
+__device__ __forceinline__ double shat_row_dot_t(int W2, const int32_t *__restrict__ sc,
+                                                 const int16_t *__restrict__ so, const T *__restrict__ S,
+                                                 const T *__restrict__ z, int64_t r0, int ro, int lane) {
   double a = 0.0;
   for (int q0 = 0; q0 < W2; q0 += 64) {
     int c[4];
     double v[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      c[u] = sc[r0 + q0 + lane + 16 * u];
+      c[u] = OFF ? ro + (int)so[r0 + q0 + lane + 16 * u] : sc[r0 + q0 + lane + 16 * u];
       v[u] = ld(S, r0 + q0 + lane + 16 * u);
     }
 #pragma unroll
     for (int u = 0; u < 4; ++u) a += v[u] * ld(z, c[u]);
   }
   return a;
+}
+template <typename T>
+__device__ __forceinline__ double shat_row_dot(int W2, const int32_t *__restrict__ sc,
+                                               const int16_t *__restrict__ so, const T *__restrict__ S,
+                                               const T *__restrict__ z, int ro, int lane) {
+  const int64_t r0 = (int64_t)W2 * ro;
+  return so ? shat_row_dot_t<T, true>(W2, sc, so, S, z, r0, ro, lane)
+            : shat_row_dot_t<T, false>(W2, sc, so, S, z, r0, ro, lane);
 }
 
 // CG step i on S^, first half: every workgroup sums the <r,z> partials
@@ -891,9 +902,9 @@ __device__ __forceinline__ double shat_row_dot(int W2, const int32_t *__restrict
 // is copied by the update kernel), with one partial of <p,q> per workgroup.
 template <typename T>
 __global__ void __launch_bounds__(VMS_BLOCK)
-k_scg_spmv(int n, int W2, const int32_t *__restrict__ sc, const T *__restrict__ S, const T *__restrict__ Sd,
-           const T *__restrict__ z, T *p, T *q, double *ctl, const double *prz, int nrz, double *ppq, int *flag,
-           int i) {
+k_scg_spmv(int n, int W2, const int32_t *__restrict__ sc, const int16_t *__restrict__ so, const T *__restrict__ S,
+           const T *__restrict__ Sd, const T *__restrict__ z, T *p, T *q, double *ctl, const double *prz, int nrz,
+           double *ppq, int *flag, int i) {
   __shared__ double sm[16];
   __shared__ int done0;
   if (threadIdx.x == 0) done0 = *flag;
@@ -919,7 +930,7 @@ k_scg_spmv(int n, int W2, const int32_t *__restrict__ sc, const T *__restrict__ 
     // the row's own values ahead of the product
     const double zi = ld(z, ro), sii = ld(Sd, ro);
     const double pi = first ? 0.0 : ld(p, ro), qi = first ? 0.0 : ld(q, ro);
-    const double a = reduce16(shat_row_dot(W2, sc, S, z, (int64_t)W2 * ro, lane)) + sii * zi;
+    const double a = reduce16(shat_row_dot(W2, sc, so, S, z, ro, lane)) + sii * zi;
     if (act && lane == 0) {
       const T pn = first ? (T)zi : (T)(zi + beta * pi);
       const T qn = first ? (T)a : (T)(a + beta * qi);
@@ -1065,9 +1076,9 @@ __device__ __forceinline__ void cheb_coef(const double *lam, double ratio, int k
 // MODE 1 (Chebyshev step k): x += d; r -= S^ d; y = rho1 rho0 d + 2 rho1/delta diag(S^)^-1 r
 template <typename T, int MODE>
 __global__ void __launch_bounds__(VMS_BLOCK)
-k_shat_cheb(int n, int W2, const int32_t *__restrict__ sc, const T *__restrict__ S, const T *__restrict__ Sd,
-            const T *__restrict__ d, const T *__restrict__ sdinv, T *y, T *x, T *r, const double *lam, double ratio,
-            int k) {
+k_shat_cheb(int n, int W2, const int32_t *__restrict__ sc, const int16_t *__restrict__ so, const T *__restrict__ S,
+            const T *__restrict__ Sd, const T *__restrict__ d, const T *__restrict__ sdinv, T *y, T *x, T *r,
+            const double *lam, double ratio, int k) {
   const int lane = threadIdx.x & 15;
   const int row = xcd_block(blockIdx.x, gridDim.x) * SPMV_ROWS_PER_BLOCK + (threadIdx.x >> 4);
   const bool act = row < n;
@@ -1081,19 +1092,7 @@ k_shat_cheb(int n, int W2, const int32_t *__restrict__ sc, const T *__restrict__
     ri = ld(r, ro);
     cheb_coef(lam, ratio, k, rho0, rho1, delta, theta);
   }
-  double a = 0.0;
-  for (int q0 = 0; q0 < W2; q0 += 64) {
-    int c[4];
-    double v[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      c[u] = sc[r0 + q0 + lane + 16 * u];
-      v[u] = ld(S, r0 + q0 + lane + 16 * u);
-    }
-#pragma unroll
-    for (int u = 0; u < 4; ++u) a += v[u] * ld(d, c[u]);
-  }
-  a = reduce16(a) + sii * di;
+  const double a = reduce16(shat_row_dot(W2, sc, so, S, d, ro, lane)) + sii * di;
   if (act && lane == 0) {
     if (MODE == 0) {
       y[row] = (T)(sdi * a);
@@ -1170,15 +1169,15 @@ __global__ void k_merge(int n, const T *v, const T *p, double *full) {
 // y = S^ x (off-diagonal distance-2 slots plus the diagonal), skipped when the level is done
 template <typename T>
 __global__ void __launch_bounds__(VMS_BLOCK)
-k_shat_spmv(int n, int W2, const int32_t *__restrict__ sc, const T *__restrict__ S, const T *__restrict__ Sd,
-            const T *__restrict__ x, T *y, const int *done) {
+k_shat_spmv(int n, int W2, const int32_t *__restrict__ sc, const int16_t *__restrict__ so, const T *__restrict__ S,
+            const T *__restrict__ Sd, const T *__restrict__ x, T *y, const int *done) {
   if (done && *done) return;
   const int lane = threadIdx.x & 15;
   const int row = xcd_block(blockIdx.x, gridDim.x) * SPMV_ROWS_PER_BLOCK + (threadIdx.x >> 4);
   const bool act = row < n;
   const int ro = act ? row : 0;
   const double xi = ld(x, ro), sii = ld(Sd, ro);
-  const double a = reduce16(shat_row_dot(W2, sc, S, x, (int64_t)W2 * ro, lane)) + sii * xi;
+  const double a = reduce16(shat_row_dot(W2, sc, so, S, x, ro, lane)) + sii * xi;
   if (act && lane == 0) y[row] = (T)a;
 }
 
@@ -1495,7 +1494,8 @@ struct Nested {
     hipLaunchKernelGGL(k_cheb_init<T>, g1, bl, 0, s, n, v, (const T *)sdinv, z, cr, cd0, (const double *)lam, ratio);
     T *d = cd0, *dn = cd1;
     for (int k = 0; k < deg; ++k) {
-      hipLaunchKernelGGL((k_shat_cheb<T, 1>), gw, bl, 0, s, n, mesh->shat_width, mesh->shat_col, (const T *)Shat,
+      hipLaunchKernelGGL((k_shat_cheb<T, 1>), gw, bl, 0, s, n, mesh->shat_width, mesh->shat_col, mesh->shat_off,
+                         (const T *)Shat,
                          (const T *)Shd, (const T *)d, (const T *)sdinv, dn, z, cr, (const double *)lam, ratio, k);
       std::swap(d, dn);
     }
@@ -1512,7 +1512,7 @@ struct Nested {
     hipLaunchKernelGGL(k_scg_init<T>, dim3(nbv), dim3(KRY_BLOCK), 0, s, n, v, (const T *)sdinv, z, r, zz, prz, sflag);
     for (int i = 0; i < k; ++i) {
       hipLaunchKernelGGL(k_scg_spmv<T>, dim3(gs), dim3(VMS_BLOCK), 0, s, n, mesh->shat_width, mesh->shat_col,
-                         (const T *)Shat, (const T *)Shd, (const T *)zz, p, q, sctl, (const double *)prz, nbv, ppq,
+                         mesh->shat_off, (const T *)Shat, (const T *)Shd, (const T *)zz, p, q, sctl, (const double *)prz, nbv, ppq,
                          sflag, i);
       hipLaunchKernelGGL(k_scg_update<T>, dim3(nbv), dim3(KRY_BLOCK), 0, s, n, z, r, zz, p, (const T *)q,
                          (const T *)sdinv, (const double *)sctl, (const double *)ppq, gs, prz, sflag, i,
@@ -1528,7 +1528,8 @@ struct Nested {
     double *part = LS.ctrl + LS.off.part;
     hipLaunchKernelGGL(k_power_init<T>, g1, bl, 0, s, n, px);
     for (int it = 0; it < iters; ++it) {
-      hipLaunchKernelGGL((k_shat_cheb<T, 0>), gw, bl, 0, s, n, mesh->shat_width, mesh->shat_col, (const T *)Shat,
+      hipLaunchKernelGGL((k_shat_cheb<T, 0>), gw, bl, 0, s, n, mesh->shat_width, mesh->shat_col, mesh->shat_off,
+                         (const T *)Shat,
                          (const T *)Shd, (const T *)px, (const T *)sdinv, py, (T *)nullptr, (T *)nullptr,
                          (const double *)nullptr, 0.0, 0);
       hipLaunchKernelGGL(k_norm_part<T>, dim3(nb), bl, 0, s, (int64_t)n, (const T *)py, part, (const int *)nullptr);
@@ -1605,7 +1606,7 @@ struct Nested {
       T *z = LS.Z + (int64_t)j * LS.nvec;
       shat_prec(LS.V + (int64_t)j * LS.nvec, z);
       hipLaunchKernelGGL(k_shat_spmv<T>, dim3(spmv_grid(n)), dim3(VMS_BLOCK), 0, ctx->stream, n, mesh->shat_width,
-                         mesh->shat_col, (const T *)Shat, (const T *)Shd, (const T *)z, LS.W,
+                         mesh->shat_col, mesh->shat_off, (const T *)Shat, (const T *)Shd, (const T *)z, LS.W,
                          (const int *)(LS.iflag + IF_DONE));
       return VMS_OK;
     };
@@ -1918,12 +1919,12 @@ extern "C" int vms_shat_spmv(vms_ctx *ctx, const vms_mesh *mesh, const void *S, 
   // step 0 of the CG product kernel with a unit <r,z>: y = S^ x (its <x, y> partials go to scratch)
   if (fp32)
     hipLaunchKernelGGL(k_scg_spmv<float>, dim3(cg_spmv_blocks(n)), dim3(VMS_BLOCK), 0, ctx->stream, n,
-                       mesh->shat_width, mesh->shat_col, (const float *)S, (const float *)Sd, (const float *)x,
+                       mesh->shat_width, mesh->shat_col, mesh->shat_off, (const float *)S, (const float *)Sd, (const float *)x,
                        (float *)nullptr, (float *)y, d->scg_ctl, (const double *)&d->scg_one, 1, d->scg_part,
                        &d->scg_flag, 0);
   else
     hipLaunchKernelGGL(k_scg_spmv<double>, dim3(cg_spmv_blocks(n)), dim3(VMS_BLOCK), 0, ctx->stream, n,
-                       mesh->shat_width, mesh->shat_col, (const double *)S, (const double *)Sd, (const double *)x,
+                       mesh->shat_width, mesh->shat_col, mesh->shat_off, (const double *)S, (const double *)Sd, (const double *)x,
                        (double *)nullptr, (double *)y, d->scg_ctl, (const double *)&d->scg_one, 1, d->scg_part,
                        &d->scg_flag, 0);
   VMS_LAUNCH_CHECK(ctx);

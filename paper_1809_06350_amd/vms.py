@@ -77,7 +77,7 @@ class Matrix:
 class Problem:
     """One mesh + material on one device: pattern, contribution lists, dead load, context."""
 
-    def __init__(self, mesh, mat, device="cuda:0"):
+    def __init__(self, mesh, mat, device="cuda:0", compact_shat=True):
         self.lib = L.load()
         self.dev = torch.device(device)
         if self.dev.type != "cuda" or not torch.cuda.is_available():
@@ -87,19 +87,22 @@ class Problem:
         n, m, f = mesh.n_nodes, mesh.n_tets, int(mesh.bfaces.shape[0])
         tets = np.ascontiguousarray(mesh.tets, dtype=np.int32)
         bfaces = np.ascontiguousarray(mesh.bfaces, dtype=np.int32).reshape(-1, 3)
-        nnzb, sw, w2 = C.c_int64(), C.c_int32(), C.c_int32()
-        self._check(lib.vms_setup_sizes(n, m, tets.ctypes.data, C.byref(nnzb), C.byref(sw), C.byref(w2)),
-                    "vms_setup_sizes", ctx=False)
+        nnzb, sw, w2, span = C.c_int64(), C.c_int32(), C.c_int32(), C.c_int32()
+        self._check(lib.vms_setup_sizes(n, m, tets.ctypes.data, C.byref(nnzb), C.byref(sw), C.byref(w2),
+                                        C.byref(span)), "vms_setup_sizes", ctx=False)
         nz = nnzb.value
+        self.shat_span = span.value
+        compact = compact_shat and span.value <= 32767   # 2-byte S^ column offsets
         h = {"row_len": np.zeros(n, np.int32), "col": np.zeros(nz, np.int32), "tpos": np.zeros(nz, np.int32),
              "diag_pos": np.zeros(n, np.int32), "blk_src_ptr": np.zeros(nz + 1, np.int32),
              "blk_src": np.zeros(max(16 * m, 1), np.int32),
              "shat_col": np.zeros(n * w2.value, np.int32),
+             "shat_off": np.zeros(n * w2.value if compact else 1, np.int16),
              "nf_ptr": np.zeros(n + 1, np.int32), "nf_face": np.zeros(max(3 * f, 1), np.int32)}
-        self._check(lib.vms_setup_build(n, m, tets.ctypes.data, f, bfaces.ctypes.data if f else None,
-                                        *(h[k].ctypes.data for k in ("row_len", "col", "tpos", "diag_pos",
-                                                                     "blk_src_ptr", "blk_src", "shat_col", "nf_ptr",
-                                                                     "nf_face"))),
+        ptrs = [h[k].ctypes.data for k in ("row_len", "col", "tpos", "diag_pos", "blk_src_ptr", "blk_src",
+                                            "shat_col")]
+        ptrs += [h["shat_off"].ctypes.data if compact else None, h["nf_ptr"].ctypes.data, h["nf_face"].ctypes.data]
+        self._check(lib.vms_setup_build(n, m, tets.ctypes.data, f, bfaces.ctypes.data if f else None, *ptrs),
                     "vms_setup_build", ctx=False)
         self.slot_width = sw.value
         self.shat_width = w2.value
@@ -118,12 +121,13 @@ class Problem:
                   "fibre": up(mesh.fibre, np.float64) if mesh.fibre is not None else None}
         for k in ("col", "tpos", "diag_pos", "blk_src_ptr", "blk_src", "shat_col", "nf_ptr", "nf_face"):
             self.d[k] = up(h[k], np.int32)
+        self.d["shat_off"] = up(h["shat_off"], np.int16) if compact else None
         d = self.d
         self.cmesh = L.Mesh(n, m, f, self.slot_width, nz, _p(d["X"]), _p(d["tets"]), _p(d["bfaces"]),
                             _p(d["traction"]), _p(d["dir_mask"]), _p(d["dir_vel"]), _p(d["fibre"]),
                             _p(d["col"]), _p(d["tpos"]), _p(d["diag_pos"]), _p(d["blk_src_ptr"]),
-                            _p(d["blk_src"]), self.shat_width, _p(d["shat_col"]), _p(d["nf_ptr"]),
-                            _p(d["nf_face"]))
+                            _p(d["blk_src"]), self.shat_width, _p(d["shat_col"]), _p(d["shat_off"]),
+                            _p(d["nf_ptr"]), _p(d["nf_face"]))
         self.set_material(mat)
         self.stream = torch.cuda.current_stream(dev)
         ctx = C.c_void_p()

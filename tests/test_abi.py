@@ -37,19 +37,20 @@ def build_host(mesh):
     n, m, f = mesh.n_nodes, mesh.n_tets, mesh.bfaces.shape[0]
     tets = np.ascontiguousarray(mesh.tets, np.int32)
     bf = np.ascontiguousarray(mesh.bfaces, np.int32)
-    nnzb, sw, w2 = C.c_int64(), C.c_int32(), C.c_int32()
-    assert lib.vms_setup_sizes(n, m, tets.ctypes.data, C.byref(nnzb), C.byref(sw), C.byref(w2)) == 0
+    nnzb, sw, w2, span = C.c_int64(), C.c_int32(), C.c_int32(), C.c_int32()
+    assert lib.vms_setup_sizes(n, m, tets.ctypes.data, C.byref(nnzb), C.byref(sw), C.byref(w2), C.byref(span)) == 0
     nz = nnzb.value
     assert nz == sw.value * n and sw.value % 16 == 0
     assert w2.value % 64 == 0
-    h = {"W": sw.value, "W2": w2.value, "row_len": np.zeros(n, np.int32), "col": np.zeros(nz, np.int32), "tpos": np.zeros(nz, np.int32),
+    h = {"W": sw.value, "W2": w2.value, "span": span.value, "row_len": np.zeros(n, np.int32),
+         "col": np.zeros(nz, np.int32), "tpos": np.zeros(nz, np.int32),
          "diag_pos": np.zeros(n, np.int32), "blk_src_ptr": np.zeros(nz + 1, np.int32),
          "blk_src": np.zeros(16 * m, np.int32),
-         "shat_col": np.zeros(n * w2.value, np.int32),
+         "shat_col": np.zeros(n * w2.value, np.int32), "shat_off": np.zeros(n * w2.value, np.int16),
          "nf_ptr": np.zeros(n + 1, np.int32), "nf_face": np.zeros(max(3 * f, 1), np.int32)}
     rc = lib.vms_setup_build(n, m, tets.ctypes.data, f, bf.ctypes.data,
                              *(h[k].ctypes.data for k in ("row_len", "col", "tpos", "diag_pos", "blk_src_ptr",
-                                                          "blk_src", "shat_col", "nf_ptr", "nf_face")))
+                                                          "blk_src", "shat_col", "shat_off", "nf_ptr", "nf_face")))
     assert rc == 0
     return h
 
@@ -130,14 +131,14 @@ def test_setup_rejects_out_of_range_nodes():
     lib = L.load()
     tets = np.array([[0, 1, 2, 7]], np.int32)
     nnzb, sw, w2 = C.c_int64(), C.c_int32(), C.c_int32()
-    assert lib.vms_setup_sizes(4, 1, tets.ctypes.data, C.byref(nnzb), C.byref(sw), C.byref(w2)) == -1
+    assert lib.vms_setup_sizes(4, 1, tets.ctypes.data, C.byref(nnzb), C.byref(sw), C.byref(w2), None) == -1
 
 
 def _sizes(n, tets):
     lib = L.load()
     tets = np.ascontiguousarray(tets, np.int32).reshape(-1, 4)
     nnzb, sw, w2 = C.c_int64(), C.c_int32(), C.c_int32()
-    rc = lib.vms_setup_sizes(n, tets.shape[0], tets.ctypes.data, C.byref(nnzb), C.byref(sw), C.byref(w2))
+    rc = lib.vms_setup_sizes(n, tets.shape[0], tets.ctypes.data, C.byref(nnzb), C.byref(sw), C.byref(w2), None)
     return rc, nnzb.value, sw.value, w2.value
 
 
@@ -168,12 +169,45 @@ def test_setup_limits():
     lib = L.load()
     small = np.zeros(4, np.int32)
     nnzb, sw, w2 = C.c_int64(), C.c_int32(), C.c_int32()
-    assert lib.vms_setup_sizes(4, 134217728, small.ctypes.data, C.byref(nnzb), C.byref(sw), C.byref(w2)) == -1
-    assert lib.vms_setup_sizes(4, -1, small.ctypes.data, C.byref(nnzb), C.byref(sw), C.byref(w2)) == -1
-    assert lib.vms_setup_sizes(4, 1, small.ctypes.data, None, C.byref(sw), C.byref(w2)) == -1
+    assert lib.vms_setup_sizes(4, 134217728, small.ctypes.data, C.byref(nnzb), C.byref(sw), C.byref(w2), None) == -1
+    assert lib.vms_setup_sizes(4, -1, small.ctypes.data, C.byref(nnzb), C.byref(sw), C.byref(w2), None) == -1
+    assert lib.vms_setup_sizes(4, 1, small.ctypes.data, None, C.byref(sw), C.byref(w2), None) == -1
     hub = np.array([[0, 3 * k + 1, 3 * k + 2, 3 * k + 3] for k in range(66)], np.int32)
     rc, nnzb_, sw_, w2_ = _sizes(199, hub)
     assert rc == -1
     few = hub[:20]                     # 61 nodes: the longest distance-2 row has 60 entries
     rc, nnzb_, sw_, w2_ = _sizes(61, few)
     assert rc == 0 and sw_ == 64 and w2_ == 64 and nnzb_ == 64 * 61
+
+
+@pytest.mark.parametrize("N", [2, 4])
+def test_shat_offsets_and_span(N):
+    """shat_off is shat_col minus the row (padding slots: 0), and the span
+    reported by vms_setup_sizes is the largest |offset|."""
+    mesh = synth.cube_mesh(N)
+    h = build_host(mesh)
+    n, W2 = mesh.n_nodes, h["W2"]
+    off = h["shat_col"].reshape(n, W2) - np.arange(n)[:, None]
+    np.testing.assert_array_equal(h["shat_off"].reshape(n, W2), off)
+    assert h["span"] == np.abs(off).max()
+
+
+def test_shat_offsets_refused_when_too_far():
+    """A tet joining nodes 40000 apart: the span says so, and building the
+    2-byte offsets is refused (the caller then passes NULL); without them the
+    build succeeds."""
+    lib = L.load()
+    n = 40001
+    tets = np.array([[0, 1, 2, 40000]], np.int32)
+    nnzb, sw, w2, span = C.c_int64(), C.c_int32(), C.c_int32(), C.c_int32()
+    assert lib.vms_setup_sizes(n, 1, tets.ctypes.data, C.byref(nnzb), C.byref(sw), C.byref(w2), C.byref(span)) == 0
+    assert span.value == 40000
+    nz = nnzb.value
+    arrs = [np.zeros(n, np.int32), np.zeros(nz, np.int32), np.zeros(nz, np.int32), np.zeros(n, np.int32),
+            np.zeros(nz + 1, np.int32), np.zeros(16, np.int32), np.zeros(n * w2.value, np.int32)]
+    off = np.zeros(n * w2.value, np.int16)
+    tail = [np.zeros(n + 1, np.int32), np.zeros(1, np.int32)]
+    args = [a.ctypes.data for a in arrs]
+    assert lib.vms_setup_build(n, 1, tets.ctypes.data, 0, None, *args, off.ctypes.data,
+                               *[a.ctypes.data for a in tail]) == -1
+    assert lib.vms_setup_build(n, 1, tets.ctypes.data, 0, None, *args, None, *[a.ctypes.data for a in tail]) == 0

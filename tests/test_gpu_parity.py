@@ -209,6 +209,30 @@ def test_shat_product_matches_oracle(problems, name, fp32):
     assert np.abs(y - ref).max() <= (1e-5 if fp32 else 1e-11) * scale
 
 
+@pytest.mark.parametrize("method", [V.SHAT_CG, V.SHAT_CHEBYSHEV])
+def test_compact_shat_offsets_give_identical_results(method):
+    """The S^ products read 2-byte column offsets when the mesh has them and
+    4-byte columns otherwise; both address the same entries in the same
+    order, so products and solves agree bit for bit."""
+    mesh, mat, ti = case("cube-nu0499")
+    pa = V.Problem(mesh, mat, "cuda:0")
+    pb = V.Problem(mesh, mat, "cuda:0", compact_shat=False)
+    assert pa.d["shat_off"] is not None and pb.d["shat_off"] is None
+    sn, it = states(mesh, 63)
+    out = []
+    for prob in (pa, pb):
+        st = gpu_state(prob, sn, it)
+        K, R, corr = prob.assemble(st, gpu_ti(ti, 0.0), V.ASM_RESIDUAL | V.ASM_TANGENT | V.ASM_RKCORR)
+        rhs = prob.prepare(K, R, corr)
+        S, Sd, _ = prob.schur_hat(K)
+        xs = torch.linspace(-1.0, 1.0, mesh.n_nodes, dtype=torch.float64, device="cuda:0")
+        y = prob.shat_spmv(S, Sd, xs)
+        x, stats = prob.solve_scaled(K, rhs, V.solver_opts(rtol=1e-8, shat_method=method, shat_degree=8))
+        out.append((y, x, stats["it_S"]))
+    assert torch.equal(out[0][0], out[1][0])
+    assert torch.equal(out[0][1], out[1][1]) and out[0][2] == out[1][2]
+
+
 def _with_mirrors(prob, K):
     K2 = prob.new_matrix(mirror32=True)
     for a, b in ((K2.A, K.A), (K2.B, K.B), (K2.C, K.C), (K2.D, K.D)):
