@@ -3,30 +3,34 @@
 //
 // Levels (section 4.4):
 //   outer         FGMRES on the scaled K* = [[A, B], [C, D]], FP64, right-
-//                 preconditioned by the Schur complement reduction (Alg. 1);
-//   intermediate  GMRES on A (3x3 block-Jacobi right preconditioner, the
-//                 stand-in for the paper's AMG) and GMRES on
-//                 S = D - C A^-1 B (right preconditioner diag(S^),
-//                 S^ = D - C diag(A)^-1 B);
-//   inner         GMRES on A inside the matrix-free Schur product (Alg. 2).
-// Every level is right-preconditioned with x0 = 0 and stops on the
-// least-squares residual |g_{j+1}| <= max(rtol ||b||, atol) or at maxit.
+//                 preconditioned by the Schur complement reduction (Alg. 1;
+//                 or its partial factorizations, or SIMPLE of section 4.3);
+//   intermediate  GMRES or CG on A (3x3 block-Jacobi right preconditioner,
+//                 the stand-in for the paper's AMG) and GMRES on
+//                 S = D - C A^-1 B (right preconditioner from
+//                 S^ = D - C diag(A)^-1 B: diag(S^)^-1, a Chebyshev
+//                 polynomial, or a fixed number of CG steps on S^);
+//   inner         GMRES or CG on A inside the matrix-free Schur product
+//                 (Alg. 2); CG is the inner solver the conclusions suggest.
+// Every level starts from x0 = 0 and stops on ||r|| <= max(rtol ||b||, atol)
+// (GMRES: its least-squares residual) or at maxit.
 //
-// Device-resident Arnoldi: the Hessenberg matrix, Givens rotations and the
-// convergence flag live in a per-level control block in device memory; the
-// kernels of an iteration read the `done` flag and return immediately once
-// the level has converged, so the host can enqueue several A-level
-// iterations before it reads the flag back (one host sync per batch).
-// Orthogonalisation is classical Gram-Schmidt -- one multi-dot and one
-// multi-update pass per iteration (CGS1), a second pass always (CGS2) or when
-// the first removed more than half of the vector ("if needed") -- or modified
-// Gram-Schmidt (one dot/axpy launch pair per basis vector).  The outer FGMRES
-// always uses CGS2 (or MGS).
+// Device-resident Krylov: the Hessenberg matrix, Givens rotations, CG
+// scalars and the convergence flags live in a per-level control block in
+// device memory; the kernels of an iteration read the `done` flag and return
+// immediately once the level has converged, so the host can enqueue several
+// A-level iterations before it reads the flags back (posted by the last
+// kernel of a batch into pinned host memory).  GMRES orthogonalisation is
+// classical Gram-Schmidt -- one multi-dot and one multi-update pass per
+// iteration (CGS1), a second pass always (CGS2) or when the first removed
+// more than half of the vector ("if needed") -- or modified Gram-Schmidt
+// (one dot/axpy launch pair per basis vector).  The outer FGMRES always uses
+// CGS2 (or MGS).
 //
 // Mixed form: the intermediate and inner levels run on FP32 copies of the
 // scaled blocks with FP32 Krylov vectors (FP64 accumulation of every sum and
-// FP64 Hessenberg/Givens); the outer FGMRES, its vectors and the Newton
-// update stay FP64.
+// FP64 Hessenberg/Givens/CG scalars); the outer FGMRES, its vectors and the
+// Newton update stay FP64.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -49,7 +53,7 @@ inline int kry_blocks(int64_t nvec) {
   return (int)std::min<int64_t>(std::max<int64_t>(nb, 1), KRY_MAX_BLOCKS);
 }
 enum { KS_OK = 0, KS_MAXIT = 1, KS_NAN = 2, KS_BREAKDOWN = 3 };
-enum { IF_DONE = 0, IF_ITS = 1, IF_STATUS = 2, IF_COUNTER = 3 };
+enum { IF_DONE = 0, IF_ITS = 1, IF_STATUS = 2 };
 
 struct KOff {
   int m;
