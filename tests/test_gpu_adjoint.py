@@ -56,8 +56,8 @@ def _gpu_state(prob, sn, s1):
     return st
 
 
-@pytest.mark.parametrize("name", ["cube", "tube"])
-def test_transposed_solve_matches_oracle(name):
+@pytest.mark.parametrize("name,a_krylov", [("cube", 0), ("tube", 0), ("cube", 2)])
+def test_transposed_solve_matches_oracle(name, a_krylov):
     mesh, mat, ti, pmask, sel = _case(name)
     prob = _prob(mesh, mat)
     sn, s1 = _consistent_states(mesh, ti, 5)
@@ -74,7 +74,7 @@ def test_transposed_solve_matches_oracle(name):
     rhs = np.random.default_rng(2).standard_normal(4 * mesh.n_nodes)
     rhs[disc.dof_dir] = 0.0
     Kt = prob.new_matrix()
-    opts = V.solver_opts(rtol=1e-11, rtol_A=1e-12, rtol_S=1e-12, rtol_I=1e-13)
+    opts = V.solver_opts(rtol=1e-11, rtol_A=1e-12, rtol_S=1e-12, rtol_I=1e-13, a_krylov=a_krylov, cg_symmetrise=0)
     lam, stats = prob.solve_transpose(K, Kt, torch.from_numpy(rhs.reshape(-1, 4)).cuda(), opts)
     lg = lam.cpu().numpy().ravel()
     print(f"[transpose] {name} {stats}", flush=True)

@@ -447,12 +447,16 @@ def _run_steps(prob, mesh, ti, n_steps, nopts, sopts):
     return st, hist
 
 
-@pytest.mark.parametrize("N,nu,n_steps", [(4, None, 1), (4, 0.45, 3), (3, 0.5, 2)])
-def test_time_steps_match_oracle(N, nu, n_steps):
+@pytest.mark.parametrize("N,nu,n_steps,variant", [(4, None, 1, "gmres"), (4, 0.45, 3, "gmres"), (3, 0.5, 2, "gmres"),
+                                                   (4, 0.45, 3, "cg"), (4, 0.45, 3, "simple")])
+def test_time_steps_match_oracle(N, nu, n_steps, variant):
+    """Whole time steps against the oracle's: GMRES A-levels; CG A-levels
+    (on A itself); and the SIMPLE preconditioner."""
     mesh, mat, ti = synth.cube_case(N, nu=nu, n_steps=n_steps)
     prob = V.Problem(mesh, mat, "cuda:0")
     nopts = V.newton_opts(tol_R=1e-10, l_max=10)
-    sopts = V.solver_opts(rtol=1e-10, rtol_A=1e-10, rtol_S=1e-10, rtol_I=1e-12)
+    extra = {"gmres": {}, "cg": dict(a_krylov=V.AK_CG, cg_symmetrise=0), "simple": dict(precond=V.PC_SIMPLE)}[variant]
+    sopts = V.solver_opts(rtol=1e-10, rtol_A=1e-10, rtol_S=1e-10, rtol_I=1e-12, **extra)
     st, hist = _run_steps(prob, mesh, ti, n_steps, nopts, sopts)
     disc = AS.Discretization(mesh, mat)
     so = NW.rest_state(mesh)
@@ -465,11 +469,15 @@ def test_time_steps_match_oracle(N, nu, n_steps):
         assert rel_err(st[k].cpu().numpy(), so[k]) < 1e-7, k
 
 
-def test_mixed_precision_time_step_error():
+@pytest.mark.parametrize("a_krylov", [V.AK_GMRES, V.AK_CG])
+def test_mixed_precision_time_step_error(a_krylov):
+    """The mixed form (FP32 intermediate and inner levels; GMRES or, as the
+    bench runs it, CG on A itself) reaches the oracle's FP64 time steps."""
     mesh, mat, ti = synth.cube_case(4, nu=0.499, n_steps=2)
     prob = V.Problem(mesh, mat, "cuda:0")
     nopts = V.newton_opts(tol_R=1e-8, l_max=10)
-    sopts = V.solver_opts(rtol=1e-8, rtol_A=1e-5, rtol_S=1e-5, rtol_I=1e-3, precision=V.MIXED)
+    sopts = V.solver_opts(rtol=1e-8, rtol_A=1e-5, rtol_S=1e-5, rtol_I=1e-3, precision=V.MIXED, a_krylov=a_krylov,
+                          cg_symmetrise=0)
     st, hist = _run_steps(prob, mesh, ti, 2, nopts, sopts)
     disc = AS.Discretization(mesh, mat)
     so = NW.rest_state(mesh)
