@@ -41,9 +41,9 @@ def spmv_A_bytes(n, nnzb, elem):
 
 
 def shat_bytes(n, nnz, elem, idx=4):
-    """Algorithmic bytes of one S^ product of the Schur preconditioner's CG
-    steps (its first step, as timed): the real off-diagonal entries (value +
-    column index or 2-byte offset), the diagonal, x once (gathers cached) and y."""
+    """Algorithmic bytes of one S^ product (the product of the Schur
+    preconditioner's CG steps): the real off-diagonal entries (value + column
+    index or 2-byte offset), the diagonal, x once (gathers cached) and y."""
     return (elem + idx) * nnz + 3 * elem * n
 
 
@@ -54,8 +54,7 @@ def shat_idx_bytes(prob):
 # kernel -> (source file, first and end markers of the kernel's source text (None: whole file), summary)
 PMC_FILES = {
     "spmv_A": ("linalg.h", None, None, "spmv_A_cube64_pmc.md"),
-    "shat": ("solver.hip", "// Off-diagonal part of row ro of S^ times z",
-             "template <typename T>\n__global__ void __launch_bounds__(KRY_BLOCK)\nk_scg_update(",
+    "shat": ("solver.hip", "// Off-diagonal part of row ro of S^ times z", "// ---- pipelined CG steps on S^",
              "shat_spmv_cube64_pmc.md"),
 }
 
@@ -337,14 +336,15 @@ def main():
     bys64 = shat_bytes(n, nzs, 8, shat_idx_bytes(prob))
     steps_stats = r["per_step"]
     launches_A = sum(p["it_A_total"] + p["it_I_total"] for p in steps_stats) / args.steps
-    launches_S = (sum(p["it_S_total"] for p in steps_stats) / args.steps * so.shat_degree
+    # the CG steps on S^: one product to start and one per step
+    launches_S = (sum(p["it_S_total"] for p in steps_stats) / args.steps * (so.shat_degree + 1)
                   if so.shat_method == V.SHAT_CG else 0.0)
     kern = {
         "k_spmv_A<double,double>": {"achieved": by64 / t64 / 1e9, "us_per_launch": t64 * 1e6,
                                     "bytes_per_launch": by64, "launches_per_step": launches_A,
                                     "est_ms_per_step": launches_A * t64 * 1e3,
                                     "traffic": pmc_traffic("spmv_A", "traffic_bytes_fp64") if N == 64 else None},
-        "k_scg_spmv<double>": {"achieved": bys64 / ts64 / 1e9, "us_per_launch": ts64 * 1e6,
+        "k_shat_spmv<double>": {"achieved": bys64 / ts64 / 1e9, "us_per_launch": ts64 * 1e6,
                                "bytes_per_launch": bys64, "launches_per_step": launches_S,
                                "est_ms_per_step": launches_S * ts64 * 1e3,
                                "traffic": pmc_traffic("shat", "traffic_bytes_fp64") if N == 64 else None},

@@ -42,10 +42,7 @@ extern "C" int vms_ctx_create(vms_ctx **out, int device, void *stream) {
     return VMS_ERR_HIP;
   }
   for (int q = 0; q < 64; ++q) c->h_post[q] = 0;
-  const double one = 1.0;
-  if (hipMemset(c->dstat, 0, sizeof(vms_dev_status)) != hipSuccess ||
-      hipMemcpy(&c->dstat->scg_one, &one, sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
-      hipDeviceSynchronize() != hipSuccess) {
+  if (hipMemset(c->dstat, 0, sizeof(vms_dev_status)) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
     (void)hipHostFree(c->h_i);
     (void)hipHostFree(c->h_d);
     (void)hipHostFree((void *)c->h_post);

@@ -691,9 +691,8 @@ k_cg_init(int64_t nn, const T *__restrict__ b, T *x, T *r, T *z, const T *__rest
 // (16 lanes per row, 16 rows per workgroup); a workgroup takes a contiguous
 // range of row groups (XCD-aware order) when the grid is capped.
 #ifndef CG_SPMV_BLOCKS
-#define CG_SPMV_BLOCKS VMS_SCG_MAX_BLOCKS
+#define CG_SPMV_BLOCKS 2048
 #endif
-static_assert(CG_SPMV_BLOCKS <= VMS_SCG_MAX_BLOCKS, "CG product grid larger than the partial buffers");
 inline int cg_spmv_blocks(int n) {
   const int ng = (n + SPMV_ROWS_PER_BLOCK - 1) / SPMV_ROWS_PER_BLOCK;
   return std::max(1, std::min(ng, CG_SPMV_BLOCKS));
@@ -825,15 +824,17 @@ k_cg_update(int64_t nn, T *x, T *r, T *z, const T *__restrict__ p, const T *__re
 }
 
 // ---- CG steps on S^ as the Schur-level preconditioner ---------------------------
-// A fixed number k of Jacobi-preconditioned CG steps on S^ z = v from z = 0:
-// for each right-hand side the Krylov-optimal polynomial of degree k, where
-// the Chebyshev option applies one fixed polynomial.  The result depends
-// nonlinearly on v, which the flexible Schur-level GMRES (it keeps the Z
-// vectors) tolerates.  Same kernel pattern as the CG A-levels: the product
-// kernel forms w = S^ z and the rows' own p = z + beta p, q = w + beta q;
-// the update kernel advances x, r, z.  A zero or non-finite <r,z> or
-// <p,S^p> ends the steps early (x keeps the last iterate); the host never
-// waits on them.
+// A fixed number k of diag(S^)-preconditioned CG steps on S^ z = v from
+// z = 0: for each right-hand side the Krylov-optimal polynomial of degree k,
+// where the Chebyshev option applies one fixed polynomial.  The result
+// depends nonlinearly on v, which the flexible Schur-level GMRES (it keeps
+// the Z vectors) tolerates.  The steps use the pipelined recurrences of
+// Ghysels and Vanroose (2014), equivalent to CG in exact arithmetic: the
+// product n = S^ m is a plain kernel with no reduction, and one vector kernel
+// per step reduces the previous step's <r,u> and <w,u>, updates every vector
+// and forms the next step's partials.  A zero or non-finite <r,u> or a
+// non-positive curvature ends the steps early (x keeps the last iterate); the
+// host never waits on them.
 
 // sum over a workgroup of any size (fixed order), valid in thread 0
 __device__ __forceinline__ double blk_sum_any(double v, double *sm) {
@@ -845,24 +846,6 @@ __device__ __forceinline__ double blk_sum_any(double v, double *sm) {
   if (threadIdx.x == 0)
     for (int q = 0; q < nw; ++q) r += sm[q];
   return r;
-}
-
-template <typename T>
-__global__ void __launch_bounds__(KRY_BLOCK)
-k_scg_init(int n, const T *__restrict__ v, const T *__restrict__ dinv, T *x, T *r, T *z, double *prz, int *flag) {
-  __shared__ double sm[16];
-  if (blockIdx.x == 0 && threadIdx.x == 0) *flag = 0;
-  double rz = 0.0;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-    const double vi = ld(v, i);
-    const T zi = (T)(ld(dinv, i) * vi);
-    r[i] = (T)vi;
-    z[i] = zi;
-    x[i] = (T)0;
-    rz += vi * (double)zi;
-  }
-  rz = blk_sum_any(rz, sm);
-  if (threadIdx.x == 0) prz[blockIdx.x] = rz;
 }
 
 // Off-diagonal part of row ro of S^ times z: lane l of the row's 16 takes
@@ -900,85 +883,113 @@ __device__ __forceinline__ double shat_row_dot(int W2, const int32_t *__restrict
             : shat_row_dot_t<T, false>(W2, sc, so, S, z, r0, ro, lane);
 }
 
-// CG step i on S^, first half: every workgroup sums the <r,z> partials
-// (zero or non-finite: the steps end), beta = rz_i / rz_{i-1}; then w = S^ z
-// and the rows' own q = w + beta q, p = z + beta p (step 0: q = w, and p_0 = z
-// is copied by the update kernel), with one partial of <p,q> per workgroup.
+// y = S^ x (off-diagonal distance-2 slots plus the diagonal), skipped when *done is set
 template <typename T>
 __global__ void __launch_bounds__(VMS_BLOCK)
-k_scg_spmv(int n, int W2, const int32_t *__restrict__ sc, const int16_t *__restrict__ so, const T *__restrict__ S,
-           const T *__restrict__ Sd, const T *__restrict__ z, T *p, T *q, double *ctl, const double *prz, int nrz,
-           double *ppq, int *flag, int i) {
-  __shared__ double sm[16];
-  __shared__ int done0;
-  if (threadIdx.x == 0) done0 = *flag;
-  __syncthreads();
-  if (done0) return;
-  const double rz = cg_sum_partials(prz, nrz, sm);
-  if (!(rz > 0.0) || !isfinite(rz)) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) *flag = 1;
-    return;
-  }
-  const bool first = (i == 0);
-  const double beta = first ? 0.0 : rz / ctl[(i - 1) & 1];
-  if (blockIdx.x == 0 && threadIdx.x == 0) ctl[i & 1] = rz;
-  const int lane = threadIdx.x & 15, sub = threadIdx.x >> 4;
-  const int ng = (n + SPMV_ROWS_PER_BLOCK - 1) / SPMV_ROWS_PER_BLOCK;
-  const int vb = xcd_block(blockIdx.x, gridDim.x);
-  const int g0 = (int)((int64_t)vb * ng / gridDim.x), g1 = (int)((int64_t)(vb + 1) * ng / gridDim.x);
-  double pq = 0.0;
-  for (int g = g0; g < g1; ++g) {
-    const int row = g * SPMV_ROWS_PER_BLOCK + sub;
-    const bool act = row < n;
-    const int ro = act ? row : 0;
-    // the row's own values ahead of the product
-    const double zi = ld(z, ro), sii = ld(Sd, ro);
-    const double pi = first ? 0.0 : ld(p, ro), qi = first ? 0.0 : ld(q, ro);
-    const double a = reduce16(shat_row_dot(W2, sc, so, S, z, ro, lane)) + sii * zi;
-    if (act && lane == 0) {
-      const T pn = first ? (T)zi : (T)(zi + beta * pi);
-      const T qn = first ? (T)a : (T)(a + beta * qi);
-      if (!first) p[row] = pn;
-      q[row] = qn;
-      pq += (double)pn * (double)qn;
-    }
-  }
-  pq = block_sum(pq, sm);
-  if (threadIdx.x == 0) ppq[blockIdx.x] = pq;
+k_shat_spmv(int n, int W2, const int32_t *__restrict__ sc, const int16_t *__restrict__ so, const T *__restrict__ S,
+            const T *__restrict__ Sd, const T *__restrict__ x, T *y, const int *done) {
+  if (done && *done) return;
+  const int lane = threadIdx.x & 15;
+  const int row = xcd_block(blockIdx.x, gridDim.x) * SPMV_ROWS_PER_BLOCK + (threadIdx.x >> 4);
+  const bool act = row < n;
+  const int ro = act ? row : 0;
+  const double xi = ld(x, ro), sii = ld(Sd, ro);
+  const double a = reduce16(shat_row_dot(W2, sc, so, S, x, ro, lane)) + sii * xi;
+  if (act && lane == 0) y[row] = (T)a;
 }
 
+// ---- pipelined CG steps on S^ --------------------------------------------------
+// Work vectors of one application, each [n]: r, u, w, m, nv, z, q, s, p.
+template <typename T>
+struct PcgVec {
+  T *r, *u, *w, *m, *nv, *z, *q, *s, *p;
+};
+
+// start: x = 0, r = v, u = diag(S^)^-1 v; resets the flag
+template <typename T>
+__global__ void k_pcg_init(int n, const T *__restrict__ v, const T *__restrict__ dinv, T *x, PcgVec<T> V, int *flag) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (blockIdx.x == 0 && threadIdx.x == 0) *flag = 0;
+  if (i >= n) return;
+  const double vi = ld(v, i);
+  x[i] = (T)0;
+  V.r[i] = (T)vi;
+  V.u[i] = (T)(ld(dinv, i) * vi);
+}
+
+// after w = S^ u: partials of gamma = <r,u> and delta = <w,u>, and m = diag(S^)^-1 w
 template <typename T>
 __global__ void __launch_bounds__(KRY_BLOCK)
-k_scg_update(int n, T *x, T *r, T *z, T *p, const T *__restrict__ q, const T *__restrict__ dinv,
-             const double *ctl, const double *ppq, int npq, double *prz, int *flag, int i, int last) {
-  __shared__ double sm[16];
+k_pcg_start(int n, const T *__restrict__ dinv, PcgVec<T> V, double *pg, double *pd) {
+  __shared__ double sm[2][16];
+  double g = 0.0, d = 0.0;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const double ui = ld(V.u, i), wi = ld(V.w, i);
+    g += ld(V.r, i) * ui;
+    d += wi * ui;
+    V.m[i] = (T)(ld(dinv, i) * wi);
+  }
+  cg_block_sums2(g, d, pg + blockIdx.x, pd + blockIdx.x, sm);
+}
+
+// step i (nv = S^ m already formed): gamma_i, delta_i from the partials of
+// buffer i & 1; beta_i = gamma_i / gamma_{i-1}, alpha_i = gamma_i /
+// (delta_i - beta_i gamma_i / alpha_{i-1}) (step 0: beta = 0, alpha =
+// gamma / delta); z = nv + beta z, q = m + beta q, s = w + beta s,
+// p = u + beta p, x += alpha p; unless last: r -= alpha s, u -= alpha q,
+// w -= alpha z, m = diag(S^)^-1 w and the partials of the next gamma, delta
+// into buffer (i + 1) & 1.  ctl: gamma and alpha of the last two steps.
+template <typename T>
+__global__ void __launch_bounds__(KRY_BLOCK)
+k_pcg_step(int n, int i, int last, T *x, PcgVec<T> V, const T *__restrict__ dinv, double *ctl, double *pg0,
+           double *pd0, double *pg1, double *pd1, int nbp, int *flag) {
+  __shared__ double sm[2][16];
   __shared__ int done0;
   if (threadIdx.x == 0) done0 = *flag;
   __syncthreads();
   if (done0) return;
-  const double pq = cg_sum_partials(ppq, npq, sm);
-  const double alpha = ctl[i & 1] / pq;
-  if (!(pq > 0.0) || !isfinite(alpha)) {
+  const double *pg = (i & 1) ? pg1 : pg0, *pd = (i & 1) ? pd1 : pd0;
+  const double g = cg_sum_partials(pg, nbp, sm[0]);
+  const double d = cg_sum_partials(pd, nbp, sm[1]);
+  double beta = 0.0, den = d;
+  if (i > 0) {
+    beta = g / ctl[(i - 1) & 1];
+    den = d - beta * g / ctl[2 + ((i - 1) & 1)];
+  }
+  const double alpha = g / den;
+  if (!(g > 0.0) || !(den > 0.0) || !isfinite(alpha) || !isfinite(beta)) {
     if (blockIdx.x == 0 && threadIdx.x == 0) *flag = 1;
     return;
   }
-  double rz = 0.0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    ctl[i & 1] = g;
+    ctl[2 + (i & 1)] = alpha;
+  }
+  const bool first = (i == 0);
+  double gn = 0.0, dn = 0.0;
   for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) {
-    const T pk = (i == 0) ? z[k] : p[k];   // p_0 = z_0, kept for the next step
-    if (i == 0 && !last) p[k] = pk;
-    x[k] = (T)(ld(x, k) + alpha * (double)pk);
+    const double zk = ld(V.nv, k) + (first ? 0.0 : beta * ld(V.z, k));
+    const double qk = ld(V.m, k) + (first ? 0.0 : beta * ld(V.q, k));
+    const double sk = ld(V.w, k) + (first ? 0.0 : beta * ld(V.s, k));
+    const double pk = ld(V.u, k) + (first ? 0.0 : beta * ld(V.p, k));
+    x[k] = (T)(ld(x, k) + alpha * pk);
     if (!last) {
-      const T rk = (T)(ld(r, k) - alpha * ld(q, k));
-      const T zk = (T)(ld(dinv, k) * (double)rk);
-      r[k] = rk;
-      z[k] = zk;
-      rz += (double)rk * (double)zk;
+      V.z[k] = (T)zk;
+      V.q[k] = (T)qk;
+      V.s[k] = (T)sk;
+      V.p[k] = (T)pk;
+      const T rk = (T)(ld(V.r, k) - alpha * sk);
+      const T uk = (T)(ld(V.u, k) - alpha * qk);
+      const T wk = (T)(ld(V.w, k) - alpha * zk);
+      V.r[k] = rk;
+      V.u[k] = uk;
+      V.w[k] = wk;
+      V.m[k] = (T)(ld(dinv, k) * (double)wk);
+      gn += (double)rk * (double)uk;
+      dn += (double)wk * (double)uk;
     }
   }
-  if (!last) {
-    rz = blk_sum_any(rz, sm);
-    if (threadIdx.x == 0) prz[blockIdx.x] = rz;
-  }
+  if (!last) cg_block_sums2(gn, dn, ((i + 1) & 1 ? pg1 : pg0) + blockIdx.x, ((i + 1) & 1 ? pd1 : pd0) + blockIdx.x, sm);
 }
 
 // ---- S^ = D - C diag(A)^-1 B, assembled on the distance-2 pattern ----------
@@ -1170,21 +1181,6 @@ __global__ void k_merge(int n, const T *v, const T *p, double *full) {
   full[o + 2] = (double)v[3 * (int64_t)i + 2];
   full[o + 3] = (double)p[i];
 }
-// y = S^ x (off-diagonal distance-2 slots plus the diagonal), skipped when the level is done
-template <typename T>
-__global__ void __launch_bounds__(VMS_BLOCK)
-k_shat_spmv(int n, int W2, const int32_t *__restrict__ sc, const int16_t *__restrict__ so, const T *__restrict__ S,
-            const T *__restrict__ Sd, const T *__restrict__ x, T *y, const int *done) {
-  if (done && *done) return;
-  const int lane = threadIdx.x & 15;
-  const int row = xcd_block(blockIdx.x, gridDim.x) * SPMV_ROWS_PER_BLOCK + (threadIdx.x >> 4);
-  const bool act = row < n;
-  const int ro = act ? row : 0;
-  const double xi = ld(x, ro), sii = ld(Sd, ro);
-  const double a = reduce16(shat_row_dot(W2, sc, so, S, x, ro, lane)) + sii * xi;
-  if (act && lane == 0) y[row] = (T)a;
-}
-
 // z = d .* v
 template <typename T>
 __global__ void k_diag_scale(int n, const T *d, const T *v, T *z) {
@@ -1451,8 +1447,9 @@ struct Nested {
   T *Shat, *Shd, *cr, *cd0, *cd1, *px, *py;  // S^ (off-diagonal, diagonal); Chebyshev / power-iteration vectors
   T *As = nullptr;                            // (A + A^T)/2 for the CG levels (when symmetrised)
   double *cgpart = nullptr;                   // partials of <p, A p> of the CG product kernel
-  double *sctl = nullptr;                     // CG steps on S^: rz history [2], <p,q> partials, <r,z> partials
+  double *sctl = nullptr;                     // CG steps on S^: gamma, alpha of two steps [4], partials [4][...]
   int *sflag = nullptr;
+  PcgVec<T> pv{};                             // their work vectors
   T *dAinv = nullptr;                         // SIMPLE: diag(A)^-1
   double *lam = nullptr;                      // device: lmax estimate of diag(S^)^-1 S^
   vms_solve_stats *stats;
@@ -1480,8 +1477,10 @@ struct Nested {
     py = cv.take<T>(nn);
     if (o_->precond == VMS_PC_SIMPLE) dAinv = cv.take<T>(3 * nn);
     if (o_->shat_method == VMS_SHAT_CG && o_->shat_degree > 0) {
-      sctl = cv.take<double>(2 + CG_SPMV_BLOCKS + VMS_MAX_RED_BLOCKS);
+      sctl = cv.take<double>(4 + 4 * VMS_MAX_RED_BLOCKS);
       sflag = cv.take<int>(1);
+      T **vs[9] = {&pv.r, &pv.u, &pv.w, &pv.m, &pv.nv, &pv.z, &pv.q, &pv.s, &pv.p};
+      for (T **v : vs) *v = cv.take<T>(nn);
     }
     if (o_->a_krylov != VMS_AK_GMRES) {
       cgpart = cv.take<double>(cg_spmv_blocks(m_->n_nodes));
@@ -1505,22 +1504,25 @@ struct Nested {
     }
   }
 
-  // z = k Jacobi-preconditioned CG steps on S^ z = v (k = shat_degree)
+  // z = k diag(S^)-preconditioned CG steps on S^ z = v (k = shat_degree), pipelined
   void scg_apply(const T *v, T *z) {
     hipStream_t s = ctx->stream;
     const int k = o->shat_degree;
-    const int gs = cg_spmv_blocks(n);
     const int nbv = kry_blocks(n);
-    double *ppq = sctl + 2, *prz = sctl + 2 + CG_SPMV_BLOCKS;
-    T *r = cr, *zz = cd0, *p = cd1, *q = px;
-    hipLaunchKernelGGL(k_scg_init<T>, dim3(nbv), dim3(KRY_BLOCK), 0, s, n, v, (const T *)sdinv, z, r, zz, prz, sflag);
+    double *pg0 = sctl + 4, *pd0 = pg0 + VMS_MAX_RED_BLOCKS, *pg1 = pd0 + VMS_MAX_RED_BLOCKS,
+           *pd1 = pg1 + VMS_MAX_RED_BLOCKS;
+    const dim3 gp(spmv_grid(n)), bl(VMS_BLOCK), gv(nbv), bk(KRY_BLOCK);
+    auto product = [&](const T *xin, T *yout) {
+      hipLaunchKernelGGL(k_shat_spmv<T>, gp, bl, 0, s, n, mesh->shat_width, mesh->shat_col, mesh->shat_off,
+                         (const T *)Shat, (const T *)Shd, xin, yout, (const int *)sflag);
+    };
+    hipLaunchKernelGGL(k_pcg_init<T>, dim3(grid1(n)), bl, 0, s, n, v, (const T *)sdinv, z, pv, sflag);
+    product(pv.u, pv.w);
+    hipLaunchKernelGGL(k_pcg_start<T>, gv, bk, 0, s, n, (const T *)sdinv, pv, pg0, pd0);
     for (int i = 0; i < k; ++i) {
-      hipLaunchKernelGGL(k_scg_spmv<T>, dim3(gs), dim3(VMS_BLOCK), 0, s, n, mesh->shat_width, mesh->shat_col,
-                         mesh->shat_off, (const T *)Shat, (const T *)Shd, (const T *)zz, p, q, sctl, (const double *)prz, nbv, ppq,
-                         sflag, i);
-      hipLaunchKernelGGL(k_scg_update<T>, dim3(nbv), dim3(KRY_BLOCK), 0, s, n, z, r, zz, p, (const T *)q,
-                         (const T *)sdinv, (const double *)sctl, (const double *)ppq, gs, prz, sflag, i,
-                         (int)(i == k - 1));
+      product(pv.m, pv.nv);
+      hipLaunchKernelGGL(k_pcg_step<T>, gv, bk, 0, s, n, i, (int)(i == k - 1), z, pv, (const T *)sdinv, sctl, pg0,
+                         pd0, pg1, pd1, nbv, sflag);
     }
   }
 
@@ -1919,18 +1921,15 @@ extern "C" int vms_shat_spmv(vms_ctx *ctx, const vms_mesh *mesh, const void *S, 
   if (!S || !Sd || !x || !y) return vms_set_error(ctx, VMS_ERR_ARG, "vms_shat_spmv: missing argument");
   if (x == y) return vms_set_error(ctx, VMS_ERR_ARG, "vms_shat_spmv: x and y must not alias");
   const int n = mesh->n_nodes;
-  vms_dev_status *d = ctx->dstat;
-  // step 0 of the CG product kernel with a unit <r,z>: y = S^ x (its <x, y> partials go to scratch)
+  const dim3 gp(spmv_grid(n)), bl(VMS_BLOCK);
   if (fp32)
-    hipLaunchKernelGGL(k_scg_spmv<float>, dim3(cg_spmv_blocks(n)), dim3(VMS_BLOCK), 0, ctx->stream, n,
-                       mesh->shat_width, mesh->shat_col, mesh->shat_off, (const float *)S, (const float *)Sd, (const float *)x,
-                       (float *)nullptr, (float *)y, d->scg_ctl, (const double *)&d->scg_one, 1, d->scg_part,
-                       &d->scg_flag, 0);
+    hipLaunchKernelGGL(k_shat_spmv<float>, gp, bl, 0, ctx->stream, n, mesh->shat_width, mesh->shat_col,
+                       mesh->shat_off, (const float *)S, (const float *)Sd, (const float *)x, (float *)y,
+                       (const int *)nullptr);
   else
-    hipLaunchKernelGGL(k_scg_spmv<double>, dim3(cg_spmv_blocks(n)), dim3(VMS_BLOCK), 0, ctx->stream, n,
-                       mesh->shat_width, mesh->shat_col, mesh->shat_off, (const double *)S, (const double *)Sd, (const double *)x,
-                       (double *)nullptr, (double *)y, d->scg_ctl, (const double *)&d->scg_one, 1, d->scg_part,
-                       &d->scg_flag, 0);
+    hipLaunchKernelGGL(k_shat_spmv<double>, gp, bl, 0, ctx->stream, n, mesh->shat_width, mesh->shat_col,
+                       mesh->shat_off, (const double *)S, (const double *)Sd, (const double *)x, (double *)y,
+                       (const int *)nullptr);
   VMS_LAUNCH_CHECK(ctx);
   return VMS_OK;
 }

@@ -14,7 +14,6 @@
 
 #define VMS_BLOCK 256
 #define VMS_MAX_RED_BLOCKS 1024
-#define VMS_SCG_MAX_BLOCKS 2048   // workgroups of the CG product kernels (one partial each)
 // internal assembly mode: cotangents lam^T dR/d(staged fields), [n][11] = (u 3, p, v 3, v-dot 3, p-dot)
 #define VMS_ASM_VJP 8u
 // internal assembly mode: per-element lam_e^T dR_e/dtheta, [m][5] for (mu, kappa, k1, k2, phi)
@@ -28,13 +27,6 @@ struct vms_dev_status {
   int pad2;
   double norm2;        // result of the residual-norm reduction
   double part[VMS_MAX_RED_BLOCKS];
-  // stand-alone S^ product (vms_shat_spmv): the CG product kernel's flag, a
-  // unit <r,z> partial (set at create), its rz record and <p,q> partials
-  int scg_flag;
-  int pad3;
-  double scg_one;
-  double scg_ctl[2];
-  double scg_part[VMS_SCG_MAX_BLOCKS];
 };
 
 #define VMS_MAX_TIMED 65536   // timed launches per kind between two reads
