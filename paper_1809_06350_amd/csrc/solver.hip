@@ -899,6 +899,15 @@ k_shat_spmv(int n, int W2, const int32_t *__restrict__ sc, const int16_t *__rest
 }
 
 // ---- pipelined CG steps on S^ --------------------------------------------------
+// Vector kernels of the steps: 1024-thread workgroups, PCG_THREAD_NODES nodes
+// per thread (at most VMS_MAX_RED_BLOCKS workgroups, one partial each).
+#ifndef PCG_THREAD_NODES
+#define PCG_THREAD_NODES 2
+#endif
+inline int pcg_blocks(int64_t n) {
+  const int64_t per = (int64_t)KRY_BLOCK * PCG_THREAD_NODES;
+  return (int)std::min<int64_t>(std::max<int64_t>((n + per - 1) / per, 1), VMS_MAX_RED_BLOCKS);
+}
 // Work vectors of one application, each [n]: r, u, w, m, nv, z, q, s, p.
 template <typename T>
 struct PcgVec {
@@ -1508,7 +1517,7 @@ struct Nested {
   void scg_apply(const T *v, T *z) {
     hipStream_t s = ctx->stream;
     const int k = o->shat_degree;
-    const int nbv = kry_blocks(n);
+    const int nbv = pcg_blocks(n);
     double *pg0 = sctl + 4, *pd0 = pg0 + VMS_MAX_RED_BLOCKS, *pg1 = pd0 + VMS_MAX_RED_BLOCKS,
            *pd1 = pg1 + VMS_MAX_RED_BLOCKS;
     const dim3 gp(spmv_grid(n)), bl(VMS_BLOCK), gv(nbv), bk(KRY_BLOCK);
