@@ -174,6 +174,19 @@ __device__ __forceinline__ double kry_sum_partials(const double *p, int nbp, int
   return r;
 }
 
+// Workgroup total of one value per thread, in a fixed order; every thread
+// receives it. Lets a kernel load its partials, issue its first streaming
+// loads, and only then reduce.
+__device__ __forceinline__ double kry_block_total(double v, double *sm) {
+  v = wave_sum(v);
+  const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  if ((threadIdx.x & 63) == 0) sm[w] = v;
+  __syncthreads();
+  double r = 0.0;
+  for (int q = 0; q < nw; ++q) r += sm[q];
+  __syncthreads();
+  return r;
+}
 // Reorthogonalisation test of the "if needed" mode (Daniel-Gragg-Kaufman-
 // Stewart with eta^2 = 1/2): after the first pass w' = w - V h, a second pass
 // is needed when ||w'||^2 < (||w'||^2 + ||h||^2) / 2, i.e. when more than half
@@ -453,12 +466,46 @@ k_normalize_givens(int64_t nvec, const T *__restrict__ w, T *V1, T *Z1, double *
     return;
   }
   if (nsum == 3) nsum = kry_need_reorth(ctrl, off, nbp, j + 1, sm) ? 2 : 1;   // "if needed" mode
-  const double hn = sqrt(kry_sum_partials(ctrl + (nsum == 2 ? off.pn2 : off.pn), nbp, 1, sm));
+  const double *pn = ctrl + (nsum == 2 ? off.pn2 : off.pn);
+  const double pl = (threadIdx.x < (unsigned)nbp) ? pn[threadIdx.x] : 0.0;
+  if (pc != PC_BJ33) {
+    const double hn = sqrt(kry_block_total(pl, sm));
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      givens_update(ctrl, off, iflag, j, nsum, maxit, hn);
+      if (post) post_flags(iflag, post, seq);   // the host may decide while the normalisation runs
+    }
+    scale_and_precond(nvec, w, hn > 0.0 ? 1.0 / hn : 0.0, V1, Z1, pc, pcd);
+    return;
+  }
+  // block-Jacobi: the first node's w and M^-1 block are loaded while the partials are reduced
+  const int64_t nn = nvec / 3, stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t i0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  double fw[3] = {0, 0, 0}, fm[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  if (i0 < nn) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) fw[c] = dl(w, 3 * i0 + c);
+#pragma unroll
+    for (int e = 0; e < 9; ++e) fm[e] = dl(pcd, 9 * i0 + e);
+  }
+  const double hn = sqrt(kry_block_total(pl, sm));
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     givens_update(ctrl, off, iflag, j, nsum, maxit, hn);
     if (post) post_flags(iflag, post, seq);   // the host may decide while the normalisation runs
   }
-  scale_and_precond(nvec, w, hn > 0.0 ? 1.0 / hn : 0.0, V1, Z1, pc, pcd);
+  const double inv = hn > 0.0 ? 1.0 / hn : 0.0;
+  for (int64_t i = i0; i < nn; i += stride) {
+    const bool pre = (i == i0);
+    const T v0 = (T)((pre ? fw[0] : dl(w, 3 * i)) * inv), v1 = (T)((pre ? fw[1] : dl(w, 3 * i + 1)) * inv),
+            v2 = (T)((pre ? fw[2] : dl(w, 3 * i + 2)) * inv);
+    V1[3 * i] = v0; V1[3 * i + 1] = v1; V1[3 * i + 2] = v2;
+    double M[9];
+#pragma unroll
+    for (int e = 0; e < 9; ++e) M[e] = pre ? fm[e] : dl(pcd, 9 * i + e);
+    const double a0 = (double)v0, a1 = (double)v1, a2 = (double)v2;
+    Z1[3 * i] = (T)(M[0] * a0 + M[1] * a1 + M[2] * a2);
+    Z1[3 * i + 1] = (T)(M[3] * a0 + M[4] * a1 + M[5] * a2);
+    Z1[3 * i + 2] = (T)(M[6] * a0 + M[7] * a1 + M[8] * a2);
+  }
 }
 
 // MGS step k: w -= H[k-1,j] V_{k-1} (k > 0), then partial dots <w, V_k>
