@@ -11,6 +11,12 @@ FP64 (GMRES at every level) and mixed (FP32 intermediate/inner levels with
 CG on the A-solves, FP64 outer FGMRES/Newton); --fp64-a-krylov and
 --mixed-a-krylov choose the A-level method of each form.
 
+--workload strip runs the paper's second workload instead: the eighth of the
+10 x 3 x 0.5 mm tensile strip (section 5.2), fully incompressible HGO with
+dispersion k_d = 0.226, fibres at +-49.98 deg, symmetry conditions on three
+planes, a tensile force ramped to 2 N over 100 s, dt = 1e-5, on the mesh
+1/dx = --size (400: 400 x 120 x 20 hexes, 5.76 M tets, 1.02 M nodes).
+
 Prints one JSON line (value = Newton iterations per second of the FP64 form).
 """
 from __future__ import annotations
@@ -239,8 +245,20 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--size", type=int, default=64)
+    ap.add_argument("--workload", default="cube", choices=["cube", "strip"],
+                    help="cube: the unit-cube compression (the headline); strip: the eighth of the anisotropic "
+                         "tensile strip of section 5.2 (HGO with dispersion, symmetry conditions, dt = 1e-5)")
+    ap.add_argument("--size", type=int, default=None,
+                    help="cube: hexes per edge (64); strip: 1/dx of the half-length (400: 400 x 120 x 20 hexes)")
     ap.add_argument("--nu", type=float, default=0.499)
+    ap.add_argument("--kd", type=float, default=0.226, help="strip: fibre dispersion k_d")
+    ap.add_argument("--fibre-deg", type=float, default=49.98,
+                    help="strip: fibre angle to the loading direction (49.98 circumferential, 40.02 axial)")
+    ap.add_argument("--dt", type=float, default=None, help="time step (cube 1e-3, strip 1e-5)")
+    ap.add_argument("--tol-abs", type=float, default=None,
+                    help="absolute Newton tolerance beside the relative 1e-8 (cube: none; strip: 1e-15, which "
+                         "ends the first step from rest, whose initial residual is ~1e-9 against a round-off "
+                         "floor near 2e-17)")
     ap.add_argument("--forms", default="fp64,mixed")
     ap.add_argument("--shat-degree", type=int, default=16)
     ap.add_argument("--shat-ratio", type=float, default=20.0)
@@ -253,9 +271,11 @@ def main():
     ap.add_argument("--orth", default="cgs1", choices=["cgs2", "cgs1", "cgs_ifneeded", "mgs"],
                     help="Arnoldi orthogonalisation of every Krylov level")
     akc = ["gmres", "cg-inner", "cg", "cg-inner-sym", "cg-sym"]
-    ap.add_argument("--fp64-a-krylov", default="gmres", choices=akc,
+    ap.add_argument("--fp64-a-krylov", default=None, choices=akc,
                     help="Krylov method of the A-solves in the FP64 form: GMRES, or CG at the inner level or at "
-                         "both A-levels, on A itself or on (A + A^T)/2 (-sym)")
+                         "both A-levels, on A itself or on (A + A^T)/2 (-sym); default gmres for the cube (few "
+                         "A-iterations), cg for the strip (about 190 per A-solve, where GMRES's growing "
+                         "orthogonalisation costs twice the time)")
     ap.add_argument("--mixed-a-krylov", default="cg", choices=akc,
                     help="the same for the mixed form")
     ap.add_argument("--precond", default="ldu", choices=["ldu", "upper", "lower", "diag", "simple"],
@@ -280,12 +300,25 @@ def main():
     import synth
     from paper_1809_06350_amd import vms as V
 
-    N = args.size
-    mesh, mat, ti = synth.cube_case(N, nu=args.nu, n_steps=10)
-    log(f"cube {N}^3: nodes={mesh.n_nodes} tets={mesh.n_tets}")
+    cube = args.workload == "cube"
+    N = args.size or (64 if cube else 400)
+    if cube:
+        dt = args.dt or 1e-3
+        mesh, mat, ti = synth.cube_case(N, nu=args.nu, n_steps=10, dt=dt)
+        wl = f"cube{N}^3 Kuhn tets, nu={args.nu}, neo-Hookean, dt={dt:g}, Newton/FGMRES 1e-8"
+    else:
+        dt = args.dt or 1e-5
+        mesh, mat, ti = synth.strip_case(N, kd=args.kd, fibre_deg=args.fibre_deg, dt=dt)
+        nx, ny, nz = synth.strip_dims(N)
+        wl = (f"tensile strip (eighth) 1/dx={N}: {nx}x{ny}x{nz} hexes x 6 Kuhn tets, incompressible HGO "
+              f"k_d={args.kd}, phi={args.fibre_deg} deg, 2 N over 100 s, dt={dt:g}, Newton/FGMRES 1e-8 "
+              f"(Newton also ends below {args.tol_abs if args.tol_abs is not None else 1e-15:g} absolute)")
+        args.no_cpu_baseline = True
+    log(f"{mesh.name}: nodes={mesh.n_nodes} tets={mesh.n_tets}")
     prob = V.Problem(mesh, mat, "cuda:0")
     n, nnzb = mesh.n_nodes, int(prob.host["row_len"].sum())   # real blocks (slots: prob.nnzb)
-    nopts = V.newton_opts(tol_R=1e-8, l_max=20)
+    tol_abs = args.tol_abs if args.tol_abs is not None else (1e-50 if cube else 1e-15)
+    nopts = V.newton_opts(tol_R=1e-8, tol_A=tol_abs, l_max=20)
     mt = [float(x) for x in args.mixed_tol.split(",")]
     ft = [float(x) for x in args.fp64_tol.split(",")]
     if args.spmv_only:
@@ -295,6 +328,8 @@ def main():
             "mgs": V.ORTH_MGS}[args.orth]
     akm = {"gmres": (V.AK_GMRES, 0), "cg-inner": (V.AK_CG_INNER, 0), "cg": (V.AK_CG, 0),
            "cg-inner-sym": (V.AK_CG_INNER, 1), "cg-sym": (V.AK_CG, 1)}
+    if args.fp64_a_krylov is None:
+        args.fp64_a_krylov = "gmres" if cube else "cg"
     fk, fs = akm[args.fp64_a_krylov]
     mk, ms = akm[args.mixed_a_krylov]
     sm = {"chebyshev": V.SHAT_CHEBYSHEV, "cg": V.SHAT_CG}[args.shat_method]
@@ -343,11 +378,11 @@ def main():
         "k_spmv_A<double,double>": {"achieved": by64 / t64 / 1e9, "us_per_launch": t64 * 1e6,
                                     "bytes_per_launch": by64, "launches_per_step": launches_A,
                                     "est_ms_per_step": launches_A * t64 * 1e3,
-                                    "traffic": pmc_traffic("spmv_A", "traffic_bytes_fp64") if N == 64 else None},
+                                    "traffic": pmc_traffic("spmv_A", "traffic_bytes_fp64") if cube and N == 64 else None},
         "k_shat_spmv<double>": {"achieved": bys64 / ts64 / 1e9, "us_per_launch": ts64 * 1e6,
                                "bytes_per_launch": bys64, "launches_per_step": launches_S,
                                "est_ms_per_step": launches_S * ts64 * 1e3,
-                               "traffic": pmc_traffic("shat", "traffic_bytes_fp64") if N == 64 else None},
+                               "traffic": pmc_traffic("shat", "traffic_bytes_fp64") if cube and N == 64 else None},
     }
     dom = max(kern, key=lambda k: kern[k]["est_ms_per_step"])
     kd = kern[dom]
@@ -370,12 +405,12 @@ def main():
         t32 = time_spmv(prob, rm["K"], V.OP_A, x64.float(), True)
         extra["spmv_A_fp32"] = {"GB/s": by32 / t32 / 1e9, "us_per_launch": t32 * 1e6, "bytes_per_launch": by32,
                                 "frac_hbm": by32 / t32 / 1e9 / HBM_PEAK_GBS,
-                                "traffic": pmc_traffic("spmv_A", "traffic_bytes_fp32") if N == 64 else None}
+                                "traffic": pmc_traffic("spmv_A", "traffic_bytes_fp32") if cube and N == 64 else None}
         ts32 = time_shat(prob, rm["K"], True)
         bys32 = shat_bytes(n, nzs, 4, shat_idx_bytes(prob))
         extra["shat_fp32"] = {"GB/s": bys32 / ts32 / 1e9, "us_per_launch": ts32 * 1e6, "bytes_per_launch": bys32,
                               "frac_hbm": bys32 / ts32 / 1e9 / HBM_PEAK_GBS,
-                              "traffic": pmc_traffic("shat", "traffic_bytes_fp32") if N == 64 else None}
+                              "traffic": pmc_traffic("shat", "traffic_bytes_fp32") if cube and N == 64 else None}
         u64 = results.get("fp64", rm)["u"]
         err = float((rm["u"] - u64).norm() / u64.norm()) if "fp64" in results else None
         extra["mixed"] = {"newton_per_s": rm["n_newton"] / rm["wall_s"],
@@ -393,7 +428,7 @@ def main():
            "ms_per_newton_step": 1e3 * r["wall_s"] / r["n_newton"], "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "f64" if primary == "fp64" else "f32+f64",
            "data": "synthetic",
-           "config": {"workload": f"cube{N}^3 Kuhn tets, nu={args.nu}, neo-Hookean, dt=1e-3, Newton/FGMRES 1e-8",
+           "config": {"workload": wl,
                       "nodes": n, "tets": mesh.n_tets, "unknowns": 4 * n, "nnzb": nnzb,
                       "block_slots": prob.nnzb,
                       "shat_degree": args.shat_degree, "shat_ratio": args.shat_ratio,

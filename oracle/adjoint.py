@@ -26,7 +26,7 @@ import numpy as np
 import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
-from synth import helical_fibres
+from synth import fibre_field
 
 from . import assemble as AS
 from . import element as E
@@ -43,7 +43,7 @@ def with_params(mesh, mat, theta):
     mat2 = dataclasses.replace(mat, mu=theta[0], kappa=theta[1], k1=theta[2], k2=theta[3])
     mesh2 = mesh
     if mesh.fibre is not None:
-        fib, _ = helical_fibres(mesh.X, mesh.tets, theta[4])
+        fib, _ = fibre_field(mesh, theta[4])
         mesh2 = dataclasses.replace(mesh, fibre=fib)
     return mesh2, mat2
 

@@ -16,7 +16,7 @@ import dataclasses
 import numpy as np
 import torch
 
-from synth import helical_fibres
+from synth import fibre_field
 
 from . import vms as V
 
@@ -42,7 +42,7 @@ class TimeHistory:
         self.prob.set_material(dataclasses.replace(mat, mu=th[0], kappa=th[1] if th[1] > 0 else mat.kappa,
                                                    k1=th[2], k2=th[3]))
         if mesh.fibre is not None:
-            fib, dfib = helical_fibres(mesh.X, mesh.tets, th[4])
+            fib, dfib = fibre_field(mesh, th[4])
             self.prob.set_fibres(fib, dfib)
 
     def timeint(self, s):

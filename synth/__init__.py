@@ -5,9 +5,10 @@ random vectors.  It holds none of the method's arithmetic (no residual, no
 tangent, no solver step): every number it produces is problem data that both
 sides consume independently.
 """
-from .mesh import cube_mesh, tube_mesh, helical_fibres, Mesh
-from .cases import (Material, TimeInt, cube_case, tube_case, material_from_nu,
+from .mesh import (cube_mesh, tube_mesh, strip_mesh, strip_dims, helical_fibres, planar_fibres,
+                   fibre_field, Mesh)
+from .cases import (Material, TimeInt, cube_case, tube_case, strip_case, material_from_nu,
                     random_vector, random_state, NH_COMP, NH_INCOMP, HGO_INCOMP)
 
-__all__ = ["cube_mesh", "tube_mesh", "Mesh", "Material", "TimeInt",
-           "cube_case", "material_from_nu"]
+__all__ = ["cube_mesh", "tube_mesh", "strip_mesh", "Mesh", "Material", "TimeInt",
+           "cube_case", "tube_case", "strip_case", "material_from_nu", "fibre_field"]

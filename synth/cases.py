@@ -12,7 +12,7 @@ from dataclasses import dataclass
 
 import numpy as np
 
-from .mesh import cube_mesh, tube_mesh
+from .mesh import cube_mesh, strip_dims, strip_mesh, tube_mesh
 
 NH_COMP, NH_INCOMP, HGO_INCOMP = 0, 1, 2
 
@@ -62,6 +62,19 @@ def tube_case(nr: int = 2, nt: int = 16, nz: int = 8, dt: float = 0.05, n_steps:
     mat = Material(kind=HGO_INCOMP, rho0=1000.0, mu=3.0e4, kappa=np.inf,
                    k1=2.36e5, k2=0.84, kd=0.0)
     return mesh, mat, TimeInt(dt=dt, rho_inf=0.5, n_steps=n_steps)
+
+
+def strip_case(n: int = 200, kd: float = 0.226, fibre_deg: float = 49.98, dt: float = 1.0e-5,
+               t_ramp: float = 100.0, seed: int = 0, dims: tuple | None = None):
+    """Tensile test of the adventitial strip (section 5.2): fully incompressible
+    HGO, mu = 7.64 kPa, k1 = 996.6 kPa, k2 = 524.6, density 1 g/cm^3; the
+    tensile force ramps linearly to 2 N over t_ramp seconds.  n = 1/dx sets the
+    mesh (strip_dims); fibre_deg = 49.98 is the circumferential specimen,
+    40.02 the axial one.  dims = (nx, ny, nz) overrides the hex counts."""
+    mesh = strip_mesh(*(dims or strip_dims(n)), fibre_deg=fibre_deg, seed=seed)
+    mat = Material(kind=HGO_INCOMP, rho0=1000.0, mu=7.64e3, kappa=np.inf,
+                   k1=996.6e3, k2=524.6, kd=kd)
+    return mesh, mat, TimeInt(dt=dt, rho_inf=0.5, n_steps=int(round(t_ramp / dt)))
 
 
 def random_vector(n: int, seed: int, dtype=np.float64) -> np.ndarray:

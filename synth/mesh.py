@@ -9,10 +9,16 @@
 * ``tube_mesh(nr, nt, nz)``: a thick-walled tube (inner radius 1.0, wall 0.2,
   length 2.0) meshed structured in (r, theta, z), periodic in theta, with the
   same Kuhn split; carries two helical fibre directions per element.
+* ``strip_mesh(nx, ny, nz)``: one eighth of the tensile-test strip of
+  section 5.2 (10 x 3 x 0.5 mm), i.e. the box [0, 5] x [0, 1.5] x [0, 0.25] mm,
+  with symmetry conditions on the three coordinate planes, the loading face
+  x = 5 mm held to move along x only and loaded by a dead traction along x;
+  two in-plane fibre families at +-phi from the loading direction.
 
-Node numbering is lexicographic with the first index fastest, tets are
-emitted hex by hex, and every tet is positively oriented in the reference
-configuration.
+Node numbering is lexicographic with the first index fastest (for the strip
+the thickness index fastest and the length index slowest), tets are emitted
+hex by hex in the same order, and every tet is positively oriented in the
+reference configuration.
 """
 from __future__ import annotations
 
@@ -145,6 +151,26 @@ def helical_fibres(X, tets, phi):
     return fibre, dfibre
 
 
+def planar_fibres(n_tets, phi):
+    """Fibre directions a_{1,2} = cos(phi) e_x +- sin(phi) e_y in every element
+    and their derivatives with respect to phi (phi may be complex)."""
+    c, s = np.cos(phi), np.sin(phi)
+    one = np.ones(n_tets)
+    zero = np.zeros(n_tets)
+    fibre = np.stack([np.stack([c * one, s * one, zero], axis=1),
+                      np.stack([c * one, -s * one, zero], axis=1)], axis=1)
+    dfibre = np.stack([np.stack([-s * one, c * one, zero], axis=1),
+                       np.stack([-s * one, -c * one, zero], axis=1)], axis=1)
+    return fibre, dfibre
+
+
+def fibre_field(mesh, phi):
+    """The mesh's fibre field at fibre angle phi and its derivative in phi."""
+    if mesh.meta.get("fibre_field") == "planar":
+        return planar_fibres(mesh.n_tets, phi)
+    return helical_fibres(mesh.X, mesh.tets, phi)
+
+
 def tube_mesh(nr: int, nt: int, nz: int, r_in: float = 1.0, wall: float = 0.2,
               length: float = 2.0, fibre_deg: float = 45.0, stretch: float = 1.5,
               t_end: float = 1.0) -> Mesh:
@@ -176,4 +202,67 @@ def tube_mesh(nr: int, nt: int, nz: int, r_in: float = 1.0, wall: float = 0.2,
     return Mesh(name=f"tube{nr}x{nt}x{nz}", X=X, tets=tets, bfaces=bfaces,
                 traction=traction, dir_mask=dir_mask, dir_vel=dir_vel, fibre=fibre,
                 meta={"nr": nr, "nt": nt, "nz": nz, "stretch": stretch, "t_end": t_end,
-                      "fibre_rad": float(np.deg2rad(fibre_deg))})
+                      "fibre_rad": float(np.deg2rad(fibre_deg)), "fibre_field": "helical"})
+
+
+# Dimensions of the tensile specimen of section 5.2 in metres; the model is
+# the eighth x, y, z >= 0 of the specimen centred at the origin.
+STRIP_FULL = (10.0e-3, 3.0e-3, 0.5e-3)
+
+
+def strip_dims(n: int):
+    """Hexes per axis of the eighth-strip for mesh size dx = 1/n of its
+    half-length (the paper's 1/dx = 200, 400, 600 ladder): n x 0.3n x 0.05n."""
+    return n, max(1, int(round(0.3 * n))), max(1, int(round(0.05 * n)))
+
+
+def strip_mesh(nx: int, ny: int, nz: int, fibre_deg: float = 49.98, force: float = 2.0,
+               seed: int = 0, jitter: float = 0.01) -> Mesh:
+    """Eighth of the tensile strip, nx * ny * nz hexes x 6 Kuhn tets.
+
+    Symmetry planes fix u_x on x = 0, u_y on y = 0 and u_z on z = 0.  The
+    loading face x = L/2 moves along x only (u_y = u_z = 0 there) and carries
+    the dead traction force / (W T) along x, the nominal stress of the full
+    specimen under the tensile force.  Interior nodes get a seeded jitter of
+    +-1% of the hex size per axis; boundary nodes stay on their planes.
+    """
+    lx, ly, lz = (0.5 * d for d in STRIP_FULL)
+    gx = lx * np.arange(nx + 1) / nx
+    gy = ly * np.arange(ny + 1) / ny
+    gz = lz * np.arange(nz + 1) / nz
+    # nodes numbered with the thickness index fastest and the length index
+    # slowest: the narrowest bandwidth of the node graph for this shape
+    xx, yy, zz = np.meshgrid(gx, gy, gz, indexing="ij")
+    X = np.stack([xx.ravel(), yy.ravel(), zz.ravel()], axis=1)
+    ix, iy, iz = (a.ravel() for a in np.meshgrid(np.arange(nx + 1), np.arange(ny + 1), np.arange(nz + 1),
+                                                  indexing="ij"))
+    interior = (ix > 0) & (ix < nx) & (iy > 0) & (iy < ny) & (iz > 0) & (iz < nz)
+    h = np.array([lx / nx, ly / ny, lz / nz])
+    rng = np.random.default_rng(seed)
+    pert = rng.uniform(-1.0, 1.0, size=X.shape) * (jitter * h)[None, :]
+    X = X + pert * interior[:, None]
+
+    def node_id(a, b, c):          # a: z index, b: y index, c: x index
+        return a + (nz + 1) * (b + (ny + 1) * c)
+
+    # hexes in the same order (z fastest); the (z, y, x) index frame is a
+    # reflection of (x, y, z), so every simplex is reoriented
+    tets = _kuhn_tets(nz, ny, nx, node_id)[:, [0, 2, 1, 3]]
+    load = ix == nx
+    bfaces = _faces_on(tets, load)
+    t_full = force / (STRIP_FULL[1] * STRIP_FULL[2])
+    traction = np.zeros((bfaces.shape[0], 3))
+    traction[:, 0] = t_full
+    dir_mask = np.zeros((X.shape[0], 4), dtype=np.uint8)
+    dir_mask[ix == 0, 0] = 1
+    dir_mask[iy == 0, 1] = 1
+    dir_mask[iz == 0, 2] = 1
+    dir_mask[load, 1] = 1
+    dir_mask[load, 2] = 1
+    dir_vel = np.zeros((X.shape[0], 3))
+    phi = float(np.deg2rad(fibre_deg))
+    fibre, _ = planar_fibres(tets.shape[0], phi)
+    return Mesh(name=f"strip{nx}x{ny}x{nz}", X=X, tets=tets, bfaces=bfaces, traction=traction,
+                dir_mask=dir_mask, dir_vel=dir_vel, fibre=fibre,
+                meta={"nx": nx, "ny": ny, "nz": nz, "seed": seed, "jitter": jitter, "force": force,
+                      "t_full": t_full, "fibre_rad": phi, "fibre_field": "planar"})

@@ -29,7 +29,7 @@ def _case(name):
 def _prob(mesh, mat):
     prob = V.Problem(mesh, mat, "cuda:0")
     if mesh.fibre is not None:
-        fib, dfib = synth.helical_fibres(mesh.X, mesh.tets, mesh.meta["fibre_rad"])
+        fib, dfib = synth.fibre_field(mesh, mesh.meta["fibre_rad"])
         prob.set_fibres(fib, dfib)
     return prob
 

@@ -1,6 +1,7 @@
 """Parity at the benchmark sizes, where the oracle cannot solve.
 
-* sampled rows: at a seeded state on the 64^3 cube (and the full tube) the
+* sampled rows: at a seeded state on the 64^3 cube (the full tube, the
+  tensile strip at 1/dx = 400) the
   oracle computes the element residuals/tangents of the elements around a
   few sampled nodes and sums them into those nodes' rows; the GPU rows must
   agree to 1e-11 of the largest entry;
@@ -8,7 +9,8 @@
   configuration satisfies the oracle's own discrete equations: the oracle's
   norm of (R-bar_k, R_p, R_m) at that state, relative to its norm at the
   predictor, is below the Newton tolerance (FP64 and mixed forms; 64^3
-  nu = 0.499, the 32^3 Poisson-ratio sweep, the full-size HGO tube);
+  nu = 0.499, the 32^3 Poisson-ratio sweep, the full-size HGO tube, the
+  tensile strip at 1/dx = 200);
 * the adjoint gradient at 32^3 matches central differences of the GPU
   forward run (h = 1e-6 relative).
 """
@@ -30,7 +32,7 @@ pytestmark = pytest.mark.gpu
 def _problem(mesh, mat):
     prob = V.Problem(mesh, mat, "cuda:0")
     if mesh.fibre is not None:
-        fib, dfib = synth.helical_fibres(mesh.X, mesh.tets, mesh.meta["fibre_rad"])
+        fib, dfib = synth.fibre_field(mesh, mesh.meta["fibre_rad"])
         prob.set_fibres(fib, dfib)
     return prob
 
@@ -38,7 +40,8 @@ def _problem(mesh, mat):
 def _sampled_rows(mesh, mat, ti, prob, seed, n_sample=12):
     rng = np.random.default_rng(seed)
     nodes = rng.choice(mesh.n_nodes, n_sample, replace=False)
-    small = {"u": 1e-4}                 # well below the element size (1/64 and 1/80)
+    # displacements well below the element size (1/64 and 1/80; 12.5 um across the strip's thickness)
+    small = {"u": 1e-7, "v": 1e-3, "du": 1e-3} if mesh.name.startswith("strip") else {"u": 1e-4}
     sn = synth.random_state(mesh.n_nodes, seed, small)
     it = synth.random_state(mesh.n_nodes, seed + 1, small)
     st = prob.new_state()
@@ -96,10 +99,12 @@ def _sampled_rows(mesh, mat, ti, prob, seed, n_sample=12):
         yield "corr_p", cg[node, 3], corr_o[3]
 
 
-@pytest.mark.parametrize("name", ["cube64", "tube"])
+@pytest.mark.parametrize("name", ["cube64", "tube", "strip400"])
 def test_sampled_rows_at_full_size(name):
     if name == "cube64":
         mesh, mat, ti = synth.cube_case(64, nu=0.499, n_steps=10)
+    elif name == "strip400":
+        mesh, mat, ti = synth.strip_case(400)
     else:
         mesh, mat, ti = synth.tube_case(8, 256, 160, dt=1e-3, n_steps=20, stretch=1.001)
     prob = _problem(mesh, mat)
@@ -125,7 +130,7 @@ def _oracle_residual_ratio(mesh, mat, ti, s, state_n, state_np1):
     return norm(state_np1) / norm(pred)
 
 
-def _gpu_steps(prob, mesh, ti, n_steps, sopts, tol=1e-8):
+def _gpu_steps(prob, mesh, ti, n_steps, sopts, tol=1e-8, tol_abs=1e-50):
     st = prob.new_state()
     vm = torch.from_numpy(mesh.dir_mask[:, 0:3].astype(bool)).cuda()
     dv = torch.from_numpy(mesh.dir_vel).cuda()
@@ -135,7 +140,7 @@ def _gpu_steps(prob, mesh, ti, n_steps, sopts, tol=1e-8):
     K = None
     for s in range(n_steps):
         stats, K = prob.step(st, V.time_int(ti.dt, ti.rho_inf, s * ti.dt, ti.n_steps * ti.dt),
-                             V.newton_opts(tol_R=tol), sopts, K)
+                             V.newton_opts(tol_R=tol, tol_A=tol_abs), sopts, K)
         assert stats["status"] == 0
         states.append({k: st[k].cpu().numpy().copy() for k in ("u", "p", "v", "du", "dp", "dv")})
         prob.roll(st)
@@ -175,6 +180,24 @@ def test_full_tube_time_step_satisfies_oracle_equations():
     ratio = _oracle_residual_ratio(mesh, mat, ti, 0, states[0], states[1])
     print(f"[tube] oracle |R|/|R0| = {ratio:.3e}", flush=True)
     assert ratio <= 1.5e-8
+
+
+@pytest.mark.parametrize("precision", [V.FP64, V.MIXED])
+def test_full_strip_time_steps_satisfy_oracle_equations(precision):
+    """The eighth-strip at 1/dx = 200 (200 x 60 x 10 hexes, 720,000 tets) at the
+    paper's dt = 1e-5, three steps from rest with the bench's options.  The
+    first step's initial residual is ~1e-9 against a round-off floor near
+    2e-17 (the load is 1e-7 of full), so it ends at the 1e-15 absolute
+    tolerance; the next two are checked against the oracle's equations."""
+    mesh, mat, ti = synth.strip_case(200)
+    prob = _problem(mesh, mat)
+    ak = V.AK_CG if precision == V.MIXED else V.AK_GMRES
+    sopts = V.solver_opts(rtol=1e-8, precision=precision, a_krylov=ak, cg_symmetrise=0)
+    states = _gpu_steps(prob, mesh, ti, 3, sopts, tol_abs=1e-15)
+    for s in (1, 2):
+        ratio = _oracle_residual_ratio(mesh, mat, ti, s, states[s], states[s + 1])
+        print(f"[strip200] precision={precision} step {s} oracle |R|/|R0| = {ratio:.3e}", flush=True)
+        assert ratio <= 1.5e-8
 
 
 def _adjoint_vs_fd(mesh, mat, ti, n_steps, sel, params, theta0, seed, sopts, nopts, rel, h_rel=None):

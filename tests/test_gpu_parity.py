@@ -33,9 +33,22 @@ def case(name):
         mesh, mat, ti = synth.cube_case(5, nu=0.499, n_steps=2)
     elif name == "tube-hgo":
         mesh, mat, ti = synth.tube_case(2, 12, 4, dt=0.05, n_steps=20)
+    elif name == "strip-hgo":
+        mesh, mat, ti = STRIP()
     else:
         raise KeyError(name)
     return mesh, mat, ti
+
+
+def STRIP():
+    """A small eighth-strip (10 x 4 x 3 hexes, dispersion 0.226) whose load
+    ramps over 1 ms, so that the first steps at the paper's dt = 1e-5 carry a
+    load well above round-off."""
+    return synth.strip_case(dims=(10, 4, 3), dt=1e-5, t_ramp=1e-3)
+
+
+# random states at the strip's scale: its elements are 0.08-0.5 mm across
+STRIP_STATE = {"u": 2e-6, "v": 1e-3, "du": 1e-3}
 
 
 def gpu_ti(ti, t_n):
@@ -43,8 +56,9 @@ def gpu_ti(ti, t_n):
 
 
 def states(mesh, seed):
-    sn = synth.random_state(mesh.n_nodes, seed)
-    it = synth.random_state(mesh.n_nodes, seed + 1)
+    scale = STRIP_STATE if mesh.name.startswith("strip") else None
+    sn = synth.random_state(mesh.n_nodes, seed, scale)
+    it = synth.random_state(mesh.n_nodes, seed + 1, scale)
     return sn, it
 
 
@@ -68,7 +82,7 @@ def problems():
     return get
 
 
-@pytest.mark.parametrize("name", ["cube-comp", "cube-incomp", "cube-nu0499", "tube-hgo"])
+@pytest.mark.parametrize("name", ["cube-comp", "cube-incomp", "cube-nu0499", "tube-hgo", "strip-hgo"])
 def test_assembly_matches_oracle(problems, name):
     prob, mesh, mat, ti, disc = problems(name)
     print(f"[assembly] {name} n={mesh.n_nodes} m={mesh.n_tets}", flush=True)
@@ -112,7 +126,7 @@ def test_assembly_is_bitwise_reproducible(problems):
         assert torch.equal(a, b)
 
 
-@pytest.mark.parametrize("name", ["cube-comp", "tube-hgo"])
+@pytest.mark.parametrize("name", ["cube-comp", "tube-hgo", "strip-hgo"])
 def test_block_products_match_oracle_matrix(problems, name):
     prob, mesh, mat, ti, disc = problems(name)
     sn, it = states(mesh, 51)
@@ -162,7 +176,7 @@ def _prepared(prob, mesh, ti, disc, seed, mirror32=False, nonzero_rk=True, zero_
     return st, K, rhs, Ks, W * rd, W, (sn, it, sto)
 
 
-@pytest.mark.parametrize("name", ["cube-nu0499", "cube-incomp", "tube-hgo"])
+@pytest.mark.parametrize("name", ["cube-nu0499", "cube-incomp", "tube-hgo", "strip-hgo"])
 def test_schur_hat_matches_oracle(problems, name):
     """S^ = D - C diag(A)^-1 B (section 4.2) of the oracle's scaled system, formed with scipy."""
     import scipy.sparse as sp
@@ -185,7 +199,7 @@ def test_schur_hat_matches_oracle(problems, name):
     assert rel_err(sdinv.cpu().numpy(), expect) < 1e-12
 
 
-@pytest.mark.parametrize("name", ["cube-nu0499", "tube-hgo"])
+@pytest.mark.parametrize("name", ["cube-nu0499", "tube-hgo", "strip-hgo"])
 @pytest.mark.parametrize("fp32", [False, True])
 def test_shat_product_matches_oracle(problems, name, fp32):
     """y = S^ x by the product kernel of the Schur preconditioner's CG steps
@@ -240,7 +254,7 @@ def _with_mirrors(prob, K):
     return K2
 
 
-@pytest.mark.parametrize("name", ["cube-comp", "tube-hgo"])
+@pytest.mark.parametrize("name", ["cube-comp", "tube-hgo", "strip-hgo"])
 def test_dirichlet_and_scaling_match_oracle(problems, name):
     prob, mesh, mat, ti, disc = problems(name)
     st, K, rhs, Ks, rs, W, _ = _prepared(prob, mesh, ti, disc, 61, mirror32=True)
@@ -275,7 +289,7 @@ def test_nested_solve_matches_lu(problems, precond, max_outer, orth, shat, metho
     assert np.linalg.norm(xg - xo) <= 1e-7 * np.linalg.norm(xo)
 
 
-@pytest.mark.parametrize("name", ["cube-nu0499", "cube-incomp", "tube-hgo"])
+@pytest.mark.parametrize("name", ["cube-nu0499", "cube-incomp", "tube-hgo", "strip-hgo"])
 @pytest.mark.parametrize("precision", [V.FP64, V.MIXED])
 @pytest.mark.parametrize("shat,shat_method", [(0, V.SHAT_CHEBYSHEV), (6, V.SHAT_CHEBYSHEV), (6, V.SHAT_CG)])
 def test_solve_reaches_requested_residual(problems, name, precision, shat, shat_method):
@@ -296,7 +310,7 @@ def test_solve_reaches_requested_residual(problems, name, precision, shat, shat_
     assert np.linalg.norm(xg - xo) <= 1e-5 * np.linalg.norm(xo)
 
 
-@pytest.mark.parametrize("name", ["cube-nu0499", "tube-hgo"])
+@pytest.mark.parametrize("name", ["cube-nu0499", "tube-hgo", "strip-hgo"])
 @pytest.mark.parametrize("precision", [V.FP64, V.MIXED])
 @pytest.mark.parametrize("a_krylov,sym", [(V.AK_CG_INNER, 1), (V.AK_CG, 1), (V.AK_CG, 0)])
 def test_cg_levels_solve_matches_lu(problems, name, precision, a_krylov, sym):
@@ -487,3 +501,33 @@ def test_mixed_precision_time_step_error(a_krylov):
     print(f"[mixed] displacement error vs FP64 oracle = {err:.3e}; stats={hist[-1]}", flush=True)
     assert all(h["status"] == 0 for h in hist)
     assert err < 1e-6
+
+
+@pytest.mark.parametrize("precision,a_krylov", [(V.FP64, V.AK_GMRES), (V.MIXED, V.AK_CG)])
+def test_strip_time_steps_match_oracle(precision, a_krylov):
+    """Three time steps of the small eighth-strip (incompressible HGO with
+    dispersion, symmetry conditions, traction on the loading face) against the
+    oracle's: FP64 with GMRES A-levels, and the mixed form with CG on A as the
+    bench runs it."""
+    mesh, mat, ti = STRIP()
+    prob = V.Problem(mesh, mat, "cuda:0")
+    mixed = precision == V.MIXED
+    nopts = V.newton_opts(tol_R=1e-8 if mixed else 1e-10, l_max=10)
+    if mixed:
+        sopts = V.solver_opts(rtol=1e-8, rtol_A=1e-5, rtol_S=1e-5, rtol_I=1e-3, precision=V.MIXED,
+                              a_krylov=a_krylov, cg_symmetrise=0)
+    else:
+        sopts = V.solver_opts(rtol=1e-10, rtol_A=1e-10, rtol_S=1e-10, rtol_I=1e-12)
+    st, hist = _run_steps(prob, mesh, ti, 3, nopts, sopts)
+    disc = AS.Discretization(mesh, mat)
+    so = NW.rest_state(mesh)
+    for s in range(3):
+        so, info = NW.time_step(disc, ti, so, s * ti.dt, tol_R=nopts.tol_R)
+        print(f"[strip step {s}] gpu newton={hist[s]['n_newton']} res={hist[s]['res_norm']} "
+              f"oracle={info['norms']}", flush=True)
+        assert hist[s]["status"] == 0
+        if not mixed:
+            assert hist[s]["n_newton"] == info["n_newton"]
+    tol = 1e-6 if mixed else 1e-7
+    for k in ("u", "p", "v") if mixed else ("u", "p", "v", "du", "dp", "dv"):
+        assert rel_err(st[k].cpu().numpy(), so[k]) < tol, k
