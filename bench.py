@@ -46,6 +46,15 @@ def spmv_A_bytes(n, nnzb, elem):
     return (9 * elem + 4) * nnzb + 2 * 3 * elem * n
 
 
+def cg_spmv_bytes(n, nnzb, elem):
+    """Algorithmic bytes of one CG product launch (w = A z with the direction
+    updates p = z + beta p, q = w + beta q): values + column indices of the
+    nnzb real blocks, z once, p and q read and written.  The first launch of a
+    solve reads no p, q (2 * 3 * elem * n less; about one launch in eight at
+    64^3, so the mean is within 0.5 % of this)."""
+    return (9 * elem + 4) * nnzb + 5 * 3 * elem * n
+
+
 def shat_bytes(n, nnz, elem, idx=4):
     """Algorithmic bytes of one S^ product (the product of the Schur
     preconditioner's CG steps): the real off-diagonal entries (value + column
@@ -62,6 +71,8 @@ PMC_FILES = {
     "spmv_A": ("linalg.h", None, None, "spmv_A_cube64_pmc.md"),
     "shat": ("solver.hip", "// Off-diagonal part of row ro of S^ times z", "// ---- pipelined CG steps on S^",
              "shat_spmv_cube64_pmc.md"),
+    "cg_spmv": ("solver.hip", "// CG iteration j, first half.", "// CG iteration j, second half",
+                "cg_spmv_cube64_pmc.md"),
 }
 
 
@@ -165,6 +176,23 @@ def run_form(prob, mesh, ti, nopts, sopts, steps, warmup, timing=False):
     n_newton = sum(p["n_newton"] for p in per)
     return {"wall_s": wall, "n_newton": n_newton, "per_step": per, "u": st["u"].clone(), "K": K,
             "spmv_A_ms": ktime[0], "spmv_A_launches": ktime[1]}
+
+
+def time_a_product(prob, ti, nopts, sopts):
+    """Duration of the A-level product kernel inside a time step (the plain
+    A-block product on GMRES levels, the CG product kernel on CG levels): one
+    extra step from rest (after the timed steps) with the library's launch
+    timing on, so every working launch records its own start and end with HIP
+    events on the library's stream.  Returns (ms in the step, launches)."""
+    import torch
+    from paper_1809_06350_amd import vms as V
+    st = prob.new_state()
+    prob.set_timing(True)
+    prob.step(st, V.time_int(ti.dt, ti.rho_inf, 0.0, ti.n_steps * ti.dt), nopts, sopts, None)
+    torch.cuda.synchronize()
+    ms, cnt = prob.kernel_time(fp32=sopts.precision == V.MIXED)
+    prob.set_timing(False)
+    return ms, cnt
 
 
 def cpu_baseline(N=16, nu=0.499, steps=2):
@@ -273,9 +301,9 @@ def main():
     akc = ["gmres", "cg-inner", "cg", "cg-inner-sym", "cg-sym"]
     ap.add_argument("--fp64-a-krylov", default=None, choices=akc,
                     help="Krylov method of the A-solves in the FP64 form: GMRES, or CG at the inner level or at "
-                         "both A-levels, on A itself or on (A + A^T)/2 (-sym); default gmres for the cube (few "
-                         "A-iterations), cg for the strip (about 190 per A-solve, where GMRES's growing "
-                         "orthogonalisation costs twice the time)")
+                         "both A-levels, on A itself or on (A + A^T)/2 (-sym); default gmres for the cube, cg for "
+                         "the strip (about 190 iterations per A-solve, where GMRES's growing orthogonalisation "
+                         "costs twice the time)")
     ap.add_argument("--mixed-a-krylov", default="cg", choices=akc,
                     help="the same for the mixed form")
     ap.add_argument("--precond", default="ldu", choices=["ldu", "upper", "lower", "diag", "simple"],
@@ -354,13 +382,17 @@ def main():
     r = results[primary]
     value = r["n_newton"] / r["wall_s"]
 
-    # dominant kernel of the FP64 form: the 3x3 block product of the A-levels or the S^ product of the
-    # Schur preconditioner's CG steps, whichever takes more time per step (launches counted from the
-    # solver statistics times the kernel's duration).  Each duration is the average over 50 back-to-back
-    # launches on the matrices of the workload's last Newton system, between two HIP events on the
-    # library's stream (the torch current stream).  With --kernel-timing every launch of the A-product
-    # inside the timed steps is event-timed as well and reported beside it (that figure includes the
-    # per-launch event overhead).
+    # dominant kernel of the FP64 form: the A-level product (the plain A-block product on GMRES levels,
+    # the CG product kernel that fuses it with the direction updates on CG levels) or the S^ product of
+    # the Schur preconditioner's CG steps, whichever takes more time per step.  The A-level product is
+    # timed inside one extra time step from rest: every working launch records its own start and end
+    # (launches and ms per step counted directly; back-to-back launches of the plain product run
+    # faster, about 55 against 62 us at 64^3, on caches that the steps do not leave warm).  The S^
+    # product is timed as the average over 50 back-to-back launches on the S^ of the workload's last
+    # Newton system, between two HIP events on the library's stream (the torch current stream), times
+    # the launches the solver statistics give (the kernel trace of the steps gives the same duration).
+    # With --kernel-timing every A-product launch inside the timed steps is event-timed as well and
+    # reported beside it (that figure includes the per-launch event overhead).
     K = r["K"]
     so = forms[primary]
     x64 = torch.randn(n, 3, dtype=torch.float64, device="cuda:0", generator=torch.Generator("cuda:0").manual_seed(1))
@@ -370,30 +402,52 @@ def main():
     ts64 = time_shat(prob, K, False)
     bys64 = shat_bytes(n, nzs, 8, shat_idx_bytes(prob))
     steps_stats = r["per_step"]
-    launches_A = sum(p["it_A_total"] + p["it_I_total"] for p in steps_stats) / args.steps
     # the CG steps on S^: one product to start and one per step
     launches_S = (sum(p["it_S_total"] for p in steps_stats) / args.steps * (so.shat_degree + 1)
                   if so.shat_method == V.SHAT_CG else 0.0)
+    isolated = "HIP events around 50 back-to-back launches on the last Newton system of the timed steps"
+    in_step = ("HIP events recorded by each working launch of the kernel (hipExtLaunchKernelGGL, the library's "
+               "stream) during one extra time step from rest after the timed steps")
     kern = {
-        "k_spmv_A<double,double>": {"achieved": by64 / t64 / 1e9, "us_per_launch": t64 * 1e6,
-                                    "bytes_per_launch": by64, "launches_per_step": launches_A,
-                                    "est_ms_per_step": launches_A * t64 * 1e3,
-                                    "traffic": pmc_traffic("spmv_A", "traffic_bytes_fp64") if cube and N == 64 else None},
         "k_shat_spmv<double>": {"achieved": bys64 / ts64 / 1e9, "us_per_launch": ts64 * 1e6,
                                "bytes_per_launch": bys64, "launches_per_step": launches_S,
                                "est_ms_per_step": launches_S * ts64 * 1e3,
-                               "traffic": pmc_traffic("shat", "traffic_bytes_fp64") if cube and N == 64 else None},
+                               "traffic": pmc_traffic("shat", "traffic_bytes_fp64") if cube and N == 64 else None,
+                               "timing": isolated},
     }
+    # the A-level product runs as the plain A-block product on GMRES levels and inside the CG product
+    # kernel on CG levels; with one method at both levels it is timed inside a time step
+    if so.a_krylov in (V.AK_GMRES, V.AK_CG):
+        cg_levels = so.a_krylov == V.AK_CG
+        ms_a, cnt_a = time_a_product(prob, ti, nopts, so)
+        ta = ms_a * 1e-3 / max(cnt_a, 1)
+        bya = cg_spmv_bytes(n, nnzb, 8) if cg_levels else by64
+        name = "k_cg_spmv<double>" if cg_levels else "k_spmv_A<double,double>"
+        kern[name] = {"achieved": bya / ta / 1e9, "us_per_launch": ta * 1e6, "bytes_per_launch": bya,
+                      "launches_per_step": cnt_a, "est_ms_per_step": ms_a,
+                      "traffic": (pmc_traffic("cg_spmv" if cg_levels else "spmv_A", "traffic_bytes_fp64")
+                                  if cube and N == 64 else None),
+                      "timing": in_step}
+        if not cg_levels:
+            kern[name]["back_to_back_us_per_launch"] = t64 * 1e6
+    else:
+        launches_A = sum(p["it_A_total"] for p in steps_stats) / args.steps
+        kern["k_spmv_A<double,double>"] = {
+            "achieved": by64 / t64 / 1e9, "us_per_launch": t64 * 1e6, "bytes_per_launch": by64,
+            "launches_per_step": launches_A, "est_ms_per_step": launches_A * t64 * 1e3,
+            "traffic": pmc_traffic("spmv_A", "traffic_bytes_fp64") if cube and N == 64 else None,
+            "timing": isolated}
     dom = max(kern, key=lambda k: kern[k]["est_ms_per_step"])
     kd = kern[dom]
     roof = {"bound": "hbm", "kernel": dom, "achieved": kd["achieved"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": kd["achieved"] / HBM_PEAK_GBS, "traffic": kd["traffic"],
             "bytes_per_launch": kd["bytes_per_launch"], "us_per_launch": kd["us_per_launch"],
-            "timing": "HIP events around 50 back-to-back launches on the last Newton system of the timed steps"}
+            "timing": kd["timing"]}
     extra = {"fp64_kernels": kern}
     if r["spmv_A_launches"] > 0:
         t_in = r["spmv_A_ms"] * 1e-3 / r["spmv_A_launches"]
-        extra["spmv_A_in_steps"] = {"us_per_launch": t_in * 1e6, "GB/s": by64 / t_in / 1e9,
+        by_in = cg_spmv_bytes(n, nnzb, 8) if so.a_krylov == V.AK_CG else by64
+        extra["spmv_A_in_steps"] = {"us_per_launch": t_in * 1e6, "GB/s": by_in / t_in / 1e9,
                                     "launches": r["spmv_A_launches"],
                                     "note": "start/stop events of every working launch in the timed steps"}
     first = r["per_step"][0]

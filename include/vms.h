@@ -221,7 +221,8 @@ const char *vms_last_error(const vms_ctx *ctx);
 /* Launch timing of the A-block product, the solver's dominant kernel (a
  * measurement aid for the HBM roofline of its products).  With enable != 0
  * every launch of it -- inside vms_solve_scaled / vms_step (intermediate and
- * inner A-levels) and from vms_spmv(VMS_OP_A) -- carries a start and a stop
+ * inner A-levels; on a CG level the CG product kernel, which fuses the
+ * direction updates into the product) and from vms_spmv(VMS_OP_A) -- carries a start and a stop
  * HIP event that the dispatch itself records (hipExtLaunchKernelGGL: the
  * kernel's own begin and end on the context stream), and the kernel sets a
  * per-launch device flag when it does work (launches enqueued past a level's

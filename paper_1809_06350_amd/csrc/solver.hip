@@ -748,7 +748,7 @@ template <typename T>
 __global__ void __launch_bounds__(VMS_BLOCK)
 k_cg_spmv(int n, int64_t nnzb, int W, const int32_t *__restrict__ col, const T *__restrict__ A,
           const T *__restrict__ z, T *p, T *q, double *ctrl, KOff off, double *ppart, int *iflag, int j, int nbk,
-          double rtol, double atol, int maxit, volatile int32_t *post, int32_t seq) {
+          double rtol, double atol, int maxit, volatile int32_t *post, int32_t seq, int *worked) {
   __shared__ double sm[16];
   __shared__ int done0;
   if (threadIdx.x == 0) done0 = iflag[IF_DONE];
@@ -779,6 +779,7 @@ k_cg_spmv(int n, int64_t nnzb, int W, const int32_t *__restrict__ col, const T *
     if (post) post_flags(iflag, post, seq);
   }
   if (stop) return;
+  if (worked && blockIdx.x == 0 && threadIdx.x == 0) *worked = 1;   // launch timing: this launch did the product
   const bool first = (j == 0);
   const double beta = first ? 0.0 : rz / ctrl[off.scal + 3 + ((j - 1) & 1)];
   constexpr bool NT = sizeof(T) == 8;
@@ -1495,9 +1496,18 @@ int cg_run(vms_ctx *ctx, KLevel<T> &L, const vms_mesh *mesh, const T *Acg, doubl
   const int nbk = (int)gk.x;
   hipLaunchKernelGGL(k_cg_init<T>, gk, bk, 0, s, nn, b, x, r, z, Minv, L.ctrl + L.off.pn, L.ctrl + L.off.pn2,
                      L.iflag);
+  // with launch timing on, the product launches of a CG level are the A-block
+  // products that the context times (kind 0 FP64, 1 FP32)
   auto spmv = [&](int j, volatile int32_t *post, int32_t seq) {
-    hipLaunchKernelGGL(k_cg_spmv<T>, gsp, bl, 0, s, n, (int64_t)mesh->nnzb, (int)mesh->slot_width, mesh->col, Acg,
-                       (const T *)z, p, q, L.ctrl, L.off, ppart, L.iflag, j, nbk, rtol, atol, maxit, post, seq);
+    const vms_timed tm = vms_timer_next(ctx, std::is_same<T, float>::value ? 1 : 0);
+    if (tm.slot >= 0)
+      hipExtLaunchKernelGGL(k_cg_spmv<T>, gsp, bl, 0, s, tm.e0, tm.e1, 0, n, (int64_t)mesh->nnzb,
+                            (int)mesh->slot_width, mesh->col, Acg, (const T *)z, p, q, L.ctrl, L.off, ppart, L.iflag,
+                            j, nbk, rtol, atol, maxit, post, seq, tm.worked);
+    else
+      hipLaunchKernelGGL(k_cg_spmv<T>, gsp, bl, 0, s, n, (int64_t)mesh->nnzb, (int)mesh->slot_width, mesh->col,
+                         Acg, (const T *)z, p, q, L.ctrl, L.off, ppart, L.iflag, j, nbk, rtol, atol, maxit, post, seq,
+                         (int *)nullptr);
   };
   int j = 0;
   spmv(0, nullptr, 0);

@@ -153,7 +153,9 @@ def _gpu_steps(prob, mesh, ti, n_steps, sopts, tol=1e-8, tol_abs=1e-50):
 def test_cube64_time_step_satisfies_oracle_equations(precision):
     mesh, mat, ti = synth.cube_case(64, nu=0.499, n_steps=10)
     prob = _problem(mesh, mat)
-    sopts = V.solver_opts(rtol=1e-8, precision=precision)     # the benchmark configuration
+    # the benchmark configuration: GMRES A-levels in FP64, CG on A itself in the mixed form
+    ak = V.AK_CG if precision == V.MIXED else V.AK_GMRES
+    sopts = V.solver_opts(rtol=1e-8, precision=precision, a_krylov=ak, cg_symmetrise=0)
     states = _gpu_steps(prob, mesh, ti, 1, sopts)
     ratio = _oracle_residual_ratio(mesh, mat, ti, 0, states[0], states[1])
     print(f"[cube64] precision={precision} oracle |R|/|R0| = {ratio:.3e}", flush=True)

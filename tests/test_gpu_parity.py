@@ -330,6 +330,24 @@ def test_cg_levels_solve_matches_lu(problems, name, precision, a_krylov, sym):
     assert stats["n_I_solves"] > 0 and stats["it_I"] > 0
 
 
+@pytest.mark.parametrize("precision", [V.FP64, V.MIXED])
+def test_cg_product_launch_timing(problems, precision):
+    """With launch timing on, every CG product launch that does the product is
+    timed and counted: one per CG iteration of the two A-levels, none for the
+    launches that only find the level converged."""
+    prob, mesh, mat, ti, disc = problems("cube-nu0499")
+    st, K, rhs, Ks, rs, W, _ = _prepared(prob, mesh, ti, disc, 84, mirror32=(precision == V.MIXED))
+    opts = V.solver_opts(rtol=1e-8, precision=precision, a_krylov=V.AK_CG, cg_symmetrise=0)
+    prob.set_timing(True)
+    x, stats = prob.solve_scaled(K, rhs, opts)
+    ms, cnt = prob.kernel_time(fp32=precision == V.MIXED)
+    other = prob.kernel_time(fp32=precision != V.MIXED)
+    prob.set_timing(False)
+    print(f"[timing] precision={precision} launches={cnt} ms={ms:.3f} stats={stats}", flush=True)
+    assert cnt == stats["it_A"] + stats["it_I"] > 0
+    assert ms > 0.0 and other == (0.0, 0)
+
+
 @pytest.mark.parametrize("a_krylov,sym", [(V.AK_CG_INNER, 1), (V.AK_CG, 1), (V.AK_CG, 0)])
 def test_cg_exact_on_symmetric_A(problems, a_krylov, sym):
     """With zero accelerations A is symmetric, so (A + A^T)/2 = A: CG solved
