@@ -292,6 +292,8 @@ def main():
     ap.add_argument("--shat-ratio", type=float, default=20.0)
     ap.add_argument("--shat-method", default="cg", choices=["chebyshev", "cg"],
                     help="S^ preconditioner of the Schur solve: Chebyshev polynomial or CG steps (--shat-degree)")
+    ap.add_argument("--outer-tol", type=float, default=1e-8,
+                    help="relative tolerance of the outer FGMRES (the Newton tolerance stays 1e-8)")
     ap.add_argument("--fp64-tol", default="3e-5,1e-5,1e-4",
                     help="intermediate A, Schur and inner tolerances of the FP64 form")
     ap.add_argument("--mixed-tol", default="3e-5,1e-5,1e-4",
@@ -333,13 +335,14 @@ def main():
     if cube:
         dt = args.dt or 1e-3
         mesh, mat, ti = synth.cube_case(N, nu=args.nu, n_steps=10, dt=dt)
-        wl = f"cube{N}^3 Kuhn tets, nu={args.nu}, neo-Hookean, dt={dt:g}, Newton/FGMRES 1e-8"
+        wl = f"cube{N}^3 Kuhn tets, nu={args.nu}, neo-Hookean, dt={dt:g}, Newton 1e-8, FGMRES {args.outer_tol:g}"
     else:
         dt = args.dt or 1e-5
         mesh, mat, ti = synth.strip_case(N, kd=args.kd, fibre_deg=args.fibre_deg, dt=dt)
         nx, ny, nz = synth.strip_dims(N)
         wl = (f"tensile strip (eighth) 1/dx={N}: {nx}x{ny}x{nz} hexes x 6 Kuhn tets, incompressible HGO "
-              f"k_d={args.kd}, phi={args.fibre_deg} deg, 2 N over 100 s, dt={dt:g}, Newton/FGMRES 1e-8 "
+              f"k_d={args.kd}, phi={args.fibre_deg} deg, 2 N over 100 s, dt={dt:g}, Newton 1e-8, "
+              f"FGMRES {args.outer_tol:g} "
               f"(Newton also ends below {args.tol_abs if args.tol_abs is not None else 1e-15:g} absolute)")
         args.no_cpu_baseline = True
     log(f"{mesh.name}: nodes={mesh.n_nodes} tets={mesh.n_tets}")
@@ -365,10 +368,10 @@ def main():
           "simple": V.PC_SIMPLE}[args.precond]
     ss = {"krylov": V.SCHUR_KRYLOV, "shat": V.SCHUR_SHAT}[args.schur_step]
     forms = {
-        "fp64": V.solver_opts(rtol=1e-8, rtol_A=ft[0], rtol_S=ft[1], rtol_I=ft[2], shat_degree=args.shat_degree,
+        "fp64": V.solver_opts(rtol=args.outer_tol, rtol_A=ft[0], rtol_S=ft[1], rtol_I=ft[2], shat_degree=args.shat_degree,
                               shat_ratio=args.shat_ratio, orth=orth, a_krylov=fk, cg_symmetrise=fs,
                               shat_method=sm, precond=pc, schur_solve=ss),
-        "mixed": V.solver_opts(rtol=1e-8, rtol_A=mt[0], rtol_S=mt[1], rtol_I=mt[2], precision=V.MIXED,
+        "mixed": V.solver_opts(rtol=args.outer_tol, rtol_A=mt[0], rtol_S=mt[1], rtol_I=mt[2], precision=V.MIXED,
                                shat_degree=args.shat_degree, shat_ratio=args.shat_ratio, orth=orth, a_krylov=mk,
                                cg_symmetrise=ms, shat_method=sm, precond=pc, schur_solve=ss),
     }
@@ -488,6 +491,7 @@ def main():
                       "shat_degree": args.shat_degree, "shat_ratio": args.shat_ratio,
                       "shat_method": args.shat_method, "orth": args.orth, "precond": args.precond,
                       "schur_step": args.schur_step,
+                      "tolerances": {"outer": args.outer_tol, "fp64_A_S_I": ft, "mixed_A_S_I": mt},
                       "a_krylov": {"fp64": args.fp64_a_krylov, "mixed": args.mixed_a_krylov},
                       "parallelism": "single GPU"},
            "roofline": roof}
