@@ -313,6 +313,9 @@ def main():
                          "factorizations, or SIMPLE")
     ap.add_argument("--schur-step", default="krylov", choices=["krylov", "shat"],
                     help="Schur step: Krylov solve to the Schur tolerance, or one S^ preconditioner application")
+    ap.add_argument("--relax-inner", default="off", choices=["on", "off"],
+                    help="relax the inner tolerance of the Schur products as the Schur level converges "
+                         "(relax_inner; off, as in the paper, by default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-timing", action="store_true",
                     help="also event-time every A-block product launch inside the timed steps (each launch then "
@@ -361,6 +364,7 @@ def main():
            "cg-inner-sym": (V.AK_CG_INNER, 1), "cg-sym": (V.AK_CG, 1)}
     if args.fp64_a_krylov is None:
         args.fp64_a_krylov = "gmres" if cube else "cg"
+    relax = int(args.relax_inner == "on")
     fk, fs = akm[args.fp64_a_krylov]
     mk, ms = akm[args.mixed_a_krylov]
     sm = {"chebyshev": V.SHAT_CHEBYSHEV, "cg": V.SHAT_CG}[args.shat_method]
@@ -370,10 +374,10 @@ def main():
     forms = {
         "fp64": V.solver_opts(rtol=args.outer_tol, rtol_A=ft[0], rtol_S=ft[1], rtol_I=ft[2], shat_degree=args.shat_degree,
                               shat_ratio=args.shat_ratio, orth=orth, a_krylov=fk, cg_symmetrise=fs,
-                              shat_method=sm, precond=pc, schur_solve=ss),
+                              shat_method=sm, precond=pc, schur_solve=ss, relax_inner=relax),
         "mixed": V.solver_opts(rtol=args.outer_tol, rtol_A=mt[0], rtol_S=mt[1], rtol_I=mt[2], precision=V.MIXED,
                                shat_degree=args.shat_degree, shat_ratio=args.shat_ratio, orth=orth, a_krylov=mk,
-                               cg_symmetrise=ms, shat_method=sm, precond=pc, schur_solve=ss),
+                               cg_symmetrise=ms, shat_method=sm, precond=pc, schur_solve=ss, relax_inner=relax),
     }
     results = {}
     for name in args.forms.split(","):
@@ -491,7 +495,8 @@ def main():
                       "shat_degree": args.shat_degree, "shat_ratio": args.shat_ratio,
                       "shat_method": args.shat_method, "orth": args.orth, "precond": args.precond,
                       "schur_step": args.schur_step,
-                      "tolerances": {"outer": args.outer_tol, "fp64_A_S_I": ft, "mixed_A_S_I": mt},
+                      "tolerances": {"outer": args.outer_tol, "fp64_A_S_I": ft, "mixed_A_S_I": mt,
+                                     "relax_inner": relax},
                       "a_krylov": {"fp64": args.fp64_a_krylov, "mixed": args.mixed_a_krylov},
                       "parallelism": "single GPU"},
            "roofline": roof}

@@ -180,6 +180,10 @@ typedef struct {
   int32_t cg_symmetrise; /* CG levels: 1 = on (A + A^T)/2, 0 = on A */
   int32_t shat_method;   /* VMS_SHAT_*: Chebyshev polynomial or CG steps on S^ (shat_degree > 0) */
   int32_t schur_solve;   /* VMS_SCHUR_*: Krylov solve of the Schur step, or one S^ preconditioner application */
+  int32_t relax_inner;   /* 1: the inner A-solve of the Schur product at Schur iteration k stops at
+                            rtol_I * ||r_0|| / ||r_k|| of the Schur level (at most 0.01), the
+                            relaxation of inexact Krylov methods (Simoncini and Szyld 2003);
+                            0: at rtol_I throughout, as in the paper */
 } vms_solver_opts;
 
 typedef struct {

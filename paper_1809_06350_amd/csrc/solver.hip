@@ -138,19 +138,33 @@ __device__ __forceinline__ void scale_and_precond(int64_t nvec, const T *w, doub
   }
 }
 
+// Relative tolerance of a level: rtol, or -- for the inner A-solve of a Schur
+// product with relaxation on (relax = the Schur level's control scalars: its
+// initial residual norm and current estimate) -- rtol * ||r_0|| / ||r_k|| of
+// the Schur level, at most max(rtol, RELAX_MAX).
+#ifndef RELAX_MAX
+#define RELAX_MAX 1e-2
+#endif
+__device__ __forceinline__ double relaxed_rtol(double rtol, const double *relax) {
+  if (!relax) return rtol;
+  const double r0 = relax[0], rk = relax[2];
+  if (!(rk > 0.0) || !(r0 > rk)) return rtol;
+  return fmin(rtol * (r0 / rk), fmax(rtol, RELAX_MAX));
+}
+
 // Start of a level: beta = ||b|| from the k_norm_part partials (every
 // workgroup reduces them in the same order), V_0 = b / beta, Z_0 = M^-1 V_0;
 // workgroup 0 also sets the tolerance, g_0 and the level flags.
 template <typename T>
 __global__ void __launch_bounds__(VMS_BLOCK)
 k_kinit(int64_t nvec, const T *__restrict__ b, T *V0, T *Z0, double *ctrl, KOff off, int *iflag, int nb,
-        double rtol, double atol, int pc, const T *pcd) {
+        double rtol, double atol, int pc, const T *pcd, const double *relax) {
   __shared__ double sm[4];
   const double beta = sqrt(sum_partials1(ctrl + off.part, nb, sm));
   const bool done = !isfinite(beta) || beta == 0.0 || beta <= atol;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     ctrl[off.scal + 0] = beta;
-    ctrl[off.scal + 1] = fmax(rtol * beta, atol);
+    ctrl[off.scal + 1] = fmax(relaxed_rtol(rtol, relax) * beta, atol);
     ctrl[off.scal + 2] = beta;
     ctrl[off.g] = beta;
     iflag[IF_ITS] = 0;
@@ -748,7 +762,8 @@ template <typename T>
 __global__ void __launch_bounds__(VMS_BLOCK)
 k_cg_spmv(int n, int64_t nnzb, int W, const int32_t *__restrict__ col, const T *__restrict__ A,
           const T *__restrict__ z, T *p, T *q, double *ctrl, KOff off, double *ppart, int *iflag, int j, int nbk,
-          double rtol, double atol, int maxit, volatile int32_t *post, int32_t seq, int *worked) {
+          double rtol, double atol, int maxit, volatile int32_t *post, int32_t seq, int *worked,
+          const double *relax) {
   __shared__ double sm[16];
   __shared__ int done0;
   if (threadIdx.x == 0) done0 = iflag[IF_DONE];
@@ -760,7 +775,7 @@ k_cg_spmv(int n, int64_t nnzb, int W, const int32_t *__restrict__ col, const T *
   const double rz = cg_sum_partials(ctrl + off.pn, nbk, sm);
   const double rr = cg_sum_partials(ctrl + off.pn2, nbk, sm);
   const double rn = sqrt(rr);
-  const double tol = (j == 0) ? fmax(rtol * rn, atol) : ctrl[off.scal + 1];
+  const double tol = (j == 0) ? fmax(relaxed_rtol(rtol, relax) * rn, atol) : ctrl[off.scal + 1];
   const bool bad = !isfinite(rr) || !isfinite(rz);
   const bool conv = !bad && rn <= tol;
   const bool stop = bad || conv || j >= maxit;
@@ -1430,12 +1445,14 @@ int orth_level(vms_ctx *ctx, KLevel<T> &L, int j, int maxit, int mode, int pc, c
 // level flags (kernels past convergence return at once).
 template <typename T, typename OpF>
 int gmres_run(vms_ctx *ctx, KLevel<T> &L, const T *b, T *x, double rtol, double atol, int maxit, int orth, int pc,
-              const T *pcd, bool sync_each, int &est, OpF op, int &its_out, int &status_out) {
+              const T *pcd, bool sync_each, int &est, OpF op, int &its_out, int &status_out,
+              const double *relax = nullptr) {
   hipStream_t s = ctx->stream;
   maxit = std::min(maxit, L.m);
   const dim3 gr(L.nb), bl(VMS_BLOCK);
   hipLaunchKernelGGL(k_norm_part<T>, gr, bl, 0, s, L.nvec, b, L.ctrl + L.off.part, (const int *)nullptr);
-  hipLaunchKernelGGL(k_kinit<T>, gr, bl, 0, s, L.nvec, b, L.V, L.Z, L.ctrl, L.off, L.iflag, L.nb, rtol, atol, pc, pcd);
+  hipLaunchKernelGGL(k_kinit<T>, gr, bl, 0, s, L.nvec, b, L.V, L.Z, L.ctrl, L.off, L.iflag, L.nb, rtol, atol, pc, pcd,
+                     relax);
   VMS_LAUNCH_CHECK(ctx);
   int j = 0, rc;
   bool done = false, read = false;
@@ -1485,7 +1502,8 @@ int gmres_run(vms_ctx *ctx, KLevel<T> &L, const T *b, T *x, double rtol, double 
 // flags that the last product kernel of a batch posts.
 template <typename T>
 int cg_run(vms_ctx *ctx, KLevel<T> &L, const vms_mesh *mesh, const T *Acg, double *ppart, const T *b, T *x,
-           double rtol, double atol, int maxit, const T *Minv, int &est, int &its_out, int &status_out) {
+           double rtol, double atol, int maxit, const T *Minv, int &est, int &its_out, int &status_out,
+           const double *relax = nullptr) {
   hipStream_t s = ctx->stream;
   const int n = mesh->n_nodes;
   const int64_t nn = n;
@@ -1503,11 +1521,11 @@ int cg_run(vms_ctx *ctx, KLevel<T> &L, const vms_mesh *mesh, const T *Acg, doubl
     if (tm.slot >= 0)
       hipExtLaunchKernelGGL(k_cg_spmv<T>, gsp, bl, 0, s, tm.e0, tm.e1, 0, n, (int64_t)mesh->nnzb,
                             (int)mesh->slot_width, mesh->col, Acg, (const T *)z, p, q, L.ctrl, L.off, ppart, L.iflag,
-                            j, nbk, rtol, atol, maxit, post, seq, tm.worked);
+                            j, nbk, rtol, atol, maxit, post, seq, tm.worked, relax);
     else
       hipLaunchKernelGGL(k_cg_spmv<T>, gsp, bl, 0, s, n, (int64_t)mesh->nnzb, (int)mesh->slot_width, mesh->col,
                          Acg, (const T *)z, p, q, L.ctrl, L.off, ppart, L.iflag, j, nbk, rtol, atol, maxit, post, seq,
-                         (int *)nullptr);
+                         (int *)nullptr, relax);
   };
   int j = 0;
   spmv(0, nullptr, 0);
@@ -1663,9 +1681,13 @@ struct Nested {
     };
     int st = 0;
     const bool cg = inner ? (o->a_krylov != VMS_AK_GMRES) : (o->a_krylov == VMS_AK_CG);
+    // the inner solve of a Schur product (called only from the Schur level's
+    // operator) may relax its tolerance with the Schur level's progress
+    const double *relax = (inner && o->relax_inner) ? LS.ctrl + LS.off.scal : nullptr;
     int rc = cg ? cg_run<T>(ctx, LA, mesh, o->cg_symmetrise ? (const T *)As : A, cgpart, b, x, rtol, atol, maxit,
-                            Minv, est, its, st)
-                : gmres_run<T>(ctx, LA, b, x, rtol, atol, maxit, o->orth, PC_BJ33, Minv, false, est, op, its, st);
+                            Minv, est, its, st, relax)
+                : gmres_run<T>(ctx, LA, b, x, rtol, atol, maxit, o->orth, PC_BJ33, Minv, false, est, op, its, st,
+                               relax);
     if (inner) { stats->n_I_solves++; stats->it_I += its; }
     else { stats->n_A_solves++; stats->it_A += its; }
     return rc;
@@ -1845,6 +1867,8 @@ int check_opts(vms_ctx *ctx, const vms_solver_opts *o) {
     return vms_set_error(ctx, VMS_ERR_ARG, "unknown S^ preconditioner method");
   if (o->schur_solve != VMS_SCHUR_KRYLOV && o->schur_solve != VMS_SCHUR_SHAT)
     return vms_set_error(ctx, VMS_ERR_ARG, "unknown Schur step");
+  if (o->relax_inner != 0 && o->relax_inner != 1)
+    return vms_set_error(ctx, VMS_ERR_ARG, "relax_inner must be 0 or 1");
   return VMS_OK;
 }
 

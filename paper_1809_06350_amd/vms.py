@@ -39,10 +39,10 @@ def solver_opts(rtol=1e-8, atol=1e-50, maxit=200, rtol_A=3e-5, atol_A=1e-50, max
                 rtol_S=1e-5, atol_S=1e-50, maxit_S=200, rtol_I=1e-4, atol_I=1e-50, maxit_I=500,
                 precond=PC_LDU, precision=FP64, orth=ORTH_CGS1, shat_degree=16,
                 shat_ratio=20.0, a_krylov=AK_GMRES, cg_symmetrise=1, shat_method=SHAT_CG,
-                schur_solve=SCHUR_KRYLOV) -> L.SolverOpts:
+                schur_solve=SCHUR_KRYLOV, relax_inner=0) -> L.SolverOpts:
     return L.SolverOpts(rtol, atol, maxit, rtol_A, atol_A, maxit_A, rtol_S, atol_S, maxit_S,
                         rtol_I, atol_I, maxit_I, precond, precision, orth, shat_degree, shat_ratio, a_krylov,
-                        cg_symmetrise, shat_method, schur_solve)
+                        cg_symmetrise, shat_method, schur_solve, relax_inner)
 
 
 def newton_opts(tol_R=1e-8, tol_A=1e-50, l_max=20, rk_corr=1, eps_diag=1e-15) -> L.NewtonOpts:

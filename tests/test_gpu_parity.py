@@ -330,6 +330,29 @@ def test_cg_levels_solve_matches_lu(problems, name, precision, a_krylov, sym):
     assert stats["n_I_solves"] > 0 and stats["it_I"] > 0
 
 
+@pytest.mark.parametrize("name", ["cube-nu0499", "strip-hgo"])
+@pytest.mark.parametrize("precision,a_krylov", [(V.FP64, V.AK_GMRES), (V.MIXED, V.AK_CG)])
+def test_relaxed_inner_tolerance_solve_matches_lu(problems, name, precision, a_krylov):
+    """With the inner tolerance relaxed as the Schur level converges, the
+    nested preconditioner changes but the outer FGMRES still reaches the
+    requested residual of the oracle's system and its LU solution."""
+    import scipy.sparse.linalg as spla
+    prob, mesh, mat, ti, disc = problems(name)
+    st, K, rhs, Ks, rs, W, _ = _prepared(prob, mesh, ti, disc, 85, mirror32=(precision == V.MIXED))
+    res = {}
+    for relax in (0, 1):   # relaxation off (the paper's fixed inner tolerance) and on
+        opts = V.solver_opts(rtol=1e-8, rtol_I=1e-4, precision=precision, a_krylov=a_krylov, cg_symmetrise=0,
+                             relax_inner=relax)
+        x, stats = prob.solve_scaled(K, rhs, opts)
+        xg = x.cpu().numpy().ravel()
+        print(f"[relax] {name} precision={precision} relax={relax} stats={stats}", flush=True)
+        assert np.linalg.norm(Ks @ xg - rs) <= 2e-8 * np.linalg.norm(rs)
+        xo = spla.splu(Ks.tocsc()).solve(rs)
+        assert np.linalg.norm(xg - xo) <= 1e-5 * np.linalg.norm(xo)
+        res[relax] = stats
+    assert res[0]["status"] == 0 and res[1]["status"] == 0
+
+
 @pytest.mark.parametrize("precision", [V.FP64, V.MIXED])
 def test_cg_product_launch_timing(problems, precision):
     """With launch timing on, every CG product launch that does the product is
