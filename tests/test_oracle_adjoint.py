@@ -13,10 +13,14 @@ def _case(name):
         mesh, mat, ti = synth.cube_case(2, nu=0.45, n_steps=2)
         sel = np.isclose(mesh.X[:, 2], 1.0)
         params = (0, 1)
-    else:
+    elif name == "tube":
         mesh, mat, ti = synth.tube_case(1, 8, 2, dt=0.05, n_steps=20)
         r = np.hypot(mesh.X[:, 0], mesh.X[:, 1])
         sel = np.isclose(r, 1.2)
+        params = (0, 2, 3, 4)
+    else:   # the eighth-strip: in-plane fibres at +-phi, dispersion, load ramped over 0.1 ms
+        mesh, mat, ti = synth.strip_case(dims=(5, 3, 2), dt=1e-5, t_ramp=1e-4)
+        sel = np.isclose(mesh.X[:, 0], 5e-3, rtol=0.0, atol=1e-12)
         params = (0, 2, 3, 4)
     return mesh, mat, ti, sel, params
 
@@ -27,7 +31,7 @@ def _J(mesh, mat, ti, theta, sel, target, n_steps):
     return AD.objective(states[-1]["u"], sel, target)[0]
 
 
-@pytest.mark.parametrize("name", ["cube", "tube"])
+@pytest.mark.parametrize("name", ["cube", "tube", "strip"])
 def test_adjoint_gradient_matches_central_differences(name):
     mesh, mat, ti, sel, params = _case(name)
     n_steps = 2
