@@ -256,10 +256,16 @@ def spmv_only(prob, mesh, ti, reps):
     torch.cuda.synchronize()
     t64 = time_spmv(prob, K32, V.OP_A, x, False)
     t32 = time_spmv(prob, K32, V.OP_A, xf, True)
+    # the HBM rate a plain streaming kernel reaches on this device (context for the roofline fractions)
+    tcal = time_launches(lambda: torch.mul(src, 1.0, out=dst))
+    acc = torch.empty(1, dtype=torch.float64, device="cuda:0")
+    tsum = time_launches(lambda: torch.sum(src, dim=0, out=acc[0]))
     nzs = shat_real_entries(prob)
     nz = int(prob.host["row_len"].sum())
     print(json.dumps({"spmv_only": True, "n": n, "nnzb": nz, "nnzb_slots": prob.nnzb,
                       "calibration_bytes_each_way": src.numel() * 8,
+                      "calibration_us": tcal * 1e6, "copy_GBps": 2 * src.numel() * 8 / tcal / 1e9,
+                      "read_only_sum_us": tsum * 1e6, "read_only_GBps": src.numel() * 8 / tsum / 1e9,
                       "bytes_fp64": spmv_A_bytes(n, nz, 8), "us_fp64": t64 * 1e6,
                       "bytes_fp32": spmv_A_bytes(n, nz, 4), "us_fp32": t32 * 1e6,
                       "shat_nnz": nzs, "shat_bytes_fp64": shat_bytes(n, nzs, 8, shat_idx_bytes(prob)),
@@ -450,6 +456,17 @@ def main():
             "frac": kd["achieved"] / HBM_PEAK_GBS, "traffic": kd["traffic"],
             "bytes_per_launch": kd["bytes_per_launch"], "us_per_launch": kd["us_per_launch"],
             "timing": kd["timing"]}
+    # context: the rate of a plain streaming kernel on this device (1 GiB -> 1 GiB float64 copy-scale,
+    # larger than the Infinity Cache), and the dominant kernel's measured HBM traffic per launch over
+    # its duration against it
+    src = torch.ones(1 << 27, dtype=torch.float64, device="cuda:0")
+    dst = torch.empty_like(src)
+    tcopy = time_launches(lambda: torch.mul(src, 1.0, out=dst))
+    roof["copy_GBps"] = 2 * src.numel() * 8 / tcopy / 1e9
+    if kd["traffic"]:
+        roof["traffic_GBps"] = kd["traffic"] / (kd["us_per_launch"] * 1e-6) / 1e9
+        roof["traffic_frac_of_copy"] = roof["traffic_GBps"] / roof["copy_GBps"]
+    del src, dst
     extra = {"fp64_kernels": kern}
     if r["spmv_A_launches"] > 0:
         t_in = r["spmv_A_ms"] * 1e-3 / r["spmv_A_launches"]
