@@ -104,7 +104,7 @@ enum { VMS_AK_GMRES = 0, VMS_AK_CG_INNER = 1, VMS_AK_CG = 2 };
  * (a fixed linear operator), or k steps of diag(S^)-preconditioned CG on S^
  * (the Krylov-optimal degree-k polynomial for each vector; nonlinear, which
  * the flexible Schur-level GMRES allows). */
-enum { VMS_SHAT_CHEBYSHEV = 0, VMS_SHAT_CG = 1 };
+enum { VMS_SHAT_CHEBYSHEV = 0, VMS_SHAT_CG = 1, VMS_SHAT_NONE = 2 };   /* NONE: no S^ part (schur_mass > 0) */
 
 typedef struct vms_ctx vms_ctx;
 
@@ -184,6 +184,14 @@ typedef struct {
                             rtol_I * ||r_0|| / ||r_k|| of the Schur level (at most 0.01), the
                             relaxation of inexact Krylov methods (Simoncini and Szyld 2003);
                             0: at rtol_I throughout, as in the paper */
+  double schur_mass;     /* w >= 0: the Schur solve's right preconditioner gains the term
+                            w (c M_p)^-1, M_p the lumped pressure mass matrix of the reference
+                            configuration in the scaled variables and c = 1^T S 1 / 1^T M_p 1
+                            (one Schur product per solve).  A scaled mass matrix approximates S
+                            when A is stiffness-dominated (section 1); with shat_method
+                            VMS_SHAT_NONE it is the whole preconditioner.  Krylov Schur step of
+                            P_SCR only (precond != SIMPLE, schur_solve = VMS_SCHUR_KRYLOV).
+                            0: off, as in the paper */
 } vms_solver_opts;
 
 typedef struct {

@@ -47,7 +47,7 @@ class SolverOpts(C.Structure):
                 ("precond", C.c_int32), ("precision", C.c_int32), ("orth", C.c_int32),
                 ("shat_degree", C.c_int32), ("shat_ratio", C.c_double), ("a_krylov", C.c_int32),
                 ("cg_symmetrise", C.c_int32), ("shat_method", C.c_int32),
-                ("schur_solve", C.c_int32), ("relax_inner", C.c_int32)]
+                ("schur_solve", C.c_int32), ("relax_inner", C.c_int32), ("schur_mass", C.c_double)]
 
 
 class SolveStats(C.Structure):

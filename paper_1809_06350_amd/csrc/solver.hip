@@ -1302,6 +1302,86 @@ __global__ void k_diag_scale(int n, const T *d, const T *v, T *z) {
   if (i < n) z[i] = (T)(ld(d, i) * ld(v, i));
 }
 
+// z += d .* v
+template <typename T>
+__global__ void k_diag_axpy(int n, const T *d, const T *v, T *z) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) z[i] = (T)(ld(z, i) + ld(d, i) * ld(v, i));
+}
+
+// Lumped pressure mass of node i in the reference configuration -- the sum of
+// vol_e / 4 over the elements at i, read from the (element, local node)
+// incidences that the contribution list of i's diagonal block holds -- in the
+// scaled variables: mlw_i = W_p,i^2 m_i.  one_i = 1 on free pressure dofs, 0
+// on prescribed ones.
+template <typename T>
+__global__ void k_mass_lumped(int n, const int32_t *__restrict__ diag_pos, const int32_t *__restrict__ ptr,
+                              const int32_t *__restrict__ src, const double *__restrict__ X,
+                              const int32_t *__restrict__ tets, const uint8_t *__restrict__ dir,
+                              const double *__restrict__ W, double *mlw, T *one) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int blk = diag_pos[i];
+  double m = 0.0;
+  for (int k = ptr[blk]; k < ptr[blk + 1]; ++k) {
+    const int64_t e = src[k] >> 4;
+    const int32_t *t = tets + 4 * e;
+    const double *x0 = X + 3 * (int64_t)t[0], *x1 = X + 3 * (int64_t)t[1], *x2 = X + 3 * (int64_t)t[2],
+                 *x3 = X + 3 * (int64_t)t[3];
+    const double a0 = x1[0] - x0[0], a1 = x1[1] - x0[1], a2 = x1[2] - x0[2];
+    const double b0 = x2[0] - x0[0], b1 = x2[1] - x0[1], b2 = x2[2] - x0[2];
+    const double c0 = x3[0] - x0[0], c1 = x3[1] - x0[1], c2 = x3[2] - x0[2];
+    const double det = a0 * (b1 * c2 - b2 * c1) - a1 * (b0 * c2 - b2 * c0) + a2 * (b0 * c1 - b1 * c0);
+    m += fabs(det) / 24.0;   // vol_e / 4
+  }
+  const double w = W[4 * (int64_t)i + 3];
+  const bool fixed = dir[4 * (int64_t)i + 3] != 0;
+  mlw[i] = w * w * m;
+  one[i] = (T)(fixed ? 0.0 : 1.0);
+}
+
+// One workgroup: sums[0] = sum of (S 1)_i and sums[1] = sum of mlw_i over the
+// free pressure dofs, each thread in a fixed order, then a fixed block order.
+template <typename T>
+__global__ void __launch_bounds__(1024) k_mass_sums(int n, const T *__restrict__ s1, const double *__restrict__ mlw,
+                                                    const uint8_t *__restrict__ dir, double *sums) {
+  __shared__ double sm[2][16];
+  double a = 0.0, b = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    if (dir[4 * (int64_t)i + 3]) continue;
+    a += ld(s1, i);
+    b += mlw[i];
+  }
+  a = wave_sum(a);
+  b = wave_sum(b);
+  const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  if ((threadIdx.x & 63) == 0) { sm[0][w] = a; sm[1][w] = b; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double ta = 0.0, tb = 0.0;
+    for (int q = 0; q < nw; ++q) { ta += sm[0][q]; tb += sm[1][q]; }
+    sums[0] = ta;
+    sums[1] = tb;
+  }
+}
+
+// minv_i = w / (c mlw_i) with c = sums[0] / sums[1] (the Rayleigh quotient of
+// S and the scaled lumped mass on the constant vector; c = 1 if it is not
+// positive), w on prescribed pressure dofs (their S row is the identity);
+// with pdiag, also pdiag = minv (+ diag(S^)^-1 when sdinv is given).
+template <typename T>
+__global__ void k_mass_inv(int n, const double *__restrict__ mlw, const double *__restrict__ sums,
+                           const uint8_t *__restrict__ dir, double w, const T *sdinv, T *minv, T *pdiag) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double c = sums[0] / sums[1];
+  if (!(c > 0.0) || !isfinite(c)) c = 1.0;
+  const double m = mlw[i];
+  const double v = (dir[4 * (int64_t)i + 3] || !(m > 0.0)) ? w : w / (c * m);
+  minv[i] = (T)v;
+  if (pdiag) pdiag[i] = (T)(v + (sdinv ? ld(sdinv, i) : 0.0));
+}
+
 // diag(A)^-1: the diagonal entries of the 3x3 diagonal blocks (1 where zero)
 template <typename T>
 __global__ void k_diagA_inv(int n, const int32_t *diag_pos, int64_t nnzb, const double *A, T *dAinv) {
@@ -1570,6 +1650,9 @@ struct Nested {
   const T *A, *B, *C, *D;  // scaled blocks in the level precision
   KLevel<T> LA, LS;
   T *rv, *rp, *xh, *xp, *xv, *xbar, *xt, *Minv, *sdinv;
+  // pressure-mass term of the Schur preconditioner (schur_mass > 0)
+  double *mlw = nullptr, *msum = nullptr;
+  T *minv = nullptr, *pdiag = nullptr, *mone = nullptr, *ms1 = nullptr;
   T *Shat, *Shd, *cr, *cd0, *cd1, *px, *py;  // S^ (off-diagonal, diagonal); Chebyshev / power-iteration vectors
   T *As = nullptr;                            // (A + A^T)/2 for the CG levels (when symmetrised)
   double *cgpart = nullptr;                   // partials of <p, A p> of the CG product kernel
@@ -1611,6 +1694,14 @@ struct Nested {
     if (o_->a_krylov != VMS_AK_GMRES) {
       cgpart = cv.take<double>(cg_spmv_blocks(m_->n_nodes));
       if (o_->cg_symmetrise) As = cv.take<T>(9 * m_->nnzb);
+    }
+    if (o_->schur_mass > 0.0) {
+      mlw = cv.take<double>(nn);
+      msum = cv.take<double>(4);
+      minv = cv.take<T>(nn);
+      pdiag = cv.take<T>(nn);
+      mone = cv.take<T>(nn);
+      ms1 = cv.take<T>(nn);
     }
   }
 
@@ -1670,7 +1761,7 @@ struct Nested {
   }
 
   // x = A^-1 b by GMRES with block-Jacobi (intermediate or inner level)
-  int solve_A(const T *b, T *x, bool inner) {
+  int solve_A(const T *b, T *x, bool inner, bool may_relax = true) {
     int its = 0;
     const double rtol = inner ? o->rtol_I : o->rtol_A, atol = inner ? o->atol_I : o->atol_A;
     const int maxit = inner ? o->maxit_I : o->maxit_A;
@@ -1683,7 +1774,7 @@ struct Nested {
     const bool cg = inner ? (o->a_krylov != VMS_AK_GMRES) : (o->a_krylov == VMS_AK_CG);
     // the inner solve of a Schur product (called only from the Schur level's
     // operator) may relax its tolerance with the Schur level's progress
-    const double *relax = (inner && o->relax_inner) ? LS.ctrl + LS.off.scal : nullptr;
+    const double *relax = (inner && may_relax && o->relax_inner) ? LS.ctrl + LS.off.scal : nullptr;
     int rc = cg ? cg_run<T>(ctx, LA, mesh, o->cg_symmetrise ? (const T *)As : A, cgpart, b, x, rtol, atol, maxit,
                             Minv, est, its, st, relax)
                 : gmres_run<T>(ctx, LA, b, x, rtol, atol, maxit, o->orth, PC_BJ33, Minv, false, est, op, its, st,
@@ -1696,12 +1787,19 @@ struct Nested {
   // x_p = S^-1 b by GMRES with the matrix-free Schur product (Algorithm 2)
   int solve_S(const T *b, T *x) {
     int its = 0;
-    const bool cheb = o->shat_degree > 0;
+    // right preconditioner: CG steps or a Chebyshev polynomial on S^ (poly), else
+    // diag(S^)^-1; plus the pressure-mass term; a diagonal one is applied inside
+    // the level's normalisation
+    const bool poly = o->shat_method != VMS_SHAT_NONE && o->shat_degree > 0;
+    const bool mass = o->schur_mass > 0.0;
     auto op = [&](int j) -> int {
       T *z = LS.Z + (int64_t)j * LS.nvec;
-      if (cheb) {
-        if (o->shat_method == VMS_SHAT_CG) scg_apply(LS.V + (int64_t)j * LS.nvec, z);
-        else cheb_apply(LS.V + (int64_t)j * LS.nvec, z);
+      if (poly) {
+        const T *v = LS.V + (int64_t)j * LS.nvec;
+        if (o->shat_method == VMS_SHAT_CG) scg_apply(v, z);
+        else cheb_apply(v, z);
+        if (mass)
+          hipLaunchKernelGGL(k_diag_axpy<T>, dim3(grid1(n)), dim3(VMS_BLOCK), 0, ctx->stream, n, (const T *)minv, v, z);
       }
       // x-bar = B z
       hipLaunchKernelGGL((k_spmv_B<T, T>), dim3(spmv_grid(n)), dim3(VMS_BLOCK), 0, ctx->stream, n, nnzb,
@@ -1716,8 +1814,8 @@ struct Nested {
       return VMS_OK;
     };
     int st = 0;
-    int rc = gmres_run<T>(ctx, LS, b, x, o->rtol_S, o->atol_S, o->maxit_S, o->orth, cheb ? PC_NONE : PC_DIAG, sdinv,
-                          true, ctx->est_S, op, its, st);
+    int rc = gmres_run<T>(ctx, LS, b, x, o->rtol_S, o->atol_S, o->maxit_S, o->orth, poly ? PC_NONE : PC_DIAG,
+                          mass ? (const T *)pdiag : (const T *)sdinv, true, ctx->est_S, op, its, st);
     stats->n_S_solves++;
     stats->it_S += its;
     return rc;
@@ -1822,6 +1920,25 @@ struct Nested {
       lam = LS.ctrl + LS.off.scal + 5;
       power_lmax(12);
     }
+    if (o->schur_mass > 0.0) {
+      hipStream_t s = ctx->stream;
+      const dim3 g1(grid1(n)), bl(VMS_BLOCK);
+      hipLaunchKernelGGL(k_mass_lumped<T>, g1, bl, 0, s, n, mesh->diag_pos, mesh->blk_src_ptr, mesh->blk_src, mesh->X,
+                         mesh->tets, mesh->dir_mask, (const double *)K->W, mlw, mone);
+      // S 1 = D 1 - C A^-1 B 1 (one Schur product, its inner solve counted with the others)
+      hipLaunchKernelGGL((k_spmv_B<T, T>), dim3(spmv_grid(n)), bl, 0, s, n, nnzb, mesh->slot_width, mesh->col, B,
+                         (const T *)mone, xbar, (const T *)nullptr, 1.0, (const int *)nullptr);
+      int rc = solve_A(xbar, xt, true, false);   // no Schur level is running: no relaxation
+      if (rc) return rc;
+      hipLaunchKernelGGL((k_spmv_CD<T, T>), dim3(spmv_grid(n)), bl, 0, s, n, nnzb, mesh->slot_width, mesh->col, C, D,
+                         (const T *)xt, (const T *)mone, ms1, (const T *)nullptr, -1.0, 1.0, (const int *)nullptr);
+      hipLaunchKernelGGL(k_mass_sums<T>, dim3(1), dim3(1024), 0, s, n, (const T *)ms1, (const double *)mlw,
+                         mesh->dir_mask, msum);
+      const bool poly = o->shat_method != VMS_SHAT_NONE && o->shat_degree > 0;
+      hipLaunchKernelGGL(k_mass_inv<T>, g1, bl, 0, s, n, (const double *)mlw, (const double *)msum, mesh->dir_mask,
+                         o->schur_mass, o->shat_method == VMS_SHAT_NONE ? (const T *)nullptr : (const T *)sdinv,
+                         minv, poly ? (T *)nullptr : pdiag);
+    }
     VMS_LAUNCH_CHECK(ctx);
     return VMS_OK;
   }
@@ -1863,8 +1980,15 @@ int check_opts(vms_ctx *ctx, const vms_solver_opts *o) {
     return vms_set_error(ctx, VMS_ERR_ARG, "unknown A-level Krylov method");
   if (o->cg_symmetrise != 0 && o->cg_symmetrise != 1)
     return vms_set_error(ctx, VMS_ERR_ARG, "cg_symmetrise must be 0 or 1");
-  if (o->shat_method != VMS_SHAT_CHEBYSHEV && o->shat_method != VMS_SHAT_CG)
+  if (o->shat_method != VMS_SHAT_CHEBYSHEV && o->shat_method != VMS_SHAT_CG && o->shat_method != VMS_SHAT_NONE)
     return vms_set_error(ctx, VMS_ERR_ARG, "unknown S^ preconditioner method");
+  if (!(o->schur_mass >= 0.0) || !std::isfinite(o->schur_mass))
+    return vms_set_error(ctx, VMS_ERR_ARG, "schur_mass must be finite and >= 0");
+  if (o->shat_method == VMS_SHAT_NONE && !(o->schur_mass > 0.0))
+    return vms_set_error(ctx, VMS_ERR_ARG, "shat_method NONE needs schur_mass > 0");
+  if ((o->schur_mass > 0.0 || o->shat_method == VMS_SHAT_NONE) &&
+      (o->precond == VMS_PC_SIMPLE || o->schur_solve != VMS_SCHUR_KRYLOV))
+    return vms_set_error(ctx, VMS_ERR_ARG, "the pressure-mass term needs the Krylov Schur step of P_SCR");
   if (o->schur_solve != VMS_SCHUR_KRYLOV && o->schur_solve != VMS_SCHUR_SHAT)
     return vms_set_error(ctx, VMS_ERR_ARG, "unknown Schur step");
   if (o->relax_inner != 0 && o->relax_inner != 1)

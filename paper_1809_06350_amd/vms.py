@@ -23,7 +23,7 @@ PC_LDU, PC_UPPER, PC_LOWER, PC_DIAG, PC_SIMPLE = 0, 1, 2, 3, 4
 FP64, MIXED = 0, 1
 ORTH_CGS2, ORTH_MGS, ORTH_CGS1, ORTH_CGS_IFNEEDED = 0, 1, 2, 3
 AK_GMRES, AK_CG_INNER, AK_CG = 0, 1, 2
-SHAT_CHEBYSHEV, SHAT_CG = 0, 1
+SHAT_CHEBYSHEV, SHAT_CG, SHAT_NONE = 0, 1, 2
 SCHUR_KRYLOV, SCHUR_SHAT = 0, 1
 
 STATE_KEYS = ("u_n", "p_n", "v_n", "du_n", "dp_n", "dv_n", "u", "p", "v", "du", "dp", "dv")
@@ -39,10 +39,10 @@ def solver_opts(rtol=1e-8, atol=1e-50, maxit=200, rtol_A=3e-5, atol_A=1e-50, max
                 rtol_S=1e-5, atol_S=1e-50, maxit_S=200, rtol_I=1e-4, atol_I=1e-50, maxit_I=500,
                 precond=PC_LDU, precision=FP64, orth=ORTH_CGS1, shat_degree=16,
                 shat_ratio=20.0, a_krylov=AK_GMRES, cg_symmetrise=1, shat_method=SHAT_CG,
-                schur_solve=SCHUR_KRYLOV, relax_inner=0) -> L.SolverOpts:
+                schur_solve=SCHUR_KRYLOV, relax_inner=0, schur_mass=0.0) -> L.SolverOpts:
     return L.SolverOpts(rtol, atol, maxit, rtol_A, atol_A, maxit_A, rtol_S, atol_S, maxit_S,
                         rtol_I, atol_I, maxit_I, precond, precision, orth, shat_degree, shat_ratio, a_krylov,
-                        cg_symmetrise, shat_method, schur_solve, relax_inner)
+                        cg_symmetrise, shat_method, schur_solve, relax_inner, schur_mass)
 
 
 def newton_opts(tol_R=1e-8, tol_A=1e-50, l_max=20, rk_corr=1, eps_diag=1e-15) -> L.NewtonOpts:

@@ -71,7 +71,9 @@ def test_iteration_limit_and_zero_rhs():
 @pytest.mark.parametrize("kw", [dict(maxit=0), dict(maxit_A=1001), dict(maxit_I=0), dict(orth=7),
                                 dict(shat_degree=65), dict(precision=2), dict(precond=9), dict(a_krylov=3),
                                 dict(a_krylov=V.AK_CG, cg_symmetrise=2), dict(precond=5), dict(schur_solve=2),
-                                dict(shat_method=2), dict(relax_inner=2)])
+                                dict(shat_method=3), dict(relax_inner=2), dict(schur_mass=-1.0),
+                                dict(shat_method=V.SHAT_NONE), dict(schur_mass=1.0, precond=V.PC_SIMPLE),
+                                dict(schur_mass=1.0, schur_solve=V.SCHUR_SHAT)])
 def test_bad_solver_options_are_refused(kw):
     prob, mesh, ti, st, K, rhs = _system()
     with pytest.raises(V.VmsError) as ei:

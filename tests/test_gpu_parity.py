@@ -353,6 +353,28 @@ def test_relaxed_inner_tolerance_solve_matches_lu(problems, name, precision, a_k
     assert res[0]["status"] == 0 and res[1]["status"] == 0
 
 
+@pytest.mark.parametrize("name", ["cube-nu0499", "tube-hgo", "strip-hgo"])
+@pytest.mark.parametrize("precision,a_krylov", [(V.FP64, V.AK_GMRES), (V.MIXED, V.AK_CG)])
+@pytest.mark.parametrize("shat_method,shat_degree", [(V.SHAT_CG, 6), (V.SHAT_NONE, 0), (V.SHAT_CG, 0)])
+def test_pressure_mass_schur_preconditioner_solve_matches_lu(problems, name, precision, a_krylov, shat_method,
+                                                             shat_degree):
+    """The pressure-mass term of the Schur preconditioner (added to CG steps on
+    S^ or to diag(S^)^-1, or alone) changes only the preconditioner: the solve
+    reaches the requested residual and the oracle's LU solution."""
+    import scipy.sparse.linalg as spla
+    prob, mesh, mat, ti, disc = problems(name)
+    st, K, rhs, Ks, rs, W, _ = _prepared(prob, mesh, ti, disc, 86, mirror32=(precision == V.MIXED))
+    opts = V.solver_opts(rtol=1e-8, precision=precision, a_krylov=a_krylov, cg_symmetrise=0,
+                         shat_method=shat_method, shat_degree=shat_degree, schur_mass=1.0)
+    x, stats = prob.solve_scaled(K, rhs, opts)
+    xg = x.cpu().numpy().ravel()
+    print(f"[mass] {name} precision={precision} method={shat_method} degree={shat_degree} stats={stats}", flush=True)
+    assert stats["status"] == 0
+    assert np.linalg.norm(Ks @ xg - rs) <= 2e-8 * np.linalg.norm(rs)
+    xo = spla.splu(Ks.tocsc()).solve(rs)
+    assert np.linalg.norm(xg - xo) <= 1e-5 * np.linalg.norm(xo)
+
+
 @pytest.mark.parametrize("precision", [V.FP64, V.MIXED])
 def test_cg_product_launch_timing(problems, precision):
     """With launch timing on, every CG product launch that does the product is
