@@ -11,7 +11,8 @@ FP64 (GMRES at every level) and mixed (FP32 intermediate/inner levels with
 CG on the A-solves, FP64 outer FGMRES/Newton); --fp64-a-krylov and
 --mixed-a-krylov choose the A-level method of each form.
 
---workload strip runs the paper's second workload instead: the eighth of the
+--workload tube runs the fully incompressible HGO tube (8 x 256 x 160 hexes)
+under axial stretch; --workload strip runs the paper's second workload: the eighth of the
 10 x 3 x 0.5 mm tensile strip (section 5.2), fully incompressible HGO with
 dispersion k_d = 0.226, fibres at +-49.98 deg, symmetry conditions on three
 planes, a tensile force ramped to 2 N over 100 s, dt = 1e-5, on the mesh
@@ -147,8 +148,16 @@ def run_form(prob, mesh, ti, nopts, sopts, steps, warmup, timing=False):
     import torch
     from paper_1809_06350_amd import vms as V
 
+    import numpy as np
+    vm = torch.from_numpy(mesh.dir_mask[:, 0:3].astype(bool)).to(prob.dev)
+    dv = torch.from_numpy(np.ascontiguousarray(mesh.dir_vel)).to(prob.dev)
+
     def from_rest():
-        return prob.new_state()
+        # at rest except for prescribed velocities (the tube's moving end), which hold from t = 0
+        st = prob.new_state()
+        for key in ("v_n", "du_n"):
+            st[key][vm] = dv[vm]
+        return st
 
     K = None
     st = from_rest()
@@ -187,6 +196,10 @@ def time_a_product(prob, ti, nopts, sopts):
     import torch
     from paper_1809_06350_amd import vms as V
     st = prob.new_state()
+    vm = torch.from_numpy(prob.mesh.dir_mask[:, 0:3].astype(bool)).to(prob.dev)
+    dv = torch.from_numpy(prob.mesh.dir_vel.copy()).to(prob.dev)
+    for key in ("v_n", "du_n"):
+        st[key][vm] = dv[vm]
     prob.set_timing(True)
     prob.step(st, V.time_int(ti.dt, ti.rho_inf, 0.0, ti.n_steps * ti.dt), nopts, sopts, None)
     torch.cuda.synchronize()
@@ -279,11 +292,16 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="cube", choices=["cube", "strip"],
+    ap.add_argument("--workload", default="cube", choices=["cube", "strip", "tube"],
                     help="cube: the unit-cube compression (the headline); strip: the eighth of the anisotropic "
-                         "tensile strip of section 5.2 (HGO with dispersion, symmetry conditions, dt = 1e-5)")
+                         "tensile strip of section 5.2 (HGO with dispersion, symmetry conditions, dt = 1e-5); "
+                         "tube: the fully incompressible HGO tube under axial stretch (8 x 256 x 160 hexes)")
     ap.add_argument("--size", type=int, default=None,
-                    help="cube: hexes per edge (64); strip: 1/dx of the half-length (400: 400 x 120 x 20 hexes)")
+                    help="cube: hexes per edge (64); strip: 1/dx of the half-length (400: 400 x 120 x 20 hexes); "
+                         "tube: hexes around the circumference (256; radial and axial counts scale with it)")
+    ap.add_argument("--stretch", type=float, default=1.001,
+                    help="tube: axial stretch reached after the 20-step ramp (1.001 at dt = 1e-3: a stretch of "
+                         "1.5 over 20 steps of 1e-3 moves the end face by several element lengths per step)")
     ap.add_argument("--nu", type=float, default=0.499)
     ap.add_argument("--kd", type=float, default=0.226, help="strip: fibre dispersion k_d")
     ap.add_argument("--fibre-deg", type=float, default=49.98,
@@ -296,7 +314,7 @@ def main():
     ap.add_argument("--forms", default="fp64,mixed")
     ap.add_argument("--shat-degree", type=int, default=16)
     ap.add_argument("--shat-ratio", type=float, default=20.0)
-    ap.add_argument("--shat-method", default="cg", choices=["chebyshev", "cg"],
+    ap.add_argument("--shat-method", default="cg", choices=["chebyshev", "cg", "none"],
                     help="S^ preconditioner of the Schur solve: Chebyshev polynomial or CG steps (--shat-degree)")
     ap.add_argument("--outer-tol", type=float, default=1e-8,
                     help="relative tolerance of the outer FGMRES (the Newton tolerance stays 1e-8)")
@@ -322,6 +340,8 @@ def main():
     ap.add_argument("--relax-inner", default="off", choices=["on", "off"],
                     help="relax the inner tolerance of the Schur products as the Schur level converges "
                          "(relax_inner; off, as in the paper, by default)")
+    ap.add_argument("--schur-mass", type=float, default=0.0,
+                    help="weight of the lumped pressure-mass term in the Schur preconditioner (schur_mass; 0: off)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-timing", action="store_true",
                     help="also event-time every A-block product launch inside the timed steps (each launch then "
@@ -340,8 +360,16 @@ def main():
     from paper_1809_06350_amd import vms as V
 
     cube = args.workload == "cube"
-    N = args.size or (64 if cube else 400)
-    if cube:
+    N = args.size or {"cube": 64, "strip": 400, "tube": 256}[args.workload]
+    if args.workload == "tube":
+        dt = args.dt or 1e-3
+        nt = N
+        nr, nz = max(1, nt // 32), max(1, (nt * 5) // 8)
+        mesh, mat, ti = synth.tube_case(nr, nt, nz, dt=dt, n_steps=20, stretch=args.stretch)
+        wl = (f"HGO tube {nr}x{nt}x{nz} hexes x 6 Kuhn tets, fully incompressible, fibres +-45 deg, axial stretch "
+              f"{args.stretch} over 20 steps, dt={dt:g}, Newton 1e-8, FGMRES {args.outer_tol:g}")
+        args.no_cpu_baseline = True
+    elif cube:
         dt = args.dt or 1e-3
         mesh, mat, ti = synth.cube_case(N, nu=args.nu, n_steps=10, dt=dt)
         wl = f"cube{N}^3 Kuhn tets, nu={args.nu}, neo-Hookean, dt={dt:g}, Newton 1e-8, FGMRES {args.outer_tol:g}"
@@ -356,6 +384,8 @@ def main():
         args.no_cpu_baseline = True
     log(f"{mesh.name}: nodes={mesh.n_nodes} tets={mesh.n_tets}")
     prob = V.Problem(mesh, mat, "cuda:0")
+    if mesh.fibre is not None:
+        prob.set_fibres(*synth.fibre_field(mesh, mesh.meta["fibre_rad"]))
     n, nnzb = mesh.n_nodes, int(prob.host["row_len"].sum())   # real blocks (slots: prob.nnzb)
     tol_abs = args.tol_abs if args.tol_abs is not None else (1e-50 if cube else 1e-15)
     nopts = V.newton_opts(tol_R=1e-8, tol_A=tol_abs, l_max=20)
@@ -369,21 +399,23 @@ def main():
     akm = {"gmres": (V.AK_GMRES, 0), "cg-inner": (V.AK_CG_INNER, 0), "cg": (V.AK_CG, 0),
            "cg-inner-sym": (V.AK_CG_INNER, 1), "cg-sym": (V.AK_CG, 1)}
     if args.fp64_a_krylov is None:
-        args.fp64_a_krylov = "gmres" if cube else "cg"
+        args.fp64_a_krylov = "gmres" if cube else "cg"   # many A-iterations per solve off the cube
     relax = int(args.relax_inner == "on")
     fk, fs = akm[args.fp64_a_krylov]
     mk, ms = akm[args.mixed_a_krylov]
-    sm = {"chebyshev": V.SHAT_CHEBYSHEV, "cg": V.SHAT_CG}[args.shat_method]
+    sm = {"chebyshev": V.SHAT_CHEBYSHEV, "cg": V.SHAT_CG, "none": V.SHAT_NONE}[args.shat_method]
     pc = {"ldu": V.PC_LDU, "upper": V.PC_UPPER, "lower": V.PC_LOWER, "diag": V.PC_DIAG,
           "simple": V.PC_SIMPLE}[args.precond]
     ss = {"krylov": V.SCHUR_KRYLOV, "shat": V.SCHUR_SHAT}[args.schur_step]
     forms = {
         "fp64": V.solver_opts(rtol=args.outer_tol, rtol_A=ft[0], rtol_S=ft[1], rtol_I=ft[2], shat_degree=args.shat_degree,
                               shat_ratio=args.shat_ratio, orth=orth, a_krylov=fk, cg_symmetrise=fs,
-                              shat_method=sm, precond=pc, schur_solve=ss, relax_inner=relax),
+                              shat_method=sm, precond=pc, schur_solve=ss, relax_inner=relax,
+                              schur_mass=args.schur_mass),
         "mixed": V.solver_opts(rtol=args.outer_tol, rtol_A=mt[0], rtol_S=mt[1], rtol_I=mt[2], precision=V.MIXED,
                                shat_degree=args.shat_degree, shat_ratio=args.shat_ratio, orth=orth, a_krylov=mk,
-                               cg_symmetrise=ms, shat_method=sm, precond=pc, schur_solve=ss, relax_inner=relax),
+                               cg_symmetrise=ms, shat_method=sm, precond=pc, schur_solve=ss, relax_inner=relax,
+                               schur_mass=args.schur_mass),
     }
     results = {}
     for name in args.forms.split(","):
@@ -513,7 +545,7 @@ def main():
                       "shat_method": args.shat_method, "orth": args.orth, "precond": args.precond,
                       "schur_step": args.schur_step,
                       "tolerances": {"outer": args.outer_tol, "fp64_A_S_I": ft, "mixed_A_S_I": mt,
-                                     "relax_inner": relax},
+                                     "relax_inner": relax, "schur_mass": args.schur_mass},
                       "a_krylov": {"fp64": args.fp64_a_krylov, "mixed": args.mixed_a_krylov},
                       "parallelism": "single GPU"},
            "roofline": roof}
