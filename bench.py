@@ -318,9 +318,9 @@ def main():
                     help="S^ preconditioner of the Schur solve: Chebyshev polynomial or CG steps (--shat-degree)")
     ap.add_argument("--outer-tol", type=float, default=1e-8,
                     help="relative tolerance of the outer FGMRES (the Newton tolerance stays 1e-8)")
-    ap.add_argument("--fp64-tol", default="3e-5,1e-5,1e-4",
+    ap.add_argument("--fp64-tol", default="5e-5,1.5e-5,7e-5",
                     help="intermediate A, Schur and inner tolerances of the FP64 form")
-    ap.add_argument("--mixed-tol", default="3e-5,1e-5,1e-4",
+    ap.add_argument("--mixed-tol", default="5e-5,1.5e-5,7e-5",
                     help="intermediate A, Schur and inner tolerances of the mixed form")
     ap.add_argument("--orth", default="cgs1", choices=["cgs2", "cgs1", "cgs_ifneeded", "mgs"],
                     help="Arnoldi orthogonalisation of every Krylov level")

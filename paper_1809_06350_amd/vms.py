@@ -35,8 +35,8 @@ class VmsError(RuntimeError):
         self.code = code
 
 
-def solver_opts(rtol=1e-8, atol=1e-50, maxit=200, rtol_A=3e-5, atol_A=1e-50, maxit_A=500,
-                rtol_S=1e-5, atol_S=1e-50, maxit_S=200, rtol_I=1e-4, atol_I=1e-50, maxit_I=500,
+def solver_opts(rtol=1e-8, atol=1e-50, maxit=200, rtol_A=5e-5, atol_A=1e-50, maxit_A=500,
+                rtol_S=1.5e-5, atol_S=1e-50, maxit_S=200, rtol_I=7e-5, atol_I=1e-50, maxit_I=500,
                 precond=PC_LDU, precision=FP64, orth=ORTH_CGS1, shat_degree=16,
                 shat_ratio=20.0, a_krylov=AK_GMRES, cg_symmetrise=1, shat_method=SHAT_CG,
                 schur_solve=SCHUR_KRYLOV, relax_inner=0, schur_mass=0.0) -> L.SolverOpts:
