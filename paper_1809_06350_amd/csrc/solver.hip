@@ -750,7 +750,11 @@ k_cg_init(int64_t nn, const T *__restrict__ b, T *x, T *r, T *z, const T *__rest
 // q_j = A p_j = w + beta_j q_{j-1} are updated in place (only z is gathered),
 // with one partial of <p_j, q_j> per workgroup.  Layout of the A-block product
 // (16 lanes per row, 16 rows per workgroup); a workgroup takes a contiguous
-// range of row groups (XCD-aware order) when the grid is capped.
+// range of row groups (XCD-aware order) when the grid is capped.  The cap is
+// 8 resident 256-thread workgroups on each of the 256 CUs, so the capped grid
+// runs as one wave: the FP64 instance is held to 8 waves per SIMD (at most 64
+// VGPRs; the compiler would otherwise take 66, leave 7 resident and run the
+// last 256 workgroups as a second, nearly empty wave).
 #ifndef CG_SPMV_BLOCKS
 #define CG_SPMV_BLOCKS 2048
 #endif
@@ -759,7 +763,7 @@ inline int cg_spmv_blocks(int n) {
   return std::max(1, std::min(ng, CG_SPMV_BLOCKS));
 }
 template <typename T>
-__global__ void __launch_bounds__(VMS_BLOCK)
+__global__ void __launch_bounds__(VMS_BLOCK) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 8 : 1)))
 k_cg_spmv(int n, int64_t nnzb, int W, const int32_t *__restrict__ col, const T *__restrict__ A,
           const T *__restrict__ z, T *p, T *q, double *ctrl, KOff off, double *ppart, int *iflag, int j, int nbk,
           double rtol, double atol, int maxit, volatile int32_t *post, int32_t seq, int *worked,
