@@ -753,8 +753,11 @@ k_cg_init(int64_t nn, const T *__restrict__ b, T *x, T *r, T *z, const T *__rest
 // range of row groups (XCD-aware order) when the grid is capped.  The cap is
 // 8 resident 256-thread workgroups on each of the 256 CUs, so the capped grid
 // runs as one wave: the FP64 instance is held to 8 waves per SIMD (at most 64
-// VGPRs; the compiler would otherwise take 66, leave 7 resident and run the
-// last 256 workgroups as a second, nearly empty wave).
+// VGPRs; with 7 resident the last 256 workgroups would run as a second, nearly
+// empty wave).  In FP64 the row's own z, p, q are loaded after the product
+// loop: held across it they push the kernel past that bound, and the compiler
+// then recycles registers between the matrix loads and waits after each one
+// instead of keeping all of a row group's loads in flight.
 #ifndef CG_SPMV_BLOCKS
 #define CG_SPMV_BLOCKS 2048
 #endif
@@ -802,6 +805,7 @@ k_cg_spmv(int n, int64_t nnzb, int W, const int32_t *__restrict__ col, const T *
   const bool first = (j == 0);
   const double beta = first ? 0.0 : rz / ctrl[off.scal + 3 + ((j - 1) & 1)];
   constexpr bool NT = sizeof(T) == 8;
+  constexpr bool LATE = sizeof(T) == 8;
   const int lane = threadIdx.x & 15, sub = threadIdx.x >> 4;
   const int ng = (n + SPMV_ROWS_PER_BLOCK - 1) / SPMV_ROWS_PER_BLOCK;
   const int vb = xcd_block(blockIdx.x, gridDim.x);   // even split: every workgroup gets floor or ceil(ng / grid)
@@ -811,11 +815,12 @@ k_cg_spmv(int n, int64_t nnzb, int W, const int32_t *__restrict__ col, const T *
     const int row = g * SPMV_ROWS_PER_BLOCK + sub;
     const bool act = row < n;
     const int b0 = act ? W * row : 0, b1 = act ? b0 + W : 0;
-    // lanes 0-2 own component `lane` of the row: its z, p, q are loaded ahead of the product
+    // lanes 0-2 own component `lane` of the row: its z, p, q are loaded ahead of the
+    // product in FP32 and after it in FP64 (LATE)
     const bool own = act && lane < 3;
     const int64_t oc = 3 * (int64_t)(act ? row : 0) + (lane < 3 ? lane : 0);
     double zc = 0.0, pc = 0.0, qc = 0.0;
-    if (own) {
+    if (!LATE && own) {
       zc = ld(z, oc);
       if (!first) { pc = ld(p, oc); qc = ld(q, oc); }
     }
@@ -826,6 +831,10 @@ k_cg_spmv(int n, int64_t nnzb, int W, const int32_t *__restrict__ col, const T *
       a0 += ldm<NT>(A, 0 * nnzb + b) * x0 + ldm<NT>(A, 1 * nnzb + b) * x1 + ldm<NT>(A, 2 * nnzb + b) * x2;
       a1 += ldm<NT>(A, 3 * nnzb + b) * x0 + ldm<NT>(A, 4 * nnzb + b) * x1 + ldm<NT>(A, 5 * nnzb + b) * x2;
       a2 += ldm<NT>(A, 6 * nnzb + b) * x0 + ldm<NT>(A, 7 * nnzb + b) * x1 + ldm<NT>(A, 8 * nnzb + b) * x2;
+    }
+    if (LATE && own) {
+      zc = ld(z, oc);
+      if (!first) { pc = ld(p, oc); qc = ld(q, oc); }
     }
     a0 = reduce16(a0);
     a1 = reduce16(a1);
