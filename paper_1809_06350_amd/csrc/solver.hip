@@ -239,9 +239,14 @@ k_mdot_part(int64_t nvec, const T *__restrict__ V, int nk, const T *__restrict__
     const T *Vk = V + (int64_t)k0 * nvec;
     for (int64_t r = t0; r < nvec; r += stride) {
       const double wr = dl(w, r);
+      // every load unconditional (slots q >= kk read basis vector k0 again and
+      // are not used), so that the eight loads are issued together
+      double v[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) v[q] = dl(Vk, (int64_t)(q < kk ? q : 0) * nvec + r);
 #pragma unroll
       for (int q = 0; q < 8; ++q)
-        if (q < kk) acc[q] += dl(Vk, (int64_t)q * nvec + r) * wr;
+        if (q < kk) acc[q] += v[q] * wr;
     }
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
@@ -304,16 +309,20 @@ k_mupdate_fin(int64_t nvec, const T *__restrict__ V, int nk, T *w, const double 
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   double ss = 0.0;
   for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < nvec; r += stride) {
-    double a0 = 0, a1 = 0, a2 = 0, a3 = 0;
-    int k = 0;
-    for (; k + 4 <= nk; k += 4) {
-      a0 += cs[k] * dl(V, (int64_t)k * nvec + r);
-      a1 += cs[k + 1] * dl(V, (int64_t)(k + 1) * nvec + r);
-      a2 += cs[k + 2] * dl(V, (int64_t)(k + 2) * nvec + r);
-      a3 += cs[k + 3] * dl(V, (int64_t)(k + 3) * nvec + r);
+    // eight basis vectors per round, every load unconditional (slots past nk
+    // read vector k0 again and are not used) so that they are issued together;
+    // term k goes to accumulator k mod 4
+    const double wr = dl(w, r);
+    double a[4] = {0, 0, 0, 0};
+    for (int k0 = 0; k0 < nk; k0 += 8) {
+      double v[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) v[q] = dl(V, (int64_t)(k0 + q < nk ? k0 + q : k0) * nvec + r);
+#pragma unroll
+      for (int q = 0; q < 8; ++q)
+        if (k0 + q < nk) a[q & 3] += cs[k0 + q] * v[q];
     }
-    for (; k < nk; ++k) a0 += cs[k] * dl(V, (int64_t)k * nvec + r);
-    const T out = (T)(dl(w, r) - ((a0 + a1) + (a2 + a3)));
+    const T out = (T)(wr - ((a[0] + a[1]) + (a[2] + a[3])));
     w[r] = out;
     if (NORM) ss += (double)out * (double)out;
   }
@@ -878,19 +887,30 @@ k_cg_update(int64_t nn, T *x, T *r, T *z, const T *__restrict__ p, const T *__re
   double rz = 0.0, rr = 0.0;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nn; i += stride) {
-    double rv[3];
-    T zv[3];
+    // every load of the node before any store (x and r are not restrict: loads
+    // placed after their stores would be issued only once the stores are done)
+    double xo[3], po[3], ro[3], qo[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       const int64_t o = 3 * i + c;
-      x[o] = (T)(dl(x, o) + alpha * dl(p, o));
-      const T rt = (T)(dl(r, o) - alpha * dl(q, o));
-      r[o] = rt;
-      rv[c] = (double)rt;
+      xo[c] = dl(x, o);
+      po[c] = dl(p, o);
+      ro[c] = dl(r, o);
+      qo[c] = dl(q, o);
+    }
+    double rv[3];
+    T xn[3], rt[3], zv[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      xn[c] = (T)(xo[c] + alpha * po[c]);
+      rt[c] = (T)(ro[c] - alpha * qo[c]);
+      rv[c] = (double)rt[c];
     }
     bj33_apply(Minv + 9 * i, rv, zv);
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
+      x[3 * i + c] = xn[c];
+      r[3 * i + c] = rt[c];
       z[3 * i + c] = zv[c];
       rz += rv[c] * (double)zv[c];
       rr += rv[c] * rv[c];
@@ -1094,29 +1114,42 @@ k_pcg_step(int n, int i, int last, T *x, PcgVec<T> V, const T *__restrict__ dinv
   }
   const bool first = (i == 0);
   double gn = 0.0, dn = 0.0;
-  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) {
-    const double zk = ld(V.nv, k) + (first ? 0.0 : beta * ld(V.z, k));
-    const double qk = ld(V.m, k) + (first ? 0.0 : beta * ld(V.q, k));
-    const double sk = ld(V.w, k) + (first ? 0.0 : beta * ld(V.s, k));
-    const double pk = ld(V.u, k) + (first ? 0.0 : beta * ld(V.p, k));
-    x[k] = (T)(ld(x, k) + alpha * pk);
-    if (!last) {
-      V.z[k] = (T)zk;
-      V.q[k] = (T)qk;
-      V.s[k] = (T)sk;
-      V.p[k] = (T)pk;
-      const T rk = (T)(ld(V.r, k) - alpha * sk);
-      const T uk = (T)(ld(V.u, k) - alpha * qk);
-      const T wk = (T)(ld(V.w, k) - alpha * zk);
-      V.r[k] = rk;
-      V.u[k] = uk;
-      V.w[k] = wk;
-      V.m[k] = (T)(ld(dinv, k) * (double)wk);
-      gn += (double)rk * (double)uk;
-      dn += (double)wk * (double)uk;
+  const int stride = gridDim.x * blockDim.x;
+  if (last) {   // only x changes
+    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += stride) {
+      const double uo = ld(V.u, k), po = first ? 0.0 : ld(V.p, k), xo = ld(x, k);
+      const double pk = uo + (first ? 0.0 : beta * po);
+      x[k] = (T)(xo + alpha * pk);
     }
+    return;
   }
-  if (!last) cg_block_sums2(gn, dn, ((i + 1) & 1 ? pg1 : pg0) + blockIdx.x, ((i + 1) & 1 ? pd1 : pd0) + blockIdx.x, sm);
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += stride) {
+    // every load of the node before any store (the work vectors are not
+    // restrict: loads placed after stores would wait for them).  On the first
+    // step z, q, s, p are read but not used (the select keeps 0).
+    const double nvo = ld(V.nv, k), mo = ld(V.m, k), wo = ld(V.w, k), uo = ld(V.u, k), ro = ld(V.r, k);
+    const double zo = ld(V.z, k), qo = ld(V.q, k), so = ld(V.s, k), po = ld(V.p, k);
+    const double xo = ld(x, k), dk = ld(dinv, k);
+    const double zk = nvo + (first ? 0.0 : beta * zo);
+    const double qk = mo + (first ? 0.0 : beta * qo);
+    const double sk = wo + (first ? 0.0 : beta * so);
+    const double pk = uo + (first ? 0.0 : beta * po);
+    x[k] = (T)(xo + alpha * pk);
+    V.z[k] = (T)zk;
+    V.q[k] = (T)qk;
+    V.s[k] = (T)sk;
+    V.p[k] = (T)pk;
+    const T rk = (T)(ro - alpha * sk);
+    const T uk = (T)(uo - alpha * qk);
+    const T wk = (T)(wo - alpha * zk);
+    V.r[k] = rk;
+    V.u[k] = uk;
+    V.w[k] = wk;
+    V.m[k] = (T)(dk * (double)wk);
+    gn += (double)rk * (double)uk;
+    dn += (double)wk * (double)uk;
+  }
+  cg_block_sums2(gn, dn, ((i + 1) & 1 ? pg1 : pg0) + blockIdx.x, ((i + 1) & 1 ? pd1 : pd0) + blockIdx.x, sm);
 }
 
 // ---- S^ = D - C diag(A)^-1 B, assembled on the distance-2 pattern ----------
