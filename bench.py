@@ -176,7 +176,9 @@ def run_form(prob, mesh, ti, nopts, sopts, steps, warmup, timing=False):
         per.append(stats)
         log(f"  step {s}: newton={stats['n_newton']} outer={stats['it_outer_total']} A={stats['it_A_total']} "
             f"S={stats['it_S_total']} I={stats['it_I_total']} ms={stats['ms_total']:.1f} "
-            f"(asm {stats['ms_assemble']:.1f}, solve {stats['ms_solve']:.1f})")
+            f"(asm {stats['ms_assemble']:.1f}, solve {stats['ms_solve']:.1f}: scale {stats['ms_scale_total']:.1f} "
+            f"setup {stats['ms_setup_total']:.1f} A {stats['ms_A_solve_total']:.1f} S {stats['ms_S_solve_total']:.1f} "
+            f"inner {stats['ms_inner_total']:.1f})")
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     fp32 = sopts.precision == V.MIXED
@@ -209,24 +211,44 @@ def time_a_product(prob, ti, nopts, sopts):
 
 
 def cpu_baseline(N=16, nu=0.499, steps=2):
-    """The oracle (NumPy/SciPy, sparse LU) on a 16^3 sample of the workload:
-    its first `steps` time steps from rest."""
-    import numpy as np  # noqa: F401
-
+    """The oracle (NumPy/SciPy, sparse LU) on an N^3 sample of the workload:
+    its first `steps` time steps from rest, with the BLAS pools held to one
+    thread (threadpoolctl), so that the oracle runs on one core.  Returns the
+    wall time, the process CPU time over it (the cores actually used) and the
+    final state (for the GPU-vs-oracle check at this size)."""
     import synth
     from oracle import assemble as AS
     from oracle import newton as NW
+    from threadpoolctl import threadpool_limits
     mesh, mat, ti = synth.cube_case(N, nu=nu, n_steps=10)
-    disc = AS.Discretization(mesh, mat)
-    t0 = time.perf_counter()
-    st, n_newton = NW.rest_state(mesh), 0
-    for s in range(steps):
-        st, info = NW.time_step(disc, ti, st, s * ti.dt, tol_R=1e-8)
-        n_newton += info["n_newton"]
-    wall = time.perf_counter() - t0
-    threads = os.environ.get("OMP_NUM_THREADS") or os.environ.get("OPENBLAS_NUM_THREADS") or "unset"
-    return {"wall_s": wall, "n_newton": n_newton, "steps": steps, "n_unknowns": 4 * mesh.n_nodes,
-            "threads_env": threads}
+    with threadpool_limits(limits=1):
+        disc = AS.Discretization(mesh, mat)
+        t0, c0 = time.perf_counter(), time.process_time()
+        st, n_newton = NW.rest_state(mesh), 0
+        for s in range(steps):
+            st, info = NW.time_step(disc, ti, st, s * ti.dt, tol_R=1e-8)
+            n_newton += info["n_newton"]
+        wall, cpu = time.perf_counter() - t0, time.process_time() - c0
+    return {"N": N, "wall_s": wall, "cpu_s": cpu, "n_newton": n_newton, "steps": steps,
+            "n_unknowns": 4 * mesh.n_nodes, "u": st["u"], "mesh": mesh, "mat": mat, "ti": ti}
+
+
+def gpu_vs_oracle(cb, nopts, forms):
+    """The GPU forms on the oracle's sample (same mesh, steps and Newton tolerance): relative l2 error
+    of u after the last step against the oracle's u, per form."""
+    import numpy as np
+    from paper_1809_06350_amd import vms as V
+    mesh, mat, ti = cb["mesh"], cb["mat"], cb["ti"]
+    prob = V.Problem(mesh, mat, "cuda:0")
+    out = {}
+    for name, so in forms.items():
+        st, K = prob.new_state(), None
+        for s in range(cb["steps"]):
+            _, K = prob.step(st, V.time_int(ti.dt, ti.rho_inf, s * ti.dt, ti.n_steps * ti.dt), nopts, so, K)
+            prob.roll(st)
+        u = st["u"].cpu().numpy()
+        out[name] = float(np.linalg.norm(u - cb["u"]) / np.linalg.norm(cb["u"]))
+    return out
 
 
 def spmv_only(prob, mesh, ti, reps):
@@ -529,10 +551,20 @@ def main():
                           "first_step_ms": rm["per_step"][0]["ms_total"],
                           "speedup_vs_fp64": (r["wall_s"] / rm["wall_s"]) if "fp64" in results else None,
                           "u_rel_err_vs_fp64": err}
+    phase_keys = ("ms_scale_total", "ms_setup_total", "ms_outer_total", "ms_A_solve_total", "ms_S_solve_total",
+                  "ms_inner_total")
     for name, rr in results.items():
         last = rr["per_step"][-1]
         extra[f"{name}_last_step"] = {k: last[k] for k in ("n_newton", "it_outer_total", "it_A_total", "it_S_total",
                                                            "it_I_total", "ms_assemble", "ms_solve", "ms_total")}
+        # device time per step of the solver's phases (HIP events on the library's stream), mean over the
+        # timed steps; they nest: outer includes A and S, S includes inner
+        per = rr["per_step"]
+        ph = {k[3:-6]: sum(p[k] for p in per) / len(per) for k in phase_keys}
+        ph["outer_excl"] = ph["outer"] - ph["A_solve"] - ph["S_solve"]
+        ph["S_excl"] = ph["S_solve"] - ph["inner"]
+        ph["assemble_host"] = sum(p["ms_assemble"] for p in per) / len(per)
+        extra[f"{name}_phase_ms_per_step"] = ph
     out = {"metric": METRIC, "value": value, "unit": "newton_steps/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": 1e3 * r["wall_s"] / args.steps,
            "ms_per_newton_step": 1e3 * r["wall_s"] / r["n_newton"], "higher_is_better": True,
@@ -551,15 +583,36 @@ def main():
            "roofline": roof}
     out.update(extra)
     if not args.no_cpu_baseline:
-        log("cpu baseline: oracle on a 16^3 sample")
-        cb = cpu_baseline(16, args.nu)
-        rate16 = cb["n_newton"] / cb["wall_s"]
-        out["cpu_baseline"] = {"value": rate16 * cb["n_unknowns"] / (4 * n), "unit": "newton_steps/s",
-                               "cores": 1, "kind": "oracle",
-                               "sample": f"the first {cb['steps']} time steps of the 16^3 cube ({cb['n_unknowns']} "
-                                         f"unknowns, {cb['n_newton']} Newton its, {cb['wall_s']:.1f} s), scaled "
-                                         f"linearly by unknowns to {N}^3; SuperLU single-threaded, "
-                                         f"OMP/OPENBLAS threads={cb['threads_env']}"}
+        # the oracle on two samples of the workload (12^3 and 16^3 cubes, 2 time steps each); its time per
+        # Newton iteration is fitted as c * unknowns^alpha through the two points and evaluated at the
+        # workload's size (sparse LU grows faster than linearly, so a linear scaling would flatter the CPU)
+        import math
+        pts = []
+        for Ns in (12, 16):
+            log(f"cpu baseline: oracle on the {Ns}^3 sample")
+            pts.append(cpu_baseline(Ns, args.nu))
+        t_per = [p["wall_s"] / p["n_newton"] for p in pts]
+        alpha = math.log(t_per[1] / t_per[0]) / math.log(pts[1]["n_unknowns"] / pts[0]["n_unknowns"])
+        t_full = t_per[1] * (4 * n / pts[1]["n_unknowns"]) ** alpha
+        cores = sum(p["cpu_s"] for p in pts) / sum(p["wall_s"] for p in pts)
+        out["cpu_baseline"] = {
+            "value": 1.0 / t_full, "unit": "newton_steps/s", "cores": round(cores, 2), "kind": "oracle",
+            "sample": (f"the first 2 time steps of the 12^3 and 16^3 cubes (nu={args.nu}), timed on the host "
+                       f"with the BLAS pools held to 1 thread; seconds per Newton iteration "
+                       + ", ".join(f"{p['N']}^3 ({p['n_unknowns']} unknowns): {t:.3f} s ({p['n_newton']} its)"
+                                   for p, t in zip(pts, t_per))
+                       + f"; fitted t ~ unknowns^{alpha:.2f}, evaluated at {4 * n} unknowns; cores = process "
+                         f"CPU time / wall time; host os.cpu_count()={os.cpu_count()}, "
+                         f"OMP_NUM_THREADS={os.environ.get('OMP_NUM_THREADS', 'unset')}"),
+            "points": [{"N": p["N"], "unknowns": p["n_unknowns"], "s_per_newton": t, "newton": p["n_newton"],
+                        "wall_s": p["wall_s"], "cpu_s": p["cpu_s"]} for p, t in zip(pts, t_per)],
+            "fitted_exponent": alpha}
+        if cube:
+            log("oracle check: the GPU forms on the 16^3 sample")
+            out["oracle_check_16"] = {
+                "u_rel_err": gpu_vs_oracle(pts[1], nopts, {k: forms[k] for k in results}),
+                "note": "GPU u after the sample's 2 time steps (bench tolerances, Newton 1e-8) against the "
+                        "oracle's (sparse LU, Newton 1e-8), relative l2"}
     print(json.dumps(out), flush=True)
 
 

@@ -13,7 +13,9 @@
  *  - Memory: every array pointer is a DEVICE pointer owned by the caller
  *    unless its comment says "host".  The library allocates no device memory
  *    after vms_ctx_create: solver scratch comes from a caller-provided
- *    workspace.  vms_ctx_create allocates a small pinned host buffer.
+ *    workspace.  vms_ctx_create allocates a small device status area, the
+ *    512 KB launch-timing flags, pinned host buffers and a fixed pool of HIP
+ *    events (the solver's phase timing).
  *  - Streams: all kernels are enqueued on the stream given to
  *    vms_ctx_create (in order).  Calls marked [async] return without waiting;
  *    calls marked [sync] wait for the stream work they need to take host-side
@@ -55,7 +57,9 @@ enum vms_status {
   VMS_ERR_WORKSPACE = -3,       /* workspace too small */
   VMS_ERR_INVERTED_ELEMENT = -4,/* J <= 0 in some element */
   VMS_ERR_BREAKDOWN = -5,       /* Arnoldi breakdown with a nonzero residual */
-  VMS_ERR_NAN = -6              /* NaN/Inf in a residual or Krylov norm */
+  VMS_ERR_NAN = -6,             /* NaN/Inf in a residual or Krylov norm */
+  VMS_ERR_STATE = -7            /* the call needs a state the context does not hold (e.g. kernel
+                                   timing read while it is off; no static scratch on this device) */
 };
 
 enum vms_material_kind { VMS_NH_COMP = 0, VMS_NH_INCOMP = 1, VMS_HGO_INCOMP = 2 };
@@ -202,6 +206,20 @@ typedef struct {
   int32_t n_I_solves, it_I;         /* inner A-solves and their total iterations */
   double res0, res;                 /* outer ||r*|| at start and the final least-squares residual */
   double ms_total;                  /* host wall time of the call */
+  /* Device time of the phases (HIP events recorded on the context stream, ms).  They nest:
+   * ms_outer covers the whole Krylov solve after the preconditioner set-up, so it includes
+   * ms_A and ms_S, and ms_S includes the ms_inner of the inner solves of its Schur products. */
+  double ms_scale;                  /* Dirichlet rows, scaling, FP32 mirrors, rhs* (vms_solve only) and
+                                       Delta = W x* */
+  double ms_setup;                  /* preconditioner set-up: block-Jacobi inverses, S^, its
+                                       Chebyshev bounds or pressure-mass fit */
+  double ms_outer;                  /* outer FGMRES with its preconditioner applications */
+  double ms_A;                      /* intermediate A-solves (Algorithm 1, steps 1 and 5) */
+  double ms_S;                      /* Schur solves (Algorithm 1, step 3) */
+  double ms_inner;                  /* inner A-solves of the Schur products (Algorithm 2) */
+  int32_t phases_timed;             /* 1: every phase above was timed; 0: the context's event
+                                       pool ran out and the figures are partial */
+  int32_t pad_;
 } vms_solve_stats;
 
 typedef struct {
@@ -218,6 +236,8 @@ typedef struct {
   vms_solve_stats last;     /* stats of the last linear solve */
   int32_t it_outer_total, it_A_total, it_S_total, it_I_total;
   double ms_assemble, ms_solve, ms_total;
+  /* sums over the step's linear solves of the device phase times of vms_solve_stats */
+  double ms_scale_total, ms_setup_total, ms_outer_total, ms_A_solve_total, ms_S_solve_total, ms_inner_total;
 } vms_step_stats;
 
 /* ---- context ------------------------------------------------------------ */
@@ -231,7 +251,9 @@ void vms_ctx_destroy(vms_ctx *ctx);
 const char *vms_last_error(const vms_ctx *ctx);
 
 /* Launch timing of the A-block product, the solver's dominant kernel (a
- * measurement aid for the HBM roofline of its products).  With enable != 0
+ * measurement aid for the HBM roofline of its products).  vms_ctx_create
+ * allocates its per-launch flags (512 KB of device memory) and a pool of
+ * HIP events for the solver's phase timing.  With enable != 0
  * every launch of it -- inside vms_solve_scaled / vms_step (intermediate and
  * inner A-levels; on a CG level the CG product kernel, which fuses the
  * direction updates into the product) and from vms_spmv(VMS_OP_A) -- carries a start and a stop
@@ -239,13 +261,12 @@ const char *vms_last_error(const vms_ctx *ctx);
  * kernel's own begin and end on the context stream), and the kernel sets a
  * per-launch device flag when it does work (launches enqueued past a level's
  * convergence return at once and are not counted).
- * Enabling or disabling resets the counts; the first enable allocates a
- * 512 KB device flag array.  [sync] */
+ * Enabling or disabling resets the counts.  [sync] */
 int vms_ctx_set_timing(vms_ctx *ctx, int enable);
 /* Sum of the event-timed durations (ms) and number of the counted launches
  * since the last call or reset, kind 0 = FP64 product, 1 = FP32 product;
  * resets that kind's counts.  At most 65536 launches per kind are recorded
- * between two calls.  [sync] */
+ * between two calls.  VMS_ERR_STATE if timing is off.  [sync] */
 int vms_ctx_kernel_time(vms_ctx *ctx, int kind, double *ms_total, int64_t *launches);
 
 /* ---- setup (host, integer work) ---------------------------------------- */
@@ -355,9 +376,28 @@ int vms_schur_hat(vms_ctx *ctx, const vms_mesh *mesh, const vms_matrix *K, doubl
 int vms_shat_spmv(vms_ctx *ctx, const vms_mesh *mesh, const void *S, const void *Sd, const void *x, void *y,
                   int fp32);
 
-/* Workspace bytes needed by vms_solve_scaled / vms_solve_transpose for these
- * options (Krylov bases of the four levels, control blocks, temporaries). */
+/* Workspace bytes needed by vms_solve, vms_solve_scaled, vms_solve_transpose
+ * and vms_solve_transpose_scaled for these options (Krylov bases of the four
+ * levels, control blocks, temporaries, the scaled right-hand side and
+ * solution). */
 size_t vms_solve_workspace(const vms_mesh *mesh, const vms_solver_opts *opts);
+
+/* solve(K, R) -> Delta: stage 1 of the Newton iteration (section 3.3 step 5,
+ * with the right-hand side of eq. NR_smaller_eqn_1): solve
+ *     K Delta = rhs,  rhs = -R + corr  (corr may be NULL: rhs = -R),
+ * K = [[A, B], [C, D]] as vms_assemble wrote it, by the symmetric diagonal
+ * scaling of section 4.1 and the nested solve of vms_solve_scaled:
+ * Dirichlet rows and columns replaced by the identity (Delta = 0 there),
+ * W_ii = |K_ii|^(-1/2) (>= eps_diag, else 1), (W K W) x* = W rhs,
+ * Delta = W x*.  K is OVERWRITTEN with W K W (the FP32 mirrors too when
+ * opts->precision is VMS_MIXED) and K->W with W, as by vms_prepare_system.
+ * R, corr, delta: [n][4] (v_x, v_y, v_z, p); delta = (Delta v-dot,
+ * Delta p-dot).  Workspace as vms_solve_workspace.  [sync]  Status codes as
+ * vms_solve_scaled; with VMS_NOT_CONVERGED delta holds W times the last
+ * iterate. */
+int vms_solve(vms_ctx *ctx, const vms_mesh *mesh, vms_matrix *K, const double *R, const double *corr,
+              double *delta, double eps_diag, const vms_solver_opts *opts, void *workspace,
+              size_t workspace_bytes, vms_solve_stats *stats);
 
 /* Solve the scaled system K* x* = rhs* by FGMRES (outer level) right-
  * preconditioned by the nested Schur-complement-reduction preconditioner
@@ -373,7 +413,8 @@ int vms_solve_scaled(vms_ctx *ctx, const vms_mesh *mesh, const vms_matrix *K,
                      const double *rhs_scaled, double *x_scaled, const vms_solver_opts *opts,
                      void *workspace, size_t workspace_bytes, vms_solve_stats *stats);
 
-/* Stage 2 and update (section 3.3 steps 6-7): Delta = W x*; Delta u-dot =
+/* Stage 2 and update (section 3.3 steps 6-7): Delta = W x* (W = NULL:
+ * x_scaled already holds Delta, as vms_solve returns it); Delta u-dot =
  * (alpha_f gamma dt/alpha_m) Delta v-dot - R-bar_k/alpha_m; y-dot += Delta
  * y-dot, y += gamma dt Delta y-dot on the iterate (Dirichlet components fixed).
  * [async] */
@@ -397,16 +438,27 @@ int vms_step(vms_ctx *ctx, const vms_mesh *mesh, const vms_material *mat,
 
 /* ---- adjoint (implicit differentiation of a converged time step) --------- */
 
-/* Transposed solve (W K^T W) lam* = rhs_scaled through the same nested
- * preconditioner built for K^T = [[A^T, C^T], [B^T, D^T]] (Algorithm 1 applied
- * to the transposed system; its Schur complement is S^T = D^T - B^T A^-T C^T).
- * K holds the scaled system from vms_prepare_system (K->W its scaling); Kt is
- * caller storage with the same layout (FP32 parts needed only for VMS_MIXED)
- * and is overwritten with the transposed blocks.  [sync]  Same status codes
- * as vms_solve_scaled. */
-int vms_solve_transpose(vms_ctx *ctx, const vms_mesh *mesh, const vms_matrix *K, vms_matrix *Kt,
-                        const double *rhs_scaled, double *lam_scaled, const vms_solver_opts *opts,
-                        void *workspace, size_t workspace_bytes, vms_solve_stats *stats);
+/* Transposed solve, the adjoint counterpart of vms_solve: K^T lam = g with K
+ * as vms_assemble wrote it.  Dirichlet rows and columns of K are replaced by
+ * the identity (lam = 0 on Dirichlet dofs, g ignored there), W is formed from
+ * K's diagonal as in vms_solve, and (W K^T W) lam* = W g is solved by the
+ * nested preconditioner built for K^T = [[A^T, C^T], [B^T, D^T]] (Algorithm 1
+ * applied to the transposed system; its Schur complement is
+ * S^T = D^T - B^T A^-T C^T); lam = W lam*.  K is OVERWRITTEN with W K W and
+ * K->W with W; Kt is caller storage with K's layout (FP32 parts needed only
+ * for VMS_MIXED), overwritten with the transposed blocks.  g, lam: [n][4].
+ * [sync]  Status codes as vms_solve. */
+int vms_solve_transpose(vms_ctx *ctx, const vms_mesh *mesh, vms_matrix *K, vms_matrix *Kt, const double *g,
+                        double *lam, double eps_diag, const vms_solver_opts *opts, void *workspace,
+                        size_t workspace_bytes, vms_solve_stats *stats);
+
+/* Transposed solve of an already scaled system: (W K^T W) lam* = rhs_scaled,
+ * with K holding W K W from vms_prepare_system (K->W its scaling), through the
+ * nested preconditioner built for the transposed blocks; Kt as in
+ * vms_solve_transpose.  [sync]  Same status codes as vms_solve_scaled. */
+int vms_solve_transpose_scaled(vms_ctx *ctx, const vms_mesh *mesh, const vms_matrix *K, vms_matrix *Kt,
+                               const double *rhs_scaled, double *lam_scaled, const vms_solver_opts *opts,
+                               void *workspace, size_t workspace_bytes, vms_solve_stats *stats);
 
 /* out[k] (HOST, 5 doubles) = lam^T dR/dtheta_k at the generalized-alpha stages
  * of `st`, theta = (mu, kappa, k1, k2, fibre angle) for the bits set in pmask

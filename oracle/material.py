@@ -10,19 +10,13 @@ import numpy as np
 NH_COMP, NH_INCOMP, HGO_INCOMP = 0, 1, 2
 
 
-def gibbs_vol(p, kappa, rho0):
-    """Volumetric Gibbs energy of the compressible neo-Hookean block benchmark
-    (numerical results, block compression): (p s - p^2)/(2 kappa rho0)
-    - kappa/(2 rho0) ln((s - p)/kappa), s = sqrt(p^2 + kappa^2)."""
-    s = np.sqrt(p * p + kappa * kappa)
-    return (p * s - p * p) / (2.0 * kappa * rho0) - kappa / (2.0 * rho0) * np.log((s - p) / kappa)
-
-
 def rho_beta(p, mat):
     """rho(p) = (dG_vol/dp)^-1 and beta(p) = rho^-1 d rho/dp (section 2),
     plus d rho/dp and d beta/dp.
 
-    For the Gibbs energy above, dG_vol/dp = (s - p)/(kappa rho0), hence
+    For the volumetric Gibbs energy of the block-compression example,
+    G_vol = (p s - p^2)/(2 kappa rho0) - kappa/(2 rho0) ln((s - p)/kappa) with
+    s = sqrt(p^2 + kappa^2), dG_vol/dp = (s - p)/(kappa rho0), hence
     rho = rho0 (s + p)/kappa, beta = 1/s, rho_p = rho beta, beta_p = -p/s^3.
     The fully incompressible energy G_vol = p/rho0 gives rho = rho0, beta = 0.
     """
@@ -51,23 +45,6 @@ def structure_tensors(fibre, kd):
     a = np.asarray(fibre)
     eye = np.eye(3)
     return kd * eye[None, None] + (1.0 - 3.0 * kd) * np.einsum("mfi,mfj->mfij", a, a)
-
-
-def iso_energy(F, mat, H=None):
-    """rho0 * G_iso(C~) per unit reference volume, C~ = J^(-2/3) F^T F.
-
-    neo-Hookean matrix: mu/2 (tr C~ - 3); each fibre family:
-    k1/(2 k2) (exp(k2 E_i^2) - 1), E_i = H_i : C~ - 1.
-    """
-    J = np.linalg.det(F)
-    C = np.einsum("...kI,...kJ->...IJ", F, F)
-    Ct = J[..., None, None] ** (-2.0 / 3.0) * C
-    W = 0.5 * mat.mu * (np.einsum("...II->...", Ct) - 3.0)
-    if mat.kind == HGO_INCOMP and H is not None:
-        for f in range(2):
-            E = np.einsum("...IJ,...IJ->...", H[..., f, :, :], Ct) - 1.0
-            W = W + mat.k1 / (2.0 * mat.k2) * (np.exp(mat.k2 * E * E) - 1.0)
-    return W
 
 
 def piola_iso(F, mat, H=None):

@@ -53,10 +53,13 @@ class SolverOpts(C.Structure):
 class SolveStats(C.Structure):
     _fields_ = [("status", C.c_int32), ("n_outer", C.c_int32), ("n_A_solves", C.c_int32), ("it_A", C.c_int32),
                 ("n_S_solves", C.c_int32), ("it_S", C.c_int32), ("n_I_solves", C.c_int32), ("it_I", C.c_int32),
-                ("res0", C.c_double), ("res", C.c_double), ("ms_total", C.c_double)]
+                ("res0", C.c_double), ("res", C.c_double), ("ms_total", C.c_double),
+                ("ms_scale", C.c_double), ("ms_setup", C.c_double), ("ms_outer", C.c_double),
+                ("ms_A", C.c_double), ("ms_S", C.c_double), ("ms_inner", C.c_double),
+                ("phases_timed", C.c_int32), ("pad_", C.c_int32)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_}
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad_"}
 
 
 class NewtonOpts(C.Structure):
@@ -68,7 +71,10 @@ class StepStats(C.Structure):
     _fields_ = [("status", C.c_int32), ("n_newton", C.c_int32), ("res_norm", C.c_double * 32),
                 ("last", SolveStats), ("it_outer_total", C.c_int32), ("it_A_total", C.c_int32),
                 ("it_S_total", C.c_int32), ("it_I_total", C.c_int32), ("ms_assemble", C.c_double),
-                ("ms_solve", C.c_double), ("ms_total", C.c_double)]
+                ("ms_solve", C.c_double), ("ms_total", C.c_double),
+                ("ms_scale_total", C.c_double), ("ms_setup_total", C.c_double), ("ms_outer_total", C.c_double),
+                ("ms_A_solve_total", C.c_double), ("ms_S_solve_total", C.c_double),
+                ("ms_inner_total", C.c_double)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_ if k not in ("res_norm", "last")}
@@ -100,6 +106,8 @@ SIGNATURES = {
     "vms_schur_hat": (C.c_int, [C.c_void_p, P(Mesh), P(Matrix), C.c_void_p, C.c_void_p, C.c_void_p]),
     "vms_shat_spmv": (C.c_int, [C.c_void_p, P(Mesh), C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]),
     "vms_solve_workspace": (C.c_size_t, [P(Mesh), P(SolverOpts)]),
+    "vms_solve": (C.c_int, [C.c_void_p, P(Mesh), P(Matrix), C.c_void_p, C.c_void_p, C.c_void_p, C.c_double,
+                            P(SolverOpts), C.c_void_p, C.c_size_t, P(SolveStats)]),
     "vms_solve_scaled": (C.c_int, [C.c_void_p, P(Mesh), P(Matrix), C.c_void_p, C.c_void_p, P(SolverOpts),
                                    C.c_void_p, C.c_size_t, P(SolveStats)]),
     "vms_newton_update": (C.c_int, [C.c_void_p, P(Mesh), P(TimeInt), P(State), C.c_void_p, C.c_void_p]),
@@ -107,7 +115,9 @@ SIGNATURES = {
     "vms_step": (C.c_int, [C.c_void_p, P(Mesh), P(Material), P(TimeInt), P(State), C.c_void_p, P(Matrix),
                            P(NewtonOpts), P(SolverOpts), C.c_void_p, C.c_size_t, P(StepStats)]),
     "vms_solve_transpose": (C.c_int, [C.c_void_p, P(Mesh), P(Matrix), P(Matrix), C.c_void_p, C.c_void_p,
-                                      P(SolverOpts), C.c_void_p, C.c_size_t, P(SolveStats)]),
+                                      C.c_double, P(SolverOpts), C.c_void_p, C.c_size_t, P(SolveStats)]),
+    "vms_solve_transpose_scaled": (C.c_int, [C.c_void_p, P(Mesh), P(Matrix), P(Matrix), C.c_void_p, C.c_void_p,
+                                             P(SolverOpts), C.c_void_p, C.c_size_t, P(SolveStats)]),
     "vms_param_sensitivity": (C.c_int, [C.c_void_p, P(Mesh), P(Material), P(TimeInt), P(State), C.c_void_p,
                                         C.c_void_p, C.c_int, P(C.c_double), C.c_void_p, C.c_size_t]),
     "vms_adjoint_workspace": (C.c_size_t, [P(Mesh), P(SolverOpts)]),

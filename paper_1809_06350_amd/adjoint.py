@@ -89,16 +89,29 @@ class TimeHistory:
 
 
 class VmsAdjoint(torch.autograd.Function):
-    """u_N = VmsAdjoint.apply(theta, history); backward gives dJ/dtheta."""
+    """u_N = VmsAdjoint.apply(theta, history); backward gives dJ/dtheta.
+
+    The forward pass keeps its own theta and checkpoint list on the autograd
+    context, so a later ``history.run`` (another forward, a finite-difference
+    evaluation) does not change what this graph's backward differentiates:
+    backward restores both before it runs the adjoint steps.  The gradient is
+    returned on theta's device and in its dtype."""
 
     @staticmethod
     def forward(ctx, theta, history):
-        u = history.run(theta.detach().cpu().numpy())
+        th = theta.detach().cpu().numpy().astype(np.float64).copy()
+        u = history.run(th)
         ctx.history = history
+        ctx.theta = th
+        ctx.checkpoints = history.checkpoints
         ctx.theta_dtype = theta.dtype
+        ctx.theta_device = theta.device
         return u.clone()
 
     @staticmethod
     def backward(ctx, grad_u):
-        g = ctx.history.gradient(grad_u.contiguous())
-        return torch.as_tensor(g, dtype=ctx.theta_dtype), None
+        h = ctx.history
+        h.set_theta(ctx.theta)
+        h.checkpoints = ctx.checkpoints
+        g = h.gradient(grad_u.contiguous())
+        return torch.as_tensor(g, dtype=ctx.theta_dtype, device=ctx.theta_device), None

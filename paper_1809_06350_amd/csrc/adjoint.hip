@@ -145,15 +145,9 @@ size_t sens_bytes(const vms_mesh *mesh) {
 
 }  // namespace
 
-extern "C" int vms_solve_transpose(vms_ctx *ctx, const vms_mesh *mesh, const vms_matrix *K, vms_matrix *Kt,
-                                   const double *rhs_scaled, double *lam_scaled, const vms_solver_opts *opts,
-                                   void *workspace, size_t workspace_bytes, vms_solve_stats *stats) {
-  if (!ctx) return VMS_ERR_ARG;
-  int rc = vms_check_mesh(ctx, mesh);
-  if (rc) return rc;
-  if (!K || !Kt || !K->A || !K->B || !K->C || !K->D || !Kt->A || !Kt->B || !Kt->C || !Kt->D || !opts)
-    return vms_set_error(ctx, VMS_ERR_ARG, "vms_solve_transpose: matrix arrays missing");
-  const bool m32 = opts->precision == VMS_MIXED;
+int vms_launch_transpose(vms_ctx *ctx, const vms_mesh *mesh, const vms_matrix *K, vms_matrix *Kt, bool m32) {
+  if (!Kt || !Kt->A || !Kt->B || !Kt->C || !Kt->D)
+    return vms_set_error(ctx, VMS_ERR_ARG, "transposed solve: storage for the transposed blocks missing");
   if (m32 && (!Kt->A32 || !Kt->B32 || !Kt->C32 || !Kt->D32))
     return vms_set_error(ctx, VMS_ERR_ARG, "mixed precision needs FP32 storage for the transpose");
   const int64_t nnzb = mesh->nnzb;
@@ -161,9 +155,43 @@ extern "C" int vms_solve_transpose(vms_ctx *ctx, const vms_mesh *mesh, const vms
                      K->C, K->D, Kt->A, Kt->B, Kt->C, Kt->D, m32 ? Kt->A32 : nullptr, m32 ? Kt->B32 : nullptr,
                      m32 ? Kt->C32 : nullptr, m32 ? Kt->D32 : nullptr);
   VMS_LAUNCH_CHECK(ctx);
+  Kt->W = K->W;
+  return VMS_OK;
+}
+
+extern "C" int vms_solve_transpose_scaled(vms_ctx *ctx, const vms_mesh *mesh, const vms_matrix *K, vms_matrix *Kt,
+                                          const double *rhs_scaled, double *lam_scaled, const vms_solver_opts *opts,
+                                          void *workspace, size_t workspace_bytes, vms_solve_stats *stats) {
+  if (!ctx) return VMS_ERR_ARG;
+  int rc = vms_check_mesh(ctx, mesh);
+  if (rc) return rc;
+  if (!K || !K->A || !K->B || !K->C || !K->D || !Kt || !opts)
+    return vms_set_error(ctx, VMS_ERR_ARG, "vms_solve_transpose_scaled: matrix arrays missing");
   vms_matrix T = *Kt;
-  T.W = K->W;
+  if ((rc = vms_launch_transpose(ctx, mesh, K, &T, opts->precision == VMS_MIXED))) return rc;
   return vms_solve_scaled(ctx, mesh, &T, rhs_scaled, lam_scaled, opts, workspace, workspace_bytes, stats);
+}
+
+extern "C" int vms_solve_transpose(vms_ctx *ctx, const vms_mesh *mesh, vms_matrix *K, vms_matrix *Kt, const double *g,
+                                   double *lam, double eps_diag, const vms_solver_opts *opts, void *workspace,
+                                   size_t workspace_bytes, vms_solve_stats *stats) {
+  if (!ctx) return VMS_ERR_ARG;
+  int rc = vms_check_solve(ctx, mesh, K, opts, workspace, workspace_bytes, vms_solve_workspace(mesh, opts), stats,
+                           "vms_solve_transpose");
+  if (rc) return rc;
+  if (!g || !lam || !K->W || !Kt) return vms_set_error(ctx, VMS_ERR_ARG, "vms_solve_transpose: missing argument");
+  std::memset(stats, 0, sizeof(*stats));
+  vms_phase_reset(ctx);
+  const auto t0 = std::chrono::steady_clock::now();
+  vms_matrix T = *Kt;
+  rc = vms_solve_full(ctx, mesh, K, g, nullptr, nullptr, lam, eps_diag, opts, workspace, stats, &T);
+  if (rc >= 0) {
+    VMS_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    vms_phase_finish(ctx, stats);
+  }
+  stats->status = rc;
+  stats->ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  return rc;
 }
 
 extern "C" int vms_param_sensitivity(vms_ctx *ctx, const vms_mesh *mesh, const vms_material *mat,
@@ -245,7 +273,7 @@ extern "C" int vms_adjoint_step(vms_ctx *ctx, const vms_mesh *mesh, const vms_ma
   // transposed nested solve, lam = W lam*
   vms_matrix Kt2 = *Kt;
   if (!m32) { Kt2.A32 = Kt2.B32 = Kt2.C32 = Kt2.D32 = nullptr; }
-  rc = vms_solve_transpose(ctx, mesh, K, &Kt2, rhs, lams, opts, sws, sws_bytes, stats);
+  rc = vms_solve_transpose_scaled(ctx, mesh, K, &Kt2, rhs, lams, opts, sws, sws_bytes, stats);
   if (rc < 0) return rc;
   const int solve_rc = rc;
   hipLaunchKernelGGL(k_unscale, dim3(grid1(4 * (int64_t)n)), dim3(VMS_BLOCK), 0, s, 4 * (int64_t)n,

@@ -17,6 +17,18 @@ int vms_set_error(vms_ctx *ctx, int code, const char *fmt, ...) {
   return code;
 }
 
+static void ctx_free(vms_ctx *c) {
+  for (int k = 0; k < 2; ++k)
+    for (hipEvent_t e : c->tev[k]) (void)hipEventDestroy(e);
+  for (hipEvent_t e : c->ph.ev) (void)hipEventDestroy(e);
+  if (c->tflag) (void)hipFree(c->tflag);
+  if (c->dstat) (void)hipFree(c->dstat);
+  if (c->h_i) (void)hipHostFree(c->h_i);
+  if (c->h_d) (void)hipHostFree(c->h_d);
+  if (c->h_post) (void)hipHostFree((void *)c->h_post);
+  delete c;
+}
+
 extern "C" int vms_ctx_create(vms_ctx **out, int device, void *stream) {
   if (!out) return VMS_ERR_ARG;
   *out = nullptr;
@@ -27,29 +39,33 @@ extern "C" int vms_ctx_create(vms_ctx **out, int device, void *stream) {
     delete c;
     return VMS_ERR_HIP;
   }
-  if (hipMalloc((void **)&c->dstat, sizeof(vms_dev_status)) != hipSuccess) {
-    delete c;
+  // everything the context owns on the device is allocated here: the status area, the per-launch
+  // flags of the A-product launch timing and the events of the phase timing
+  bool ok = hipMalloc((void **)&c->dstat, sizeof(vms_dev_status)) == hipSuccess &&
+            hipMalloc((void **)&c->tflag, 2 * VMS_MAX_TIMED * sizeof(int)) == hipSuccess &&
+            hipHostMalloc((void **)&c->h_i, 64 * sizeof(int32_t), hipHostMallocDefault) == hipSuccess &&
+            hipHostMalloc((void **)&c->h_d, 64 * sizeof(double), hipHostMallocDefault) == hipSuccess &&
+            hipHostMalloc((void **)&c->h_post, 64 * sizeof(int32_t), hipHostMallocCoherent | hipHostMallocMapped) ==
+                hipSuccess;
+  if (ok) {
+    c->ph.ev.reserve(2 * VMS_PHASE_EVENTS);
+    for (int k = 0; k < 2 * VMS_PHASE_EVENTS && ok; ++k) {
+      hipEvent_t e;
+      ok = hipEventCreate(&e) == hipSuccess;
+      if (ok) c->ph.ev.push_back(e);
+    }
+  }
+  if (ok) {
+    for (int q = 0; q < 64; ++q) c->h_post[q] = 0;
+    ok = hipMemset(c->dstat, 0, sizeof(vms_dev_status)) == hipSuccess &&
+         hipMemset(c->tflag, 0, 2 * VMS_MAX_TIMED * sizeof(int)) == hipSuccess &&
+         hipDeviceSynchronize() == hipSuccess;
+  }
+  if (!ok) {
+    ctx_free(c);
     return VMS_ERR_HIP;
   }
-  if (hipHostMalloc((void **)&c->h_i, 64 * sizeof(int32_t), hipHostMallocDefault) != hipSuccess ||
-      hipHostMalloc((void **)&c->h_d, 64 * sizeof(double), hipHostMallocDefault) != hipSuccess ||
-      hipHostMalloc((void **)&c->h_post, 64 * sizeof(int32_t), hipHostMallocCoherent | hipHostMallocMapped) !=
-          hipSuccess) {
-    if (c->h_i) (void)hipHostFree(c->h_i);
-    if (c->h_d) (void)hipHostFree(c->h_d);
-    (void)hipFree(c->dstat);
-    delete c;
-    return VMS_ERR_HIP;
-  }
-  for (int q = 0; q < 64; ++q) c->h_post[q] = 0;
-  if (hipMemset(c->dstat, 0, sizeof(vms_dev_status)) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
-    (void)hipHostFree(c->h_i);
-    (void)hipHostFree(c->h_d);
-    (void)hipHostFree((void *)c->h_post);
-    (void)hipFree(c->dstat);
-    delete c;
-    return VMS_ERR_HIP;
-  }
+  vms_phase_reset(c);
   *out = c;
   return VMS_OK;
 }
@@ -57,14 +73,77 @@ extern "C" int vms_ctx_create(vms_ctx **out, int device, void *stream) {
 extern "C" void vms_ctx_destroy(vms_ctx *ctx) {
   if (!ctx) return;
   (void)hipStreamSynchronize(ctx->stream);
-  for (int k = 0; k < 2; ++k)
-    for (hipEvent_t e : ctx->tev[k]) (void)hipEventDestroy(e);
-  if (ctx->tflag) (void)hipFree(ctx->tflag);
-  if (ctx->dstat) (void)hipFree(ctx->dstat);
-  if (ctx->h_i) (void)hipHostFree(ctx->h_i);
-  if (ctx->h_d) (void)hipHostFree(ctx->h_d);
-  if (ctx->h_post) (void)hipHostFree((void *)ctx->h_post);
-  delete ctx;
+  ctx_free(ctx);
+}
+
+// ---- phase timing of the solver --------------------------------------------------
+void vms_phase_reset(vms_ctx *ctx) {
+  vms_phase_timer &t = ctx->ph;
+  t.free_pairs.clear();
+  for (int k = (int)t.ev.size() / 2 - 1; k >= 0; --k) t.free_pairs.push_back(k);
+  t.pending.clear();
+  for (double &m : t.ms) m = 0.0;
+  t.complete = true;
+}
+
+// fold every pending pair whose stop event has completed into ms[] (all of them when wait is set)
+static void phase_harvest(vms_ctx *ctx, bool wait) {
+  vms_phase_timer &t = ctx->ph;
+  size_t keep = 0;
+  for (size_t i = 0; i < t.pending.size(); ++i) {
+    const auto p = t.pending[i];
+    hipEvent_t e0 = t.ev[2 * p.pair], e1 = t.ev[2 * p.pair + 1];
+    bool done = wait ? hipEventSynchronize(e1) == hipSuccess : hipEventQuery(e1) == hipSuccess;
+    if (!done) {
+      if (wait) t.complete = false;
+      else { t.pending[keep++] = p; continue; }
+    } else {
+      float ms = 0.0f;
+      if (hipEventElapsedTime(&ms, e0, e1) == hipSuccess) t.ms[p.kind] += ms;
+      else t.complete = false;
+    }
+    t.free_pairs.push_back(p.pair);
+  }
+  t.pending.resize(keep);
+}
+
+int vms_phase_begin(vms_ctx *ctx) {
+  vms_phase_timer &t = ctx->ph;
+  if (t.free_pairs.empty()) phase_harvest(ctx, false);
+  if (t.free_pairs.empty()) {
+    t.complete = false;
+    return -1;
+  }
+  const int pair = t.free_pairs.back();
+  if (hipEventRecord(t.ev[2 * pair], ctx->stream) != hipSuccess) {
+    t.complete = false;
+    return -1;
+  }
+  t.free_pairs.pop_back();
+  return pair;
+}
+
+void vms_phase_end(vms_ctx *ctx, int pair, int kind) {
+  if (pair < 0) return;
+  vms_phase_timer &t = ctx->ph;
+  if (hipEventRecord(t.ev[2 * pair + 1], ctx->stream) != hipSuccess) {
+    t.complete = false;
+    t.free_pairs.push_back(pair);   // its start event is harmless
+    return;
+  }
+  t.pending.push_back({pair, kind});
+}
+
+void vms_phase_finish(vms_ctx *ctx, vms_solve_stats *stats) {
+  phase_harvest(ctx, true);
+  const vms_phase_timer &t = ctx->ph;
+  stats->ms_scale = t.ms[VMS_PH_SCALE];
+  stats->ms_setup = t.ms[VMS_PH_SETUP];
+  stats->ms_outer = t.ms[VMS_PH_OUTER];
+  stats->ms_A = t.ms[VMS_PH_A];
+  stats->ms_S = t.ms[VMS_PH_S];
+  stats->ms_inner = t.ms[VMS_PH_INNER];
+  stats->phases_timed = t.complete ? 1 : 0;
 }
 
 // ---- low-latency flag readback ---------------------------------------------------
@@ -128,8 +207,7 @@ vms_timed vms_timer_next(vms_ctx *ctx, int kind) {
 extern "C" int vms_ctx_set_timing(vms_ctx *ctx, int enable) {
   if (!ctx) return VMS_ERR_ARG;
   VMS_HIP(ctx, hipStreamSynchronize(ctx->stream));
-  if (enable && !ctx->tflag) VMS_HIP(ctx, hipMalloc((void **)&ctx->tflag, 2 * VMS_MAX_TIMED * sizeof(int)));
-  if (ctx->tflag) VMS_HIP(ctx, hipMemset(ctx->tflag, 0, 2 * VMS_MAX_TIMED * sizeof(int)));
+  VMS_HIP(ctx, hipMemset(ctx->tflag, 0, 2 * VMS_MAX_TIMED * sizeof(int)));
   ctx->tused[0] = ctx->tused[1] = 0;
   ctx->timing = enable != 0;
   return VMS_OK;
@@ -139,6 +217,7 @@ extern "C" int vms_ctx_kernel_time(vms_ctx *ctx, int kind, double *ms_total, int
   if (!ctx || kind < 0 || kind > 1 || !ms_total || !launches) return VMS_ERR_ARG;
   *ms_total = 0.0;
   *launches = 0;
+  if (!ctx->timing) return vms_set_error(ctx, VMS_ERR_STATE, "vms_ctx_kernel_time: launch timing is off");
   VMS_HIP(ctx, hipStreamSynchronize(ctx->stream));
   const int used = ctx->tused[kind];
   if (used == 0) return VMS_OK;
@@ -238,7 +317,7 @@ extern "C" int vms_newton_update(vms_ctx *ctx, const vms_mesh *mesh, const vms_t
   int rc = vms_check_mesh(ctx, mesh);
   if (rc) return rc;
   if ((rc = check_state(ctx, st))) return rc;
-  if (!ti || !W || !x_scaled) return vms_set_error(ctx, VMS_ERR_ARG, "vms_newton_update: bad arguments");
+  if (!ti || !x_scaled) return vms_set_error(ctx, VMS_ERR_ARG, "vms_newton_update: bad arguments");
   const vms_ga ga = vms_genalpha(ti);
   return vms_launch_update(ctx, mesh, ga, st, W, x_scaled);
 }

@@ -685,7 +685,7 @@ __global__ void k_update(int n, vms_ga ga, const uint8_t *dir, const double *W, 
   for (int c = 0; c < 3; ++c) {
     const int64_t o = 3 * (int64_t)i + c;
     if (dir[o4 + c]) continue;
-    const double ddv = W[o4 + c] * x[o4 + c];
+    const double ddv = W ? W[o4 + c] * x[o4 + c] : x[o4 + c];
     const double rk = (sp.du_n[o] + ga.am * (du[o] - sp.du_n[o])) - (sp.v_n[o] + ga.af * (v[o] - sp.v_n[o]));
     const double ddu = ga.c2 / ga.am * ddv - rk / ga.am;
     dv[o] += ddv;
@@ -694,7 +694,7 @@ __global__ void k_update(int n, vms_ga ga, const uint8_t *dir, const double *W, 
     u[o] += gdt * ddu;
   }
   if (!dir[o4 + 3]) {
-    const double ddp = W[o4 + 3] * x[o4 + 3];
+    const double ddp = W ? W[o4 + 3] * x[o4 + 3] : x[o4 + 3];
     dp[i] += ddp;
     p[i] += gdt * ddp;
   }

@@ -1817,6 +1817,7 @@ struct Nested {
       return VMS_OK;
     };
     int st = 0;
+    const int ph = vms_phase_begin(ctx);
     const bool cg = inner ? (o->a_krylov != VMS_AK_GMRES) : (o->a_krylov == VMS_AK_CG);
     // the inner solve of a Schur product (called only from the Schur level's
     // operator) may relax its tolerance with the Schur level's progress
@@ -1825,6 +1826,7 @@ struct Nested {
                             Minv, est, its, st, relax)
                 : gmres_run<T>(ctx, LA, b, x, rtol, atol, maxit, o->orth, PC_BJ33, Minv, false, est, op, its, st,
                                relax);
+    vms_phase_end(ctx, ph, inner ? VMS_PH_INNER : VMS_PH_A);
     if (inner) { stats->n_I_solves++; stats->it_I += its; }
     else { stats->n_A_solves++; stats->it_A += its; }
     return rc;
@@ -1898,13 +1900,17 @@ struct Nested {
   // x_p for the Schur step: a Krylov solve (S by Algorithm 2, or S^ for SIMPLE) or one application
   // of the S^ preconditioner
   int schur_step(const T *b, T *x) {
+    const int ph = vms_phase_begin(ctx);
+    int rc = VMS_OK;
     if (o->schur_solve == VMS_SCHUR_SHAT) {
       shat_prec(b, x);
-      VMS_LAUNCH_CHECK(ctx);
       stats->n_S_solves++;
-      return VMS_OK;
+    } else {
+      rc = (o->precond == VMS_PC_SIMPLE) ? solve_shat(b, x) : solve_S(b, x);
     }
-    return (o->precond == VMS_PC_SIMPLE) ? solve_shat(b, x) : solve_S(b, x);
+    vms_phase_end(ctx, ph, VMS_PH_S);
+    VMS_LAUNCH_CHECK(ctx);
+    return rc;
   }
 
   // z = P_SCR^-1 v (Algorithm 1 and its partial-factorization variants) or P_SIMPLE^-1 v (section 4.3)
@@ -1995,7 +2001,8 @@ struct Outer {
   void carve(Carver &cv, const vms_mesh *m, const vms_solver_opts *o) { L.carve(cv, 4 * (int64_t)m->n_nodes, o->maxit); }
 };
 
-size_t workspace_bytes(const vms_mesh *m, const vms_solver_opts *o) {
+// the nested solve's own workspace (Krylov bases, control blocks, temporaries)
+size_t core_bytes(const vms_mesh *m, const vms_solver_opts *o) {
   Carver cv{nullptr};
   Outer ou;
   ou.carve(cv, m, o);
@@ -2062,7 +2069,9 @@ int solve_impl(vms_ctx *ctx, const vms_mesh *mesh, const vms_matrix *K, const do
   } else {
     ne.A = (const T *)K->A; ne.B = (const T *)K->B; ne.C = (const T *)K->C; ne.D = (const T *)K->D;
   }
+  const int ph_setup = vms_phase_begin(ctx);
   int rc = ne.setup_precond();
+  vms_phase_end(ctx, ph_setup, VMS_PH_SETUP);
   if (rc) return rc;
   KLevel<double> &L = ou.L;
   const int n = mesh->n_nodes;
@@ -2083,8 +2092,10 @@ int solve_impl(vms_ctx *ctx, const vms_mesh *mesh, const vms_matrix *K, const do
   // the outer FGMRES (a few iterations) always reorthogonalises, so its least-squares residual is that of a
   // numerically orthonormal basis whatever the inner levels use
   const int orth_outer = (o->orth == VMS_ORTH_MGS) ? VMS_ORTH_MGS : VMS_ORTH_CGS2;
+  const int ph_outer = vms_phase_begin(ctx);
   rc = gmres_run<double>(ctx, L, rhs, x, o->rtol, o->atol, maxit, orth_outer, PC_NONE, (const double *)nullptr, true,
                          est_outer, op, its, status);
+  vms_phase_end(ctx, ph_outer, VMS_PH_OUTER);
   if (rc) return rc;
   stats->n_outer = its;
   VMS_HIP(ctx, hipMemcpyAsync(ctx->h_d, L.ctrl + L.off.scal, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -2100,34 +2111,124 @@ int solve_impl(vms_ctx *ctx, const vms_mesh *mesh, const vms_matrix *K, const do
   return VMS_OK;
 }
 
+// the unscaled entry points keep rhs* and x* in front of the nested solve's workspace
+size_t workspace_bytes(const vms_mesh *m, const vms_solver_opts *o) {
+  Carver cv{nullptr};
+  cv.take<double>(4 * (int64_t)m->n_nodes);
+  cv.take<double>(4 * (int64_t)m->n_nodes);
+  cv.take<char>(0);
+  return cv.off + core_bytes(m, o);
+}
+
+__global__ void k_wscale(int64_t n4, const double *W, const double *x, double *y) {
+  const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (k < n4) y[k] = W[k] * x[k];
+}
+
+// rhs* = W g on free dofs, 0 on Dirichlet dofs
+__global__ void k_wrhs(int64_t n4, const uint8_t *dir, const double *W, const double *g, double *rhs) {
+  const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (k < n4) rhs[k] = dir[k] ? 0.0 : W[k] * g[k];
+}
+
 }  // namespace
+
+int vms_check_solve(vms_ctx *ctx, const vms_mesh *mesh, const vms_matrix *K, const vms_solver_opts *opts,
+                    const void *workspace, size_t workspace_bytes_in, size_t need, const vms_solve_stats *stats,
+                    const char *who) {
+  int rc = vms_check_mesh(ctx, mesh);
+  if (rc) return rc;
+  if ((rc = check_opts(ctx, opts))) return rc;
+  if (!K || !K->A || !K->B || !K->C || !K->D || !stats || !workspace)
+    return vms_set_error(ctx, VMS_ERR_ARG, "%s: missing argument", who);
+  if (workspace_bytes_in < need)
+    return vms_set_error(ctx, VMS_ERR_WORKSPACE, "%s: workspace too small: %zu < %zu", who, workspace_bytes_in,
+                         need);
+  return VMS_OK;
+}
+
+size_t vms_solve_core_bytes(const vms_mesh *mesh, const vms_solver_opts *opts) { return core_bytes(mesh, opts); }
+
+int vms_solve_core(vms_ctx *ctx, const vms_mesh *mesh, const vms_matrix *K, const double *rhs, double *x,
+                   const vms_solver_opts *opts, void *ws, vms_solve_stats *stats) {
+  if (opts->precision == VMS_MIXED && (!K->A32 || !K->B32 || !K->C32 || !K->D32))
+    return vms_set_error(ctx, VMS_ERR_ARG, "mixed precision needs the FP32 mirrors");
+  ws = (void *)(((uintptr_t)ws + 255) & ~(uintptr_t)255);
+  return opts->precision == VMS_MIXED ? solve_impl<float>(ctx, mesh, K, rhs, x, opts, ws, stats)
+                                      : solve_impl<double>(ctx, mesh, K, rhs, x, opts, ws, stats);
+}
+
+int vms_solve_full(vms_ctx *ctx, const vms_mesh *mesh, vms_matrix *K, const double *g, const double *R,
+                   const double *corr, double *delta, double eps_diag, const vms_solver_opts *opts, void *workspace,
+                   vms_solve_stats *stats, vms_matrix *Kt) {
+  const int64_t n4 = 4 * (int64_t)mesh->n_nodes;
+  Carver cv{(char *)(((uintptr_t)workspace + 255) & ~(uintptr_t)255)};
+  double *rhs = cv.take<double>(n4);
+  double *xs = cv.take<double>(n4);
+  char *core = cv.take<char>(0);
+  const int mirror = (opts->precision == VMS_MIXED && !Kt) ? 1 : 0;
+  const dim3 g4((unsigned)((n4 + VMS_BLOCK - 1) / VMS_BLOCK)), bl(VMS_BLOCK);
+  int ph = vms_phase_begin(ctx);
+  int rc = vms_launch_prepare(ctx, mesh, K, R, corr, R ? rhs : nullptr, eps_diag, mirror);
+  if (rc) return rc;
+  if (g) hipLaunchKernelGGL(k_wrhs, g4, bl, 0, ctx->stream, n4, mesh->dir_mask, (const double *)K->W, g, rhs);
+  const vms_matrix *Ks = K;
+  if (Kt) {
+    if ((rc = vms_launch_transpose(ctx, mesh, K, Kt, opts->precision == VMS_MIXED))) return rc;
+    Ks = Kt;
+  }
+  vms_phase_end(ctx, ph, VMS_PH_SCALE);
+  rc = vms_solve_core(ctx, mesh, Ks, rhs, xs, opts, core, stats);
+  if (rc < 0) return rc;
+  ph = vms_phase_begin(ctx);
+  hipLaunchKernelGGL(k_wscale, g4, bl, 0, ctx->stream, n4, (const double *)K->W, (const double *)xs, delta);
+  vms_phase_end(ctx, ph, VMS_PH_SCALE);
+  VMS_LAUNCH_CHECK(ctx);
+  return rc;
+}
 
 extern "C" size_t vms_solve_workspace(const vms_mesh *mesh, const vms_solver_opts *opts) {
   if (!mesh || !opts || mesh->n_nodes <= 0) return 0;
   return workspace_bytes(mesh, opts);
 }
 
+extern "C" int vms_solve(vms_ctx *ctx, const vms_mesh *mesh, vms_matrix *K, const double *R, const double *corr,
+                         double *delta, double eps_diag, const vms_solver_opts *opts, void *workspace,
+                         size_t workspace_bytes_in, vms_solve_stats *stats) {
+  if (!ctx) return VMS_ERR_ARG;
+  int rc = vms_check_solve(ctx, mesh, K, opts, workspace, workspace_bytes_in,
+                           workspace_bytes(mesh, opts), stats, "vms_solve");
+  if (rc) return rc;
+  if (!R || !delta || !K->W) return vms_set_error(ctx, VMS_ERR_ARG, "vms_solve: missing argument");
+  std::memset(stats, 0, sizeof(*stats));
+  vms_phase_reset(ctx);
+  const auto t0 = std::chrono::steady_clock::now();
+  rc = vms_solve_full(ctx, mesh, K, nullptr, R, corr, delta, eps_diag, opts, workspace, stats, nullptr);
+  if (rc >= 0) {
+    VMS_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    vms_phase_finish(ctx, stats);
+  }
+  stats->status = rc;
+  stats->ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  return rc;
+}
+
 extern "C" int vms_solve_scaled(vms_ctx *ctx, const vms_mesh *mesh, const vms_matrix *K, const double *rhs_scaled,
                                 double *x_scaled, const vms_solver_opts *opts, void *workspace,
                                 size_t workspace_bytes_in, vms_solve_stats *stats) {
   if (!ctx) return VMS_ERR_ARG;
-  int rc = vms_check_mesh(ctx, mesh);
+  int rc = vms_check_solve(ctx, mesh, K, opts, workspace, workspace_bytes_in, core_bytes(mesh, opts), stats,
+                           "vms_solve_scaled");
   if (rc) return rc;
-  if ((rc = check_opts(ctx, opts))) return rc;
-  if (!K || !K->A || !K->B || !K->C || !K->D || !rhs_scaled || !x_scaled || !stats || !workspace)
-    return vms_set_error(ctx, VMS_ERR_ARG, "vms_solve_scaled: missing argument");
-  if (opts->precision == VMS_MIXED && (!K->A32 || !K->B32 || !K->C32 || !K->D32))
-    return vms_set_error(ctx, VMS_ERR_ARG, "mixed precision needs the FP32 mirrors");
-  const size_t need = workspace_bytes(mesh, opts);
-  if (workspace_bytes_in < need)
-    return vms_set_error(ctx, VMS_ERR_WORKSPACE, "workspace too small: %zu < %zu", workspace_bytes_in, need);
-  void *ws = (void *)(((uintptr_t)workspace + 255) & ~(uintptr_t)255);
+  if (!rhs_scaled || !x_scaled) return vms_set_error(ctx, VMS_ERR_ARG, "vms_solve_scaled: missing argument");
   std::memset(stats, 0, sizeof(*stats));
+  vms_phase_reset(ctx);
   const auto t0 = std::chrono::steady_clock::now();
-  if (opts->precision == VMS_MIXED)
-    rc = solve_impl<float>(ctx, mesh, K, rhs_scaled, x_scaled, opts, ws, stats);
-  else
-    rc = solve_impl<double>(ctx, mesh, K, rhs_scaled, x_scaled, opts, ws, stats);
+  rc = vms_solve_core(ctx, mesh, K, rhs_scaled, x_scaled, opts, workspace, stats);
+  if (rc >= 0) {
+    VMS_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    vms_phase_finish(ctx, stats);
+  }
   stats->status = rc;
   stats->ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   return rc;
@@ -2233,10 +2334,10 @@ extern "C" int vms_shat_spmv(vms_ctx *ctx, const vms_mesh *mesh, const void *S, 
 // ---- time step ---------------------------------------------------------------
 extern "C" size_t vms_step_workspace(const vms_mesh *mesh, const vms_solver_opts *opts) {
   if (!mesh || !opts || mesh->n_nodes <= 0) return 0;
-  // the solver's bases and the assembly's element buffers share one region (used in turn)
+  // R, corr and Delta, then one region that the assembly's element buffers and the solver use in turn
   const size_t asm_b = vms_asm_scratch_bytes(mesh, VMS_ASM_TANGENT | VMS_ASM_RKCORR);
   const size_t sol_b = workspace_bytes(mesh, opts);
-  return (sol_b > asm_b ? sol_b : asm_b) + 4 * (size_t)(4 * mesh->n_nodes) * sizeof(double) + 4 * 256;
+  return (sol_b > asm_b ? sol_b : asm_b) + 3 * (size_t)(4 * mesh->n_nodes) * sizeof(double) + 4 * 256;
 }
 
 extern "C" int vms_step(vms_ctx *ctx, const vms_mesh *mesh, const vms_material *mat, const vms_timeint *ti,
@@ -2252,14 +2353,15 @@ extern "C" int vms_step(vms_ctx *ctx, const vms_mesh *mesh, const vms_material *
   const size_t need = vms_step_workspace(mesh, so);
   if (workspace_bytes_in < need)
     return vms_set_error(ctx, VMS_ERR_WORKSPACE, "workspace too small: %zu < %zu", workspace_bytes_in, need);
+  if (so->precision == VMS_MIXED && (!K->A32 || !K->B32 || !K->C32 || !K->D32))
+    return vms_set_error(ctx, VMS_ERR_ARG, "mixed precision needs the FP32 mirrors");
   std::memset(stats, 0, sizeof(*stats));
   const auto t_start = std::chrono::steady_clock::now();
   const int n = mesh->n_nodes;
   Carver cv{(char *)(((uintptr_t)workspace + 255) & ~(uintptr_t)255)};
   double *R = cv.take<double>(4 * (int64_t)n);
   double *corr = cv.take<double>(4 * (int64_t)n);
-  double *rhs = cv.take<double>(4 * (int64_t)n);
-  double *x = cv.take<double>(4 * (int64_t)n);
+  double *delta = cv.take<double>(4 * (int64_t)n);
   char *sws = (char *)cv.take<char>(0);
   const size_t sws_bytes = workspace_bytes_in - (size_t)(sws - (char *)workspace);
   const vms_ga ga = vms_genalpha(ti);
@@ -2267,7 +2369,6 @@ extern "C" int vms_step(vms_ctx *ctx, const vms_mesh *mesh, const vms_material *
   if ((rc = vms_launch_predictor(ctx, mesh, ga, ti->t_n + ti->dt, st))) return rc;
   hipLaunchKernelGGL(k_clear_ints, dim3(1), dim3(64), 0, s, &ctx->dstat->inverted, 1);
   double R0 = -1.0;
-  const bool mixed = so->precision == VMS_MIXED;
   stats->status = VMS_NOT_CONVERGED;
   for (int l = 1; l <= no->l_max; ++l) {
     auto ta = std::chrono::steady_clock::now();
@@ -2292,21 +2393,35 @@ extern "C" int vms_step(vms_ctx *ctx, const vms_mesh *mesh, const vms_material *
     if ((rc = vms_launch_assemble(ctx, mesh, mat, ga, st, f_ext, K, nullptr, no->rk_corr ? corr : nullptr, fl, sws,
                                   sws_bytes)))
       return rc;
-    if ((rc = vms_launch_prepare(ctx, mesh, K, R, no->rk_corr ? corr : nullptr, rhs, no->eps_diag, mixed ? 1 : 0)))
-      return rc;
     VMS_HIP(ctx, hipStreamSynchronize(s));
     auto tb = std::chrono::steady_clock::now();
     stats->ms_assemble += std::chrono::duration<double, std::milli>(tb - ta).count();
+    // solve(K, R) -> Delta: Dirichlet rows, scaling, nested solve, Delta = W x*
     vms_solve_stats ss;
-    rc = vms_solve_scaled(ctx, mesh, K, rhs, x, so, sws, sws_bytes, &ss);
-    stats->ms_solve += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tb).count();
+    std::memset(&ss, 0, sizeof(ss));
+    vms_phase_reset(ctx);
+    rc = vms_solve_full(ctx, mesh, K, nullptr, R, no->rk_corr ? corr : nullptr, delta, no->eps_diag, so, sws, &ss,
+                        nullptr);
+    if (rc >= 0) {
+      VMS_HIP(ctx, hipStreamSynchronize(s));
+      vms_phase_finish(ctx, &ss);
+    }
+    ss.status = rc;
+    ss.ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tb).count();
+    stats->ms_solve += ss.ms_total;
     stats->last = ss;
     stats->it_outer_total += ss.n_outer;
     stats->it_A_total += ss.it_A;
     stats->it_S_total += ss.it_S;
     stats->it_I_total += ss.it_I;
+    stats->ms_scale_total += ss.ms_scale;
+    stats->ms_setup_total += ss.ms_setup;
+    stats->ms_outer_total += ss.ms_outer;
+    stats->ms_A_solve_total += ss.ms_A;
+    stats->ms_S_solve_total += ss.ms_S;
+    stats->ms_inner_total += ss.ms_inner;
     if (rc < 0) return rc;
-    if ((rc = vms_launch_update(ctx, mesh, ga, st, K->W, x))) return rc;
+    if ((rc = vms_launch_update(ctx, mesh, ga, st, nullptr, delta))) return rc;
     stats->n_newton = l;
   }
   VMS_HIP(ctx, hipStreamSynchronize(s));

@@ -30,6 +30,24 @@ struct vms_dev_status {
 };
 
 #define VMS_MAX_TIMED 65536   // timed launches per kind between two reads
+#define VMS_PHASE_EVENTS 1024 // event pairs of the solver's phase timing (created with the context)
+
+// Phases of a solve timed with HIP events (vms_solve_stats.ms_*)
+enum { VMS_PH_SCALE = 0, VMS_PH_SETUP, VMS_PH_OUTER, VMS_PH_A, VMS_PH_S, VMS_PH_INNER, VMS_PH_N };
+
+// Device time of nested solver phases: begin() records a start event on the
+// context stream, end() the stop event; completed pairs are folded into ms[]
+// as their stop events finish (harvest), all of them at finish().  The
+// events come from a fixed pool created with the context; when every pair is
+// in flight a phase goes untimed and `complete` turns false.
+struct vms_phase_timer {
+  std::vector<hipEvent_t> ev;      // 2 * VMS_PHASE_EVENTS, pair k = (ev[2k], ev[2k+1])
+  std::vector<int> free_pairs;
+  struct open_t { int pair, kind; };
+  std::vector<open_t> pending;     // stop recorded, not yet folded in
+  double ms[VMS_PH_N] = {};
+  bool complete = true;
+};
 
 struct vms_ctx {
   int device = 0;
@@ -49,7 +67,16 @@ struct vms_ctx {
   // sequence number into pinned coherent host memory, the host spins on it
   volatile int32_t *h_post = nullptr;   // [8]: seq, flags[4]
   int32_t post_seq = 0;
+  vms_phase_timer ph;
 };
+
+// Phase timing of the solver (see vms_phase_timer): reset before a solve,
+// begin/end around a phase (begin returns -1 when no event pair is free;
+// end(-1) is a no-op), finish after the stream has drained.
+void vms_phase_reset(vms_ctx *ctx);
+int vms_phase_begin(vms_ctx *ctx);
+void vms_phase_end(vms_ctx *ctx, int pair, int kind);
+void vms_phase_finish(vms_ctx *ctx, vms_solve_stats *stats);
 
 // Read the 4 ints at dev (device) into ctx->h_i once every earlier kernel of
 // the stream has finished, by the low-latency path (falls back to a stream
@@ -148,3 +175,25 @@ int vms_launch_predictor(vms_ctx *ctx, const vms_mesh *mesh, const vms_ga &ga, d
                          vms_state *st);
 int vms_launch_spmv(vms_ctx *ctx, const vms_mesh *mesh, const vms_matrix *K, int op,
                     const void *x, void *y, int fp32);
+// Kt = blocks of K^T (FP32 copies too when m32)
+int vms_launch_transpose(vms_ctx *ctx, const vms_mesh *mesh, const vms_matrix *K, vms_matrix *Kt, bool m32);
+
+// ---------------------------------------------------------------------------
+// the nested solve shared by the entry points of solver.hip and adjoint.hip
+
+// argument checks common to the solve entry points (need: the workspace bytes they require)
+int vms_check_solve(vms_ctx *ctx, const vms_mesh *mesh, const vms_matrix *K, const vms_solver_opts *opts,
+                    const void *workspace, size_t workspace_bytes, size_t need, const vms_solve_stats *stats,
+                    const char *who);
+// bytes of the nested solve's own workspace (Krylov bases, control blocks, temporaries)
+size_t vms_solve_core_bytes(const vms_mesh *mesh, const vms_solver_opts *opts);
+// (scaled K) x = rhs by the nested solver; fills the iteration counts, residuals and phase events of
+// stats (the caller resets the phase timer and finishes it)
+int vms_solve_core(vms_ctx *ctx, const vms_mesh *mesh, const vms_matrix *K, const double *rhs, double *x,
+                   const vms_solver_opts *opts, void *ws, vms_solve_stats *stats);
+// Dirichlet rows and scaling of K in place, rhs* = W(-R + corr) (R given) or W g (g given), the
+// nested solve of W K W (Kt == NULL) or of its transpose (blocks written to Kt), delta = W x*.
+// Workspace: rhs*, x*, then the nested solve's (vms_solve_workspace bytes).
+int vms_solve_full(vms_ctx *ctx, const vms_mesh *mesh, vms_matrix *K, const double *g, const double *R,
+                   const double *corr, double *delta, double eps_diag, const vms_solver_opts *opts, void *workspace,
+                   vms_solve_stats *stats, vms_matrix *Kt);

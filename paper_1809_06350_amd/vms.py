@@ -283,19 +283,45 @@ class Problem:
                     "vms_solve_scaled", allow_nc=allow_nc)
         return x, stats.as_dict()
 
-    def newton_update(self, st, ti, K, x):
-        self._check(self.lib.vms_newton_update(self.ctx, C.byref(self.cmesh), C.byref(ti), C.byref(self.cstate(st)),
-                                               _p(K.W), _p(x)), "vms_newton_update")
+    def solve(self, K, R, opts, corr=None, eps_diag=1e-15, delta=None, allow_nc=False):
+        """solve(K, R) -> Delta (vms_solve): K as assembled (overwritten with W K W, K.W written)."""
+        nb = self.lib.vms_solve_workspace(C.byref(self.cmesh), C.byref(opts))
+        ws = self.workspace(nb)
+        if delta is None:
+            delta = torch.empty_like(R)
+        stats = L.SolveStats()
+        self._check(self.lib.vms_solve(self.ctx, C.byref(self.cmesh), C.byref(K.c()), _p(R), _p(corr), _p(delta),
+                                       eps_diag, C.byref(opts), _p(ws), ws.numel(), C.byref(stats)),
+                    "vms_solve", allow_nc=allow_nc)
+        return delta, stats.as_dict()
 
-    def solve_transpose(self, K, Kt, rhs, opts, x=None, allow_nc=False):
+    def newton_update(self, st, ti, K, x):
+        """Stage 2 and the update from x = x* (with K.W) or, for K = None, from x = Delta."""
+        self._check(self.lib.vms_newton_update(self.ctx, C.byref(self.cmesh), C.byref(ti), C.byref(self.cstate(st)),
+                                               _p(K.W) if K is not None else None, _p(x)), "vms_newton_update")
+
+    def solve_transpose(self, K, Kt, g, opts, eps_diag=1e-15, lam=None, allow_nc=False):
+        """K^T lam = g (vms_solve_transpose): K as assembled (overwritten with W K W, K.W written)."""
+        nb = self.lib.vms_solve_workspace(C.byref(self.cmesh), C.byref(opts))
+        ws = self.workspace(nb)
+        if lam is None:
+            lam = torch.empty_like(g)
+        stats = L.SolveStats()
+        self._check(self.lib.vms_solve_transpose(self.ctx, C.byref(self.cmesh), C.byref(K.c()), C.byref(Kt.c()),
+                                                 _p(g), _p(lam), eps_diag, C.byref(opts), _p(ws), ws.numel(),
+                                                 C.byref(stats)), "vms_solve_transpose", allow_nc=allow_nc)
+        return lam, stats.as_dict()
+
+    def solve_transpose_scaled(self, K, Kt, rhs, opts, x=None, allow_nc=False):
         nb = self.lib.vms_solve_workspace(C.byref(self.cmesh), C.byref(opts))
         ws = self.workspace(nb + 512)
         if x is None:
             x = torch.empty_like(rhs)
         stats = L.SolveStats()
-        self._check(self.lib.vms_solve_transpose(self.ctx, C.byref(self.cmesh), C.byref(K.c()), C.byref(Kt.c()),
-                                                 _p(rhs), _p(x), C.byref(opts), _p(ws), ws.numel(),
-                                                 C.byref(stats)), "vms_solve_transpose", allow_nc=allow_nc)
+        self._check(self.lib.vms_solve_transpose_scaled(self.ctx, C.byref(self.cmesh), C.byref(K.c()),
+                                                        C.byref(Kt.c()), _p(rhs), _p(x), C.byref(opts), _p(ws),
+                                                        ws.numel(), C.byref(stats)),
+                    "vms_solve_transpose_scaled", allow_nc=allow_nc)
         return x, stats.as_dict()
 
     def adjoint_workspace(self, opts):

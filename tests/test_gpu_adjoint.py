@@ -81,7 +81,7 @@ def test_transposed_solve_matches_oracle(name, a_krylov):
     rhs[disc.dof_dir] = 0.0
     Kt = prob.new_matrix()
     opts = V.solver_opts(rtol=1e-11, rtol_A=1e-12, rtol_S=1e-12, rtol_I=1e-13, a_krylov=a_krylov, cg_symmetrise=0)
-    lam, stats = prob.solve_transpose(K, Kt, torch.from_numpy(rhs.reshape(-1, 4)).cuda(), opts)
+    lam, stats = prob.solve_transpose_scaled(K, Kt, torch.from_numpy(rhs.reshape(-1, 4)).cuda(), opts)
     lg = lam.cpu().numpy().ravel()
     print(f"[transpose] {name} {stats}", flush=True)
     # lambda solves the transposed system of the GPU's scaled matrix, which is the
@@ -95,6 +95,47 @@ def test_transposed_solve_matches_oracle(name, a_krylov):
     assert np.linalg.norm(Kg.T @ lg - rhs) <= 1e-10 * np.linalg.norm(rhs) + floor
     assert np.linalg.norm(Ks.T @ lg - rhs) <= 1e-10 * np.linalg.norm(rhs) + floor + 1e-11 * np.linalg.norm(
         abs(Ks).T @ np.abs(lg))
+
+
+@pytest.mark.parametrize("name,precision", [("cube", V.FP64), ("tube", V.FP64), ("cube", V.MIXED)])
+def test_unscaled_transposed_solve_matches_lu(name, precision):
+    """vms_solve_transpose: K as assembled in, K^T lam = g out (Dirichlet rows and
+    columns of K replaced by the identity, lam = 0 there), against sparse LU on
+    the oracle's K^T."""
+    import scipy.sparse.linalg as spla
+    mesh, mat, ti, pmask, sel = _case(name)
+    prob = _prob(mesh, mat)
+    sn, s1 = _consistent_states(mesh, ti, 6)
+    st = _gpu_state(prob, sn, s1)
+    tiv = V.time_int(ti.dt, ti.rho_inf, 0.0, ti.n_steps * ti.dt)
+    mixed = precision == V.MIXED
+    K, _, _ = prob.assemble(st, tiv, V.ASM_TANGENT)
+    if mixed:
+        K2 = prob.new_matrix(mirror32=True)
+        for a, b in ((K2.A, K.A), (K2.B, K.B), (K2.C, K.C), (K2.D, K.D)):
+            a.copy_(b)
+        K = K2
+    am, af, gm = E.genalpha(ti.rho_inf)
+    disc = AS.Discretization(mesh, mat)
+    Ko = disc.tangent(NW.stage(sn, s1, am, af), (am, af, gm, ti.dt))
+    Kd, _ = AS.apply_dirichlet(Ko, np.zeros(Ko.shape[0]), disc.dof_dir)
+    g = np.random.default_rng(3).standard_normal(4 * mesh.n_nodes)
+    opts = (V.solver_opts(rtol=1e-11, rtol_A=1e-6, rtol_S=1e-6, rtol_I=1e-6, precision=V.MIXED, maxit=400)
+            if mixed else V.solver_opts(rtol=1e-11, rtol_A=1e-12, rtol_S=1e-12, rtol_I=1e-13))
+    Kt = prob.new_matrix(mirror32=mixed)
+    lam, stats = prob.solve_transpose(K, Kt, torch.from_numpy(g.reshape(-1, 4)).cuda(), opts)
+    lg = lam.cpu().numpy().ravel()
+    gd = np.where(disc.dof_dir, 0.0, g)
+    lo = spla.splu(Kd.T.tocsc()).solve(gd)
+    print(f"[transpose unscaled] {name} precision={precision} {stats}", flush=True)
+    assert stats["status"] == 0 and stats["phases_timed"] == 1
+    assert np.all(lg[disc.dof_dir] == 0.0)
+    W = AS.scaling(Kd)
+    assert rel_err(K.W.cpu().numpy().ravel(), W) < 1e-13
+    # residual of the scaled transposed system (W K^T W) lam* = W g, lam* = lam / W
+    Ks = Kd.multiply(W[:, None]).multiply(W[None, :]).tocsr()
+    assert np.linalg.norm(Ks.T @ (lg / W) - W * gd) <= 1e-10 * np.linalg.norm(W * gd)
+    assert np.linalg.norm(lg - lo) <= 1e-7 * np.linalg.norm(lo)
 
 
 @pytest.mark.parametrize("name", ["cube", "tube", "strip"])
@@ -173,3 +214,40 @@ def test_autograd_gradient_matches_oracle(name, precision):
     assert rel_err(u.detach().cpu().numpy(), uo) < 1e-9
     for k in params:
         assert gg[k] == pytest.approx(go[k], rel=1e-5, abs=0.0), AD.PARAMS[k]
+
+
+def test_backward_after_a_second_forward_uses_its_own_theta():
+    """Two graphs through one TimeHistory at different theta: the first graph's
+    backward, run after the second forward, must still give the gradient at the
+    first theta and trajectory (against the oracle's adjoint gradient there),
+    and the gradient comes back on theta's device."""
+    mesh, mat, ti, pmask, sel = _case("cube")
+    prob = _prob(mesh, mat)
+    sopts = V.solver_opts(rtol=1e-12, rtol_A=1e-12, rtol_S=1e-12, rtol_I=1e-13)
+    hist = GA.TimeHistory(prob, ti, 2, V.newton_opts(tol_R=1e-12), sopts, sopts, pmask)
+    theta0 = AD.theta_of(mesh, mat)
+    states = AD.forward(mesh, mat, ti, 2)
+    uo = states[-1]["u"]
+    selt = torch.from_numpy(sel).cuda()
+    target = torch.from_numpy(uo[sel] * 0.9).cuda()
+    t1 = torch.tensor(theta0, dtype=torch.float64, device="cuda:0", requires_grad=True)
+    u1 = GA.VmsAdjoint.apply(t1, hist)
+    J1 = 0.5 * ((u1[selt] - target) ** 2).sum()
+    th2 = theta0.copy()
+    th2[0] *= 1.3
+    th2[1] *= 0.7
+    t2 = torch.tensor(th2, dtype=torch.float64, device="cuda:0", requires_grad=True)
+    u2 = GA.VmsAdjoint.apply(t2, hist)
+    J2 = 0.5 * ((u2[selt] - target) ** 2).sum()
+    J1.backward()
+    _, dJo = AD.objective(uo, sel, uo[sel] * 0.9)
+    params = tuple(k for k in range(5) if pmask & (1 << k))
+    go = AD.adjoint_gradient(mesh, mat, ti, theta0, states, dJo, params)
+    assert t1.grad.device == t1.device
+    g1 = t1.grad.cpu().numpy()
+    print(f"[two graphs] first graph's gradient {g1} oracle {go}", flush=True)
+    for k in params:
+        assert g1[k] == pytest.approx(go[k], rel=1e-5, abs=0.0)
+    J2.backward()
+    assert np.all(np.isfinite(t2.grad.cpu().numpy()))
+    assert not np.allclose(t2.grad.cpu().numpy()[list(params)], g1[list(params)], rtol=1e-3)
