@@ -26,13 +26,20 @@ def rest_state(mesh):
     return st
 
 
-def predictor(mesh, state_n, gm, t_np1):
-    """y_(0) = y_n, y-dot_(0) = (gamma - 1)/gamma y-dot_n; Dirichlet components
-    take their prescribed motion u = g(t), v = g-dot(t), v-dot = 0."""
+def predictor(mesh, state_n, gm, t_np1, lift=False):
+    """y_(0) = y_n, y-dot_(0) = (gamma - 1)/gamma y-dot_n (section 3.3, predictor
+    stage).  Preset form (lift=False): the Dirichlet components take their
+    prescribed motion u = g(t), v = g-dot(t), v-dot = 0 at once.  Lifted form
+    (lift=True): every node takes the predictor, v-dot = 0 on the Dirichlet
+    components, and the prescribed displacement arrives through R-bar_k in the
+    first corrector (newton_update)."""
     it = {k: state_n[k].copy() for k in KEYS_VAL}
     for k in KEYS_RATE:
         it[k] = (gm - 1.0) / gm * state_n[k]
     vm = mesh.dir_mask[:, 0:3].astype(bool)
+    if lift:
+        it["dv"][vm] = 0.0
+        return it
     it["u"][vm] = (mesh.dir_vel * t_np1)[vm]
     it["v"][vm] = mesh.dir_vel[vm]
     it["du"][vm] = mesh.dir_vel[vm]
@@ -90,18 +97,22 @@ def solve_scaled(K, rhs, dof_dir, eps_diag=1.0e-15, scaled=True):
     return W * xs
 
 
-def newton_update(disc, ti, it, x, Rk):
+def newton_update(disc, ti, it, x, Rk, lift=False):
     """Stage 2 and the update: Delta u-dot = (af g dt/am) Delta v-dot - R-bar_k/am;
-    y-dot_(l) = y-dot_(l-1) + Delta y-dot; y_(l) = y_(l-1) + gamma dt Delta y-dot."""
+    y-dot_(l) = y-dot_(l-1) + Delta y-dot; y_(l) = y_(l-1) + gamma dt Delta y-dot.
+    Delta v-dot = 0 on Dirichlet components.  Preset form: Delta u-dot = 0 there
+    too.  Lifted form: Delta u-dot = -R-bar_k/am there, which carries u to
+    g(t_{n+1}) in the first corrector."""
     am, af, gm = genalpha(ti.rho_inf)
     c2 = af * gm * ti.dt
     n = disc.n
     x = x.reshape(n, 4)
     d = {"dv": x[:, 0:3].copy(), "dp": x[:, 3].copy()}
-    d["du"] = (c2 / am) * d["dv"] - Rk / am
-    d["du"][disc.vmask] = 0.0
     d["dv"][disc.vmask] = 0.0
     d["dp"][disc.pmask] = 0.0
+    d["du"] = (c2 / am) * d["dv"] - Rk / am
+    if not lift:
+        d["du"][disc.vmask] = 0.0
     out = {}
     for rk, vk in (("du", "u"), ("dp", "p"), ("dv", "v")):
         out[rk] = it[rk] + d[rk]
@@ -110,17 +121,22 @@ def newton_update(disc, ti, it, x, Rk):
 
 
 def time_step(disc, ti, state_n, t_n, tol_R=1e-10, tol_A=1e-50, l_max=20,
-              rk_corr=True, solver=None):
+              rk_corr=True, solver=None, lift=False):
     """One generalized-alpha step by the predictor multi-corrector algorithm.
 
     ``solver(K, rhs, dof_dir) -> Delta`` defaults to the scaled sparse LU.
+    ``lift`` selects the lifted Dirichlet predictor (predictor, newton_update);
+    it needs rk_corr, whose right-hand-side term K_{.,u-dot} R-bar_k / alpha_m
+    then spreads the boundary motion into the interior.
     Returns (state_{n+1}, info) with the residual history and a flag.
     """
+    if lift and not rk_corr:
+        raise ValueError("the lifted Dirichlet predictor needs rk_corr")
     am, af, gm = genalpha(ti.rho_inf)
     solver = solver or solve_scaled
     t_np1 = t_n + ti.dt
     load = load_scale(ti, t_n + af * ti.dt)
-    it = predictor(disc.mesh, state_n, gm, t_np1)
+    it = predictor(disc.mesh, state_n, gm, t_np1, lift)
     norms, R0, converged = [], None, False
     for l in range(1, l_max + 1):
         st = stage(state_n, it, am, af)
@@ -135,5 +151,5 @@ def time_step(disc, ti, state_n, t_n, tol_R=1e-10, tol_A=1e-50, l_max=20,
             break
         K, rhs, _, _ = linear_system(disc, ti, st, load, rk_corr)
         x = solver(K, rhs, disc.dof_dir)
-        it, _ = newton_update(disc, ti, it, x, Rk)
+        it, _ = newton_update(disc, ti, it, x, Rk, lift)
     return it, {"norms": norms, "converged": converged, "n_newton": len(norms) - 1}

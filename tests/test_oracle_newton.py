@@ -233,3 +233,51 @@ def test_simple_is_exact_when_A_is_diagonal():
     x, its, _ = KR.fgmres(lambda z: Kp @ z, rp, KR.simple_preconditioner(A, B, C, D), rtol=1e-10, maxit=200)
     assert its > 2
     np.testing.assert_allclose(Kp @ x, rp, rtol=0, atol=1e-9 * np.linalg.norm(rp))
+
+
+def test_lifted_dirichlet_predictor_reaches_the_preset_solution():
+    """The lifted predictor changes the Newton path only: the converged steps
+    satisfy the same equations (R = 0 on free dofs, R-bar_k = 0, the prescribed
+    motion on Dirichlet dofs), so both forms reach the same state."""
+    mesh, mat, ti = synth.tube_case(1, 8, 4, dt=0.05, n_steps=20)
+    disc = AS.Discretization(mesh, mat)
+    vm = mesh.dir_mask[:, 0:3].astype(bool)
+    sa, sb = NW.rest_state(mesh), NW.rest_state(mesh)
+    for s in range(3):
+        sa, ia = NW.time_step(disc, ti, sa, s * ti.dt, tol_R=1e-12, tol_A=1e-9)
+        sb, ib = NW.time_step(disc, ti, sb, s * ti.dt, tol_R=1e-12, tol_A=1e-9, lift=True)
+        assert ia["converged"] and ib["converged"]
+        g = mesh.dir_vel * (s + 1) * ti.dt
+        assert np.abs(sb["u"][vm] - g[vm]).max() <= 1e-14
+        assert np.abs(sb["v"][vm] - mesh.dir_vel[vm]).max() == 0.0
+        for k in ("u", "p", "v", "du", "dp", "dv"):
+            scale = np.abs(sa[k]).max()
+            assert np.abs(sa[k] - sb[k]).max() <= 1e-8 * scale, (s, k)
+
+
+def test_lifted_first_corrector_carries_the_boundary_motion():
+    """With the lifted predictor the Dirichlet displacement stays at g(t_n) in
+    the predictor and reaches g(t_{n+1}) after the first corrector, through
+    Delta u-dot = -R-bar_k / alpha_m; R-bar_k then vanishes everywhere (the
+    remark after the block reduction), and the interior has moved with the
+    boundary (the right-hand-side term K_{.,u-dot} R-bar_k / alpha_m)."""
+    mesh, mat, ti = synth.tube_case(1, 8, 4, dt=0.05, n_steps=20)
+    disc = AS.Discretization(mesh, mat)
+    am, af, gm = E.genalpha(ti.rho_inf)
+    vm = mesh.dir_mask[:, 0:3].astype(bool)
+    sn = NW.rest_state(mesh)
+    it = NW.predictor(mesh, sn, gm, ti.dt, lift=True)
+    assert np.abs(it["u"]).max() == 0.0 and np.abs(it["dv"][vm]).max() == 0.0
+    st = NW.stage(sn, it, am, af)
+    Rk = st["du"] - st["v"]
+    K, rhs, _, _ = NW.linear_system(disc, ti, st, 0.0)
+    x = NW.solve_scaled(K, rhs, disc.dof_dir)
+    it1, _ = NW.newton_update(disc, ti, it, x, Rk, lift=True)
+    g = mesh.dir_vel * ti.dt
+    np.testing.assert_allclose(it1["u"][vm], g[vm], rtol=0.0, atol=1e-15)
+    st1 = NW.stage(sn, it1, am, af)
+    assert np.abs(st1["du"] - st1["v"]).max() <= 1e-14 * np.abs(Rk).max()
+    free_top = (~vm[:, 2]) & (mesh.X[:, 2] > 1.0)
+    assert np.all(it1["u"][free_top, 2] > 0.0)
+    with pytest.raises(ValueError):
+        NW.time_step(disc, ti, sn, 0.0, rk_corr=False, lift=True)
