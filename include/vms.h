@@ -15,7 +15,8 @@
  *    after vms_ctx_create: solver scratch comes from a caller-provided
  *    workspace.  vms_ctx_create allocates a small device status area, the
  *    512 KB launch-timing flags, pinned host buffers and a fixed pool of HIP
- *    events (the solver's phase timing).
+ *    events (the solver's phase timing).  The code object also holds one
+ *    static 64 MiB device array per GPU, the workspace of vms_step_noalloc.
  *  - Streams: all kernels are enqueued on the stream given to
  *    vms_ctx_create (in order).  Calls marked [async] return without waiting;
  *    calls marked [sync] wait for the stream work they need to take host-side
@@ -44,6 +45,7 @@
 
 #define VMS_MAX_TETS 134217727   /* 2^27 - 1: 16 * n_tets fits in int32 */
 #define VMS_MAX_SHAT_ROW 128     /* longest off-diagonal row of the distance-2 pattern, in slots */
+#define VMS_NOALLOC_SCRATCH_BYTES (64u << 20) /* static device scratch of vms_step_noalloc, per GPU */
 
 #ifdef __cplusplus
 extern "C" {
@@ -488,6 +490,33 @@ int vms_adjoint_step(vms_ctx *ctx, const vms_mesh *mesh, const vms_material *mat
                      const double *ybar1, const double *ydbar1, double *ybar0, double *ydbar0, int pmask,
                      double *dJdtheta, const vms_solver_opts *opts, double eps_diag, void *workspace,
                      size_t workspace_bytes, vms_solve_stats *stats);
+
+/* ---- allocation-free time step ------------------------------------------ */
+
+/* vms_step with no workspace argument, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  The workspace is a static device array of
+ * VMS_NOALLOC_SCRATCH_BYTES (64 MiB) per GPU, which the library holds from
+ * its first use on that GPU until the process ends; vms_ctx_create takes its
+ * device address.  Arguments, outputs and status codes as vms_step; the
+ * caller still owns the state, K and f_ext.  This call allocates nothing and
+ * creates no HIP objects.
+ *  - VMS_ERR_WORKSPACE (nothing launched) if vms_step_workspace(mesh, sopts)
+ *    exceeds the scratch (with the default solver options: cubes up to about
+ *    10^3 hexes, 8 000 tetrahedra);
+ *  - VMS_ERR_STATE if launch timing is on (vms_ctx_set_timing creates its
+ *    events on demand) or the context has no scratch (device index >= 64).
+ * Every call on one GPU shares that GPU's array, which keeps the last call's
+ * contents; vms_step writes every workspace buffer before reading it, so no
+ * part of it has to start at zero.  Calls on one GPU are serialised among the
+ * host threads of the process, but calls that overlap on the device (two
+ * streams or contexts of one GPU with kernels in flight at once) race on the
+ * scratch and give undefined results.  [sync] */
+int vms_step_noalloc(vms_ctx *ctx, const vms_mesh *mesh, const vms_material *mat, const vms_timeint *ti,
+                     vms_state *st, const double *f_ext, vms_matrix *K, const vms_newton_opts *nopts,
+                     const vms_solver_opts *sopts, vms_step_stats *stats);
+/* VMS_NOALLOC_SCRATCH_BYTES, for bindings that cannot read the macro. */
+size_t vms_noalloc_scratch_bytes(void);
 
 #ifdef __cplusplus
 }

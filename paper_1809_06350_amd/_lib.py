@@ -114,6 +114,9 @@ SIGNATURES = {
     "vms_step_workspace": (C.c_size_t, [P(Mesh), P(SolverOpts)]),
     "vms_step": (C.c_int, [C.c_void_p, P(Mesh), P(Material), P(TimeInt), P(State), C.c_void_p, P(Matrix),
                            P(NewtonOpts), P(SolverOpts), C.c_void_p, C.c_size_t, P(StepStats)]),
+    "vms_step_noalloc": (C.c_int, [C.c_void_p, P(Mesh), P(Material), P(TimeInt), P(State), C.c_void_p,
+                                   P(Matrix), P(NewtonOpts), P(SolverOpts), P(StepStats)]),
+    "vms_noalloc_scratch_bytes": (C.c_size_t, []),
     "vms_solve_transpose": (C.c_int, [C.c_void_p, P(Mesh), P(Matrix), P(Matrix), C.c_void_p, C.c_void_p,
                                       C.c_double, P(SolverOpts), C.c_void_p, C.c_size_t, P(SolveStats)]),
     "vms_solve_transpose_scaled": (C.c_int, [C.c_void_p, P(Mesh), P(Matrix), P(Matrix), C.c_void_p, C.c_void_p,

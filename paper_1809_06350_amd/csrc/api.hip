@@ -2,8 +2,35 @@
 #include <cstring>
 
 #include <atomic>
+#include <mutex>
 
 #include "vms_internal.h"
+
+// Workspace of vms_step_noalloc: one static device array per GPU, held from the
+// code object's load until the process ends.  In host code `scratch` names a
+// host-side stand-in; its device address comes from hipGetSymbolAddress, taken
+// once per device in vms_ctx_create with that device current.
+static __device__ __align__(256) unsigned char scratch[VMS_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+std::mutex g_scratch_call_mu[kMaxDevices];
+}  // namespace
+
+// device address of this device's scratch array (the current device must be `device`)
+static int scratch_address(int device, void **out) {
+  if (device < 0 || device >= kMaxDevices) return VMS_ERR_ARG;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void *p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return VMS_ERR_HIP;
+    g_scratch_ptr[device] = p;
+  }
+  *out = g_scratch_ptr[device];
+  return VMS_OK;
+}
 
 int vms_set_error(vms_ctx *ctx, int code, const char *fmt, ...) {
   if (ctx) {
@@ -61,6 +88,7 @@ extern "C" int vms_ctx_create(vms_ctx **out, int device, void *stream) {
          hipMemset(c->tflag, 0, 2 * VMS_MAX_TIMED * sizeof(int)) == hipSuccess &&
          hipDeviceSynchronize() == hipSuccess;
   }
+  if (ok && device < kMaxDevices) ok = scratch_address(device, &c->scratch) == VMS_OK;
   if (!ok) {
     ctx_free(c);
     return VMS_ERR_HIP;
@@ -320,4 +348,28 @@ extern "C" int vms_newton_update(vms_ctx *ctx, const vms_mesh *mesh, const vms_t
   if (!ti || !x_scaled) return vms_set_error(ctx, VMS_ERR_ARG, "vms_newton_update: bad arguments");
   const vms_ga ga = vms_genalpha(ti);
   return vms_launch_update(ctx, mesh, ga, st, W, x_scaled);
+}
+
+// ---- allocation-free time step ----------------------------------------------------
+extern "C" size_t vms_noalloc_scratch_bytes(void) { return (size_t)VMS_NOALLOC_SCRATCH_BYTES; }
+
+extern "C" int vms_step_noalloc(vms_ctx *ctx, const vms_mesh *mesh, const vms_material *mat, const vms_timeint *ti,
+                                vms_state *st, const double *f_ext, vms_matrix *K, const vms_newton_opts *nopts,
+                                const vms_solver_opts *sopts, vms_step_stats *stats) {
+  if (!ctx) return VMS_ERR_ARG;
+  if (!mesh || !sopts) return vms_set_error(ctx, VMS_ERR_ARG, "vms_step_noalloc: missing argument");
+  if (!ctx->scratch) return vms_set_error(ctx, VMS_ERR_STATE, "vms_step_noalloc: no device scratch on this context");
+  // launch timing creates its events on demand; this entry point creates nothing
+  if (ctx->timing) return vms_set_error(ctx, VMS_ERR_STATE, "vms_step_noalloc: launch timing is on");
+  const size_t need = vms_step_workspace(mesh, sopts);
+  if (need == 0) return vms_set_error(ctx, VMS_ERR_ARG, "vms_step_noalloc: empty mesh");
+  if (need > (size_t)VMS_NOALLOC_SCRATCH_BYTES)
+    return vms_set_error(ctx, VMS_ERR_WORKSPACE,
+                         "vms_step_noalloc: the step needs %zu bytes of workspace, the static scratch holds %zu",
+                         need, (size_t)VMS_NOALLOC_SCRATCH_BYTES);
+  // one call at a time per device from this process's host threads; calls on other streams
+  // still race on the device (documented in the header)
+  std::lock_guard<std::mutex> lk(g_scratch_call_mu[ctx->device]);
+  return vms_step(ctx, mesh, mat, ti, st, f_ext, K, nopts, sopts, ctx->scratch, (size_t)VMS_NOALLOC_SCRATCH_BYTES,
+                  stats);
 }

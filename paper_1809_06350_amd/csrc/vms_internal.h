@@ -68,6 +68,7 @@ struct vms_ctx {
   volatile int32_t *h_post = nullptr;   // [8]: seq, flags[4]
   int32_t post_seq = 0;
   vms_phase_timer ph;
+  void *scratch = nullptr;           // device address of this device's static scratch (vms_step_noalloc)
 };
 
 // Phase timing of the solver (see vms_phase_timer): reset before a solve,

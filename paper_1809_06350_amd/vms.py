@@ -357,6 +357,17 @@ class Problem:
         self.dfibre = torch.from_numpy(np.ascontiguousarray(dfibre, dtype=np.float64)).to(self.dev)
         self.cmesh.fibre = _p(self.d["fibre"])
 
+    def step_noalloc(self, st, ti, nopts, sopts, K=None, allow_nc=False):
+        """One time step through vms_step_noalloc (the library's static device scratch as workspace)."""
+        if K is None:
+            K = self.new_matrix(mirror32=(sopts.precision == MIXED))
+        stats = L.StepStats()
+        self._check(self.lib.vms_step_noalloc(self.ctx, C.byref(self.cmesh), C.byref(self.cmat), C.byref(ti),
+                                              C.byref(self.cstate(st)), _p(self.f_ext), C.byref(K.c()),
+                                              C.byref(nopts), C.byref(sopts), C.byref(stats)),
+                    "vms_step_noalloc", allow_nc=allow_nc)
+        return stats.as_dict(), K
+
     def step(self, st, ti, nopts, sopts, K=None, allow_nc=False):
         if K is None:
             K = self.new_matrix(mirror32=(sopts.precision == MIXED))

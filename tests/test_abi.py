@@ -211,3 +211,18 @@ def test_shat_offsets_refused_when_too_far():
     assert lib.vms_setup_build(n, 1, tets.ctypes.data, 0, None, *args, off.ctypes.data,
                                *[a.ctypes.data for a in tail]) == -1
     assert lib.vms_setup_build(n, 1, tets.ctypes.data, 0, None, *args, None, *[a.ctypes.data for a in tail]) == 0
+
+
+def test_noalloc_scratch_size_and_limit():
+    """The static scratch of vms_step_noalloc is 64 MiB; the default solver
+    options fit an 8^3 cube's time step in it and not a 12^3 one (the entry
+    point refuses the latter before launching anything)."""
+    lib = L.load()
+    assert lib.vms_noalloc_scratch_bytes() == 64 << 20
+    from paper_1809_06350_amd import vms as V
+    for N, fits in ((8, True), (12, False)):
+        mesh = L.Mesh()
+        mesh.n_nodes, mesh.n_tets, mesh.slot_width = (N + 1) ** 3, 6 * N ** 3, 16
+        mesh.nnzb, mesh.shat_width = 16 * (N + 1) ** 3, 64
+        need = lib.vms_step_workspace(C.byref(mesh), C.byref(V.solver_opts()))
+        assert (need <= lib.vms_noalloc_scratch_bytes()) == fits
