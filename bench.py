@@ -324,6 +324,9 @@ def main():
     ap.add_argument("--stretch", type=float, default=1.001,
                     help="tube: axial stretch reached after the 20-step ramp (1.001 at dt = 1e-3: a stretch of "
                          "1.5 over 20 steps of 1e-3 moves the end face by several element lengths per step)")
+    ap.add_argument("--dir-lift", default="auto", choices=["auto", "on", "off"],
+                    help="Dirichlet velocity components in the predictor: lifted (the prescribed motion enters "
+                         "through R-bar_k in the first corrector) or preset; auto = lifted for the tube")
     ap.add_argument("--nu", type=float, default=0.499)
     ap.add_argument("--kd", type=float, default=0.226, help="strip: fibre dispersion k_d")
     ap.add_argument("--fibre-deg", type=float, default=49.98,
@@ -410,7 +413,8 @@ def main():
         prob.set_fibres(*synth.fibre_field(mesh, mesh.meta["fibre_rad"]))
     n, nnzb = mesh.n_nodes, int(prob.host["row_len"].sum())   # real blocks (slots: prob.nnzb)
     tol_abs = args.tol_abs if args.tol_abs is not None else (1e-50 if cube else 1e-15)
-    nopts = V.newton_opts(tol_R=1e-8, tol_A=tol_abs, l_max=20)
+    lift = {"on": 1, "off": 0}.get(args.dir_lift, 1 if args.workload == "tube" else 0)
+    nopts = V.newton_opts(tol_R=1e-8, tol_A=tol_abs, l_max=20, dir_lift=lift)
     mt = [float(x) for x in args.mixed_tol.split(",")]
     ft = [float(x) for x in args.fp64_tol.split(",")]
     if args.spmv_only:

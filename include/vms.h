@@ -229,6 +229,16 @@ typedef struct {
   int32_t l_max;        /* maximum corrector iterations */
   int32_t rk_corr;      /* 1: keep the -K_{.,u-dot} R-bar_k / alpha_m term of the stage-1 rhs */
   double eps_diag;      /* scaling threshold epsilon_diag (section 4.1) */
+  int32_t dir_lift;     /* Dirichlet velocity components in the predictor (section 3.3):
+                           0 = preset: u = g(t_{n+1}), v = u-dot = g-dot, v-dot = 0 at once;
+                           1 = lifted: they take the predictor like every node (v-dot = 0), and
+                           the first corrector carries u to g(t_{n+1}) through R-bar_k, whose
+                           rhs term K_{.,u-dot} R-bar_k / alpha_m spreads the boundary motion
+                           into the interior (needs rk_corr; prescribed velocities constant in
+                           time, as dir_vel states them).  The relative Newton test then divides
+                           by the largest ||R_(l)|| so far instead of ||R_(0)||, which does
+                           not yet hold the prescribed motion */
+  int32_t pad_;
 } vms_newton_opts;
 
 typedef struct {
@@ -310,8 +320,10 @@ int vms_nodal_load(vms_ctx *ctx, const vms_mesh *mesh, double *f_ext);
 
 /* Set the iterate to the predictor y_(0) = y_n, y-dot_(0) = (gamma-1)/gamma
  * y-dot_n (section 3.3, predictor stage); Dirichlet velocity components take
- * u = dir_vel * t_{n+1}, v = u-dot = dir_vel, v-dot = 0.  [async] */
-int vms_predictor(vms_ctx *ctx, const vms_mesh *mesh, const vms_timeint *ti, vms_state *st);
+ * u = dir_vel * t_{n+1}, v = u-dot = dir_vel, v-dot = 0 (dir_lift = 0), or
+ * the predictor with v-dot = 0 (dir_lift = 1, vms_newton_opts.dir_lift).
+ * [async] */
+int vms_predictor(vms_ctx *ctx, const vms_mesh *mesh, const vms_timeint *ti, vms_state *st, int dir_lift);
 
 /* Workspace bytes of vms_assemble for these flags: the element matrices and
  * vectors (2 KB per element for the tangent, 128 B each for the residual and
@@ -418,10 +430,11 @@ int vms_solve_scaled(vms_ctx *ctx, const vms_mesh *mesh, const vms_matrix *K,
 /* Stage 2 and update (section 3.3 steps 6-7): Delta = W x* (W = NULL:
  * x_scaled already holds Delta, as vms_solve returns it); Delta u-dot =
  * (alpha_f gamma dt/alpha_m) Delta v-dot - R-bar_k/alpha_m; y-dot += Delta
- * y-dot, y += gamma dt Delta y-dot on the iterate (Dirichlet components fixed).
- * [async] */
+ * y-dot, y += gamma dt Delta y-dot on the iterate.  Dirichlet components keep
+ * v and v-dot; u and u-dot stay fixed there too (dir_lift = 0) or move by
+ * Delta u-dot = -R-bar_k/alpha_m (dir_lift = 1).  [async] */
 int vms_newton_update(vms_ctx *ctx, const vms_mesh *mesh, const vms_timeint *ti,
-                      vms_state *st, const double *W, const double *x_scaled);
+                      vms_state *st, const double *W, const double *x_scaled, int dir_lift);
 
 /* Workspace bytes of vms_step: the larger of vms_solve_workspace and the
  * assembly's element buffers (they are used in turn), plus its vectors. */

@@ -127,7 +127,9 @@ def time_step(disc, ti, state_n, t_n, tol_R=1e-10, tol_A=1e-50, l_max=20,
     ``solver(K, rhs, dof_dir) -> Delta`` defaults to the scaled sparse LU.
     ``lift`` selects the lifted Dirichlet predictor (predictor, newton_update);
     it needs rk_corr, whose right-hand-side term K_{.,u-dot} R-bar_k / alpha_m
-    then spreads the boundary motion into the interior.
+    then spreads the boundary motion into the interior.  Its relative Newton
+    test divides by the largest residual norm of the iterates so far, since the
+    predictor's residual does not yet hold the prescribed motion.
     Returns (state_{n+1}, info) with the residual history and a flag.
     """
     if lift and not rk_corr:
@@ -146,6 +148,10 @@ def time_step(disc, ti, state_n, t_n, tol_R=1e-10, tol_A=1e-50, l_max=20,
         norms.append(nrm)
         if R0 is None:
             R0 = nrm
+        if lift:
+            # the predictor's residual lacks the prescribed motion, which arrives with the first
+            # corrector: the reference is the largest residual of the iterates so far
+            R0 = max(R0, nrm)
         if (R0 > 0 and nrm / R0 <= tol_R) or nrm <= tol_A:
             converged = True
             break

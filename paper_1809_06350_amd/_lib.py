@@ -64,7 +64,7 @@ class SolveStats(C.Structure):
 
 class NewtonOpts(C.Structure):
     _fields_ = [("tol_R", C.c_double), ("tol_A", C.c_double), ("l_max", C.c_int32), ("rk_corr", C.c_int32),
-                ("eps_diag", C.c_double)]
+                ("eps_diag", C.c_double), ("dir_lift", C.c_int32), ("pad_", C.c_int32)]
 
 
 class StepStats(C.Structure):
@@ -95,7 +95,7 @@ SIGNATURES = {
                                   P(C.c_int32)]),
     "vms_setup_build": (C.c_int, [C.c_int32, C.c_int32, C.c_void_p, C.c_int32, C.c_void_p] + [C.c_void_p] * 10),
     "vms_nodal_load": (C.c_int, [C.c_void_p, P(Mesh), C.c_void_p]),
-    "vms_predictor": (C.c_int, [C.c_void_p, P(Mesh), P(TimeInt), P(State)]),
+    "vms_predictor": (C.c_int, [C.c_void_p, P(Mesh), P(TimeInt), P(State), C.c_int]),
     "vms_assemble_workspace": (C.c_size_t, [P(Mesh), C.c_uint]),
     "vms_assemble": (C.c_int, [C.c_void_p, P(Mesh), P(Material), P(TimeInt), P(State), C.c_void_p, P(Matrix),
                                C.c_void_p, C.c_void_p, C.c_uint, C.c_void_p, C.c_size_t]),
@@ -110,7 +110,8 @@ SIGNATURES = {
                             P(SolverOpts), C.c_void_p, C.c_size_t, P(SolveStats)]),
     "vms_solve_scaled": (C.c_int, [C.c_void_p, P(Mesh), P(Matrix), C.c_void_p, C.c_void_p, P(SolverOpts),
                                    C.c_void_p, C.c_size_t, P(SolveStats)]),
-    "vms_newton_update": (C.c_int, [C.c_void_p, P(Mesh), P(TimeInt), P(State), C.c_void_p, C.c_void_p]),
+    "vms_newton_update": (C.c_int, [C.c_void_p, P(Mesh), P(TimeInt), P(State), C.c_void_p, C.c_void_p,
+                                    C.c_int]),
     "vms_step_workspace": (C.c_size_t, [P(Mesh), P(SolverOpts)]),
     "vms_step": (C.c_int, [C.c_void_p, P(Mesh), P(Material), P(TimeInt), P(State), C.c_void_p, P(Matrix),
                            P(NewtonOpts), P(SolverOpts), C.c_void_p, C.c_size_t, P(StepStats)]),

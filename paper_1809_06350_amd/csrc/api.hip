@@ -276,14 +276,16 @@ static int check_state(vms_ctx *ctx, const vms_state *st) {
   return VMS_OK;
 }
 
-extern "C" int vms_predictor(vms_ctx *ctx, const vms_mesh *mesh, const vms_timeint *ti, vms_state *st) {
+extern "C" int vms_predictor(vms_ctx *ctx, const vms_mesh *mesh, const vms_timeint *ti, vms_state *st,
+                             int dir_lift) {
   if (!ctx) return VMS_ERR_ARG;
   int rc = vms_check_mesh(ctx, mesh);
   if (rc) return rc;
   if ((rc = check_state(ctx, st))) return rc;
   if (!ti || !(ti->dt > 0.0)) return vms_set_error(ctx, VMS_ERR_ARG, "bad time-integration parameters");
   const vms_ga ga = vms_genalpha(ti);
-  return vms_launch_predictor(ctx, mesh, ga, ti->t_n + ti->dt, st);
+  if (dir_lift != 0 && dir_lift != 1) return vms_set_error(ctx, VMS_ERR_ARG, "dir_lift must be 0 or 1");
+  return vms_launch_predictor(ctx, mesh, ga, ti->t_n + ti->dt, st, dir_lift);
 }
 
 extern "C" size_t vms_assemble_workspace(const vms_mesh *mesh, unsigned flags) {
@@ -340,14 +342,15 @@ extern "C" int vms_prepare_system(vms_ctx *ctx, const vms_mesh *mesh, vms_matrix
 }
 
 extern "C" int vms_newton_update(vms_ctx *ctx, const vms_mesh *mesh, const vms_timeint *ti, vms_state *st,
-                                 const double *W, const double *x_scaled) {
+                                 const double *W, const double *x_scaled, int dir_lift) {
   if (!ctx) return VMS_ERR_ARG;
   int rc = vms_check_mesh(ctx, mesh);
   if (rc) return rc;
   if ((rc = check_state(ctx, st))) return rc;
   if (!ti || !x_scaled) return vms_set_error(ctx, VMS_ERR_ARG, "vms_newton_update: bad arguments");
   const vms_ga ga = vms_genalpha(ti);
-  return vms_launch_update(ctx, mesh, ga, st, W, x_scaled);
+  if (dir_lift != 0 && dir_lift != 1) return vms_set_error(ctx, VMS_ERR_ARG, "dir_lift must be 0 or 1");
+  return vms_launch_update(ctx, mesh, ga, st, W, x_scaled, dir_lift);
 }
 
 // ---- allocation-free time step ----------------------------------------------------

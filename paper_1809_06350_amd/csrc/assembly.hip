@@ -563,14 +563,19 @@ __global__ void k_nodal_load(int n, const int32_t *nf_ptr, const int32_t *nf_fac
   f_ext[3 * (int64_t)i + 2] = f2;
 }
 
-__global__ void k_predictor(int n, vms_ga ga, double t_np1, const uint8_t *dir, const double *dir_vel,
+__global__ void k_predictor(int n, vms_ga ga, double t_np1, const uint8_t *dir, const double *dir_vel, int lift,
                             StateP sp, double *u, double *p, double *v, double *du, double *dp, double *dv) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const double r = (ga.gm - 1.0) / ga.gm;
   for (int c = 0; c < 3; ++c) {
     const int64_t o = 3 * (int64_t)i + c;
-    if (dir[4 * (int64_t)i + c]) {
+    if (dir[4 * (int64_t)i + c] && lift) {
+      u[o] = sp.u_n[o];
+      v[o] = sp.v_n[o];
+      du[o] = r * sp.du_n[o];
+      dv[o] = 0.0;
+    } else if (dir[4 * (int64_t)i + c]) {
       u[o] = dir_vel[o] * t_np1;
       v[o] = dir_vel[o];
       du[o] = dir_vel[o];
@@ -676,7 +681,7 @@ __global__ void k_rhs(int n, const uint8_t *dir, const double *W, const double *
   rhs[k] = dir[k] ? 0.0 : W[k] * r;
 }
 
-__global__ void k_update(int n, vms_ga ga, const uint8_t *dir, const double *W, const double *x, StateP sp,
+__global__ void k_update(int n, vms_ga ga, const uint8_t *dir, const double *W, const double *x, int lift, StateP sp,
                          double *u, double *p, double *v, double *du, double *dp, double *dv) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
@@ -684,8 +689,9 @@ __global__ void k_update(int n, vms_ga ga, const uint8_t *dir, const double *W, 
   const double gdt = ga.gm * ga.dt;
   for (int c = 0; c < 3; ++c) {
     const int64_t o = 3 * (int64_t)i + c;
-    if (dir[o4 + c]) continue;
-    const double ddv = W ? W[o4 + c] * x[o4 + c] : x[o4 + c];
+    const bool d = dir[o4 + c] != 0;
+    if (d && !lift) continue;
+    const double ddv = d ? 0.0 : (W ? W[o4 + c] * x[o4 + c] : x[o4 + c]);
     const double rk = (sp.du_n[o] + ga.am * (du[o] - sp.du_n[o])) - (sp.v_n[o] + ga.af * (v[o] - sp.v_n[o]));
     const double ddu = ga.c2 / ga.am * ddv - rk / ga.am;
     dv[o] += ddv;
@@ -855,19 +861,20 @@ int vms_launch_prepare(vms_ctx *ctx, const vms_mesh *mesh, vms_matrix *K, const 
 }
 
 int vms_launch_update(vms_ctx *ctx, const vms_mesh *mesh, const vms_ga &ga, vms_state *st, const double *W,
-                      const double *x) {
+                      const double *x, int lift) {
   const int n = mesh->n_nodes;
   hipLaunchKernelGGL(k_update, dim3(grid1(n)), dim3(VMS_BLOCK), 0, ctx->stream, n, ga, mesh->dir_mask, W, x,
-                     mk_state(st), st->u, st->p, st->v, st->du, st->dp, st->dv);
+                     lift ? 1 : 0, mk_state(st), st->u, st->p, st->v, st->du, st->dp, st->dv);
   VMS_LAUNCH_CHECK(ctx);
   return VMS_OK;
 }
 
-int vms_launch_predictor(vms_ctx *ctx, const vms_mesh *mesh, const vms_ga &ga, double t_np1, vms_state *st) {
+int vms_launch_predictor(vms_ctx *ctx, const vms_mesh *mesh, const vms_ga &ga, double t_np1, vms_state *st,
+                         int lift) {
   const int n = mesh->n_nodes;
   if (!mesh->dir_vel) return vms_set_error(ctx, VMS_ERR_ARG, "dir_vel missing");
   hipLaunchKernelGGL(k_predictor, dim3(grid1(n)), dim3(VMS_BLOCK), 0, ctx->stream, n, ga, t_np1, mesh->dir_mask,
-                     mesh->dir_vel, mk_state(st), st->u, st->p, st->v, st->du, st->dp, st->dv);
+                     mesh->dir_vel, lift ? 1 : 0, mk_state(st), st->u, st->p, st->v, st->du, st->dp, st->dv);
   VMS_LAUNCH_CHECK(ctx);
   return VMS_OK;
 }

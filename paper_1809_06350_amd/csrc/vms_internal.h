@@ -171,9 +171,9 @@ int vms_launch_norm(vms_ctx *ctx, const vms_mesh *mesh, const vms_ga &ga, const 
 int vms_launch_prepare(vms_ctx *ctx, const vms_mesh *mesh, vms_matrix *K, const double *R,
                        const double *corr, double *rhs, double eps_diag, int mirror32);
 int vms_launch_update(vms_ctx *ctx, const vms_mesh *mesh, const vms_ga &ga, vms_state *st,
-                      const double *W, const double *x);
+                      const double *W, const double *x, int lift);
 int vms_launch_predictor(vms_ctx *ctx, const vms_mesh *mesh, const vms_ga &ga, double t_np1,
-                         vms_state *st);
+                         vms_state *st, int lift);
 int vms_launch_spmv(vms_ctx *ctx, const vms_mesh *mesh, const vms_matrix *K, int op,
                     const void *x, void *y, int fp32);
 // Kt = blocks of K^T (FP32 copies too when m32)

@@ -45,8 +45,8 @@ def solver_opts(rtol=1e-8, atol=1e-50, maxit=200, rtol_A=5e-5, atol_A=1e-50, max
                         cg_symmetrise, shat_method, schur_solve, relax_inner, schur_mass)
 
 
-def newton_opts(tol_R=1e-8, tol_A=1e-50, l_max=20, rk_corr=1, eps_diag=1e-15) -> L.NewtonOpts:
-    return L.NewtonOpts(tol_R, tol_A, l_max, rk_corr, eps_diag)
+def newton_opts(tol_R=1e-8, tol_A=1e-50, l_max=20, rk_corr=1, eps_diag=1e-15, dir_lift=0) -> L.NewtonOpts:
+    return L.NewtonOpts(tol_R, tol_A, l_max, rk_corr, eps_diag, dir_lift, 0)
 
 
 def time_int(dt, rho_inf=0.5, t_n=0.0, t_load=0.0) -> L.TimeInt:
@@ -212,9 +212,9 @@ class Problem:
         return K
 
     # ---- entry points ----------------------------------------------------------
-    def predictor(self, st, ti):
-        self._check(self.lib.vms_predictor(self.ctx, C.byref(self.cmesh), C.byref(ti), C.byref(self.cstate(st))),
-                    "vms_predictor")
+    def predictor(self, st, ti, dir_lift=0):
+        self._check(self.lib.vms_predictor(self.ctx, C.byref(self.cmesh), C.byref(ti), C.byref(self.cstate(st)),
+                                           dir_lift), "vms_predictor")
 
     def assemble(self, st, ti, flags, K=None, R=None, corr=None, load=True):
         n = self.mesh.n_nodes
@@ -295,10 +295,11 @@ class Problem:
                     "vms_solve", allow_nc=allow_nc)
         return delta, stats.as_dict()
 
-    def newton_update(self, st, ti, K, x):
+    def newton_update(self, st, ti, K, x, dir_lift=0):
         """Stage 2 and the update from x = x* (with K.W) or, for K = None, from x = Delta."""
         self._check(self.lib.vms_newton_update(self.ctx, C.byref(self.cmesh), C.byref(ti), C.byref(self.cstate(st)),
-                                               _p(K.W) if K is not None else None, _p(x)), "vms_newton_update")
+                                               _p(K.W) if K is not None else None, _p(x), dir_lift),
+                    "vms_newton_update")
 
     def solve_transpose(self, K, Kt, g, opts, eps_diag=1e-15, lam=None, allow_nc=False):
         """K^T lam = g (vms_solve_transpose): K as assembled (overwritten with W K W, K.W written)."""

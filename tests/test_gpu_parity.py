@@ -615,7 +615,7 @@ def test_newton_update_matches_oracle(problems):
         assert rel_err(st[k].cpu().numpy(), out[k]) < 1e-13, k
 
 
-def _run_steps(prob, mesh, ti, n_steps, nopts, sopts):
+def _run_steps(prob, mesh, ti, n_steps, nopts, sopts, allow_nc=False):
     st = prob.new_state()
     vm = mesh.dir_mask[:, 0:3].astype(bool)
     for key in ("v_n", "du_n"):
@@ -625,8 +625,12 @@ def _run_steps(prob, mesh, ti, n_steps, nopts, sopts):
     hist = []
     K = None
     for s in range(n_steps):
-        stats, K = prob.step(st, V.time_int(ti.dt, ti.rho_inf, s * ti.dt, ti.n_steps * ti.dt), nopts, sopts, K)
+        stats, K = prob.step(st, V.time_int(ti.dt, ti.rho_inf, s * ti.dt, ti.n_steps * ti.dt), nopts, sopts, K,
+                             allow_nc=allow_nc)
         hist.append(stats)
+        if stats["status"] != 0:
+            print(f"[step {s}] status {stats['status']} res={stats['res_norm']}", flush=True)
+            break
         prob.roll(st)
     return st, hist
 
@@ -696,6 +700,66 @@ def test_strip_time_steps_match_oracle(precision, a_krylov):
         print(f"[strip step {s}] gpu newton={hist[s]['n_newton']} res={hist[s]['res_norm']} "
               f"oracle={info['norms']}", flush=True)
         assert hist[s]["status"] == 0
+        if not mixed:
+            assert hist[s]["n_newton"] == info["n_newton"]
+    tol = 1e-6 if mixed else 1e-7
+    for k in ("u", "p", "v") if mixed else ("u", "p", "v", "du", "dp", "dv"):
+        assert rel_err(st[k].cpu().numpy(), so[k]) < tol, k
+
+
+def test_lifted_predictor_and_update_match_oracle(problems):
+    """Lifted Dirichlet form (reading: the prescribed motion arrives through
+    R-bar_k): the predictor keeps u, v of the Dirichlet components at y_n with
+    v-dot = 0, and the update moves their u by Delta u-dot = -R-bar_k/alpha_m,
+    against the oracle's predictor and newton_update with lift=True."""
+    prob, mesh, mat, ti, disc = problems("tube-hgo")
+    sn, _ = states(mesh, 23)
+    vm = mesh.dir_mask[:, 0:3].astype(bool)
+    st = gpu_state(prob, sn, sn)
+    t_n = 0.3
+    prob.predictor(st, gpu_ti(ti, t_n), dir_lift=1)
+    am, af, gm = E.genalpha(ti.rho_inf)
+    ito = NW.predictor(mesh, sn, gm, t_n + ti.dt, lift=True)
+    for k in ("u", "p", "v", "du", "dp", "dv"):
+        assert np.abs(st[k].cpu().numpy() - ito[k]).max() <= 1e-15 * max(np.abs(ito[k]).max(), 1.0), k
+    assert np.array_equal(st["u"].cpu().numpy()[vm], sn["u"][vm])
+    rng = np.random.default_rng(6)
+    n = mesh.n_nodes
+    x = rng.standard_normal((n, 4))
+    x[mesh.dir_mask.astype(bool)] = 0.0
+    prob.newton_update(st, gpu_ti(ti, t_n), None, torch.from_numpy(x).cuda(), dir_lift=1)
+    sto = NW.stage(sn, ito, am, af)
+    out, _ = NW.newton_update(disc, ti, ito, x.ravel(), sto["du"] - sto["v"], lift=True)
+    for k in ("u", "p", "v", "du", "dp", "dv"):
+        assert rel_err(st[k].cpu().numpy(), out[k]) < 1e-13, k
+    moved = np.abs(out["u"][vm] - sn["u"][vm]).max()
+    assert moved > 0.0
+
+
+@pytest.mark.parametrize("precision", [V.FP64, V.MIXED])
+def test_lifted_tube_time_steps_match_oracle(precision):
+    """Three time steps of a small HGO tube at the stretch rate and step of the
+    full workload (stretch 1.5 over 20 steps of 0.05) with the lifted
+    Dirichlet predictor, against the oracle's lifted steps."""
+    mesh, mat, ti = synth.tube_case(1, 16, 20, dt=0.05, n_steps=20)
+    prob = V.Problem(mesh, mat, "cuda:0")
+    fib, dfib = synth.fibre_field(mesh, mesh.meta["fibre_rad"])
+    prob.set_fibres(fib, dfib)
+    mixed = precision == V.MIXED
+    nopts = V.newton_opts(tol_R=1e-8 if mixed else 1e-10, l_max=15, dir_lift=1)
+    if mixed:
+        sopts = V.solver_opts(rtol=1e-8, precision=V.MIXED, a_krylov=V.AK_CG, cg_symmetrise=0)
+    else:
+        sopts = V.solver_opts(rtol=1e-10, rtol_A=1e-10, rtol_S=1e-10, rtol_I=1e-12)
+    st, hist = _run_steps(prob, mesh, ti, 3, nopts, sopts, allow_nc=True)
+    assert all(h["status"] == 0 for h in hist) and len(hist) == 3
+    disc = AS.Discretization(mesh, mat)
+    so = NW.rest_state(mesh)
+    for s in range(3):
+        so, info = NW.time_step(disc, ti, so, s * ti.dt, tol_R=nopts.tol_R, l_max=15, lift=True)
+        print(f"[lifted tube step {s}] gpu newton={hist[s]['n_newton']} oracle={info['n_newton']} "
+              f"gpu res={hist[s]['res_norm'][:hist[s]['n_newton'] + 1]}", flush=True)
+        assert hist[s]["status"] == 0 and info["converged"]
         if not mixed:
             assert hist[s]["n_newton"] == info["n_newton"]
     tol = 1e-6 if mixed else 1e-7
