@@ -46,6 +46,7 @@
 #define VMS_MAX_TETS 134217727   /* 2^27 - 1: 16 * n_tets fits in int32 */
 #define VMS_MAX_SHAT_ROW 128     /* longest off-diagonal row of the distance-2 pattern, in slots */
 #define VMS_NOALLOC_SCRATCH_BYTES (64u << 20) /* static device scratch of vms_step_noalloc, per GPU */
+#define VMS_AMG_MAX_LEVELS 8     /* levels of the aggregation multigrid hierarchy */
 
 #ifdef __cplusplus
 extern "C" {
@@ -105,6 +106,13 @@ enum { VMS_ORTH_CGS2 = 0, VMS_ORTH_MGS = 1, VMS_ORTH_CGS1 = 2, VMS_ORTH_CGS_IFNE
  * the outer FGMRES still solves the unsymmetrised system. */
 enum { VMS_AK_GMRES = 0, VMS_AK_CG_INNER = 1, VMS_AK_CG = 2 };
 
+/* Preconditioner of the A-level Krylov solves.  The paper preconditions them by
+ * algebraic multigrid (section 5); VMS_APC_BJ is the 3x3 block-Jacobi
+ * stand-in, VMS_APC_AMG one V-cycle of the library's aggregation multigrid
+ * (vms_amg_create; mesh->amg), a fixed symmetric operator that CG and GMRES
+ * both accept. */
+enum { VMS_APC_BJ = 0, VMS_APC_AMG = 1 };
+
 /* How the Schur solve's right preconditioner approximates S^-1 when
  * shat_degree = k > 0: the degree-k Chebyshev polynomial in diag(S^)^-1 S^
  * (a fixed linear operator), or k steps of diag(S^)-preconditioned CG on S^
@@ -113,6 +121,8 @@ enum { VMS_AK_GMRES = 0, VMS_AK_CG_INNER = 1, VMS_AK_CG = 2 };
 enum { VMS_SHAT_CHEBYSHEV = 0, VMS_SHAT_CG = 1, VMS_SHAT_NONE = 2 };   /* NONE: no S^ part (schur_mass > 0) */
 
 typedef struct vms_ctx vms_ctx;
+/* Aggregation multigrid hierarchy of a mesh (host object; vms_amg_create). */
+typedef struct vms_amg vms_amg;
 
 typedef struct {
   int32_t kind;     /* vms_material_kind */
@@ -154,6 +164,8 @@ typedef struct {
                                these 2-byte offsets instead of the 4-byte columns */
   const int32_t *nf_ptr;    /* [n+1] node -> loaded faces */
   const int32_t *nf_face;   /* [3f] */
+  const vms_amg *amg;       /* HOST pointer: multigrid hierarchy uploaded by vms_amg_upload, needed
+                               by a_prec = VMS_APC_AMG (NULL otherwise) */
 } vms_mesh;
 
 typedef struct {
@@ -198,6 +210,8 @@ typedef struct {
                             VMS_SHAT_NONE it is the whole preconditioner.  Krylov Schur step of
                             P_SCR only (precond != SIMPLE, schur_solve = VMS_SCHUR_KRYLOV).
                             0: off, as in the paper */
+  int32_t a_prec;        /* VMS_APC_*: preconditioner of both A-levels */
+  int32_t pad_;
 } vms_solver_opts;
 
 typedef struct {
@@ -503,6 +517,63 @@ int vms_adjoint_step(vms_ctx *ctx, const vms_mesh *mesh, const vms_material *mat
                      const double *ybar1, const double *ydbar1, double *ybar0, double *ydbar0, int pmask,
                      double *dJdtheta, const vms_solver_opts *opts, double eps_diag, void *workspace,
                      size_t workspace_bytes, vms_solve_stats *stats);
+
+/* ---- aggregation multigrid for the A-levels (section 5: the paper uses AMG) */
+
+typedef struct {
+  int32_t max_levels;     /* 2 .. VMS_AMG_MAX_LEVELS */
+  int32_t min_coarse;     /* a level with at most this many nodes is the coarsest */
+  int32_t degree;         /* Chebyshev degree of pre- and post-smoothing (1 .. 16) */
+  int32_t coarse_degree;  /* Chebyshev degree on the coarsest level (1 .. 64) */
+} vms_amg_opts;
+
+typedef struct {
+  int32_t n_levels;
+  int32_t n[VMS_AMG_MAX_LEVELS];     /* nodes per level (level 0: the mesh) */
+  int32_t bs[VMS_AMG_MAX_LEVELS];    /* dofs per node: 3, then 10 */
+  int64_t nnzb[VMS_AMG_MAX_LEVELS];  /* blocks per level (level 0: the mesh's slots) */
+  size_t device_bytes;               /* bytes vms_amg_upload needs */
+} vms_amg_info;
+
+/* Build the mesh-dependent part of a plain-aggregation multigrid hierarchy for
+ * the velocity block A (host work, once per mesh): greedy aggregates of the
+ * node graph (row_len, col of vms_setup_build, slot width W), the ten
+ * conformal motions (translations, rotations, dilation, special conformal
+ * fields) per aggregate as near-null space, zero on Dirichlet velocity
+ * components (dir_mask), orthonormalised per aggregate by modified
+ * Gram-Schmidt into the tentative prolongator, coarse patterns and the block
+ * lists of the Galerkin products.  All arrays are HOST arrays.  *out receives
+ * the object (free with vms_amg_destroy).  VMS_ERR_ARG on a bad pattern or
+ * option.  Each linear solve with a_prec = VMS_APC_AMG forms the coarse
+ * operators P^T A P, their block-diagonal inverses and the Chebyshev bounds on
+ * the device. */
+int vms_amg_create(int32_t n_nodes, int32_t slot_width, const int32_t *row_len, const int32_t *col,
+                   const double *X, const uint8_t *dir_mask, const vms_amg_opts *opts, vms_amg **out);
+void vms_amg_destroy(vms_amg *amg);
+int vms_amg_get_info(const vms_amg *amg, vms_amg_info *info);
+/* Bytes of device memory the hierarchy's fixed arrays take (vms_amg_upload). */
+size_t vms_amg_device_bytes(const vms_amg *amg);
+/* Copy the fixed arrays into caller-owned device memory (at least
+ * vms_amg_device_bytes) on ctx's device; the object keeps the device
+ * pointers, so the buffer must outlive every solve that uses the hierarchy.
+ * [sync] */
+int vms_amg_upload(vms_ctx *ctx, vms_amg *amg, void *device_buffer, size_t bytes);
+/* HOST views of level `level` (for checks): agg[n] (coarse node of each node)
+ * and P[n][bs][10] (the unscaled tentative prolongator) when a coarser level
+ * follows, else NULL; for level >= 1 its CSR pattern ptr[n+1], col[] and the
+ * dropped-dof mask dropped[n*10]. */
+int vms_amg_level_arrays(const vms_amg *amg, int level, const int32_t **agg, const double **P,
+                         const int32_t **ptr, const int32_t **col, const uint8_t **dropped);
+/* z = one V-cycle of the A-levels' multigrid applied to r ([n][3] velocity
+ * vectors, FP64), for the scaled velocity block of K (K->A, K->W as
+ * vms_prepare_system left them; symmetrised (A + A^T)/2 when sym = 1): the
+ * coarse operators, block inverses and Chebyshev bounds are formed as in a
+ * solve, then the cycle is applied.  Workspace at least
+ * vms_amg_apply_workspace(mesh, sym).  [sync]  VMS_ERR_BREAKDOWN if a coarse
+ * diagonal block is singular. */
+size_t vms_amg_apply_workspace(const vms_mesh *mesh, int sym);
+int vms_amg_apply(vms_ctx *ctx, const vms_mesh *mesh, const vms_matrix *K, int sym, const double *r, double *z,
+                  void *workspace, size_t workspace_bytes);
 
 /* ---- allocation-free time step ------------------------------------------ */
 

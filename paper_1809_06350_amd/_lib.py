@@ -27,7 +27,7 @@ class Mesh(C.Structure):
                 ("col", C.c_void_p), ("tpos", C.c_void_p), ("diag_pos", C.c_void_p),
                 ("blk_src_ptr", C.c_void_p), ("blk_src", C.c_void_p), ("shat_width", C.c_int32),
                 ("shat_col", C.c_void_p), ("shat_off", C.c_void_p), ("nf_ptr", C.c_void_p),
-                ("nf_face", C.c_void_p)]
+                ("nf_face", C.c_void_p), ("amg", C.c_void_p)]
 
 
 class State(C.Structure):
@@ -47,7 +47,8 @@ class SolverOpts(C.Structure):
                 ("precond", C.c_int32), ("precision", C.c_int32), ("orth", C.c_int32),
                 ("shat_degree", C.c_int32), ("shat_ratio", C.c_double), ("a_krylov", C.c_int32),
                 ("cg_symmetrise", C.c_int32), ("shat_method", C.c_int32),
-                ("schur_solve", C.c_int32), ("relax_inner", C.c_int32), ("schur_mass", C.c_double)]
+                ("schur_solve", C.c_int32), ("relax_inner", C.c_int32), ("schur_mass", C.c_double),
+                ("a_prec", C.c_int32), ("pad_", C.c_int32)]
 
 
 class SolveStats(C.Structure):
@@ -81,6 +82,16 @@ class StepStats(C.Structure):
         d["res_norm"] = list(self.res_norm[: max(self.n_newton + 1, 1)])
         d["last"] = self.last.as_dict()
         return d
+
+
+class AmgOpts(C.Structure):
+    _fields_ = [("max_levels", C.c_int32), ("min_coarse", C.c_int32), ("degree", C.c_int32),
+                ("coarse_degree", C.c_int32)]
+
+
+class AmgInfo(C.Structure):
+    _fields_ = [("n_levels", C.c_int32), ("n", C.c_int32 * 8), ("bs", C.c_int32 * 8), ("nnzb", C.c_int64 * 8),
+                ("device_bytes", C.c_size_t)]
 
 
 P = C.POINTER
@@ -118,6 +129,17 @@ SIGNATURES = {
     "vms_step_noalloc": (C.c_int, [C.c_void_p, P(Mesh), P(Material), P(TimeInt), P(State), C.c_void_p,
                                    P(Matrix), P(NewtonOpts), P(SolverOpts), P(StepStats)]),
     "vms_noalloc_scratch_bytes": (C.c_size_t, []),
+    "vms_amg_create": (C.c_int, [C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, P(AmgOpts),
+                                 P(C.c_void_p)]),
+    "vms_amg_destroy": (None, [C.c_void_p]),
+    "vms_amg_get_info": (C.c_int, [C.c_void_p, P(AmgInfo)]),
+    "vms_amg_device_bytes": (C.c_size_t, [C.c_void_p]),
+    "vms_amg_upload": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t]),
+    "vms_amg_level_arrays": (C.c_int, [C.c_void_p, C.c_int, P(C.c_void_p), P(C.c_void_p), P(C.c_void_p),
+                                       P(C.c_void_p), P(C.c_void_p)]),
+    "vms_amg_apply_workspace": (C.c_size_t, [P(Mesh), C.c_int]),
+    "vms_amg_apply": (C.c_int, [C.c_void_p, P(Mesh), P(Matrix), C.c_int, C.c_void_p, C.c_void_p, C.c_void_p,
+                                C.c_size_t]),
     "vms_solve_transpose": (C.c_int, [C.c_void_p, P(Mesh), P(Matrix), P(Matrix), C.c_void_p, C.c_void_p,
                                       C.c_double, P(SolverOpts), C.c_void_p, C.c_size_t, P(SolveStats)]),
     "vms_solve_transpose_scaled": (C.c_int, [C.c_void_p, P(Mesh), P(Matrix), P(Matrix), C.c_void_p, C.c_void_p,

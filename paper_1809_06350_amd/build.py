@@ -14,8 +14,8 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libvms.so")
 
-SOURCES = ["api.hip", "assembly.hip", "solver.hip", "adjoint.hip", "setup.cpp"]
-HEADERS = ["vms_internal.h", "linalg.h"]
+SOURCES = ["api.hip", "assembly.hip", "solver.hip", "adjoint.hip", "setup.cpp", "amg_setup.cpp"]
+HEADERS = ["vms_internal.h", "linalg.h", "amg.h"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("VMS_OFFLOAD_ARCH", "gfx950")

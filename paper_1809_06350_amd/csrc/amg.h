@@ -1,0 +1,443 @@
+// Device part of the aggregation multigrid that preconditions the A-level
+// solves (included by solver.hip inside its anonymous namespace).  The
+// mesh-dependent arrays (aggregates, tentative prolongators, coarse patterns,
+// Galerkin lists) come from amg_setup.cpp; per linear system the kernels here
+// form
+//   A_1 = P*^T A P*  with P* = W^-1 Q (the scaled system x = W x*: the W of
+//                    the velocity dofs divides the unscaled prolongator Q),
+//   A_{l+1} = Q_l^T A_l Q_l on coarser levels (FP64, summed over each coarse
+//                    block's list in the finer level's block order),
+// the inverses of their 10x10 diagonal blocks (the finest level uses the 3x3
+// block-Jacobi inverses of the solver) and the Chebyshev bound lmax of
+// D^-1 A_l (1.1 times the ratio after 12 power steps from a SplitMix64
+// vector).  A V-cycle is then: Chebyshev pre-smoothing from zero, residual,
+// restriction, the coarser level, prolongation, Chebyshev post-smoothing; the
+// coarsest level only smooths from zero.  Every kernel returns at once when
+// the Krylov level's `done` flag is set (iterations enqueued past convergence).
+//
+// Layouts.  Finest level: the mesh's fixed-slot 3x3 blocks (entry-major),
+// vectors [n][3], 16 lanes per row as in the block products.  Coarse levels:
+// CSR of 10x10 blocks stored block-major ([nnzb][10][10], row-major blocks),
+// vectors [n][10]; ten lanes per row, lane r owns component r, 25 rows per
+// 256-thread workgroup; the block-diagonal solve exchanges the row's ten
+// sums through LDS.
+#pragma once
+
+#define AMG_NM 10
+#define AMG_CROWS 25
+#define AMG_RATIO 30.0
+#define AMG_POWER_STEPS 12
+#define AMG_LMAX_SAFETY 1.1
+
+inline int amg_cgrid(int n) { return (n + AMG_CROWS - 1) / AMG_CROWS; }
+
+// output i of SplitMix64 (Steele, Lea and Flood 2014) started at `seed`, mapped to [-1, 1)
+__device__ __forceinline__ double splitmix_unit(uint64_t seed, uint64_t i) {
+  uint64_t z = seed + (i + 1) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  z = z ^ (z >> 31);
+  return 2.0 * ((double)(z >> 11) * 0x1.0p-53) - 1.0;
+}
+
+// Chebyshev constants on [lmax / AMG_RATIO, lmax]: theta, and for step k the coefficients of
+// d_{k+1} = c1 d_k + c2 r with rho_0 = 1/sigma, rho_{k+1} = 1 / (2 sigma - rho_k)
+__device__ __forceinline__ void amg_cheb(double lmax, int k, double &theta, double &c1, double &c2) {
+  const double lmin = lmax / AMG_RATIO;
+  theta = 0.5 * (lmax + lmin);
+  const double delta = 0.5 * (lmax - lmin);
+  const double sigma = theta / delta;
+  double rho = 1.0 / sigma, rn = 0.0;
+  for (int q = 0; q <= k; ++q) {
+    rn = 1.0 / (2.0 * sigma - rho);
+    if (q < k) rho = rn;
+  }
+  c1 = rn * rho;
+  c2 = 2.0 * rn / delta;
+}
+
+__device__ __forceinline__ bool amg_done(const int *done) { return done && *done; }
+
+// ---- finest level (3x3 fixed-slot blocks, 16 lanes per row) ---------------------------------
+
+// row sums (A x)_row for all three components, valid in all 16 lanes of the row
+template <typename T>
+__device__ __forceinline__ void amgf_row(int64_t nnzb, int b0, int b1, int lane, const int32_t *__restrict__ col,
+                                         const T *__restrict__ A, const T *__restrict__ x, double &a0, double &a1,
+                                         double &a2) {
+  a0 = a1 = a2 = 0.0;
+  for (int b = b0 + lane; b < b1; b += 16) {
+    const int64_t o = 3 * (int64_t)col[b];
+    const double x0 = ld(x, o), x1 = ld(x, o + 1), x2 = ld(x, o + 2);
+    a0 += ld(A, 0 * nnzb + b) * x0 + ld(A, 1 * nnzb + b) * x1 + ld(A, 2 * nnzb + b) * x2;
+    a1 += ld(A, 3 * nnzb + b) * x0 + ld(A, 4 * nnzb + b) * x1 + ld(A, 5 * nnzb + b) * x2;
+    a2 += ld(A, 6 * nnzb + b) * x0 + ld(A, 7 * nnzb + b) * x1 + ld(A, 8 * nnzb + b) * x2;
+  }
+  a0 = reduce16(a0);
+  a1 = reduce16(a1);
+  a2 = reduce16(a2);
+}
+
+// component c of M w for the row's 3x3 block M (row-major)
+template <typename T>
+__device__ __forceinline__ double bj3_comp(const T *M, int c, double w0, double w1, double w2) {
+  return ld(M, 3 * c) * w0 + ld(M, 3 * c + 1) * w1 + ld(M, 3 * c + 2) * w2;
+}
+
+// zero start: r = M b, d = r / theta, x = d (no product)
+template <typename T>
+__global__ void __launch_bounds__(VMS_BLOCK)
+k_amgf_cheb0(int n, const T *__restrict__ Minv, const T *__restrict__ b, T *x, T *r, T *d, const double *lam,
+             const int *done) {
+  if (amg_done(done)) return;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double th, c1, c2;
+  amg_cheb(*lam, 0, th, c1, c2);
+  const double b0 = ld(b, 3 * (int64_t)i), b1 = ld(b, 3 * (int64_t)i + 1), b2 = ld(b, 3 * (int64_t)i + 2);
+  const T *M = Minv + 9 * (int64_t)i;
+  for (int c = 0; c < 3; ++c) {
+    const double z = bj3_comp(M, c, b0, b1, b2);
+    r[3 * (int64_t)i + c] = (T)z;
+    const T dz = (T)(z / th);
+    d[3 * (int64_t)i + c] = dz;
+    x[3 * (int64_t)i + c] = dz;
+  }
+}
+
+// start from x: r = M (b - A x), d = r / theta (x += d is left to the next step)
+template <typename T>
+__global__ void __launch_bounds__(VMS_BLOCK)
+k_amgf_chebres(int n, int64_t nnzb, int W, const int32_t *__restrict__ col, const T *__restrict__ A,
+               const T *__restrict__ Minv, const T *__restrict__ b, const T *__restrict__ x, T *r, T *d,
+               const double *lam, const int *done) {
+  SPMV_PROLOGUE
+  double a0, a1, a2;
+  amgf_row(nnzb, b0, b1, lane, col, A, x, a0, a1, a2);
+  if (!act || lane >= 3) return;
+  double th, c1, c2;
+  amg_cheb(*lam, 0, th, c1, c2);
+  const int64_t o = 3 * (int64_t)row;
+  const double w0 = ld(b, o) - a0, w1 = ld(b, o + 1) - a1, w2 = ld(b, o + 2) - a2;
+  const double z = bj3_comp(Minv + 9 * (int64_t)row, lane, w0, w1, w2);
+  r[o + lane] = (T)z;
+  d[o + lane] = (T)(z / th);
+}
+
+// Chebyshev step k: r -= M A d_k, d_{k+1} = c1 d_k + c2 r, x += (pending ? d_k : 0) + d_{k+1}
+template <typename T>
+__global__ void __launch_bounds__(VMS_BLOCK)
+k_amgf_step(int n, int64_t nnzb, int W, const int32_t *__restrict__ col, const T *__restrict__ A,
+            const T *__restrict__ Minv, const T *__restrict__ dk, T *dn, T *r, T *x, const double *lam, int k,
+            int pending, const int *done) {
+  SPMV_PROLOGUE
+  double a0, a1, a2;
+  amgf_row(nnzb, b0, b1, lane, col, A, dk, a0, a1, a2);
+  if (!act || lane >= 3) return;
+  double th, c1, c2;
+  amg_cheb(*lam, k, th, c1, c2);
+  const int64_t o = 3 * (int64_t)row + lane;
+  const double z = bj3_comp(Minv + 9 * (int64_t)row, lane, a0, a1, a2);
+  const double rn = ld(r, o) - z;
+  const double dko = ld(dk, o);
+  const double dnv = c1 * dko + c2 * rn;
+  r[o] = (T)rn;
+  dn[o] = (T)dnv;
+  x[o] = (T)(ld(x, o) + (pending ? dko : 0.0) + dnv);
+}
+
+// res = b - A x
+template <typename T>
+__global__ void __launch_bounds__(VMS_BLOCK)
+k_amgf_resid(int n, int64_t nnzb, int W, const int32_t *__restrict__ col, const T *__restrict__ A,
+             const T *__restrict__ b, const T *__restrict__ x, T *res, const int *done) {
+  SPMV_PROLOGUE
+  double a0, a1, a2;
+  amgf_row(nnzb, b0, b1, lane, col, A, x, a0, a1, a2);
+  if (!act || lane >= 3) return;
+  const int64_t o = 3 * (int64_t)row + lane;
+  res[o] = (T)(ld(b, o) - (lane == 0 ? a0 : (lane == 1 ? a1 : a2)));
+}
+
+// y = M A x (power iteration)
+template <typename T>
+__global__ void __launch_bounds__(VMS_BLOCK)
+k_amgf_dapply(int n, int64_t nnzb, int W, const int32_t *__restrict__ col, const T *__restrict__ A,
+              const T *__restrict__ Minv, const T *__restrict__ x, T *y) {
+  const int *done = nullptr;
+  SPMV_PROLOGUE
+  double a0, a1, a2;
+  amgf_row(nnzb, b0, b1, lane, col, A, x, a0, a1, a2);
+  if (!act || lane >= 3) return;
+  y[3 * (int64_t)row + lane] = (T)bj3_comp(Minv + 9 * (int64_t)row, lane, a0, a1, a2);
+}
+
+// ---- coarse levels (10x10 CSR blocks, ten lanes per row) ------------------------------------
+
+template <typename T>
+__device__ __forceinline__ double amgc_row(const int32_t *__restrict__ ptr, const int32_t *__restrict__ col,
+                                           const T *__restrict__ A, const T *__restrict__ x, int row, int rr) {
+  double acc = 0.0;
+  const int k1 = ptr[row + 1];
+  for (int k = ptr[row]; k < k1; ++k) {
+    const T *a = A + (int64_t)k * (AMG_NM * AMG_NM) + rr * AMG_NM;
+    const T *xv = x + (int64_t)col[k] * AMG_NM;
+#pragma unroll
+    for (int c = 0; c < AMG_NM; ++c) acc += ld(a, c) * ld(xv, c);
+  }
+  return acc;
+}
+
+template <typename T>
+__device__ __forceinline__ double amgc_dapply(const T *__restrict__ Dinv, int row, int rr, const double *w) {
+  const T *m = Dinv + (int64_t)row * (AMG_NM * AMG_NM) + rr * AMG_NM;
+  double z = 0.0;
+#pragma unroll
+  for (int c = 0; c < AMG_NM; ++c) z += ld(m, c) * w[c];
+  return z;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_amgc_cheb0(int n, const T *__restrict__ Dinv, const T *__restrict__ b, T *x, T *r, T *d, const double *lam,
+             const int *done) {
+  if (amg_done(done)) return;
+  const int t = threadIdx.x, row = blockIdx.x * AMG_CROWS + t / AMG_NM, rr = t % AMG_NM;
+  if (t >= AMG_CROWS * AMG_NM || row >= n) return;
+  double th, c1, c2;
+  amg_cheb(*lam, 0, th, c1, c2);
+  double w[AMG_NM];
+#pragma unroll
+  for (int c = 0; c < AMG_NM; ++c) w[c] = ld(b, (int64_t)row * AMG_NM + c);
+  const double z = amgc_dapply(Dinv, row, rr, w);
+  const int64_t o = (int64_t)row * AMG_NM + rr;
+  r[o] = (T)z;
+  const T dz = (T)(z / th);
+  d[o] = dz;
+  x[o] = dz;
+}
+
+// MODE 0: start from x (r = D^-1 (b - A x), d = r / theta); MODE 1: step k (as the finest level's)
+template <typename T, int MODE>
+__global__ void __launch_bounds__(256)
+k_amgc_cheb(int n, const int32_t *__restrict__ ptr, const int32_t *__restrict__ col, const T *__restrict__ A,
+            const T *__restrict__ Dinv, const T *__restrict__ b, const T *__restrict__ v, T *dn, T *r, T *x,
+            const double *lam, int k, int pending, const int *done) {
+  __shared__ double sm[AMG_CROWS][AMG_NM];
+  if (amg_done(done)) return;
+  const int t = threadIdx.x, lr = t / AMG_NM, row = blockIdx.x * AMG_CROWS + lr, rr = t % AMG_NM;
+  const bool act = t < AMG_CROWS * AMG_NM && row < n;
+  const int64_t o = (int64_t)(act ? row : 0) * AMG_NM + rr;
+  double w = 0.0;
+  if (act) {
+    const double av = amgc_row(ptr, col, A, v, row, rr);
+    w = MODE == 0 ? ld(b, o) - av : av;
+  }
+  if (t < AMG_CROWS * AMG_NM) sm[lr][rr] = w;
+  __syncthreads();
+  if (!act) return;
+  double th, c1, c2;
+  amg_cheb(*lam, k, th, c1, c2);
+  const double z = amgc_dapply(Dinv, row, rr, sm[lr]);
+  if (MODE == 0) {
+    r[o] = (T)z;
+    dn[o] = (T)(z / th);
+  } else {
+    const double rn = ld(r, o) - z;
+    const double dko = ld(v, o);
+    const double dnv = c1 * dko + c2 * rn;
+    r[o] = (T)rn;
+    dn[o] = (T)dnv;
+    x[o] = (T)(ld(x, o) + (pending ? dko : 0.0) + dnv);
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_amgc_resid(int n, const int32_t *__restrict__ ptr, const int32_t *__restrict__ col, const T *__restrict__ A,
+             const T *__restrict__ b, const T *__restrict__ x, T *res, const int *done) {
+  if (amg_done(done)) return;
+  const int t = threadIdx.x, row = blockIdx.x * AMG_CROWS + t / AMG_NM, rr = t % AMG_NM;
+  if (t >= AMG_CROWS * AMG_NM || row >= n) return;
+  const int64_t o = (int64_t)row * AMG_NM + rr;
+  res[o] = (T)(ld(b, o) - amgc_row(ptr, col, A, x, row, rr));
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_amgc_dapply(int n, const int32_t *__restrict__ ptr, const int32_t *__restrict__ col, const T *__restrict__ A,
+              const T *__restrict__ Dinv, const T *__restrict__ x, T *y) {
+  __shared__ double sm[AMG_CROWS][AMG_NM];
+  const int t = threadIdx.x, lr = t / AMG_NM, row = blockIdx.x * AMG_CROWS + lr, rr = t % AMG_NM;
+  const bool act = t < AMG_CROWS * AMG_NM && row < n;
+  if (t < AMG_CROWS * AMG_NM) sm[lr][rr] = act ? amgc_row(ptr, col, A, x, row, rr) : 0.0;
+  __syncthreads();
+  if (act) y[(int64_t)row * AMG_NM + rr] = (T)amgc_dapply(Dinv, row, rr, sm[lr]);
+}
+
+// x += d (the pending step of a degree-1 smoothing from a nonzero start)
+template <typename T>
+__global__ void k_amg_axpy(int64_t nv, const T *__restrict__ d, T *x, const int *done) {
+  if (amg_done(done)) return;
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < nv) x[i] = (T)(ld(x, i) + ld(d, i));
+}
+
+// ---- transfers -----------------------------------------------------------------------------
+// restriction bc[I][a] = sum over the members i of I (ascending) and their dofs r of
+// P[i][r][a] s[i][r] res[i][r], s = 1 / W on the finest level (Wsc != NULL), else 1
+template <typename T, typename TP, int BS>
+__global__ void k_amg_restrict(int nc, const int32_t *__restrict__ mptr, const int32_t *__restrict__ mem,
+                               const TP *__restrict__ P, const double *__restrict__ Wsc, const T *__restrict__ res,
+                               T *bc, const int *done) {
+  if (amg_done(done)) return;
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= (int64_t)nc * AMG_NM) return;
+  const int I = (int)(t / AMG_NM), a = (int)(t % AMG_NM);
+  double acc = 0.0;
+  for (int k = mptr[I]; k < mptr[I + 1]; ++k) {
+    const int i = mem[k];
+#pragma unroll
+    for (int r = 0; r < BS; ++r) {
+      const double s = Wsc ? 1.0 / Wsc[4 * (int64_t)i + r] : 1.0;
+      acc += ld(P, ((int64_t)i * BS + r) * AMG_NM + a) * s * ld(res, (int64_t)i * BS + r);
+    }
+  }
+  bc[t] = (T)acc;
+}
+
+// prolongation x[i][r] += s[i][r] sum_a P[i][r][a] xc[agg(i)][a]
+template <typename T, typename TP, int BS>
+__global__ void k_amg_prolong(int n, const int32_t *__restrict__ agg, const TP *__restrict__ P,
+                              const double *__restrict__ Wsc, const T *__restrict__ xc, T *x, const int *done) {
+  if (amg_done(done)) return;
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= (int64_t)n * BS) return;
+  const int i = (int)(t / BS), r = (int)(t % BS);
+  const T *e = xc + (int64_t)agg[i] * AMG_NM;
+  const TP *p = P + t * AMG_NM;
+  double acc = 0.0;
+#pragma unroll
+  for (int a = 0; a < AMG_NM; ++a) acc += ld(p, a) * ld(e, a);
+  const double s = Wsc ? 1.0 / Wsc[4 * (int64_t)i + r] : 1.0;
+  x[t] = (T)(ld(x, t) + s * acc);
+}
+
+// ---- coarse operators (per linear system, FP64) ---------------------------------------------
+// A_1[cb][a][c] = sum over the finest blocks b of the list of cb, with b = (i, j):
+//   sum_{r,q} (Q[i][r][a] / W[i][r]) A_b[r][q] (Q[j][q][c] / W[j][q]),
+// A_b from the entry-major fine blocks, symmetrised ((A_b + A_{tpos b}^T) / 2) when sym; plus a
+// unit diagonal on dropped coarse dofs.  One thread per coarse entry.
+__global__ void k_amg_gal0(int64_t nbc, const int32_t *__restrict__ cbrow, const int32_t *__restrict__ ccol,
+                           const uint8_t *__restrict__ dropped, const int32_t *__restrict__ gptr,
+                           const int32_t *__restrict__ gsrc, int Wslot, int64_t nnzb, const int32_t *__restrict__ fcol,
+                           const int32_t *__restrict__ tpos, const double *__restrict__ A, int sym,
+                           const double *__restrict__ Wsc, const double *__restrict__ Q, double *Ac) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= nbc * (AMG_NM * AMG_NM)) return;
+  const int64_t cb = t / (AMG_NM * AMG_NM);
+  const int e = (int)(t % (AMG_NM * AMG_NM)), a = e / AMG_NM, c = e % AMG_NM;
+  double acc = 0.0;
+  for (int k = gptr[cb]; k < gptr[cb + 1]; ++k) {
+    const int b = gsrc[k];
+    const int i = b / Wslot, j = fcol[b];
+    const int bt = sym ? tpos[b] : b;
+    double pj[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) pj[q] = Q[((int64_t)j * 3 + q) * AMG_NM + c] / Wsc[4 * (int64_t)j + q];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      double row = 0.0;
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        const double v = sym ? 0.5 * (A[(int64_t)(3 * r + q) * nnzb + b] + A[(int64_t)(3 * q + r) * nnzb + bt])
+                             : A[(int64_t)(3 * r + q) * nnzb + b];
+        row += v * pj[q];
+      }
+      acc += Q[((int64_t)i * 3 + r) * AMG_NM + a] / Wsc[4 * (int64_t)i + r] * row;
+    }
+  }
+  if (a == c && cbrow[cb] == ccol[cb] && dropped[(int64_t)cbrow[cb] * AMG_NM + a]) acc += 1.0;
+  Ac[t] = acc;
+}
+
+// A_{l+1}[cb][a][c] = sum over the level-l blocks k of the list (row i, column j) of
+// sum_r Q[i][r][a] sum_q A_l[k][r][q] Q[j][q][c]; unit diagonal on dropped coarse dofs
+__global__ void k_amg_gal(int64_t nbc, const int32_t *__restrict__ cbrow, const int32_t *__restrict__ ccol,
+                          const uint8_t *__restrict__ dropped, const int32_t *__restrict__ gptr,
+                          const int32_t *__restrict__ gsrc, const int32_t *__restrict__ fbrow,
+                          const int32_t *__restrict__ fcol, const double *__restrict__ Af,
+                          const double *__restrict__ Q, double *Ac) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= nbc * (AMG_NM * AMG_NM)) return;
+  const int64_t cb = t / (AMG_NM * AMG_NM);
+  const int e = (int)(t % (AMG_NM * AMG_NM)), a = e / AMG_NM, c = e % AMG_NM;
+  double acc = 0.0;
+  for (int k = gptr[cb]; k < gptr[cb + 1]; ++k) {
+    const int fb = gsrc[k];
+    const int i = fbrow[fb], j = fcol[fb];
+    const double *Ab = Af + (int64_t)fb * (AMG_NM * AMG_NM);
+    double pj[AMG_NM];
+#pragma unroll
+    for (int q = 0; q < AMG_NM; ++q) pj[q] = Q[((int64_t)j * AMG_NM + q) * AMG_NM + c];
+    for (int r = 0; r < AMG_NM; ++r) {
+      double row = 0.0;
+#pragma unroll
+      for (int q = 0; q < AMG_NM; ++q) row += Ab[r * AMG_NM + q] * pj[q];
+      acc += Q[((int64_t)i * AMG_NM + r) * AMG_NM + a] * row;
+    }
+  }
+  if (a == c && cbrow[cb] == ccol[cb] && dropped[(int64_t)cbrow[cb] * AMG_NM + a]) acc += 1.0;
+  Ac[t] = acc;
+}
+
+// inverse of the 10x10 diagonal block of every row (Gauss-Jordan, partial pivoting, FP64); a
+// singular block leaves its row's inverse zero and raises the level's flag
+template <typename T>
+__global__ void k_amg_dinv(int n, const int32_t *__restrict__ dpos, const double *__restrict__ Ac, T *Dinv,
+                           int *bad) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double m[AMG_NM][2 * AMG_NM];
+  const double *blk = Ac + (int64_t)dpos[i] * (AMG_NM * AMG_NM);
+  for (int r = 0; r < AMG_NM; ++r)
+    for (int c = 0; c < AMG_NM; ++c) {
+      m[r][c] = blk[r * AMG_NM + c];
+      m[r][AMG_NM + c] = (r == c) ? 1.0 : 0.0;
+    }
+  bool ok = true;
+  for (int c = 0; c < AMG_NM && ok; ++c) {
+    int p = c;
+    for (int r = c + 1; r < AMG_NM; ++r)
+      if (fabs(m[r][c]) > fabs(m[p][c])) p = r;
+    if (!(fabs(m[p][c]) > 0.0)) { ok = false; break; }
+    if (p != c)
+      for (int q = 0; q < 2 * AMG_NM; ++q) { const double tmp = m[c][q]; m[c][q] = m[p][q]; m[p][q] = tmp; }
+    const double inv = 1.0 / m[c][c];
+    for (int q = 0; q < 2 * AMG_NM; ++q) m[c][q] *= inv;
+    for (int r = 0; r < AMG_NM; ++r) {
+      if (r == c) continue;
+      const double f = m[r][c];
+      if (f != 0.0)
+        for (int q = 0; q < 2 * AMG_NM; ++q) m[r][q] -= f * m[c][q];
+    }
+  }
+  T *out = Dinv + (int64_t)i * (AMG_NM * AMG_NM);
+  for (int r = 0; r < AMG_NM; ++r)
+    for (int c = 0; c < AMG_NM; ++c) out[r * AMG_NM + c] = ok ? (T)m[r][AMG_NM + c] : (T)0;
+  if (!ok) *bad = 1;
+}
+
+template <typename T>
+__global__ void k_amg_cvt(int64_t count, const double *__restrict__ src, T *dst) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < count) dst[i] = (T)src[i];
+}
+
+template <typename T>
+__global__ void k_amg_power_init(int64_t nv, uint64_t seed, T *x) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < nv) x[i] = (T)splitmix_unit(seed, (uint64_t)i);
+}
+
+__global__ void k_amg_lam_final(const double *lam_tmp, double *lam) { *lam = AMG_LMAX_SAFETY * *lam_tmp; }

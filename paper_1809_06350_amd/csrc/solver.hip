@@ -919,6 +919,77 @@ k_cg_update(int64_t nn, T *x, T *r, T *z, const T *__restrict__ p, const T *__re
   cg_block_sums2(rz, rr, ctrl + off.pn + blockIdx.x, ctrl + off.pn2 + blockIdx.x, sm);
 }
 
+// ---- CG with the preconditioner applied by separate kernels (the multigrid V-cycle) -----------
+// The iteration is the one above with z = M^-1 r formed between the update and the product: an
+// update kernel (x += alpha p, r -= alpha q), the V-cycle r -> z, the partials of <r,z> and
+// <r,r>, then k_cg_spmv, which reads those partials, tests convergence and forms p and q.
+
+// start: r = b, x = 0, the level flags reset
+template <typename T>
+__global__ void __launch_bounds__(KRY_BLOCK)
+k_cgx_init(int64_t nn, const T *__restrict__ b, T *x, T *r, int *iflag) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    iflag[IF_DONE] = 0;
+    iflag[IF_ITS] = 0;
+    iflag[IF_STATUS] = KS_OK;
+  }
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < 3 * nn; i += stride) {
+    r[i] = b[i];
+    x[i] = (T)0;
+  }
+}
+
+// partials of <r,z> and <r,r> (one per workgroup, the layout k_cg_spmv reads)
+template <typename T>
+__global__ void __launch_bounds__(KRY_BLOCK)
+k_cgx_rz(int64_t nn, const T *__restrict__ r, const T *__restrict__ z, double *prz, double *prr, const int *iflag) {
+  __shared__ double sm[2][16];
+  if (iflag[IF_DONE]) return;
+  double rz = 0.0, rr = 0.0;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nn; i += stride) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const double rv = dl(r, 3 * i + c);
+      rz += rv * dl(z, 3 * i + c);
+      rr += rv * rv;
+    }
+  }
+  cg_block_sums2(rz, rr, prz + blockIdx.x, prr + blockIdx.x, sm);
+}
+
+// second half of iteration j without the preconditioner: alpha = rz_j / <p_j, q>, x += alpha p,
+// r -= alpha q (a non-positive <p, A p> ends the level, as in k_cg_update)
+template <typename T>
+__global__ void __launch_bounds__(KRY_BLOCK)
+k_cgx_update(int64_t nn, T *x, T *r, const T *__restrict__ p, const T *__restrict__ q, double *ctrl, KOff off,
+             const double *ppart, int nps, int *iflag, int j) {
+  __shared__ double sm[16];
+  __shared__ int done0;
+  if (threadIdx.x == 0) done0 = iflag[IF_DONE];
+  __syncthreads();
+  if (done0) return;
+  const double pq = cg_sum_partials(ppart, nps, sm);
+  const double alpha = ctrl[off.scal + 3 + (j & 1)] / pq;
+  if (!(pq > 0.0) || !isfinite(alpha)) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      iflag[IF_ITS] = j;
+      iflag[IF_STATUS] = isfinite(pq) ? KS_BREAKDOWN : KS_NAN;
+      iflag[IF_DONE] = 1;
+    }
+    return;
+  }
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < 3 * nn; i += stride) {
+    const double xo = dl(x, i), po = dl(p, i), ro = dl(r, i), qo = dl(q, i);
+    x[i] = (T)(xo + alpha * po);
+    r[i] = (T)(ro - alpha * qo);
+  }
+}
+
+#include "amg.h"
+
 // ---- CG steps on S^ as the Schur-level preconditioner ---------------------------
 // A fixed number k of diag(S^)-preconditioned CG steps on S^ z = v from
 // z = 0: for each right-hand side the Krylov-optimal polynomial of degree k,
@@ -1685,6 +1756,245 @@ int cg_run(vms_ctx *ctx, KLevel<T> &L, const vms_mesh *mesh, const T *Acg, doubl
   return VMS_OK;
 }
 
+// The multigrid of one linear system: coarse operators, block-diagonal inverses, Chebyshev bounds
+// and the V-cycle work vectors in the level precision T (FP64 copies of the coarse operators for
+// the Galerkin products), carved from the solve's workspace.
+template <typename T>
+struct AmgSys {
+  const vms_amg_dev *h = nullptr;
+  int L = 0;
+  double *Ac64[VMS_AMG_MAX_LEVELS] = {};
+  T *Ac[VMS_AMG_MAX_LEVELS] = {};
+  T *Dinv[VMS_AMG_MAX_LEVELS] = {};
+  T *xv[VMS_AMG_MAX_LEVELS] = {}, *bv[VMS_AMG_MAX_LEVELS] = {}, *rv[VMS_AMG_MAX_LEVELS] = {};
+  T *d0[VMS_AMG_MAX_LEVELS] = {}, *d1[VMS_AMG_MAX_LEVELS] = {};
+  double *lam = nullptr, *ltmp = nullptr, *part = nullptr;
+  int *bad = nullptr;
+  // finest level: the A-level operator and its 3x3 block-Jacobi inverses
+  const T *A0 = nullptr, *M0 = nullptr;
+  const vms_mesh *mesh = nullptr;
+  const double *Wsc = nullptr;
+
+  void carve(Carver &cv, const vms_mesh *m) {
+    h = vms_amg_device(m->amg);   // checked by check_opts before any solve; absent: nothing to carve
+    L = h ? h->n_levels : 0;
+    for (int l = 0; l < L; ++l) {
+      const vms_amg_level_dev &lv = h->lev[l];
+      const int64_t nv = (int64_t)lv.n * lv.bs;
+      if (l > 0) {
+        Ac64[l] = cv.take<double>(lv.nnzb * AMG_NM * AMG_NM);
+        Ac[l] = std::is_same<T, double>::value ? (T *)Ac64[l] : cv.take<T>(lv.nnzb * AMG_NM * AMG_NM);
+        Dinv[l] = cv.take<T>((int64_t)lv.n * AMG_NM * AMG_NM);
+        xv[l] = cv.take<T>(nv);
+        bv[l] = cv.take<T>(nv);
+      }
+      rv[l] = cv.take<T>(nv);
+      d0[l] = cv.take<T>(nv);
+      d1[l] = cv.take<T>(nv);
+    }
+    lam = cv.take<double>(VMS_AMG_MAX_LEVELS);
+    ltmp = cv.take<double>(8);
+    part = cv.take<double>(VMS_MAX_RED_BLOCKS);
+    bad = cv.take<int>(4);
+  }
+
+  // per linear system: Galerkin products from the FP64 scaled A (symmetrised when sym), inverses
+  // of the coarse diagonal blocks, FP32 copies, and lmax of every level
+  int setup(vms_ctx *ctx, const vms_mesh *m, const vms_matrix *K, const T *A0_, const T *M0_, int sym) {
+    hipStream_t s = ctx->stream;
+    mesh = m;
+    A0 = A0_;
+    M0 = M0_;
+    Wsc = K->W;
+    const dim3 bl(VMS_BLOCK);
+    hipLaunchKernelGGL(k_clear_ints, dim3(1), dim3(64), 0, s, bad, 1);
+    for (int l = 1; l < L; ++l) {
+      const vms_amg_level_dev &c = h->lev[l], &f = h->lev[l - 1];
+      const int64_t ne = c.nnzb * AMG_NM * AMG_NM;
+      const dim3 g((unsigned)((ne + VMS_BLOCK - 1) / VMS_BLOCK));
+      if (l == 1)
+        hipLaunchKernelGGL(k_amg_gal0, g, bl, 0, s, c.nnzb, c.brow, c.col, c.dropped, f.gptr, f.gsrc,
+                           m->slot_width, m->nnzb, m->col, m->tpos, (const double *)K->A, sym,
+                           (const double *)K->W, f.P, Ac64[1]);
+      else
+        hipLaunchKernelGGL(k_amg_gal, g, bl, 0, s, c.nnzb, c.brow, c.col, c.dropped, f.gptr, f.gsrc, f.brow, f.col,
+                           (const double *)Ac64[l - 1], f.P, Ac64[l]);
+      hipLaunchKernelGGL(k_amg_dinv<T>, dim3(grid1(c.n)), bl, 0, s, c.n, c.dpos, (const double *)Ac64[l], Dinv[l],
+                         bad);
+      if (!std::is_same<T, double>::value) hipLaunchKernelGGL(k_amg_cvt<T>, g, bl, 0, s, ne, (const double *)Ac64[l], Ac[l]);
+    }
+    for (int l = 0; l < L; ++l) power(ctx, l);
+    VMS_LAUNCH_CHECK(ctx);
+    return VMS_OK;
+  }
+
+  // lam[l] = 1.1 ||D^-1 A x|| / ||x|| after AMG_POWER_STEPS power steps from a SplitMix64 vector
+  void power(vms_ctx *ctx, int l) {
+    hipStream_t s = ctx->stream;
+    const vms_amg_level_dev &lv = h->lev[l];
+    const int64_t nv = (int64_t)lv.n * lv.bs;
+    const int nb = vms_red_blocks(nv);
+    const dim3 bl(VMS_BLOCK), gv((unsigned)((nv + VMS_BLOCK - 1) / VMS_BLOCK));
+    T *x = d0[l], *y = d1[l];
+    hipLaunchKernelGGL(k_amg_power_init<T>, gv, bl, 0, s, nv, (uint64_t)(l + 1), x);
+    hipLaunchKernelGGL(k_norm_part<T>, dim3(nb), bl, 0, s, nv, (const T *)x, part, (const int *)nullptr);
+    hipLaunchKernelGGL(k_store_norm, dim3(1), bl, 0, s, nb, (const double *)part, ltmp);
+    hipLaunchKernelGGL(k_power_scale<T>, gv, bl, 0, s, (int)nv, (const T *)x, (const double *)ltmp, x);
+    for (int it = 0; it < AMG_POWER_STEPS; ++it) {
+      if (l == 0)
+        hipLaunchKernelGGL(k_amgf_dapply<T>, dim3(spmv_grid(lv.n)), bl, 0, s, lv.n, mesh->nnzb, mesh->slot_width,
+                           mesh->col, A0, M0, (const T *)x, y);
+      else
+        hipLaunchKernelGGL(k_amgc_dapply<T>, dim3(amg_cgrid(lv.n)), dim3(256), 0, s, lv.n, lv.ptr, lv.col,
+                           (const T *)Ac[l], (const T *)Dinv[l], (const T *)x, y);
+      hipLaunchKernelGGL(k_norm_part<T>, dim3(nb), bl, 0, s, nv, (const T *)y, part, (const int *)nullptr);
+      hipLaunchKernelGGL(k_store_norm, dim3(1), bl, 0, s, nb, (const double *)part, ltmp);
+      hipLaunchKernelGGL(k_power_scale<T>, gv, bl, 0, s, (int)nv, (const T *)y, (const double *)ltmp, x);
+    }
+    hipLaunchKernelGGL(k_amg_lam_final, dim3(1), dim3(1), 0, s, (const double *)ltmp, lam + l);
+  }
+
+  // degree-k Chebyshev smoothing of level l for A x = b, from zero (zero) or from x
+  void smooth(hipStream_t s, int l, const T *b, T *x, bool zero, int deg, const int *done) {
+    const vms_amg_level_dev &lv = h->lev[l];
+    const int n = lv.n;
+    const double *lm = lam + l;
+    const dim3 bl(VMS_BLOCK), gf(spmv_grid(n)), gc(amg_cgrid(n)), bc(256);
+    T *dk = d0[l], *dn = d1[l], *r = rv[l];
+    if (l == 0) {
+      if (zero)
+        hipLaunchKernelGGL(k_amgf_cheb0<T>, dim3(grid1(n)), bl, 0, s, n, M0, b, x, r, dk, lm, done);
+      else
+        hipLaunchKernelGGL(k_amgf_chebres<T>, gf, bl, 0, s, n, mesh->nnzb, mesh->slot_width, mesh->col, A0, M0, b,
+                           (const T *)x, r, dk, lm, done);
+    } else {
+      if (zero)
+        hipLaunchKernelGGL(k_amgc_cheb0<T>, gc, bc, 0, s, n, (const T *)Dinv[l], b, x, r, dk, lm, done);
+      else
+        hipLaunchKernelGGL((k_amgc_cheb<T, 0>), gc, bc, 0, s, n, lv.ptr, lv.col, (const T *)Ac[l],
+                           (const T *)Dinv[l], b, (const T *)x, dk, r, x, lm, 0, 0, done);
+    }
+    const int pending = zero ? 0 : 1;
+    for (int k = 0; k + 1 < deg; ++k) {
+      if (l == 0)
+        hipLaunchKernelGGL(k_amgf_step<T>, gf, bl, 0, s, n, mesh->nnzb, mesh->slot_width, mesh->col, A0, M0,
+                           (const T *)dk, dn, r, x, lm, k, k == 0 ? pending : 0, done);
+      else
+        hipLaunchKernelGGL((k_amgc_cheb<T, 1>), gc, bc, 0, s, n, lv.ptr, lv.col, (const T *)Ac[l],
+                           (const T *)Dinv[l], (const T *)nullptr, (const T *)dk, dn, r, x, lm, k,
+                           k == 0 ? pending : 0, done);
+      std::swap(dk, dn);
+    }
+    if (deg == 1 && !zero) {
+      const int64_t nv = (int64_t)n * lv.bs;
+      hipLaunchKernelGGL(k_amg_axpy<T>, dim3((unsigned)((nv + VMS_BLOCK - 1) / VMS_BLOCK)), bl, 0, s, nv,
+                         (const T *)dk, x, done);
+    }
+  }
+
+  // x = V-cycle(b) on level l
+  void vcycle(hipStream_t s, int l, const T *b, T *x, const int *done) {
+    const vms_amg_level_dev &lv = h->lev[l];
+    if (l == L - 1) {
+      smooth(s, l, b, x, true, h->coarse_degree, done);
+      return;
+    }
+    const vms_amg_level_dev &c = h->lev[l + 1];
+    smooth(s, l, b, x, true, h->degree, done);
+    T *res = rv[l];
+    const dim3 bl(VMS_BLOCK);
+    if (l == 0)
+      hipLaunchKernelGGL(k_amgf_resid<T>, dim3(spmv_grid(lv.n)), bl, 0, s, lv.n, mesh->nnzb, mesh->slot_width,
+                         mesh->col, A0, b, (const T *)x, res, done);
+    else
+      hipLaunchKernelGGL(k_amgc_resid<T>, dim3(amg_cgrid(lv.n)), dim3(256), 0, s, lv.n, lv.ptr, lv.col,
+                         (const T *)Ac[l], b, (const T *)x, res, done);
+    const dim3 gr((unsigned)(((int64_t)c.n * AMG_NM + VMS_BLOCK - 1) / VMS_BLOCK));
+    const dim3 gp((unsigned)(((int64_t)lv.n * lv.bs + VMS_BLOCK - 1) / VMS_BLOCK));
+    constexpr bool F32 = std::is_same<T, float>::value;
+    using TP = typename std::conditional<F32, float, double>::type;
+    const TP *P = F32 ? (const TP *)lv.P32 : (const TP *)lv.P;
+    if (l == 0)
+      hipLaunchKernelGGL((k_amg_restrict<T, TP, 3>), gr, bl, 0, s, c.n, lv.mptr, lv.mem, P, Wsc, (const T *)res,
+                         bv[1], done);
+    else
+      hipLaunchKernelGGL((k_amg_restrict<T, TP, AMG_NM>), gr, bl, 0, s, c.n, lv.mptr, lv.mem, P,
+                         (const double *)nullptr, (const T *)res, bv[l + 1], done);
+    vcycle(s, l + 1, bv[l + 1], xv[l + 1], done);
+    if (l == 0)
+      hipLaunchKernelGGL((k_amg_prolong<T, TP, 3>), gp, bl, 0, s, lv.n, lv.agg, P, Wsc, (const T *)xv[1], x, done);
+    else
+      hipLaunchKernelGGL((k_amg_prolong<T, TP, AMG_NM>), gp, bl, 0, s, lv.n, lv.agg, P, (const double *)nullptr,
+                         (const T *)xv[l + 1], x, done);
+    smooth(s, l, b, x, false, h->degree, done);
+  }
+};
+
+// Preconditioned CG with the multigrid V-cycle as the preconditioner (same stopping test, flags
+// and batching as cg_run): update, V-cycle, <r,z> partials, product.
+template <typename T>
+int amg_cg_run(vms_ctx *ctx, KLevel<T> &L, const vms_mesh *mesh, const T *Acg, double *ppart, const T *b, T *x,
+               double rtol, double atol, int maxit, AmgSys<T> &mg, int &est, int &its_out, int &status_out,
+               const double *relax = nullptr) {
+  hipStream_t s = ctx->stream;
+  const int n = mesh->n_nodes;
+  const int64_t nn = n;
+  T *r = L.V, *z = L.Z, *p = L.V + L.nvec, *q = L.W;
+  const int gs = cg_spmv_blocks(n);
+  const dim3 gk(kry_blocks(nn)), bk(KRY_BLOCK), gsp(gs), bl(VMS_BLOCK);
+  const int nbk = (int)gk.x;
+  const int *done = L.iflag + IF_DONE;
+  hipLaunchKernelGGL(k_cgx_init<T>, gk, bk, 0, s, nn, b, x, r, L.iflag);
+  auto precond = [&]() {
+    mg.vcycle(s, 0, (const T *)r, z, done);
+    hipLaunchKernelGGL(k_cgx_rz<T>, gk, bk, 0, s, nn, (const T *)r, (const T *)z, L.ctrl + L.off.pn,
+                       L.ctrl + L.off.pn2, (const int *)L.iflag);
+  };
+  auto spmv = [&](int j, volatile int32_t *post, int32_t seq) {
+    const vms_timed tm = vms_timer_next(ctx, std::is_same<T, float>::value ? 1 : 0);
+    if (tm.slot >= 0)
+      hipExtLaunchKernelGGL(k_cg_spmv<T>, gsp, bl, 0, s, tm.e0, tm.e1, 0, n, (int64_t)mesh->nnzb,
+                            (int)mesh->slot_width, mesh->col, Acg, (const T *)z, p, q, L.ctrl, L.off, ppart, L.iflag,
+                            j, nbk, rtol, atol, maxit, post, seq, tm.worked, relax);
+    else
+      hipLaunchKernelGGL(k_cg_spmv<T>, gsp, bl, 0, s, n, (int64_t)mesh->nnzb, (int)mesh->slot_width, mesh->col,
+                         Acg, (const T *)z, p, q, L.ctrl, L.off, ppart, L.iflag, j, nbk, rtol, atol, maxit, post, seq,
+                         (int *)nullptr, relax);
+  };
+  precond();
+  int j = 0;
+  spmv(0, nullptr, 0);
+  VMS_LAUNCH_CHECK(ctx);
+  int batch = std::max(1, est);
+  bool fin = false;
+  while (!fin) {
+    const int nbt = std::min(batch, maxit - j);
+    if (nbt <= 0) {   // not reached: the product kernel of iteration maxit always ends the level
+      int rc = sync_level_flags(ctx, L.iflag);
+      if (rc) return rc;
+      break;
+    }
+    const int32_t seq = ++ctx->post_seq;
+    for (int i = 0; i < nbt; ++i) {
+      hipLaunchKernelGGL(k_cgx_update<T>, gk, bk, 0, s, nn, x, r, (const T *)p, (const T *)q, L.ctrl, L.off,
+                         (const double *)ppart, gs, L.iflag, j);
+      precond();
+      ++j;
+      spmv(j, i == nbt - 1 ? ctx->h_post : nullptr, seq);
+    }
+    VMS_LAUNCH_CHECK(ctx);
+    int rc = vms_wait_post(ctx, seq, L.iflag);
+    if (rc) return rc;
+    fin = ctx->h_i[IF_DONE] != 0;
+    batch = std::min(2 * batch, 64);
+  }
+  status_out = ctx->h_i[IF_STATUS];
+  its_out = ctx->h_i[IF_ITS];
+  est = std::max(1, its_out);
+  if (status_out == KS_NAN) return vms_set_error(ctx, VMS_ERR_NAN, "NaN/Inf in a CG level");
+  return VMS_OK;
+}
+
 template <typename T>
 struct Nested {
   vms_ctx *ctx;
@@ -1707,6 +2017,7 @@ struct Nested {
   PcgVec<T> pv{};                             // their work vectors
   T *dAinv = nullptr;                         // SIMPLE: diag(A)^-1
   double *lam = nullptr;                      // device: lmax estimate of diag(S^)^-1 S^
+  AmgSys<T> mg;                               // multigrid of the A-levels (a_prec = AMG)
   vms_solve_stats *stats;
   int err = VMS_OK;
 
@@ -1741,6 +2052,7 @@ struct Nested {
       cgpart = cv.take<double>(cg_spmv_blocks(m_->n_nodes));
       if (o_->cg_symmetrise) As = cv.take<T>(9 * m_->nnzb);
     }
+    if (o_->a_prec == VMS_APC_AMG) mg.carve(cv, m_);
     if (o_->schur_mass > 0.0) {
       mlw = cv.take<double>(nn);
       msum = cv.take<double>(4);
@@ -1812,7 +2124,10 @@ struct Nested {
     const double rtol = inner ? o->rtol_I : o->rtol_A, atol = inner ? o->atol_I : o->atol_A;
     const int maxit = inner ? o->maxit_I : o->maxit_A;
     int &est = inner ? ctx->est_I : ctx->est_A;
+    const bool amg = o->a_prec == VMS_APC_AMG;
     auto op = [&](int j) -> int {
+      // multigrid: flexible form, Z_j = V-cycle(V_j) before the product
+      if (amg) mg.vcycle(ctx->stream, 0, LA.V + (int64_t)j * LA.nvec, LA.Z + (int64_t)j * LA.nvec, LA.iflag + IF_DONE);
       launch_spmv_A<T>(ctx, mesh, A, LA.Z + (int64_t)j * LA.nvec, LA.W, LA.iflag + IF_DONE);
       return VMS_OK;
     };
@@ -1822,10 +2137,15 @@ struct Nested {
     // the inner solve of a Schur product (called only from the Schur level's
     // operator) may relax its tolerance with the Schur level's progress
     const double *relax = (inner && may_relax && o->relax_inner) ? LS.ctrl + LS.off.scal : nullptr;
-    int rc = cg ? cg_run<T>(ctx, LA, mesh, o->cg_symmetrise ? (const T *)As : A, cgpart, b, x, rtol, atol, maxit,
-                            Minv, est, its, st, relax)
-                : gmres_run<T>(ctx, LA, b, x, rtol, atol, maxit, o->orth, PC_BJ33, Minv, false, est, op, its, st,
-                               relax);
+    const T *Acg = o->cg_symmetrise ? (const T *)As : A;
+    int rc;
+    if (cg && amg)
+      rc = amg_cg_run<T>(ctx, LA, mesh, Acg, cgpart, b, x, rtol, atol, maxit, mg, est, its, st, relax);
+    else if (cg)
+      rc = cg_run<T>(ctx, LA, mesh, Acg, cgpart, b, x, rtol, atol, maxit, Minv, est, its, st, relax);
+    else
+      rc = gmres_run<T>(ctx, LA, b, x, rtol, atol, maxit, o->orth, amg ? PC_NONE : PC_BJ33, Minv, false, est, op,
+                        its, st, relax);
     vms_phase_end(ctx, ph, inner ? VMS_PH_INNER : VMS_PH_A);
     if (inner) { stats->n_I_solves++; stats->it_I += its; }
     else { stats->n_A_solves++; stats->it_A += its; }
@@ -1961,6 +2281,11 @@ struct Nested {
                        K->A, Minv, sym);
     if (sym)
       hipLaunchKernelGGL(k_sym_A<T>, dim3(grid1(nnzb)), dim3(VMS_BLOCK), 0, ctx->stream, nnzb, mesh->tpos, K->A, As);
+    if (o->a_prec == VMS_APC_AMG) {
+      if (!K->W) return vms_set_error(ctx, VMS_ERR_ARG, "a_prec AMG needs the scaling K->W");
+      int rc = mg.setup(ctx, mesh, K, sym ? (const T *)As : A, Minv, sym);
+      if (rc) return rc;
+    }
     if (o->precond == VMS_PC_SIMPLE)
       hipLaunchKernelGGL(k_diagA_inv<T>, dim3(grid1(n)), dim3(VMS_BLOCK), 0, ctx->stream, n, mesh->diag_pos, nnzb,
                          K->A, dAinv);
@@ -2016,7 +2341,7 @@ size_t core_bytes(const vms_mesh *m, const vms_solver_opts *o) {
   return cv.off + 256;
 }
 
-int check_opts(vms_ctx *ctx, const vms_solver_opts *o) {
+int check_opts(vms_ctx *ctx, const vms_solver_opts *o, const vms_mesh *m) {
   if (!o || o->maxit <= 0 || o->maxit_A <= 0 || o->maxit_S <= 0 || o->maxit_I <= 0 || o->maxit > 1000 ||
       o->maxit_A > 1000 || o->maxit_S > 1000 || o->maxit_I > 1000)
     return vms_set_error(ctx, VMS_ERR_ARG, "solver options: maxit must be in [1, 1000]");
@@ -2046,6 +2371,16 @@ int check_opts(vms_ctx *ctx, const vms_solver_opts *o) {
     return vms_set_error(ctx, VMS_ERR_ARG, "unknown Schur step");
   if (o->relax_inner != 0 && o->relax_inner != 1)
     return vms_set_error(ctx, VMS_ERR_ARG, "relax_inner must be 0 or 1");
+  if (o->a_prec != VMS_APC_BJ && o->a_prec != VMS_APC_AMG)
+    return vms_set_error(ctx, VMS_ERR_ARG, "unknown A-level preconditioner");
+  if (o->a_prec == VMS_APC_AMG) {
+    const vms_amg_dev *h = m ? vms_amg_device(m->amg) : nullptr;
+    if (!h) return vms_set_error(ctx, VMS_ERR_ARG, "a_prec AMG needs mesh->amg");
+    if (!h->uploaded || h->device != ctx->device)
+      return vms_set_error(ctx, VMS_ERR_STATE, "the multigrid hierarchy is not uploaded to this device");
+    if (h->lev[0].n != m->n_nodes || h->lev[0].nnzb != m->nnzb)
+      return vms_set_error(ctx, VMS_ERR_ARG, "the multigrid hierarchy belongs to another mesh");
+  }
   return VMS_OK;
 }
 
@@ -2138,7 +2473,7 @@ int vms_check_solve(vms_ctx *ctx, const vms_mesh *mesh, const vms_matrix *K, con
                     const char *who) {
   int rc = vms_check_mesh(ctx, mesh);
   if (rc) return rc;
-  if ((rc = check_opts(ctx, opts))) return rc;
+  if ((rc = check_opts(ctx, opts, mesh))) return rc;
   if (!K || !K->A || !K->B || !K->C || !K->D || !stats || !workspace)
     return vms_set_error(ctx, VMS_ERR_ARG, "%s: missing argument", who);
   if (workspace_bytes_in < need)
@@ -2331,6 +2666,67 @@ extern "C" int vms_shat_spmv(vms_ctx *ctx, const vms_mesh *mesh, const void *S, 
   return VMS_OK;
 }
 
+// ---- one multigrid V-cycle (the A-levels' preconditioner on its own) -------------
+namespace {
+struct AmgApplyWs {
+  double *Minv = nullptr, *As = nullptr;
+  AmgSys<double> mg;
+  void carve(Carver &cv, const vms_mesh *m, int sym) {
+    Minv = cv.take<double>(9 * (int64_t)m->n_nodes);
+    if (sym) As = cv.take<double>(9 * m->nnzb);
+    mg.carve(cv, m);
+  }
+};
+}  // namespace
+
+extern "C" size_t vms_amg_apply_workspace(const vms_mesh *mesh, int sym) {
+  if (!mesh || mesh->n_nodes <= 0 || !vms_amg_device(mesh->amg)) return 0;
+  Carver cv{nullptr};
+  AmgApplyWs w;
+  w.carve(cv, mesh, sym ? 1 : 0);
+  return cv.off + 256;
+}
+
+extern "C" int vms_amg_apply(vms_ctx *ctx, const vms_mesh *mesh, const vms_matrix *K, int sym, const double *r,
+                             double *z, void *workspace, size_t workspace_bytes) {
+  if (!ctx) return VMS_ERR_ARG;
+  int rc = vms_check_mesh(ctx, mesh);
+  if (rc) return rc;
+  vms_solver_opts o{};
+  o.maxit = o.maxit_A = o.maxit_S = o.maxit_I = 1;
+  o.a_prec = VMS_APC_AMG;
+  o.orth = VMS_ORTH_CGS1;
+  o.a_krylov = VMS_AK_GMRES;
+  o.shat_method = VMS_SHAT_CG;
+  if ((rc = check_opts(ctx, &o, mesh))) return rc;
+  if (!K || !K->A || !K->W || !r || !z || !workspace)
+    return vms_set_error(ctx, VMS_ERR_ARG, "vms_amg_apply: missing argument");
+  if (sym != 0 && sym != 1) return vms_set_error(ctx, VMS_ERR_ARG, "vms_amg_apply: sym must be 0 or 1");
+  const size_t need = vms_amg_apply_workspace(mesh, sym);
+  if (workspace_bytes < need)
+    return vms_set_error(ctx, VMS_ERR_WORKSPACE, "vms_amg_apply: workspace too small: %zu < %zu", workspace_bytes,
+                         need);
+  Carver cv{(char *)(((uintptr_t)workspace + 255) & ~(uintptr_t)255)};
+  AmgApplyWs w;
+  w.carve(cv, mesh, sym);
+  hipStream_t s = ctx->stream;
+  const int n = mesh->n_nodes;
+  hipLaunchKernelGGL(k_bj33_setup<double>, dim3(grid1(n)), dim3(VMS_BLOCK), 0, s, n, mesh->diag_pos, mesh->nnzb,
+                     (const double *)K->A, w.Minv, sym);
+  if (sym)
+    hipLaunchKernelGGL(k_sym_A<double>, dim3(grid1(mesh->nnzb)), dim3(VMS_BLOCK), 0, s, mesh->nnzb, mesh->tpos,
+                       (const double *)K->A, w.As);
+  if ((rc = w.mg.setup(ctx, mesh, K, sym ? (const double *)w.As : (const double *)K->A, (const double *)w.Minv,
+                       sym)))
+    return rc;
+  w.mg.vcycle(s, 0, r, z, nullptr);
+  VMS_LAUNCH_CHECK(ctx);
+  VMS_HIP(ctx, hipMemcpyAsync(ctx->h_i, w.mg.bad, sizeof(int), hipMemcpyDeviceToHost, s));
+  VMS_HIP(ctx, hipStreamSynchronize(s));
+  if (ctx->h_i[0]) return vms_set_error(ctx, VMS_ERR_BREAKDOWN, "vms_amg_apply: singular coarse diagonal block");
+  return VMS_OK;
+}
+
 // ---- time step ---------------------------------------------------------------
 extern "C" size_t vms_step_workspace(const vms_mesh *mesh, const vms_solver_opts *opts) {
   if (!mesh || !opts || mesh->n_nodes <= 0) return 0;
@@ -2347,7 +2743,7 @@ extern "C" int vms_step(vms_ctx *ctx, const vms_mesh *mesh, const vms_material *
   if (!ctx) return VMS_ERR_ARG;
   int rc = vms_check_mesh(ctx, mesh);
   if (rc) return rc;
-  if ((rc = check_opts(ctx, so))) return rc;
+  if ((rc = check_opts(ctx, so, mesh))) return rc;
   if (!mat || !ti || !st || !K || !no || !stats || !workspace || no->l_max <= 0 || !(ti->dt > 0.0))
     return vms_set_error(ctx, VMS_ERR_ARG, "vms_step: missing argument");
   if (no->dir_lift != 0 && no->dir_lift != 1) return vms_set_error(ctx, VMS_ERR_ARG, "dir_lift must be 0 or 1");

@@ -29,6 +29,25 @@ struct vms_dev_status {
   double part[VMS_MAX_RED_BLOCKS];
 };
 
+#define VMS_AMG_MODES 10      // near-null modes per aggregate (coarse dofs per coarse node)
+
+// device arrays of one multigrid level (fixed per mesh; amg_setup.cpp)
+struct vms_amg_level_dev {
+  int32_t n = 0, bs = 3;
+  int64_t nnzb = 0;                     // level 0: the mesh's slots; level >= 1: CSR blocks
+  const int32_t *ptr = nullptr, *col = nullptr, *brow = nullptr, *dpos = nullptr;   // level >= 1
+  const uint8_t *dropped = nullptr;     // level >= 1: [n * 10], coarse dofs without a mode
+  const int32_t *agg = nullptr, *mptr = nullptr, *mem = nullptr;   // to the next level
+  const double *P = nullptr;            // [n][bs][10]
+  const float *P32 = nullptr;
+  const int32_t *gptr = nullptr, *gsrc = nullptr;   // Galerkin lists of the next level's blocks
+};
+struct vms_amg_dev {
+  int n_levels = 0, degree = 2, coarse_degree = 8, uploaded = 0, device = -1;
+  vms_amg_level_dev lev[VMS_AMG_MAX_LEVELS];
+};
+const vms_amg_dev *vms_amg_device(const vms_amg *amg);
+
 #define VMS_MAX_TIMED 65536   // timed launches per kind between two reads
 #define VMS_PHASE_EVENTS 1024 // event pairs of the solver's phase timing (created with the context)
 

@@ -25,6 +25,7 @@ ORTH_CGS2, ORTH_MGS, ORTH_CGS1, ORTH_CGS_IFNEEDED = 0, 1, 2, 3
 AK_GMRES, AK_CG_INNER, AK_CG = 0, 1, 2
 SHAT_CHEBYSHEV, SHAT_CG, SHAT_NONE = 0, 1, 2
 SCHUR_KRYLOV, SCHUR_SHAT = 0, 1
+APC_BJ, APC_AMG = 0, 1
 
 STATE_KEYS = ("u_n", "p_n", "v_n", "du_n", "dp_n", "dv_n", "u", "p", "v", "du", "dp", "dv")
 
@@ -39,10 +40,14 @@ def solver_opts(rtol=1e-8, atol=1e-50, maxit=200, rtol_A=5e-5, atol_A=1e-50, max
                 rtol_S=1.5e-5, atol_S=1e-50, maxit_S=200, rtol_I=7e-5, atol_I=1e-50, maxit_I=500,
                 precond=PC_LDU, precision=FP64, orth=ORTH_CGS1, shat_degree=16,
                 shat_ratio=20.0, a_krylov=AK_GMRES, cg_symmetrise=1, shat_method=SHAT_CG,
-                schur_solve=SCHUR_KRYLOV, relax_inner=0, schur_mass=0.0) -> L.SolverOpts:
+                schur_solve=SCHUR_KRYLOV, relax_inner=0, schur_mass=0.0, a_prec=APC_BJ) -> L.SolverOpts:
     return L.SolverOpts(rtol, atol, maxit, rtol_A, atol_A, maxit_A, rtol_S, atol_S, maxit_S,
                         rtol_I, atol_I, maxit_I, precond, precision, orth, shat_degree, shat_ratio, a_krylov,
-                        cg_symmetrise, shat_method, schur_solve, relax_inner, schur_mass)
+                        cg_symmetrise, shat_method, schur_solve, relax_inner, schur_mass, a_prec, 0)
+
+
+def amg_opts(max_levels=4, min_coarse=64, degree=2, coarse_degree=8) -> L.AmgOpts:
+    return L.AmgOpts(max_levels, min_coarse, degree, coarse_degree)
 
 
 def newton_opts(tol_R=1e-8, tol_A=1e-50, l_max=20, rk_corr=1, eps_diag=1e-15, dir_lift=0) -> L.NewtonOpts:
@@ -127,7 +132,7 @@ class Problem:
                             _p(d["traction"]), _p(d["dir_mask"]), _p(d["dir_vel"]), _p(d["fibre"]),
                             _p(d["col"]), _p(d["tpos"]), _p(d["diag_pos"]), _p(d["blk_src_ptr"]),
                             _p(d["blk_src"]), self.shat_width, _p(d["shat_col"]), _p(d["shat_off"]),
-                            _p(d["nf_ptr"]), _p(d["nf_face"]))
+                            _p(d["nf_ptr"]), _p(d["nf_face"]), None)
         self.set_material(mat)
         self.stream = torch.cuda.current_stream(dev)
         ctx = C.c_void_p()
@@ -139,6 +144,66 @@ class Problem:
         self.f_ext = torch.zeros(3 * n, dtype=torch.float64, device=dev)
         self._check(lib.vms_nodal_load(self.ctx, C.byref(self.cmesh), _p(self.f_ext)), "vms_nodal_load")
         self._ws = None
+        self.amg = None
+
+    def setup_amg(self, opts=None):
+        """Build the multigrid hierarchy of the mesh (vms_amg_create, host), upload its fixed arrays
+        into a device buffer (vms_amg_upload) and attach it to the mesh (a_prec = APC_AMG)."""
+        lib, n = self.lib, self.mesh.n_nodes
+        opts = opts or amg_opts()
+        X = np.ascontiguousarray(self.mesh.X, dtype=np.float64)
+        dm = np.ascontiguousarray(self.mesh.dir_mask, dtype=np.uint8)
+        obj = C.c_void_p()
+        self._check(lib.vms_amg_create(n, self.slot_width, self.host["row_len"].ctypes.data,
+                                       self.host["col"].ctypes.data, X.ctypes.data, dm.ctypes.data,
+                                       C.byref(opts), C.byref(obj)), "vms_amg_create", ctx=False)
+        self.free_amg()
+        self.amg = obj
+        nb = lib.vms_amg_device_bytes(obj)
+        self._amg_buf = torch.empty(int(nb), dtype=torch.uint8, device=self.dev)
+        self._check(lib.vms_amg_upload(self.ctx, obj, _p(self._amg_buf), int(nb)), "vms_amg_upload")
+        self.cmesh.amg = obj.value
+        return self.amg_info()
+
+    def amg_info(self):
+        info = L.AmgInfo()
+        self._check(self.lib.vms_amg_get_info(self.amg, C.byref(info)), "vms_amg_get_info", ctx=False)
+        k = info.n_levels
+        return {"n_levels": k, "n": list(info.n[:k]), "bs": list(info.bs[:k]), "nnzb": list(info.nnzb[:k]),
+                "device_bytes": int(info.device_bytes)}
+
+    def amg_level(self, level):
+        """Host views of one level (copies): agg, P [n][bs][10], and for level >= 1 ptr, col, dropped."""
+        info = self.amg_info()
+        n, bs = info["n"][level], info["bs"][level]
+        ptrs = [C.c_void_p() for _ in range(5)]
+        self._check(self.lib.vms_amg_level_arrays(self.amg, level, *(C.byref(p) for p in ptrs)), "vms_amg_level_arrays",
+                    ctx=False)
+        out = {}
+        if ptrs[0].value:
+            out["agg"] = np.ctypeslib.as_array(C.cast(ptrs[0], C.POINTER(C.c_int32)), (n,)).copy()
+            out["P"] = np.ctypeslib.as_array(C.cast(ptrs[1], C.POINTER(C.c_double)), (n * bs * 10,)).reshape(n, bs, 10).copy()
+        if level > 0:
+            nnzb = info["nnzb"][level]
+            out["ptr"] = np.ctypeslib.as_array(C.cast(ptrs[2], C.POINTER(C.c_int32)), (n + 1,)).copy()
+            out["col"] = np.ctypeslib.as_array(C.cast(ptrs[3], C.POINTER(C.c_int32)), (nnzb,)).copy()
+            out["dropped"] = np.ctypeslib.as_array(C.cast(ptrs[4], C.POINTER(C.c_uint8)), (n * 10,)).copy()
+        return out
+
+    def amg_apply(self, K, r, sym=0):
+        """z = one V-cycle for the scaled A of K (vms_amg_apply); r: [n][3] FP64 device tensor."""
+        nb = self.lib.vms_amg_apply_workspace(C.byref(self.cmesh), sym)
+        ws = self.workspace(nb + 512)
+        z = torch.empty_like(r)
+        self._check(self.lib.vms_amg_apply(self.ctx, C.byref(self.cmesh), C.byref(K.c()), sym, _p(r), _p(z), _p(ws),
+                                           ws.numel()), "vms_amg_apply")
+        return z
+
+    def free_amg(self):
+        if self.amg is not None:
+            self.cmesh.amg = None
+            self.lib.vms_amg_destroy(self.amg)
+            self.amg = None
 
     # ---- helpers -----------------------------------------------------------
     def set_material(self, mat):
@@ -154,6 +219,8 @@ class Problem:
 
     def __del__(self):
         try:
+            if getattr(self, "amg", None) is not None:
+                self.free_amg()
             if getattr(self, "ctx", None):
                 self.lib.vms_ctx_destroy(self.ctx)
                 self.ctx = None
