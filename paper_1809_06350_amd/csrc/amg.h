@@ -146,17 +146,23 @@ k_amgf_step(int n, int64_t nnzb, int W, const int32_t *__restrict__ col, const T
   x[o] = (T)(ld(x, o) + (pending ? dko : 0.0) + dnv);
 }
 
-// res = b - A x
-template <typename T>
+// restriction, first half: the residual res = b - A x of the row and its ten mode contributions
+// t[i][a] = sum_r Q[i][r][a] res_r / W[i][r] (lane a of the row's 16)
+template <typename T, typename TP>
 __global__ void __launch_bounds__(VMS_BLOCK)
-k_amgf_resid(int n, int64_t nnzb, int W, const int32_t *__restrict__ col, const T *__restrict__ A,
-             const T *__restrict__ b, const T *__restrict__ x, T *res, const int *done) {
+k_amgf_resid_t(int n, int64_t nnzb, int W, const int32_t *__restrict__ col, const T *__restrict__ A,
+               const T *__restrict__ b, const T *__restrict__ x, const TP *__restrict__ Q,
+               const double *__restrict__ Wsc, T *t, const int *done) {
   SPMV_PROLOGUE
   double a0, a1, a2;
   amgf_row(nnzb, b0, b1, lane, col, A, x, a0, a1, a2);
-  if (!act || lane >= 3) return;
-  const int64_t o = 3 * (int64_t)row + lane;
-  res[o] = (T)(ld(b, o) - (lane == 0 ? a0 : (lane == 1 ? a1 : a2)));
+  if (!act || lane >= AMG_NM) return;
+  const int64_t o = 3 * (int64_t)row;
+  const double r0 = (ld(b, o) - a0) / Wsc[4 * (int64_t)row];
+  const double r1 = (ld(b, o + 1) - a1) / Wsc[4 * (int64_t)row + 1];
+  const double r2 = (ld(b, o + 2) - a2) / Wsc[4 * (int64_t)row + 2];
+  const TP *q = Q + (int64_t)row * 3 * AMG_NM + lane;
+  t[(int64_t)row * AMG_NM + lane] = (T)(ld(q, 0) * r0 + ld(q, AMG_NM) * r1 + ld(q, 2 * AMG_NM) * r2);
 }
 
 // y = M A x (power iteration)
@@ -252,15 +258,24 @@ k_amgc_cheb(int n, const int32_t *__restrict__ ptr, const int32_t *__restrict__ 
   }
 }
 
-template <typename T>
+// coarse level: residual of the row and its mode contributions t[i][a] = sum_r Q[i][r][a] res_r
+template <typename T, typename TP>
 __global__ void __launch_bounds__(256)
-k_amgc_resid(int n, const int32_t *__restrict__ ptr, const int32_t *__restrict__ col, const T *__restrict__ A,
-             const T *__restrict__ b, const T *__restrict__ x, T *res, const int *done) {
+k_amgc_resid_t(int n, const int32_t *__restrict__ ptr, const int32_t *__restrict__ col, const T *__restrict__ A,
+               const T *__restrict__ b, const T *__restrict__ x, const TP *__restrict__ Q, T *t, const int *done) {
+  __shared__ double sm[AMG_CROWS][AMG_NM];
   if (amg_done(done)) return;
-  const int t = threadIdx.x, row = blockIdx.x * AMG_CROWS + t / AMG_NM, rr = t % AMG_NM;
-  if (t >= AMG_CROWS * AMG_NM || row >= n) return;
-  const int64_t o = (int64_t)row * AMG_NM + rr;
-  res[o] = (T)(ld(b, o) - amgc_row(ptr, col, A, x, row, rr));
+  const int th = threadIdx.x, lr = th / AMG_NM, row = blockIdx.x * AMG_CROWS + lr, rr = th % AMG_NM;
+  const bool act = th < AMG_CROWS * AMG_NM && row < n;
+  const int64_t o = (int64_t)(act ? row : 0) * AMG_NM + rr;
+  if (th < AMG_CROWS * AMG_NM) sm[lr][rr] = act ? ld(b, o) - amgc_row(ptr, col, A, x, row, rr) : 0.0;
+  __syncthreads();
+  if (!act) return;
+  const TP *q = Q + (int64_t)row * AMG_NM * AMG_NM + rr;   // column rr of the row's 10x10 block
+  double acc = 0.0;
+#pragma unroll
+  for (int r = 0; r < AMG_NM; ++r) acc += ld(q, r * AMG_NM) * sm[lr][r];
+  t[o] = (T)acc;
 }
 
 template <typename T>
@@ -284,26 +299,19 @@ __global__ void k_amg_axpy(int64_t nv, const T *__restrict__ d, T *x, const int 
 }
 
 // ---- transfers -----------------------------------------------------------------------------
-// restriction bc[I][a] = sum over the members i of I (ascending) and their dofs r of
-// P[i][r][a] s[i][r] res[i][r], s = 1 / W on the finest level (Wsc != NULL), else 1
-template <typename T, typename TP, int BS>
-__global__ void k_amg_restrict(int nc, const int32_t *__restrict__ mptr, const int32_t *__restrict__ mem,
-                               const TP *__restrict__ P, const double *__restrict__ Wsc, const T *__restrict__ res,
-                               T *bc, const int *done) {
+// restriction, second half: bc[I][a] = sum of t[i][a] over the members i of I (ascending)
+template <typename T>
+__global__ void k_amg_aggsum(int nc, const int32_t *__restrict__ mptr, const int32_t *__restrict__ mem,
+                             const T *__restrict__ t, T *bc, const int *done) {
   if (amg_done(done)) return;
-  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (t >= (int64_t)nc * AMG_NM) return;
-  const int I = (int)(t / AMG_NM), a = (int)(t % AMG_NM);
+  const int64_t th = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (th >= (int64_t)nc * AMG_NM) return;
+  const int I = (int)(th / AMG_NM), a = (int)(th % AMG_NM);
+  const int k0 = mptr[I], k1 = mptr[I + 1];
   double acc = 0.0;
-  for (int k = mptr[I]; k < mptr[I + 1]; ++k) {
-    const int i = mem[k];
-#pragma unroll
-    for (int r = 0; r < BS; ++r) {
-      const double s = Wsc ? 1.0 / Wsc[4 * (int64_t)i + r] : 1.0;
-      acc += ld(P, ((int64_t)i * BS + r) * AMG_NM + a) * s * ld(res, (int64_t)i * BS + r);
-    }
-  }
-  bc[t] = (T)acc;
+#pragma unroll 4
+  for (int k = k0; k < k1; ++k) acc += ld(t, (int64_t)mem[k] * AMG_NM + a);
+  bc[th] = (T)acc;
 }
 
 // prolongation x[i][r] += s[i][r] sum_a P[i][r][a] xc[agg(i)][a]

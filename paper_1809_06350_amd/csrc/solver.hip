@@ -1768,6 +1768,7 @@ struct AmgSys {
   T *Dinv[VMS_AMG_MAX_LEVELS] = {};
   T *xv[VMS_AMG_MAX_LEVELS] = {}, *bv[VMS_AMG_MAX_LEVELS] = {}, *rv[VMS_AMG_MAX_LEVELS] = {};
   T *d0[VMS_AMG_MAX_LEVELS] = {}, *d1[VMS_AMG_MAX_LEVELS] = {};
+  T *tv[VMS_AMG_MAX_LEVELS] = {};   // mode contributions of the residual (restriction), [n_l][10]
   double *lam = nullptr, *ltmp = nullptr, *part = nullptr;
   int *bad = nullptr;
   // finest level: the A-level operator and its 3x3 block-Jacobi inverses
@@ -1791,6 +1792,7 @@ struct AmgSys {
       rv[l] = cv.take<T>(nv);
       d0[l] = cv.take<T>(nv);
       d1[l] = cv.take<T>(nv);
+      if (l + 1 < L) tv[l] = cv.take<T>((int64_t)lv.n * AMG_NM);
     }
     lam = cv.take<double>(VMS_AMG_MAX_LEVELS);
     ltmp = cv.take<double>(8);
@@ -1901,25 +1903,20 @@ struct AmgSys {
     }
     const vms_amg_level_dev &c = h->lev[l + 1];
     smooth(s, l, b, x, true, h->degree, done);
-    T *res = rv[l];
     const dim3 bl(VMS_BLOCK);
-    if (l == 0)
-      hipLaunchKernelGGL(k_amgf_resid<T>, dim3(spmv_grid(lv.n)), bl, 0, s, lv.n, mesh->nnzb, mesh->slot_width,
-                         mesh->col, A0, b, (const T *)x, res, done);
-    else
-      hipLaunchKernelGGL(k_amgc_resid<T>, dim3(amg_cgrid(lv.n)), dim3(256), 0, s, lv.n, lv.ptr, lv.col,
-                         (const T *)Ac[l], b, (const T *)x, res, done);
-    const dim3 gr((unsigned)(((int64_t)c.n * AMG_NM + VMS_BLOCK - 1) / VMS_BLOCK));
-    const dim3 gp((unsigned)(((int64_t)lv.n * lv.bs + VMS_BLOCK - 1) / VMS_BLOCK));
     constexpr bool F32 = std::is_same<T, float>::value;
     using TP = typename std::conditional<F32, float, double>::type;
     const TP *P = F32 ? (const TP *)lv.P32 : (const TP *)lv.P;
+    // restriction: residual with its mode contributions per node, then the sums over aggregates
     if (l == 0)
-      hipLaunchKernelGGL((k_amg_restrict<T, TP, 3>), gr, bl, 0, s, c.n, lv.mptr, lv.mem, P, Wsc, (const T *)res,
-                         bv[1], done);
+      hipLaunchKernelGGL((k_amgf_resid_t<T, TP>), dim3(spmv_grid(lv.n)), bl, 0, s, lv.n, mesh->nnzb,
+                         mesh->slot_width, mesh->col, A0, b, (const T *)x, P, Wsc, tv[0], done);
     else
-      hipLaunchKernelGGL((k_amg_restrict<T, TP, AMG_NM>), gr, bl, 0, s, c.n, lv.mptr, lv.mem, P,
-                         (const double *)nullptr, (const T *)res, bv[l + 1], done);
+      hipLaunchKernelGGL((k_amgc_resid_t<T, TP>), dim3(amg_cgrid(lv.n)), dim3(256), 0, s, lv.n, lv.ptr, lv.col,
+                         (const T *)Ac[l], b, (const T *)x, P, tv[l], done);
+    const dim3 gr((unsigned)(((int64_t)c.n * AMG_NM + VMS_BLOCK - 1) / VMS_BLOCK));
+    const dim3 gp((unsigned)(((int64_t)lv.n * lv.bs + VMS_BLOCK - 1) / VMS_BLOCK));
+    hipLaunchKernelGGL(k_amg_aggsum<T>, gr, bl, 0, s, c.n, lv.mptr, lv.mem, (const T *)tv[l], bv[l + 1], done);
     vcycle(s, l + 1, bv[l + 1], xv[l + 1], done);
     if (l == 0)
       hipLaunchKernelGGL((k_amg_prolong<T, TP, 3>), gp, bl, 0, s, lv.n, lv.agg, P, Wsc, (const T *)xv[1], x, done);
