@@ -56,6 +56,16 @@ def cg_spmv_bytes(n, nnzb, elem):
     return (9 * elem + 4) * nnzb + 5 * 3 * elem * n
 
 
+def tangent_bytes(n, m, W=16, hgo=False, corr=True):
+    """Algorithmic bytes of one row-owner tangent assembly (with the R-bar_k term): each node's
+    staged state read once (X, and u, v, v-dot, u-dot at both time levels: 27 doubles; p, p-dot at
+    both: 4), its diagonal incidence list and row columns, the tets (and fibres), and the K blocks
+    of its W slots (16 doubles each) plus the corr row written once."""
+    reads = (31 * 8 + 3 * 4 + W * 4) * n + (16 + 16 + (48 if hgo else 0)) * m
+    writes = (16 * 8 * W + (32 if corr else 0)) * n
+    return reads, writes
+
+
 def shat_bytes(n, nnz, elem, idx=4):
     """Algorithmic bytes of one S^ product (the product of the Schur
     preconditioner's CG steps): the real off-diagonal entries (value + column
@@ -251,6 +261,54 @@ def gpu_vs_oracle(cb, nopts, forms):
     return out
 
 
+def time_tangent(prob, ti, reps=20):
+    """Wall time per tangent assembly with the R-bar_k term (the step's tangent call) at the predicted
+    first state, each call including its host synchronisation (the inverted-element check)."""
+    import torch
+    from paper_1809_06350_amd import vms as V
+    st = prob.new_state()
+    tiv = V.time_int(ti.dt, ti.rho_inf, 0.0, ti.n_steps * ti.dt)
+    prob.predictor(st, tiv)
+    fl = V.ASM_TANGENT | V.ASM_RKCORR
+    K, _, corr = prob.assemble(st, tiv, fl)
+    for _ in range(3):
+        prob.assemble(st, tiv, fl, K=K, corr=corr)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        prob.assemble(st, tiv, fl, K=K, corr=corr)
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / reps
+
+
+def assemble_only(prob, mesh, ti, reps, hgo):
+    """Kernel-level run for hardware counters and the kernel trace: reps tangent assemblies with
+    the R-bar_k term (the step's tangent call) at the predicted first state, then the calibration
+    copy of spmv_only."""
+    import torch
+    from paper_1809_06350_amd import vms as V
+    st = prob.new_state()
+    tiv = V.time_int(ti.dt, ti.rho_inf, 0.0, ti.n_steps * ti.dt)
+    prob.predictor(st, tiv)
+    fl = V.ASM_TANGENT | V.ASM_RKCORR
+    K, _, corr = prob.assemble(st, tiv, fl)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        prob.assemble(st, tiv, fl, K=K, corr=corr)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / reps
+    src = torch.ones(1 << 27, dtype=torch.float64, device="cuda:0")
+    dst = torch.empty_like(src)
+    for _ in range(reps):
+        torch.mul(src, 1.0, out=dst)
+    torch.cuda.synchronize()
+    rd, wr = tangent_bytes(mesh.n_nodes, mesh.n_tets, prob.slot_width, hgo)
+    print(json.dumps({"assemble_only": True, "n": mesh.n_nodes, "m": mesh.n_tets, "flags": fl,
+                      "bytes_read": rd, "bytes_written": wr, "wall_us_per_call": wall * 1e6,
+                      "calibration_bytes_each_way": src.numel() * 8}), flush=True)
+
+
 def spmv_only(prob, mesh, ti, reps):
     """Kernel-level run for hardware counters: the A-block SpMV (FP64 and FP32)
     on the assembled, scaled first Newton system, and a calibration kernel of
@@ -372,7 +430,8 @@ def main():
     ap.add_argument("--schur-mass", type=float, default=None,
                     help="weight of the lumped pressure-mass term in the Schur preconditioner (schur_mass; 0: off); "
                          "default 1 on the tube (with --shat-method none there: a stiffness-dominated A at dt = "
-                         "0.05 makes S close to a scaled pressure mass matrix), 0 elsewhere")
+                         "0.05 makes S close to a scaled pressure mass matrix) and on the strip (beside the CG "
+                         "steps on S^: 28 %% less time per step at 1/dx = 400), 0 on the cube")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-timing", action="store_true",
                     help="also event-time every A-block product launch inside the timed steps (each launch then "
@@ -380,6 +439,9 @@ def main():
     ap.add_argument("--spmv-only", type=int, default=0,
                     help="only launch the A-block SpMV (FP64 and FP32) this many times each on the first "
                          "Newton system, plus a 256 MiB device copy as the counter calibration kernel")
+    ap.add_argument("--assemble-only", type=int, default=0,
+                    help="only run the tangent assembly (with the R-bar_k term) this many times at the first "
+                         "predicted state, plus the copy calibration kernel (for the kernel trace and counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
@@ -394,7 +456,7 @@ def main():
     N = args.size or {"cube": 64, "strip": 400, "tube": 256}[args.workload]
     tube = args.workload == "tube"
     if args.schur_mass is None:
-        args.schur_mass = 1.0 if tube else 0.0
+        args.schur_mass = 0.0 if cube else 1.0
     if args.shat_method is None:
         args.shat_method = "none" if tube and args.schur_mass > 0.0 else "cg"
     if args.a_prec == "auto":
@@ -439,6 +501,9 @@ def main():
     ft = [float(x) for x in args.fp64_tol.split(",")]
     if args.spmv_only:
         spmv_only(prob, mesh, ti, args.spmv_only)
+        return
+    if args.assemble_only:
+        assemble_only(prob, mesh, ti, args.assemble_only, mesh.fibre is not None)
         return
     orth = {"cgs2": V.ORTH_CGS2, "cgs1": V.ORTH_CGS1, "cgs_ifneeded": V.ORTH_CGS_IFNEEDED,
             "mgs": V.ORTH_MGS}[args.orth]
@@ -552,6 +617,11 @@ def main():
         extra["spmv_A_in_steps"] = {"us_per_launch": t_in * 1e6, "GB/s": by_in / t_in / 1e9,
                                     "launches": r["spmv_A_launches"],
                                     "note": "start/stop events of every working launch in the timed steps"}
+    ttan = time_tangent(prob, ti)
+    rd, wr = tangent_bytes(n, mesh.n_tets, prob.slot_width, mesh.fibre is not None)
+    extra["tangent_assembly"] = {"us_per_call": ttan * 1e6, "bytes_read": rd, "bytes_written": wr,
+                                 "GB/s": (rd + wr) / ttan / 1e9, "frac_hbm": (rd + wr) / ttan / 1e9 / HBM_PEAK_GBS,
+                                 "timing": "wall time per call over 20 calls, each with its host synchronisation"}
     first = r["per_step"][0]
     extra["first_step"] = {"ms": first["ms_total"], "n_newton": first["n_newton"],
                            "ms_per_newton": first["ms_total"] / max(first["n_newton"], 1)}

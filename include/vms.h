@@ -339,16 +339,20 @@ int vms_nodal_load(vms_ctx *ctx, const vms_mesh *mesh, double *f_ext);
  * [async] */
 int vms_predictor(vms_ctx *ctx, const vms_mesh *mesh, const vms_timeint *ti, vms_state *st, int dir_lift);
 
-/* Workspace bytes of vms_assemble for these flags: the element matrices and
- * vectors (2 KB per element for the tangent, 128 B each for the residual and
- * the R-bar_k term). */
+/* Workspace bytes of vms_assemble for these flags.  With the tangent on a
+ * mesh of 16 slots per block row, the rows are assembled by their owners
+ * straight into K, R and corr and the workspace is 1 KB; otherwise it holds
+ * the element matrices and vectors (2 KB per element for the tangent, 128 B
+ * each for the residual and the R-bar_k term). */
 size_t vms_assemble_workspace(const vms_mesh *mesh, unsigned flags);
 
 /* Element-by-element assembly at the generalized-alpha stages
  * y-dot_{n+alpha_m}, y_{n+alpha_f} computed from (y_n, y-dot_n) and the
- * iterate (section 3.3 step 1).  Every element writes its matrices to the
- * workspace; each block (and each nodal entry) then sums its contributions
- * in element order, so the result is bitwise reproducible.
+ * iterate (section 3.3 step 1).  Each block (and each nodal entry) sums its
+ * element contributions in increasing element order, so the result is
+ * bitwise reproducible: the tangent on 16-slot rows by the row's owner, which
+ * evaluates every incident element's terms itself; otherwise every element
+ * writes its matrices to the workspace and the blocks gather them.
  *   VMS_ASM_RESIDUAL: R[n][4] = (R_m, R_p) of the appendix (P1, 4-point
  *     rule, tau_M frozen per element) plus load_scale * f_ext;
  *   VMS_ASM_TANGENT: K->A, B, C, D of the block reduction (eqs. defining A,

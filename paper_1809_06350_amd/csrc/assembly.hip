@@ -69,11 +69,24 @@ __device__ __forceinline__ double dot3(const double *a, const double *b) {
 
 // Sum over the four lanes of an element (every lane receives the same bits:
 // the pairwise sums are commutative and combined in the same order).
+// The quad exchanges are DPP moves (quad_perm: lane j of each quad reads lane p_j of the same
+// quad), which the VALU executes in a few cycles, instead of LDS-routed permutes.
+template <int QPERM>
+__device__ __forceinline__ double quad_move(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffffll), QPERM, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), QPERM, 0xf, 0xf, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
 __device__ __forceinline__ double qsum4(double v) {
-  v += __shfl_xor(v, 1, 64);
-  v += __shfl_xor(v, 2, 64);
+  v += quad_move<0xB1>(v);   // lanes 1, 0, 3, 2
+  v += quad_move<0x4E>(v);   // lanes 2, 3, 0, 1
   return v;
 }
+// lane B of the quad, to every lane of the quad
+template <int B>
+__device__ __forceinline__ double qbc(double v) { return quad_move<B * 0x55>(v); }
+// any lane of the wavefront (a lane number known only at run time)
 __device__ __forceinline__ double qget(double v, int src_lane) { return __shfl(v, src_lane, 64); }
 
 // sum_q c_q N_qA N_qB for the symmetric rule (N_qA = QB + QD delta_qA), S = sum_q c_q
@@ -83,50 +96,64 @@ __device__ __forceinline__ double qsum2(double ca, double cb, double S, bool sam
   return r;
 }
 
-// Four lanes per element: lane a owns local node a (and quadrature point a of
-// the symmetric rule, whose point q has N_q = QB + QD delta_qA).  Element sums
-// (F, grad v, grad p, quadrature sums) are quad reductions; in the pair loop
-// lane a computes row a of the element matrix, fetching node b's data from
-// lane b by shuffle, so no lane holds the whole element.
-template <int FL, bool HGO>
-__global__ void __launch_bounds__(256)
-k_assemble(int ne, const double *__restrict__ X, const int32_t *__restrict__ tets,
-           const double *__restrict__ fibre, MatP mp, vms_ga ga, StateP sp, double *__restrict__ KE,
-           double *__restrict__ RE, double *__restrict__ CE, const double *__restrict__ lam,
-           double *__restrict__ VE, const double *__restrict__ dfibre, int pmask, double *sens, int *inverted) {
-  constexpr bool RES = FL & VMS_ASM_RESIDUAL;
-  constexpr bool TAN = FL & VMS_ASM_TANGENT;
-  constexpr bool COR = FL & VMS_ASM_RKCORR;
-  constexpr bool VJP = FL & VMS_ASM_VJP;
-  constexpr bool SENS = FL & VMS_ASM_SENS;
-  const int gt = blockIdx.x * blockDim.x + threadIdx.x;
-  const int k = gt >> 2;
-  const int a = gt & 3;
-  const int base = (threadIdx.x & 63) & ~3;
-  const bool act = k < ne;
-  const int e = act ? k : ne - 1;
-  const int nda = tets[4 * (int64_t)e + a];
+// Per-lane (local node a = quadrature point a of the symmetric rule) and
+// element quantities of one element at the generalized-alpha stages: what the
+// residual, tangent, R-bar_k and adjoint terms are built from.
+struct ElemQ {
+  double Ga[3], ga_[3], FGa[3], F[3][3], FiT[3][3], L[3][3], gradp[3];
+  double fa[2][3], Fa[2][3], HC[2], W1[2], W2[2];
+  double J, Jm23, V, w, tau, trC, pbar, PaA, Xbar[3], sA[3], rka[3];
+  double rho, beta, rhop, betap, pq, dpq, dvq[3];
+  bool ok;
+};
 
-  // staged values of node a: rates at n+alpha_m, values at n+alpha_f
-  double Xa[3], ua[3], va[3], dva[3], rka[3];
-  const int64_t o3 = 3 * (int64_t)nda;
+// Staged values of one node: X, u, v at n+alpha_f, v-dot at n+alpha_m, R-bar_k = u-dot - v at the
+// stages (COR), p at n+alpha_f, p-dot at n+alpha_m -- NODE_STAGE doubles, in this order.
+#define NODE_STAGE 17
+template <bool COR>
+__device__ __forceinline__ void stage_node(int nd, const double *__restrict__ X, const vms_ga &ga, const StateP &sp,
+                                           double *out) {
+  const int64_t o3 = 3 * (int64_t)nd;
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
-    Xa[i] = X[o3 + i];
-    ua[i] = sp.u_n[o3 + i] + ga.af * (sp.u[o3 + i] - sp.u_n[o3 + i]);
-    va[i] = sp.v_n[o3 + i] + ga.af * (sp.v[o3 + i] - sp.v_n[o3 + i]);
-    dva[i] = sp.dv_n[o3 + i] + ga.am * (sp.dv[o3 + i] - sp.dv_n[o3 + i]);
-    rka[i] = COR ? sp.du_n[o3 + i] + ga.am * (sp.du[o3 + i] - sp.du_n[o3 + i]) - va[i] : 0.0;
+    const double v = sp.v_n[o3 + i] + ga.af * (sp.v[o3 + i] - sp.v_n[o3 + i]);
+    out[i] = X[o3 + i];
+    out[3 + i] = sp.u_n[o3 + i] + ga.af * (sp.u[o3 + i] - sp.u_n[o3 + i]);
+    out[6 + i] = v;
+    out[9 + i] = sp.dv_n[o3 + i] + ga.am * (sp.dv[o3 + i] - sp.dv_n[o3 + i]);
+    out[12 + i] = COR ? sp.du_n[o3 + i] + ga.am * (sp.du[o3 + i] - sp.du_n[o3 + i]) - v : 0.0;
   }
-  const double pa = sp.p_n[nda] + ga.af * (sp.p[nda] - sp.p_n[nda]);
-  const double dpa = sp.dp_n[nda] + ga.am * (sp.dp[nda] - sp.dp_n[nda]);
+  out[15] = sp.p_n[nd] + ga.af * (sp.p[nd] - sp.p_n[nd]);
+  out[16] = sp.dp_n[nd] + ga.am * (sp.dp[nd] - sp.dp_n[nd]);
+}
+
+// Element prologue of lane a (four lanes per element, lanes base..base+3) from the staged values
+// of its node (stage_node): reference geometry, F, J, the stress scalars and the quadrature-point
+// values; element sums are quad reductions over the four lanes.
+template <bool HGO>
+__device__ __forceinline__ void elem_prologue_staged(int e, int a, int base, bool act, const double *nodev,
+                                                     const double *__restrict__ fibre, const MatP &mp,
+                                                     const vms_ga &ga, int *inverted, ElemQ &q) {
+  double Xa[3], ua[3], va[3], dva[3], rka[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    Xa[i] = nodev[i];
+    ua[i] = nodev[3 + i];
+    va[i] = nodev[6 + i];
+    dva[i] = nodev[9 + i];
+    rka[i] = nodev[12 + i];
+  }
+  const double pa = nodev[15], dpa = nodev[16];
 
   // reference geometry: G_A are the rows of the inverse edge matrix
   double Xn[4][3];
 #pragma unroll
-  for (int b = 0; b < 4; ++b)
-#pragma unroll
-    for (int i = 0; i < 3; ++i) Xn[b][i] = qget(Xa[i], base + b);
+  for (int i = 0; i < 3; ++i) {
+    Xn[0][i] = qbc<0>(Xa[i]);
+    Xn[1][i] = qbc<1>(Xa[i]);
+    Xn[2][i] = qbc<2>(Xa[i]);
+    Xn[3][i] = qbc<3>(Xa[i]);
+  }
   double e1[3], e2[3], e3[3];
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
@@ -147,9 +174,10 @@ k_assemble(int ne, const double *__restrict__ X, const int32_t *__restrict__ tet
   const double det6 = dot3(e1, G1);
   const double V = det6 / 6.0;
   double Ga[3];
+  const double rdet6 = 1.0 / det6;
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
-    const double g1 = G1[i] / det6, g2 = G2[i] / det6, g3 = G3[i] / det6;
+    const double g1 = G1[i] * rdet6, g2 = G2[i] * rdet6, g3 = G3[i] * rdet6;
     Ga[i] = (a == 0) ? -(g1 + g2 + g3) : (a == 1) ? g1 : (a == 2) ? g2 : g3;
   }
   double h2 = 0.0;
@@ -182,10 +210,11 @@ k_assemble(int ne, const double *__restrict__ X, const int32_t *__restrict__ tet
   const bool ok = act && (J > 0.0);
   if (act && !(J > 0.0) && a == 0) atomicOr(inverted, 1);
   double FiT[3][3];
+  const double rJ = 1.0 / J;
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
-    for (int I = 0; I < 3; ++I) FiT[i][I] = cof[i][I] / J;
+    for (int I = 0; I < 3; ++I) FiT[i][I] = cof[i][I] * rJ;
 
   // spatial gradient g_a = F^-T G_a, F G_a, grad v, grad p
   double ga_[3], FGa[3];
@@ -251,6 +280,71 @@ k_assemble(int ne, const double *__restrict__ X, const int32_t *__restrict__ tet
   double Xbar[3];
 #pragma unroll
   for (int i = 0; i < 3; ++i) Xbar[i] = w * Srv[i] + V * gradp[i];
+
+  // hand the quantities the element's terms use to the caller
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    q.Ga[i] = Ga[i]; q.ga_[i] = ga_[i]; q.FGa[i] = FGa[i]; q.gradp[i] = gradp[i];
+    q.Xbar[i] = Xbar[i]; q.sA[i] = sA[i]; q.rka[i] = rka[i]; q.dvq[i] = dvq[i];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) { q.F[i][j] = F[i][j]; q.FiT[i][j] = FiT[i][j]; q.L[i][j] = L[i][j]; }
+  }
+#pragma unroll
+  for (int f = 0; f < 2; ++f) {
+    q.HC[f] = HC[f]; q.W1[f] = W1[f]; q.W2[f] = W2[f];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) { q.fa[f][i] = fa[f][i]; q.Fa[f][i] = Fa[f][i]; }
+  }
+  q.J = J; q.Jm23 = Jm23; q.V = V; q.w = w; q.tau = tau; q.trC = trC; q.pbar = pbar; q.PaA = PaA;
+  q.rho = rho; q.beta = beta; q.rhop = rhop; q.betap = betap; q.pq = pq; q.dpq = dpq; q.ok = ok;
+}
+
+// The prologue of lane a from global memory: stage node nda, then the staged prologue.
+template <bool HGO, bool COR>
+__device__ __forceinline__ void elem_prologue(int e, int a, int nda, int base, bool act,
+                                              const double *__restrict__ X, const double *__restrict__ fibre,
+                                              const MatP &mp, const vms_ga &ga, const StateP &sp, int *inverted,
+                                              ElemQ &q) {
+  double nodev[NODE_STAGE];
+  stage_node<COR>(nda, X, ga, sp, nodev);
+  elem_prologue_staged<HGO>(e, a, base, act, nodev, fibre, mp, ga, inverted, q);
+}
+
+
+// Four lanes per element: lane a owns local node a (and quadrature point a of
+// the symmetric rule, whose point q has N_q = QB + QD delta_qA).  Element sums
+// (F, grad v, grad p, quadrature sums) are quad reductions; in the pair loop
+// lane a computes row a of the element matrix, fetching node b's data from
+// lane b by shuffle, so no lane holds the whole element.
+template <int FL, bool HGO>
+__global__ void __launch_bounds__(256)
+k_assemble(int ne, const double *__restrict__ X, const int32_t *__restrict__ tets,
+           const double *__restrict__ fibre, MatP mp, vms_ga ga, StateP sp, double *__restrict__ KE,
+           double *__restrict__ RE, double *__restrict__ CE, const double *__restrict__ lam,
+           double *__restrict__ VE, const double *__restrict__ dfibre, int pmask, double *sens, int *inverted) {
+  constexpr bool RES = FL & VMS_ASM_RESIDUAL;
+  constexpr bool TAN = FL & VMS_ASM_TANGENT;
+  constexpr bool COR = FL & VMS_ASM_RKCORR;
+  constexpr bool VJP = FL & VMS_ASM_VJP;
+  constexpr bool SENS = FL & VMS_ASM_SENS;
+  const int gt = blockIdx.x * blockDim.x + threadIdx.x;
+  const int k = gt >> 2;
+  const int a = gt & 3;
+  const int base = (threadIdx.x & 63) & ~3;
+  const bool act = k < ne;
+  const int e = act ? k : ne - 1;
+  const int nda = tets[4 * (int64_t)e + a];
+  ElemQ q;
+  elem_prologue<HGO, COR>(e, a, nda, base, act, X, fibre, mp, ga, sp, inverted, q);
+  const double(&Ga)[3] = q.Ga, (&ga_)[3] = q.ga_, (&FGa)[3] = q.FGa, (&gradp)[3] = q.gradp;
+  const double(&F)[3][3] = q.F, (&FiT)[3][3] = q.FiT, (&L)[3][3] = q.L;
+  const double(&fa)[2][3] = q.fa, (&Fa)[2][3] = q.Fa;
+  const double(&HC)[2] = q.HC, (&W1)[2] = q.W1, (&W2)[2] = q.W2;
+  const double(&Xbar)[3] = q.Xbar, (&sA)[3] = q.sA, (&rka)[3] = q.rka, (&dvq)[3] = q.dvq;
+  const double &J = q.J, &Jm23 = q.Jm23, &V = q.V, &w = q.w, &tau = q.tau, &trC = q.trC, &pbar = q.pbar;
+  const double &PaA = q.PaA, &rho = q.rho, &beta = q.beta, &rhop = q.rhop, &betap = q.betap;
+  const double &pq = q.pq, &dpq = q.dpq;
+  const bool ok = q.ok;
 
   if (RES) {
     double Pg[3];
@@ -514,6 +608,245 @@ k_gather_blocks(int64_t nnzb, const int32_t *__restrict__ ptr, const int32_t *__
     KD[b] = s;
 }
 
+// Row-owner assembly of the tangent (with the residual and the R-bar_k term when asked): sixteen
+// lanes per node i, as four element slots of four lanes.  The node's incident elements -- the
+// contributions of its diagonal block, in increasing element order -- are taken four at a time;
+// each slot runs its element's prologue (lane b = local node b = quadrature point b, as in
+// k_assemble) and forms the element-matrix row of node i, lane b holding block (a_i, b).  The
+// slots then add their blocks, in element order, into the row's accumulator in LDS, and the row's
+// W = 16 slots are written once, lane v storing value v of all of them (one 128-byte line).  Every
+// element is computed once per node, so its prologue runs four times, but no element matrix goes
+// through HBM.  The sums run in the order of k_gather_blocks / k_gather_nodes over the same
+// per-pair values, so K, R and the R-bar_k term are those of the element-buffer path.
+#define ROW_NODES 16
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <int FL, bool HGO>
+__global__ void __launch_bounds__(256)
+k_assemble_rows(int n, const int32_t *__restrict__ col, const int32_t *__restrict__ diag_pos,
+                const int32_t *__restrict__ src_ptr, const int32_t *__restrict__ src, int64_t nnzb,
+                const double *__restrict__ X, const int32_t *__restrict__ tets, const double *__restrict__ fibre,
+                MatP mp, vms_ga ga, StateP sp, double *__restrict__ KA, double *__restrict__ KB,
+                double *__restrict__ KC, double *__restrict__ KD, double *__restrict__ Rout,
+                double *__restrict__ Cout, const double *__restrict__ f_ext, double load, int *inverted) {
+  constexpr bool RES = FL & VMS_ASM_RESIDUAL;
+  constexpr bool COR = FL & VMS_ASM_RKCORR;
+  constexpr int W = 16;
+  __shared__ double acc[ROW_NODES][W][16];   // [node][slot][value]
+  __shared__ double accv[ROW_NODES][2][4];   // residual row, R-bar_k row
+  __shared__ int cols[ROW_NODES][W];         // the row's block columns
+  __shared__ double stg[ROW_NODES][W][NODE_STAGE];   // their staged values
+  const int g = threadIdx.x >> 4, l = threadIdx.x & 15;
+  const int sub = l >> 2, a = l & 3;
+  const int base = (threadIdx.x & 63) & ~3;
+  // XCD-aware: each XCD takes a contiguous range of rows, so its L2 holds that range's 1-ring state
+  const int node = xcd_block(blockIdx.x, gridDim.x) * ROW_NODES + g;
+  const bool nact = node < n;
+  const int i = nact ? node : n - 1;
+  const int dp = diag_pos[i];
+  const int k0 = src_ptr[dp];
+  const int cnt = nact ? src_ptr[dp + 1] - k0 : 0;
+#pragma unroll
+  for (int s = 0; s < W; ++s) acc[g][s][l] = 0.0;
+  {   // lane l stages the node of slot l (the padding slots repeat node i)
+    const int nd = col[(int64_t)W * i + l];
+    cols[g][l] = nd;
+    double v[NODE_STAGE];
+    stage_node<COR>(nd, X, ga, sp, v);
+#pragma unroll
+    for (int c = 0; c < NODE_STAGE; ++c) stg[g][l][c] = v[c];
+  }
+  if (l < 8) {
+    const int c = l & 3;
+    accv[g][l >> 2][c] = (RES && l < 4 && c < 3 && f_ext) ? load * f_ext[3 * (int64_t)i + c] : 0.0;
+  }
+  // the wavefront's four nodes run the same number of rounds (shuffles need every lane)
+  int rounds = (cnt + 3) >> 2;
+  rounds = max(rounds, __shfl_xor(rounds, 16, 64));
+  rounds = max(rounds, __shfl_xor(rounds, 32, 64));
+  wave_lds_sync();
+  // the next round's incidence and node are requested before this round's arithmetic (an inactive
+  // slot takes element 0, which exists whenever the wavefront has a round)
+  int ent_n = 0, nda_n = 0;
+  if (rounds > 0) {
+    ent_n = sub < cnt ? src[k0 + sub] : 0;
+    nda_n = tets[4 * (int64_t)(ent_n >> 4) + a];
+  }
+  for (int r = 0; r < rounds; ++r) {
+    const int kk = 4 * r + sub;
+    const bool act = kk < cnt;
+    const int ent = ent_n, nda = nda_n;
+    const int e = ent >> 4, ai = (ent >> 2) & 3;   // element and node i's local index in it
+    ent_n = kk + 4 < cnt ? src[k0 + kk + 4] : 0;
+    // this lane's slot in row i: the column nda among the row's sorted real blocks (every node of
+    // an element of node i is a column of row i; an inactive slot reads slot 0 and is discarded)
+    int slot = 0;
+    for (int s = 0; s < W; ++s)
+      if (cols[g][s] == nda) { slot = s; break; }
+    ElemQ q;
+    elem_prologue_staged<HGO>(e, a, base, act, stg[g][slot], fibre, mp, ga, inverted, q);
+    nda_n = tets[4 * (int64_t)(ent_n >> 4) + a];
+    const double(&ga_)[3] = q.ga_, (&gradp)[3] = q.gradp, (&L)[3][3] = q.L;
+    const double &J = q.J, &Jm23 = q.Jm23, &V = q.V, &w = q.w, &tau = q.tau, &trC = q.trC, &pbar = q.pbar;
+    const double &rho = q.rho, &beta = q.beta, &rhop = q.rhop, &betap = q.betap, &dpq = q.dpq;
+    const bool ok = q.ok;
+    const int src_row = base + ai;
+    double resv[4] = {0.0, 0.0, 0.0, 0.0};
+    if (RES) {   // the row of local node a, kept by lane a_i
+      double Pg[3];
+#pragma unroll
+      for (int ii = 0; ii < 3; ++ii) {
+        double pgi = mp.mu * Jm23 * ((q.F[ii][0] - trC / 3.0 * q.FiT[ii][0]) * q.Ga[0] +
+                                     (q.F[ii][1] - trC / 3.0 * q.FiT[ii][1]) * q.Ga[1] +
+                                     (q.F[ii][2] - trC / 3.0 * q.FiT[ii][2]) * q.Ga[2]);
+        if (HGO) {
+#pragma unroll
+          for (int f = 0; f < 2; ++f) {
+            const double aG = dot3(q.fa[f], q.Ga);
+            const double FHG = mp.kd * q.FGa[ii] + (1.0 - 3.0 * mp.kd) * q.Fa[f][ii] * aG;
+            pgi += q.W1[f] * Jm23 * (2.0 * FHG - 2.0 / 3.0 * q.HC[f] * ga_[ii]);
+          }
+        }
+        Pg[ii] = pgi;
+      }
+      resv[0] = q.sA[0] + V * Pg[0] - V * J * pbar * ga_[0];
+      resv[1] = q.sA[1] + V * Pg[1] - V * J * pbar * ga_[1];
+      resv[2] = q.sA[2] + V * Pg[2] - V * J * pbar * ga_[2];
+      resv[3] = q.PaA + tau * J * dot3(ga_, q.Xbar);
+    }
+    // element sums and this lane's column quantities (node b = a), as in k_assemble
+    const double cRb = q.w * J * rho, cBb = w * J * beta, cBpb = w * J * betap * dpq;
+    const double SR = qsum4(cRb), SB = qsum4(cBb), SBp = qsum4(cBpb), Srho = qsum4(rho);
+    double rpdb[3], Srpd[3];
+#pragma unroll
+    for (int ii = 0; ii < 3; ++ii) {
+      rpdb[ii] = rhop * q.dvq[ii];
+      Srpd[ii] = qsum4(rpdb[ii]);
+    }
+    const double gXb = dot3(ga_, q.Xbar);
+    double Lgb[3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) Lgb[j] = L[0][j] * ga_[0] + L[1][j] * ga_[1] + L[2][j] * ga_[2];
+    // row quantities of node a_i, from its lane
+    double Ga[3], gar[3], FGa[3], rpd[3], sA[3];
+#pragma unroll
+    for (int ii = 0; ii < 3; ++ii) {
+      Ga[ii] = qget(q.Ga[ii], src_row);
+      gar[ii] = qget(ga_[ii], src_row);
+      FGa[ii] = qget(q.FGa[ii], src_row);
+      rpd[ii] = qget(rpdb[ii], src_row);
+      sA[ii] = qget(q.sA[ii], src_row);
+    }
+    const double PaA = qget(q.PaA, src_row), gXa = qget(gXb, src_row);
+    const double cRa = qget(cRb, src_row), cBa = qget(cBb, src_row), cBpa = qget(cBpb, src_row);
+    const double(&Gb)[3] = q.Ga, (&gb)[3] = ga_, (&FGb)[3] = q.FGa;
+    const bool same = (ai == a);
+    const double ab = dot3(Ga, Gb);
+    const double gg = dot3(gar, gb);
+    double Ku[3][3];
+#pragma unroll
+    for (int ii = 0; ii < 3; ++ii)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        const double m = (ii == j ? ab : 0.0) - 2.0 / 3.0 * FGa[ii] * gb[j] - 2.0 / 3.0 * gar[ii] * FGb[j] +
+                         2.0 / 9.0 * trC * gar[ii] * gb[j] + trC / 3.0 * gar[j] * gb[ii];
+        Ku[ii][j] = V * mp.mu * Jm23 * m + V * J * pbar * (gar[j] * gb[ii] - gar[ii] * gb[j]) + sA[ii] * gb[j];
+      }
+    if (HGO) {
+#pragma unroll
+      for (int f = 0; f < 2; ++f) {
+        const double aGa = dot3(q.fa[f], Ga), aGb = dot3(q.fa[f], Gb);
+        const double GHG = mp.kd * ab + (1.0 - 3.0 * mp.kd) * aGa * aGb;
+        double FHa[3], FHb[3], Qa[3], Qb[3];
+#pragma unroll
+        for (int ii = 0; ii < 3; ++ii) {
+          FHa[ii] = mp.kd * FGa[ii] + (1.0 - 3.0 * mp.kd) * q.Fa[f][ii] * aGa;
+          FHb[ii] = mp.kd * FGb[ii] + (1.0 - 3.0 * mp.kd) * q.Fa[f][ii] * aGb;
+          Qa[ii] = Jm23 * (2.0 * FHa[ii] - 2.0 / 3.0 * q.HC[f] * gar[ii]);
+          Qb[ii] = Jm23 * (2.0 * FHb[ii] - 2.0 / 3.0 * q.HC[f] * gb[ii]);
+        }
+#pragma unroll
+        for (int ii = 0; ii < 3; ++ii)
+#pragma unroll
+          for (int j = 0; j < 3; ++j) {
+            const double d2E = -2.0 / 3.0 * Jm23 * gb[j] * (2.0 * FHa[ii] - 2.0 / 3.0 * q.HC[f] * gar[ii]) +
+                               Jm23 * ((ii == j ? 2.0 * GHG : 0.0) - 4.0 / 3.0 * gar[ii] * FHb[j] +
+                                       2.0 / 3.0 * q.HC[f] * gar[j] * gb[ii]);
+            Ku[ii][j] += V * (q.W2[f] * Qa[ii] * Qb[j] + q.W1[f] * d2E);
+          }
+      }
+    }
+    double Kpu[3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      Kpu[j] = gb[j] * PaA - J * w * Lgb[j] + tau * J * (gb[j] * gXa - gar[j] * gXb - V * gg * gradp[j]);
+    const double mR = qsum2(cRa, cRb, SR, same);
+    const double rN = w * (QB * Srho + QD * rho);
+    const double st = w * (QB * dot3(gar, Srpd) + QD * dot3(gar, rpdb));
+    double dRm_dp[3], dRp_dvd[3], dRp_dv[3];
+#pragma unroll
+    for (int ii = 0; ii < 3; ++ii) {
+      const double rpv = w * J * (QB * QB * Srpd[ii] + QB * QD * (rpd[ii] + rpdb[ii]) + (same ? QD * QD * rpd[ii] : 0.0));
+      dRm_dp[ii] = rpv - J * gar[ii] * w;
+      dRp_dvd[ii] = tau * J * gar[ii] * rN;
+      dRp_dv[ii] = J * gb[ii] * w;
+    }
+    const double dRp_dp = qsum2(cBpa, cBpb, SBp, same) + tau * J * (V * gg + st);
+    const double dRp_dpd = qsum2(cBa, cBb, SB, same);
+    double kv[16];
+#pragma unroll
+    for (int ii = 0; ii < 3; ++ii)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) kv[3 * ii + j] = (ii == j ? ga.am * mR : 0.0) + ga.c3 * Ku[ii][j];
+#pragma unroll
+    for (int ii = 0; ii < 3; ++ii) kv[9 + ii] = ga.c2 * dRm_dp[ii];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) kv[12 + j] = ga.am * dRp_dvd[j] + ga.c2 * dRp_dv[j] + ga.c3 * Kpu[j];
+    kv[15] = ga.am * dRp_dpd + ga.c2 * dRp_dp;
+    // the R-bar_k term of row a_i: sum over the columns b in order (the lanes of the slot)
+    double cv[4] = {0.0, 0.0, 0.0, 0.0};
+    if (COR) {
+      double tu[3], tp;
+#pragma unroll
+      for (int ii = 0; ii < 3; ++ii) tu[ii] = Ku[ii][0] * q.rka[0] + Ku[ii][1] * q.rka[1] + Ku[ii][2] * q.rka[2];
+      tp = Kpu[0] * q.rka[0] + Kpu[1] * q.rka[1] + Kpu[2] * q.rka[2];
+      double cu[3] = {0.0, 0.0, 0.0}, cp = 0.0;
+#pragma unroll
+      for (int ii = 0; ii < 3; ++ii) cu[ii] = ((qbc<0>(tu[ii]) + qbc<1>(tu[ii])) + qbc<2>(tu[ii])) + qbc<3>(tu[ii]);
+      cp = ((qbc<0>(tp) + qbc<1>(tp)) + qbc<2>(tp)) + qbc<3>(tp);
+      const double sc = ok ? ga.c2 / ga.am : 0.0;
+      cv[0] = sc * cu[0]; cv[1] = sc * cu[1]; cv[2] = sc * cu[2]; cv[3] = sc * cp;
+    }
+    // add the four elements' contributions in element order
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      if (sub == t && act) {
+#pragma unroll
+        for (int v = 0; v < 16; ++v) acc[g][slot][v] += ok ? kv[v] : 0.0;
+        if ((RES || COR) && a == ai) {
+#pragma unroll
+          for (int c = 0; c < 4; ++c) {
+            if (RES) accv[g][0][c] += ok ? resv[c] : 0.0;
+            if (COR) accv[g][1][c] += cv[c];
+          }
+        }
+      }
+      wave_lds_sync();
+    }
+  }
+  if (!nact) return;
+  const int64_t b0 = (int64_t)W * i;
+  double *dst = l < 9 ? KA + l * nnzb : (l < 12 ? KB + (l - 9) * nnzb : (l < 15 ? KC + (l - 12) * nnzb : KD));
+#pragma unroll
+  for (int s = 0; s < W; ++s) dst[b0 + s] = acc[g][s][l];
+  if (RES && l < 4) Rout[4 * (int64_t)i + l] = accv[g][0][l];
+  if (COR && l >= 4 && l < 8) Cout[4 * (int64_t)i + (l - 4)] = accv[g][1][l - 4];
+}
+
 // Nodal rows from an element buffer E[e][a][ws]: out[i][c] (c < w) = init +
 // sum over the (element, local node) incidences of node i, which are the
 // contributions of its diagonal block (pairs a*4 + a).  init = load * f_ext
@@ -527,10 +860,15 @@ k_gather_nodes(int n, int w, const int32_t *__restrict__ diag_pos, const int32_t
   const int i = (int)(gt / w), c = (int)(gt % w);
   const int blk = diag_pos[i];
   double s = (f_ext && c < 3) ? load * f_ext[3 * (int64_t)i + c] : 0.0;
-  for (int k = ptr[blk]; k < ptr[blk + 1]; ++k) {
-    const int q = src[k];
-    s += E[(4 * (int64_t)(q >> 4) + ((q & 15) >> 2)) * ws + c];
+  auto at = [&](int q) { return (4 * (int64_t)(q >> 4) + ((q & 15) >> 2)) * ws + c; };
+  const int k1 = ptr[blk + 1];
+  int k = ptr[blk];
+  for (; k + 4 <= k1; k += 4) {   // four loads in flight, sums in list order
+    const int q0 = src[k], q1 = src[k + 1], q2 = src[k + 2], q3 = src[k + 3];
+    const double x0 = E[at(q0)], x1 = E[at(q1)], x2 = E[at(q2)], x3 = E[at(q3)];
+    s = (((s + x0) + x1) + x2) + x3;
   }
+  for (; k < k1; ++k) s += E[at(src[k])];
   out[gt] = s;
 }
 
@@ -741,7 +1079,14 @@ int vms_check_mesh(vms_ctx *ctx, const vms_mesh *m) {
   return VMS_OK;
 }
 
+// The tangent (with the residual and the R-bar_k term) goes by row owners, straight into K, R and
+// corr, when every block row has sixteen slots and no VJP or sensitivity is asked.
+static bool asm_by_rows(const vms_mesh *mesh, unsigned flags) {
+  return (flags & VMS_ASM_TANGENT) && !(flags & (VMS_ASM_VJP | VMS_ASM_SENS)) && mesh->slot_width == 16;
+}
+
 size_t vms_asm_scratch_bytes(const vms_mesh *mesh, unsigned flags) {
+  if (asm_by_rows(mesh, flags)) return 4 * 256;
   size_t per = 0;   // doubles per element
   if (flags & VMS_ASM_TANGENT) per += 256;
   if (flags & VMS_ASM_RESIDUAL) per += 16;
@@ -777,11 +1122,31 @@ int vms_launch_assemble(vms_ctx *ctx, const vms_mesh *mesh, const vms_material *
     p += ((per * sizeof(double) * (size_t)m + 255) / 256) * 256;
     return r;
   };
+  const bool hgo = (mat->kind == VMS_HGO_INCOMP);
+  if (asm_by_rows(mesh, flags)) {   // nodes without elements get zero blocks and load * f_ext
+    dim3 gr((unsigned)((n + ROW_NODES - 1) / ROW_NODES)), bl(256);
+#define VMS_ROWS_CASE(FLV)                                                                               \
+  case FLV: {                                                                                            \
+    auto kern = hgo ? (k_assemble_rows<FLV, true>) : (k_assemble_rows<FLV, false>);                      \
+    hipLaunchKernelGGL(kern, gr, bl, 0, ctx->stream, n, mesh->col, mesh->diag_pos, mesh->blk_src_ptr,    \
+                       mesh->blk_src, nnzb, mesh->X, mesh->tets, mesh->fibre, mp, ga, sp, K->A, K->B, K->C, \
+                       K->D, R, corr, f_ext, ga.load, &ctx->dstat->inverted);                            \
+  } break;
+    switch (flags & 7u) {
+      VMS_ROWS_CASE(2)
+      VMS_ROWS_CASE(3)
+      VMS_ROWS_CASE(6)
+      VMS_ROWS_CASE(7)
+      default: return vms_set_error(ctx, VMS_ERR_ARG, "unsupported assembly flags");
+    }
+#undef VMS_ROWS_CASE
+    VMS_LAUNCH_CHECK(ctx);
+    return VMS_OK;
+  }
   double *KE = tan ? take(256) : nullptr;
   double *RE = res ? take(16) : nullptr;
   double *CE = cor ? take(16) : nullptr;
   double *VE = vj ? take(48) : nullptr;
-  const bool hgo = (mat->kind == VMS_HGO_INCOMP);
   if (m > 0) {
     dim3 gr((unsigned)((4 * (int64_t)m + 255) / 256)), bl(256);
 #define VMS_ASM_CASE(FLV)                                                                                 \

@@ -820,6 +820,14 @@ k_cg_spmv(int n, int64_t nnzb, int W, const int32_t *__restrict__ col, const T *
   const int vb = xcd_block(blockIdx.x, gridDim.x);   // even split: every workgroup gets floor or ceil(ng / grid)
   const int g0 = (int)((int64_t)vb * ng / gridDim.x), g1 = (int)((int64_t)(vb + 1) * ng / gridDim.x);
   double pq = 0.0;
+  // FP64, rows of 16 slots: one block per lane, and the next group's column index is requested
+  // before this group's gathers, so a group waits for one load latency (A and z together), not two
+  const bool pf = LATE && W == 16;
+  int cnext = 0;
+  if (pf && g0 < g1) {
+    const int row = g0 * SPMV_ROWS_PER_BLOCK + sub;
+    cnext = row < n ? ldc<NT>(col, 16 * (int64_t)row + lane) : 0;
+  }
   for (int g = g0; g < g1; ++g) {
     const int row = g * SPMV_ROWS_PER_BLOCK + sub;
     const bool act = row < n;
@@ -834,12 +842,27 @@ k_cg_spmv(int n, int64_t nnzb, int W, const int32_t *__restrict__ col, const T *
       if (!first) { pc = ld(p, oc); qc = ld(q, oc); }
     }
     double a0 = 0, a1 = 0, a2 = 0;
-    for (int b = b0 + lane; b < b1; b += 16) {
-      const int64_t o = 3 * (int64_t)ldc<NT>(col, b);
-      const double x0 = ld(z, o), x1 = ld(z, o + 1), x2 = ld(z, o + 2);
-      a0 += ldm<NT>(A, 0 * nnzb + b) * x0 + ldm<NT>(A, 1 * nnzb + b) * x1 + ldm<NT>(A, 2 * nnzb + b) * x2;
-      a1 += ldm<NT>(A, 3 * nnzb + b) * x0 + ldm<NT>(A, 4 * nnzb + b) * x1 + ldm<NT>(A, 5 * nnzb + b) * x2;
-      a2 += ldm<NT>(A, 6 * nnzb + b) * x0 + ldm<NT>(A, 7 * nnzb + b) * x1 + ldm<NT>(A, 8 * nnzb + b) * x2;
+    if (pf) {
+      const int64_t o = 3 * (int64_t)cnext;
+      if (g + 1 < g1) {
+        const int rn = row + SPMV_ROWS_PER_BLOCK;
+        cnext = rn < n ? ldc<NT>(col, 16 * (int64_t)rn + lane) : 0;
+      }
+      if (act) {
+        const int b = b0 + lane;
+        const double x0 = ld(z, o), x1 = ld(z, o + 1), x2 = ld(z, o + 2);
+        a0 = ldm<NT>(A, 0 * nnzb + b) * x0 + ldm<NT>(A, 1 * nnzb + b) * x1 + ldm<NT>(A, 2 * nnzb + b) * x2;
+        a1 = ldm<NT>(A, 3 * nnzb + b) * x0 + ldm<NT>(A, 4 * nnzb + b) * x1 + ldm<NT>(A, 5 * nnzb + b) * x2;
+        a2 = ldm<NT>(A, 6 * nnzb + b) * x0 + ldm<NT>(A, 7 * nnzb + b) * x1 + ldm<NT>(A, 8 * nnzb + b) * x2;
+      }
+    } else {
+      for (int b = b0 + lane; b < b1; b += 16) {
+        const int64_t o = 3 * (int64_t)ldc<NT>(col, b);
+        const double x0 = ld(z, o), x1 = ld(z, o + 1), x2 = ld(z, o + 2);
+        a0 += ldm<NT>(A, 0 * nnzb + b) * x0 + ldm<NT>(A, 1 * nnzb + b) * x1 + ldm<NT>(A, 2 * nnzb + b) * x2;
+        a1 += ldm<NT>(A, 3 * nnzb + b) * x0 + ldm<NT>(A, 4 * nnzb + b) * x1 + ldm<NT>(A, 5 * nnzb + b) * x2;
+        a2 += ldm<NT>(A, 6 * nnzb + b) * x0 + ldm<NT>(A, 7 * nnzb + b) * x1 + ldm<NT>(A, 8 * nnzb + b) * x2;
+      }
     }
     if (LATE && own) {
       zc = ld(z, oc);

@@ -111,10 +111,22 @@ def test_small_workspaces_are_refused():
                               C.byref(V.solver_opts()), ws.data_ptr(), ws.numel(), C.byref(stats))
     assert rc == -3
     R = torch.empty(mesh.n_nodes, 4, dtype=torch.float64, device="cuda:0")
+    # the residual alone goes through element vectors (128 B per element)
+    assert lib.vms_assemble_workspace(C.byref(prob.cmesh), V.ASM_RESIDUAL) > ws.numel()
+    rc = lib.vms_assemble(prob.ctx, C.byref(prob.cmesh), C.byref(prob.cmat), C.byref(_ti(ti)),
+                          C.byref(prob.cstate(st)), prob.f_ext.data_ptr(), None, R.data_ptr(), None,
+                          V.ASM_RESIDUAL, ws.data_ptr(), ws.numel())
+    assert rc == -3
+    # the tangent on 16-slot rows is assembled by the row owners and needs 1 KB only
+    assert lib.vms_assemble_workspace(C.byref(prob.cmesh), V.ASM_RESIDUAL | V.ASM_TANGENT) == 1024
+    rc = lib.vms_assemble(prob.ctx, C.byref(prob.cmesh), C.byref(prob.cmat), C.byref(_ti(ti)),
+                          C.byref(prob.cstate(st)), prob.f_ext.data_ptr(), C.byref(K.c()), R.data_ptr(), None,
+                          V.ASM_RESIDUAL | V.ASM_TANGENT, ws.data_ptr(), 512)
+    assert rc == -3
     rc = lib.vms_assemble(prob.ctx, C.byref(prob.cmesh), C.byref(prob.cmat), C.byref(_ti(ti)),
                           C.byref(prob.cstate(st)), prob.f_ext.data_ptr(), C.byref(K.c()), R.data_ptr(), None,
                           V.ASM_RESIDUAL | V.ASM_TANGENT, ws.data_ptr(), ws.numel())
-    assert rc == -3
+    assert rc == 0
     rc = lib.vms_assemble(prob.ctx, C.byref(prob.cmesh), C.byref(prob.cmat), C.byref(_ti(ti)),
                           C.byref(prob.cstate(st)), prob.f_ext.data_ptr(), C.byref(K.c()), R.data_ptr(), None,
                           0, ws.data_ptr(), ws.numel())
