@@ -84,6 +84,7 @@ PMC_FILES = {
              "shat_spmv_cube64_pmc.md"),
     "cg_spmv": ("solver.hip", "// CG iteration j, first half.", "// CG iteration j, second half",
                 "cg_spmv_cube64_pmc.md"),
+    "assemble_rows": ("assembly.hip", None, None, "assembly_cube64_pmc.md"),
 }
 
 
@@ -621,6 +622,8 @@ def main():
     rd, wr = tangent_bytes(n, mesh.n_tets, prob.slot_width, mesh.fibre is not None)
     extra["tangent_assembly"] = {"us_per_call": ttan * 1e6, "bytes_read": rd, "bytes_written": wr,
                                  "GB/s": (rd + wr) / ttan / 1e9, "frac_hbm": (rd + wr) / ttan / 1e9 / HBM_PEAK_GBS,
+                                 "traffic": (pmc_traffic("assemble_rows", "traffic_bytes")
+                                             if cube and N == 64 else None),
                                  "timing": "wall time per call over 20 calls, each with its host synchronisation"}
     first = r["per_step"][0]
     extra["first_step"] = {"ms": first["ms_total"], "n_newton": first["n_newton"],
