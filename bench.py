@@ -401,7 +401,9 @@ def main():
                     help="preconditioner of the A-levels: 3x3 block-Jacobi or the aggregation multigrid; auto = "
                          "block-Jacobi on the cube (mass-dominated A at dt = 1e-3), multigrid on the strip and tube")
     ap.add_argument("--amg-levels", type=int, default=3)
-    ap.add_argument("--amg-degree", type=int, default=2)
+    ap.add_argument("--amg-degree", type=int, default=3,
+                    help="Chebyshev degree of the multigrid's pre- and post-smoothing (3: 5-8 %% less time per "
+                         "step than 2 on the strip and the tube's mixed form)")
     ap.add_argument("--shat-method", default=None, choices=["chebyshev", "cg", "none"],
                     help="S^ preconditioner of the Schur solve: Chebyshev polynomial or CG steps (--shat-degree)")
     ap.add_argument("--outer-tol", type=float, default=1e-8,

@@ -616,8 +616,9 @@ k_gather_blocks(int64_t nnzb, const int32_t *__restrict__ ptr, const int32_t *__
 // slots then add their blocks, in element order, into the row's accumulator in LDS, and the row's
 // W = 16 slots are written once, lane v storing value v of all of them (one 128-byte line).  Every
 // element is computed once per node, so its prologue runs four times, but no element matrix goes
-// through HBM.  The sums run in the order of k_gather_blocks / k_gather_nodes over the same
-// per-pair values, so K, R and the R-bar_k term are those of the element-buffer path.
+// through HBM.  The sums run in the order of k_gather_blocks / k_gather_nodes (increasing element)
+// over the same per-pair formulas, so K, R and the R-bar_k term agree with the element-buffer path
+// to rounding (the two kernels' FMA contractions differ) and are bitwise reproducible run to run.
 #define ROW_NODES 16
 __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");

@@ -1658,6 +1658,15 @@ int orth_level(vms_ctx *ctx, KLevel<T> &L, int j, int maxit, int mode, int pc, c
   return VMS_OK;
 }
 
+// Iterations to enqueue before the host next reads a level's flags.  The first batch is most of
+// the previous solve's count on the level (consecutive solves differ by a few iterations), later
+// ones start at an eighth of it and double: a launch past convergence still costs a few
+// microseconds per kernel, a host round trip about as much as one iteration's kernels.
+inline int next_batch(int est, int round) {
+  if (round == 0) return std::max(1, (7 * est + 7) / 8);
+  return std::min(64, std::max(2, (est + 7) / 8) << std::min(round - 1, 5));
+}
+
 // Right-preconditioned (F)GMRES with x0 = 0 on level L.  op(j) enqueues
 // W = Op Z_j; for pc != PC_NONE the device preconditioner fills Z_{j+1} from
 // V_{j+1}, otherwise op(j) itself must first fill Z_j (flexible variant).
@@ -1682,7 +1691,8 @@ int gmres_run(vms_ctx *ctx, KLevel<T> &L, const T *b, T *x, double rtol, double 
     read = true;
   }
   const bool posting = (orth != VMS_ORTH_MGS);   // the last normalisation kernel of a batch posts the flags
-  int batch = sync_each ? 1 : std::max(1, est);
+  int round = 0;
+  int batch = sync_each ? 1 : next_batch(est, round++);
   while (!done && j < maxit) {
     const int nbt = std::min(batch, maxit - j);
     int32_t seq = 0;
@@ -1696,7 +1706,7 @@ int gmres_run(vms_ctx *ctx, KLevel<T> &L, const T *b, T *x, double rtol, double 
     if ((rc = posting ? vms_wait_post(ctx, seq, L.iflag) : sync_level_flags(ctx, L.iflag))) return rc;
     done = ctx->h_i[IF_DONE] != 0;
     read = true;
-    if (!sync_each) batch = std::min(2 * batch, 64);
+    if (!sync_each) batch = next_batch(est, round++);
   }
   if (!read && (rc = sync_level_flags(ctx, L.iflag))) return rc;
   status_out = ctx->h_i[IF_STATUS];
@@ -1750,7 +1760,8 @@ int cg_run(vms_ctx *ctx, KLevel<T> &L, const vms_mesh *mesh, const T *Acg, doubl
   int j = 0;
   spmv(0, nullptr, 0);
   VMS_LAUNCH_CHECK(ctx);
-  int batch = std::max(1, est);
+  int round = 0;
+  int batch = next_batch(est, round++);
   bool done = false;
   while (!done) {
     const int nbt = std::min(batch, maxit - j);
@@ -1770,7 +1781,7 @@ int cg_run(vms_ctx *ctx, KLevel<T> &L, const vms_mesh *mesh, const T *Acg, doubl
     int rc = vms_wait_post(ctx, seq, L.iflag);
     if (rc) return rc;
     done = ctx->h_i[IF_DONE] != 0;
-    batch = std::min(2 * batch, 64);
+    batch = next_batch(est, round++);
   }
   status_out = ctx->h_i[IF_STATUS];
   its_out = ctx->h_i[IF_ITS];
@@ -1985,7 +1996,8 @@ int amg_cg_run(vms_ctx *ctx, KLevel<T> &L, const vms_mesh *mesh, const T *Acg, d
   int j = 0;
   spmv(0, nullptr, 0);
   VMS_LAUNCH_CHECK(ctx);
-  int batch = std::max(1, est);
+  int round = 0;
+  int batch = next_batch(est, round++);
   bool fin = false;
   while (!fin) {
     const int nbt = std::min(batch, maxit - j);
@@ -2006,7 +2018,7 @@ int amg_cg_run(vms_ctx *ctx, KLevel<T> &L, const vms_mesh *mesh, const T *Acg, d
     int rc = vms_wait_post(ctx, seq, L.iflag);
     if (rc) return rc;
     fin = ctx->h_i[IF_DONE] != 0;
-    batch = std::min(2 * batch, 64);
+    batch = next_batch(est, round++);
   }
   status_out = ctx->h_i[IF_STATUS];
   its_out = ctx->h_i[IF_ITS];

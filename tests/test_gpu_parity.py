@@ -765,3 +765,105 @@ def test_lifted_tube_time_steps_match_oracle(precision):
     tol = 1e-6 if mixed else 1e-7
     for k in ("u", "p", "v") if mixed else ("u", "p", "v", "du", "dp", "dv"):
         assert rel_err(st[k].cpu().numpy(), so[k]) < tol, k
+
+
+def fan_mesh(offset=(0.0, 0.0, 0.0)):
+    """A node of valence 18: the centre of a ball whose surface is the octahedron with each face
+    split in four (18 surface nodes, 32 tets).  Its block row has 19 blocks, so the pattern takes
+    32 slots per row and the tangent goes through the element matrices and the block gather."""
+    V6 = [np.eye(3)[i] * s for i in range(3) for s in (1.0, -1.0)]
+    faces = [(a, b, c) for a in (0, 1) for b in (2, 3) for c in (4, 5)]
+    pts = [np.zeros(3)] + [v for v in V6]          # centre 0, octahedron vertices 1..6
+    mid = {}
+
+    def midpoint(i, j):
+        key = (min(i, j), max(i, j))
+        if key not in mid:
+            p = pts[i] + pts[j]
+            pts.append(p / np.linalg.norm(p))
+            mid[key] = len(pts) - 1
+        return mid[key]
+    tris = []
+    for a, b, c in faces:
+        a, b, c = a + 1, b + 1, c + 1
+        ab, bc, ca = midpoint(a, b), midpoint(b, c), midpoint(c, a)
+        tris += [(a, ab, ca), (ab, b, bc), (ca, bc, c), (ab, bc, ca)]
+    X = np.array(pts) + np.asarray(offset)
+    tets = []
+    for a, b, c in tris:
+        t = [0, a, b, c]
+        if np.linalg.det(np.array([X[a] - X[0], X[b] - X[0], X[c] - X[0]])) < 0.0:
+            t = [0, b, a, c]
+        tets.append(t)
+    return X, np.array(tets, np.int32)
+
+
+def _asm_case_with_fan(with_cube):
+    mesh, mat, ti = synth.cube_case(3, nu=0.45, n_steps=2)
+    if not with_cube:
+        X, tets = fan_mesh()
+        n = X.shape[0]
+        m = synth.mesh.Mesh("fan", X, tets, np.zeros((0, 3), np.int32), np.zeros((0, 3)),
+                            np.zeros((n, 4), np.uint8), np.zeros((n, 3)))
+        return m, mat, ti
+    Xf, tf = fan_mesh(offset=(10.0, 0.0, 0.0))
+    n0, nf = mesh.n_nodes, Xf.shape[0]
+    m = synth.mesh.Mesh("cube+fan", np.vstack([mesh.X, Xf]), np.vstack([mesh.tets, tf + n0]).astype(np.int32),
+                        mesh.bfaces, mesh.traction, np.vstack([mesh.dir_mask, np.zeros((nf, 4), np.uint8)]),
+                        np.vstack([mesh.dir_vel, np.zeros((nf, 3))]))
+    return m, mat, ti
+
+
+def test_wide_rows_assemble_through_the_element_buffer():
+    """A mesh whose longest block row needs 32 slots: the tangent, residual and R-bar_k term come
+    from the element kernel and the gathers, and match the oracle."""
+    mesh, mat, ti = _asm_case_with_fan(False)
+    prob = V.Problem(mesh, mat, "cuda:0")
+    assert prob.slot_width == 32
+    print(f"[assembly] fan n={mesh.n_nodes} m={mesh.n_tets} W={prob.slot_width}", flush=True)
+    sn = synth.random_state(mesh.n_nodes, 61, {"u": 1e-3})
+    it = synth.random_state(mesh.n_nodes, 62, {"u": 1e-3})
+    st = gpu_state(prob, sn, it)
+    t_n = 0.4 * ti.dt
+    K, R, corr = prob.assemble(st, gpu_ti(ti, t_n), V.ASM_RESIDUAL | V.ASM_TANGENT | V.ASM_RKCORR)
+    disc = AS.Discretization(mesh, mat)
+    am, af, gm = E.genalpha(ti.rho_inf)
+    sto = NW.stage(sn, it, am, af)
+    R_o = disc.residual(sto, NW.load_scale(ti, t_n + af * ti.dt))
+    K_o = disc.tangent(sto, (am, af, gm, ti.dt))
+    corr_o = (af * gm * ti.dt / am) * disc.u_jvp(sto, sto["du"] - sto["v"])
+    assert rel_err(R.cpu().numpy(), R_o) < TOL_ASM
+    assert rel_err(corr.cpu().numpy(), corr_o) < TOL_ASM
+    assert rel_err(gpu_K_scipy(prob, K).toarray(), K_o.toarray()) < TOL_ASM
+
+
+def test_row_owner_and_element_buffer_tangents_agree():
+    """The cube's rows assembled by their owners (16-slot pattern) against the same rows of the cube
+    with a disjoint wide-row component appended (32-slot pattern, element buffer): both sum the
+    same per-pair values in element order, so they agree to rounding (FMA contraction may differ
+    between the two kernels)."""
+    out = []
+    for with_fan in (False, True):
+        mesh, mat, ti = synth.cube_case(3, nu=0.45, n_steps=2) if not with_fan else _asm_case_with_fan(True)
+        prob = V.Problem(mesh, mat, "cuda:0")
+        print(f"[assembly] {mesh.name} W={prob.slot_width}", flush=True)
+        n0 = 64
+        st = prob.new_state()
+        rs = synth.random_state(n0, 71, {"u": 1e-3})
+        rn = synth.random_state(n0, 72, {"u": 1e-3})
+        for k in ("u", "p", "v", "du", "dp", "dv"):
+            st[k][:n0].copy_(torch.from_numpy(rs[k]))
+            st[k + "_n"][:n0].copy_(torch.from_numpy(rn[k]))
+        K, R, corr = prob.assemble(st, gpu_ti(ti, 0.3 * ti.dt), V.ASM_RESIDUAL | V.ASM_TANGENT | V.ASM_RKCORR)
+        W = prob.slot_width
+        rl = prob.host["row_len"][:n0]
+        real = np.concatenate([W * i + np.arange(rl[i]) for i in range(n0)])
+        blocks = [t.cpu().numpy().reshape(t.shape[0] if t.dim() > 1 else 1, -1)[:, real] for t in (K.A, K.B, K.C, K.D)]
+        out.append((R.cpu().numpy()[:n0], corr.cpu().numpy()[:n0], blocks, W))
+    (R0, c0, b0, W0), (R1, c1, b1, W1) = out
+    assert (W0, W1) == (16, 32)
+    assert rel_err(R1, R0) < 1e-14 and rel_err(c1, c0) < 1e-14
+    for x, y in zip(b1, b0):
+        assert rel_err(x, y) < 1e-14
+    same = sum(int(np.array_equal(x, y)) for x, y in zip(b1 + [R1, c1], b0 + [R0, c0]))
+    print(f"[assembly] row-owner vs element-buffer: {same} of 6 arrays bitwise equal", flush=True)
