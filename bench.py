@@ -401,9 +401,10 @@ def main():
                     help="preconditioner of the A-levels: 3x3 block-Jacobi or the aggregation multigrid; auto = "
                          "block-Jacobi on the cube (mass-dominated A at dt = 1e-3), multigrid on the strip and tube")
     ap.add_argument("--amg-levels", type=int, default=3)
-    ap.add_argument("--amg-degree", type=int, default=3,
-                    help="Chebyshev degree of the multigrid's pre- and post-smoothing (3: 5-8 %% less time per "
-                         "step than 2 on the strip and the tube's mixed form)")
+    ap.add_argument("--amg-degree", type=int, default=None,
+                    help="Chebyshev degree of the multigrid's pre- and post-smoothing; default 3 on the strip "
+                         "(5-7 %% less time per step than 2), 2 elsewhere (the tube's steps take more outer "
+                         "iterations with 3)")
     ap.add_argument("--shat-method", default=None, choices=["chebyshev", "cg", "none"],
                     help="S^ preconditioner of the Schur solve: Chebyshev polynomial or CG steps (--shat-degree)")
     ap.add_argument("--outer-tol", type=float, default=1e-8,
@@ -462,6 +463,8 @@ def main():
         args.schur_mass = 0.0 if cube else 1.0
     if args.shat_method is None:
         args.shat_method = "none" if tube and args.schur_mass > 0.0 else "cg"
+    if args.amg_degree is None:
+        args.amg_degree = 3 if args.workload == "strip" else 2
     if args.a_prec == "auto":
         args.a_prec = "bj" if args.workload == "cube" else "amg"
     if args.workload == "tube":

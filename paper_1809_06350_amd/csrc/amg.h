@@ -112,16 +112,26 @@ k_amgf_chebres(int n, int64_t nnzb, int W, const int32_t *__restrict__ col, cons
                const T *__restrict__ Minv, const T *__restrict__ b, const T *__restrict__ x, T *r, T *d,
                const double *lam, const int *done) {
   SPMV_PROLOGUE
+  // the row's own operands are requested before the product, so their loads overlap its loads
+  const bool own = act && lane < 3;
+  const int64_t o = 3 * (int64_t)(act ? row : 0);
+  const int c = own ? lane : 0;
+  double bo0 = 0.0, bo1 = 0.0, bo2 = 0.0, m0 = 0.0, m1 = 0.0, m2 = 0.0;
+  if (own) {
+    bo0 = ld(b, o); bo1 = ld(b, o + 1); bo2 = ld(b, o + 2);
+    const T *M = Minv + 9 * (int64_t)row + 3 * c;
+    m0 = ld(M, 0); m1 = ld(M, 1); m2 = ld(M, 2);
+  }
+  const double lamv = *lam;
   double a0, a1, a2;
   amgf_row(nnzb, b0, b1, lane, col, A, x, a0, a1, a2);
-  if (!act || lane >= 3) return;
+  if (!own) return;
   double th, c1, c2;
-  amg_cheb(*lam, 0, th, c1, c2);
-  const int64_t o = 3 * (int64_t)row;
-  const double w0 = ld(b, o) - a0, w1 = ld(b, o + 1) - a1, w2 = ld(b, o + 2) - a2;
-  const double z = bj3_comp(Minv + 9 * (int64_t)row, lane, w0, w1, w2);
-  r[o + lane] = (T)z;
-  d[o + lane] = (T)(z / th);
+  amg_cheb(lamv, 0, th, c1, c2);
+  const double w0 = bo0 - a0, w1 = bo1 - a1, w2 = bo2 - a2;
+  const double z = m0 * w0 + m1 * w1 + m2 * w2;
+  r[o + c] = (T)z;
+  d[o + c] = (T)(z / th);
 }
 
 // Chebyshev step k: r -= M A d_k, d_{k+1} = c1 d_k + c2 r, x += (pending ? d_k : 0) + d_{k+1}
@@ -131,19 +141,27 @@ k_amgf_step(int n, int64_t nnzb, int W, const int32_t *__restrict__ col, const T
             const T *__restrict__ Minv, const T *__restrict__ dk, T *dn, T *r, T *x, const double *lam, int k,
             int pending, const int *done) {
   SPMV_PROLOGUE
+  // the row's own operands are requested before the product, so their loads overlap its loads
+  const bool own = act && lane < 3;
+  const int64_t o = 3 * (int64_t)(act ? row : 0) + (own ? lane : 0);
+  double ro = 0.0, dko = 0.0, xo = 0.0, m0 = 0.0, m1 = 0.0, m2 = 0.0;
+  if (own) {
+    ro = ld(r, o); dko = ld(dk, o); xo = ld(x, o);
+    const T *M = Minv + 9 * (int64_t)row + 3 * lane;
+    m0 = ld(M, 0); m1 = ld(M, 1); m2 = ld(M, 2);
+  }
+  const double lamv = *lam;
   double a0, a1, a2;
   amgf_row(nnzb, b0, b1, lane, col, A, dk, a0, a1, a2);
-  if (!act || lane >= 3) return;
+  if (!own) return;
   double th, c1, c2;
-  amg_cheb(*lam, k, th, c1, c2);
-  const int64_t o = 3 * (int64_t)row + lane;
-  const double z = bj3_comp(Minv + 9 * (int64_t)row, lane, a0, a1, a2);
-  const double rn = ld(r, o) - z;
-  const double dko = ld(dk, o);
+  amg_cheb(lamv, k, th, c1, c2);
+  const double z = m0 * a0 + m1 * a1 + m2 * a2;
+  const double rn = ro - z;
   const double dnv = c1 * dko + c2 * rn;
   r[o] = (T)rn;
   dn[o] = (T)dnv;
-  x[o] = (T)(ld(x, o) + (pending ? dko : 0.0) + dnv);
+  x[o] = (T)(xo + (pending ? dko : 0.0) + dnv);
 }
 
 // restriction, first half: the residual res = b - A x of the row and its ten mode contributions
@@ -154,15 +172,23 @@ k_amgf_resid_t(int n, int64_t nnzb, int W, const int32_t *__restrict__ col, cons
                const T *__restrict__ b, const T *__restrict__ x, const TP *__restrict__ Q,
                const double *__restrict__ Wsc, T *t, const int *done) {
   SPMV_PROLOGUE
+  // the row's own operands are requested before the product, so their loads overlap its loads
+  const bool own = act && lane < AMG_NM;
+  const int64_t o = 3 * (int64_t)(act ? row : 0);
+  double bo0 = 0.0, bo1 = 0.0, bo2 = 0.0, w0 = 1.0, w1 = 1.0, w2 = 1.0, q0 = 0.0, q1 = 0.0, q2 = 0.0;
+  if (own) {
+    bo0 = ld(b, o); bo1 = ld(b, o + 1); bo2 = ld(b, o + 2);
+    w0 = Wsc[4 * (int64_t)row]; w1 = Wsc[4 * (int64_t)row + 1]; w2 = Wsc[4 * (int64_t)row + 2];
+    const TP *q = Q + (int64_t)row * 3 * AMG_NM + lane;
+    q0 = ld(q, 0); q1 = ld(q, AMG_NM); q2 = ld(q, 2 * AMG_NM);
+  }
   double a0, a1, a2;
   amgf_row(nnzb, b0, b1, lane, col, A, x, a0, a1, a2);
-  if (!act || lane >= AMG_NM) return;
-  const int64_t o = 3 * (int64_t)row;
-  const double r0 = (ld(b, o) - a0) / Wsc[4 * (int64_t)row];
-  const double r1 = (ld(b, o + 1) - a1) / Wsc[4 * (int64_t)row + 1];
-  const double r2 = (ld(b, o + 2) - a2) / Wsc[4 * (int64_t)row + 2];
-  const TP *q = Q + (int64_t)row * 3 * AMG_NM + lane;
-  t[(int64_t)row * AMG_NM + lane] = (T)(ld(q, 0) * r0 + ld(q, AMG_NM) * r1 + ld(q, 2 * AMG_NM) * r2);
+  if (!own) return;
+  const double r0 = (bo0 - a0) / w0;
+  const double r1 = (bo1 - a1) / w1;
+  const double r2 = (bo2 - a2) / w2;
+  t[(int64_t)row * AMG_NM + lane] = (T)(q0 * r0 + q1 * r1 + q2 * r2);
 }
 
 // y = M A x (power iteration)
