@@ -977,9 +977,10 @@ __global__ void k_diagW(int n, const int32_t *diag_pos, int64_t nnzb, const doub
 
 // K <- W K W with Dirichlet rows/columns replaced by the identity
 __global__ void __launch_bounds__(VMS_BLOCK)
-k_scale_blocks(int n, int64_t nnzb, int SW, const int32_t *col, const int32_t *diag_pos, const uint8_t *dir,
-               const double *W, double *A, double *B, double *C, double *D, float *A32, float *B32,
-               float *C32, float *D32) {
+k_scale_blocks(int n, int64_t nnzb, int SW, const int32_t *__restrict__ col, const int32_t *__restrict__ diag_pos,
+               const uint8_t *__restrict__ dir, const double *__restrict__ W, double *__restrict__ A,
+               double *__restrict__ B, double *__restrict__ C, double *__restrict__ D, float *__restrict__ A32,
+               float *__restrict__ B32, float *__restrict__ C32, float *__restrict__ D32) {
   const int lane = threadIdx.x & 15;
   const int row = blockIdx.x * 16 + (threadIdx.x >> 4);
   if (row >= n) return;
@@ -991,24 +992,45 @@ k_scale_blocks(int n, int64_t nnzb, int SW, const int32_t *col, const int32_t *d
     const uint8_t *dj = dir + 4 * (int64_t)j;
     const double *Wj = W + 4 * (int64_t)j;
     const bool same = (b == bd);
-    for (int r = 0; r < 3; ++r)
-      for (int c = 0; c < 3; ++c) {
-        const int64_t k = (3 * r + c) * nnzb + b;
-        double val = (di[r] || dj[c]) ? ((same && r == c) ? 1.0 : 0.0) : A[k] * Wi[r] * Wj[c];
-        A[k] = val;
-        if (A32) A32[k] = (float)val;
-      }
+    // every value of the block is loaded before any is stored
+    double va[9], vb[3], vc[3];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) va[q] = A[q * nnzb + b];
+#pragma unroll
     for (int r = 0; r < 3; ++r) {
-      const int64_t k = r * nnzb + b;
-      double vb = (di[r] || dj[3]) ? 0.0 : B[k] * Wi[r] * Wj[3];
-      double vc = (di[3] || dj[r]) ? 0.0 : C[k] * Wi[3] * Wj[r];
-      B[k] = vb;
-      C[k] = vc;
-      if (B32) { B32[k] = (float)vb; C32[k] = (float)vc; }
+      vb[r] = B[r * nnzb + b];
+      vc[r] = C[r * nnzb + b];
     }
-    double vd = (di[3] || dj[3]) ? (same ? 1.0 : 0.0) : D[b] * Wi[3] * Wj[3];
+    double vd = D[b];
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+        va[3 * r + c] = (di[r] || dj[c]) ? ((same && r == c) ? 1.0 : 0.0) : va[3 * r + c] * Wi[r] * Wj[c];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      vb[r] = (di[r] || dj[3]) ? 0.0 : vb[r] * Wi[r] * Wj[3];
+      vc[r] = (di[3] || dj[r]) ? 0.0 : vc[r] * Wi[3] * Wj[r];
+    }
+    vd = (di[3] || dj[3]) ? (same ? 1.0 : 0.0) : vd * Wi[3] * Wj[3];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) A[q * nnzb + b] = va[q];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      B[r * nnzb + b] = vb[r];
+      C[r * nnzb + b] = vc[r];
+    }
     D[b] = vd;
-    if (D32) D32[b] = (float)vd;
+    if (A32) {
+#pragma unroll
+      for (int q = 0; q < 9; ++q) A32[q * nnzb + b] = (float)va[q];
+#pragma unroll
+      for (int r = 0; r < 3; ++r) {
+        B32[r * nnzb + b] = (float)vb[r];
+        C32[r * nnzb + b] = (float)vc[r];
+      }
+      D32[b] = (float)vd;
+    }
   }
 }
 
