@@ -1288,21 +1288,58 @@ k_shat_form(int n, int W, const int32_t *__restrict__ col, const int32_t *__rest
     }
     return lo;
   };
-  for (int kk = 0; kk < W; ++kk) {
-    const int64_t bik = (int64_t)W * row + kk;
-    const double c0 = C[bik], c1 = C[nnzb + bik], c2 = C[2 * nnzb + bik];
-    if (c0 == 0.0 && c1 == 0.0 && c2 == 0.0) continue;   // padding slot, or no coupling
-    const int k = col[bik];
-    const int64_t dk = diag_pos[k];
+  if (W == 16) {
+    // lane kk forms the weights C_ik,c / A_kk,cc of neighbour slot kk (all sixteen at once); the
+    // slots are then taken in order, each lane holding block (k, lane) of row k, and the next
+    // slot's blocks are requested before this slot's accumulation
+    const int64_t bi = (int64_t)W * row + lane;
+    const double c0 = C[bi], c1 = C[nnzb + bi], c2 = C[2 * nnzb + bi];
+    const bool use = !(c0 == 0.0 && c1 == 0.0 && c2 == 0.0);   // padding slot, or no coupling
+    const int kme = col[bi];
+    const int64_t dk = diag_pos[kme];
     const double a0 = A[dk], a1 = A[4 * nnzb + dk], a2 = A[8 * nnzb + dk];
-    const double w0 = (a0 != 0.0) ? c0 / a0 : 0.0, w1 = (a1 != 0.0) ? c1 / a1 : 0.0, w2 = (a2 != 0.0) ? c2 / a2 : 0.0;
-    for (int l = lane; l < W; l += 16) {
-      const int64_t bkj = (int64_t)W * k + l;
-      const double v = w0 * B[bkj] + w1 * B[nnzb + bkj] + w2 * B[2 * nnzb + bkj];
+    const double w0m = (a0 != 0.0) ? c0 / a0 : 0.0, w1m = (a1 != 0.0) ? c1 / a1 : 0.0;
+    const double w2m = (a2 != 0.0) ? c2 / a2 : 0.0;
+    const unsigned long long usem = __ballot(use);
+    const int gl = (threadIdx.x & 63) & ~15;   // first lane of this row's sixteen
+    auto fetch = [&](int kk, double &b0, double &b1, double &b2, int &j) {
+      const int k = __shfl(kme, gl + kk, 64);
+      const int64_t bkj = (int64_t)W * k + lane;
+      b0 = B[bkj]; b1 = B[nnzb + bkj]; b2 = B[2 * nnzb + bkj];
+      j = col[bkj];
+    };
+    double nb0 = 0.0, nb1 = 0.0, nb2 = 0.0;
+    int nj = 0;
+    fetch(0, nb0, nb1, nb2, nj);
+    for (int kk = 0; kk < W; ++kk) {
+      const double b0 = nb0, b1 = nb1, b2 = nb2;
+      const int j = nj;
+      if (kk + 1 < W) fetch(kk + 1, nb0, nb1, nb2, nj);
+      const double w0 = __shfl(w0m, gl + kk, 64), w1 = __shfl(w1m, gl + kk, 64), w2 = __shfl(w2m, gl + kk, 64);
+      if (!((usem >> (gl + kk)) & 1ull)) continue;
+      const double v = w0 * b0 + w1 * b1 + w2 * b2;
       if (v != 0.0) {
-        const int j = col[bkj];
         if (j == row) dacc[g] -= v;
         else acc[g][slot(j)] -= v;
+      }
+    }
+  } else {
+    for (int kk = 0; kk < W; ++kk) {
+      const int64_t bik = (int64_t)W * row + kk;
+      const double c0 = C[bik], c1 = C[nnzb + bik], c2 = C[2 * nnzb + bik];
+      if (c0 == 0.0 && c1 == 0.0 && c2 == 0.0) continue;   // padding slot, or no coupling
+      const int k = col[bik];
+      const int64_t dk = diag_pos[k];
+      const double a0 = A[dk], a1 = A[4 * nnzb + dk], a2 = A[8 * nnzb + dk];
+      const double w0 = (a0 != 0.0) ? c0 / a0 : 0.0, w1 = (a1 != 0.0) ? c1 / a1 : 0.0, w2 = (a2 != 0.0) ? c2 / a2 : 0.0;
+      for (int l = lane; l < W; l += 16) {
+        const int64_t bkj = (int64_t)W * k + l;
+        const double v = w0 * B[bkj] + w1 * B[nnzb + bkj] + w2 * B[2 * nnzb + bkj];
+        if (v != 0.0) {
+          const int j = col[bkj];
+          if (j == row) dacc[g] -= v;
+          else acc[g][slot(j)] -= v;
+        }
       }
     }
   }
