@@ -149,3 +149,28 @@ def test_lifted_tube_steps_with_amg_match_oracle(precision):
     tol = 1e-6 if mixed else 1e-7
     for k in ("u", "p", "v") if mixed else ("u", "p", "v", "du", "dp", "dv"):
         assert rel_err(st[k + "_n"].cpu().numpy(), so[k]) < tol, k
+
+
+@pytest.mark.parametrize("name,degree", [("strip", 3), ("tube", 2), ("cube", 4)])
+def test_vcycle_matches_oracle_at_bench_settings(name, degree):
+    """The bench's hierarchy shape (three levels, coarsest smoothing of degree 2) with the
+    smoothing degree of its workload (3 on the strip, 2 on the tube) and a higher one."""
+    mesh, mat, ti = _case(name)
+    opts = dict(max_levels=3, min_coarse=8, degree=degree, coarse_degree=2)
+    prob = V.Problem(mesh, mat, "cuda:0")
+    if mesh.fibre is not None:
+        prob.set_fibres(*synth.fibre_field(mesh, mesh.meta["fibre_rad"]))
+    info = prob.setup_amg(V.amg_opts(**opts))
+    K_o, A, Wv = _oracle_system(mesh, mat, ti, 21)
+    dv = mesh.dir_mask[:, 0:3].astype(bool)
+    lev = AMG.build(A, Wv, mesh.X, dv, max_levels=3, min_coarse=8, graph=AMG.mesh_graph(mesh.tets, mesh.n_nodes))
+    assert info["n_levels"] == len(lev) >= 2
+    K = upload_K(prob, K_o)
+    prob.prepare(K, torch.zeros(mesh.n_nodes, 4, dtype=torch.float64, device="cuda:0"))
+    r = np.random.default_rng(22).standard_normal((mesh.n_nodes, 3))
+    r[dv] = 0.0
+    z = prob.amg_apply(K, torch.from_numpy(r).cuda(), 0).cpu().numpy()
+    zo = AMG.vcycle(lev, r.ravel(), degree=degree, coarse_degree=2)
+    err = rel_err(z.ravel(), zo)
+    print(f"[amg {name} degree={degree}] V-cycle rel err {err:.2e}", flush=True)
+    assert err < 1e-11

@@ -229,6 +229,23 @@ def test_full_strip_time_steps_satisfy_oracle_equations(precision, relax):
         assert ratio <= 1.5e-8
 
 
+@pytest.mark.parametrize("precision", [V.FP64, V.MIXED])
+def test_full_strip_time_steps_with_the_bench_options_satisfy_oracle_equations(precision):
+    """The same strip with the bench's strip options: CG at the A-levels preconditioned by the
+    multigrid (three levels, Chebyshev degree 3), the Schur level by CG steps on S^ plus the
+    pressure-mass term."""
+    mesh, mat, ti = synth.strip_case(200)
+    prob = _problem(mesh, mat)
+    prob.setup_amg(V.amg_opts(max_levels=3, degree=3))
+    sopts = V.solver_opts(rtol=1e-8, precision=precision, a_krylov=V.AK_CG, cg_symmetrise=0, a_prec=V.APC_AMG,
+                          schur_mass=1.0, shat_method=V.SHAT_CG)
+    states = _gpu_steps(prob, mesh, ti, 3, sopts, tol_abs=1e-15)
+    for s in (1, 2):
+        ratio = _oracle_residual_ratio(mesh, mat, ti, s, states[s], states[s + 1])
+        print(f"[strip200 multigrid] precision={precision} step {s} oracle |R|/|R0| = {ratio:.3e}", flush=True)
+        assert ratio <= 1.5e-8
+
+
 def _adjoint_vs_fd(mesh, mat, ti, n_steps, sel, params, theta0, seed, sopts, nopts, rel, h_rel=None, amg=False):
     """J = 1/2 ||u_sel - u_target||^2 with u_target from a forward run at seeded, perturbed
     parameters; the autograd gradient against central differences (step h_rel[k] relative,
