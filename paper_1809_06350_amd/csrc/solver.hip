@@ -1081,8 +1081,28 @@ __device__ __forceinline__ double shat_row_dot(int W2, const int32_t *__restrict
 template <typename T, int LPR, bool OFF, int W2F>
 __global__ void __launch_bounds__(VMS_BLOCK)
 k_shat_spmv(int n, int W2rt, const int32_t *__restrict__ sc, const int16_t *__restrict__ so, const T *__restrict__ S,
-            const T *__restrict__ Sd, const T *__restrict__ x, T *y, const int *done) {
+            const T *__restrict__ Sd, const T *__restrict__ x, T *y, const int *done, const double *rpa,
+            const double *rpb, int nred, double *rtot) {
   if (done && *done) return;
+  if (rpa && blockIdx.x == 0) {
+    // the totals of the previous CG step's two partial sums (fixed order), for the next vector step
+    __shared__ double sm[2][VMS_BLOCK / 64];
+    double ta = 0.0, tb = 0.0;
+    for (int q = threadIdx.x; q < nred; q += VMS_BLOCK) {
+      ta += rpa[q];
+      tb += rpb[q];
+    }
+    ta = wave_sum(ta);
+    tb = wave_sum(tb);
+    if ((threadIdx.x & 63) == 0) { sm[0][threadIdx.x >> 6] = ta; sm[1][threadIdx.x >> 6] = tb; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double a = 0.0, b = 0.0;
+      for (int q = 0; q < VMS_BLOCK / 64; ++q) { a += sm[0][q]; b += sm[1][q]; }
+      rtot[0] = a;
+      rtot[1] = b;
+    }
+  }
   constexpr int RPB = VMS_BLOCK / LPR, PER = 64 / LPR;
   const int W2 = W2F ? W2F : W2rt;
   const int lane = threadIdx.x % LPR;
@@ -1110,23 +1130,30 @@ k_shat_spmv(int n, int W2rt, const int32_t *__restrict__ sc, const int16_t *__re
   if (act && lane == 0) y[row] = (T)a;
 }
 
+// y = S^ x; with rpa, workgroup 0 also writes the totals of the partials rpa[0..nred) and
+// rpb[0..nred) to rtot[0..1] (the next pipelined CG step reads them instead of the partials).
 template <typename T>
 void launch_shat_spmv(hipStream_t s, const vms_mesh *mesh, const T *S, const T *Sd, const T *x, T *y,
-                      const int *done) {
+                      const int *done, const double *rpa = nullptr, const double *rpb = nullptr, int nred = 0,
+                      double *rtot = nullptr) {
   constexpr int LPR = sizeof(T) == 4 ? 8 : 16;
   const int n = mesh->n_nodes, W2 = mesh->shat_width;
   const dim3 g((n + VMS_BLOCK / LPR - 1) / (VMS_BLOCK / LPR)), b(VMS_BLOCK);
   const bool off = mesh->shat_off != nullptr;
   if (W2 == 64) {
     if (off)
-      hipLaunchKernelGGL((k_shat_spmv<T, LPR, true, 64>), g, b, 0, s, n, W2, mesh->shat_col, mesh->shat_off, S, Sd, x, y, done);
+      hipLaunchKernelGGL((k_shat_spmv<T, LPR, true, 64>), g, b, 0, s, n, W2, mesh->shat_col, mesh->shat_off, S, Sd,
+                         x, y, done, rpa, rpb, nred, rtot);
     else
-      hipLaunchKernelGGL((k_shat_spmv<T, LPR, false, 64>), g, b, 0, s, n, W2, mesh->shat_col, mesh->shat_off, S, Sd, x, y, done);
+      hipLaunchKernelGGL((k_shat_spmv<T, LPR, false, 64>), g, b, 0, s, n, W2, mesh->shat_col, mesh->shat_off, S, Sd,
+                         x, y, done, rpa, rpb, nred, rtot);
   } else {
     if (off)
-      hipLaunchKernelGGL((k_shat_spmv<T, LPR, true, 0>), g, b, 0, s, n, W2, mesh->shat_col, mesh->shat_off, S, Sd, x, y, done);
+      hipLaunchKernelGGL((k_shat_spmv<T, LPR, true, 0>), g, b, 0, s, n, W2, mesh->shat_col, mesh->shat_off, S, Sd,
+                         x, y, done, rpa, rpb, nred, rtot);
     else
-      hipLaunchKernelGGL((k_shat_spmv<T, LPR, false, 0>), g, b, 0, s, n, W2, mesh->shat_col, mesh->shat_off, S, Sd, x, y, done);
+      hipLaunchKernelGGL((k_shat_spmv<T, LPR, false, 0>), g, b, 0, s, n, W2, mesh->shat_col, mesh->shat_off, S, Sd,
+                         x, y, done, rpa, rpb, nred, rtot);
   }
 }
 
@@ -1173,8 +1200,8 @@ k_pcg_start(int n, const T *__restrict__ dinv, PcgVec<T> V, double *pg, double *
   cg_block_sums2(g, d, pg + blockIdx.x, pd + blockIdx.x, sm);
 }
 
-// step i (nv = S^ m already formed): gamma_i, delta_i from the partials of
-// buffer i & 1; beta_i = gamma_i / gamma_{i-1}, alpha_i = gamma_i /
+// step i (nv = S^ m already formed, and gamma_i, delta_i, the totals of the
+// partials of buffer i & 1, in tot: the product kernel forms both); beta_i = gamma_i / gamma_{i-1}, alpha_i = gamma_i /
 // (delta_i - beta_i gamma_i / alpha_{i-1}) (step 0: beta = 0, alpha =
 // gamma / delta); z = nv + beta z, q = m + beta q, s = w + beta s,
 // p = u + beta p, x += alpha p; unless last: r -= alpha s, u -= alpha q,
@@ -1183,15 +1210,13 @@ k_pcg_start(int n, const T *__restrict__ dinv, PcgVec<T> V, double *pg, double *
 template <typename T>
 __global__ void __launch_bounds__(KRY_BLOCK)
 k_pcg_step(int n, int i, int last, T *x, PcgVec<T> V, const T *__restrict__ dinv, double *ctl, double *pg0,
-           double *pd0, double *pg1, double *pd1, int nbp, int *flag) {
+           double *pd0, double *pg1, double *pd1, const double *tot, int *flag) {
   __shared__ double sm[2][16];
   __shared__ int done0;
   if (threadIdx.x == 0) done0 = *flag;
   __syncthreads();
   if (done0) return;
-  const double *pg = (i & 1) ? pg1 : pg0, *pd = (i & 1) ? pd1 : pd0;
-  const double g = cg_sum_partials(pg, nbp, sm[0]);
-  const double d = cg_sum_partials(pd, nbp, sm[1]);
+  const double g = tot[0], d = tot[1];   // totals of the partials of buffer i & 1 (the product kernel's)
   double beta = 0.0, den = d;
   if (i > 0) {
     beta = g / ctl[(i - 1) & 1];
@@ -2112,7 +2137,7 @@ struct Nested {
     py = cv.take<T>(nn);
     if (o_->precond == VMS_PC_SIMPLE) dAinv = cv.take<T>(3 * nn);
     if (o_->shat_method == VMS_SHAT_CG && o_->shat_degree > 0) {
-      sctl = cv.take<double>(4 + 4 * VMS_MAX_RED_BLOCKS);
+      sctl = cv.take<double>(4 + 4 * VMS_MAX_RED_BLOCKS + 2);
       sflag = cv.take<int>(1);
       T **vs[9] = {&pv.r, &pv.u, &pv.w, &pv.m, &pv.nv, &pv.z, &pv.q, &pv.s, &pv.p};
       for (T **v : vs) *v = cv.take<T>(nn);
@@ -2154,18 +2179,17 @@ struct Nested {
     const int k = o->shat_degree;
     const int nbv = pcg_blocks(n);
     double *pg0 = sctl + 4, *pd0 = pg0 + VMS_MAX_RED_BLOCKS, *pg1 = pd0 + VMS_MAX_RED_BLOCKS,
-           *pd1 = pg1 + VMS_MAX_RED_BLOCKS;
+           *pd1 = pg1 + VMS_MAX_RED_BLOCKS, *tot = pd1 + VMS_MAX_RED_BLOCKS;
     const dim3 gp(spmv_grid(n)), bl(VMS_BLOCK), gv(nbv), bk(KRY_BLOCK);
-    auto product = [&](const T *xin, T *yout) {
-      launch_shat_spmv<T>(s, mesh, (const T *)Shat, (const T *)Shd, xin, yout, (const int *)sflag);
-    };
     hipLaunchKernelGGL(k_pcg_init<T>, dim3(grid1(n)), bl, 0, s, n, v, (const T *)sdinv, z, pv, sflag);
-    product(pv.u, pv.w);
+    launch_shat_spmv<T>(s, mesh, (const T *)Shat, (const T *)Shd, (const T *)pv.u, pv.w, (const int *)sflag);
     hipLaunchKernelGGL(k_pcg_start<T>, gv, bk, 0, s, n, (const T *)sdinv, pv, pg0, pd0);
     for (int i = 0; i < k; ++i) {
-      product(pv.m, pv.nv);
+      // the product also totals step i's partials (buffer i & 1) for the vector step
+      launch_shat_spmv<T>(s, mesh, (const T *)Shat, (const T *)Shd, (const T *)pv.m, pv.nv, (const int *)sflag,
+                          (i & 1) ? pg1 : pg0, (i & 1) ? pd1 : pd0, nbv, tot);
       hipLaunchKernelGGL(k_pcg_step<T>, gv, bk, 0, s, n, i, (int)(i == k - 1), z, pv, (const T *)sdinv, sctl, pg0,
-                         pd0, pg1, pd1, nbv, sflag);
+                         pd0, pg1, pd1, (const double *)tot, sflag);
     }
   }
 
