@@ -205,7 +205,9 @@ typedef struct {
   double schur_mass;     /* w >= 0: the Schur solve's right preconditioner gains the term
                             w (c M_p)^-1, M_p the lumped pressure mass matrix of the reference
                             configuration in the scaled variables and c = 1^T S 1 / 1^T M_p 1
-                            (one Schur product per solve).  A scaled mass matrix approximates S
+                            (one Schur product per solve; with shat_method VMS_SHAT_NONE c = 1,
+                            since GMRES iterates do not depend on the scale of a right
+                            preconditioner).  A scaled mass matrix approximates S
                             when A is stiffness-dominated (section 1); with shat_method
                             VMS_SHAT_NONE it is the whole preconditioner.  Krylov Schur step of
                             P_SCR only (precond != SIMPLE, schur_solve = VMS_SCHUR_KRYLOV).

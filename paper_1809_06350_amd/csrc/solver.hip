@@ -1569,14 +1569,14 @@ __global__ void __launch_bounds__(1024) k_mass_sums(int n, const T *__restrict__
 
 // minv_i = w / (c mlw_i) with c = sums[0] / sums[1] (the Rayleigh quotient of
 // S and the scaled lumped mass on the constant vector; c = 1 if it is not
-// positive), w on prescribed pressure dofs (their S row is the identity);
+// positive or sums is null), w on prescribed pressure dofs (their S row is the identity);
 // with pdiag, also pdiag = minv (+ diag(S^)^-1 when sdinv is given).
 template <typename T>
 __global__ void k_mass_inv(int n, const double *__restrict__ mlw, const double *__restrict__ sums,
                            const uint8_t *__restrict__ dir, double w, const T *sdinv, T *minv, T *pdiag) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  double c = sums[0] / sums[1];
+  double c = sums ? sums[0] / sums[1] : 1.0;
   if (!(c > 0.0) || !isfinite(c)) c = 1.0;
   const double m = mlw[i];
   const double v = (dir[4 * (int64_t)i + 3] || !(m > 0.0)) ? w : w / (c * m);
@@ -2395,17 +2395,24 @@ struct Nested {
       const dim3 g1(grid1(n)), bl(VMS_BLOCK);
       hipLaunchKernelGGL(k_mass_lumped<T>, g1, bl, 0, s, n, mesh->diag_pos, mesh->blk_src_ptr, mesh->blk_src, mesh->X,
                          mesh->tets, mesh->dir_mask, (const double *)K->W, mlw, mone);
-      // S 1 = D 1 - C A^-1 B 1 (one Schur product, its inner solve counted with the others)
-      hipLaunchKernelGGL((k_spmv_B<T, T>), dim3(spmv_grid(n)), bl, 0, s, n, nnzb, mesh->slot_width, mesh->col, B,
-                         (const T *)mone, xbar, (const T *)nullptr, 1.0, (const int *)nullptr);
-      int rc = solve_A(xbar, xt, true, false);   // no Schur level is running: no relaxation
-      if (rc) return rc;
-      hipLaunchKernelGGL((k_spmv_CD<T, T>), dim3(spmv_grid(n)), bl, 0, s, n, nnzb, mesh->slot_width, mesh->col, C, D,
-                         (const T *)xt, (const T *)mone, ms1, (const T *)nullptr, -1.0, 1.0, (const int *)nullptr);
-      hipLaunchKernelGGL(k_mass_sums<T>, dim3(1), dim3(1024), 0, s, n, (const T *)ms1, (const double *)mlw,
-                         mesh->dir_mask, msum);
+      // The fit c = 1^T S 1 / 1^T M 1 weighs the term against the S^ part.  Alone (VMS_SHAT_NONE) the
+      // term is the whole right preconditioner of the Schur level's GMRES, whose iterates do not
+      // depend on its scale: c = 1 there, and no Schur product is spent on it.
+      const bool fit = o->shat_method != VMS_SHAT_NONE;
+      if (fit) {
+        // S 1 = D 1 - C A^-1 B 1 (one Schur product, its inner solve counted with the others)
+        hipLaunchKernelGGL((k_spmv_B<T, T>), dim3(spmv_grid(n)), bl, 0, s, n, nnzb, mesh->slot_width, mesh->col, B,
+                           (const T *)mone, xbar, (const T *)nullptr, 1.0, (const int *)nullptr);
+        int rc = solve_A(xbar, xt, true, false);   // no Schur level is running: no relaxation
+        if (rc) return rc;
+        hipLaunchKernelGGL((k_spmv_CD<T, T>), dim3(spmv_grid(n)), bl, 0, s, n, nnzb, mesh->slot_width, mesh->col, C,
+                           D, (const T *)xt, (const T *)mone, ms1, (const T *)nullptr, -1.0, 1.0, (const int *)nullptr);
+        hipLaunchKernelGGL(k_mass_sums<T>, dim3(1), dim3(1024), 0, s, n, (const T *)ms1, (const double *)mlw,
+                           mesh->dir_mask, msum);
+      }
       const bool poly = o->shat_method != VMS_SHAT_NONE && o->shat_degree > 0;
-      hipLaunchKernelGGL(k_mass_inv<T>, g1, bl, 0, s, n, (const double *)mlw, (const double *)msum, mesh->dir_mask,
+      hipLaunchKernelGGL(k_mass_inv<T>, g1, bl, 0, s, n, (const double *)mlw, fit ? (const double *)msum : nullptr,
+                         mesh->dir_mask,
                          o->schur_mass, o->shat_method == VMS_SHAT_NONE ? (const T *)nullptr : (const T *)sdinv,
                          minv, poly ? (T *)nullptr : pdiag);
     }
