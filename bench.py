@@ -605,6 +605,10 @@ def main():
             "frac": kd["achieved"] / HBM_PEAK_GBS, "traffic": kd["traffic"],
             "bytes_per_launch": kd["bytes_per_launch"], "us_per_launch": kd["us_per_launch"],
             "timing": kd["timing"]}
+    if amg_info is not None:
+        roof["scope"] = ("the dominant kernel among the products the bench times (A-level and S^ products); with the "
+                         "multigrid on, its finest-level smoothing and residual kernels (k_amgf_*) take more of the "
+                         "step than the CG product (see the kernel trace of this workload)")
     # context: the rate of a plain streaming kernel on this device (1 GiB -> 1 GiB float64 copy-scale,
     # larger than the Infinity Cache), and the dominant kernel's measured HBM traffic per launch over
     # its duration against it
