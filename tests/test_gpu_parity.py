@@ -35,6 +35,8 @@ def case(name):
         mesh, mat, ti = synth.tube_case(2, 12, 4, dt=0.05, n_steps=20)
     elif name == "strip-hgo":
         mesh, mat, ti = STRIP()
+    elif name == "cube-fan":   # a 32-slot pattern (the fan's centre has 19 blocks in its row)
+        mesh, mat, ti = _asm_case_with_fan(True)
     else:
         raise KeyError(name)
     return mesh, mat, ti
@@ -176,7 +178,7 @@ def _prepared(prob, mesh, ti, disc, seed, mirror32=False, nonzero_rk=True, zero_
     return st, K, rhs, Ks, W * rd, W, (sn, it, sto)
 
 
-@pytest.mark.parametrize("name", ["cube-nu0499", "cube-incomp", "tube-hgo", "strip-hgo"])
+@pytest.mark.parametrize("name", ["cube-nu0499", "cube-incomp", "tube-hgo", "strip-hgo", "cube-fan"])
 def test_schur_hat_matches_oracle(problems, name):
     """S^ = D - C diag(A)^-1 B (section 4.2) of the oracle's scaled system, formed with scipy."""
     import scipy.sparse as sp
@@ -199,7 +201,7 @@ def test_schur_hat_matches_oracle(problems, name):
     assert rel_err(sdinv.cpu().numpy(), expect) < 1e-12
 
 
-@pytest.mark.parametrize("name", ["cube-nu0499", "tube-hgo", "strip-hgo"])
+@pytest.mark.parametrize("name", ["cube-nu0499", "tube-hgo", "strip-hgo", "cube-fan"])
 @pytest.mark.parametrize("fp32", [False, True])
 def test_shat_product_matches_oracle(problems, name, fp32):
     """y = S^ x by the product kernel of the Schur preconditioner's CG steps
