@@ -398,7 +398,7 @@ def test_predictor_literal_factors(problems):
         assert np.abs(st[k].cpu().numpy() - want).max() <= 1e-15 * np.abs(sn[k]).max(), k
 
 
-@pytest.mark.parametrize("name", ["cube-nu0499", "cube-incomp", "tube-hgo", "strip-hgo"])
+@pytest.mark.parametrize("name", ["cube-nu0499", "cube-incomp", "tube-hgo", "strip-hgo", "cube-fan"])
 @pytest.mark.parametrize("precision", [V.FP64, V.MIXED])
 @pytest.mark.parametrize("shat,shat_method", [(0, V.SHAT_CHEBYSHEV), (6, V.SHAT_CHEBYSHEV), (6, V.SHAT_CG)])
 def test_solve_reaches_requested_residual(problems, name, precision, shat, shat_method):
@@ -419,7 +419,7 @@ def test_solve_reaches_requested_residual(problems, name, precision, shat, shat_
     assert np.linalg.norm(xg - xo) <= 1e-5 * np.linalg.norm(xo)
 
 
-@pytest.mark.parametrize("name", ["cube-nu0499", "tube-hgo", "strip-hgo"])
+@pytest.mark.parametrize("name", ["cube-nu0499", "tube-hgo", "strip-hgo", "cube-fan"])
 @pytest.mark.parametrize("precision", [V.FP64, V.MIXED])
 @pytest.mark.parametrize("a_krylov,sym", [(V.AK_CG_INNER, 1), (V.AK_CG, 1), (V.AK_CG, 0)])
 def test_cg_levels_solve_matches_lu(problems, name, precision, a_krylov, sym):
