@@ -401,6 +401,10 @@ def main():
                     help="preconditioner of the A-levels: 3x3 block-Jacobi or the aggregation multigrid; auto = "
                          "block-Jacobi on the cube (mass-dominated A at dt = 1e-3), multigrid on the strip and tube")
     ap.add_argument("--amg-levels", type=int, default=3)
+    ap.add_argument("--amg-coarse-degree", type=int, default=None,
+                    help="Chebyshev degree of the multigrid's coarsest-level smoothing; default 4 on the tube "
+                         "(15 %% less time per step than 2; 8 and 16 are slower again), 2 elsewhere (4 and 8 "
+                         "change nothing on the strip)")
     ap.add_argument("--amg-degree", type=int, default=None,
                     help="Chebyshev degree of the multigrid's pre- and post-smoothing; default 3 on the strip "
                          "(5-7 %% less time per step than 2), 2 elsewhere (the tube's steps take more outer "
@@ -465,6 +469,8 @@ def main():
         args.shat_method = "none" if tube and args.schur_mass > 0.0 else "cg"
     if args.amg_degree is None:
         args.amg_degree = 3 if args.workload == "strip" else 2
+    if args.amg_coarse_degree is None:
+        args.amg_coarse_degree = 4 if args.workload == "tube" else 2
     if args.a_prec == "auto":
         args.a_prec = "bj" if args.workload == "cube" else "amg"
     if args.workload == "tube":
@@ -495,7 +501,8 @@ def main():
     amg_info = None
     if args.a_prec == "amg":
         t0 = time.perf_counter()
-        amg_info = prob.setup_amg(V.amg_opts(max_levels=args.amg_levels, degree=args.amg_degree))
+        amg_info = prob.setup_amg(V.amg_opts(max_levels=args.amg_levels, degree=args.amg_degree,
+                                             coarse_degree=args.amg_coarse_degree))
         amg_info["host_setup_s"] = time.perf_counter() - t0
         log(f"multigrid: levels {amg_info['n']} ({amg_info['host_setup_s']:.2f} s host set-up)")
     apc = V.APC_AMG if args.a_prec == "amg" else V.APC_BJ
