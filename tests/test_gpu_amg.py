@@ -151,12 +151,12 @@ def test_lifted_tube_steps_with_amg_match_oracle(precision):
         assert rel_err(st[k + "_n"].cpu().numpy(), so[k]) < tol, k
 
 
-@pytest.mark.parametrize("name,degree", [("strip", 3), ("tube", 2), ("cube", 4)])
-def test_vcycle_matches_oracle_at_bench_settings(name, degree):
-    """The bench's hierarchy shape (three levels, coarsest smoothing of degree 2) with the
-    smoothing degree of its workload (3 on the strip, 2 on the tube) and a higher one."""
+@pytest.mark.parametrize("name,degree,coarse", [("strip", 3, 2), ("tube", 2, 4), ("cube", 4, 2)])
+def test_vcycle_matches_oracle_at_bench_settings(name, degree, coarse):
+    """The bench's hierarchy shape (three levels) with the smoothing degrees of its workloads
+    (3 on the strip; 2, and 4 on the coarsest level, on the tube) and a higher one."""
     mesh, mat, ti = _case(name)
-    opts = dict(max_levels=3, min_coarse=8, degree=degree, coarse_degree=2)
+    opts = dict(max_levels=3, min_coarse=8, degree=degree, coarse_degree=coarse)
     prob = V.Problem(mesh, mat, "cuda:0")
     if mesh.fibre is not None:
         prob.set_fibres(*synth.fibre_field(mesh, mesh.meta["fibre_rad"]))
@@ -170,7 +170,7 @@ def test_vcycle_matches_oracle_at_bench_settings(name, degree):
     r = np.random.default_rng(22).standard_normal((mesh.n_nodes, 3))
     r[dv] = 0.0
     z = prob.amg_apply(K, torch.from_numpy(r).cuda(), 0).cpu().numpy()
-    zo = AMG.vcycle(lev, r.ravel(), degree=degree, coarse_degree=2)
+    zo = AMG.vcycle(lev, r.ravel(), degree=degree, coarse_degree=coarse)
     err = rel_err(z.ravel(), zo)
-    print(f"[amg {name} degree={degree}] V-cycle rel err {err:.2e}", flush=True)
+    print(f"[amg {name} degree={degree} coarse={coarse}] V-cycle rel err {err:.2e}", flush=True)
     assert err < 1e-11
