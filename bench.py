@@ -405,6 +405,10 @@ def main():
                     help="Chebyshev degree of the multigrid's coarsest-level smoothing; default 4 on the tube "
                          "(15 %% less time per step than 2; 8 and 16 are slower again), 2 elsewhere (4 and 8 "
                          "change nothing on the strip)")
+    ap.add_argument("--amg-mid-degree", type=int, default=None,
+                    help="Chebyshev degree of the multigrid's middle level (between the finest and the coarsest); "
+                         "default 4 on the tube (6 %% less time per step than the finest level's 2), 0 = the "
+                         "finest level's degree elsewhere (4 is slower on the strip)")
     ap.add_argument("--amg-degree", type=int, default=None,
                     help="Chebyshev degree of the multigrid's pre- and post-smoothing; default 3 on the strip "
                          "(5-7 %% less time per step than 2), 2 elsewhere (the tube's steps take more outer "
@@ -471,6 +475,8 @@ def main():
         args.amg_degree = 3 if args.workload == "strip" else 2
     if args.amg_coarse_degree is None:
         args.amg_coarse_degree = 4 if args.workload == "tube" else 2
+    if args.amg_mid_degree is None:
+        args.amg_mid_degree = 4 if args.workload == "tube" else 0
     if args.a_prec == "auto":
         args.a_prec = "bj" if args.workload == "cube" else "amg"
     if args.workload == "tube":
@@ -502,8 +508,11 @@ def main():
     if args.a_prec == "amg":
         t0 = time.perf_counter()
         amg_info = prob.setup_amg(V.amg_opts(max_levels=args.amg_levels, degree=args.amg_degree,
-                                             coarse_degree=args.amg_coarse_degree))
+                                             coarse_degree=args.amg_coarse_degree,
+                                             mid_degree=args.amg_mid_degree))
         amg_info["host_setup_s"] = time.perf_counter() - t0
+        amg_info["degrees"] = {"finest": args.amg_degree, "middle": args.amg_mid_degree or args.amg_degree,
+                               "coarsest": args.amg_coarse_degree}
         log(f"multigrid: levels {amg_info['n']} ({amg_info['host_setup_s']:.2f} s host set-up)")
     apc = V.APC_AMG if args.a_prec == "amg" else V.APC_BJ
     n, nnzb = mesh.n_nodes, int(prob.host["row_len"].sum())   # real blocks (slots: prob.nnzb)

@@ -531,6 +531,8 @@ typedef struct {
   int32_t min_coarse;     /* a level with at most this many nodes is the coarsest */
   int32_t degree;         /* Chebyshev degree of pre- and post-smoothing (1 .. 16) */
   int32_t coarse_degree;  /* Chebyshev degree on the coarsest level (1 .. 64) */
+  int32_t mid_degree;     /* Chebyshev degree on the levels between the finest and the coarsest
+                             (1 .. 16); 0 takes degree */
 } vms_amg_opts;
 
 typedef struct {

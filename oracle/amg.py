@@ -35,7 +35,8 @@ prolongator smoothing):
    the ratio ||D^-1 A x|| / ||x|| after 12 power steps from a SplitMix64 vector.
 6. V-cycle: degree-k pre-smoothing from zero, residual, restriction P^T,
    recursion, prolongation, degree-k post-smoothing; on the coarsest level
-   degree k_c smoothing from zero only.
+   degree k_c smoothing from zero only.  The levels between the finest and
+   the coarsest may take their own degree k_m in place of k.
 """
 from __future__ import annotations
 
@@ -302,19 +303,21 @@ def chebyshev(L, b: np.ndarray, x: np.ndarray | None, degree: int) -> np.ndarray
 
 
 def vcycle(levels, b: np.ndarray, degree: int = 2, coarse_degree: int = 8, lev: int = 0,
-           coarse_solve=None) -> np.ndarray:
+           coarse_solve=None, mid_degree: int = 0) -> np.ndarray:
     """One V-cycle for levels[lev].A x = b from x = 0.  coarse_solve(A, b)
-    replaces the coarsest smoothing when given (used by the pins)."""
+    replaces the coarsest smoothing when given (used by the pins).  The levels
+    between the finest and the coarsest smooth with mid_degree steps (0: degree)."""
     L = levels[lev]
     if lev == len(levels) - 1:
         if coarse_solve is not None:
             return coarse_solve(L.A, b)
         return chebyshev(L, b, None, coarse_degree)
-    x = chebyshev(L, b, None, degree)
+    k = degree if lev == 0 or mid_degree == 0 else mid_degree
+    x = chebyshev(L, b, None, k)
     r = b - L.A @ x
-    e = vcycle(levels, L.P.T @ r, degree, coarse_degree, lev + 1, coarse_solve)
+    e = vcycle(levels, L.P.T @ r, degree, coarse_degree, lev + 1, coarse_solve, mid_degree)
     x = x + L.P @ e
-    return chebyshev(L, b, x, degree)
+    return chebyshev(L, b, x, k)
 
 
 def pcg(A, b: np.ndarray, M, rtol: float, maxit: int = 1000):

@@ -86,7 +86,7 @@ class StepStats(C.Structure):
 
 class AmgOpts(C.Structure):
     _fields_ = [("max_levels", C.c_int32), ("min_coarse", C.c_int32), ("degree", C.c_int32),
-                ("coarse_degree", C.c_int32)]
+                ("coarse_degree", C.c_int32), ("mid_degree", C.c_int32)]
 
 
 class AmgInfo(C.Structure):

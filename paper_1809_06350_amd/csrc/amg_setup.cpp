@@ -163,7 +163,8 @@ extern "C" int vms_amg_create(int32_t n_nodes, int32_t slot_width, const int32_t
   *out = nullptr;
   if (n_nodes <= 0 || slot_width <= 0 || !row_len || !col || !X || !dir_mask || !opts) return VMS_ERR_ARG;
   if (opts->max_levels < 2 || opts->max_levels > VMS_AMG_MAX_LEVELS || opts->min_coarse < 0 ||
-      opts->degree < 1 || opts->degree > 16 || opts->coarse_degree < 1 || opts->coarse_degree > 64)
+      opts->degree < 1 || opts->degree > 16 || opts->coarse_degree < 1 || opts->coarse_degree > 64 ||
+      opts->mid_degree < 0 || opts->mid_degree > 16)
     return VMS_ERR_ARG;
   if ((int64_t)slot_width * n_nodes >= ((int64_t)1 << 31)) return VMS_ERR_ARG;
   for (int32_t i = 0; i < n_nodes; ++i) {
@@ -338,6 +339,7 @@ extern "C" int vms_amg_create(int32_t n_nodes, int32_t slot_width, const int32_t
   a->dev.n_levels = a->n_levels;
   a->dev.degree = opts->degree;
   a->dev.coarse_degree = opts->coarse_degree;
+  a->dev.mid_degree = opts->mid_degree > 0 ? opts->mid_degree : opts->degree;
   a->dev.uploaded = 0;
   a->dev_bytes = lay.off + 256;
   *out = a;

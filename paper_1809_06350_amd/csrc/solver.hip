@@ -1998,7 +1998,8 @@ struct AmgSys {
       return;
     }
     const vms_amg_level_dev &c = h->lev[l + 1];
-    smooth(s, l, b, x, true, h->degree, done);
+    const int deg = l == 0 ? h->degree : h->mid_degree;
+    smooth(s, l, b, x, true, deg, done);
     const dim3 bl(VMS_BLOCK);
     constexpr bool F32 = std::is_same<T, float>::value;
     using TP = typename std::conditional<F32, float, double>::type;
@@ -2019,7 +2020,7 @@ struct AmgSys {
     else
       hipLaunchKernelGGL((k_amg_prolong<T, TP, AMG_NM>), gp, bl, 0, s, lv.n, lv.agg, P, (const double *)nullptr,
                          (const T *)xv[l + 1], x, done);
-    smooth(s, l, b, x, false, h->degree, done);
+    smooth(s, l, b, x, false, deg, done);
   }
 };
 

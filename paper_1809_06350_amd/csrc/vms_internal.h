@@ -43,7 +43,7 @@ struct vms_amg_level_dev {
   const int32_t *gptr = nullptr, *gsrc = nullptr;   // Galerkin lists of the next level's blocks
 };
 struct vms_amg_dev {
-  int n_levels = 0, degree = 2, coarse_degree = 8, uploaded = 0, device = -1;
+  int n_levels = 0, degree = 2, coarse_degree = 8, mid_degree = 2, uploaded = 0, device = -1;
   vms_amg_level_dev lev[VMS_AMG_MAX_LEVELS];
 };
 const vms_amg_dev *vms_amg_device(const vms_amg *amg);

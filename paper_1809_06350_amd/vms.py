@@ -46,8 +46,8 @@ def solver_opts(rtol=1e-8, atol=1e-50, maxit=200, rtol_A=5e-5, atol_A=1e-50, max
                         cg_symmetrise, shat_method, schur_solve, relax_inner, schur_mass, a_prec, 0)
 
 
-def amg_opts(max_levels=3, min_coarse=64, degree=2, coarse_degree=2) -> L.AmgOpts:
-    return L.AmgOpts(max_levels, min_coarse, degree, coarse_degree)
+def amg_opts(max_levels=3, min_coarse=64, degree=2, coarse_degree=2, mid_degree=0) -> L.AmgOpts:
+    return L.AmgOpts(max_levels, min_coarse, degree, coarse_degree, mid_degree)
 
 
 def newton_opts(tol_R=1e-8, tol_A=1e-50, l_max=20, rk_corr=1, eps_diag=1e-15, dir_lift=0) -> L.NewtonOpts:

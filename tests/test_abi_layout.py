@@ -21,6 +21,7 @@ STRUCTS = {
     "vms_solve_stats": L.SolveStats,
     "vms_newton_opts": L.NewtonOpts,
     "vms_step_stats": L.StepStats,
+    "vms_amg_opts": L.AmgOpts,
 }
 
 

@@ -108,7 +108,8 @@ def test_amg_create_rejects_bad_input():
     dm = np.ascontiguousarray(mesh.dir_mask, np.uint8)
     obj = C.c_void_p()
     for opts in (V.amg_opts(max_levels=1), V.amg_opts(max_levels=9), V.amg_opts(degree=0),
-                 V.amg_opts(coarse_degree=65), V.amg_opts(min_coarse=-1)):
+                 V.amg_opts(coarse_degree=65), V.amg_opts(min_coarse=-1),
+                 V.amg_opts(mid_degree=-1), V.amg_opts(mid_degree=17)):
         assert lib.vms_amg_create(mesh.n_nodes, h["W"], h["row_len"].ctypes.data, h["col"].ctypes.data,
                                   X.ctypes.data, dm.ctypes.data, C.byref(opts), C.byref(obj)) == -1
     bad = h["col"].copy()

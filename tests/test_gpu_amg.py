@@ -151,12 +151,13 @@ def test_lifted_tube_steps_with_amg_match_oracle(precision):
         assert rel_err(st[k + "_n"].cpu().numpy(), so[k]) < tol, k
 
 
-@pytest.mark.parametrize("name,degree,coarse", [("strip", 3, 2), ("tube", 2, 4), ("cube", 4, 2)])
-def test_vcycle_matches_oracle_at_bench_settings(name, degree, coarse):
+@pytest.mark.parametrize("name,degree,coarse,mid", [("strip", 3, 2, 0), ("tube", 2, 4, 4), ("cube", 4, 2, 0),
+                                                     ("cube", 2, 3, 5)])
+def test_vcycle_matches_oracle_at_bench_settings(name, degree, coarse, mid):
     """The bench's hierarchy shape (three levels) with the smoothing degrees of its workloads
-    (3 on the strip; 2, and 4 on the coarsest level, on the tube) and a higher one."""
+    (3 on the strip; 2 on the finest level of the tube and 4 below it) and other ones."""
     mesh, mat, ti = _case(name)
-    opts = dict(max_levels=3, min_coarse=8, degree=degree, coarse_degree=coarse)
+    opts = dict(max_levels=3, min_coarse=8, degree=degree, coarse_degree=coarse, mid_degree=mid)
     prob = V.Problem(mesh, mat, "cuda:0")
     if mesh.fibre is not None:
         prob.set_fibres(*synth.fibre_field(mesh, mesh.meta["fibre_rad"]))
@@ -165,12 +166,13 @@ def test_vcycle_matches_oracle_at_bench_settings(name, degree, coarse):
     dv = mesh.dir_mask[:, 0:3].astype(bool)
     lev = AMG.build(A, Wv, mesh.X, dv, max_levels=3, min_coarse=8, graph=AMG.mesh_graph(mesh.tets, mesh.n_nodes))
     assert info["n_levels"] == len(lev) >= 2
+    assert mid == 0 or len(lev) == 3   # a middle level exists
     K = upload_K(prob, K_o)
     prob.prepare(K, torch.zeros(mesh.n_nodes, 4, dtype=torch.float64, device="cuda:0"))
     r = np.random.default_rng(22).standard_normal((mesh.n_nodes, 3))
     r[dv] = 0.0
     z = prob.amg_apply(K, torch.from_numpy(r).cuda(), 0).cpu().numpy()
-    zo = AMG.vcycle(lev, r.ravel(), degree=degree, coarse_degree=coarse)
+    zo = AMG.vcycle(lev, r.ravel(), degree=degree, coarse_degree=coarse, mid_degree=mid)
     err = rel_err(z.ravel(), zo)
-    print(f"[amg {name} degree={degree} coarse={coarse}] V-cycle rel err {err:.2e}", flush=True)
+    print(f"[amg {name} degree={degree} coarse={coarse} mid={mid}] V-cycle rel err {err:.2e}", flush=True)
     assert err < 1e-11

@@ -198,7 +198,7 @@ def test_full_tube_time_steps_satisfy_oracle_equations():
     equations (relative to the internal force)."""
     mesh, mat, ti = synth.tube_case(8, 256, 160, dt=0.05, n_steps=20, stretch=1.5)
     prob = _problem(mesh, mat)
-    prob.setup_amg(V.amg_opts(coarse_degree=4))   # the bench's tube hierarchy
+    prob.setup_amg(V.amg_opts(coarse_degree=4, mid_degree=4))   # the bench's tube hierarchy
     sopts = V.solver_opts(rtol=1e-8, precision=V.MIXED, a_krylov=V.AK_CG, cg_symmetrise=0, a_prec=V.APC_AMG,
                           schur_mass=1.0, shat_method=V.SHAT_NONE)
     states = _gpu_steps(prob, mesh, ti, 2, sopts, tol_abs=1e-15, lift=1)

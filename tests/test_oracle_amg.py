@@ -194,7 +194,8 @@ def test_power_estimate_bounds_the_top_eigenvalue():
     assert 0.95 * 1.3 <= est <= 1.3
 
 
-def test_vcycle_is_symmetric_positive_definite():
+@pytest.mark.parametrize("mid_degree", [0, 3])
+def test_vcycle_is_symmetric_positive_definite(mid_degree):
     mesh, mat, _ = synth.tube_case(2, 16, 8)
     A, W = _scaled_A(mesh, mat, 0.05)
     lev = AMG.build(A, W, mesh.X, mesh.dir_mask[:, 0:3].astype(bool), max_levels=3, min_coarse=10,
@@ -202,9 +203,31 @@ def test_vcycle_is_symmetric_positive_definite():
     assert len(lev) >= 2
     rng = np.random.default_rng(8)
     a, b = rng.standard_normal((2, A.shape[0]))
-    Va, Vb = AMG.vcycle(lev, a), AMG.vcycle(lev, b)
+    Va, Vb = AMG.vcycle(lev, a, mid_degree=mid_degree), AMG.vcycle(lev, b, mid_degree=mid_degree)
     assert abs(Va @ b - a @ Vb) <= 1e-12 * np.linalg.norm(Va) * np.linalg.norm(b)
     assert Va @ a > 0.0 and Vb @ b > 0.0
+
+
+def test_middle_level_smoothing_tends_to_the_two_grid_cycle():
+    """With an exact solve on the coarsest of three levels, raising the middle level's degree
+    makes its sub-cycle an ever better solve with that level's operator: the three-level cycle
+    tends to the two-level one whose second level is solved exactly, while the finest level keeps
+    its own degree."""
+    mesh, mat, _ = synth.tube_case(2, 16, 8)
+    A, W = _scaled_A(mesh, mat, 0.05)
+    lev = AMG.build(A, W, mesh.X, mesh.dir_mask[:, 0:3].astype(bool), max_levels=3, min_coarse=10,
+                    graph=AMG.mesh_graph(mesh.tets, mesh.n_nodes))
+    assert len(lev) == 3
+    exact = lambda Ac, r: spla.spsolve(Ac.tocsc(), r)
+    b = np.random.default_rng(9).standard_normal(A.shape[0])
+    b[mesh.dir_mask[:, 0:3].astype(bool).ravel()] = 0.0
+    two = AMG.vcycle(lev[:2], b, degree=2, coarse_solve=exact)
+    gap = [np.linalg.norm(AMG.vcycle(lev, b, degree=2, coarse_solve=exact, mid_degree=k) - two)
+           / np.linalg.norm(two) for k in (1, 2, 4, 8, 16)]
+    assert all(g1 < g0 for g0, g1 in zip(gap, gap[1:])), gap
+    assert gap[-1] < 1e-3 * gap[0], gap
+    # mid_degree equal to degree is the plain cycle
+    np.testing.assert_array_equal(AMG.vcycle(lev, b, degree=2, mid_degree=2), AMG.vcycle(lev, b, degree=2))
 
 
 def test_amg_cg_reaches_the_lu_solution_faster_than_block_jacobi():
