@@ -18,9 +18,10 @@
 // Layouts.  Finest level: the mesh's fixed-slot 3x3 blocks (entry-major),
 // vectors [n][3], 16 lanes per row as in the block products.  Coarse levels:
 // CSR of 10x10 blocks stored block-major ([nnzb][10][10], row-major blocks),
-// vectors [n][10]; ten lanes per row, lane r owns component r, 25 rows per
-// 256-thread workgroup; the block-diagonal solve exchanges the row's ten
-// sums through LDS.
+// vectors [n][10]; the products take one wavefront per row (each lane owns two
+// adjacent entries of every block, so the blocks are read contiguously), the
+// row's ten sums go through LDS to the ten lanes that apply the 10x10
+// block-diagonal inverse.
 #pragma once
 
 #define AMG_NM 10
@@ -204,21 +205,56 @@ k_amgf_dapply(int n, int64_t nnzb, int W, const int32_t *__restrict__ col, const
   y[3 * (int64_t)row + lane] = (T)bj3_comp(Minv + 9 * (int64_t)row, lane, a0, a1, a2);
 }
 
-// ---- coarse levels (10x10 CSR blocks, ten lanes per row) ------------------------------------
+// ---- coarse levels (10x10 CSR blocks) -----------------------------------------------------
+// Block-row products: one wavefront per row.  Lane j < 50 owns the entries 2j and 2j+1 of every
+// block of the row (block row j / 5, columns 2 (j % 5) and 2 (j % 5) + 1), so each block is read
+// as 800 (FP64) or 400 (FP32) contiguous bytes in one load per lane, and the row's blocks are
+// contiguous in CSR order.  The five partial sums of a block row are added in lane order
+// through LDS; lanes 0..9 then finish the row's ten components.
 
+template <typename T> struct Pair2;
+template <> struct Pair2<double> { using V = double2; };
+template <> struct Pair2<float> { using V = float2; };
+
+// lane j's partial of (A x) over the row's blocks; j < 50, A and x 2-element aligned
 template <typename T>
-__device__ __forceinline__ double amgc_row(const int32_t *__restrict__ ptr, const int32_t *__restrict__ col,
-                                           const T *__restrict__ A, const T *__restrict__ x, int row, int rr) {
+__device__ __forceinline__ double amgc_row_part(const int32_t *__restrict__ ptr, const int32_t *__restrict__ col,
+                                                const T *__restrict__ A, const T *__restrict__ x, int row, int j) {
+  using V = typename Pair2<T>::V;
+  const int c = 2 * (j % 5);
+  const int k0 = ptr[row], k1 = ptr[row + 1];
   double acc = 0.0;
-  const int k1 = ptr[row + 1];
-  for (int k = ptr[row]; k < k1; ++k) {
-    const T *a = A + (int64_t)k * (AMG_NM * AMG_NM) + rr * AMG_NM;
-    const T *xv = x + (int64_t)col[k] * AMG_NM;
-#pragma unroll
-    for (int c = 0; c < AMG_NM; ++c) acc += ld(a, c) * ld(xv, c);
+#pragma unroll 4
+  for (int k = k0; k < k1; ++k) {
+    const V a = *(const V *)(A + (int64_t)k * (AMG_NM * AMG_NM) + 2 * j);
+    const V xv = *(const V *)(x + (int64_t)col[k] * AMG_NM + c);
+    acc += (double)a.x * (double)xv.x;
+    acc += (double)a.y * (double)xv.y;
   }
   return acc;
 }
+
+// The ten block-row sums of (A x) for the wavefront's row into sw[0..9].  Every thread of the
+// workgroup calls it (two barriers); rows past n give zeros.
+template <typename T>
+__device__ __forceinline__ void amgc_row_sums(const int32_t *__restrict__ ptr, const int32_t *__restrict__ col,
+                                              const T *__restrict__ A, const T *__restrict__ x, int row, bool act,
+                                              int j, double *sp, double *sw) {
+  sp[j] = act && j < 5 * AMG_NM ? amgc_row_part(ptr, col, A, x, row, j) : 0.0;
+  __syncthreads();
+  if (j < AMG_NM) sw[j] = sp[5 * j] + sp[5 * j + 1] + sp[5 * j + 2] + sp[5 * j + 3] + sp[5 * j + 4];
+  __syncthreads();
+}
+
+#define AMG_WROWS 4   // rows (wavefronts) per 256-thread workgroup of the block-row products
+inline int amg_wgrid(int n) { return (n + AMG_WROWS - 1) / AMG_WROWS; }
+
+// the wavefront's row and lane: the row index is made wave-uniform for the CSR bounds
+#define AMGC_WAVE_PROLOGUE                                                        \
+  const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));       \
+  const int j = threadIdx.x & 63;                                                \
+  const int row = blockIdx.x * AMG_WROWS + wv;                                   \
+  const bool act = row < n;
 
 template <typename T>
 __device__ __forceinline__ double amgc_dapply(const T *__restrict__ Dinv, int row, int rr, const double *w) {
@@ -229,6 +265,7 @@ __device__ __forceinline__ double amgc_dapply(const T *__restrict__ Dinv, int ro
   return z;
 }
 
+// ten lanes per row, 25 rows per 256-thread workgroup (no product)
 template <typename T>
 __global__ void __launch_bounds__(256)
 k_amgc_cheb0(int n, const T *__restrict__ Dinv, const T *__restrict__ b, T *x, T *r, T *d, const double *lam,
@@ -255,22 +292,18 @@ __global__ void __launch_bounds__(256)
 k_amgc_cheb(int n, const int32_t *__restrict__ ptr, const int32_t *__restrict__ col, const T *__restrict__ A,
             const T *__restrict__ Dinv, const T *__restrict__ b, const T *__restrict__ v, T *dn, T *r, T *x,
             const double *lam, int k, int pending, const int *done) {
-  __shared__ double sm[AMG_CROWS][AMG_NM];
+  __shared__ double sp[AMG_WROWS][64], sw[AMG_WROWS][AMG_NM];
   if (amg_done(done)) return;
-  const int t = threadIdx.x, lr = t / AMG_NM, row = blockIdx.x * AMG_CROWS + lr, rr = t % AMG_NM;
-  const bool act = t < AMG_CROWS * AMG_NM && row < n;
-  const int64_t o = (int64_t)(act ? row : 0) * AMG_NM + rr;
-  double w = 0.0;
-  if (act) {
-    const double av = amgc_row(ptr, col, A, v, row, rr);
-    w = MODE == 0 ? ld(b, o) - av : av;
-  }
-  if (t < AMG_CROWS * AMG_NM) sm[lr][rr] = w;
-  __syncthreads();
-  if (!act) return;
+  AMGC_WAVE_PROLOGUE
+  amgc_row_sums(ptr, col, A, v, row, act, j, sp[wv], sw[wv]);
+  if (!act || j >= AMG_NM) return;
+  const int64_t o = (int64_t)row * AMG_NM + j;
+  double w[AMG_NM];
+#pragma unroll
+  for (int c = 0; c < AMG_NM; ++c) w[c] = MODE == 0 ? ld(b, (int64_t)row * AMG_NM + c) - sw[wv][c] : sw[wv][c];
   double th, c1, c2;
   amg_cheb(*lam, k, th, c1, c2);
-  const double z = amgc_dapply(Dinv, row, rr, sm[lr]);
+  const double z = amgc_dapply(Dinv, row, j, w);
   if (MODE == 0) {
     r[o] = (T)z;
     dn[o] = (T)(z / th);
@@ -289,31 +322,27 @@ template <typename T, typename TP>
 __global__ void __launch_bounds__(256)
 k_amgc_resid_t(int n, const int32_t *__restrict__ ptr, const int32_t *__restrict__ col, const T *__restrict__ A,
                const T *__restrict__ b, const T *__restrict__ x, const TP *__restrict__ Q, T *t, const int *done) {
-  __shared__ double sm[AMG_CROWS][AMG_NM];
+  __shared__ double sp[AMG_WROWS][64], sw[AMG_WROWS][AMG_NM];
   if (amg_done(done)) return;
-  const int th = threadIdx.x, lr = th / AMG_NM, row = blockIdx.x * AMG_CROWS + lr, rr = th % AMG_NM;
-  const bool act = th < AMG_CROWS * AMG_NM && row < n;
-  const int64_t o = (int64_t)(act ? row : 0) * AMG_NM + rr;
-  if (th < AMG_CROWS * AMG_NM) sm[lr][rr] = act ? ld(b, o) - amgc_row(ptr, col, A, x, row, rr) : 0.0;
-  __syncthreads();
-  if (!act) return;
-  const TP *q = Q + (int64_t)row * AMG_NM * AMG_NM + rr;   // column rr of the row's 10x10 block
+  AMGC_WAVE_PROLOGUE
+  amgc_row_sums(ptr, col, A, x, row, act, j, sp[wv], sw[wv]);
+  if (!act || j >= AMG_NM) return;
+  const TP *q = Q + (int64_t)row * AMG_NM * AMG_NM + j;   // column j of the row's 10x10 block
   double acc = 0.0;
 #pragma unroll
-  for (int r = 0; r < AMG_NM; ++r) acc += ld(q, r * AMG_NM) * sm[lr][r];
-  t[o] = (T)acc;
+  for (int r = 0; r < AMG_NM; ++r) acc += ld(q, r * AMG_NM) * (ld(b, (int64_t)row * AMG_NM + r) - sw[wv][r]);
+  t[(int64_t)row * AMG_NM + j] = (T)acc;
 }
 
+// y = D^-1 A x (power iteration)
 template <typename T>
 __global__ void __launch_bounds__(256)
 k_amgc_dapply(int n, const int32_t *__restrict__ ptr, const int32_t *__restrict__ col, const T *__restrict__ A,
               const T *__restrict__ Dinv, const T *__restrict__ x, T *y) {
-  __shared__ double sm[AMG_CROWS][AMG_NM];
-  const int t = threadIdx.x, lr = t / AMG_NM, row = blockIdx.x * AMG_CROWS + lr, rr = t % AMG_NM;
-  const bool act = t < AMG_CROWS * AMG_NM && row < n;
-  if (t < AMG_CROWS * AMG_NM) sm[lr][rr] = act ? amgc_row(ptr, col, A, x, row, rr) : 0.0;
-  __syncthreads();
-  if (act) y[(int64_t)row * AMG_NM + rr] = (T)amgc_dapply(Dinv, row, rr, sm[lr]);
+  __shared__ double sp[AMG_WROWS][64], sw[AMG_WROWS][AMG_NM];
+  AMGC_WAVE_PROLOGUE
+  amgc_row_sums(ptr, col, A, x, row, act, j, sp[wv], sw[wv]);
+  if (act && j < AMG_NM) y[(int64_t)row * AMG_NM + j] = (T)amgc_dapply(Dinv, row, j, sw[wv]);
 }
 
 // x += d (the pending step of a degree-1 smoothing from a nonzero start)

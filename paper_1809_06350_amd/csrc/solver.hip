@@ -1943,7 +1943,7 @@ struct AmgSys {
         hipLaunchKernelGGL(k_amgf_dapply<T>, dim3(spmv_grid(lv.n)), bl, 0, s, lv.n, mesh->nnzb, mesh->slot_width,
                            mesh->col, A0, M0, (const T *)x, y);
       else
-        hipLaunchKernelGGL(k_amgc_dapply<T>, dim3(amg_cgrid(lv.n)), dim3(256), 0, s, lv.n, lv.ptr, lv.col,
+        hipLaunchKernelGGL(k_amgc_dapply<T>, dim3(amg_wgrid(lv.n)), dim3(256), 0, s, lv.n, lv.ptr, lv.col,
                            (const T *)Ac[l], (const T *)Dinv[l], (const T *)x, y);
       hipLaunchKernelGGL(k_norm_part<T>, dim3(nb), bl, 0, s, nv, (const T *)y, part, (const int *)nullptr);
       hipLaunchKernelGGL(k_store_norm, dim3(1), bl, 0, s, nb, (const double *)part, ltmp);
@@ -1957,7 +1957,7 @@ struct AmgSys {
     const vms_amg_level_dev &lv = h->lev[l];
     const int n = lv.n;
     const double *lm = lam + l;
-    const dim3 bl(VMS_BLOCK), gf(spmv_grid(n)), gc(amg_cgrid(n)), bc(256);
+    const dim3 bl(VMS_BLOCK), gf(spmv_grid(n)), gc(amg_cgrid(n)), gw(amg_wgrid(n)), bc(256);
     T *dk = d0[l], *dn = d1[l], *r = rv[l];
     if (l == 0) {
       if (zero)
@@ -1969,7 +1969,7 @@ struct AmgSys {
       if (zero)
         hipLaunchKernelGGL(k_amgc_cheb0<T>, gc, bc, 0, s, n, (const T *)Dinv[l], b, x, r, dk, lm, done);
       else
-        hipLaunchKernelGGL((k_amgc_cheb<T, 0>), gc, bc, 0, s, n, lv.ptr, lv.col, (const T *)Ac[l],
+        hipLaunchKernelGGL((k_amgc_cheb<T, 0>), gw, bc, 0, s, n, lv.ptr, lv.col, (const T *)Ac[l],
                            (const T *)Dinv[l], b, (const T *)x, dk, r, x, lm, 0, 0, done);
     }
     const int pending = zero ? 0 : 1;
@@ -1978,7 +1978,7 @@ struct AmgSys {
         hipLaunchKernelGGL(k_amgf_step<T>, gf, bl, 0, s, n, mesh->nnzb, mesh->slot_width, mesh->col, A0, M0,
                            (const T *)dk, dn, r, x, lm, k, k == 0 ? pending : 0, done);
       else
-        hipLaunchKernelGGL((k_amgc_cheb<T, 1>), gc, bc, 0, s, n, lv.ptr, lv.col, (const T *)Ac[l],
+        hipLaunchKernelGGL((k_amgc_cheb<T, 1>), gw, bc, 0, s, n, lv.ptr, lv.col, (const T *)Ac[l],
                            (const T *)Dinv[l], (const T *)nullptr, (const T *)dk, dn, r, x, lm, k,
                            k == 0 ? pending : 0, done);
       std::swap(dk, dn);
@@ -2009,7 +2009,7 @@ struct AmgSys {
       hipLaunchKernelGGL((k_amgf_resid_t<T, TP>), dim3(spmv_grid(lv.n)), bl, 0, s, lv.n, mesh->nnzb,
                          mesh->slot_width, mesh->col, A0, b, (const T *)x, P, Wsc, tv[0], done);
     else
-      hipLaunchKernelGGL((k_amgc_resid_t<T, TP>), dim3(amg_cgrid(lv.n)), dim3(256), 0, s, lv.n, lv.ptr, lv.col,
+      hipLaunchKernelGGL((k_amgc_resid_t<T, TP>), dim3(amg_wgrid(lv.n)), dim3(256), 0, s, lv.n, lv.ptr, lv.col,
                          (const T *)Ac[l], b, (const T *)x, P, tv[l], done);
     const dim3 gr((unsigned)(((int64_t)c.n * AMG_NM + VMS_BLOCK - 1) / VMS_BLOCK));
     const dim3 gp((unsigned)(((int64_t)lv.n * lv.bs + VMS_BLOCK - 1) / VMS_BLOCK));
