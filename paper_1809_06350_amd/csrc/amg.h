@@ -61,18 +61,21 @@ __device__ __forceinline__ bool amg_done(const int *done) { return done && *done
 
 // ---- finest level (3x3 fixed-slot blocks, 16 lanes per row) ---------------------------------
 
-// row sums (A x)_row for all three components, valid in all 16 lanes of the row
+// row sums (A x)_row for all three components, valid in all 16 lanes of the row; in FP64 the
+// matrix values and column indices, read once per pass, are loaded non-temporally so that they
+// do not evict the gathered vector from the caches
 template <typename T>
 __device__ __forceinline__ void amgf_row(int64_t nnzb, int b0, int b1, int lane, const int32_t *__restrict__ col,
                                          const T *__restrict__ A, const T *__restrict__ x, double &a0, double &a1,
                                          double &a2) {
+  constexpr bool NT = sizeof(T) == 8;
   a0 = a1 = a2 = 0.0;
   for (int b = b0 + lane; b < b1; b += 16) {
-    const int64_t o = 3 * (int64_t)col[b];
+    const int64_t o = 3 * (int64_t)ldc<NT>(col, b);
     const double x0 = ld(x, o), x1 = ld(x, o + 1), x2 = ld(x, o + 2);
-    a0 += ld(A, 0 * nnzb + b) * x0 + ld(A, 1 * nnzb + b) * x1 + ld(A, 2 * nnzb + b) * x2;
-    a1 += ld(A, 3 * nnzb + b) * x0 + ld(A, 4 * nnzb + b) * x1 + ld(A, 5 * nnzb + b) * x2;
-    a2 += ld(A, 6 * nnzb + b) * x0 + ld(A, 7 * nnzb + b) * x1 + ld(A, 8 * nnzb + b) * x2;
+    a0 += ldm<NT>(A, 0 * nnzb + b) * x0 + ldm<NT>(A, 1 * nnzb + b) * x1 + ldm<NT>(A, 2 * nnzb + b) * x2;
+    a1 += ldm<NT>(A, 3 * nnzb + b) * x0 + ldm<NT>(A, 4 * nnzb + b) * x1 + ldm<NT>(A, 5 * nnzb + b) * x2;
+    a2 += ldm<NT>(A, 6 * nnzb + b) * x0 + ldm<NT>(A, 7 * nnzb + b) * x1 + ldm<NT>(A, 8 * nnzb + b) * x2;
   }
   a0 = reduce16(a0);
   a1 = reduce16(a1);
