@@ -64,11 +64,10 @@ __device__ __forceinline__ bool amg_done(const int *done) { return done && *done
 // row sums (A x)_row for all three components, valid in all 16 lanes of the row; in FP64 the
 // matrix values and column indices, read once per pass, are loaded non-temporally so that they
 // do not evict the gathered vector from the caches
-template <typename T>
+template <typename T, bool NT = sizeof(T) == 8>
 __device__ __forceinline__ void amgf_row(int64_t nnzb, int b0, int b1, int lane, const int32_t *__restrict__ col,
                                          const T *__restrict__ A, const T *__restrict__ x, double &a0, double &a1,
                                          double &a2) {
-  constexpr bool NT = sizeof(T) == 8;
   a0 = a1 = a2 = 0.0;
   for (int b = b0 + lane; b < b1; b += 16) {
     const int64_t o = 3 * (int64_t)ldc<NT>(col, b);
@@ -138,8 +137,10 @@ k_amgf_chebres(int n, int64_t nnzb, int W, const int32_t *__restrict__ col, cons
   d[o + c] = (T)(z / th);
 }
 
-// Chebyshev step k: r -= M A d_k, d_{k+1} = c1 d_k + c2 r, x += (pending ? d_k : 0) + d_{k+1}
-template <typename T>
+// Chebyshev step k: r -= M A d_k, d_{k+1} = c1 d_k + c2 r, x += (pending ? d_k : 0) + d_{k+1}.
+// CACHED: plain loads of the matrix (the post-smoothing steps, so that the A-values they leave in
+// the caches serve the Krylov product that follows the V-cycle).
+template <typename T, bool CACHED = false>
 __global__ void __launch_bounds__(VMS_BLOCK)
 k_amgf_step(int n, int64_t nnzb, int W, const int32_t *__restrict__ col, const T *__restrict__ A,
             const T *__restrict__ Minv, const T *__restrict__ dk, T *dn, T *r, T *x, const double *lam, int k,
@@ -156,7 +157,7 @@ k_amgf_step(int n, int64_t nnzb, int W, const int32_t *__restrict__ col, const T
   }
   const double lamv = *lam;
   double a0, a1, a2;
-  amgf_row(nnzb, b0, b1, lane, col, A, dk, a0, a1, a2);
+  amgf_row<T, sizeof(T) == 8 && !CACHED>(nnzb, b0, b1, lane, col, A, dk, a0, a1, a2);
   if (!own) return;
   double th, c1, c2;
   amg_cheb(lamv, k, th, c1, c2);

@@ -1974,9 +1974,12 @@ struct AmgSys {
     }
     const int pending = zero ? 0 : 1;
     for (int k = 0; k + 1 < deg; ++k) {
-      if (l == 0)
-        hipLaunchKernelGGL(k_amgf_step<T>, gf, bl, 0, s, n, mesh->nnzb, mesh->slot_width, mesh->col, A0, M0,
-                           (const T *)dk, dn, r, x, lm, k, k == 0 ? pending : 0, done);
+      if (l == 0 && zero)
+        hipLaunchKernelGGL((k_amgf_step<T, false>), gf, bl, 0, s, n, mesh->nnzb, mesh->slot_width, mesh->col, A0,
+                           M0, (const T *)dk, dn, r, x, lm, k, k == 0 ? pending : 0, done);
+      else if (l == 0)
+        hipLaunchKernelGGL((k_amgf_step<T, true>), gf, bl, 0, s, n, mesh->nnzb, mesh->slot_width, mesh->col, A0,
+                           M0, (const T *)dk, dn, r, x, lm, k, k == 0 ? pending : 0, done);
       else
         hipLaunchKernelGGL((k_amgc_cheb<T, 1>), gw, bc, 0, s, n, lv.ptr, lv.col, (const T *)Ac[l],
                            (const T *)Dinv[l], (const T *)nullptr, (const T *)dk, dn, r, x, lm, k,
