@@ -529,10 +529,11 @@ int vms_adjoint_step(vms_ctx *ctx, const vms_mesh *mesh, const vms_material *mat
 typedef struct {
   int32_t max_levels;     /* 2 .. VMS_AMG_MAX_LEVELS */
   int32_t min_coarse;     /* a level with at most this many nodes is the coarsest */
-  int32_t degree;         /* Chebyshev degree of pre- and post-smoothing (1 .. 16) */
-  int32_t coarse_degree;  /* Chebyshev degree on the coarsest level (1 .. 64) */
-  int32_t mid_degree;     /* Chebyshev degree on the levels between the finest and the coarsest
-                             (1 .. 16); 0 takes degree */
+  int32_t degree;         /* Chebyshev degree of pre- and post-smoothing on the finest level, and on
+                             the levels below it but the coarsest when mid_degree is 0 (1 .. 16) */
+  int32_t coarse_degree;  /* Chebyshev degree of the coarsest level's smoothing from zero (1 .. 64) */
+  int32_t mid_degree;     /* Chebyshev degree of pre- and post-smoothing on the levels between the
+                             finest and the coarsest (1 .. 16); 0 takes degree */
 } vms_amg_opts;
 
 typedef struct {
