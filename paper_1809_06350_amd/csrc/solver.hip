@@ -1026,18 +1026,6 @@ k_cgx_update(int64_t nn, T *x, T *r, const T *__restrict__ p, const T *__restric
 // non-positive curvature ends the steps early (x keeps the last iterate); the
 // host never waits on them.
 
-// sum over a workgroup of any size (fixed order), valid in thread 0
-__device__ __forceinline__ double blk_sum_any(double v, double *sm) {
-  v = wave_sum(v);
-  const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  if ((threadIdx.x & 63) == 0) sm[w] = v;
-  __syncthreads();
-  double r = 0.0;
-  if (threadIdx.x == 0)
-    for (int q = 0; q < nw; ++q) r += sm[q];
-  return r;
-}
-
 // Off-diagonal part of row ro of S^ times z: lane l of the row's 16 takes
 // slots l, l + 16, l + 32, l + 48 of each 64-slot segment (four column loads
 // and four gathers in flight per lane).  With sorted columns the 16 lanes of
@@ -1414,7 +1402,6 @@ k_shat_cheb(int n, int W2, const int32_t *__restrict__ sc, const int16_t *__rest
   const int row = xcd_block(blockIdx.x, gridDim.x) * SPMV_ROWS_PER_BLOCK + (threadIdx.x >> 4);
   const bool act = row < n;
   const int ro = act ? row : 0;
-  const int64_t r0 = (int64_t)W2 * ro;
   // the row's own values and the Chebyshev scalars ahead of the product (latency overlap)
   const double sdi = ld(sdinv, ro), sii = ld(Sd, ro), di = ld(d, ro);
   double xi = 0.0, ri = 0.0, rho0 = 0.0, rho1 = 0.0, delta = 1.0, theta = 1.0;
