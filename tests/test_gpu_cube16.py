@@ -10,9 +10,7 @@ form (FP32 intermediate and inner levels, FP64 outer FGMRES and Newton) runs
 the benchmark's tolerances; its error against the FP64 oracle is printed and
 held below 1e-6.
 """
-import numpy as np
 import pytest
-import torch
 
 import synth
 from oracle import assemble as AS
